@@ -1,0 +1,152 @@
+/* rz.h -- C ABI of the MI355X (gfx950) Riesz-map solver.
+ *
+ * Method: Brubeck, Farrell, Kirby & Parker, "Fast solvers for the high-order
+ * FEM simplicial de Rham complex" (arXiv:2506.17406).
+ *
+ * Problem (Sec. 2, eq:weak-form): find u in X^k_p(T_h) with
+ *     (u, beta v) + (d^k u, alpha d^k v) = F(v)   for all v in X^k_p(T_h),
+ * for k = 0 (H(grad), CG_p), k = 1 (H(curl), Ned_p first kind) and k = 2
+ * (H(div), RT_p first kind), on a conforming simplicial mesh (triangles for
+ * k = 0 in 2D, tetrahedra in 3D), with natural (pure Neumann) boundary
+ * conditions.  F is given as its load vector b_i = F(phi_i) in the paper's
+ * orthogonality-promoting basis (Sec. 3, eq:abstract-dofs; Sec. 4,
+ * eq:reference-basis).  The discrete system A x = b is solved by
+ * preconditioned conjugate gradients (Sec. 7.1) with the interior-interface
+ * split additive Schwarz preconditioners of Sec. 6:
+ *   H(grad)  PAFW(0)(X^0_Gamma) + J(X^0_I)          (eq:approx-sc-pafw)
+ *   H(curl)  PH(X^0_Gamma, X^{1,I}_Gamma) + J(X^1_I) (eq:hcurl-decomp)
+ *   H(div)   PAFW(1)(X^2_Gamma) + J(X^2_I)           (eq:hdiv-decomp)
+ * each with an exact solve on the Whitney coarse space W^k.
+ *
+ * Numbering (host-exported, see rz_export_topology): each cell's vertices are
+ * sorted by global number; edges and faces are the sorted vertex tuples,
+ * numbered in lexicographic order; global dofs are entity-major -- all vertex
+ * dofs, then edges, faces, and the cell interiors last (contiguous) -- with
+ * dof = offset(dim) + entity_id * N_dim + j and, within an entity, the
+ * Whitney dof, the type-I dofs, then the type-II dofs.
+ *
+ * Memory and streams.  Vectors passed to rz_apply_A / rz_apply_P / rz_solve
+ * are caller-owned DEVICE pointers to float64, column-major with leading
+ * dimension ld >= n_dofs (one column per right-hand side).  The library never
+ * retains or frees them.  Work is enqueued on the HIP stream passed in
+ * (NULL = the default stream); apply calls return without synchronising,
+ * rz_solve returns after the solve has finished.  Mesh arrays are host
+ * pointers, copied during rz_setup.  A handle owns all its device memory,
+ * is not thread-safe, and distinct handles are independent.
+ *
+ * Errors.  Every int-returning call returns 0 on success or one of the
+ * negative RZ_ERR_* codes; rz_last_error() gives a thread-local message for
+ * the last failure.  No C++ exception crosses this interface.
+ */
+#ifndef RZ_H
+#define RZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RZ_OK = 0,
+  RZ_ERR_ARG = -1,              /* bad pointer, size, alpha < 0, beta <= 0, dim */
+  RZ_ERR_UNSUPPORTED = -2,      /* (dim, space, degree) outside 2D CG / 3D CG,Ned,RT, 1 <= p <= 10 */
+  RZ_ERR_MESH = -3,             /* vertex index out of range or repeated in a cell */
+  RZ_ERR_DEGENERATE_CELL = -4,  /* |det J_T| <= 1e-12 h^d */
+  RZ_ERR_NOT_SPD = -5,          /* non-positive pivot in a patch or coarse Cholesky */
+  RZ_ERR_NO_CONVERGENCE = -6,   /* max_iter reached; info is still filled */
+  RZ_ERR_BREAKDOWN = -7,        /* p^T A p <= 0 or a non-finite CG scalar */
+  RZ_ERR_DEVICE = -8,           /* HIP runtime error */
+  RZ_ERR_OOM = -9               /* device allocation failed */
+};
+
+typedef enum { RZ_HGRAD = 0, RZ_HCURL = 1, RZ_HDIV = 2 } rz_space;
+
+typedef struct {
+  int32_t dim;            /* 2 or 3 */
+  int64_t n_vertices;
+  const double *coords;   /* host, n_vertices x dim, row-major */
+  int64_t n_cells;
+  const int64_t *cells;   /* host, n_cells x (dim+1) vertex numbers, any order */
+} rz_mesh;
+
+typedef struct {
+  double alpha;           /* coefficient of (d u, d v), >= 0 */
+  double beta;            /* coefficient of (u, v), > 0 */
+  int32_t max_iter;       /* PCG iteration cap (<= 0: 1000) */
+} rz_options;
+
+typedef struct {
+  int32_t status;         /* RZ_OK / RZ_ERR_NO_CONVERGENCE / RZ_ERR_BREAKDOWN */
+  int32_t iterations;     /* PCG iterations taken */
+  double rel_residual;    /* ||r_k||_2 / ||b||_2 of the recursively updated residual */
+  double cond_estimate;   /* Lanczos estimate of kappa(P^{-1} A) from the CG coefficients */
+  double solve_ms;        /* wall time of the iteration loop */
+} rz_info;
+
+typedef struct rz_problem rz_problem;
+
+/* Builds the reference element (Sec. 3-4) on the host, the numbering and the
+ * patches (Sec. 6), uploads them, and assembles and factors the patch and
+ * coarse matrices on the device in FP64.  opts may be NULL (alpha = beta = 1).
+ * On success *out receives a new handle. */
+int rz_setup(const rz_mesh *mesh, int32_t degree, rz_space space, const rz_options *opts,
+             void *hip_stream, rz_problem **out);
+
+/* Sizes: global dofs, interior dofs (the trailing block), local dofs per cell,
+ * number of stacked reference matrices.  Any output pointer may be NULL. */
+int rz_sizes(const rz_problem *P, int64_t *n_dofs, int64_t *n_interior, int32_t *n_loc, int32_t *Q);
+
+/* y = A x (the matrix-free operator of eq:weak-form: gather, stacked
+ * reference-matrix contraction with per-cell geometric weights, scatter-add).
+ * x, y: device, n_dofs x n_rhs, leading dimension ld; y is overwritten. */
+int rz_apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream);
+
+/* z = P^{-1} r: point-Jacobi on the interior dofs + exact interface patch
+ * solves + exact coarse (Whitney) solve, added (Sec. 6, additive form).
+ * r, z: device, n_dofs x n_rhs, leading dimension ld; z is overwritten. */
+int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream);
+
+/* PCG on A x = b from the initial guess in x, stopping when the recursive
+ * residual satisfies ||r||_2 <= rtol ||b||_2.  b, x: device, n_dofs (one right-hand side).
+ * info (host, may be NULL) is filled on return. */
+int rz_solve(rz_problem *P, const double *b, double *x, double rtol, rz_info *info, void *hip_stream);
+
+/* Host copies of the numbering for parity checks: cell_dofs (n_cells x n_loc
+ * int32, local dofs in the element's order) and the interface patches as
+ * CSR over their ascending dof lists: patch_ptr (n_patches + 1), patch_dofs.
+ * Pass NULL pointers to query *n_patches and *n_patch_entries first.
+ * For H(curl) only the edge patches are listed (vertex potentials act through
+ * the discrete gradient). */
+int rz_export_topology(const rz_problem *P, int32_t *cell_dofs, int64_t *n_patches,
+                       int64_t *n_patch_entries, int64_t *patch_ptr, int32_t *patch_dofs);
+
+/* Host copy of the stacked reference matrices R_q (Q x n_loc x n_loc,
+ * row-major), ordered: the value family then the derivative family; a vector
+ * family lists the component pairs 00, 11, 22, 01, 02, 12 (3D; 00, 11, 01 in
+ * 2D) with off-diagonal pairs symmetrised (R_ab + R_ba), a scalar family one
+ * matrix.  A_T = sum_q w_{T,q} R_q with w from the Piola maps of
+ * eq:pullback-3d-def. */
+int rz_export_reference(const rz_problem *P, double *Rq);
+
+/* Host-only (no device work): the stacked reference matrices of
+ * (dim, degree, space) in the rz_export_reference layout.  Pass Rq = NULL to
+ * query *n_loc and *Q first. */
+int rz_reference(int32_t dim, int32_t degree, rz_space space, int32_t *n_loc, int32_t *Q, double *Rq);
+
+/* Host-only (no device work): the numbering and plain patch lists that
+ * rz_setup would build for this mesh, in the rz_export_topology layout.
+ * Pass NULL output arrays to query *n_dofs, *n_patches and *n_patch_entries
+ * first; cell_dofs needs n_cells x n_loc entries. */
+int rz_numbering(const rz_mesh *mesh, int32_t degree, rz_space space, int64_t *n_dofs, int32_t *cell_dofs,
+                 int64_t *n_patches, int64_t *n_patch_entries, int64_t *patch_ptr, int32_t *patch_dofs);
+
+void rz_destroy(rz_problem *P);
+
+const char *rz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RZ_H */

@@ -1,0 +1,578 @@
+// C ABI of the Riesz-map solver: setup (host reference build, numbering and
+// patches, then device assembly and FP64 factorisation of the patch and
+// coarse matrices), operator and preconditioner applies, and PCG.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/rz.h"
+#include "kernels.hpp"
+#include "refelem.hpp"
+#include "topology.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+struct RzError {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw RzError{e_ == hipErrorOutOfMemory ? RZ_ERR_OOM : RZ_ERR_DEVICE,              \
+                    std::string(#call) + ": " + hipGetErrorString(e_)};                 \
+  } while (0)
+
+struct DevPatchSet {
+  rz::PatchApply pa{};
+  std::vector<void *> owned;
+};
+
+}  // namespace
+
+struct rz_problem {
+  int d = 0, k = 0, p = 0;
+  rz::Family fam = rz::FAM_CG;
+  rz::RefElement el;
+  rz::Topology top;
+  std::vector<rz::PatchSet> patches;
+  int64_t off_I = 0;
+  int max_iter = 1000;
+  // device data
+  std::vector<void *> mem;
+  double *R = nullptr, *Afrag = nullptr, *w = nullptr, *dinv = nullptr;
+  int32_t *cell_dofs = nullptr;
+  rz::ApplyATables at{};
+  std::vector<DevPatchSet> dps;
+  rz::CoarseApply ca{};
+  rz::PcgState *st = nullptr;
+  rz::PcgState *st_host = nullptr;
+  double *r = nullptr, *z = nullptr, *pv = nullptr, *Ap = nullptr, *part = nullptr, *part2 = nullptr;
+
+  template <class T>
+  T *dev(size_t count) {
+    void *ptr = nullptr;
+    if (count == 0) count = 1;
+    HIPCHK(hipMalloc(&ptr, count * sizeof(T)));
+    mem.push_back(ptr);
+    return static_cast<T *>(ptr);
+  }
+  template <class T>
+  T *upload(const std::vector<T> &v, hipStream_t s) {
+    T *ptr = dev<T>(v.size());
+    // blocking copy: the host vector may be a temporary of the caller
+    (void)s;
+    if (!v.empty()) HIPCHK(hipMemcpy(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return ptr;
+  }
+  ~rz_problem() {
+    for (void *ptr : mem) (void)hipFree(ptr);
+    if (st_host) (void)hipHostFree(st_host);
+  }
+};
+
+namespace {
+
+int round_up(int64_t a, int b) { return int((a + b - 1) / b * b); }
+
+void check_cells(const rz_problem &P, const double *coords) {
+  const int d = P.d;
+  for (int64_t c = 0; c < P.top.n_cells; ++c) {
+    const int64_t *v = &P.top.cells[c * (d + 1)];
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, h = 0;
+    for (int b = 0; b < d; ++b)
+      for (int a = 0; a < d; ++a) J[a][b] = coords[v[b + 1] * d + a] - coords[v[0] * d + a];
+    for (int i = 0; i <= d; ++i)
+      for (int j = i + 1; j <= d; ++j) {
+        double s = 0;
+        for (int a = 0; a < d; ++a) {
+          const double t = coords[v[j] * d + a] - coords[v[i] * d + a];
+          s += t * t;
+        }
+        h = std::max(h, std::sqrt(s));
+      }
+    double det = d == 3 ? J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                              J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                              J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0])
+                        : J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    if (!(std::fabs(det) > 1e-12 * std::pow(h, d)))
+      throw RzError{RZ_ERR_DEGENERATE_CELL, "degenerate cell " + std::to_string(c)};
+  }
+}
+
+// factor a batch of patch matrices (chunked to bound the dense workspace)
+void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hipStream_t s) {
+  const int64_t B = ps.n_patches();
+  const int maxsz = int(ps.max_size());
+  const int N = std::max(32, round_up(maxsz, 32));
+  std::vector<int32_t> sizes(B);
+  std::vector<int64_t> off(B);
+  int64_t tot = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    sizes[b] = int32_t(ps.patch_col[b + 1] - ps.patch_col[b]);
+    off[b] = tot;
+    tot += int64_t(sizes[b]) * (sizes[b] + 1) / 2;
+  }
+  double *inv = P.dev<double>(tot);
+  const int64_t budget = int64_t(6) << 30;  // bytes for A + L^{-1} per chunk
+  const int64_t chunk = std::max<int64_t>(1, budget / (int64_t(N) * N * 16));
+  const int64_t nch = std::min(chunk, B);
+  double *Abuf = nullptr, *Lbuf = nullptr;
+  int32_t *dsizes = nullptr;
+  int64_t *doff = nullptr;
+  int *dstatus = nullptr;
+  HIPCHK(hipMalloc(&Abuf, size_t(nch) * N * N * 8));
+  HIPCHK(hipMalloc(&Lbuf, size_t(nch) * N * N * 8));
+  HIPCHK(hipMalloc(&dsizes, size_t(B) * 4));
+  HIPCHK(hipMalloc(&doff, size_t(B) * 8));
+  HIPCHK(hipMalloc(&dstatus, 4));
+  struct Freer {
+    std::vector<void *> v;
+    ~Freer() {
+      for (void *p : v) (void)hipFree(p);
+    }
+  } fr{{Abuf, Lbuf, dsizes, doff, dstatus}};
+  HIPCHK(hipMemcpyAsync(dsizes, sizes.data(), size_t(B) * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(doff, off.data(), size_t(B) * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(dstatus, 0, 4, s));
+  // coupling triples (patch column, local dof, coefficient), needed only here
+  int32_t *t_col = nullptr, *t_loc = nullptr;
+  double *t_coef = nullptr;
+  const size_t ntr = std::max<size_t>(1, ps.tr_col.size());
+  HIPCHK(hipMalloc(&t_col, ntr * 4));
+  HIPCHK(hipMalloc(&t_loc, ntr * 4));
+  HIPCHK(hipMalloc(&t_coef, ntr * 8));
+  fr.v.push_back(t_col);
+  fr.v.push_back(t_loc);
+  fr.v.push_back(t_coef);
+  HIPCHK(hipMemcpyAsync(t_col, ps.tr_col.data(), ps.tr_col.size() * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(t_loc, ps.tr_loc.data(), ps.tr_loc.size() * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(t_coef, ps.tr_coef.data(), ps.tr_coef.size() * 8, hipMemcpyHostToDevice, s));
+  for (int64_t p0 = 0; p0 < B; p0 += nch) {
+    const int64_t p1 = std::min(B, p0 + nch), nb = p1 - p0;
+    const int64_t i0 = ps.pc_ptr[p0], i1 = ps.pc_ptr[p1];
+    std::vector<int32_t> item_patch(i1 - i0), item_cell(ps.pc_cell.begin() + i0, ps.pc_cell.begin() + i1);
+    std::vector<int64_t> item_trip(ps.pc_trip.begin() + i0, ps.pc_trip.begin() + i1 + 1);
+    for (int64_t p = p0; p < p1; ++p)
+      for (int64_t it = ps.pc_ptr[p]; it < ps.pc_ptr[p + 1]; ++it) item_patch[it - i0] = int32_t(p - p0);
+    int32_t *d_ip = nullptr, *d_ic = nullptr;
+    int64_t *d_it = nullptr;
+    HIPCHK(hipMalloc(&d_ip, std::max<size_t>(1, item_patch.size()) * 4));
+    HIPCHK(hipMalloc(&d_ic, std::max<size_t>(1, item_cell.size()) * 4));
+    HIPCHK(hipMalloc(&d_it, item_trip.size() * 8));
+    fr.v.push_back(d_ip);
+    fr.v.push_back(d_ic);
+    fr.v.push_back(d_it);
+    HIPCHK(hipMemcpy(d_ip, item_patch.data(), item_patch.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d_ic, item_cell.data(), item_cell.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d_it, item_trip.data(), item_trip.size() * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemsetAsync(Abuf, 0, size_t(nb) * N * N * 8, s));
+    HIPCHK(hipMemsetAsync(Lbuf, 0, size_t(nb) * N * N * 8, s));
+    rz::launch_pad_identity(nb, N, dsizes + p0, Abuf, s);
+    rz::launch_patch_assemble(i1 - i0, d_ip, d_ic, d_it, t_col, t_loc, t_coef, P.el.n, P.el.Q, P.R, P.w, N, Abuf,
+                              s);
+    rz::launch_chol_inverse(nb, N, Abuf, Lbuf, dstatus, s);
+    rz::launch_pack_upper(nb, N, dsizes + p0, doff + p0, Abuf, inv, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  int status = 0;
+  HIPCHK(hipMemcpy(&status, dstatus, 4, hipMemcpyDeviceToHost));
+  if (status) throw RzError{RZ_ERR_NOT_SPD, "non-positive pivot in a patch Cholesky factorisation"};
+  out.pa.n_patches = B;
+  out.pa.max_size = maxsz;
+  out.pa.patch_col = P.upload(ps.patch_col, s);
+  out.pa.col_ent = P.upload(ps.col_ent, s);
+  out.pa.inv_off = P.upload(off, s);
+  out.pa.ent_dof = P.upload(ps.ent_dof, s);
+  out.pa.ent_coef = P.upload(ps.ent_coef, s);
+  out.pa.inv = inv;
+}
+
+void setup_coarse(rz_problem &P, hipStream_t s) {
+  std::vector<int32_t> wdofs, wloc, widx;
+  int nwl = 0;
+  rz::whitney_dofs(P.top, P.el, wdofs, wloc, widx, nwl);
+  const int nW = int(wdofs.size());
+  const int N = std::max(64, round_up(nW, 64));
+  const int NT = N / 64;
+  // one "patch" whose items are the cells, coupling their local Whitney dofs
+  const int64_t nc = P.top.n_cells;
+  std::vector<int32_t> item_patch(nc, 0), item_cell(nc), tr_col, tr_loc;
+  std::vector<int64_t> item_trip(nc + 1, 0);
+  std::vector<double> tr_coef;
+  for (int64_t c = 0; c < nc; ++c) {
+    item_cell[c] = int32_t(c);
+    for (int a = 0; a < nwl; ++a) {
+      tr_col.push_back(widx[c * nwl + a]);
+      tr_loc.push_back(wloc[a]);
+      tr_coef.push_back(1.0);
+    }
+    item_trip[c + 1] = int64_t(tr_col.size());
+  }
+  double *Abuf = nullptr, *Lbuf = nullptr;
+  int *dstatus = nullptr;
+  int32_t *dsz = nullptr;
+  HIPCHK(hipMalloc(&Abuf, size_t(N) * N * 8));
+  HIPCHK(hipMalloc(&Lbuf, size_t(N) * N * 8));
+  HIPCHK(hipMalloc(&dstatus, 4));
+  HIPCHK(hipMalloc(&dsz, 4));
+  std::vector<void *> tmp{Abuf, Lbuf, dstatus, dsz};
+  struct Freer {
+    std::vector<void *> &v;
+    ~Freer() {
+      for (void *p : v) (void)hipFree(p);
+    }
+  } fr{tmp};
+  auto up = [&](auto &v) {
+    using T = typename std::decay_t<decltype(v)>::value_type;
+    T *ptr = nullptr;
+    HIPCHK(hipMalloc(&ptr, std::max<size_t>(1, v.size()) * sizeof(T)));
+    tmp.push_back(ptr);
+    HIPCHK(hipMemcpy(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return ptr;
+  };
+  int32_t *d_ip = up(item_patch), *d_ic = up(item_cell), *d_col = up(tr_col), *d_loc = up(tr_loc);
+  int64_t *d_it = up(item_trip);
+  double *d_coef = up(tr_coef);
+  HIPCHK(hipMemsetAsync(Abuf, 0, size_t(N) * N * 8, s));
+  HIPCHK(hipMemsetAsync(Lbuf, 0, size_t(N) * N * 8, s));
+  HIPCHK(hipMemsetAsync(dstatus, 0, 4, s));
+  HIPCHK(hipMemcpy(dsz, &nW, 4, hipMemcpyHostToDevice));
+  rz::launch_pad_identity(1, N, dsz, Abuf, s);
+  rz::launch_patch_assemble(nc, d_ip, d_ic, d_it, d_col, d_loc, d_coef, P.el.n, P.el.Q, P.R, P.w, N, Abuf, s);
+  rz::launch_chol_inverse(1, N, Abuf, Lbuf, dstatus, s);
+  double *tiles = P.dev<double>(size_t(NT) * (NT + 1) / 2 * 4096);
+  rz::launch_pack_tiles(N, nW, Abuf, tiles, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  int status = 0;
+  HIPCHK(hipMemcpy(&status, dstatus, 4, hipMemcpyDeviceToHost));
+  if (status) throw RzError{RZ_ERR_NOT_SPD, "non-positive pivot in the coarse Cholesky factorisation"};
+  P.ca.nW = nW;
+  P.ca.NT = NT;
+  P.ca.wdofs = P.upload(wdofs, s);
+  P.ca.tiles = tiles;
+  P.ca.rW = P.dev<double>(N);
+  P.ca.zW = P.dev<double>(N);
+}
+
+void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
+  // numbering, patches
+  P.top = rz::build_topology(P.d, m->n_vertices, m->n_cells, m->cells, P.el);
+  check_cells(P, m->coords);
+  P.patches = rz::build_patches(P.top, P.el);
+  P.off_I = P.top.offset[P.d];
+  const int n = P.el.n, Q = P.el.Q, d = P.d;
+  // reference tables: plain and in MFMA fragment order
+  P.R = P.upload(P.el.R, s);
+  const int NP = round_up(n, 16), KP = round_up(n, 4), KB = KP / 4, NMB = NP / 16;
+  std::vector<double> frag(size_t(NMB) * Q * KB * 64, 0.0);
+  for (int mb = 0; mb < NMB; ++mb)
+    for (int q = 0; q < Q; ++q)
+      for (int kb = 0; kb < KB; ++kb)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int row = mb * 16 + (lane & 15), col = kb * 4 + (lane >> 4);
+          if (row < n && col < n)
+            frag[((size_t(mb) * Q + q) * KB + kb) * 64 + lane] = P.el.R[(size_t(q) * n + row) * n + col];
+        }
+  P.Afrag = P.upload(frag, s);
+  P.cell_dofs = P.upload(P.top.cell_dofs, s);
+  P.w = P.dev<double>(size_t(P.top.n_cells) * Q);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rz_last_error(void) { return g_err.c_str(); }
+
+int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options *opts, void *hip_stream,
+             rz_problem **out) {
+  if (!m || !out || !m->coords || !m->cells) return fail(RZ_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (m->dim != 2 && m->dim != 3) return fail(RZ_ERR_ARG, "dim must be 2 or 3");
+  if (m->n_vertices <= 0 || m->n_cells <= 0) return fail(RZ_ERR_ARG, "empty mesh");
+  const double alpha = opts ? opts->alpha : 1.0, beta = opts ? opts->beta : 1.0;
+  if (!(alpha >= 0.0) || !(beta > 0.0)) return fail(RZ_ERR_ARG, "need alpha >= 0 and beta > 0");
+  if (degree < 1 || degree > 10) return fail(RZ_ERR_UNSUPPORTED, "degree must be in 1..10");
+  if (space < RZ_HGRAD || space > RZ_HDIV) return fail(RZ_ERR_ARG, "unknown space");
+  if (m->dim == 2 && space != RZ_HGRAD) return fail(RZ_ERR_UNSUPPORTED, "2D supports H(grad) only");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  auto P = std::make_unique<rz_problem>();
+  P->d = m->dim;
+  P->p = degree;
+  if (opts && opts->max_iter > 0) P->max_iter = std::min<int>(opts->max_iter, rz::kMaxIter);
+  P->fam = space == RZ_HGRAD ? rz::FAM_CG : (space == RZ_HCURL ? rz::FAM_NED : rz::FAM_RT);
+  try {
+    P->el = rz::build_reference(P->d, P->fam, degree);
+    P->k = P->el.k;
+    do_setup(*P, m, s);
+    const int d = P->d, n = P->el.n, Q = P->el.Q;
+    const int64_t nc = P->top.n_cells;
+    // weights (recomputed here so the coordinates buffer is at hand)
+    {
+      std::vector<double> X(size_t(nc) * (d + 1) * d);
+      for (int64_t c = 0; c < nc; ++c)
+        for (int a = 0; a <= d; ++a)
+          for (int b = 0; b < d; ++b)
+            X[(c * (d + 1) + a) * d + b] = m->coords[P->top.cells[c * (d + 1) + a] * d + b];
+      std::vector<double> V(size_t(d + 1) * d);
+      rz::eq_vertices(d, V.data());
+      rz::Dense E(d, d);
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) E(a, b) = V[(b + 1) * d + a] - V[a];
+      rz::Dense Ei = rz::inverse(E);
+      double *dX = P->upload(X, s);
+      double *dEi = P->upload(Ei.a, s);
+      rz::launch_weights(d, P->k, nc, dX, dEi, alpha, beta, P->w, Q, s);
+    }
+    // interior diagonal (Jacobi on X^k_I)
+    std::vector<int32_t> loc_int;
+    for (int i = 0; i < n; ++i)
+      if (P->el.dofs[i].entity_dim == d) loc_int.push_back(i);
+    P->dinv = P->dev<double>(std::max<int64_t>(1, P->top.n_interior));
+    int32_t *dloc = P->upload(loc_int, s);
+    rz::launch_interior_diag(nc, n, Q, P->R, P->w, P->cell_dofs, dloc, int(loc_int.size()), P->off_I, P->dinv, s);
+    HIPCHK(hipGetLastError());
+    // apply_A tables
+    P->at.n = n;
+    P->at.Q = Q;
+    P->at.NP = round_up(n, 16);
+    P->at.KP = round_up(n, 4);
+    P->at.Afrag = P->Afrag;
+    P->at.w = P->w;
+    P->at.cell_dofs = P->cell_dofs;
+    P->at.n_cells = nc;
+    // interface patches and coarse space
+    P->dps.resize(P->patches.size());
+    for (size_t i = 0; i < P->patches.size(); ++i) setup_patch_set(*P, P->patches[i], P->dps[i], s);
+    setup_coarse(*P, s);
+    // Krylov workspace
+    const int64_t nd = P->top.n_dofs;
+    P->st = P->dev<rz::PcgState>(1);
+    HIPCHK(hipHostMalloc((void **)&P->st_host, sizeof(rz::PcgState), hipHostMallocDefault));
+    P->r = P->dev<double>(nd);
+    P->z = P->dev<double>(nd);
+    P->pv = P->dev<double>(nd);
+    P->Ap = P->dev<double>(nd);
+    P->part = P->dev<double>(rz::kRedBlocks);
+    P->part2 = P->dev<double>(rz::kRedBlocks);
+    HIPCHK(hipStreamSynchronize(s));
+  } catch (const RzError &e) {
+    return fail(e.code, e.msg);
+  } catch (const std::invalid_argument &e) {
+    return fail(RZ_ERR_MESH, e.what());
+  } catch (const std::bad_alloc &) {
+    return fail(RZ_ERR_OOM, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(RZ_ERR_UNSUPPORTED, e.what());
+  }
+  *out = P.release();
+  return RZ_OK;
+}
+
+int rz_sizes(const rz_problem *P, int64_t *n_dofs, int64_t *n_interior, int32_t *n_loc, int32_t *Q) {
+  if (!P) return fail(RZ_ERR_ARG, "null handle");
+  if (n_dofs) *n_dofs = P->top.n_dofs;
+  if (n_interior) *n_interior = P->top.n_interior;
+  if (n_loc) *n_loc = P->el.n;
+  if (Q) *Q = P->el.Q;
+  return RZ_OK;
+}
+
+static int apply_P_impl(rz_problem *P, const double *r, double *z, const rz::PcgState *st, hipStream_t s) {
+  rz::launch_jacobi(P->top.n_dofs, P->off_I, P->dinv, r, z, st, s);
+  for (auto &d : P->dps) rz::launch_patch_apply(d.pa, r, z, st, s);
+  rz::launch_coarse_apply(P->ca, r, z, st, s);
+  return 0;
+}
+
+int rz_apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream) {
+  if (!P || !x || !y) return fail(RZ_ERR_ARG, "null argument");
+  if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  for (int c = 0; c < n_rhs; ++c) rz::launch_fill(y + int64_t(c) * ld, P->top.n_dofs, 0.0, nullptr, s);
+  rz::launch_apply_A(P->at, x, y, n_rhs, ld, nullptr, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RZ_ERR_DEVICE, hipGetErrorString(e));
+  return RZ_OK;
+}
+
+int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream) {
+  if (!P || !r || !z) return fail(RZ_ERR_ARG, "null argument");
+  if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  for (int c = 0; c < n_rhs; ++c) apply_P_impl(P, r + int64_t(c) * ld, z + int64_t(c) * ld, nullptr, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RZ_ERR_DEVICE, hipGetErrorString(e));
+  return RZ_OK;
+}
+
+int rz_solve(rz_problem *P, const double *b, double *x, double rtol, rz_info *info, void *hip_stream) {
+  if (!P || !b || !x) return fail(RZ_ERR_ARG, "null argument");
+  if (!(rtol > 0.0)) return fail(RZ_ERR_ARG, "rtol must be positive");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int64_t nd = P->top.n_dofs;
+  const int maxit = P->max_iter;
+  try {
+    auto t0 = std::chrono::steady_clock::now();
+    // r = b - A x, convergence reference ||b||
+    rz::launch_fill(P->Ap, nd, 0.0, nullptr, s);
+    rz::launch_apply_A(P->at, x, P->Ap, 1, nd, nullptr, s);
+    rz::launch_residual(nd, b, P->Ap, P->r, s);
+    rz::launch_dot_partial(nd, b, b, P->part, nullptr, s);
+    rz::launch_dot_partial(nd, P->r, P->r, P->part2, nullptr, s);
+    rz::launch_pcg_init(P->st, P->part, P->part2, rtol * rtol, maxit, s);
+    apply_P_impl(P, P->r, P->z, P->st, s);
+    rz::launch_dot_partial(nd, P->r, P->z, P->part, P->st, s);
+    rz::launch_set_rz(P->st, P->part, s);
+    rz::launch_copy(nd, P->z, P->pv, s);
+    HIPCHK(hipGetLastError());
+    const int chunk = 8;
+    for (int it0 = 0; it0 < maxit; it0 += chunk) {
+      for (int it = 0; it < chunk; ++it) {
+        rz::launch_fill(P->Ap, nd, 0.0, P->st, s);
+        rz::launch_apply_A(P->at, P->pv, P->Ap, 1, nd, P->st, s);
+        rz::launch_dot_partial(nd, P->pv, P->Ap, P->part, P->st, s);
+        rz::launch_finalize_alpha(P->st, P->part, s);
+        rz::launch_update_xr(nd, x, P->r, P->pv, P->Ap, P->part, P->st, s);
+        rz::launch_finalize_rr(P->st, P->part, s);
+        apply_P_impl(P, P->r, P->z, P->st, s);
+        rz::launch_dot_partial(nd, P->r, P->z, P->part, P->st, s);
+        rz::launch_finalize_beta(P->st, P->part, s);
+        rz::launch_update_p(nd, P->pv, P->z, P->st, s);
+      }
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(P->st_host, P->st, offsetof(rz::PcgState, alphas), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (P->st_host->done) break;
+    }
+    HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(rz::PcgState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    const rz::PcgState &h = *P->st_host;
+    // Lanczos condition estimate from the CG coefficients
+    double cond = 1.0;
+    const int kk = std::min(h.iter, rz::kMaxIter);
+    if (kk > 0) {
+      rz::Dense T(kk, kk);
+      for (int j = 0; j < kk; ++j) {
+        T(j, j) = 1.0 / h.alphas[j] + (j > 0 ? h.betas[j - 1] / h.alphas[j - 1] : 0.0);
+        if (j > 0) T(j, j - 1) = T(j - 1, j) = std::sqrt(std::max(0.0, h.betas[j - 1])) / h.alphas[j - 1];
+      }
+      std::vector<double> ev;
+      rz::Dense V;
+      rz::sym_eig(T, ev, V);
+      if (ev.front() > 0) cond = ev.back() / ev.front();
+    }
+    int code = RZ_OK;
+    if (h.status == rz::PCG_MAXIT) code = RZ_ERR_NO_CONVERGENCE;
+    if (h.status == rz::PCG_BREAKDOWN) code = RZ_ERR_BREAKDOWN;
+    if (info) {
+      info->status = code;
+      info->iterations = h.iter;
+      info->rel_residual = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+      info->cond_estimate = cond;
+      info->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    if (code != RZ_OK) return fail(code, code == RZ_ERR_BREAKDOWN ? "CG breakdown" : "no convergence");
+  } catch (const RzError &e) {
+    return fail(e.code, e.msg);
+  }
+  return RZ_OK;
+}
+
+int rz_export_topology(const rz_problem *P, int32_t *cell_dofs, int64_t *n_patches, int64_t *n_patch_entries,
+                       int64_t *patch_ptr, int32_t *patch_dofs) {
+  if (!P) return fail(RZ_ERR_ARG, "null handle");
+  if (cell_dofs) std::memcpy(cell_dofs, P->top.cell_dofs.data(), P->top.cell_dofs.size() * 4);
+  const rz::PatchSet &ps = P->patches.at(0);  // plain patch set (first)
+  const int64_t np = ps.n_patches();
+  if (n_patches) *n_patches = np;
+  if (n_patch_entries) *n_patch_entries = int64_t(ps.ent_dof.size());
+  if (patch_ptr && patch_dofs) {
+    for (int64_t p = 0; p <= np; ++p) patch_ptr[p] = ps.col_ent[ps.patch_col[p]];
+    std::memcpy(patch_dofs, ps.ent_dof.data(), ps.ent_dof.size() * 4);
+  }
+  return RZ_OK;
+}
+
+int rz_export_reference(const rz_problem *P, double *Rq) {
+  if (!P || !Rq) return fail(RZ_ERR_ARG, "null argument");
+  std::memcpy(Rq, P->el.R.data(), P->el.R.size() * 8);
+  return RZ_OK;
+}
+
+static int check_space(int32_t dim, int32_t degree, rz_space space, rz::Family &fam) {
+  if (dim != 2 && dim != 3) return fail(RZ_ERR_ARG, "dim must be 2 or 3");
+  if (space < RZ_HGRAD || space > RZ_HDIV) return fail(RZ_ERR_ARG, "unknown space");
+  if (degree < 1 || degree > 10) return fail(RZ_ERR_UNSUPPORTED, "degree must be in 1..10");
+  if (dim == 2 && space != RZ_HGRAD) return fail(RZ_ERR_UNSUPPORTED, "2D supports H(grad) only");
+  fam = space == RZ_HGRAD ? rz::FAM_CG : (space == RZ_HCURL ? rz::FAM_NED : rz::FAM_RT);
+  return RZ_OK;
+}
+
+int rz_reference(int32_t dim, int32_t degree, rz_space space, int32_t *n_loc, int32_t *Q, double *Rq) {
+  rz::Family fam;
+  if (int e = check_space(dim, degree, space, fam)) return e;
+  try {
+    rz::RefElement el = rz::build_reference(dim, fam, degree);
+    if (n_loc) *n_loc = el.n;
+    if (Q) *Q = el.Q;
+    if (Rq) std::memcpy(Rq, el.R.data(), el.R.size() * 8);
+  } catch (const std::exception &e) {
+    return fail(RZ_ERR_UNSUPPORTED, e.what());
+  }
+  return RZ_OK;
+}
+
+int rz_numbering(const rz_mesh *m, int32_t degree, rz_space space, int64_t *n_dofs, int32_t *cell_dofs,
+                 int64_t *n_patches, int64_t *n_patch_entries, int64_t *patch_ptr, int32_t *patch_dofs) {
+  if (!m || !m->cells) return fail(RZ_ERR_ARG, "null argument");
+  rz::Family fam;
+  if (int e = check_space(m->dim, degree, space, fam)) return e;
+  if (m->n_vertices <= 0 || m->n_cells <= 0) return fail(RZ_ERR_ARG, "empty mesh");
+  try {
+    rz::RefElement el = rz::build_reference(m->dim, fam, degree);
+    rz::Topology top = rz::build_topology(m->dim, m->n_vertices, m->n_cells, m->cells, el);
+    if (n_dofs) *n_dofs = top.n_dofs;
+    if (cell_dofs) std::memcpy(cell_dofs, top.cell_dofs.data(), top.cell_dofs.size() * 4);
+    if (n_patches || n_patch_entries || (patch_ptr && patch_dofs)) {
+      auto sets = rz::build_patches(top, el);
+      const rz::PatchSet &ps = sets.at(0);
+      const int64_t np = ps.n_patches();
+      if (n_patches) *n_patches = np;
+      if (n_patch_entries) *n_patch_entries = int64_t(ps.ent_dof.size());
+      if (patch_ptr && patch_dofs) {
+        for (int64_t p = 0; p <= np; ++p) patch_ptr[p] = ps.col_ent[ps.patch_col[p]];
+        std::memcpy(patch_dofs, ps.ent_dof.data(), ps.ent_dof.size() * 4);
+      }
+    }
+  } catch (const std::invalid_argument &e) {
+    return fail(RZ_ERR_MESH, e.what());
+  } catch (const std::exception &e) {
+    return fail(RZ_ERR_UNSUPPORTED, e.what());
+  }
+  return RZ_OK;
+}
+
+void rz_destroy(rz_problem *P) { delete P; }
+
+}  // extern "C"

@@ -1,0 +1,823 @@
+// Device kernels (gfx950, wave64) of the Riesz-map PCG solver.
+//
+// Hot path per PCG iteration (Sec. 7.1, with the preconditioners of Sec. 6):
+//  * apply_A: y = sum_T P_T^T (sum_q w_{T,q} R_q) P_T x.  Per tile of cells the
+//    gathered x_T and the weights are staged in LDS; the contraction over the
+//    stacked reference matrices is a GEMM with M = n_loc, K = Q n_loc,
+//    N = cells, done with FP64 MFMA 16x16x4 (the weight is applied to the B
+//    fragment in registers); the result is scatter-added with FP64 atomics.
+//  * apply_P: point-Jacobi on the interior block; per interface patch a
+//    gathered right-hand side (LDS), a packed symmetric inverse streamed from
+//    HBM and an atomic scatter; the Whitney coarse solve as a tiled packed
+//    symmetric matrix-vector product.
+//  * Krylov vectors: fused axpy updates with block reductions, scalars kept
+//    on the device and a done flag that makes every later kernel a no-op.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace rz {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// deterministic block sum of 256 threads; result valid in every thread
+__device__ inline double block_sum256(double v, double *sm4) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sm4[wave] = v;
+  __syncthreads();
+  return (sm4[0] + sm4[1]) + (sm4[2] + sm4[3]);
+}
+
+inline unsigned grid_for(int64_t n, int bs, unsigned cap = 1u << 20) {
+  int64_t g = (n + bs - 1) / bs;
+  if (g < 1) g = 1;
+  return unsigned(g > cap ? cap : g);
+}
+
+// ------------------------------------------------------------------ setup
+__global__ void k_weights(int d, int k, int64_t nc, const double *__restrict__ X, const double *__restrict__ Einv,
+                          double alpha, double beta, double *__restrict__ w, int Q) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const double *x = X + c * (d + 1) * d;
+  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int a = 0; a < d; ++a)
+    for (int m = 0; m < d; ++m) {
+      double s = 0;
+      for (int b = 0; b < d; ++b) s += (x[(b + 1) * d + a] - x[a]) * Einv[b * d + m];
+      J[a][m] = s;
+    }
+  double det, Ji[3][3];
+  if (d == 3) {
+    det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    const double id = 1.0 / det;
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+  } else {
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double id = 1.0 / det;
+    Ji[0][0] = J[1][1] * id;
+    Ji[0][1] = -J[0][1] * id;
+    Ji[1][0] = -J[1][0] * id;
+    Ji[1][1] = J[0][0] * id;
+  }
+  const double s = fabs(det);
+  double G[3][3], H[3][3];  // G = J^{-1} J^{-T}, H = J^T J
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      double g = 0, h = 0;
+      for (int m = 0; m < d; ++m) {
+        g += Ji[a][m] * Ji[b][m];
+        h += J[m][a] * J[m][b];
+      }
+      G[a][b] = g;
+      H[a][b] = h;
+    }
+  const int pa3[6] = {0, 1, 2, 0, 0, 1}, pb3[6] = {0, 1, 2, 1, 2, 2};
+  const int pa2[3] = {0, 1, 0}, pb2[3] = {0, 1, 1};
+  const int np = d == 3 ? 6 : 3;
+  const int *pa = d == 3 ? pa3 : pa2, *pb = d == 3 ? pb3 : pb2;
+  double *wc = w + c * Q;
+  if (k == 0) {
+    wc[0] = beta * s;
+    for (int i = 0; i < np; ++i) wc[1 + i] = alpha * s * G[pa[i]][pb[i]];
+  } else if (k == 1) {
+    for (int i = 0; i < np; ++i) {
+      wc[i] = beta * s * G[pa[i]][pb[i]];
+      wc[np + i] = alpha * H[pa[i]][pb[i]] / s;
+    }
+  } else {
+    for (int i = 0; i < np; ++i) wc[i] = beta * H[pa[i]][pb[i]] / s;
+    wc[np] = alpha / s;
+  }
+}
+
+__global__ void k_interior_diag(int64_t nc, int n, int Q, const double *__restrict__ R, const double *__restrict__ w,
+                                const int32_t *__restrict__ cd, const int32_t *__restrict__ loc, int nloc,
+                                int64_t offI, double *__restrict__ dinv) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nc * nloc) return;
+  const int64_t c = t / nloc;
+  const int li = loc[t - c * nloc];
+  double s = 0;
+  for (int q = 0; q < Q; ++q) s += w[c * Q + q] * R[(size_t(q) * n + li) * n + li];
+  dinv[cd[c * n + li] - offI] = 1.0 / s;
+}
+
+__global__ void k_pad_identity(int64_t B, int N, const int32_t *__restrict__ sizes, double *__restrict__ A) {
+  const int64_t b = blockIdx.x;
+  for (int i = sizes[b] + threadIdx.x; i < N; i += blockDim.x) A[(b * N + i) * N + i] = 1.0;
+}
+
+__global__ void k_patch_assemble(const int32_t *__restrict__ item_patch, const int32_t *__restrict__ item_cell,
+                                 const int64_t *__restrict__ item_trip, const int32_t *__restrict__ tr_col,
+                                 const int32_t *__restrict__ tr_loc, const double *__restrict__ tr_coef, int n, int Q,
+                                 const double *__restrict__ R, const double *__restrict__ w, int N,
+                                 double *__restrict__ A) {
+  const int64_t it = blockIdx.x;
+  const int64_t t0 = item_trip[it], cnt = item_trip[it + 1] - t0;
+  const int64_t c = item_cell[it];
+  double *Ap = A + int64_t(item_patch[it]) * N * N;
+  double wq[16];
+  for (int q = 0; q < Q; ++q) wq[q] = w[c * Q + q];
+  for (int64_t pi = threadIdx.x; pi < cnt * cnt; pi += blockDim.x) {
+    const int64_t a = t0 + pi / cnt, b = t0 + pi % cnt;
+    const int la = tr_loc[a], lb = tr_loc[b];
+    double s = 0;
+    for (int q = 0; q < Q; ++q) s += wq[q] * R[(size_t(q) * n + la) * n + lb];
+    atomicAdd(&Ap[int64_t(tr_col[a]) * N + tr_col[b]], tr_coef[a] * tr_coef[b] * s);
+  }
+}
+
+// ---- batched blocked Cholesky (lower) and inverse, block size 32
+constexpr int BS = 32;
+
+__global__ void k_chol_diag(int N, int kb, double *__restrict__ A, int *__restrict__ status) {
+  __shared__ double L[BS][BS + 1];
+  __shared__ double piv;
+  double *M = A + int64_t(blockIdx.x) * N * N;
+  const int o = kb * BS;
+  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+    const int i = t / BS, j = t % BS;
+    L[i][j] = M[int64_t(o + i) * N + o + j];
+  }
+  __syncthreads();
+  for (int j = 0; j < BS; ++j) {
+    if (threadIdx.x == 0) {
+      double a = L[j][j];
+      if (!(a > 0.0)) {
+        atomicExch(status, 1);
+        a = 1.0;
+      }
+      piv = sqrt(a);
+      L[j][j] = piv;
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < BS; i += blockDim.x) L[i][j] /= piv;
+    __syncthreads();
+    for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+      const int i = t / BS, m = t % BS;
+      if (i > j && m > j && m <= i) L[i][m] -= L[i][j] * L[m][j];
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+    const int i = t / BS, j = t % BS;
+    M[int64_t(o + i) * N + o + j] = j <= i ? L[i][j] : 0.0;
+  }
+}
+
+__global__ void k_chol_panel(int N, int kb, double *__restrict__ A) {
+  __shared__ double L[BS][BS + 1];
+  __shared__ double X[BS][BS + 1];
+  double *M = A + int64_t(blockIdx.y) * N * N;
+  const int o = kb * BS, ob = (kb + 1 + blockIdx.x) * BS;
+  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+    const int i = t / BS, j = t % BS;
+    L[i][j] = M[int64_t(o + i) * N + o + j];
+    X[i][j] = M[int64_t(ob + i) * N + o + j];
+  }
+  __syncthreads();
+  // X L^T = A_block, row by row
+  if (threadIdx.x < BS) {
+    const int r = threadIdx.x;
+    for (int c = 0; c < BS; ++c) {
+      double s = X[r][c];
+      for (int m = 0; m < c; ++m) s -= X[r][m] * L[c][m];
+      X[r][c] = s / L[c][c];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+    const int i = t / BS, j = t % BS;
+    M[int64_t(ob + i) * N + o + j] = X[i][j];
+  }
+}
+
+__device__ inline void tri_decode(int64_t t, int &i, int &j) {
+  int ii = int((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
+  while (int64_t(ii + 1) * (ii + 2) / 2 <= t) ++ii;
+  while (int64_t(ii) * (ii + 1) / 2 > t) --ii;
+  i = ii;
+  j = int(t - int64_t(ii) * (ii + 1) / 2);
+}
+
+__global__ void k_chol_update(int N, int kb, double *__restrict__ A) {
+  __shared__ double La[BS][BS + 1];
+  __shared__ double Lb[BS][BS + 1];
+  double *M = A + int64_t(blockIdx.y) * N * N;
+  int i_, j_;
+  tri_decode(blockIdx.x, i_, j_);
+  const int o = kb * BS, oi = (kb + 1 + i_) * BS, oj = (kb + 1 + j_) * BS;
+  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+    const int i = t / BS, j = t % BS;
+    La[i][j] = M[int64_t(oi + i) * N + o + j];
+    Lb[i][j] = M[int64_t(oj + i) * N + o + j];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+    const int i = t / BS, j = t % BS;
+    double s = 0;
+#pragma unroll 8
+    for (int m = 0; m < BS; ++m) s += La[i][m] * Lb[j][m];
+    M[int64_t(oi + i) * N + oj + j] -= s;
+  }
+}
+
+// one block row step of X = L^{-1}: X[jb + s][jb] for every column block jb
+__global__ void k_trtri_step(int N, int s, const double *__restrict__ A, double *__restrict__ X) {
+  __shared__ double Lt[BS][BS + 1];
+  __shared__ double Xt[BS][BS + 1];
+  __shared__ double S[BS][BS + 1];
+  const int NB = N / BS;
+  const int jb = blockIdx.x, ib = jb + s;
+  if (ib >= NB) return;
+  const double *M = A + int64_t(blockIdx.y) * N * N;
+  double *Y = X + int64_t(blockIdx.y) * N * N;
+  const int oi = ib * BS, oj = jb * BS;
+  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+    const int i = t / BS, j = t % BS;
+    S[i][j] = (s == 0 && i == j) ? 1.0 : 0.0;
+  }
+  for (int mb = jb; mb < ib; ++mb) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+      const int i = t / BS, j = t % BS;
+      Lt[i][j] = M[int64_t(oi + i) * N + mb * BS + j];
+      Xt[i][j] = Y[int64_t(mb * BS + i) * N + oj + j];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+      const int i = t / BS, j = t % BS;
+      double acc = 0;
+#pragma unroll 8
+      for (int m = 0; m < BS; ++m) acc += Lt[i][m] * Xt[m][j];
+      S[i][j] -= acc;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+    const int i = t / BS, j = t % BS;
+    Lt[i][j] = M[int64_t(oi + i) * N + oi + j];
+  }
+  __syncthreads();
+  if (threadIdx.x < BS) {  // forward substitution, one column each
+    const int c = threadIdx.x;
+    for (int r = 0; r < BS; ++r) {
+      double v = S[r][c];
+      for (int m = 0; m < r; ++m) v -= Lt[r][m] * S[m][c];
+      S[r][c] = v / Lt[r][r];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+    const int i = t / BS, j = t % BS;
+    Y[int64_t(oi + i) * N + oj + j] = S[i][j];
+  }
+}
+
+// A^{-1} = X^T X with X = L^{-1} lower triangular: tile (I >= J)
+__global__ void k_lauum(int N, const double *__restrict__ X, double *__restrict__ A) {
+  __shared__ double Xa[BS][BS + 1];
+  __shared__ double Xb[BS][BS + 1];
+  const int NB = N / BS;
+  int I, J;
+  tri_decode(blockIdx.x, I, J);
+  const double *Y = X + int64_t(blockIdx.y) * N * N;
+  double *M = A + int64_t(blockIdx.y) * N * N;
+  double acc[(BS * BS) / 256];
+  for (int e = 0; e < (BS * BS) / 256; ++e) acc[e] = 0;
+  for (int K = I; K < NB; ++K) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+      const int i = t / BS, j = t % BS;
+      Xa[i][j] = Y[int64_t(K * BS + i) * N + I * BS + j];
+      Xb[i][j] = Y[int64_t(K * BS + i) * N + J * BS + j];
+    }
+    __syncthreads();
+    for (int e = 0; e < (BS * BS) / 256; ++e) {
+      const int t = threadIdx.x + e * 256;
+      const int i = t / BS, j = t % BS;
+      double s = 0;
+#pragma unroll 8
+      for (int m = 0; m < BS; ++m) s += Xa[m][i] * Xb[m][j];
+      acc[e] += s;
+    }
+  }
+  for (int e = 0; e < (BS * BS) / 256; ++e) {
+    const int t = threadIdx.x + e * 256;
+    const int i = t / BS, j = t % BS;
+    M[int64_t(I * BS + i) * N + J * BS + j] = acc[e];
+    M[int64_t(J * BS + j) * N + I * BS + i] = acc[e];
+  }
+}
+
+__global__ void k_pack_upper(int N, const int32_t *__restrict__ sizes, const int64_t *__restrict__ off,
+                             const double *__restrict__ A, double *__restrict__ P) {
+  const int64_t b = blockIdx.x;
+  const int m = sizes[b];
+  const double *M = A + b * N * N;
+  double *out = P + off[b];
+  for (int i = 0; i < m; ++i) {
+    const int64_t ro = int64_t(i) * m - int64_t(i) * (i - 1) / 2 - i;
+    for (int j = i + threadIdx.x; j < m; j += blockDim.x) out[ro + j] = M[int64_t(i) * N + j];
+  }
+}
+
+__global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A, double *__restrict__ T) {
+  const int64_t t = blockIdx.x;
+  // decode upper tile (I <= J): t = I*NT - I(I-1)/2 + (J - I)
+  int I = 0;
+  while (int64_t(I + 1) * NT - int64_t(I + 1) * I / 2 <= t) ++I;
+  const int J = int(t - (int64_t(I) * NT - int64_t(I) * (I - 1) / 2)) + I;
+  double *out = T + t * 64 * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+    const int r = e / 64, c = e % 64;
+    const int gi = I * 64 + r, gj = J * 64 + c;
+    out[e] = (gi < n && gj < n) ? A[int64_t(gi) * N + gj] : 0.0;
+  }
+}
+
+// -------------------------------------------------------------- apply_A
+template <int NT>
+__global__ __launch_bounds__(256) void k_apply_A(int n, int Q, int NMB, int KB, int64_t nc,
+                                                 const double *__restrict__ Af, const double *__restrict__ w,
+                                                 const int32_t *__restrict__ cd, const double *__restrict__ x,
+                                                 double *__restrict__ y, int64_t ld, const PcgState *st) {
+  if (st && st->done) return;
+  extern __shared__ double smem[];
+  const int KP = KB * 4, S = KP + 1;
+  double *xs = smem;           // NT x S
+  double *ws = smem + NT * S;  // Q x NT
+  const int64_t cell0 = int64_t(blockIdx.x) * NT;
+  const double *xr = x + int64_t(blockIdx.z) * ld;
+  double *yr = y + int64_t(blockIdx.z) * ld;
+  for (int idx = threadIdx.x; idx < NT * KP; idx += 256) {
+    const int c = idx / KP, j = idx - c * KP;
+    const int64_t cell = cell0 + c;
+    xs[c * S + j] = (cell < nc && j < n) ? xr[cd[cell * n + j]] : 0.0;
+  }
+  for (int idx = threadIdx.x; idx < NT * Q; idx += 256) {
+    const int c = idx / Q, q = idx - c * Q;
+    const int64_t cell = cell0 + c;
+    ws[q * NT + c] = cell < nc ? w[cell * Q + q] : 0.0;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mb = blockIdx.y * 4 + wave;
+  if (mb >= NMB) return;
+  const int li = lane & 15, lk = lane >> 4;
+  d4 acc[NT / 16];
+#pragma unroll
+  for (int nb = 0; nb < NT / 16; ++nb) acc[nb] = d4{0, 0, 0, 0};
+  const double *Ab = Af + size_t(mb) * Q * KB * 64 + lane;
+  for (int q = 0; q < Q; ++q) {
+    double wq[NT / 16];
+#pragma unroll
+    for (int nb = 0; nb < NT / 16; ++nb) wq[nb] = ws[q * NT + nb * 16 + li];
+    const double *Aq = Ab + size_t(q) * KB * 64;
+    const double *xq = xs + li * S + lk;
+#pragma unroll 4
+    for (int kb = 0; kb < KB; ++kb) {
+      const double a = Aq[kb * 64];
+#pragma unroll
+      for (int nb = 0; nb < NT / 16; ++nb) {
+        const double b = wq[nb] * xq[nb * 16 * S + kb * 4];
+        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[nb], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int nb = 0; nb < NT / 16; ++nb) {
+    const int64_t cell = cell0 + nb * 16 + li;
+    if (cell >= nc) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      // FP64 16x16x4 accumulator layout: lane l, element v holds row l/16 + 4v, column l%16
+      const int row = mb * 16 + lk + 4 * v;
+      if (row < n) atomicAdd(&yr[cd[cell * n + row]], acc[nb][v]);
+    }
+  }
+}
+
+__global__ void k_fill(double *y, int64_t n, double v, const PcgState *st) {
+  if (st && st->done) return;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = v;
+}
+
+// -------------------------------------------------------------- apply_P
+template <int MAXJ>
+__global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__ patch_col,
+                                                     const int64_t *__restrict__ col_ent,
+                                                     const int32_t *__restrict__ ent_dof,
+                                                     const double *__restrict__ ent_coef,
+                                                     const int64_t *__restrict__ inv_off,
+                                                     const double *__restrict__ inv, const double *__restrict__ r,
+                                                     double *__restrict__ z, int maxsz, const PcgState *st) {
+  if (st && st->done) return;
+  extern __shared__ double sm[];
+  double *rp = sm;              // gathered right-hand side
+  double *yr = sm + maxsz;      // row products
+  double *yc = sm + 2 * maxsz;  // 4 x column partials
+  const int64_t p = blockIdx.x;
+  const int64_t c0 = patch_col[p];
+  const int m = int(patch_col[p + 1] - c0);
+  for (int j = threadIdx.x; j < m; j += 256) {
+    double s = 0;
+    for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) s += ent_coef[e] * r[ent_dof[e]];
+    rp[j] = s;
+  }
+  __syncthreads();
+  const double *A = inv + inv_off[p];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double cacc[MAXJ];
+#pragma unroll
+  for (int jb = 0; jb < MAXJ; ++jb) cacc[jb] = 0;
+  for (int i = wave; i < m; i += 4) {
+    const double *row = A + int64_t(i) * m - int64_t(i) * (i - 1) / 2 - i;  // row[j] = A_ij, j >= i
+    const double ri = rp[i];
+    double rs = 0;
+#pragma unroll
+    for (int jb = 0; jb < MAXJ; ++jb) {
+      const int j = jb * 64 + lane;
+      if (j >= i && j < m) {
+        const double a = row[j];
+        rs += a * rp[j];
+        if (j > i) cacc[jb] += a * ri;
+      }
+    }
+    rs = wave_sum(rs);
+    if (lane == 0) yr[i] = rs;
+  }
+#pragma unroll
+  for (int jb = 0; jb < MAXJ; ++jb) {
+    const int j = jb * 64 + lane;
+    if (j < m) yc[wave * maxsz + j] = cacc[jb];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < m; j += 256) {
+    const double y = yr[j] + ((yc[j] + yc[maxsz + j]) + (yc[2 * maxsz + j] + yc[3 * maxsz + j]));
+    for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) atomicAdd(&z[ent_dof[e]], ent_coef[e] * y);
+  }
+}
+
+__global__ void k_jacobi(int64_t n, int64_t offI, const double *__restrict__ dinv, const double *__restrict__ r,
+                         double *__restrict__ z, const PcgState *st) {
+  if (st && st->done) return;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    z[i] = i >= offI ? r[i] * dinv[i - offI] : 0.0;
+}
+
+__global__ void k_coarse_gather(int nW, int npad, const int32_t *__restrict__ wd, const double *__restrict__ r,
+                                double *__restrict__ rW, double *__restrict__ zW, const PcgState *st) {
+  if (st && st->done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  rW[i] = i < nW ? r[wd[i]] : 0.0;
+  zW[i] = 0.0;
+}
+
+__global__ __launch_bounds__(64) void k_coarse_tiles(int NT, const double *__restrict__ T,
+                                                     const double *__restrict__ rW, double *__restrict__ zW,
+                                                     const PcgState *st) {
+  if (st && st->done) return;
+  __shared__ double tr[64][65];
+  const int64_t t = blockIdx.x;
+  int I = 0;
+  while (int64_t(I + 1) * NT - int64_t(I + 1) * I / 2 <= t) ++I;
+  const int J = int(t - (int64_t(I) * NT - int64_t(I) * (I - 1) / 2)) + I;
+  const int c = threadIdx.x;
+  const double *tile = T + t * 4096;
+  const double rJc = rW[J * 64 + c];
+  double col = 0;
+  for (int r = 0; r < 64; ++r) {
+    const double a = tile[r * 64 + c];
+    col += a * rW[I * 64 + r];
+    tr[r][c] = a * rJc;
+  }
+  __syncthreads();
+  double row = 0;
+  for (int cc = 0; cc < 64; ++cc) row += tr[c][cc];
+  atomicAdd(&zW[I * 64 + c], row);
+  if (I < J) atomicAdd(&zW[J * 64 + c], col);
+}
+
+__global__ void k_coarse_scatter(int nW, const int32_t *__restrict__ wd, const double *__restrict__ zW,
+                                 double *__restrict__ z, const PcgState *st) {
+  if (st && st->done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nW) z[wd[i]] += zW[i];
+}
+
+// -------------------------------------------------------------- Krylov
+__global__ __launch_bounds__(256) void k_dot_partial(int64_t n, const double *__restrict__ a,
+                                                     const double *__restrict__ b, double *__restrict__ part,
+                                                     const PcgState *st) {
+  if (st && st->done) return;
+  __shared__ double sm4[4];
+  double s = 0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) s += a[i] * b[i];
+  s = block_sum256(s, sm4);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__device__ inline double sum_partials(const double *part, double *sm4) {
+  double s = 0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += 256) s += part[i];
+  return block_sum256(s, sm4);
+}
+
+__global__ __launch_bounds__(256) void k_pcg_init(PcgState *st, const double *part, const double *part2, double tol2,
+                                                  int maxit) {
+  __shared__ double sm4[4];
+  const double bb = sum_partials(part, sm4);
+  const double rr = sum_partials(part2, sm4);
+  if (threadIdx.x == 0) {
+    st->bb = bb;
+    st->rr = rr;
+    st->tol2 = tol2;
+    st->iter = 0;
+    st->maxit = maxit;
+    st->status = PCG_RUNNING;
+    st->done = 0;
+    if (!(bb > 0.0) || rr <= tol2 * bb) {
+      st->done = 1;
+      st->status = PCG_CONVERGED;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_set_rz(PcgState *st, const double *part) {
+  if (st->done) return;
+  __shared__ double sm4[4];
+  const double rz = sum_partials(part, sm4);
+  if (threadIdx.x == 0) {
+    st->rz = rz;
+    if (!(rz > 0.0) || !isfinite(rz)) {
+      st->done = 1;
+      st->status = PCG_BREAKDOWN;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_finalize_alpha(PcgState *st, const double *part) {
+  if (st->done) return;
+  __shared__ double sm4[4];
+  const double pAp = sum_partials(part, sm4);
+  if (threadIdx.x == 0) {
+    st->pAp = pAp;
+    if (!(pAp > 0.0) || !isfinite(pAp)) {
+      st->done = 1;
+      st->status = PCG_BREAKDOWN;
+    } else {
+      st->alpha = st->rz / pAp;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_update_xr(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                   const double *__restrict__ p, const double *__restrict__ Ap,
+                                                   double *__restrict__ part, const PcgState *st) {
+  if (st->done) return;
+  __shared__ double sm4[4];
+  const double alpha = st->alpha;
+  double s = 0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * Ap[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  s = block_sum256(s, sm4);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_finalize_rr(PcgState *st, const double *part) {
+  if (st->done) return;
+  __shared__ double sm4[4];
+  const double rr = sum_partials(part, sm4);
+  if (threadIdx.x == 0) {
+    st->rr = rr;
+    const int it = st->iter;
+    if (it < kMaxIter) st->alphas[it] = st->alpha;
+    st->iter = it + 1;
+    if (!isfinite(rr)) {
+      st->done = 1;
+      st->status = PCG_BREAKDOWN;
+    } else if (rr <= st->tol2 * st->bb) {
+      st->done = 1;
+      st->status = PCG_CONVERGED;
+    } else if (it + 1 >= st->maxit) {
+      st->done = 1;
+      st->status = PCG_MAXIT;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_finalize_beta(PcgState *st, const double *part) {
+  if (st->done) return;
+  __shared__ double sm4[4];
+  const double rz = sum_partials(part, sm4);
+  if (threadIdx.x == 0) {
+    if (!(rz > 0.0) || !isfinite(rz)) {
+      st->done = 1;
+      st->status = PCG_BREAKDOWN;
+      return;
+    }
+    const double beta = rz / st->rz;
+    st->beta = beta;
+    st->rz = rz;
+    if (st->iter - 1 < kMaxIter) st->betas[st->iter - 1] = beta;
+  }
+}
+
+__global__ void k_update_p(int64_t n, double *__restrict__ p, const double *__restrict__ z, const PcgState *st) {
+  if (st->done) return;
+  const double beta = st->beta;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_residual(int64_t n, const double *__restrict__ b, const double *__restrict__ Ax,
+                           double *__restrict__ r) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    r[i] = b[i] - Ax[i];
+}
+
+__global__ void k_copy(int64_t n, const double *__restrict__ a, double *__restrict__ b) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    b[i] = a[i];
+}
+
+}  // namespace
+
+// ================================================================ launchers
+void launch_weights(int d, int k, int64_t n_cells, const double *X, const double *Einv, double alpha, double beta,
+                    double *w, int Q, hipStream_t s) {
+  hipLaunchKernelGGL(k_weights, dim3(grid_for(n_cells, 128)), dim3(128), 0, s, d, k, n_cells, X, Einv, alpha, beta,
+                     w, Q);
+}
+
+void launch_interior_diag(int64_t n_cells, int n, int Q, const double *R, const double *w, const int32_t *cell_dofs,
+                          const int32_t *loc_interior, int n_int_loc, int64_t off_I, double *dinv, hipStream_t s) {
+  if (n_int_loc == 0) return;
+  hipLaunchKernelGGL(k_interior_diag, dim3(grid_for(n_cells * n_int_loc, 256)), dim3(256), 0, s, n_cells, n, Q, R,
+                     w, cell_dofs, loc_interior, n_int_loc, off_I, dinv);
+}
+
+void launch_pad_identity(int64_t B, int N, const int32_t *sizes, double *A, hipStream_t s) {
+  hipLaunchKernelGGL(k_pad_identity, dim3(unsigned(B)), dim3(64), 0, s, B, N, sizes, A);
+}
+
+void launch_patch_assemble(int64_t n_items, const int32_t *item_patch, const int32_t *item_cell,
+                           const int64_t *item_trip, const int32_t *tr_col, const int32_t *tr_loc,
+                           const double *tr_coef, int n, int Q, const double *R, const double *w, int N, double *A,
+                           hipStream_t s) {
+  if (n_items == 0) return;
+  hipLaunchKernelGGL(k_patch_assemble, dim3(unsigned(n_items)), dim3(256), 0, s, item_patch, item_cell, item_trip,
+                     tr_col, tr_loc, tr_coef, n, Q, R, w, N, A);
+}
+
+void launch_chol_inverse(int64_t B, int N, double *A, double *Linv, int *status, hipStream_t s) {
+  const int NB = N / BS;
+  for (int kb = 0; kb < NB; ++kb) {
+    hipLaunchKernelGGL(k_chol_diag, dim3(unsigned(B)), dim3(256), 0, s, N, kb, A, status);
+    const int m = NB - kb - 1;
+    if (m > 0) {
+      hipLaunchKernelGGL(k_chol_panel, dim3(m, unsigned(B)), dim3(256), 0, s, N, kb, A);
+      hipLaunchKernelGGL(k_chol_update, dim3(unsigned(int64_t(m) * (m + 1) / 2), unsigned(B)), dim3(256), 0, s, N,
+                         kb, A);
+    }
+  }
+  for (int st = 0; st < NB; ++st)
+    hipLaunchKernelGGL(k_trtri_step, dim3(NB - st, unsigned(B)), dim3(256), 0, s, N, st, A, Linv);
+  hipLaunchKernelGGL(k_lauum, dim3(unsigned(int64_t(NB) * (NB + 1) / 2), unsigned(B)), dim3(256), 0, s, N, Linv, A);
+}
+
+void launch_pack_upper(int64_t B, int N, const int32_t *sizes, const int64_t *off, const double *Ainv,
+                       double *packed, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_upper, dim3(unsigned(B)), dim3(256), 0, s, N, sizes, off, Ainv, packed);
+}
+
+void launch_pack_tiles(int N, int n, const double *Ainv, double *tiles, hipStream_t s) {
+  const int NT = (n + 63) / 64;
+  hipLaunchKernelGGL(k_pack_tiles, dim3(unsigned(int64_t(NT) * (NT + 1) / 2)), dim3(256), 0, s, N, n, NT, Ainv,
+                     tiles);
+}
+
+void launch_apply_A(const ApplyATables &t, const double *x, double *y, int n_rhs, int64_t ld, const PcgState *st,
+                    hipStream_t s) {
+  const int KB = t.KP / 4, NMB = t.NP / 16;
+  const int S = t.KP + 1;
+  int NT = 64;
+  while (NT > 16 && (size_t(NT) * S + size_t(t.Q) * NT) * 8 > 64 * 1024) NT /= 2;
+  const size_t lds = (size_t(NT) * S + size_t(t.Q) * NT) * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {  // allow up to the 160 KB of LDS a gfx950 CU has
+    (void)hipFuncSetAttribute((const void *)k_apply_A<64>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_apply_A<32>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_apply_A<16>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  dim3 grid(unsigned((t.n_cells + NT - 1) / NT), unsigned((NMB + 3) / 4), unsigned(n_rhs));
+  if (NT == 64)
+    hipLaunchKernelGGL(k_apply_A<64>, grid, dim3(256), lds, s, t.n, t.Q, NMB, KB, t.n_cells, t.Afrag, t.w,
+                       t.cell_dofs, x, y, ld, st);
+  else if (NT == 32)
+    hipLaunchKernelGGL(k_apply_A<32>, grid, dim3(256), lds, s, t.n, t.Q, NMB, KB, t.n_cells, t.Afrag, t.w,
+                       t.cell_dofs, x, y, ld, st);
+  else
+    hipLaunchKernelGGL(k_apply_A<16>, grid, dim3(256), lds, s, t.n, t.Q, NMB, KB, t.n_cells, t.Afrag, t.w,
+                       t.cell_dofs, x, y, ld, st);
+}
+
+void launch_fill(double *y, int64_t n, double v, const PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, y, n, v, st);
+}
+
+void launch_patch_apply(const PatchApply &pa, const double *r, double *z, const PcgState *st, hipStream_t s) {
+  if (pa.n_patches == 0) return;
+  const size_t lds = size_t(6) * pa.max_size * sizeof(double);
+  const int nj = (pa.max_size + 63) / 64;
+  dim3 g(unsigned(pa.n_patches)), b(256);
+#define RZ_PATCH(MJ)                                                                                        \
+  hipLaunchKernelGGL(k_patch_apply<MJ>, g, b, lds, s, pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, \
+                     pa.inv_off, pa.inv, r, z, pa.max_size, st)
+  if (nj <= 1) RZ_PATCH(1);
+  else if (nj <= 2) RZ_PATCH(2);
+  else if (nj <= 4) RZ_PATCH(4);
+  else if (nj <= 8) RZ_PATCH(8);
+  else if (nj <= 16) RZ_PATCH(16);
+  else RZ_PATCH(24);
+#undef RZ_PATCH
+}
+
+void launch_jacobi(int64_t n_dofs, int64_t off_I, const double *dinv, const double *r, double *z,
+                   const PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_jacobi, dim3(grid_for(n_dofs, 256, 4096)), dim3(256), 0, s, n_dofs, off_I, dinv, r, z, st);
+}
+
+void launch_coarse_apply(const CoarseApply &ca, const double *r, double *z, const PcgState *st, hipStream_t s) {
+  const int npad = ca.NT * 64;
+  hipLaunchKernelGGL(k_coarse_gather, dim3(grid_for(npad, 256)), dim3(256), 0, s, ca.nW, npad, ca.wdofs, r, ca.rW,
+                     ca.zW, st);
+  hipLaunchKernelGGL(k_coarse_tiles, dim3(unsigned(int64_t(ca.NT) * (ca.NT + 1) / 2)), dim3(64), 0, s, ca.NT,
+                     ca.tiles, ca.rW, ca.zW, st);
+  hipLaunchKernelGGL(k_coarse_scatter, dim3(grid_for(ca.nW, 256)), dim3(256), 0, s, ca.nW, ca.wdofs, ca.zW, z, st);
+}
+
+void launch_dot_partial(int64_t n, const double *a, const double *b, double *part, const PcgState *st,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s, n, a, b, part, st);
+}
+void launch_pcg_init(PcgState *st, const double *part, const double *part2, double tol2, int maxit, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(256), 0, s, st, part, part2, tol2, maxit);
+}
+void launch_set_rz(PcgState *st, const double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_rz, dim3(1), dim3(256), 0, s, st, part);
+}
+void launch_finalize_alpha(PcgState *st, const double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(256), 0, s, st, part);
+}
+void launch_update_xr(int64_t n, double *x, double *r, const double *p, const double *Ap, double *part,
+                      const PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_xr, dim3(kRedBlocks), dim3(256), 0, s, n, x, r, p, Ap, part, st);
+}
+void launch_finalize_rr(PcgState *st, const double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_rr, dim3(1), dim3(256), 0, s, st, part);
+}
+void launch_finalize_beta(PcgState *st, const double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_beta, dim3(1), dim3(256), 0, s, st, part);
+}
+void launch_update_p(int64_t n, double *p, const double *z, const PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, p, z, st);
+}
+void launch_residual(int64_t n, const double *b, const double *Ax, double *r, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, b, Ax, r);
+}
+void launch_copy(int64_t n, const double *a, double *b, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, a, b);
+}
+
+}  // namespace rz

@@ -1,0 +1,313 @@
+// Mesh topology, entity-major numbering and the interface patches of Sec. 6.
+//
+// Orientation (Sec. 5, the global basis of Rognes et al.): cell vertices are
+// sorted by global number and each local subsimplex with ascending local
+// vertex tuple is the global subsimplex with the same (sorted) global tuple,
+// so neighbouring cells agree on every shared trace without permutations or
+// signs.  Numbering: all vertex dofs, then edges, faces and cell interiors
+// (last, contiguous); entities of one dimension in lexicographic order of
+// their sorted vertex tuples; dof = offset(dim) + id * N_dim + j.
+#include "topology.hpp"
+
+#include <algorithm>
+#include <numeric>
+#include <stdexcept>
+
+namespace rz {
+
+namespace {
+
+std::vector<std::vector<int>> combos(int npts, int k) {
+  std::vector<std::vector<int>> out;
+  std::vector<int> sel(k);
+  std::iota(sel.begin(), sel.end(), 0);
+  while (true) {
+    out.push_back(sel);
+    int i = k - 1;
+    while (i >= 0 && sel[i] == npts - k + i) --i;
+    if (i < 0) break;
+    ++sel[i];
+    for (int j = i + 1; j < k; ++j) sel[j] = sel[j - 1] + 1;
+  }
+  return out;
+}
+
+}  // namespace
+
+Topology build_topology(int d, int64_t nv, int64_t nc, const int64_t *cells, const RefElement &el) {
+  Topology t;
+  t.d = d;
+  t.n_vertices = nv;
+  t.n_cells = nc;
+  const int nvc = d + 1;
+  t.cells.assign(cells, cells + nc * nvc);
+  for (int64_t c = 0; c < nc; ++c) {
+    int64_t *cv = &t.cells[c * nvc];
+    for (int a = 0; a < nvc; ++a)
+      if (cv[a] < 0 || cv[a] >= nv) throw std::invalid_argument("cell vertex index out of range");
+    std::sort(cv, cv + nvc);
+    for (int a = 1; a < nvc; ++a)
+      if (cv[a] == cv[a - 1]) throw std::invalid_argument("repeated vertex in a cell");
+  }
+  t.ent.resize(d + 1);
+  t.cell_ent.resize(d + 1);
+  t.n_ent.assign(d + 1, 0);
+  for (int l = 0; l <= d; ++l) {
+    auto loc = combos(nvc, l + 1);
+    const int ns = int(loc.size());
+    auto &ce = t.cell_ent[l];
+    ce.resize(nc * ns);
+    if (l == 0) {
+      t.n_ent[0] = nv;
+      t.ent[0].resize(nv);
+      std::iota(t.ent[0].begin(), t.ent[0].end(), 0);
+      for (int64_t i = 0; i < nc * ns; ++i) ce[i] = t.cells[i];
+      continue;
+    }
+    if (l == d) {
+      t.n_ent[d] = nc;
+      t.ent[d] = t.cells;
+      for (int64_t c = 0; c < nc; ++c) ce[c] = c;
+      continue;
+    }
+    const int w = l + 1;
+    std::vector<int64_t> tup(nc * ns * w);
+    for (int64_t c = 0; c < nc; ++c)
+      for (int s = 0; s < ns; ++s)
+        for (int a = 0; a < w; ++a) tup[(c * ns + s) * w + a] = t.cells[c * nvc + loc[s][a]];
+    std::vector<int64_t> order(nc * ns);
+    std::iota(order.begin(), order.end(), 0);
+    auto less = [&](int64_t x, int64_t y) {
+      for (int a = 0; a < w; ++a) {
+        if (tup[x * w + a] != tup[y * w + a]) return tup[x * w + a] < tup[y * w + a];
+      }
+      return false;
+    };
+    std::sort(order.begin(), order.end(), less);
+    int64_t id = -1;
+    for (size_t i = 0; i < order.size(); ++i) {
+      if (i == 0 || less(order[i - 1], order[i])) {
+        ++id;
+        for (int a = 0; a < w; ++a) t.ent[l].push_back(tup[order[i] * w + a]);
+      }
+      ce[order[i]] = id;
+    }
+    t.n_ent[l] = id + 1;
+  }
+  t.offset.assign(d + 2, 0);
+  for (int l = 0; l <= d; ++l) t.offset[l + 1] = t.offset[l] + t.n_ent[l] * el.per_entity[l];
+  t.n_dofs = t.offset[d + 1];
+  t.n_interior = t.n_ent[d] * el.per_entity[d];
+  if (t.n_dofs >= (int64_t(1) << 31)) throw std::invalid_argument("more than 2^31 dofs");
+  t.cell_dofs.resize(nc * el.n);
+  std::vector<int> nsub(d + 1);
+  for (int l = 0; l <= d; ++l) nsub[l] = int(combos(nvc, l + 1).size());
+  for (int64_t c = 0; c < nc; ++c)
+    for (int i = 0; i < el.n; ++i) {
+      const LocalDof &ld = el.dofs[i];
+      const int l = ld.entity_dim;
+      const int64_t e = t.cell_ent[l][c * nsub[l] + ld.entity_index];
+      t.cell_dofs[c * el.n + i] =
+          int32_t(t.offset[l] + e * el.per_entity[l] + el.kind_start[3 * l + ld.kind] + ld.j);
+    }
+  return t;
+}
+
+int64_t PatchSet::max_size() const {
+  int64_t m = 0;
+  for (int64_t p = 0; p + 1 < int64_t(patch_col.size()); ++p) m = std::max(m, patch_col[p + 1] - patch_col[p]);
+  return m;
+}
+
+namespace {
+
+// dofs of entity (l, e) of the given kind (-1: all kinds)
+void entity_dofs(const Topology &t, const RefElement &el, int l, int64_t e, int kind, std::vector<int32_t> &out) {
+  const int N = el.per_entity[l];
+  const int64_t base = t.offset[l] + e * N;
+  for (int j = 0; j < N; ++j) {
+    int kj = KIND_W;
+    for (int kk = 0; kk < 3; ++kk)
+      if (el.kind_start[3 * l + kk] >= 0 && j >= el.kind_start[3 * l + kk]) kj = kk;
+    if (kind < 0 || kj == kind) out.push_back(int32_t(base + j));
+  }
+}
+
+struct Incidence {
+  std::vector<std::vector<int64_t>> v_edges, v_faces, v_cells, e_faces, e_cells;
+};
+
+Incidence incidence(const Topology &t) {
+  Incidence in;
+  const int d = t.d;
+  in.v_edges.resize(t.n_vertices);
+  in.v_faces.resize(t.n_vertices);
+  in.v_cells.resize(t.n_vertices);
+  for (int64_t e = 0; e < t.n_ent[1]; ++e)
+    for (int a = 0; a < 2; ++a) in.v_edges[t.ent[1][e * 2 + a]].push_back(e);
+  for (int64_t c = 0; c < t.n_cells; ++c)
+    for (int a = 0; a <= d; ++a) in.v_cells[t.cells[c * (d + 1) + a]].push_back(c);
+  if (d == 3) {
+    in.e_faces.resize(t.n_ent[1]);
+    in.e_cells.resize(t.n_ent[1]);
+    for (int64_t f = 0; f < t.n_ent[2]; ++f) {
+      for (int a = 0; a < 3; ++a) in.v_faces[t.ent[2][f * 3 + a]].push_back(f);
+      // the three edges of face f are cell-edge ids of any cell; find them via sorted lookup
+    }
+    auto edge_id = [&](int64_t a, int64_t b) {
+      auto &lst = in.v_edges[a];
+      for (int64_t e : lst)
+        if (t.ent[1][e * 2] == std::min(a, b) && t.ent[1][e * 2 + 1] == std::max(a, b)) return e;
+      throw std::logic_error("edge not found");
+    };
+    for (int64_t f = 0; f < t.n_ent[2]; ++f) {
+      const int64_t *v = &t.ent[2][f * 3];
+      in.e_faces[edge_id(v[0], v[1])].push_back(f);
+      in.e_faces[edge_id(v[0], v[2])].push_back(f);
+      in.e_faces[edge_id(v[1], v[2])].push_back(f);
+    }
+    for (int64_t c = 0; c < t.n_cells; ++c)
+      for (int s = 0; s < 6; ++s) in.e_cells[t.cell_ent[1][c * 6 + s]].push_back(c);
+  }
+  return in;
+}
+
+// Adds one patch given its columns (each a list of (dof, coef)) and the
+// cells of its support; builds the (patch, cell) coupling triples.
+void add_patch(PatchSet &ps, const Topology &t, const RefElement &el,
+               const std::vector<std::vector<std::pair<int32_t, double>>> &cols, const std::vector<int64_t> &cells,
+               std::vector<int32_t> &mark_col, std::vector<double> &mark_coef) {
+  for (size_t j = 0; j < cols.size(); ++j) {
+    for (auto &pr : cols[j]) {
+      ps.ent_dof.push_back(pr.first);
+      ps.ent_coef.push_back(pr.second);
+      mark_col[pr.first] = int32_t(j);
+      mark_coef[pr.first] = pr.second;
+    }
+    ps.col_ent.push_back(int64_t(ps.ent_dof.size()));
+  }
+  ps.patch_col.push_back(int64_t(ps.col_ent.size()) - 1);
+  for (int64_t c : cells) {
+    const int64_t before = int64_t(ps.tr_col.size());
+    for (int i = 0; i < el.n; ++i) {
+      const int32_t g = t.cell_dofs[c * el.n + i];
+      if (mark_col[g] >= 0) {
+        ps.tr_col.push_back(mark_col[g]);
+        ps.tr_loc.push_back(i);
+        ps.tr_coef.push_back(mark_coef[g]);
+      }
+    }
+    if (int64_t(ps.tr_col.size()) > before) {
+      ps.pc_cell.push_back(int32_t(c));
+      ps.pc_trip.push_back(int64_t(ps.tr_col.size()));
+    }
+  }
+  ps.pc_ptr.push_back(int64_t(ps.pc_cell.size()));
+  for (auto &col : cols)
+    for (auto &pr : col) mark_col[pr.first] = -1;
+}
+
+PatchSet empty_set() {
+  PatchSet ps;
+  ps.patch_col = {0};
+  ps.col_ent = {0};
+  ps.pc_ptr = {0};
+  ps.pc_trip = {0};
+  return ps;
+}
+
+}  // namespace
+
+std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el) {
+  const int d = t.d;
+  Incidence in = incidence(t);
+  std::vector<int32_t> mark_col(t.n_dofs, -1);
+  std::vector<double> mark_coef(t.n_dofs, 0.0);
+  std::vector<PatchSet> out;
+  auto plain_cols = [](std::vector<int32_t> &dofs) {
+    std::sort(dofs.begin(), dofs.end());
+    std::vector<std::vector<std::pair<int32_t, double>>> cols;
+    for (int32_t g : dofs) cols.push_back({{g, 1.0}});
+    return cols;
+  };
+  if (el.fam == FAM_CG) {
+    // vertex stars of the interface space X^0_Gamma (eq:approx-sc-pafw)
+    PatchSet ps = empty_set();
+    for (int64_t v = 0; v < t.n_vertices; ++v) {
+      std::vector<int32_t> dofs;
+      entity_dofs(t, el, 0, v, -1, dofs);
+      for (int64_t e : in.v_edges[v]) entity_dofs(t, el, 1, e, -1, dofs);
+      if (d == 3)
+        for (int64_t f : in.v_faces[v]) entity_dofs(t, el, 2, f, -1, dofs);
+      add_patch(ps, t, el, plain_cols(dofs), in.v_cells[v], mark_col, mark_coef);
+    }
+    out.push_back(std::move(ps));
+  } else if (el.fam == FAM_NED) {
+    // edge stars of the type-I interface space X^{1,I}_Gamma (eq:hcurl-decomp)
+    PatchSet pe = empty_set();
+    for (int64_t e = 0; e < t.n_ent[1]; ++e) {
+      std::vector<int32_t> dofs;
+      entity_dofs(t, el, 1, e, KIND_W, dofs);
+      for (int64_t f : in.e_faces[e]) entity_dofs(t, el, 2, f, KIND_I, dofs);
+      add_patch(pe, t, el, plain_cols(dofs), in.e_cells[e], mark_col, mark_coef);
+    }
+    out.push_back(std::move(pe));
+    // vertex-star potentials: d of X^0_Gamma|star V through the discrete
+    // gradient (lem:d-preserves-basis-functions): the vertex function maps to
+    // +-1 on the Whitney dofs of its edges (+1 when V is the larger vertex),
+    // a CG type-I dof to the Ned type-II dof of the same entity and index.
+    PatchSet pv = empty_set();
+    for (int64_t v = 0; v < t.n_vertices; ++v) {
+      std::vector<std::vector<std::pair<int32_t, double>>> cols(1);
+      for (int64_t e : in.v_edges[v]) {
+        std::vector<int32_t> w;
+        entity_dofs(t, el, 1, e, KIND_W, w);
+        cols[0].push_back({w[0], t.ent[1][e * 2 + 1] == v ? 1.0 : -1.0});
+      }
+      for (int64_t e : in.v_edges[v]) {
+        std::vector<int32_t> ii;
+        entity_dofs(t, el, 1, e, KIND_II, ii);
+        for (int32_t g : ii) cols.push_back({{g, 1.0}});
+      }
+      for (int64_t f : in.v_faces[v]) {
+        std::vector<int32_t> ii;
+        entity_dofs(t, el, 2, f, KIND_II, ii);
+        for (int32_t g : ii) cols.push_back({{g, 1.0}});
+      }
+      add_patch(pv, t, el, cols, in.v_cells[v], mark_col, mark_coef);
+    }
+    out.push_back(std::move(pv));
+  } else if (el.fam == FAM_RT) {
+    // edge stars of X^2_Gamma (eq:hdiv-decomp)
+    PatchSet ps = empty_set();
+    for (int64_t e = 0; e < t.n_ent[1]; ++e) {
+      std::vector<int32_t> dofs;
+      for (int64_t f : in.e_faces[e]) entity_dofs(t, el, 2, f, -1, dofs);
+      add_patch(ps, t, el, plain_cols(dofs), in.e_cells[e], mark_col, mark_coef);
+    }
+    out.push_back(std::move(ps));
+  }
+  return out;
+}
+
+void whitney_dofs(const Topology &t, const RefElement &el, std::vector<int32_t> &wdofs,
+                  std::vector<int32_t> &cell_wloc, std::vector<int32_t> &cell_widx, int &n_wloc) {
+  const int k = el.k;
+  wdofs.clear();
+  for (int64_t e = 0; e < t.n_ent[k]; ++e)
+    wdofs.push_back(int32_t(t.offset[k] + e * el.per_entity[k] + el.kind_start[3 * k + KIND_W]));
+  std::vector<int> loc;
+  for (int i = 0; i < el.n; ++i)
+    if (el.dofs[i].kind == KIND_W) loc.push_back(i);
+  n_wloc = int(loc.size());
+  cell_wloc = std::vector<int32_t>(loc.begin(), loc.end());
+  cell_widx.resize(t.n_cells * n_wloc);
+  int nsub = int(combos(t.d + 1, k + 1).size());
+  for (int64_t c = 0; c < t.n_cells; ++c)
+    for (int a = 0; a < n_wloc; ++a) {
+      const LocalDof &ld = el.dofs[loc[a]];
+      cell_widx[c * n_wloc + a] = int32_t(t.cell_ent[k][c * nsub + ld.entity_index]);
+    }
+}
+
+}  // namespace rz

@@ -1,0 +1,56 @@
+// Host-side mesh topology, global numbering and patch (subspace) lists.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "refelem.hpp"
+
+namespace rz {
+
+struct Topology {
+  int d = 0;
+  int64_t n_vertices = 0, n_cells = 0;
+  std::vector<int64_t> cells;                  // n_cells x (d+1), sorted per cell
+  std::vector<std::vector<int64_t>> ent;       // per dim l: n_ent x (l+1) sorted tuples
+  std::vector<int64_t> n_ent;                  // per dim
+  std::vector<std::vector<int64_t>> cell_ent;  // per dim l: n_cells x C(d+1, l+1) entity ids
+  std::vector<int64_t> offset;                 // d+2 dof offsets per dimension
+  int64_t n_dofs = 0, n_interior = 0;
+  std::vector<int32_t> cell_dofs;              // n_cells x n_loc
+};
+
+// Throws std::invalid_argument (bad indices / repeated vertex) on bad input.
+Topology build_topology(int d, int64_t n_vertices, int64_t n_cells, const int64_t *cells, const RefElement &el);
+
+// A family of subspaces ("patches"): each patch is a list of columns, each
+// column a sparse combination of global dofs (one entry with coefficient 1
+// for a plain dof; several for a discrete-gradient column).
+struct PatchSet {
+  std::vector<int64_t> patch_col;  // n_patches + 1, ranges into columns
+  std::vector<int64_t> col_ent;    // n_cols + 1, ranges into entries
+  std::vector<int32_t> ent_dof;    // global dof per entry
+  std::vector<double> ent_coef;    // coefficient per entry
+  // per patch: the cells of its support, and per (patch, cell) the triples
+  // (patch column, local dof of the cell, coefficient) that couple them
+  std::vector<int64_t> pc_ptr;     // n_patches + 1, ranges into pc_cell
+  std::vector<int32_t> pc_cell;    // cell of each (patch, cell) item
+  std::vector<int64_t> pc_trip;    // n_items + 1, ranges into triples
+  std::vector<int32_t> tr_col, tr_loc;
+  std::vector<double> tr_coef;
+  int64_t n_patches() const { return int64_t(patch_col.size()) - 1; }
+  int64_t max_size() const;
+};
+
+// The interface patches of Sec. 6 for the element's space:
+//  H(grad): vertex stars of X^0_Gamma; H(curl): edge stars of X^{1,I}_Gamma
+//  (plain) and vertex-star potentials through the discrete gradient;
+//  H(div): edge stars of X^2_Gamma.
+std::vector<PatchSet> build_patches(const Topology &top, const RefElement &el);
+
+// Whitney dofs (one per k-subsimplex, lem:basis-contains-whitney), ascending,
+// and per cell the local Whitney dofs with their coarse indices.
+void whitney_dofs(const Topology &top, const RefElement &el, std::vector<int32_t> &wdofs,
+                  std::vector<int32_t> &cell_wloc, std::vector<int32_t> &cell_widx, int &n_wloc);
+
+}  // namespace rz

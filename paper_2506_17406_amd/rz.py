@@ -1,0 +1,207 @@
+"""Thin ctypes binding of librz.so (the C ABI declared in include/rz.h).
+
+Argument marshalling only: every step of setup, apply_A, apply_P and the PCG
+solve runs inside the HIP library.  Device vectors are torch float64 tensors
+on the GPU; their pointers and the current HIP stream are passed through.
+Importing this module fails loudly if the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librz.so")
+
+RZ_HGRAD, RZ_HCURL, RZ_HDIV = 0, 1, 2
+SPACES = {"CG": RZ_HGRAD, "hgrad": RZ_HGRAD, "Ned": RZ_HCURL, "hcurl": RZ_HCURL, "RT": RZ_HDIV, "hdiv": RZ_HDIV}
+ERRORS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_UNSUPPORTED", -3: "RZ_ERR_MESH", -4: "RZ_ERR_DEGENERATE_CELL",
+          -5: "RZ_ERR_NOT_SPD", -6: "RZ_ERR_NO_CONVERGENCE", -7: "RZ_ERR_BREAKDOWN", -8: "RZ_ERR_DEVICE",
+          -9: "RZ_ERR_OOM"}
+
+
+class RzMesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_vertices", ctypes.c_int64), ("coords", ctypes.POINTER(ctypes.c_double)),
+                ("n_cells", ctypes.c_int64), ("cells", ctypes.POINTER(ctypes.c_int64))]
+
+
+class RzOptions(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+
+
+class RzInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("cond_estimate", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+
+
+class RzError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pi32, pi64, pdbl = ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl)
+    sig = {
+        "rz_setup": (ctypes.c_int, [ctypes.POINTER(RzMesh), i32, ctypes.c_int, ctypes.POINTER(RzOptions), P,
+                                    ctypes.POINTER(P)]),
+        "rz_sizes": (ctypes.c_int, [P, pi64, pi64, pi32, pi32]),
+        "rz_apply_A": (ctypes.c_int, [P, P, P, i32, i64, P]),
+        "rz_apply_P": (ctypes.c_int, [P, P, P, i32, i64, P]),
+        "rz_solve": (ctypes.c_int, [P, P, P, dbl, ctypes.POINTER(RzInfo), P]),
+        "rz_export_topology": (ctypes.c_int, [P, pi32, pi64, pi64, pi64, pi32]),
+        "rz_export_reference": (ctypes.c_int, [P, pdbl]),
+        "rz_reference": (ctypes.c_int, [i32, i32, ctypes.c_int, pi32, pi32, pdbl]),
+        "rz_numbering": (ctypes.c_int, [ctypes.POINTER(RzMesh), i32, ctypes.c_int, pi64, pi32, pi64, pi64, pi64,
+                                        pi32]),
+        "rz_destroy": (None, [P]),
+        "rz_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(code):
+    if code != 0:
+        raise RzError(code, lib.rz_last_error().decode())
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _mesh(coords, cells):
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    m = RzMesh(coords.shape[1], coords.shape[0], _ptr(coords, ctypes.c_double), cells.shape[0],
+               _ptr(cells, ctypes.c_int64))
+    return m, (coords, cells)
+
+
+def reference(dim, degree, space):
+    """Stacked reference matrices (Q, n_loc, n_loc), host only."""
+    n, Q = ctypes.c_int32(), ctypes.c_int32()
+    sp = SPACES[space] if isinstance(space, str) else space
+    _check(lib.rz_reference(dim, degree, sp, ctypes.byref(n), ctypes.byref(Q), None))
+    out = np.empty((Q.value, n.value, n.value))
+    _check(lib.rz_reference(dim, degree, sp, None, None, _ptr(out, ctypes.c_double)))
+    return out
+
+
+def numbering(coords, cells, degree, space, n_loc):
+    """(n_dofs, cell_dofs, patch_ptr, patch_dofs) as the library builds them, host only."""
+    m, keep = _mesh(coords, cells)
+    sp = SPACES[space] if isinstance(space, str) else space
+    nd, npat, nent = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.rz_numbering(ctypes.byref(m), degree, sp, ctypes.byref(nd), None, ctypes.byref(npat),
+                            ctypes.byref(nent), None, None))
+    cd = np.empty((m.n_cells, n_loc), dtype=np.int32)
+    ptr = np.empty(npat.value + 1, dtype=np.int64)
+    dofs = np.empty(nent.value, dtype=np.int32)
+    _check(lib.rz_numbering(ctypes.byref(m), degree, sp, None, _ptr(cd, ctypes.c_int32), None, None,
+                            _ptr(ptr, ctypes.c_int64), _ptr(dofs, ctypes.c_int32)))
+    return nd.value, cd, ptr, dofs
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Problem:
+    """A set-up Riesz-map problem on the GPU (rz_setup)."""
+
+    def __init__(self, coords, cells, degree, space, alpha=1.0, beta=1.0, max_iter=1000, stream=None):
+        m, keep = _mesh(coords, cells)
+        opts = RzOptions(alpha, beta, max_iter)
+        h = ctypes.c_void_p()
+        self._h = None
+        self.space = SPACES[space] if isinstance(space, str) else space
+        _check(lib.rz_setup(ctypes.byref(m), degree, self.space, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        nd, ni, nl, Q = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.rz_sizes(h, ctypes.byref(nd), ctypes.byref(ni), ctypes.byref(nl), ctypes.byref(Q)))
+        self.n_dofs, self.n_interior, self.n_loc, self.Q = nd.value, ni.value, nl.value, Q.value
+        self.n_cells = m.n_cells
+
+    def close(self):
+        if self._h:
+            lib.rz_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _dev(t):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+            raise TypeError("device vectors must be float64 CUDA/HIP tensors")
+        return t
+
+    def _cols(self, t):
+        self._dev(t)
+        if t.dim() == 1:
+            if not t.is_contiguous() or t.numel() < self.n_dofs:
+                raise ValueError("vector must be contiguous with n_dofs entries")
+            return 1, self.n_dofs
+        # column-major (n_dofs, n_rhs): stride(0) == 1
+        if t.stride(0) != 1 or t.shape[0] < self.n_dofs:
+            raise ValueError("matrix must be column-major with n_dofs rows")
+        return t.shape[1], t.stride(1)
+
+    def apply_A(self, x, y, stream=None):
+        nr, ld = self._cols(x)
+        self._cols(y)
+        _check(lib.rz_apply_A(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), nr, ld,
+                              _stream(stream)))
+        return y
+
+    def apply_P(self, r, z, stream=None):
+        nr, ld = self._cols(r)
+        self._cols(z)
+        _check(lib.rz_apply_P(self._h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()), nr, ld,
+                              _stream(stream)))
+        return z
+
+    def solve(self, b, x, rtol=1e-10, stream=None, check=True):
+        self._cols(b)
+        self._cols(x)
+        info = RzInfo()
+        code = lib.rz_solve(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), rtol,
+                            ctypes.byref(info), _stream(stream))
+        if check:
+            _check(code)
+        return dict(status=info.status, iterations=info.iterations, rel_residual=info.rel_residual,
+                    cond_estimate=info.cond_estimate, solve_ms=info.solve_ms, code=code)
+
+    def export_reference(self):
+        out = np.empty((self.Q, self.n_loc, self.n_loc))
+        _check(lib.rz_export_reference(self._h, _ptr(out, ctypes.c_double)))
+        return out
+
+    def export_topology(self):
+        npat, nent = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.rz_export_topology(self._h, None, ctypes.byref(npat), ctypes.byref(nent), None, None))
+        cd = np.empty((self.n_cells, self.n_loc), dtype=np.int32)
+        ptr = np.empty(npat.value + 1, dtype=np.int64)
+        dofs = np.empty(nent.value, dtype=np.int32)
+        _check(lib.rz_export_topology(self._h, _ptr(cd, ctypes.c_int32), None, None, _ptr(ptr, ctypes.c_int64),
+                                      _ptr(dofs, ctypes.c_int32)))
+        return cd, ptr, dofs
