@@ -64,6 +64,8 @@ struct rz_problem {
   rz::PcgState *st = nullptr;
   rz::PcgState *st_host = nullptr;
   double *r = nullptr, *z = nullptr, *pv = nullptr, *Ap = nullptr, *part = nullptr, *part2 = nullptr;
+  double *partA = nullptr, *partR = nullptr, *partZ = nullptr;  // block partials of pAp, rr, rz
+  rz::CoarseFold fold{};
 
   template <class T>
   T *dev(size_t count) {
@@ -195,7 +197,29 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
   int status = 0;
   HIPCHK(hipMemcpy(&status, dstatus, 4, hipMemcpyDeviceToHost));
   if (status) throw RzError{RZ_ERR_NOT_SPD, "non-positive pivot in a patch Cholesky factorisation"};
+  // work chunks: row ranges of ~equal packed-element counts
+  std::vector<int64_t> chunk_patch;
+  std::vector<int32_t> chunk_rows;
+  const int64_t target = 32768;
+  for (int64_t b = 0; b < B; ++b) {
+    const int m = sizes[b];
+    int r0 = 0;
+    int64_t acc = 0;
+    for (int i = 0; i < m; ++i) {
+      acc += m - i;
+      if (acc >= target || i == m - 1) {
+        chunk_patch.push_back(b);
+        chunk_rows.push_back(r0);
+        chunk_rows.push_back(i + 1);
+        r0 = i + 1;
+        acc = 0;
+      }
+    }
+  }
   out.pa.n_patches = B;
+  out.pa.n_chunks = int64_t(chunk_patch.size());
+  out.pa.chunk_patch = P.upload(chunk_patch, s);
+  out.pa.chunk_rows = P.upload(chunk_rows, s);
   out.pa.max_size = maxsz;
   out.pa.patch_col = P.upload(ps.patch_col, s);
   out.pa.col_ent = P.upload(ps.col_ent, s);
@@ -290,7 +314,7 @@ void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
         for (int lane = 0; lane < 64; ++lane) {
           const int row = mb * 16 + (lane & 15), col = kb * 4 + (lane >> 4);
           if (row < n && col < n)
-            frag[((size_t(mb) * Q + q) * KB + kb) * 64 + lane] = P.el.R[(size_t(q) * n + row) * n + col];
+            frag[((size_t(mb) * KB + kb) * Q + q) * 64 + lane] = P.el.R[(size_t(q) * n + row) * n + col];
         }
   P.Afrag = P.upload(frag, s);
   P.cell_dofs = P.upload(P.top.cell_dofs, s);
@@ -374,6 +398,13 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     P->Ap = P->dev<double>(nd);
     P->part = P->dev<double>(rz::kRedBlocks);
     P->part2 = P->dev<double>(rz::kRedBlocks);
+    P->partA = P->dev<double>(rz::kRedBlocks);
+    P->partR = P->dev<double>(rz::kRedBlocks);
+    P->partZ = P->dev<double>(rz::kRedBlocks);
+    P->fold.zW = P->ca.zW;
+    P->fold.off = P->top.offset[P->k];
+    P->fold.N = P->el.per_entity[P->k];
+    P->fold.span = P->top.n_ent[P->k] * P->fold.N;
     HIPCHK(hipStreamSynchronize(s));
   } catch (const RzError &e) {
     return fail(e.code, e.msg);
@@ -441,23 +472,24 @@ int rz_solve(rz_problem *P, const double *b, double *x, double rtol, rz_info *in
     rz::launch_dot_partial(nd, P->r, P->r, P->part2, nullptr, s);
     rz::launch_pcg_init(P->st, P->part, P->part2, rtol * rtol, maxit, s);
     apply_P_impl(P, P->r, P->z, P->st, s);
-    rz::launch_dot_partial(nd, P->r, P->z, P->part, P->st, s);
-    rz::launch_set_rz(P->st, P->part, s);
+    const rz::CoarseFold nofold{nullptr, 0, 0, 1};
+    rz::launch_dot2(nd, P->r, P->z, nofold, P->partZ, P->st, s);
     rz::launch_copy(nd, P->z, P->pv, s);
+    rz::launch_fill(P->Ap, nd, 0.0, nullptr, s);
     HIPCHK(hipGetLastError());
     const int chunk = 8;
     for (int it0 = 0; it0 < maxit; it0 += chunk) {
       for (int it = 0; it < chunk; ++it) {
-        rz::launch_fill(P->Ap, nd, 0.0, P->st, s);
+        // Ap was cleared by the previous p update; partZ holds the partials of (r, z)
         rz::launch_apply_A(P->at, P->pv, P->Ap, 1, nd, P->st, s);
-        rz::launch_dot_partial(nd, P->pv, P->Ap, P->part, P->st, s);
-        rz::launch_finalize_alpha(P->st, P->part, s);
-        rz::launch_update_xr(nd, x, P->r, P->pv, P->Ap, P->part, P->st, s);
-        rz::launch_finalize_rr(P->st, P->part, s);
-        apply_P_impl(P, P->r, P->z, P->st, s);
-        rz::launch_dot_partial(nd, P->r, P->z, P->part, P->st, s);
-        rz::launch_finalize_beta(P->st, P->part, s);
-        rz::launch_update_p(nd, P->pv, P->z, P->st, s);
+        rz::launch_dot2(nd, P->pv, P->Ap, nofold, P->partA, P->st, s);
+        rz::launch_update_xr2(nd, x, P->r, P->pv, P->Ap, P->partZ, P->partA, P->partR, P->st, s);
+        // convergence test, then z = P^{-1} r with the coarse part left in zW
+        rz::launch_check_jacobi(nd, P->off_I, P->dinv, P->r, P->z, P->ca, P->partR, P->st, s);
+        for (auto &d : P->dps) rz::launch_patch_apply(d.pa, P->r, P->z, P->st, s);
+        rz::launch_coarse_tiles(P->ca, P->st, s);
+        rz::launch_dot2(nd, P->r, P->z, P->fold, P->partZ, P->st, s);
+        rz::launch_update_p2(nd, P->pv, P->z, P->fold, P->Ap, P->partZ, P->st, s);
       }
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(P->st_host, P->st, offsetof(rz::PcgState, alphas), hipMemcpyDeviceToHost, s));

@@ -359,63 +359,79 @@ __global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A,
 }
 
 // -------------------------------------------------------------- apply_A
-template <int NT>
-__global__ __launch_bounds__(256) void k_apply_A(int n, int Q, int NMB, int KB, int64_t nc,
-                                                 const double *__restrict__ Af, const double *__restrict__ w,
-                                                 const int32_t *__restrict__ cd, const double *__restrict__ x,
-                                                 double *__restrict__ y, int64_t ld, const PcgState *st) {
+// One wave computes a 16-row block (mb) of y_T for 16*NB cells:
+//   y_T[rows] = sum_{jb} sum_q R_q[rows, 4jb:4jb+4] (w_{T,q} x_T[4jb:4jb+4]).
+// The four gathered x_T entries of a k-step are reused by all Q reference
+// matrices; the A fragments of all q for one k-step are contiguous (fragment
+// order (mb, jb, q, lane)).  The next k-step's fragments and x values are
+// loaded before the current step's Q*NB MFMAs are issued.
+template <int Q, int NB>
+__global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int64_t nc, const double *__restrict__ Af,
+                                                 const double *__restrict__ w, const int32_t *__restrict__ cd,
+                                                 const double *__restrict__ x, double *__restrict__ y, int64_t ld,
+                                                 const PcgState *st) {
   if (st && st->done) return;
-  extern __shared__ double smem[];
-  const int KP = KB * 4, S = KP + 1;
-  double *xs = smem;           // NT x S
-  double *ws = smem + NT * S;  // Q x NT
-  const int64_t cell0 = int64_t(blockIdx.x) * NT;
-  const double *xr = x + int64_t(blockIdx.z) * ld;
-  double *yr = y + int64_t(blockIdx.z) * ld;
-  for (int idx = threadIdx.x; idx < NT * KP; idx += 256) {
-    const int c = idx / KP, j = idx - c * KP;
-    const int64_t cell = cell0 + c;
-    xs[c * S + j] = (cell < nc && j < n) ? xr[cd[cell * n + j]] : 0.0;
-  }
-  for (int idx = threadIdx.x; idx < NT * Q; idx += 256) {
-    const int c = idx / Q, q = idx - c * Q;
-    const int64_t cell = cell0 + c;
-    ws[q * NT + c] = cell < nc ? w[cell * Q + q] : 0.0;
-  }
-  __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mb = blockIdx.y * 4 + wave;
   if (mb >= NMB) return;
   const int li = lane & 15, lk = lane >> 4;
-  d4 acc[NT / 16];
+  const double *xr = x + int64_t(blockIdx.z) * ld;
+  double *yr = y + int64_t(blockIdx.z) * ld;
+  const int64_t cell0 = int64_t(blockIdx.x) * (16 * NB);
+  const int32_t *cdp[NB];
+  double wv[NB][Q];
+  bool valid[NB];
 #pragma unroll
-  for (int nb = 0; nb < NT / 16; ++nb) acc[nb] = d4{0, 0, 0, 0};
-  const double *Ab = Af + size_t(mb) * Q * KB * 64 + lane;
-  for (int q = 0; q < Q; ++q) {
-    double wq[NT / 16];
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t c = cell0 + nb * 16 + li;
+    valid[nb] = c < nc;
+    const int64_t cc = valid[nb] ? c : nc - 1;
+    cdp[nb] = cd + cc * n;
 #pragma unroll
-    for (int nb = 0; nb < NT / 16; ++nb) wq[nb] = ws[q * NT + nb * 16 + li];
-    const double *Aq = Ab + size_t(q) * KB * 64;
-    const double *xq = xs + li * S + lk;
-#pragma unroll 4
-    for (int kb = 0; kb < KB; ++kb) {
-      const double a = Aq[kb * 64];
+    for (int q = 0; q < Q; ++q) wv[nb][q] = valid[nb] ? w[cc * Q + q] : 0.0;
+  }
+  d4 acc[NB];
 #pragma unroll
-      for (int nb = 0; nb < NT / 16; ++nb) {
-        const double b = wq[nb] * xq[nb * 16 * S + kb * 4];
-        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[nb], 0, 0, 0);
-      }
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = d4{0, 0, 0, 0};
+  const double *Ab = Af + size_t(mb) * KB * Q * 64 + lane;
+  double a0[Q], x0[NB];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) a0[q] = Ab[q * 64];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) x0[nb] = lk < n ? xr[cdp[nb][lk]] : 0.0;
+  for (int jb = 0; jb < KB; ++jb) {
+    double a1[Q], x1[NB];
+    if (jb + 1 < KB) {
+      const double *An = Ab + size_t(jb + 1) * Q * 64;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) a1[q] = An[q * 64];
+      const int col = (jb + 1) * 4 + lk;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) x1[nb] = col < n ? xr[cdp[nb][col]] : 0.0;
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) a1[q] = 0.0;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) x1[nb] = 0.0;
     }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[q], wv[nb][q] * x0[nb], acc[nb], 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) a0[q] = a1[q];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) x0[nb] = x1[nb];
   }
 #pragma unroll
-  for (int nb = 0; nb < NT / 16; ++nb) {
-    const int64_t cell = cell0 + nb * 16 + li;
-    if (cell >= nc) continue;
+  for (int nb = 0; nb < NB; ++nb) {
+    if (!valid[nb]) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       // FP64 16x16x4 accumulator layout: lane l, element v holds row l/16 + 4v, column l%16
       const int row = mb * 16 + lk + 4 * v;
-      if (row < n) atomicAdd(&yr[cd[cell * n + row]], acc[nb][v]);
+      if (row < n) atomicAdd(&yr[cdp[nb][row]], acc[nb][v]);
     }
   }
 }
@@ -427,8 +443,17 @@ __global__ void k_fill(double *y, int64_t n, double v, const PcgState *st) {
 }
 
 // -------------------------------------------------------------- apply_P
+// Work item = (patch, row range [r0, r1)) of the packed upper triangle of the
+// patch inverse (rows ~balanced by element count).  The patch right-hand side
+// is gathered into LDS; each wave takes every fourth row, with the next row's
+// entries loaded before the current row's products are reduced; columns j are
+// owned by lane j % 64.  Row sums (j >= i) and the mirrored column sums
+// (j > i) of the chunk are combined in LDS and scatter-added (atomics: chunks
+// and patches overlap).
 template <int MAXJ>
-__global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__ patch_col,
+__global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__ chunk_patch,
+                                                     const int32_t *__restrict__ chunk_rows,
+                                                     const int64_t *__restrict__ patch_col,
                                                      const int64_t *__restrict__ col_ent,
                                                      const int32_t *__restrict__ ent_dof,
                                                      const double *__restrict__ ent_coef,
@@ -438,37 +463,50 @@ __global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__
   if (st && st->done) return;
   extern __shared__ double sm[];
   double *rp = sm;              // gathered right-hand side
-  double *yr = sm + maxsz;      // row products
+  double *yr = sm + maxsz;      // row products of this chunk
   double *yc = sm + 2 * maxsz;  // 4 x column partials
-  const int64_t p = blockIdx.x;
+  const int64_t p = chunk_patch[blockIdx.x];
+  const int r0 = chunk_rows[2 * blockIdx.x], r1 = chunk_rows[2 * blockIdx.x + 1];
   const int64_t c0 = patch_col[p];
   const int m = int(patch_col[p + 1] - c0);
   for (int j = threadIdx.x; j < m; j += 256) {
     double s = 0;
     for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) s += ent_coef[e] * r[ent_dof[e]];
     rp[j] = s;
+    yr[j] = 0.0;
   }
   __syncthreads();
   const double *A = inv + inv_off[p];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double cacc[MAXJ];
+  double cacc[MAXJ], cur[MAXJ], nxt[MAXJ];
 #pragma unroll
-  for (int jb = 0; jb < MAXJ; ++jb) cacc[jb] = 0;
-  for (int i = wave; i < m; i += 4) {
+  for (int jb = 0; jb < MAXJ; ++jb) cacc[jb] = 0.0;
+  auto load_row = [&](int i, double *buf) {
     const double *row = A + int64_t(i) * m - int64_t(i) * (i - 1) / 2 - i;  // row[j] = A_ij, j >= i
-    const double ri = rp[i];
-    double rs = 0;
 #pragma unroll
     for (int jb = 0; jb < MAXJ; ++jb) {
       const int j = jb * 64 + lane;
-      if (j >= i && j < m) {
-        const double a = row[j];
-        rs += a * rp[j];
-        if (j > i) cacc[jb] += a * ri;
-      }
+      buf[jb] = (j >= i && j < m) ? row[j] : 0.0;
+    }
+  };
+  int i = r0 + wave;
+  if (i < r1) load_row(i, cur);
+  for (; i < r1; i += 4) {
+    if (i + 4 < r1) load_row(i + 4, nxt);
+    const double ri = rp[i];
+    double rs = 0.0;
+#pragma unroll
+    for (int jb = 0; jb < MAXJ; ++jb) {
+      const int j = jb * 64 + lane;
+      const double a = cur[jb];
+      const double rj = j < m ? rp[j] : 0.0;
+      rs += a * rj;
+      cacc[jb] += (j > i) ? a * ri : 0.0;
     }
     rs = wave_sum(rs);
     if (lane == 0) yr[i] = rs;
+#pragma unroll
+    for (int jb = 0; jb < MAXJ; ++jb) cur[jb] = nxt[jb];
   }
 #pragma unroll
   for (int jb = 0; jb < MAXJ; ++jb) {
@@ -476,7 +514,7 @@ __global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__
     if (j < m) yc[wave * maxsz + j] = cacc[jb];
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < m; j += 256) {
+  for (int j = r0 + threadIdx.x; j < m; j += 256) {
     const double y = yr[j] + ((yc[j] + yc[maxsz + j]) + (yc[2 * maxsz + j] + yc[3 * maxsz + j]));
     for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) atomicAdd(&z[ent_dof[e]], ent_coef[e] * y);
   }
@@ -670,6 +708,119 @@ __global__ void k_copy(int64_t n, const double *__restrict__ a, double *__restri
     b[i] = a[i];
 }
 
+// ---- fused iteration kernels.  A reduction kernel leaves one partial sum
+// per block; the kernel that consumes the scalar re-sums the partials in
+// every block (fixed order, so all blocks agree bit for bit) -- the kernel
+// boundary makes the partials visible without device-scope fences.
+
+// coarse correction of dof i folded in (z + R_W^T zW), when zW is given
+__device__ inline double z_full(int64_t i, const double *z, const CoarseFold &cf) {
+  double v = z[i];
+  if (cf.zW) {
+    const int64_t t = i - cf.off;
+    if (t >= 0 && t < cf.span && t % cf.N == 0) v += cf.zW[t / cf.N];
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_dot2(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                                              CoarseFold cf, double *__restrict__ part, const PcgState *st) {
+  if (st->done) return;
+  __shared__ double sm4[4];
+  double s = 0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    s += a[i] * z_full(i, b, cf);
+  s = block_sum256(s, sm4);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// alpha = rz / pAp; x += alpha p; r -= alpha Ap; partials of ||r||^2
+__global__ __launch_bounds__(256) void k_update_xr2(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                    const double *__restrict__ p, const double *__restrict__ Ap,
+                                                    const double *__restrict__ partZ,
+                                                    const double *__restrict__ partA, double *__restrict__ partR,
+                                                    PcgState *st) {
+  if (st->done) return;
+  __shared__ double sm4[4];
+  const double rz = sum_partials(partZ, sm4);
+  const double pAp = sum_partials(partA, sm4);
+  if (!(pAp > 0.0) || !isfinite(pAp) || !(rz > 0.0) || !isfinite(rz)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->done = 1;
+      st->status = PCG_BREAKDOWN;
+    }
+    return;
+  }
+  const double alpha = rz / pAp;
+  double s = 0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * Ap[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  s = block_sum256(s, sm4);
+  if (threadIdx.x == 0) {
+    partR[blockIdx.x] = s;
+    if (blockIdx.x == 0) {
+      st->rz = rz;
+      st->pAp = pAp;
+      st->alpha = alpha;
+      if (st->iter < kMaxIter) st->alphas[st->iter] = alpha;
+    }
+  }
+}
+
+// convergence test on ||r||^2, then z = D_I^{-1} r (0 off the interior) and
+// the coarse gather rW = R_W r, zW = 0
+__global__ __launch_bounds__(256) void k_check_jacobi(int64_t n, int64_t offI, const double *__restrict__ dinv,
+                                                      const double *__restrict__ r, double *__restrict__ z, int nW,
+                                                      int npad, const int32_t *__restrict__ wd,
+                                                      double *__restrict__ rW, double *__restrict__ zW,
+                                                      const double *__restrict__ partR, PcgState *st) {
+  if (st->done) return;
+  __shared__ double sm4[4];
+  const double rr = sum_partials(partR, sm4);
+  const bool bad = !isfinite(rr), conv = rr <= st->tol2 * st->bb;  // identical in every block
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // only this thread reads and writes the iteration count
+    const int it = st->iter + 1;
+    st->rr = rr;
+    st->iter = it;
+    if (bad || conv || it >= st->maxit) {
+      st->status = bad ? PCG_BREAKDOWN : (conv ? PCG_CONVERGED : PCG_MAXIT);
+      st->done = 1;
+    }
+  }
+  // at the iteration cap the remaining blocks still form z, which is then unused
+  if (bad || conv) return;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    z[i] = i >= offI ? r[i] * dinv[i - offI] : 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < npad; i += stride) {
+    rW[i] = i < nW ? r[wd[i]] : 0.0;
+    zW[i] = 0.0;
+  }
+}
+
+// beta = rz_new / rz; p = z + beta p (coarse part folded in); Ap = 0
+__global__ __launch_bounds__(256) void k_update_p2(int64_t n, double *__restrict__ p, const double *__restrict__ z,
+                                                   CoarseFold cf, double *__restrict__ Ap,
+                                                   const double *__restrict__ partZ, PcgState *st) {
+  if (st->done) return;
+  __shared__ double sm4[4];
+  const double rz_new = sum_partials(partZ, sm4);
+  const double beta = rz_new / st->rz;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->beta = beta;
+    if (st->iter - 1 < kMaxIter) st->betas[st->iter - 1] = beta;
+  }
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    p[i] = z_full(i, z, cf) + beta * p[i];
+    Ap[i] = 0.0;
+  }
+}
+
 }  // namespace
 
 // ================================================================ launchers
@@ -726,30 +877,31 @@ void launch_pack_tiles(int N, int n, const double *Ainv, double *tiles, hipStrea
                      tiles);
 }
 
+template <int Q>
+static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, const double *x, double *y, int64_t ld,
+                      const PcgState *st, hipStream_t s) {
+  const int KB = t.KP / 4, NMB = t.NP / 16;
+  if (NB == 4)
+    hipLaunchKernelGGL((k_apply_A<Q, 4>), grid, dim3(256), 0, s, t.n, NMB, KB, t.n_cells, t.Afrag, t.w, t.cell_dofs,
+                       x, y, ld, st);
+  else if (NB == 2)
+    hipLaunchKernelGGL((k_apply_A<Q, 2>), grid, dim3(256), 0, s, t.n, NMB, KB, t.n_cells, t.Afrag, t.w, t.cell_dofs,
+                       x, y, ld, st);
+  else
+    hipLaunchKernelGGL((k_apply_A<Q, 1>), grid, dim3(256), 0, s, t.n, NMB, KB, t.n_cells, t.Afrag, t.w, t.cell_dofs,
+                       x, y, ld, st);
+}
+
 void launch_apply_A(const ApplyATables &t, const double *x, double *y, int n_rhs, int64_t ld, const PcgState *st,
                     hipStream_t s) {
-  const int KB = t.KP / 4, NMB = t.NP / 16;
-  const int S = t.KP + 1;
-  int NT = 64;
-  while (NT > 16 && (size_t(NT) * S + size_t(t.Q) * NT) * 8 > 64 * 1024) NT /= 2;
-  const size_t lds = (size_t(NT) * S + size_t(t.Q) * NT) * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {  // allow up to the 160 KB of LDS a gfx950 CU has
-    (void)hipFuncSetAttribute((const void *)k_apply_A<64>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute((const void *)k_apply_A<32>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute((const void *)k_apply_A<16>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
-  dim3 grid(unsigned((t.n_cells + NT - 1) / NT), unsigned((NMB + 3) / 4), unsigned(n_rhs));
-  if (NT == 64)
-    hipLaunchKernelGGL(k_apply_A<64>, grid, dim3(256), lds, s, t.n, t.Q, NMB, KB, t.n_cells, t.Afrag, t.w,
-                       t.cell_dofs, x, y, ld, st);
-  else if (NT == 32)
-    hipLaunchKernelGGL(k_apply_A<32>, grid, dim3(256), lds, s, t.n, t.Q, NMB, KB, t.n_cells, t.Afrag, t.w,
-                       t.cell_dofs, x, y, ld, st);
-  else
-    hipLaunchKernelGGL(k_apply_A<16>, grid, dim3(256), lds, s, t.n, t.Q, NMB, KB, t.n_cells, t.Afrag, t.w,
-                       t.cell_dofs, x, y, ld, st);
+  const int NMB = t.NP / 16;
+  // cells per wave: as many as keep >= 2048 waves in flight (A-fragment reuse vs occupancy)
+  int NB = 4;
+  while (NB > 1 && ((t.n_cells + 16 * NB - 1) / (16 * NB)) * NMB * n_rhs < 2048) NB /= 2;
+  dim3 grid(unsigned((t.n_cells + 16 * NB - 1) / (16 * NB)), unsigned((NMB + 3) / 4), unsigned(n_rhs));
+  if (t.Q == 12) apply_A_q<12>(t, NB, grid, x, y, ld, st, s);
+  else if (t.Q == 7) apply_A_q<7>(t, NB, grid, x, y, ld, st, s);
+  else apply_A_q<4>(t, NB, grid, x, y, ld, st, s);
 }
 
 void launch_fill(double *y, int64_t n, double v, const PcgState *st, hipStream_t s) {
@@ -757,18 +909,18 @@ void launch_fill(double *y, int64_t n, double v, const PcgState *st, hipStream_t
 }
 
 void launch_patch_apply(const PatchApply &pa, const double *r, double *z, const PcgState *st, hipStream_t s) {
-  if (pa.n_patches == 0) return;
+  if (pa.n_chunks == 0) return;
   const size_t lds = size_t(6) * pa.max_size * sizeof(double);
   const int nj = (pa.max_size + 63) / 64;
-  dim3 g(unsigned(pa.n_patches)), b(256);
+  dim3 g(unsigned(pa.n_chunks)), b(256);
 #define RZ_PATCH(MJ)                                                                                        \
-  hipLaunchKernelGGL(k_patch_apply<MJ>, g, b, lds, s, pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, \
-                     pa.inv_off, pa.inv, r, z, pa.max_size, st)
+  hipLaunchKernelGGL(k_patch_apply<MJ>, g, b, lds, s, pa.chunk_patch, pa.chunk_rows, pa.patch_col, pa.col_ent, \
+                     pa.ent_dof, pa.ent_coef, pa.inv_off, pa.inv, r, z, pa.max_size, st)
   if (nj <= 1) RZ_PATCH(1);
   else if (nj <= 2) RZ_PATCH(2);
   else if (nj <= 4) RZ_PATCH(4);
   else if (nj <= 8) RZ_PATCH(8);
-  else if (nj <= 16) RZ_PATCH(16);
+  else if (nj <= 14) RZ_PATCH(14);
   else RZ_PATCH(24);
 #undef RZ_PATCH
 }
@@ -818,6 +970,28 @@ void launch_residual(int64_t n, const double *b, const double *Ax, double *r, hi
 }
 void launch_copy(int64_t n, const double *a, double *b, hipStream_t s) {
   hipLaunchKernelGGL(k_copy, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, a, b);
+}
+
+void launch_dot2(int64_t n, const double *a, const double *b, const CoarseFold &cf, double *part,
+                 const PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(256), 0, s, n, a, b, cf, part, st);
+}
+void launch_update_xr2(int64_t n, double *x, double *r, const double *p, const double *Ap, const double *partZ,
+                       const double *partA, double *partR, PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_xr2, dim3(kRedBlocks), dim3(256), 0, s, n, x, r, p, Ap, partZ, partA, partR, st);
+}
+void launch_check_jacobi(int64_t n, int64_t off_I, const double *dinv, const double *r, double *z,
+                         const CoarseApply &ca, const double *partR, PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_jacobi, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, off_I, dinv, r, z, ca.nW,
+                     ca.NT * 64, ca.wdofs, ca.rW, ca.zW, partR, st);
+}
+void launch_coarse_tiles(const CoarseApply &ca, const PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_tiles, dim3(unsigned(int64_t(ca.NT) * (ca.NT + 1) / 2)), dim3(64), 0, s, ca.NT,
+                     ca.tiles, ca.rW, ca.zW, st);
+}
+void launch_update_p2(int64_t n, double *p, const double *z, const CoarseFold &cf, double *Ap, const double *partZ,
+                      PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p2, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, p, z, cf, Ap, partZ, st);
 }
 
 }  // namespace rz

@@ -45,8 +45,10 @@ void launch_apply_A(const ApplyATables &t, const double *x, double *y, int n_rhs
 void launch_fill(double *y, int64_t n, double v, const PcgState *st, hipStream_t s);
 
 struct PatchApply {
-  int64_t n_patches;
+  int64_t n_patches, n_chunks;
   int max_size;
+  const int64_t *chunk_patch;  // patch of each work chunk
+  const int32_t *chunk_rows;   // [r0, r1) row range of each chunk
   const int64_t *patch_col, *col_ent, *inv_off;
   const int32_t *ent_dof;
   const double *ent_coef;
@@ -63,6 +65,14 @@ struct CoarseApply {
 };
 void launch_coarse_apply(const CoarseApply &ca, const double *r, double *z, const PcgState *st, hipStream_t s);
 
+// The coarse correction kept in zW and added on the fly to the dofs
+// off + t N (t < span / N): the Whitney dofs are every N-th dof of one
+// entity-dimension block.
+struct CoarseFold {
+  const double *zW;
+  int64_t off, span, N;
+};
+
 // ---- Krylov vector kernels
 constexpr int kRedBlocks = 512;
 void launch_dot_partial(int64_t n, const double *a, const double *b, double *part, const PcgState *st,
@@ -78,5 +88,16 @@ void launch_finalize_beta(PcgState *st, const double *part, hipStream_t s);
 void launch_update_p(int64_t n, double *p, const double *z, const PcgState *st, hipStream_t s);
 void launch_residual(int64_t n, const double *b, const double *Ax, double *r, hipStream_t s);
 void launch_copy(int64_t n, const double *a, double *b, hipStream_t s);
+// fused iteration kernels: a reduction leaves per-block partials, the
+// consuming kernel re-sums them in every block
+void launch_dot2(int64_t n, const double *a, const double *b, const CoarseFold &cf, double *part,
+                 const PcgState *st, hipStream_t s);
+void launch_update_xr2(int64_t n, double *x, double *r, const double *p, const double *Ap, const double *partZ,
+                       const double *partA, double *partR, PcgState *st, hipStream_t s);
+void launch_check_jacobi(int64_t n, int64_t off_I, const double *dinv, const double *r, double *z,
+                         const CoarseApply &ca, const double *partR, PcgState *st, hipStream_t s);
+void launch_coarse_tiles(const CoarseApply &ca, const PcgState *st, hipStream_t s);
+void launch_update_p2(int64_t n, double *p, const double *z, const CoarseFold &cf, double *Ap, const double *partZ,
+                      PcgState *st, hipStream_t s);
 
 }  // namespace rz
