@@ -1,0 +1,118 @@
+"""Host-side checks of the HIP library (no GPU needed).
+
+* every function declared in include/rz.h is exported by librz.so;
+* argument, mesh and geometry validation return their documented codes
+  before any device work;
+* the library's independently built reference tables match the oracle's
+  (relative 1e-11);
+* the library's numbering and patch lists are bit-identical to the oracle's,
+  also for permuted cell-vertex orders and shuffled cell orders.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.element import element
+from oracle.mesh import Topology
+from oracle.operator import reference_stack
+from oracle.precond import patch_lists
+from paper_2506_17406_amd.workloads import kuhn_mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+rz = pytest.importorskip("paper_2506_17406_amd.rz", reason="librz.so not built")
+
+
+def test_header_symbols_exported():
+    hdr = open(os.path.join(ROOT, "include", "rz.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    names = set(re.findall(r"\b(rz_\w+)\s*\(", hdr))
+    assert {"rz_setup", "rz_apply_A", "rz_apply_P", "rz_solve"} <= names
+    lib = ctypes.CDLL(rz.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_reference_argument_errors():
+    n, Q = ctypes.c_int32(), ctypes.c_int32()
+    assert rz.lib.rz_reference(4, 3, 0, ctypes.byref(n), ctypes.byref(Q), None) == -1      # dim
+    assert rz.lib.rz_reference(3, 11, 0, ctypes.byref(n), ctypes.byref(Q), None) == -2     # degree
+    assert rz.lib.rz_reference(3, 0, 0, ctypes.byref(n), ctypes.byref(Q), None) == -2
+    assert rz.lib.rz_reference(2, 3, 1, ctypes.byref(n), ctypes.byref(Q), None) == -2      # 2D H(curl)
+    assert rz.lib.rz_reference(3, 3, 7, ctypes.byref(n), ctypes.byref(Q), None) == -1      # space
+    assert b"space" in rz.lib.rz_last_error()
+
+
+def _mesh_struct(X, C):
+    return rz._mesh(X, C)
+
+
+def test_numbering_mesh_errors():
+    X, C = kuhn_mesh(1)
+    bad = C.copy()
+    bad[0, 0] = 100                       # index out of range
+    m, keep = _mesh_struct(X, bad)
+    nd = ctypes.c_int64()
+    assert rz.lib.rz_numbering(ctypes.byref(m), 2, 0, ctypes.byref(nd), None, None, None, None, None) == -3
+    rep = C.copy()
+    rep[0, 1] = rep[0, 0]                 # repeated vertex
+    m, keep = _mesh_struct(X, rep)
+    assert rz.lib.rz_numbering(ctypes.byref(m), 2, 0, ctypes.byref(nd), None, None, None, None, None) == -3
+
+
+def test_setup_rejects_before_device_work():
+    X, C = kuhn_mesh(1)
+    m, keep = _mesh_struct(X, C)
+    h = ctypes.c_void_p()
+    opts = rz.RzOptions(-1.0, 1.0, 100)
+    assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
+    opts = rz.RzOptions(1.0, 0.0, 100)
+    assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
+    assert rz.lib.rz_setup(None, 2, 0, None, None, ctypes.byref(h)) == -1
+    assert rz.lib.rz_setup(ctypes.byref(m), 12, 0, None, None, ctypes.byref(h)) == -2
+    # a flat tetrahedron: all four vertices in one plane
+    Xf = X.copy()
+    flat = C[0]
+    Xf[flat, 2] = 0.0
+    Xf[flat, 1] = Xf[flat, 0]
+    m, keep = _mesh_struct(Xf, C)
+    assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, None, None, ctypes.byref(h)) == -4
+    assert b"degenerate" in rz.lib.rz_last_error()
+
+
+REF_CASES = [(2, "CG", p) for p in (1, 2, 4, 6)] + [(3, "CG", p) for p in (1, 3, 6)] + \
+            [(3, "Ned", p) for p in (1, 2, 4, 6)] + [(3, "RT", p) for p in (1, 2, 4, 6)]
+
+
+@pytest.mark.parametrize("d,fam,p", REF_CASES, ids=lambda v: str(v))
+def test_reference_tables_match_oracle(d, fam, p):
+    R = rz.reference(d, p, fam)
+    Ro = reference_stack(element(d, fam, p))
+    assert R.shape == Ro.shape
+    assert np.abs(R - Ro).max() <= 1e-11 * np.abs(Ro).max()
+
+
+NUM_CASES = [(2, "CG", 4, 4), (2, "CG", 2, 3), (3, "CG", 1, 2), (3, "CG", 4, 2), (3, "Ned", 1, 2),
+             (3, "Ned", 3, 3), (3, "RT", 1, 2), (3, "RT", 3, 3)]
+
+
+@pytest.mark.parametrize("d,fam,p,n", NUM_CASES, ids=lambda v: str(v))
+@pytest.mark.parametrize("shuffle", [False, True])
+def test_numbering_bit_exact(d, fam, p, n, shuffle):
+    X, C = kuhn_mesh(n, d, jitter=0.1, seed=4)
+    if shuffle:
+        rng = np.random.default_rng(9)
+        C = C[rng.permutation(len(C))]
+        C = np.array([row[rng.permutation(d + 1)] for row in C])
+    el = element(d, fam, p)
+    top = Topology(X, C, el)
+    nd, cd, ptr, dofs = rz.numbering(X, C, p, fam, el.n)
+    assert nd == top.n_dofs
+    assert np.array_equal(cd, top.cell_dofs)
+    pl = patch_lists(top, fam)
+    assert len(ptr) - 1 == len(pl)
+    for i, idx in enumerate(pl):
+        assert np.array_equal(dofs[ptr[i]:ptr[i + 1]], idx)
