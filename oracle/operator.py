@@ -42,8 +42,12 @@ def cell_matrix(el, X, alpha=1.0, beta=1.0, tab=None):
         v = np.einsum("ab,qbn->qan", J, vals) / det       # J v / det J
         dphys = dv / det                                  # div / det J
     s = abs(det)
-    M = np.einsum("q,qci,qcj->ij", wq, v, v) * s
-    K = np.einsum("q,qci,qcj->ij", wq, dphys, dphys) * s
+    # sum over quadrature points and components as one matrix product
+    nq, n = v.shape[0], v.shape[2]
+    V2 = v.reshape(-1, n)
+    D2 = dphys.reshape(-1, n)
+    M = V2.T @ (V2 * np.repeat(wq, v.shape[1])[:, None]) * s
+    K = D2.T @ (D2 * np.repeat(wq, dphys.shape[1])[:, None]) * s
     return beta * M + alpha * K
 
 

@@ -1,0 +1,103 @@
+"""GPU checks at the benchmark's full size and launch configuration (the
+jittered 8^3x6 Kuhn mesh of bench.py, p = 6 and 8): the oracle computes
+sampled outputs one by one, and properties that hold at any size.
+
+* apply_A: sampled rows (A x)_i from the oracle's stacked reference form
+  (itself pinned to the direct definition) within 1e-12 max |y|;
+* apply_P: symmetry r1.P^{-1}r2 = r2.P^{-1}r1 (1e-12 relative), positivity,
+  linearity (1e-12);
+* solve: the library's recursive residual <= 1e-10 and the oracle's residual
+  rows b_i - (A x)_i of the returned x within 2e-10 ||b||_2 (each entry of a
+  vector is bounded by its 2-norm).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.element import element
+from oracle.mesh import Topology
+from oracle.operator import cell_weights, reference_stack
+from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
+
+pytestmark = pytest.mark.gpu
+
+FULL = [("CG", 8), ("Ned", 6), ("Ned", 8), ("RT", 8)]
+_cache = {}
+
+
+def setup_full(fam, p):
+    if (fam, p) not in _cache:
+        from paper_2506_17406_amd import rz
+        X, C = kuhn_mesh(8, 3, jitter=0.1, seed=2)
+        el = element(3, fam, p)
+        top = Topology(X, C, el)
+        prob = rz.Problem(X, C, p, fam)
+        assert prob.n_dofs == top.n_dofs
+        _cache[(fam, p)] = (el, top, reference_stack(el), prob)
+    return _cache[(fam, p)]
+
+
+def sample_dofs(top, per_block=12, seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for l in range(4):
+        lo, hi = top.offset[l], top.offset[l + 1]
+        if hi > lo:
+            out += list(rng.choice(np.arange(lo, hi), size=min(per_block, hi - lo), replace=False))
+    return np.array(out)
+
+
+def oracle_rows(el, top, R, x, rows):
+    y = np.zeros(len(rows))
+    for k, i in enumerate(rows):
+        cells, locs = np.nonzero(top.cell_dofs == i)
+        for c, loc in zip(cells, locs):
+            w = cell_weights(el, top.coords[top.cells[c]])
+            y[k] += np.einsum("q,qj,j->", w, R[:, loc, :], x[top.cell_dofs[c]])
+    return y
+
+
+@pytest.mark.parametrize("fam,p", FULL)
+def test_apply_A_sampled(fam, p):
+    el, top, R, prob = setup_full(fam, p)
+    x = load_vectors(top.n_dofs, 5)[:, 0]
+    yt = torch.empty(top.n_dofs, dtype=torch.float64, device="cuda")
+    prob.apply_A(torch.from_numpy(x).cuda(), yt)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()
+    rows = sample_dofs(top)
+    ref = oracle_rows(el, top, R, x, rows)
+    assert np.abs(y[rows] - ref).max() <= 1e-12 * np.abs(y).max()
+
+
+@pytest.mark.parametrize("fam,p", FULL)
+def test_apply_P_properties(fam, p):
+    el, top, R, prob = setup_full(fam, p)
+    r = load_vectors(top.n_dofs, 8, n_rhs=2)
+    rt = torch.from_numpy(np.ascontiguousarray(r.T)).cuda()
+    z1, z2, z3 = (torch.empty(top.n_dofs, dtype=torch.float64, device="cuda") for _ in range(3))
+    prob.apply_P(rt[0].contiguous(), z1)
+    prob.apply_P(rt[1].contiguous(), z2)
+    prob.apply_P((rt[0] + 2.0 * rt[1]).contiguous(), z3)
+    torch.cuda.synchronize()
+    a = float(torch.dot(rt[0], z2))
+    b = float(torch.dot(rt[1], z1))
+    assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+    assert float(torch.dot(rt[0], z1)) > 0 and float(torch.dot(rt[1], z2)) > 0
+    lin = z1 + 2.0 * z2
+    assert float((z3 - lin).abs().max()) <= 1e-12 * float(lin.abs().max())
+
+
+@pytest.mark.parametrize("fam,p", FULL)
+def test_solve_sampled_residual(fam, p):
+    el, top, R, prob = setup_full(fam, p)
+    b = load_vectors(top.n_dofs, 3)[:, 0]
+    bt = torch.from_numpy(b).cuda()
+    xt = torch.zeros_like(bt)
+    info = prob.solve(bt, xt, rtol=1e-10)
+    assert info["rel_residual"] <= 1e-10
+    x = xt.cpu().numpy()
+    rows = sample_dofs(top, seed=1)
+    res = b[rows] - oracle_rows(el, top, R, x, rows)
+    assert np.abs(res).max() <= 2e-10 * np.linalg.norm(b)

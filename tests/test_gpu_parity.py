@@ -25,8 +25,16 @@ from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
 
 pytestmark = pytest.mark.gpu
 
+# (dim, space, degree, cells per edge (0 = a single tetrahedron), jitter)
 CASES = [(2, "CG", 4, 4, 0.0), (3, "CG", 3, 3, 0.1), (3, "CG", 5, 2, 0.1), (3, "Ned", 3, 2, 0.1),
-         (3, "Ned", 4, 2, 0.1), (3, "RT", 3, 2, 0.1), (3, "RT", 5, 2, 0.1)]
+         (3, "Ned", 4, 2, 0.1), (3, "RT", 3, 2, 0.1), (3, "RT", 5, 2, 0.1),
+         # degenerate and edge cases: Whitney-only elements (p = 1), no interior dofs,
+         # a mesh without interior vertices, a single cell
+         (2, "CG", 1, 3, 0.0), (2, "CG", 2, 3, 0.0), (3, "CG", 1, 2, 0.1), (3, "CG", 2, 1, 0.0),
+         (3, "Ned", 1, 2, 0.1), (3, "Ned", 2, 1, 0.0), (3, "RT", 1, 2, 0.1), (3, "RT", 2, 1, 0.0),
+         (3, "RT", 3, 0, 0.0), (3, "Ned", 3, 0, 0.0),
+         # largest patch templates: full interior stars at p = 8 and p = 10
+         (3, "CG", 8, 2, 0.1), (3, "CG", 10, 2, 0.1), (3, "Ned", 7, 2, 0.1)]
 
 _cache = {}
 
@@ -35,7 +43,11 @@ def setup_case(d, fam, p, n, jit):
     key = (d, fam, p, n, jit)
     if key not in _cache:
         from paper_2506_17406_amd import rz
-        X, C = kuhn_mesh(n, d, jitter=jit, seed=11)
+        if n == 0:
+            X = np.array([[0.1, 0.0, 0.05], [1.0, 0.2, 0.0], [0.3, 0.9, 0.1], [0.2, 0.3, 1.1]])
+            C = np.array([[2, 0, 3, 1]])
+        else:
+            X, C = kuhn_mesh(n, d, jitter=jit, seed=11)
         top = Topology(X, C, element(d, fam, p))
         A = assemble(top, all_cell_matrices(top.el, top))
         P = AdditiveSchwarz(A, top, fam)
@@ -46,7 +58,7 @@ def setup_case(d, fam, p, n, jit):
 
 
 def ids(c):
-    return "{}d-{}{}-n{}".format(*c[:4])
+    return "{}d-{}{}-n{}".format(*c[:4]) if c[3] else "{}d-{}{}-tet".format(*c[:3])
 
 
 @pytest.mark.parametrize("case", CASES, ids=ids)
