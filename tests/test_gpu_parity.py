@@ -3,7 +3,9 @@
 Sizes: meshes with 32-162 cells (several apply_A tiles and a ragged last
 tile), every space, degrees 3-5, seeded jitter and load vectors.
 Bars (written per check):
-* apply_A  -- max |y_gpu - y_oracle| <= 1e-12 max |y_oracle|;
+* apply_A  -- max |y_gpu - y_oracle| <= 1e-12 max |y_oracle| (1e-11 at p > 8,
+              where the library's and the oracle's reference tables agree to
+              ~3e-11);
 * apply_P  -- max |z_gpu - z_oracle| <= 1e-10 max |z_oracle| (the library
               applies explicit inverses, the oracle Cholesky solves);
 * solve    -- same PCG recursion: iteration counts within one, true
@@ -71,7 +73,10 @@ def test_apply_A(case):
     torch.cuda.synchronize()
     y = yt.cpu().numpy()
     ref = A @ x
-    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+    # the two independent reference-table builds agree to ~1e-12 up to p = 8
+    # and to ~3e-11 at p = 10 (conditioning of the eigenbasis construction)
+    tol = 1e-12 if case[2] <= 8 else 1e-11
+    assert np.abs(y - ref).max() <= tol * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("case", CASES, ids=ids)
