@@ -107,10 +107,16 @@ int rz_apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t
  * r, z: device, n_dofs x n_rhs, leading dimension ld; z is overwritten. */
 int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream);
 
-/* PCG on A x = b from the initial guess in x, stopping when the recursive
- * residual satisfies ||r||_2 <= rtol ||b||_2.  b, x: device, n_dofs (one right-hand side).
- * info (host, may be NULL) is filled on return. */
-int rz_solve(rz_problem *P, const double *b, double *x, double rtol, rz_info *info, void *hip_stream);
+/* PCG on A X = B for n_rhs independent columns (each with its own CG
+ * scalars and stopping test), from the initial guess in X, stopping column j
+ * when its recursive residual satisfies ||r_j||_2 <= rtol ||b_j||_2.
+ * B, X: device, n_dofs x n_rhs, leading dimension ld.  The columns share
+ * every operator and preconditioner pass (the patch and coarse inverses are
+ * streamed once for a group of columns).  info (host, n_rhs entries, may be
+ * NULL) is filled on return; the return value is the first non-OK column
+ * status. */
+int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t ld, double rtol, rz_info *info,
+             void *hip_stream);
 
 /* Host copies of the numbering for parity checks: cell_dofs (n_cells x n_loc
  * int32, local dofs in the element's order) and the interface patches as

@@ -61,11 +61,15 @@ struct rz_problem {
   rz::ApplyATables at{};
   std::vector<DevPatchSet> dps;
   rz::CoarseApply ca{};
+  // Krylov workspace for up to ws_cols right-hand sides (grown on demand)
+  int ws_cols = 0;
+  std::vector<void *> ws;
   rz::PcgState *st = nullptr;
   rz::PcgState *st_host = nullptr;
-  double *r = nullptr, *z = nullptr, *pv = nullptr, *Ap = nullptr, *part = nullptr, *part2 = nullptr;
-  double *partA = nullptr, *partR = nullptr, *partZ = nullptr;  // block partials of pAp, rr, rz
+  double *r = nullptr, *z = nullptr, *pv = nullptr, *Ap = nullptr;
+  double *partA = nullptr, *partR = nullptr, *partZ = nullptr, *partB = nullptr;  // block partials
   rz::CoarseFold fold{};
+  std::vector<rz::PatchApply> pas;  // patch sets for the launchers
 
   template <class T>
   T *dev(size_t count) {
@@ -83,9 +87,16 @@ struct rz_problem {
     if (!v.empty()) HIPCHK(hipMemcpy(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     return ptr;
   }
-  ~rz_problem() {
-    for (void *ptr : mem) (void)hipFree(ptr);
+  void free_ws() {
+    for (void *ptr : ws) (void)hipFree(ptr);
+    ws.clear();
     if (st_host) (void)hipHostFree(st_host);
+    st_host = nullptr;
+    ws_cols = 0;
+  }
+  ~rz_problem() {
+    free_ws();
+    for (void *ptr : mem) (void)hipFree(ptr);
   }
 };
 
@@ -293,8 +304,6 @@ void setup_coarse(rz_problem &P, hipStream_t s) {
   P.ca.NT = NT;
   P.ca.wdofs = P.upload(wdofs, s);
   P.ca.tiles = tiles;
-  P.ca.rW = P.dev<double>(N);
-  P.ca.zW = P.dev<double>(N);
 }
 
 void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
@@ -388,20 +397,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     P->dps.resize(P->patches.size());
     for (size_t i = 0; i < P->patches.size(); ++i) setup_patch_set(*P, P->patches[i], P->dps[i], s);
     setup_coarse(*P, s);
-    // Krylov workspace
-    const int64_t nd = P->top.n_dofs;
-    P->st = P->dev<rz::PcgState>(1);
-    HIPCHK(hipHostMalloc((void **)&P->st_host, sizeof(rz::PcgState), hipHostMallocDefault));
-    P->r = P->dev<double>(nd);
-    P->z = P->dev<double>(nd);
-    P->pv = P->dev<double>(nd);
-    P->Ap = P->dev<double>(nd);
-    P->part = P->dev<double>(rz::kRedBlocks);
-    P->part2 = P->dev<double>(rz::kRedBlocks);
-    P->partA = P->dev<double>(rz::kRedBlocks);
-    P->partR = P->dev<double>(rz::kRedBlocks);
-    P->partZ = P->dev<double>(rz::kRedBlocks);
-    P->fold.zW = P->ca.zW;
+    for (auto &d : P->dps) P->pas.push_back(d.pa);
     P->fold.off = P->top.offset[P->k];
     P->fold.N = P->el.per_entity[P->k];
     P->fold.span = P->top.n_ent[P->k] * P->fold.N;
@@ -428,19 +424,45 @@ int rz_sizes(const rz_problem *P, int64_t *n_dofs, int64_t *n_interior, int32_t 
   return RZ_OK;
 }
 
-static int apply_P_impl(rz_problem *P, const double *r, double *z, const rz::PcgState *st, hipStream_t s) {
-  rz::launch_jacobi(P->top.n_dofs, P->off_I, P->dinv, r, z, st, s);
-  for (auto &d : P->dps) rz::launch_patch_apply(d.pa, r, z, st, s);
-  rz::launch_coarse_apply(P->ca, r, z, st, s);
-  return 0;
+static int reduction_blocks(int ncol) { return std::max(4, 512 / std::max(1, ncol)); }
+
+// grows the Krylov workspace to hold ncol columns
+static void ensure_ws(rz_problem *P, int ncol) {
+  if (ncol <= P->ws_cols) return;
+  P->free_ws();
+  const int64_t nd = P->top.n_dofs;
+  const int RB = reduction_blocks(ncol);
+  auto alloc = [&](size_t bytes) {
+    void *ptr = nullptr;
+    HIPCHK(hipMalloc(&ptr, std::max<size_t>(bytes, 8)));
+    P->ws.push_back(ptr);
+    return ptr;
+  };
+  P->st = static_cast<rz::PcgState *>(alloc(sizeof(rz::PcgState) * ncol));
+  HIPCHK(hipHostMalloc((void **)&P->st_host, sizeof(rz::PcgState) * ncol, hipHostMallocDefault));
+  P->r = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
+  P->z = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
+  P->pv = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
+  P->Ap = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
+  // any later solve with fewer columns uses more blocks per column; RB * nc <= 512 + 4 nc always
+  const size_t npart = size_t(std::max<int64_t>(int64_t(RB) * ncol, 512 + 4 * int64_t(ncol)));
+  P->partA = static_cast<double *>(alloc(sizeof(double) * npart));
+  P->partR = static_cast<double *>(alloc(sizeof(double) * npart));
+  P->partZ = static_cast<double *>(alloc(sizeof(double) * npart));
+  P->partB = static_cast<double *>(alloc(sizeof(double) * npart));
+  const size_t npad = size_t(P->ca.NT) * 64;
+  P->ca.rW = static_cast<double *>(alloc(sizeof(double) * npad * ncol));
+  P->ca.zW = static_cast<double *>(alloc(sizeof(double) * npad * ncol));
+  P->fold.zW = P->ca.zW;
+  P->ws_cols = ncol;
 }
 
 int rz_apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream) {
   if (!P || !x || !y) return fail(RZ_ERR_ARG, "null argument");
   if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  for (int c = 0; c < n_rhs; ++c) rz::launch_fill(y + int64_t(c) * ld, P->top.n_dofs, 0.0, nullptr, s);
-  rz::launch_apply_A(P->at, x, y, n_rhs, ld, nullptr, s);
+  rz::launch_fill(y, P->top.n_dofs, ld, n_rhs, nullptr, s);
+  rz::launch_apply_A(P->at, x, ld, y, ld, n_rhs, nullptr, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RZ_ERR_DEVICE, hipGetErrorString(e));
   return RZ_OK;
@@ -450,81 +472,102 @@ int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t
   if (!P || !r || !z) return fail(RZ_ERR_ARG, "null argument");
   if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  for (int c = 0; c < n_rhs; ++c) apply_P_impl(P, r + int64_t(c) * ld, z + int64_t(c) * ld, nullptr, s);
+  try {
+    ensure_ws(P, n_rhs);
+  } catch (const RzError &e) {
+    return fail(e.code, e.msg);
+  }
+  rz::launch_apply_P(P->pas.data(), int(P->pas.size()), P->ca, P->top.n_dofs, P->off_I, P->dinv, r, ld, z, ld, n_rhs,
+                     s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RZ_ERR_DEVICE, hipGetErrorString(e));
   return RZ_OK;
 }
 
-int rz_solve(rz_problem *P, const double *b, double *x, double rtol, rz_info *info, void *hip_stream) {
+int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t ld, double rtol, rz_info *info,
+             void *hip_stream) {
   if (!P || !b || !x) return fail(RZ_ERR_ARG, "null argument");
   if (!(rtol > 0.0)) return fail(RZ_ERR_ARG, "rtol must be positive");
+  if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int64_t nd = P->top.n_dofs;
   const int maxit = P->max_iter;
+  const int nc = n_rhs;
   try {
+    ensure_ws(P, nc);
+    const int RB = reduction_blocks(nc);
+    const int npad = P->ca.NT * 64;
+    const rz::CoarseFold nofold{nullptr, 0, 0, 1};
     auto t0 = std::chrono::steady_clock::now();
     // r = b - A x, convergence reference ||b||
-    rz::launch_fill(P->Ap, nd, 0.0, nullptr, s);
-    rz::launch_apply_A(P->at, x, P->Ap, 1, nd, nullptr, s);
-    rz::launch_residual(nd, b, P->Ap, P->r, s);
-    rz::launch_dot_partial(nd, b, b, P->part, nullptr, s);
-    rz::launch_dot_partial(nd, P->r, P->r, P->part2, nullptr, s);
-    rz::launch_pcg_init(P->st, P->part, P->part2, rtol * rtol, maxit, s);
-    apply_P_impl(P, P->r, P->z, P->st, s);
-    const rz::CoarseFold nofold{nullptr, 0, 0, 1};
-    rz::launch_dot2(nd, P->r, P->z, nofold, P->partZ, P->st, s);
-    rz::launch_copy(nd, P->z, P->pv, s);
-    rz::launch_fill(P->Ap, nd, 0.0, nullptr, s);
+    rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
+    rz::launch_apply_A(P->at, x, ld, P->Ap, nd, nc, nullptr, s);
+    rz::launch_residual(nd, b, ld, P->Ap, P->r, nc, s);
+    rz::launch_dot(nd, b, ld, b, ld, nofold, npad, P->partB, RB, nc, nullptr, s);
+    rz::launch_dot(nd, P->r, nd, P->r, nd, nofold, npad, P->partR, RB, nc, nullptr, s);
+    rz::launch_pcg_start(P->partB, P->partR, RB, rtol * rtol, maxit, P->st, nc, s);
+    // z = P^{-1} r, (r, z), p = z, Ap = 0
+    rz::launch_apply_P(P->pas.data(), int(P->pas.size()), P->ca, nd, P->off_I, P->dinv, P->r, nd, P->z, nd, nc, s);
+    rz::launch_dot(nd, P->r, nd, P->z, nd, nofold, npad, P->partZ, RB, nc, P->st, s);
+    rz::launch_copy(nd, P->z, nd, P->pv, nd, nc, s);
+    rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
     HIPCHK(hipGetLastError());
     const int chunk = 8;
+    const size_t head = offsetof(rz::PcgState, alphas);
     for (int it0 = 0; it0 < maxit; it0 += chunk) {
       for (int it = 0; it < chunk; ++it) {
         // Ap was cleared by the previous p update; partZ holds the partials of (r, z)
-        rz::launch_apply_A(P->at, P->pv, P->Ap, 1, nd, P->st, s);
-        rz::launch_dot2(nd, P->pv, P->Ap, nofold, P->partA, P->st, s);
-        rz::launch_update_xr2(nd, x, P->r, P->pv, P->Ap, P->partZ, P->partA, P->partR, P->st, s);
+        rz::launch_apply_A(P->at, P->pv, nd, P->Ap, nd, nc, P->st, s);
+        rz::launch_dot(nd, P->pv, nd, P->Ap, nd, nofold, npad, P->partA, RB, nc, P->st, s);
+        rz::launch_update_xr(nd, x, ld, P->r, P->pv, P->Ap, P->partZ, P->partA, P->partR, RB, nc, P->st, s);
         // convergence test, then z = P^{-1} r with the coarse part left in zW
-        rz::launch_check_jacobi(nd, P->off_I, P->dinv, P->r, P->z, P->ca, P->partR, P->st, s);
-        for (auto &d : P->dps) rz::launch_patch_apply(d.pa, P->r, P->z, P->st, s);
-        rz::launch_coarse_tiles(P->ca, P->st, s);
-        rz::launch_dot2(nd, P->r, P->z, P->fold, P->partZ, P->st, s);
-        rz::launch_update_p2(nd, P->pv, P->z, P->fold, P->Ap, P->partZ, P->st, s);
+        rz::launch_check_jacobi(nd, P->off_I, P->dinv, P->r, P->z, P->ca, P->partR, RB, nc, P->st, s);
+        for (auto &pa : P->pas) rz::launch_patch_apply(pa, P->r, nd, P->z, nd, nc, P->st, s);
+        rz::launch_coarse_tiles(P->ca, nc, P->st, s);
+        rz::launch_dot(nd, P->r, nd, P->z, nd, P->fold, npad, P->partZ, RB, nc, P->st, s);
+        rz::launch_update_p(nd, P->pv, P->z, P->fold, npad, P->Ap, P->partZ, RB, nc, P->st, s);
       }
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(P->st_host, P->st, offsetof(rz::PcgState, alphas), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpy2DAsync(P->st_host, sizeof(rz::PcgState), P->st, sizeof(rz::PcgState), head, nc,
+                              hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      if (P->st_host->done) break;
+      bool all = true;
+      for (int c = 0; c < nc; ++c) all = all && P->st_host[c].done;
+      if (all) break;
     }
-    HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(rz::PcgState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(rz::PcgState) * nc, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
-    const rz::PcgState &h = *P->st_host;
-    // Lanczos condition estimate from the CG coefficients
-    double cond = 1.0;
-    const int kk = std::min(h.iter, rz::kMaxIter);
-    if (kk > 0) {
-      rz::Dense T(kk, kk);
-      for (int j = 0; j < kk; ++j) {
-        T(j, j) = 1.0 / h.alphas[j] + (j > 0 ? h.betas[j - 1] / h.alphas[j - 1] : 0.0);
-        if (j > 0) T(j, j - 1) = T(j - 1, j) = std::sqrt(std::max(0.0, h.betas[j - 1])) / h.alphas[j - 1];
+    int worst = RZ_OK;
+    for (int c = 0; c < nc; ++c) {
+      const rz::PcgState &h = P->st_host[c];
+      // Lanczos condition estimate from the CG coefficients
+      double cond = 1.0;
+      const int kk = std::min(h.iter, rz::kMaxIter);
+      if (kk > 0) {
+        rz::Dense T(kk, kk);
+        for (int j = 0; j < kk; ++j) {
+          T(j, j) = 1.0 / h.alphas[j] + (j > 0 ? h.betas[j - 1] / h.alphas[j - 1] : 0.0);
+          if (j > 0) T(j, j - 1) = T(j - 1, j) = std::sqrt(std::max(0.0, h.betas[j - 1])) / h.alphas[j - 1];
+        }
+        std::vector<double> ev;
+        rz::Dense V;
+        rz::sym_eig(T, ev, V);
+        if (ev.front() > 0) cond = ev.back() / ev.front();
       }
-      std::vector<double> ev;
-      rz::Dense V;
-      rz::sym_eig(T, ev, V);
-      if (ev.front() > 0) cond = ev.back() / ev.front();
+      int code = RZ_OK;
+      if (h.status == rz::PCG_MAXIT || !h.done) code = RZ_ERR_NO_CONVERGENCE;
+      if (h.status == rz::PCG_BREAKDOWN) code = RZ_ERR_BREAKDOWN;
+      if (code != RZ_OK && worst == RZ_OK) worst = code;
+      if (info) {
+        info[c].status = code;
+        info[c].iterations = h.iter;
+        info[c].rel_residual = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+        info[c].cond_estimate = cond;
+        info[c].solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+      }
     }
-    int code = RZ_OK;
-    if (h.status == rz::PCG_MAXIT) code = RZ_ERR_NO_CONVERGENCE;
-    if (h.status == rz::PCG_BREAKDOWN) code = RZ_ERR_BREAKDOWN;
-    if (info) {
-      info->status = code;
-      info->iterations = h.iter;
-      info->rel_residual = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
-      info->cond_estimate = cond;
-      info->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    }
-    if (code != RZ_OK) return fail(code, code == RZ_ERR_BREAKDOWN ? "CG breakdown" : "no convergence");
+    if (worst != RZ_OK) return fail(worst, worst == RZ_ERR_BREAKDOWN ? "CG breakdown" : "no convergence");
   } catch (const RzError &e) {
     return fail(e.code, e.msg);
   }

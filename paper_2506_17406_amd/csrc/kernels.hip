@@ -368,15 +368,15 @@ __global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A,
 template <int Q, int NB>
 __global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int64_t nc, const double *__restrict__ Af,
                                                  const double *__restrict__ w, const int32_t *__restrict__ cd,
-                                                 const double *__restrict__ x, double *__restrict__ y, int64_t ld,
-                                                 const PcgState *st) {
-  if (st && st->done) return;
+                                                 const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
+                                                 int64_t ldy, const PcgState *st) {
+  if (st && st[blockIdx.z].done) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mb = blockIdx.y * 4 + wave;
   if (mb >= NMB) return;
   const int li = lane & 15, lk = lane >> 4;
-  const double *xr = x + int64_t(blockIdx.z) * ld;
-  double *yr = y + int64_t(blockIdx.z) * ld;
+  const double *xr = x + int64_t(blockIdx.z) * ldx;
+  double *yr = y + int64_t(blockIdx.z) * ldy;
   const int64_t cell0 = int64_t(blockIdx.x) * (16 * NB);
   const int32_t *cdp[NB];
   double wv[NB][Q];
@@ -436,21 +436,17 @@ __global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int64_t
   }
 }
 
-__global__ void k_fill(double *y, int64_t n, double v, const PcgState *st) {
-  if (st && st->done) return;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    y[i] = v;
-}
 
 // -------------------------------------------------------------- apply_P
 // Work item = (patch, row range [r0, r1)) of the packed upper triangle of the
-// patch inverse (rows ~balanced by element count).  The patch right-hand side
-// is gathered into LDS; each wave takes every fourth row, with the next row's
-// entries loaded before the current row's products are reduced; columns j are
-// owned by lane j % 64.  Row sums (j >= i) and the mirrored column sums
-// (j > i) of the chunk are combined in LDS and scatter-added (atomics: chunks
-// and patches overlap).
-template <int MAXJ>
+// patch inverse (rows ~balanced by element count) and a group of G right-hand
+// sides (so each packed entry streamed from HBM serves G columns).  The patch
+// right-hand sides are gathered into LDS; each wave takes every fourth row,
+// with the next row's entries loaded before the current row's products are
+// reduced; column j is owned by lane j % 64.  Row sums (j >= i) and the
+// mirrored column sums (j > i) of the chunk are combined in LDS and
+// scatter-added (atomics: chunks and patches overlap).
+template <int MAXJ, int G>
 __global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__ chunk_patch,
                                                      const int32_t *__restrict__ chunk_rows,
                                                      const int64_t *__restrict__ patch_col,
@@ -459,28 +455,41 @@ __global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__
                                                      const double *__restrict__ ent_coef,
                                                      const int64_t *__restrict__ inv_off,
                                                      const double *__restrict__ inv, const double *__restrict__ r,
-                                                     double *__restrict__ z, int maxsz, const PcgState *st) {
-  if (st && st->done) return;
+                                                     int64_t ldr, double *__restrict__ z, int64_t ldz, int ncol,
+                                                     int maxsz, const PcgState *st) {
+  const int cbase = blockIdx.y * G;
+  if (st) {
+    bool any = false;
+    for (int g = 0; g < G; ++g)
+      if (cbase + g < ncol && !st[cbase + g].done) any = true;
+    if (!any) return;
+  }
   extern __shared__ double sm[];
-  double *rp = sm;              // gathered right-hand side
-  double *yr = sm + maxsz;      // row products of this chunk
-  double *yc = sm + 2 * maxsz;  // 4 x column partials
+  double *rp = sm;                  // G x maxsz gathered right-hand sides
+  double *yr = sm + G * maxsz;      // G x maxsz row products
+  double *yc = sm + 2 * G * maxsz;  // 4 x G x maxsz column partials
   const int64_t p = chunk_patch[blockIdx.x];
   const int r0 = chunk_rows[2 * blockIdx.x], r1 = chunk_rows[2 * blockIdx.x + 1];
   const int64_t c0 = patch_col[p];
   const int m = int(patch_col[p + 1] - c0);
-  for (int j = threadIdx.x; j < m; j += 256) {
-    double s = 0;
-    for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) s += ent_coef[e] * r[ent_dof[e]];
-    rp[j] = s;
-    yr[j] = 0.0;
+  for (int t = threadIdx.x; t < G * m; t += 256) {
+    const int g = t / m, j = t - g * m;
+    double sv = 0;
+    if (cbase + g < ncol) {
+      const double *rc = r + int64_t(cbase + g) * ldr;
+      for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) sv += ent_coef[e] * rc[ent_dof[e]];
+    }
+    rp[g * maxsz + j] = sv;
+    yr[g * maxsz + j] = 0.0;
   }
   __syncthreads();
   const double *A = inv + inv_off[p];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double cacc[MAXJ], cur[MAXJ], nxt[MAXJ];
+  double cacc[MAXJ][G], cur[MAXJ], nxt[MAXJ];
 #pragma unroll
-  for (int jb = 0; jb < MAXJ; ++jb) cacc[jb] = 0.0;
+  for (int jb = 0; jb < MAXJ; ++jb)
+#pragma unroll
+    for (int g = 0; g < G; ++g) cacc[jb][g] = 0.0;
   auto load_row = [&](int i, double *buf) {
     const double *row = A + int64_t(i) * m - int64_t(i) * (i - 1) / 2 - i;  // row[j] = A_ij, j >= i
 #pragma unroll
@@ -493,53 +502,57 @@ __global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__
   if (i < r1) load_row(i, cur);
   for (; i < r1; i += 4) {
     if (i + 4 < r1) load_row(i + 4, nxt);
-    const double ri = rp[i];
-    double rs = 0.0;
 #pragma unroll
-    for (int jb = 0; jb < MAXJ; ++jb) {
-      const int j = jb * 64 + lane;
-      const double a = cur[jb];
-      const double rj = j < m ? rp[j] : 0.0;
-      rs += a * rj;
-      cacc[jb] += (j > i) ? a * ri : 0.0;
+    for (int g = 0; g < G; ++g) {
+      const double ri = rp[g * maxsz + i];
+      double rs = 0.0;
+#pragma unroll
+      for (int jb = 0; jb < MAXJ; ++jb) {
+        const int j = jb * 64 + lane;
+        const double a = cur[jb];
+        const double rj = j < m ? rp[g * maxsz + j] : 0.0;
+        rs += a * rj;
+        cacc[jb][g] += (j > i) ? a * ri : 0.0;
+      }
+      rs = wave_sum(rs);
+      if (lane == 0) yr[g * maxsz + i] = rs;
     }
-    rs = wave_sum(rs);
-    if (lane == 0) yr[i] = rs;
 #pragma unroll
     for (int jb = 0; jb < MAXJ; ++jb) cur[jb] = nxt[jb];
   }
 #pragma unroll
   for (int jb = 0; jb < MAXJ; ++jb) {
     const int j = jb * 64 + lane;
-    if (j < m) yc[wave * maxsz + j] = cacc[jb];
+    if (j < m)
+#pragma unroll
+      for (int g = 0; g < G; ++g) yc[(wave * G + g) * maxsz + j] = cacc[jb][g];
   }
   __syncthreads();
-  for (int j = r0 + threadIdx.x; j < m; j += 256) {
-    const double y = yr[j] + ((yc[j] + yc[maxsz + j]) + (yc[2 * maxsz + j] + yc[3 * maxsz + j]));
-    for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) atomicAdd(&z[ent_dof[e]], ent_coef[e] * y);
+  for (int t = threadIdx.x; t < G * m; t += 256) {
+    const int g = t / m, j = t - g * m;
+    if (j < r0 || cbase + g >= ncol) continue;
+    const double y = yr[g * maxsz + j] + ((yc[(0 * G + g) * maxsz + j] + yc[(1 * G + g) * maxsz + j]) +
+                                          (yc[(2 * G + g) * maxsz + j] + yc[(3 * G + g) * maxsz + j]));
+    double *zc = z + int64_t(cbase + g) * ldz;
+    for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) atomicAdd(&zc[ent_dof[e]], ent_coef[e] * y);
   }
 }
 
-__global__ void k_jacobi(int64_t n, int64_t offI, const double *__restrict__ dinv, const double *__restrict__ r,
-                         double *__restrict__ z, const PcgState *st) {
-  if (st && st->done) return;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    z[i] = i >= offI ? r[i] * dinv[i - offI] : 0.0;
-}
-
-__global__ void k_coarse_gather(int nW, int npad, const int32_t *__restrict__ wd, const double *__restrict__ r,
-                                double *__restrict__ rW, double *__restrict__ zW, const PcgState *st) {
-  if (st && st->done) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npad) return;
-  rW[i] = i < nW ? r[wd[i]] : 0.0;
-  zW[i] = 0.0;
-}
-
+// coarse solve: upper 64 x 64 tiles (I <= J) of the packed inverse, one wave
+// per tile, G right-hand sides per pass.  Lane c keeps column c of the tile in
+// registers; A_IJ^T r_I is a lane-local sum, A_IJ r_J goes through an LDS
+// transpose.  rW / zW: npad x ncol.
+template <int G>
 __global__ __launch_bounds__(64) void k_coarse_tiles(int NT, const double *__restrict__ T,
                                                      const double *__restrict__ rW, double *__restrict__ zW,
-                                                     const PcgState *st) {
-  if (st && st->done) return;
+                                                     int npad, int ncol, const PcgState *st) {
+  const int cbase = blockIdx.y * G;
+  if (st) {
+    bool any = false;
+    for (int g = 0; g < G; ++g)
+      if (cbase + g < ncol && !st[cbase + g].done) any = true;
+    if (!any) return;
+  }
   __shared__ double tr[64][65];
   const int64_t t = blockIdx.x;
   int I = 0;
@@ -547,278 +560,229 @@ __global__ __launch_bounds__(64) void k_coarse_tiles(int NT, const double *__res
   const int J = int(t - (int64_t(I) * NT - int64_t(I) * (I - 1) / 2)) + I;
   const int c = threadIdx.x;
   const double *tile = T + t * 4096;
-  const double rJc = rW[J * 64 + c];
-  double col = 0;
-  for (int r = 0; r < 64; ++r) {
-    const double a = tile[r * 64 + c];
-    col += a * rW[I * 64 + r];
-    tr[r][c] = a * rJc;
+  double a[64];
+#pragma unroll
+  for (int r = 0; r < 64; ++r) a[r] = tile[r * 64 + c];
+  for (int g = 0; g < G; ++g) {
+    if (cbase + g >= ncol) break;
+    const double *rc = rW + int64_t(cbase + g) * npad;
+    double *zc = zW + int64_t(cbase + g) * npad;
+    const double rJc = rc[J * 64 + c];
+    double col = 0;
+#pragma unroll
+    for (int r = 0; r < 64; ++r) {
+      col += a[r] * rc[I * 64 + r];
+      tr[r][c] = a[r] * rJc;
+    }
+    __syncthreads();
+    double row = 0;
+    for (int cc = 0; cc < 64; ++cc) row += tr[c][cc];
+    atomicAdd(&zc[I * 64 + c], row);
+    if (I < J) atomicAdd(&zc[J * 64 + c], col);
+    __syncthreads();
   }
-  __syncthreads();
-  double row = 0;
-  for (int cc = 0; cc < 64; ++cc) row += tr[c][cc];
-  atomicAdd(&zW[I * 64 + c], row);
-  if (I < J) atomicAdd(&zW[J * 64 + c], col);
-}
-
-__global__ void k_coarse_scatter(int nW, const int32_t *__restrict__ wd, const double *__restrict__ zW,
-                                 double *__restrict__ z, const PcgState *st) {
-  if (st && st->done) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nW) z[wd[i]] += zW[i];
 }
 
 // -------------------------------------------------------------- Krylov
-__global__ __launch_bounds__(256) void k_dot_partial(int64_t n, const double *__restrict__ a,
-                                                     const double *__restrict__ b, double *__restrict__ part,
-                                                     const PcgState *st) {
-  if (st && st->done) return;
-  __shared__ double sm4[4];
-  double s = 0;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) s += a[i] * b[i];
-  s = block_sum256(s, sm4);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+// Multi-column PCG: column c of every vector lives at base + c * ld; each
+// column has its own state st[c] and RB block partials at part[c * RB ...].
+// A reduction kernel leaves the partials; the kernel consuming the scalar
+// re-sums them in every block (fixed order, all blocks agree bit for bit), so
+// the kernel boundary makes them visible without device-scope fences.
+__device__ inline double sum_part(const double *part, int RB, double *sm4) {
+  double v = 0;
+  for (int i = threadIdx.x; i < RB; i += 256) v += part[i];
+  return block_sum256(v, sm4);
 }
 
-__device__ inline double sum_partials(const double *part, double *sm4) {
-  double s = 0;
-  for (int i = threadIdx.x; i < kRedBlocks; i += 256) s += part[i];
-  return block_sum256(s, sm4);
-}
-
-__global__ __launch_bounds__(256) void k_pcg_init(PcgState *st, const double *part, const double *part2, double tol2,
-                                                  int maxit) {
-  __shared__ double sm4[4];
-  const double bb = sum_partials(part, sm4);
-  const double rr = sum_partials(part2, sm4);
-  if (threadIdx.x == 0) {
-    st->bb = bb;
-    st->rr = rr;
-    st->tol2 = tol2;
-    st->iter = 0;
-    st->maxit = maxit;
-    st->status = PCG_RUNNING;
-    st->done = 0;
-    if (!(bb > 0.0) || rr <= tol2 * bb) {
-      st->done = 1;
-      st->status = PCG_CONVERGED;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_set_rz(PcgState *st, const double *part) {
-  if (st->done) return;
-  __shared__ double sm4[4];
-  const double rz = sum_partials(part, sm4);
-  if (threadIdx.x == 0) {
-    st->rz = rz;
-    if (!(rz > 0.0) || !isfinite(rz)) {
-      st->done = 1;
-      st->status = PCG_BREAKDOWN;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_finalize_alpha(PcgState *st, const double *part) {
-  if (st->done) return;
-  __shared__ double sm4[4];
-  const double pAp = sum_partials(part, sm4);
-  if (threadIdx.x == 0) {
-    st->pAp = pAp;
-    if (!(pAp > 0.0) || !isfinite(pAp)) {
-      st->done = 1;
-      st->status = PCG_BREAKDOWN;
-    } else {
-      st->alpha = st->rz / pAp;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_update_xr(int64_t n, double *__restrict__ x, double *__restrict__ r,
-                                                   const double *__restrict__ p, const double *__restrict__ Ap,
-                                                   double *__restrict__ part, const PcgState *st) {
-  if (st->done) return;
-  __shared__ double sm4[4];
-  const double alpha = st->alpha;
-  double s = 0;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * Ap[i];
-    r[i] = ri;
-    s += ri * ri;
-  }
-  s = block_sum256(s, sm4);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-__global__ __launch_bounds__(256) void k_finalize_rr(PcgState *st, const double *part) {
-  if (st->done) return;
-  __shared__ double sm4[4];
-  const double rr = sum_partials(part, sm4);
-  if (threadIdx.x == 0) {
-    st->rr = rr;
-    const int it = st->iter;
-    if (it < kMaxIter) st->alphas[it] = st->alpha;
-    st->iter = it + 1;
-    if (!isfinite(rr)) {
-      st->done = 1;
-      st->status = PCG_BREAKDOWN;
-    } else if (rr <= st->tol2 * st->bb) {
-      st->done = 1;
-      st->status = PCG_CONVERGED;
-    } else if (it + 1 >= st->maxit) {
-      st->done = 1;
-      st->status = PCG_MAXIT;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_finalize_beta(PcgState *st, const double *part) {
-  if (st->done) return;
-  __shared__ double sm4[4];
-  const double rz = sum_partials(part, sm4);
-  if (threadIdx.x == 0) {
-    if (!(rz > 0.0) || !isfinite(rz)) {
-      st->done = 1;
-      st->status = PCG_BREAKDOWN;
-      return;
-    }
-    const double beta = rz / st->rz;
-    st->beta = beta;
-    st->rz = rz;
-    if (st->iter - 1 < kMaxIter) st->betas[st->iter - 1] = beta;
-  }
-}
-
-__global__ void k_update_p(int64_t n, double *__restrict__ p, const double *__restrict__ z, const PcgState *st) {
-  if (st->done) return;
-  const double beta = st->beta;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    p[i] = z[i] + beta * p[i];
-}
-
-__global__ void k_residual(int64_t n, const double *__restrict__ b, const double *__restrict__ Ax,
-                           double *__restrict__ r) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    r[i] = b[i] - Ax[i];
-}
-
-__global__ void k_copy(int64_t n, const double *__restrict__ a, double *__restrict__ b) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    b[i] = a[i];
-}
-
-// ---- fused iteration kernels.  A reduction kernel leaves one partial sum
-// per block; the kernel that consumes the scalar re-sums the partials in
-// every block (fixed order, so all blocks agree bit for bit) -- the kernel
-// boundary makes the partials visible without device-scope fences.
-
-// coarse correction of dof i folded in (z + R_W^T zW), when zW is given
-__device__ inline double z_full(int64_t i, const double *z, const CoarseFold &cf) {
+// coarse correction folded in: z_i + zW[t / N] when i = off + t, t % N == 0
+__device__ inline double z_full(int64_t i, const double *z, const double *zW, const CoarseFold &cf) {
   double v = z[i];
-  if (cf.zW) {
+  if (zW) {
     const int64_t t = i - cf.off;
-    if (t >= 0 && t < cf.span && t % cf.N == 0) v += cf.zW[t / cf.N];
+    if (t >= 0 && t < cf.span && t % cf.N == 0) v += zW[t / cf.N];
   }
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_dot2(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
-                                              CoarseFold cf, double *__restrict__ part, const PcgState *st) {
-  if (st->done) return;
+__global__ __launch_bounds__(256) void k_dot_m(int64_t n, const double *__restrict__ a, int64_t lda,
+                                               const double *__restrict__ b, int64_t ldb, CoarseFold cf, int npad,
+                                               double *__restrict__ part, int RB, const PcgState *st) {
+  const int c = blockIdx.y;
+  if (st && st[c].done) return;
   __shared__ double sm4[4];
+  const double *ac = a + c * lda, *bc = b + c * ldb;
+  const double *zW = cf.zW ? cf.zW + int64_t(c) * npad : nullptr;
   double s = 0;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
-    s += a[i] * z_full(i, b, cf);
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(RB) * 256)
+    s += ac[i] * z_full(i, bc, zW, cf);
   s = block_sum256(s, sm4);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (threadIdx.x == 0) part[c * RB + blockIdx.x] = s;
+}
+
+// PCG start: bb = ||b||^2, rr = ||r||^2 (partials in partZ / partR)
+__global__ __launch_bounds__(256) void k_pcg_start(const double *__restrict__ partB, const double *__restrict__ partR,
+                                                   int RB, double tol2, int maxit, PcgState *st) {
+  __shared__ double sm4[4];
+  const int c = blockIdx.x;
+  const double bb = sum_part(partB + c * RB, RB, sm4);
+  const double rr = sum_part(partR + c * RB, RB, sm4);
+  if (threadIdx.x == 0) {
+    PcgState &s = st[c];
+    s.bb = bb;
+    s.rr = rr;
+    s.tol2 = tol2;
+    s.iter = 0;
+    s.maxit = maxit;
+    s.status = PCG_RUNNING;
+    s.done = 0;
+    if (!(bb > 0.0) || rr <= tol2 * bb) {
+      s.done = 1;
+      s.status = PCG_CONVERGED;
+    }
+  }
 }
 
 // alpha = rz / pAp; x += alpha p; r -= alpha Ap; partials of ||r||^2
-__global__ __launch_bounds__(256) void k_update_xr2(int64_t n, double *__restrict__ x, double *__restrict__ r,
-                                                    const double *__restrict__ p, const double *__restrict__ Ap,
-                                                    const double *__restrict__ partZ,
-                                                    const double *__restrict__ partA, double *__restrict__ partR,
-                                                    PcgState *st) {
-  if (st->done) return;
+__global__ __launch_bounds__(256) void k_update_xr_m(int64_t n, double *__restrict__ x, int64_t ldx,
+                                                     double *__restrict__ r, const double *__restrict__ p,
+                                                     const double *__restrict__ Ap, const double *__restrict__ partZ,
+                                                     const double *__restrict__ partA, double *__restrict__ partR,
+                                                     int RB, PcgState *st) {
+  const int c = blockIdx.y;
+  if (st[c].done) return;
   __shared__ double sm4[4];
-  const double rz = sum_partials(partZ, sm4);
-  const double pAp = sum_partials(partA, sm4);
+  const double rz = sum_part(partZ + c * RB, RB, sm4);
+  const double pAp = sum_part(partA + c * RB, RB, sm4);
   if (!(pAp > 0.0) || !isfinite(pAp) || !(rz > 0.0) || !isfinite(rz)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->done = 1;
-      st->status = PCG_BREAKDOWN;
+      st[c].done = 1;
+      st[c].status = PCG_BREAKDOWN;
     }
     return;
   }
   const double alpha = rz / pAp;
+  double *xc = x + c * ldx, *rc = r + c * n;
+  const double *pc = p + c * n, *apc = Ap + c * n;
   double s = 0;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * Ap[i];
-    r[i] = ri;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(RB) * 256) {
+    xc[i] += alpha * pc[i];
+    const double ri = rc[i] - alpha * apc[i];
+    rc[i] = ri;
     s += ri * ri;
   }
   s = block_sum256(s, sm4);
   if (threadIdx.x == 0) {
-    partR[blockIdx.x] = s;
+    partR[c * RB + blockIdx.x] = s;
     if (blockIdx.x == 0) {
-      st->rz = rz;
-      st->pAp = pAp;
-      st->alpha = alpha;
-      if (st->iter < kMaxIter) st->alphas[st->iter] = alpha;
+      st[c].rz = rz;
+      st[c].pAp = pAp;
+      st[c].alpha = alpha;
+      if (st[c].iter < kMaxIter) st[c].alphas[st[c].iter] = alpha;
     }
   }
 }
 
 // convergence test on ||r||^2, then z = D_I^{-1} r (0 off the interior) and
-// the coarse gather rW = R_W r, zW = 0
-__global__ __launch_bounds__(256) void k_check_jacobi(int64_t n, int64_t offI, const double *__restrict__ dinv,
-                                                      const double *__restrict__ r, double *__restrict__ z, int nW,
-                                                      int npad, const int32_t *__restrict__ wd,
-                                                      double *__restrict__ rW, double *__restrict__ zW,
-                                                      const double *__restrict__ partR, PcgState *st) {
-  if (st->done) return;
+// the coarse gather rW = R_W r, zW = 0 (all for column blockIdx.y)
+__global__ __launch_bounds__(256) void k_check_jacobi_m(int64_t n, int64_t offI, const double *__restrict__ dinv,
+                                                        const double *__restrict__ r, double *__restrict__ z,
+                                                        int nW, int npad, const int32_t *__restrict__ wd,
+                                                        double *__restrict__ rW, double *__restrict__ zW,
+                                                        const double *__restrict__ partR, int RB, PcgState *st) {
+  const int c = blockIdx.y;
+  if (st[c].done) return;
   __shared__ double sm4[4];
-  const double rr = sum_partials(partR, sm4);
-  const bool bad = !isfinite(rr), conv = rr <= st->tol2 * st->bb;  // identical in every block
+  const double rr = sum_part(partR + c * RB, RB, sm4);
+  const bool bad = !isfinite(rr), conv = rr <= st[c].tol2 * st[c].bb;  // identical in every block
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     // only this thread reads and writes the iteration count
-    const int it = st->iter + 1;
-    st->rr = rr;
-    st->iter = it;
-    if (bad || conv || it >= st->maxit) {
-      st->status = bad ? PCG_BREAKDOWN : (conv ? PCG_CONVERGED : PCG_MAXIT);
-      st->done = 1;
+    const int it = st[c].iter + 1;
+    st[c].rr = rr;
+    st[c].iter = it;
+    if (bad || conv || it >= st[c].maxit) {
+      st[c].status = bad ? PCG_BREAKDOWN : (conv ? PCG_CONVERGED : PCG_MAXIT);
+      st[c].done = 1;
     }
   }
   // at the iteration cap the remaining blocks still form z, which is then unused
   if (bad || conv) return;
+  const double *rc = r + c * n;
+  double *zc = z + c * n, *rWc = rW + int64_t(c) * npad, *zWc = zW + int64_t(c) * npad;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
-    z[i] = i >= offI ? r[i] * dinv[i - offI] : 0.0;
+    zc[i] = i >= offI ? rc[i] * dinv[i - offI] : 0.0;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < npad; i += stride) {
-    rW[i] = i < nW ? r[wd[i]] : 0.0;
-    zW[i] = 0.0;
+    rWc[i] = i < nW ? rc[wd[i]] : 0.0;
+    zWc[i] = 0.0;
   }
 }
 
 // beta = rz_new / rz; p = z + beta p (coarse part folded in); Ap = 0
-__global__ __launch_bounds__(256) void k_update_p2(int64_t n, double *__restrict__ p, const double *__restrict__ z,
-                                                   CoarseFold cf, double *__restrict__ Ap,
-                                                   const double *__restrict__ partZ, PcgState *st) {
-  if (st->done) return;
+__global__ __launch_bounds__(256) void k_update_p_m(int64_t n, double *__restrict__ p, const double *__restrict__ z,
+                                                    CoarseFold cf, int npad, double *__restrict__ Ap,
+                                                    const double *__restrict__ partZ, int RB, PcgState *st) {
+  const int c = blockIdx.y;
+  if (st[c].done) return;
   __shared__ double sm4[4];
-  const double rz_new = sum_partials(partZ, sm4);
-  const double beta = rz_new / st->rz;
+  const double rz_new = sum_part(partZ + c * RB, RB, sm4);
+  const double beta = rz_new / st[c].rz;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->beta = beta;
-    if (st->iter - 1 < kMaxIter) st->betas[st->iter - 1] = beta;
+    st[c].beta = beta;
+    if (st[c].iter - 1 < kMaxIter) st[c].betas[st[c].iter - 1] = beta;
   }
+  double *pc = p + c * n, *apc = Ap + c * n;
+  const double *zc = z + c * n;
+  const double *zW = cf.zW ? cf.zW + int64_t(c) * npad : nullptr;
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
-    p[i] = z_full(i, z, cf) + beta * p[i];
-    Ap[i] = 0.0;
+    pc[i] = z_full(i, zc, zW, cf) + beta * pc[i];
+    apc[i] = 0.0;
   }
+}
+
+// per column: r = b - Ax (b at ldb), p = 0 (set later), used at the start
+__global__ void k_residual_m(int64_t n, const double *__restrict__ b, int64_t ldb, const double *__restrict__ Ax,
+                             double *__restrict__ r) {
+  const int c = blockIdx.y;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    r[c * n + i] = b[c * ldb + i] - Ax[c * n + i];
+}
+
+__global__ void k_fill_m(double *__restrict__ y, int64_t n, int64_t ld, const PcgState *st) {
+  const int c = blockIdx.y;
+  if (st && st[c].done) return;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[c * ld + i] = 0.0;
+}
+
+__global__ void k_copy_m(int64_t n, const double *__restrict__ a, int64_t lda, double *__restrict__ b, int64_t ldb) {
+  const int c = blockIdx.y;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    b[c * ldb + i] = a[c * lda + i];
+}
+
+// coarse: rW = R_W r (all columns), zW = 0; and z += R_W^T zW
+__global__ void k_coarse_gather_m(int nW, int npad, const int32_t *__restrict__ wd, const double *__restrict__ r,
+                                  int64_t ldr, double *__restrict__ rW, double *__restrict__ zW) {
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  rW[int64_t(c) * npad + i] = i < nW ? r[c * ldr + wd[i]] : 0.0;
+  zW[int64_t(c) * npad + i] = 0.0;
+}
+
+__global__ void k_coarse_scatter_m(int nW, int npad, const int32_t *__restrict__ wd, const double *__restrict__ zW,
+                                   double *__restrict__ z, int64_t ldz) {
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nW) z[c * ldz + wd[i]] += zW[int64_t(c) * npad + i];
+}
+
+__global__ void k_jacobi_m(int64_t n, int64_t offI, const double *__restrict__ dinv, const double *__restrict__ r,
+                           int64_t ldr, double *__restrict__ z, int64_t ldz) {
+  const int c = blockIdx.y;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    z[c * ldz + i] = i >= offI ? r[c * ldr + i] * dinv[i - offI] : 0.0;
 }
 
 }  // namespace
@@ -878,120 +842,126 @@ void launch_pack_tiles(int N, int n, const double *Ainv, double *tiles, hipStrea
 }
 
 template <int Q>
-static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, const double *x, double *y, int64_t ld,
-                      const PcgState *st, hipStream_t s) {
+static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, const double *x, int64_t ldx, double *y,
+                      int64_t ldy, const PcgState *st, hipStream_t s) {
   const int KB = t.KP / 4, NMB = t.NP / 16;
   if (NB == 4)
     hipLaunchKernelGGL((k_apply_A<Q, 4>), grid, dim3(256), 0, s, t.n, NMB, KB, t.n_cells, t.Afrag, t.w, t.cell_dofs,
-                       x, y, ld, st);
+                       x, ldx, y, ldy, st);
   else if (NB == 2)
     hipLaunchKernelGGL((k_apply_A<Q, 2>), grid, dim3(256), 0, s, t.n, NMB, KB, t.n_cells, t.Afrag, t.w, t.cell_dofs,
-                       x, y, ld, st);
+                       x, ldx, y, ldy, st);
   else
     hipLaunchKernelGGL((k_apply_A<Q, 1>), grid, dim3(256), 0, s, t.n, NMB, KB, t.n_cells, t.Afrag, t.w, t.cell_dofs,
-                       x, y, ld, st);
+                       x, ldx, y, ldy, st);
 }
 
-void launch_apply_A(const ApplyATables &t, const double *x, double *y, int n_rhs, int64_t ld, const PcgState *st,
-                    hipStream_t s) {
+void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
+                    const PcgState *st, hipStream_t s) {
   const int NMB = t.NP / 16;
   // cells per wave: as many as keep >= 2048 waves in flight (A-fragment reuse vs occupancy)
   int NB = 4;
   while (NB > 1 && ((t.n_cells + 16 * NB - 1) / (16 * NB)) * NMB * n_rhs < 2048) NB /= 2;
   dim3 grid(unsigned((t.n_cells + 16 * NB - 1) / (16 * NB)), unsigned((NMB + 3) / 4), unsigned(n_rhs));
-  if (t.Q == 12) apply_A_q<12>(t, NB, grid, x, y, ld, st, s);
-  else if (t.Q == 7) apply_A_q<7>(t, NB, grid, x, y, ld, st, s);
-  else apply_A_q<4>(t, NB, grid, x, y, ld, st, s);
+  if (t.Q == 12) apply_A_q<12>(t, NB, grid, x, ldx, y, ldy, st, s);
+  else if (t.Q == 7) apply_A_q<7>(t, NB, grid, x, ldx, y, ldy, st, s);
+  else apply_A_q<4>(t, NB, grid, x, ldx, y, ldy, st, s);
 }
 
-void launch_fill(double *y, int64_t n, double v, const PcgState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, y, n, v, st);
+// patch apply: largest G in {8,4,2,1} with G <= ncol, LDS <= 96 KB, MAXJ * G <= 32
+template <int MJ>
+static void patch_g(const PatchApply &pa, dim3 g1, int G, size_t lds_per_g, const double *r, int64_t ldr, double *z,
+                    int64_t ldz, int ncol, const PcgState *st, hipStream_t s) {
+  dim3 g(g1.x, unsigned((ncol + G - 1) / G));
+#define RZ_PG(GG)                                                                                               \
+  hipLaunchKernelGGL((k_patch_apply<MJ, GG>), g, dim3(256), lds_per_g * GG, s, pa.chunk_patch, pa.chunk_rows,  \
+                     pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, pa.inv_off, pa.inv, r, ldr, z, ldz, ncol, \
+                     pa.max_size, st)
+  if (G >= 8) RZ_PG(8);
+  else if (G >= 4) RZ_PG(4);
+  else if (G >= 2) RZ_PG(2);
+  else RZ_PG(1);
+#undef RZ_PG
 }
 
-void launch_patch_apply(const PatchApply &pa, const double *r, double *z, const PcgState *st, hipStream_t s) {
+void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
+                        const PcgState *st, hipStream_t s) {
   if (pa.n_chunks == 0) return;
-  const size_t lds = size_t(6) * pa.max_size * sizeof(double);
+  const size_t lds_per_g = size_t(6) * pa.max_size * sizeof(double);
   const int nj = (pa.max_size + 63) / 64;
-  dim3 g(unsigned(pa.n_chunks)), b(256);
-#define RZ_PATCH(MJ)                                                                                        \
-  hipLaunchKernelGGL(k_patch_apply<MJ>, g, b, lds, s, pa.chunk_patch, pa.chunk_rows, pa.patch_col, pa.col_ent, \
-                     pa.ent_dof, pa.ent_coef, pa.inv_off, pa.inv, r, z, pa.max_size, st)
-  if (nj <= 1) RZ_PATCH(1);
-  else if (nj <= 2) RZ_PATCH(2);
-  else if (nj <= 4) RZ_PATCH(4);
-  else if (nj <= 8) RZ_PATCH(8);
-  else if (nj <= 14) RZ_PATCH(14);
-  else RZ_PATCH(24);
-#undef RZ_PATCH
+  const int mj = nj <= 1 ? 1 : nj <= 2 ? 2 : nj <= 4 ? 4 : nj <= 8 ? 8 : nj <= 14 ? 14 : 24;
+  int G = 8;
+  while (G > 1 && (G > ncol || lds_per_g * G > 96 * 1024 || mj * G > 32)) G /= 2;
+  const dim3 g1(unsigned(pa.n_chunks));
+  switch (mj) {
+    case 1: patch_g<1>(pa, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;
+    case 2: patch_g<2>(pa, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;
+    case 4: patch_g<4>(pa, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;
+    case 8: patch_g<8>(pa, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;
+    case 14: patch_g<14>(pa, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;
+    default: patch_g<24>(pa, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;
+  }
 }
 
-void launch_jacobi(int64_t n_dofs, int64_t off_I, const double *dinv, const double *r, double *z,
-                   const PcgState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_jacobi, dim3(grid_for(n_dofs, 256, 4096)), dim3(256), 0, s, n_dofs, off_I, dinv, r, z, st);
-}
-
-void launch_coarse_apply(const CoarseApply &ca, const double *r, double *z, const PcgState *st, hipStream_t s) {
+void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hipStream_t s) {
+  const unsigned nt = unsigned(int64_t(ca.NT) * (ca.NT + 1) / 2);
   const int npad = ca.NT * 64;
-  hipLaunchKernelGGL(k_coarse_gather, dim3(grid_for(npad, 256)), dim3(256), 0, s, ca.nW, npad, ca.wdofs, r, ca.rW,
-                     ca.zW, st);
-  hipLaunchKernelGGL(k_coarse_tiles, dim3(unsigned(int64_t(ca.NT) * (ca.NT + 1) / 2)), dim3(64), 0, s, ca.NT,
-                     ca.tiles, ca.rW, ca.zW, st);
-  hipLaunchKernelGGL(k_coarse_scatter, dim3(grid_for(ca.nW, 256)), dim3(256), 0, s, ca.nW, ca.wdofs, ca.zW, z, st);
+  int G = 8;
+  while (G > 1 && G > ncol) G /= 2;
+  dim3 g(nt, unsigned((ncol + G - 1) / G));
+#define RZ_CT(GG) hipLaunchKernelGGL(k_coarse_tiles<GG>, g, dim3(64), 0, s, ca.NT, ca.tiles, ca.rW, ca.zW, npad, ncol, st)
+  if (G == 8) RZ_CT(8);
+  else if (G == 4) RZ_CT(4);
+  else if (G == 2) RZ_CT(2);
+  else RZ_CT(1);
+#undef RZ_CT
 }
 
-void launch_dot_partial(int64_t n, const double *a, const double *b, double *part, const PcgState *st,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s, n, a, b, part, st);
-}
-void launch_pcg_init(PcgState *st, const double *part, const double *part2, double tol2, int maxit, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(256), 0, s, st, part, part2, tol2, maxit);
-}
-void launch_set_rz(PcgState *st, const double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_rz, dim3(1), dim3(256), 0, s, st, part);
-}
-void launch_finalize_alpha(PcgState *st, const double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(256), 0, s, st, part);
-}
-void launch_update_xr(int64_t n, double *x, double *r, const double *p, const double *Ap, double *part,
-                      const PcgState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_xr, dim3(kRedBlocks), dim3(256), 0, s, n, x, r, p, Ap, part, st);
-}
-void launch_finalize_rr(PcgState *st, const double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_rr, dim3(1), dim3(256), 0, s, st, part);
-}
-void launch_finalize_beta(PcgState *st, const double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_beta, dim3(1), dim3(256), 0, s, st, part);
-}
-void launch_update_p(int64_t n, double *p, const double *z, const PcgState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_p, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, p, z, st);
-}
-void launch_residual(int64_t n, const double *b, const double *Ax, double *r, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, b, Ax, r);
-}
-void launch_copy(int64_t n, const double *a, double *b, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, a, b);
+void launch_apply_P(const PatchApply *sets, int nsets, const CoarseApply &ca, int64_t n, int64_t off_I,
+                    const double *dinv, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_jacobi_m, dim3(grid_for(n, 256, 2048), ncol), dim3(256), 0, s, n, off_I, dinv, r, ldr, z, ldz);
+  for (int i = 0; i < nsets; ++i) launch_patch_apply(sets[i], r, ldr, z, ldz, ncol, nullptr, s);
+  const int npad = ca.NT * 64;
+  hipLaunchKernelGGL(k_coarse_gather_m, dim3(grid_for(npad, 256), ncol), dim3(256), 0, s, ca.nW, npad, ca.wdofs, r,
+                     ldr, ca.rW, ca.zW);
+  launch_coarse_tiles(ca, ncol, nullptr, s);
+  hipLaunchKernelGGL(k_coarse_scatter_m, dim3(grid_for(ca.nW, 256), ncol), dim3(256), 0, s, ca.nW, npad, ca.wdofs,
+                     ca.zW, z, ldz);
 }
 
-void launch_dot2(int64_t n, const double *a, const double *b, const CoarseFold &cf, double *part,
-                 const PcgState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(256), 0, s, n, a, b, cf, part, st);
+void launch_fill(double *y, int64_t n, int64_t ld, int ncol, const PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_m, dim3(grid_for(n, 256, 2048), ncol), dim3(256), 0, s, y, n, ld, st);
 }
-void launch_update_xr2(int64_t n, double *x, double *r, const double *p, const double *Ap, const double *partZ,
-                       const double *partA, double *partR, PcgState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_xr2, dim3(kRedBlocks), dim3(256), 0, s, n, x, r, p, Ap, partZ, partA, partR, st);
+void launch_copy(int64_t n, const double *a, int64_t lda, double *b, int64_t ldb, int ncol, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_m, dim3(grid_for(n, 256, 2048), ncol), dim3(256), 0, s, n, a, lda, b, ldb);
+}
+void launch_residual(int64_t n, const double *b, int64_t ldb, const double *Ax, double *r, int ncol, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_m, dim3(grid_for(n, 256, 2048), ncol), dim3(256), 0, s, n, b, ldb, Ax, r);
+}
+void launch_dot(int64_t n, const double *a, int64_t lda, const double *b, int64_t ldb, const CoarseFold &cf,
+                int npad, double *part, int RB, int ncol, const PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_m, dim3(RB, ncol), dim3(256), 0, s, n, a, lda, b, ldb, cf, npad, part, RB, st);
+}
+void launch_pcg_start(const double *partB, const double *partR, int RB, double tol2, int maxit, PcgState *st,
+                      int ncol, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_start, dim3(ncol), dim3(256), 0, s, partB, partR, RB, tol2, maxit, st);
+}
+void launch_update_xr(int64_t n, double *x, int64_t ldx, double *r, const double *p, const double *Ap,
+                      const double *partZ, const double *partA, double *partR, int RB, int ncol, PcgState *st,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_update_xr_m, dim3(RB, ncol), dim3(256), 0, s, n, x, ldx, r, p, Ap, partZ, partA, partR, RB,
+                     st);
 }
 void launch_check_jacobi(int64_t n, int64_t off_I, const double *dinv, const double *r, double *z,
-                         const CoarseApply &ca, const double *partR, PcgState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_jacobi, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, off_I, dinv, r, z, ca.nW,
-                     ca.NT * 64, ca.wdofs, ca.rW, ca.zW, partR, st);
+                         const CoarseApply &ca, const double *partR, int RB, int ncol, PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_jacobi_m, dim3(grid_for(n, 256, std::max(1, 2048 / ncol)), ncol), dim3(256), 0, s, n,
+                     off_I, dinv, r, z, ca.nW, ca.NT * 64, ca.wdofs, ca.rW, ca.zW, partR, RB, st);
 }
-void launch_coarse_tiles(const CoarseApply &ca, const PcgState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_tiles, dim3(unsigned(int64_t(ca.NT) * (ca.NT + 1) / 2)), dim3(64), 0, s, ca.NT,
-                     ca.tiles, ca.rW, ca.zW, st);
-}
-void launch_update_p2(int64_t n, double *p, const double *z, const CoarseFold &cf, double *Ap, const double *partZ,
-                      PcgState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_p2, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, p, z, cf, Ap, partZ, st);
+void launch_update_p(int64_t n, double *p, const double *z, const CoarseFold &cf, int npad, double *Ap,
+                     const double *partZ, int RB, int ncol, PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p_m, dim3(grid_for(n, 256, std::max(1, 2048 / ncol)), ncol), dim3(256), 0, s, n, p, z,
+                     cf, npad, Ap, partZ, RB, st);
 }
 
 }  // namespace rz

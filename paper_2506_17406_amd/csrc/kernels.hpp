@@ -32,7 +32,7 @@ void launch_pack_upper(int64_t B, int N, const int32_t *sizes, const int64_t *of
                        double *packed, hipStream_t s);
 void launch_pack_tiles(int N, int n, const double *Ainv, double *tiles, hipStream_t s);
 
-// ---- hot path
+// ---- hot path (multi-column: column c of a vector at base + c * ld)
 struct ApplyATables {
   int n, Q, NP, KP;         // local dofs, stacked matrices, padded rows, padded k
   const double *Afrag;      // fragment-ordered reference stack
@@ -40,9 +40,10 @@ struct ApplyATables {
   const int32_t *cell_dofs; // n_cells x n
   int64_t n_cells;
 };
-void launch_apply_A(const ApplyATables &t, const double *x, double *y, int n_rhs, int64_t ld,
+// y += A x for n_rhs columns (y must be zeroed by the caller); st: per-column
+// state (columns that are done are skipped) or null
+void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
                     const PcgState *st, hipStream_t s);
-void launch_fill(double *y, int64_t n, double v, const PcgState *st, hipStream_t s);
 
 struct PatchApply {
   int64_t n_patches, n_chunks;
@@ -54,17 +55,12 @@ struct PatchApply {
   const double *ent_coef;
   const double *inv;        // packed upper rows per patch
 };
-void launch_patch_apply(const PatchApply &pa, const double *r, double *z, const PcgState *st, hipStream_t s);
-void launch_jacobi(int64_t n_dofs, int64_t off_I, const double *dinv, const double *r, double *z,
-                   const PcgState *st, hipStream_t s);
 struct CoarseApply {
   int nW, NT;               // coarse size, tiles per side
   const int32_t *wdofs;
   const double *tiles;      // upper tiles (I <= J), 64 x 64 each, row-major
-  double *rW, *zW;          // work vectors (NT * 64)
+  double *rW, *zW;          // work vectors (NT * 64 per column)
 };
-void launch_coarse_apply(const CoarseApply &ca, const double *r, double *z, const PcgState *st, hipStream_t s);
-
 // The coarse correction kept in zW and added on the fly to the dofs
 // off + t N (t < span / N): the Whitney dofs are every N-th dof of one
 // entity-dimension block.
@@ -73,31 +69,29 @@ struct CoarseFold {
   int64_t off, span, N;
 };
 
-// ---- Krylov vector kernels
-constexpr int kRedBlocks = 512;
-void launch_dot_partial(int64_t n, const double *a, const double *b, double *part, const PcgState *st,
-                        hipStream_t s);
-void launch_pcg_init(PcgState *st, const double *part, const double *part2, double tol2, int maxit,
-                     hipStream_t s);
-void launch_set_rz(PcgState *st, const double *part, hipStream_t s);
-void launch_finalize_alpha(PcgState *st, const double *part, hipStream_t s);
-void launch_update_xr(int64_t n, double *x, double *r, const double *p, const double *Ap, double *part,
-                      const PcgState *st, hipStream_t s);
-void launch_finalize_rr(PcgState *st, const double *part, hipStream_t s);
-void launch_finalize_beta(PcgState *st, const double *part, hipStream_t s);
-void launch_update_p(int64_t n, double *p, const double *z, const PcgState *st, hipStream_t s);
-void launch_residual(int64_t n, const double *b, const double *Ax, double *r, hipStream_t s);
-void launch_copy(int64_t n, const double *a, double *b, hipStream_t s);
-// fused iteration kernels: a reduction leaves per-block partials, the
-// consuming kernel re-sums them in every block
-void launch_dot2(int64_t n, const double *a, const double *b, const CoarseFold &cf, double *part,
-                 const PcgState *st, hipStream_t s);
-void launch_update_xr2(int64_t n, double *x, double *r, const double *p, const double *Ap, const double *partZ,
-                       const double *partA, double *partR, PcgState *st, hipStream_t s);
+// z += sum_patches (scatter-add; z must hold the Jacobi part already)
+void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
+                        const PcgState *st, hipStream_t s);
+void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hipStream_t s);
+// the whole preconditioner, z = P^{-1} r (no state)
+void launch_apply_P(const PatchApply *sets, int nsets, const CoarseApply &ca, int64_t n, int64_t off_I,
+                    const double *dinv, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
+                    hipStream_t s);
+
+// ---- Krylov (RB block partials per column)
+void launch_fill(double *y, int64_t n, int64_t ld, int ncol, const PcgState *st, hipStream_t s);
+void launch_copy(int64_t n, const double *a, int64_t lda, double *b, int64_t ldb, int ncol, hipStream_t s);
+void launch_residual(int64_t n, const double *b, int64_t ldb, const double *Ax, double *r, int ncol, hipStream_t s);
+void launch_dot(int64_t n, const double *a, int64_t lda, const double *b, int64_t ldb, const CoarseFold &cf,
+                int npad, double *part, int RB, int ncol, const PcgState *st, hipStream_t s);
+void launch_pcg_start(const double *partB, const double *partR, int RB, double tol2, int maxit, PcgState *st,
+                      int ncol, hipStream_t s);
+void launch_update_xr(int64_t n, double *x, int64_t ldx, double *r, const double *p, const double *Ap,
+                      const double *partZ, const double *partA, double *partR, int RB, int ncol, PcgState *st,
+                      hipStream_t s);
 void launch_check_jacobi(int64_t n, int64_t off_I, const double *dinv, const double *r, double *z,
-                         const CoarseApply &ca, const double *partR, PcgState *st, hipStream_t s);
-void launch_coarse_tiles(const CoarseApply &ca, const PcgState *st, hipStream_t s);
-void launch_update_p2(int64_t n, double *p, const double *z, const CoarseFold &cf, double *Ap, const double *partZ,
-                      PcgState *st, hipStream_t s);
+                         const CoarseApply &ca, const double *partR, int RB, int ncol, PcgState *st, hipStream_t s);
+void launch_update_p(int64_t n, double *p, const double *z, const CoarseFold &cf, int npad, double *Ap,
+                     const double *partZ, int RB, int ncol, PcgState *st, hipStream_t s);
 
 }  // namespace rz

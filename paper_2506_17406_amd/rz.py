@@ -53,7 +53,7 @@ def _load():
         "rz_sizes": (ctypes.c_int, [P, pi64, pi64, pi32, pi32]),
         "rz_apply_A": (ctypes.c_int, [P, P, P, i32, i64, P]),
         "rz_apply_P": (ctypes.c_int, [P, P, P, i32, i64, P]),
-        "rz_solve": (ctypes.c_int, [P, P, P, dbl, ctypes.POINTER(RzInfo), P]),
+        "rz_solve": (ctypes.c_int, [P, P, P, i32, i64, dbl, ctypes.POINTER(RzInfo), P]),
         "rz_export_topology": (ctypes.c_int, [P, pi32, pi64, pi64, pi64, pi32]),
         "rz_export_reference": (ctypes.c_int, [P, pdbl]),
         "rz_reference": (ctypes.c_int, [i32, i32, ctypes.c_int, pi32, pi32, pdbl]),
@@ -181,15 +181,20 @@ class Problem:
         return z
 
     def solve(self, b, x, rtol=1e-10, stream=None, check=True):
-        self._cols(b)
-        self._cols(x)
-        info = RzInfo()
-        code = lib.rz_solve(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), rtol,
-                            ctypes.byref(info), _stream(stream))
+        """PCG on A x = b (one column) or A X = B (column-major n_dofs x n_rhs);
+        returns the info dict, or a list of dicts for several columns."""
+        nr, ld = self._cols(b)
+        nr2, ld2 = self._cols(x)
+        if nr != nr2 or ld != ld2:
+            raise ValueError("b and x need the same shape and leading dimension")
+        info = (RzInfo * nr)()
+        code = lib.rz_solve(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), nr, ld, rtol,
+                            info, _stream(stream))
         if check:
             _check(code)
-        return dict(status=info.status, iterations=info.iterations, rel_residual=info.rel_residual,
-                    cond_estimate=info.cond_estimate, solve_ms=info.solve_ms, code=code)
+        out = [dict(status=i.status, iterations=i.iterations, rel_residual=i.rel_residual,
+                    cond_estimate=i.cond_estimate, solve_ms=i.solve_ms, code=code) for i in info]
+        return out[0] if b.dim() == 1 else out
 
     def export_reference(self):
         out = np.empty((self.Q, self.n_loc, self.n_loc))

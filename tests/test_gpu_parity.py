@@ -112,3 +112,28 @@ def test_reference_export_matches_host_build():
     assert np.array_equal(prob.export_reference(), rz.reference(3, 3, "Ned"))
     cd, ptr, dofs = prob.export_topology()
     assert np.array_equal(cd, top.cell_dofs)
+
+
+MULTI = [(3, "CG", 4, 2, 0.1), (3, "Ned", 3, 2, 0.1), (3, "RT", 3, 2, 0.1), (2, "CG", 4, 4, 0.0)]
+
+
+@pytest.mark.parametrize("case", MULTI, ids=ids)
+@pytest.mark.parametrize("nr", [3, 9])
+def test_multi_rhs_apply_P_and_solve(case, nr):
+    """Several right-hand sides at once (column groups of 8, 4, 2, 1 and a
+    ragged last group) give the oracle's per-column results."""
+    top, A, P, prob = setup_case(*case)
+    B = load_vectors(top.n_dofs, 21, n_rhs=nr)
+    Bt = torch.from_numpy(np.ascontiguousarray(B.T)).cuda().T      # column-major view
+    Zt = torch.zeros_like(Bt)
+    prob.apply_P(Bt, Zt)
+    Xt = torch.zeros_like(Bt)
+    infos = prob.solve(Bt, Xt, rtol=1e-12)
+    torch.cuda.synchronize()
+    Z, X = Zt.cpu().numpy(), Xt.cpu().numpy()
+    for j in range(nr):
+        ref = P.apply(B[:, j])
+        assert np.abs(Z[:, j] - ref).max() <= 1e-10 * np.abs(ref).max()
+        xo, io = pcg(lambda v: A @ v, P.apply, B[:, j], rtol=1e-12)
+        assert abs(infos[j]["iterations"] - io["iterations"]) <= 1
+        assert np.linalg.norm(X[:, j] - xo) <= 1e-10 * np.linalg.norm(xo)
