@@ -455,6 +455,14 @@ static void ensure_ws(rz_problem *P, int ncol) {
   P->ca.zW = static_cast<double *>(alloc(sizeof(double) * npad * ncol));
   P->fold.zW = P->ca.zW;
   P->ws_cols = ncol;
+  if (ncol >= 8 && !P->ca.full) {
+    // many columns: the coarse solve becomes a GEMM over a full copy of the inverse
+    const int NT = P->ca.NT;
+    double *full = P->dev<double>(size_t(NT) * NT * 4096);
+    rz::launch_coarse_expand(NT, P->ca.tiles, full, nullptr);
+    HIPCHK(hipDeviceSynchronize());
+    P->ca.full = full;
+  }
 }
 
 int rz_apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream) {

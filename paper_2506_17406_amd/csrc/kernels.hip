@@ -583,6 +583,161 @@ __global__ __launch_bounds__(64) void k_coarse_tiles(int NT, const double *__res
   }
 }
 
+// ---- many columns: the coarse and small-patch solves as FP64 MFMA GEMMs
+// Full coarse inverse in MFMA fragment order, built from the packed upper
+// tiles: index (((I NT + J) 4 + w) 16 + kb) 64 + lane holds
+// A[64 I + 16 w + lane % 16][64 J + 4 kb + lane / 16].
+__global__ void k_coarse_expand(int NT, const double *__restrict__ T, double *__restrict__ F) {
+  const int I = blockIdx.x, J = blockIdx.y;
+  double *out = F + (int64_t(I) * NT + J) * 4096;
+  for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+    const int lane = e & 63, kb = (e >> 6) & 15, w = e >> 10;
+    const int r = 16 * w + (lane & 15), c = 4 * kb + (lane >> 4);
+    double v;
+    if (I <= J) {
+      const int64_t t = int64_t(I) * NT - int64_t(I) * (I - 1) / 2 + (J - I);
+      v = T[t * 4096 + r * 64 + c];
+    } else {
+      const int64_t t = int64_t(J) * NT - int64_t(J) * (J - 1) / 2 + (I - J);
+      v = T[t * 4096 + c * 64 + r];
+    }
+    out[e] = v;
+  }
+}
+
+// zW[64 I : 64 I + 64, 64 cg : 64 cg + 64] += sum_{J in split} A_IJ rW_J.
+// Wave w owns rows 16 w .. 16 w + 15 of the block row; rW_J is staged in LDS
+// (the next one is loaded into registers during the current MFMAs).
+__global__ __launch_bounds__(256) void k_coarse_gemm(int NT, int nsplit, const double *__restrict__ F,
+                                                     const double *__restrict__ rW, double *__restrict__ zW,
+                                                     int npad, int ncol, const PcgState *st) {
+  const int I = blockIdx.x, cg = blockIdx.y, sp = blockIdx.z;
+  const int c0 = cg * 64;
+  if (st) {
+    bool any = false;
+    for (int c = c0; c < min(ncol, c0 + 64); ++c)
+      if (!st[c].done) any = true;
+    if (!any) return;
+  }
+  __shared__ double R[64][65];  // R[k][col]
+  const int J0 = int(int64_t(NT) * sp / nsplit), J1 = int(int64_t(NT) * (sp + 1) / nsplit);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  d4 acc[4];
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = d4{0, 0, 0, 0};
+  // thread t stages 16 entries: column (t / 4), rows 16 (t % 4) .. + 15
+  const int scol = threadIdx.x >> 2, srow = (threadIdx.x & 3) * 16;
+  double stage[16];
+  auto load_R = [&](int J) {
+    const int c = c0 + scol;
+    const double *src = rW + int64_t(c) * npad + int64_t(J) * 64 + srow;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) stage[e] = c < ncol ? src[e] : 0.0;
+  };
+  if (J0 < J1) load_R(J0);
+  for (int J = J0; J < J1; ++J) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) R[srow + e][scol] = stage[e];
+    __syncthreads();
+    if (J + 1 < J1) load_R(J + 1);
+    const double *Af = F + ((int64_t(I) * NT + J) * 4 + wave) * 1024 + lane;
+    double a_cur = Af[0];
+#pragma unroll 4
+    for (int kb = 0; kb < 16; ++kb) {
+      const double a_nxt = kb + 1 < 16 ? Af[(kb + 1) * 64] : 0.0;
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur, R[kb * 4 + lk][nb * 16 + li], acc[nb], 0, 0, 0);
+      a_cur = a_nxt;
+    }
+  }
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int c = c0 + nb * 16 + li;
+    if (c >= ncol) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = I * 64 + wave * 16 + lk + 4 * v;
+      atomicAdd(&zW[int64_t(c) * npad + row], acc[nb][v]);
+    }
+  }
+}
+
+// One patch (m <= 96) and 64 columns per block: the packed inverse unpacked
+// to a full MP x MP matrix in LDS, the gathered right-hand sides MP x 64 in
+// LDS, Z = A R by FP64 MFMA, then the scatter-add.
+constexpr int kSmallPatch = 96;
+__global__ __launch_bounds__(256) void k_patch_gemm(const int64_t *__restrict__ patch_col,
+                                                    const int64_t *__restrict__ col_ent,
+                                                    const int32_t *__restrict__ ent_dof,
+                                                    const double *__restrict__ ent_coef,
+                                                    const int64_t *__restrict__ inv_off,
+                                                    const double *__restrict__ inv, const double *__restrict__ r,
+                                                    int64_t ldr, double *__restrict__ z, int64_t ldz, int ncol,
+                                                    const PcgState *st) {
+  const int64_t p = blockIdx.x;
+  const int c0 = blockIdx.y * 64;
+  if (st) {
+    bool any = false;
+    for (int c = c0; c < min(ncol, c0 + 64); ++c)
+      if (!st[c].done) any = true;
+    if (!any) return;
+  }
+  extern __shared__ double sm[];
+  const int64_t cb = patch_col[p];
+  const int m = int(patch_col[p + 1] - cb);
+  const int MP = (m + 15) & ~15;
+  double *A = sm;              // MP x (MP + 1)
+  double *R = sm + MP * (MP + 1);  // MP x 65 (row k, column c)
+  const double *P = inv + inv_off[p];
+  for (int t = threadIdx.x; t < MP * MP; t += 256) {
+    const int i = t / MP, j = t - i * MP;
+    double v = 0.0;
+    if (i < m && j < m) {
+      const int a = min(i, j), b = max(i, j);
+      v = P[int64_t(a) * m - int64_t(a) * (a - 1) / 2 + (b - a)];
+    }
+    A[i * (MP + 1) + j] = v;
+  }
+  for (int t = threadIdx.x; t < MP * 64; t += 256) {
+    const int c = t / MP, j = t - c * MP;
+    double v = 0.0;
+    if (j < m && c0 + c < ncol) {
+      const double *rc = r + int64_t(c0 + c) * ldr;
+      for (int64_t e = col_ent[cb + j]; e < col_ent[cb + j + 1]; ++e) v += ent_coef[e] * rc[ent_dof[e]];
+    }
+    R[j * 65 + c] = v;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nmb = MP / 16, nkb = MP / 4;
+  for (int mb = wave; mb < nmb; mb += 4) {
+    d4 acc[4];
+    for (int nb = 0; nb < 4; ++nb) acc[nb] = d4{0, 0, 0, 0};
+    for (int kb = 0; kb < nkb; ++kb) {
+      const double a = A[(mb * 16 + li) * (MP + 1) + kb * 4 + lk];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, R[(kb * 4 + lk) * 65 + nb * 16 + li], acc[nb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      const int c = c0 + nb * 16 + li;
+      if (c >= ncol) continue;
+      double *zc = z + int64_t(c) * ldz;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = mb * 16 + lk + 4 * v;
+        if (row < m)
+          for (int64_t e = col_ent[cb + row]; e < col_ent[cb + row + 1]; ++e)
+            atomicAdd(&zc[ent_dof[e]], ent_coef[e] * acc[nb][v]);
+      }
+    }
+  }
+}
+
 // -------------------------------------------------------------- Krylov
 // Multi-column PCG: column c of every vector lives at base + c * ld; each
 // column has its own state st[c] and RB block partials at part[c * RB ...].
@@ -887,6 +1042,19 @@ static void patch_g(const PatchApply &pa, dim3 g1, int G, size_t lds_per_g, cons
 void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
                         const PcgState *st, hipStream_t s) {
   if (pa.n_chunks == 0) return;
+  if (ncol >= 8 && pa.max_size <= kSmallPatch) {
+    const int MP = (pa.max_size + 15) & ~15;
+    const size_t lds = size_t(MP * (MP + 1) + MP * 65) * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void *)k_patch_gemm, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      attr = true;
+    }
+    hipLaunchKernelGGL(k_patch_gemm, dim3(unsigned(pa.n_patches), unsigned((ncol + 63) / 64)), dim3(256), lds, s,
+                       pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, pa.inv_off, pa.inv, r, ldr, z, ldz, ncol,
+                       st);
+    return;
+  }
   const size_t lds_per_g = size_t(6) * pa.max_size * sizeof(double);
   const int nj = (pa.max_size + 63) / 64;
   const int mj = nj <= 1 ? 1 : nj <= 2 ? 2 : nj <= 4 ? 4 : nj <= 8 ? 8 : nj <= 14 ? 14 : 24;
@@ -906,6 +1074,14 @@ void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, doub
 void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hipStream_t s) {
   const unsigned nt = unsigned(int64_t(ca.NT) * (ca.NT + 1) / 2);
   const int npad = ca.NT * 64;
+  if (ncol >= 8 && ca.full) {
+    // split the block-row sum so that there are >= ~1024 blocks
+    const int cgs = (ncol + 63) / 64;
+    int nsplit = std::max(1, std::min(ca.NT, 1024 / std::max(1, ca.NT * cgs)));
+    hipLaunchKernelGGL(k_coarse_gemm, dim3(ca.NT, cgs, nsplit), dim3(256), 0, s, ca.NT, nsplit, ca.full, ca.rW,
+                       ca.zW, npad, ncol, st);
+    return;
+  }
   int G = 8;
   while (G > 1 && G > ncol) G /= 2;
   dim3 g(nt, unsigned((ncol + G - 1) / G));
@@ -962,6 +1138,10 @@ void launch_update_p(int64_t n, double *p, const double *z, const CoarseFold &cf
                      const double *partZ, int RB, int ncol, PcgState *st, hipStream_t s) {
   hipLaunchKernelGGL(k_update_p_m, dim3(grid_for(n, 256, std::max(1, 2048 / ncol)), ncol), dim3(256), 0, s, n, p, z,
                      cf, npad, Ap, partZ, RB, st);
+}
+
+void launch_coarse_expand(int NT, const double *tiles, double *full, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_expand, dim3(NT, NT), dim3(256), 0, s, NT, tiles, full);
 }
 
 }  // namespace rz

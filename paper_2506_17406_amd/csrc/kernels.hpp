@@ -60,7 +60,10 @@ struct CoarseApply {
   const int32_t *wdofs;
   const double *tiles;      // upper tiles (I <= J), 64 x 64 each, row-major
   double *rW, *zW;          // work vectors (NT * 64 per column)
+  const double *full;       // all NT x NT tiles in MFMA fragment order (many-column solves), or null
 };
+// builds CoarseApply::full from the packed upper tiles
+void launch_coarse_expand(int NT, const double *tiles, double *full, hipStream_t s);
 // The coarse correction kept in zW and added on the fly to the dofs
 // off + t N (t < span / N): the Whitney dofs are every N-th dof of one
 // entity-dimension block.
