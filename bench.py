@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
+PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0
 
 
@@ -38,9 +39,11 @@ def parse():
     ap.add_argument("--spaces", type=str, default="CG,Ned,RT")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=20)
-    ap.add_argument("--workload", choices=["sweep", "multirhs"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "multirhs", "mixed"], default="sweep",
                     help="sweep: the 3D FP64 sweep (default, the headline line); multirhs: H(div) RT_5 on the "
-                         "12^3x6 mesh with 64 right-hand sides, one batched solve vs 64 single solves")
+                         "12^3x6 mesh with 64 right-hand sides, one batched solve vs 64 single solves; mixed: "
+                         "H(curl) Ned_6 on the 16^3x6 mesh, FP32 refinement vs plain FP64 PCG")
+    ap.add_argument("--inner-rtol", type=float, default=0.0)
     ap.add_argument("--nrhs", type=int, default=64)
     return ap.parse_args()
 
@@ -100,6 +103,98 @@ def multirhs(args):
     print(json.dumps(line), flush=True)
 
 
+def _apply_time(fn, x, y, reps, stream):
+    import torch
+    for _ in range(3):
+        fn(x, y)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        fn(x, y)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / 1e3 / reps
+
+
+def mixed(args):
+    """H(curl) Ned_6 on the jittered 16^3x6 = 24576-tet mesh (mesh seed 4),
+    one uniform[-1,1] load vector (seed 5), solved to a true FP64 relative
+    residual of 1e-10 by FP32 iterative refinement, against plain FP64 PCG
+    on the same GPU."""
+    import torch
+    from paper_2506_17406_amd import rz
+    from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    X, C = kuhn_mesh(16, 3, jitter=0.1, seed=4)
+    t0 = time.perf_counter()
+    pm = rz.Problem(X, C, 6, "Ned", precision="fp32-ir", inner_rtol=args.inner_rtol)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    print(f"setup Ned6 n=16 (FP64 + FP32 copies): {pm.n_dofs} dofs in {t_setup:.1f}s", file=sys.stderr, flush=True)
+    p64 = rz.Problem(X, C, 6, "Ned")
+    torch.cuda.synchronize()
+    print("setup FP64 handle done", file=sys.stderr, flush=True)
+    b = torch.from_numpy(load_vectors(pm.n_dofs, 5)[:, 0]).cuda()
+    xm, x64 = torch.zeros_like(b), torch.zeros_like(b)
+
+    def timed(prob, x):
+        for _ in range(args.warmup):
+            x.zero_()
+            prob.solve(b, x, rtol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x.zero_()
+            info = prob.solve(b, x, rtol=1e-10)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, info
+
+    dt_m, info_m = timed(pm, xm)
+    print(f"FP32-IR: {dt_m * 1e3:.1f} ms, {info_m['iterations']} its, {info_m['outer_iterations']} outer",
+          file=sys.stderr, flush=True)
+    dt_64, info_64 = timed(p64, x64)
+    print(f"FP64: {dt_64 * 1e3:.1f} ms, {info_64['iterations']} its", file=sys.stderr, flush=True)
+    # true FP64 residuals and the distance between the two solutions
+    r = torch.empty_like(b)
+    nb = b.norm().item()
+    p64.apply_A(x64, r)
+    res64 = (b - r).norm().item() / nb
+    p64.apply_A(xm, r)
+    res_m = (b - r).norm().item() / nb
+    diff = (xm - x64).norm().item() / x64.norm().item()
+    # dominant kernels: the FP32 and FP64 operator applies, the two preconditioner applies
+    xa = torch.rand(pm.n_dofs, dtype=torch.float64, device="cuda")
+    ya = torch.empty_like(xa)
+    reps = args.apply_reps
+    t_a32 = _apply_time(lambda u, v: pm.apply_A(u, v, fp32=True), xa, ya, reps, stream)
+    t_a64 = _apply_time(pm.apply_A, xa, ya, reps, stream)
+    t_p32 = _apply_time(lambda u, v: pm.apply_P(u, v, fp32=True), xa, ya, reps, stream)
+    t_p64 = _apply_time(pm.apply_P, xa, ya, reps, stream)
+    flops = 2.0 * pm.Q * pm.n_loc ** 2 * pm.n_cells
+    tf32 = flops / t_a32 / 1e12
+    line = {
+        "metric": "Riesz-map solve DOFs/s to rel. residual 1e-10 (mixed precision)",
+        "value": pm.n_dofs / dt_m, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt_m * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 applies, f64 refinement", "data": "synthetic",
+        "config": {"workload": "H(curl) Ned_6 Riesz map, jittered Kuhn 16^3x6 = 24576 tets, FP32 iterative "
+                               "refinement to true FP64 rel. residual 1e-10", "dofs": pm.n_dofs,
+                   "setup_s": round(t_setup, 2)},
+        "roofline": {"kernel": "apply_A FP32 (Ned6)", "bound": "mfma", "achieved": tf32, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tf32 / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flops_per_launch": flops, "launch_us": t_a32 * 1e6},
+        "iterations": info_m["iterations"], "outer_iterations": info_m["outer_iterations"],
+        "true_rel_residual": res_m,
+        "rel_diff_vs_fp64_solution": diff,
+        "fp64": {"value": pm.n_dofs / dt_64, "ms": dt_64 * 1e3, "iterations": info_64["iterations"],
+                 "true_rel_residual": res64},
+        "speedup_vs_fp64": dt_64 / dt_m,
+        "apply_us": {"A_fp32": t_a32 * 1e6, "A_fp64": t_a64 * 1e6, "P_fp32": t_p32 * 1e6, "P_fp64": t_p64 * 1e6},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline():
     """The oracle, as it stands, on a bounded sample of the workload: the
     H(grad) p=4 and H(curl) p=3 problems of the sweep (same mesh and load
@@ -138,6 +233,8 @@ def main():
         sys.exit(2)
     if args.workload == "multirhs":
         return multirhs(args)
+    if args.workload == "mixed":
+        return mixed(args)
     import torch
     from paper_2506_17406_amd import rz
     from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors

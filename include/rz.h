@@ -70,25 +70,42 @@ typedef struct {
   const int64_t *cells;   /* host, n_cells x (dim+1) vertex numbers, any order */
 } rz_mesh;
 
+/* Arithmetic of rz_solve.  RZ_FP64: PCG entirely in FP64.  RZ_FP32_IR:
+ * iterative refinement -- the residual b - A x and the update x += d are
+ * FP64; each correction d solves A d = r by PCG to inner_rtol whose operator
+ * and preconditioner applies read FP32 copies of the reference tables,
+ * weights, patch inverses and coarse inverse (FP32 MFMA, FP32 accumulation
+ * inside a cell, FP64 scatter and FP64 Krylov vectors and inner products).
+ * The copies are rounded from the FP64 factors built at setup.  If an outer
+ * step contracts the true residual by less than a factor 2 the remaining
+ * corrections use the FP64 applies. */
+typedef enum { RZ_FP64 = 0, RZ_FP32_IR = 1 } rz_precision;
+
 typedef struct {
   double alpha;           /* coefficient of (d u, d v), >= 0 */
   double beta;            /* coefficient of (u, v), > 0 */
-  int32_t max_iter;       /* PCG iteration cap (<= 0: 1000) */
+  int32_t max_iter;       /* PCG iteration cap, per inner solve under refinement (<= 0: 1000) */
+  int32_t precision;      /* rz_precision */
+  double inner_rtol;      /* refinement: relative residual of each correction solve (<= 0: 1e-4) */
 } rz_options;
 
 typedef struct {
   int32_t status;         /* RZ_OK / RZ_ERR_NO_CONVERGENCE / RZ_ERR_BREAKDOWN */
-  int32_t iterations;     /* PCG iterations taken */
-  double rel_residual;    /* ||r_k||_2 / ||b||_2 of the recursively updated residual */
-  double cond_estimate;   /* Lanczos estimate of kappa(P^{-1} A) from the CG coefficients */
+  int32_t iterations;     /* PCG iterations taken (summed over the correction solves) */
+  double rel_residual;    /* FP64: ||r_k||_2 / ||b||_2 of the recursively updated residual;
+                             refinement: ||b - A x||_2 / ||b||_2 with the FP64 operator */
+  double cond_estimate;   /* Lanczos estimate of kappa(P^{-1} A) from the CG coefficients
+                             (of the first correction solve under refinement) */
   double solve_ms;        /* wall time of the iteration loop */
+  int32_t outer_iterations; /* refinement steps (0 for RZ_FP64) */
 } rz_info;
 
 typedef struct rz_problem rz_problem;
 
 /* Builds the reference element (Sec. 3-4) on the host, the numbering and the
  * patches (Sec. 6), uploads them, and assembles and factors the patch and
- * coarse matrices on the device in FP64.  opts may be NULL (alpha = beta = 1).
+ * coarse matrices on the device in FP64 (plus their FP32 copies when
+ * opts->precision is RZ_FP32_IR).  opts may be NULL (alpha = beta = 1, FP64).
  * On success *out receives a new handle. */
 int rz_setup(const rz_mesh *mesh, int32_t degree, rz_space space, const rz_options *opts,
              void *hip_stream, rz_problem **out);
@@ -107,9 +124,20 @@ int rz_apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t
  * r, z: device, n_dofs x n_rhs, leading dimension ld; z is overwritten. */
 int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream);
 
+/* The FP32-copy applies that the RZ_FP32_IR correction solves use, with the
+ * rz_apply_A / rz_apply_P argument conventions (FP64 vectors in and out):
+ * the reference tables, weights and x are rounded to FP32 and contracted by
+ * FP32 MFMA, cell results are scatter-added in FP64; the preconditioner
+ * reads FP32 patch and coarse inverses and accumulates in FP64.  RZ_ERR_ARG
+ * for a handle set up without RZ_FP32_IR. */
+int rz_apply_A_fp32(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream);
+int rz_apply_P_fp32(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream);
+
 /* PCG on A X = B for n_rhs independent columns (each with its own CG
  * scalars and stopping test), from the initial guess in X, stopping column j
- * when its recursive residual satisfies ||r_j||_2 <= rtol ||b_j||_2.
+ * when its recursive residual satisfies ||r_j||_2 <= rtol ||b_j||_2 (under
+ * RZ_FP32_IR: when its true FP64 residual does, checked after each
+ * refinement step; a column with b_j = 0 is left unchanged).
  * B, X: device, n_dofs x n_rhs, leading dimension ld.  The columns share
  * every operator and preconditioner pass (the patch and coarse inverses are
  * streamed once for a group of columns).  info (host, n_rhs entries, may be

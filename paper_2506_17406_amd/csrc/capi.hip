@@ -41,7 +41,7 @@ struct RzError {
 
 struct DevPatchSet {
   rz::PatchApply pa{};
-  std::vector<void *> owned;
+  int64_t n_inv = 0;  // packed inverse entries
 };
 
 }  // namespace
@@ -54,6 +54,8 @@ struct rz_problem {
   std::vector<rz::PatchSet> patches;
   int64_t off_I = 0;
   int max_iter = 1000;
+  int precision = RZ_FP64;
+  double inner_rtol = 1e-4;
   // device data
   std::vector<void *> mem;
   double *R = nullptr, *Afrag = nullptr, *w = nullptr, *dinv = nullptr;
@@ -68,6 +70,9 @@ struct rz_problem {
   rz::PcgState *st_host = nullptr;
   double *r = nullptr, *z = nullptr, *pv = nullptr, *Ap = nullptr;
   double *partA = nullptr, *partR = nullptr, *partZ = nullptr, *partB = nullptr;  // block partials
+  // refinement: outer state (true residual), outer residual and correction
+  rz::PcgState *sto = nullptr, *sto_host = nullptr;
+  double *ro = nullptr, *dx = nullptr;
   rz::CoarseFold fold{};
   std::vector<rz::PatchApply> pas;  // patch sets for the launchers
 
@@ -91,7 +96,10 @@ struct rz_problem {
     for (void *ptr : ws) (void)hipFree(ptr);
     ws.clear();
     if (st_host) (void)hipHostFree(st_host);
-    st_host = nullptr;
+    if (sto_host) (void)hipHostFree(sto_host);
+    st_host = sto_host = nullptr;
+    sto = nullptr;
+    ro = dx = nullptr;
     ws_cols = 0;
   }
   ~rz_problem() {
@@ -238,6 +246,7 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
   out.pa.ent_dof = P.upload(ps.ent_dof, s);
   out.pa.ent_coef = P.upload(ps.ent_coef, s);
   out.pa.inv = inv;
+  out.n_inv = tot;
 }
 
 void setup_coarse(rz_problem &P, hipStream_t s) {
@@ -352,6 +361,12 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
   P->d = m->dim;
   P->p = degree;
   if (opts && opts->max_iter > 0) P->max_iter = std::min<int>(opts->max_iter, rz::kMaxIter);
+  if (opts) {
+    if (opts->precision != RZ_FP64 && opts->precision != RZ_FP32_IR) return fail(RZ_ERR_ARG, "unknown precision");
+    if (!(opts->inner_rtol < 1.0)) return fail(RZ_ERR_ARG, "inner_rtol must be below 1");
+    P->precision = opts->precision;
+    if (opts->inner_rtol > 0.0) P->inner_rtol = opts->inner_rtol;
+  }
   P->fam = space == RZ_HGRAD ? rz::FAM_CG : (space == RZ_HCURL ? rz::FAM_NED : rz::FAM_RT);
   try {
     P->el = rz::build_reference(P->d, P->fam, degree);
@@ -397,6 +412,19 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     P->dps.resize(P->patches.size());
     for (size_t i = 0; i < P->patches.size(); ++i) setup_patch_set(*P, P->patches[i], P->dps[i], s);
     setup_coarse(*P, s);
+    if (P->precision == RZ_FP32_IR) {
+      // FP32 copies of everything the correction solves read
+      auto lo = [&](const double *a, int64_t count) {
+        float *b = P->dev<float>(size_t(count));
+        rz::launch_to_float(count, a, b, s);
+        return static_cast<const float *>(b);
+      };
+      P->at.Afrag32 = lo(P->Afrag, int64_t(P->at.NP) * P->at.KP * Q);
+      P->at.w32 = lo(P->w, nc * Q);
+      for (auto &d : P->dps) d.pa.inv32 = lo(d.pa.inv, d.n_inv);
+      P->ca.tiles32 = lo(P->ca.tiles, int64_t(P->ca.NT) * (P->ca.NT + 1) / 2 * 4096);
+      HIPCHK(hipGetLastError());
+    }
     for (auto &d : P->dps) P->pas.push_back(d.pa);
     P->fold.off = P->top.offset[P->k];
     P->fold.N = P->el.per_entity[P->k];
@@ -454,6 +482,12 @@ static void ensure_ws(rz_problem *P, int ncol) {
   P->ca.rW = static_cast<double *>(alloc(sizeof(double) * npad * ncol));
   P->ca.zW = static_cast<double *>(alloc(sizeof(double) * npad * ncol));
   P->fold.zW = P->ca.zW;
+  if (P->precision != RZ_FP64) {
+    P->sto = static_cast<rz::PcgState *>(alloc(sizeof(rz::PcgState) * ncol));
+    HIPCHK(hipHostMalloc((void **)&P->sto_host, sizeof(rz::PcgState) * ncol, hipHostMallocDefault));
+    P->ro = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
+    P->dx = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
+  }
   P->ws_cols = ncol;
   if (ncol >= 8 && !P->ca.full) {
     // many columns: the coarse solve becomes a GEMM over a full copy of the inverse
@@ -465,20 +499,24 @@ static void ensure_ws(rz_problem *P, int ncol) {
   }
 }
 
-int rz_apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream) {
+static int apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream,
+                   bool lo) {
   if (!P || !x || !y) return fail(RZ_ERR_ARG, "null argument");
   if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
+  if (lo && !P->at.Afrag32) return fail(RZ_ERR_ARG, "FP32 copies exist only for handles set up with RZ_FP32_IR");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   rz::launch_fill(y, P->top.n_dofs, ld, n_rhs, nullptr, s);
-  rz::launch_apply_A(P->at, x, ld, y, ld, n_rhs, nullptr, s);
+  rz::launch_apply_A(P->at, x, ld, y, ld, n_rhs, nullptr, s, lo);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RZ_ERR_DEVICE, hipGetErrorString(e));
   return RZ_OK;
 }
 
-int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream) {
+static int apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream,
+                   bool lo) {
   if (!P || !r || !z) return fail(RZ_ERR_ARG, "null argument");
   if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
+  if (lo && !P->at.Afrag32) return fail(RZ_ERR_ARG, "FP32 copies exist only for handles set up with RZ_FP32_IR");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   try {
     ensure_ws(P, n_rhs);
@@ -486,10 +524,157 @@ int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t
     return fail(e.code, e.msg);
   }
   rz::launch_apply_P(P->pas.data(), int(P->pas.size()), P->ca, P->top.n_dofs, P->off_I, P->dinv, r, ld, z, ld, n_rhs,
-                     s);
+                     s, lo);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RZ_ERR_DEVICE, hipGetErrorString(e));
   return RZ_OK;
+}
+
+int rz_apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream) {
+  return apply_A(P, x, y, n_rhs, ld, hip_stream, false);
+}
+int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream) {
+  return apply_P(P, r, z, n_rhs, ld, hip_stream, false);
+}
+int rz_apply_A_fp32(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream) {
+  return apply_A(P, x, y, n_rhs, ld, hip_stream, true);
+}
+int rz_apply_P_fp32(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream) {
+  return apply_P(P, r, z, n_rhs, ld, hip_stream, true);
+}
+
+// Lanczos estimate of kappa(P^{-1} A) from the CG coefficients (Sec. 7.1 reports these)
+static double lanczos_cond(const rz::PcgState &h) {
+  const int kk = std::min(h.iter, rz::kMaxIter);
+  if (kk <= 0) return 1.0;
+  rz::Dense T(kk, kk);
+  for (int j = 0; j < kk; ++j) {
+    T(j, j) = 1.0 / h.alphas[j] + (j > 0 ? h.betas[j - 1] / h.alphas[j - 1] : 0.0);
+    if (j > 0) T(j, j - 1) = T(j - 1, j) = std::sqrt(std::max(0.0, h.betas[j - 1])) / h.alphas[j - 1];
+  }
+  std::vector<double> ev;
+  rz::Dense V;
+  rz::sym_eig(T, ev, V);
+  return ev.front() > 0 ? ev.back() / ev.front() : 1.0;
+}
+
+// PCG (Sec. 7.1) on A x = b over nc columns to ||r_j|| <= tol ||b_j||, from x
+// (or from zero when x_zero).  lo: FP32 operator and preconditioner copies.
+// outer (or null): columns whose outer state is done are skipped.  On return
+// st_host holds every column's final state.
+static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int64_t ldx, int nc, double tol, bool lo,
+                    bool x_zero, const rz::PcgState *outer, hipStream_t s) {
+  const int64_t nd = P->top.n_dofs;
+  const int maxit = P->max_iter;
+  const int RB = reduction_blocks(nc);
+  const int npad = P->ca.NT * 64;
+  const rz::CoarseFold nofold{nullptr, 0, 0, 1};
+  if (x_zero) {
+    // r = b, ||r|| = ||b||
+    rz::launch_fill(x, nd, ldx, nc, nullptr, s);
+    rz::launch_copy(nd, b, ldb, P->r, nd, nc, s);
+    rz::launch_dot(nd, b, ldb, b, ldb, nofold, npad, P->partB, RB, nc, nullptr, s);
+    rz::launch_pcg_start(P->partB, P->partB, RB, tol * tol, maxit, P->st, nc, s, outer);
+  } else {
+    // r = b - A x, convergence reference ||b||
+    rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
+    rz::launch_apply_A(P->at, x, ldx, P->Ap, nd, nc, nullptr, s, lo);
+    rz::launch_residual(nd, b, ldb, P->Ap, P->r, nc, s);
+    rz::launch_dot(nd, b, ldb, b, ldb, nofold, npad, P->partB, RB, nc, nullptr, s);
+    rz::launch_dot(nd, P->r, nd, P->r, nd, nofold, npad, P->partR, RB, nc, nullptr, s);
+    rz::launch_pcg_start(P->partB, P->partR, RB, tol * tol, maxit, P->st, nc, s, outer);
+  }
+  // z = P^{-1} r, (r, z), p = z, Ap = 0
+  rz::launch_apply_P(P->pas.data(), int(P->pas.size()), P->ca, nd, P->off_I, P->dinv, P->r, nd, P->z, nd, nc, s, lo);
+  rz::launch_dot(nd, P->r, nd, P->z, nd, nofold, npad, P->partZ, RB, nc, P->st, s);
+  rz::launch_copy(nd, P->z, nd, P->pv, nd, nc, s);
+  rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
+  HIPCHK(hipGetLastError());
+  const int chunk = 8;
+  const size_t head = offsetof(rz::PcgState, alphas);
+  for (int it0 = 0; it0 < maxit; it0 += chunk) {
+    for (int it = 0; it < chunk; ++it) {
+      // Ap was cleared by the previous p update; partZ holds the partials of (r, z)
+      rz::launch_apply_A(P->at, P->pv, nd, P->Ap, nd, nc, P->st, s, lo);
+      rz::launch_dot(nd, P->pv, nd, P->Ap, nd, nofold, npad, P->partA, RB, nc, P->st, s);
+      rz::launch_update_xr(nd, x, ldx, P->r, P->pv, P->Ap, P->partZ, P->partA, P->partR, RB, nc, P->st, s);
+      // convergence test, then z = P^{-1} r with the coarse part left in zW
+      rz::launch_check_jacobi(nd, P->off_I, P->dinv, P->r, P->z, P->ca, P->partR, RB, nc, P->st, s);
+      for (auto &pa : P->pas) rz::launch_patch_apply(pa, P->r, nd, P->z, nd, nc, P->st, s, lo);
+      rz::launch_coarse_tiles(P->ca, nc, P->st, s, lo);
+      rz::launch_dot(nd, P->r, nd, P->z, nd, P->fold, npad, P->partZ, RB, nc, P->st, s);
+      rz::launch_update_p(nd, P->pv, P->z, P->fold, npad, P->Ap, P->partZ, RB, nc, P->st, s);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy2DAsync(P->st_host, sizeof(rz::PcgState), P->st, sizeof(rz::PcgState), head, nc,
+                            hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bool all = true;
+    for (int c = 0; c < nc; ++c) all = all && P->st_host[c].done;
+    if (all) break;
+  }
+  HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(rz::PcgState) * nc, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// Iterative refinement: r = b - A x in FP64, d from PCG on A d = r with the
+// FP32 applies to inner_rtol, x += d, until ||b - A x|| <= rtol ||b|| per
+// column.  A step that fails to halve the largest outer residual switches
+// the remaining corrections to the FP64 applies.
+static void refine(rz_problem *P, const double *b, double *x, int64_t ld, int nc, double rtol, std::vector<int> &its,
+                   std::vector<int> &outer, std::vector<double> &cond, std::vector<double> &rel,
+                   std::vector<int> &code, hipStream_t s) {
+  const int64_t nd = P->top.n_dofs;
+  const int RB = reduction_blocks(nc);
+  const int npad = P->ca.NT * 64;
+  const rz::CoarseFold nofold{nullptr, 0, 0, 1};
+  const size_t head = offsetof(rz::PcgState, alphas);
+  const int max_outer = 40;
+  bool lo = true;
+  std::vector<double> prev(nc, 0.0);
+  for (int k = 0;; ++k) {
+    // true residual and the outer convergence test
+    rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
+    rz::launch_apply_A(P->at, x, ld, P->Ap, nd, nc, nullptr, s, false);
+    rz::launch_residual(nd, b, ld, P->Ap, P->ro, nc, s);
+    rz::launch_dot(nd, b, ld, b, ld, nofold, npad, P->partB, RB, nc, nullptr, s);
+    rz::launch_dot(nd, P->ro, nd, P->ro, nd, nofold, npad, P->partR, RB, nc, nullptr, s);
+    rz::launch_pcg_start(P->partB, P->partR, RB, rtol * rtol, P->max_iter, P->sto, nc, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy2DAsync(P->sto_host, sizeof(rz::PcgState), P->sto, sizeof(rz::PcgState), head, nc,
+                            hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bool all = true;
+    double worst_ratio = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      const rz::PcgState &h = P->sto_host[c];
+      rel[c] = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+      all = all && h.done;
+      if (k > 0 && !h.done && prev[c] > 0) worst_ratio = std::max(worst_ratio, rel[c] / prev[c]);
+      prev[c] = rel[c];
+    }
+    if (all || k == max_outer) break;
+    if (worst_ratio > 0.5) lo = false;
+    // correction solve from zero on the columns that are not yet converged
+    pcg_run(P, P->ro, nd, P->dx, nd, nc, P->inner_rtol, lo, true, P->sto, s);
+    bool broke = false;
+    for (int c = 0; c < nc; ++c) {
+      if (P->sto_host[c].done) continue;
+      const rz::PcgState &h = P->st_host[c];
+      its[c] += h.iter;
+      outer[c] += 1;
+      if (outer[c] == 1) cond[c] = lanczos_cond(h);
+      if (h.status == rz::PCG_BREAKDOWN) {
+        if (!lo) code[c] = RZ_ERR_BREAKDOWN;
+        broke = true;
+      }
+    }
+    if (broke && !lo) break;
+    if (broke) lo = false;
+    rz::launch_axpy(nd, P->dx, x, ld, nc, s);
+  }
+  for (int c = 0; c < nc; ++c)
+    if (code[c] == RZ_OK && !P->sto_host[c].done) code[c] = RZ_ERR_NO_CONVERGENCE;
 }
 
 int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t ld, double rtol, rz_info *info,
@@ -498,81 +683,37 @@ int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t l
   if (!(rtol > 0.0)) return fail(RZ_ERR_ARG, "rtol must be positive");
   if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  const int64_t nd = P->top.n_dofs;
-  const int maxit = P->max_iter;
   const int nc = n_rhs;
   try {
     ensure_ws(P, nc);
-    const int RB = reduction_blocks(nc);
-    const int npad = P->ca.NT * 64;
-    const rz::CoarseFold nofold{nullptr, 0, 0, 1};
+    std::vector<int> its(nc, 0), outer(nc, 0);
+    std::vector<double> cond(nc, 1.0), rel(nc, 0.0);
+    std::vector<int> code(nc, RZ_OK);
     auto t0 = std::chrono::steady_clock::now();
-    // r = b - A x, convergence reference ||b||
-    rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
-    rz::launch_apply_A(P->at, x, ld, P->Ap, nd, nc, nullptr, s);
-    rz::launch_residual(nd, b, ld, P->Ap, P->r, nc, s);
-    rz::launch_dot(nd, b, ld, b, ld, nofold, npad, P->partB, RB, nc, nullptr, s);
-    rz::launch_dot(nd, P->r, nd, P->r, nd, nofold, npad, P->partR, RB, nc, nullptr, s);
-    rz::launch_pcg_start(P->partB, P->partR, RB, rtol * rtol, maxit, P->st, nc, s);
-    // z = P^{-1} r, (r, z), p = z, Ap = 0
-    rz::launch_apply_P(P->pas.data(), int(P->pas.size()), P->ca, nd, P->off_I, P->dinv, P->r, nd, P->z, nd, nc, s);
-    rz::launch_dot(nd, P->r, nd, P->z, nd, nofold, npad, P->partZ, RB, nc, P->st, s);
-    rz::launch_copy(nd, P->z, nd, P->pv, nd, nc, s);
-    rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
-    HIPCHK(hipGetLastError());
-    const int chunk = 8;
-    const size_t head = offsetof(rz::PcgState, alphas);
-    for (int it0 = 0; it0 < maxit; it0 += chunk) {
-      for (int it = 0; it < chunk; ++it) {
-        // Ap was cleared by the previous p update; partZ holds the partials of (r, z)
-        rz::launch_apply_A(P->at, P->pv, nd, P->Ap, nd, nc, P->st, s);
-        rz::launch_dot(nd, P->pv, nd, P->Ap, nd, nofold, npad, P->partA, RB, nc, P->st, s);
-        rz::launch_update_xr(nd, x, ld, P->r, P->pv, P->Ap, P->partZ, P->partA, P->partR, RB, nc, P->st, s);
-        // convergence test, then z = P^{-1} r with the coarse part left in zW
-        rz::launch_check_jacobi(nd, P->off_I, P->dinv, P->r, P->z, P->ca, P->partR, RB, nc, P->st, s);
-        for (auto &pa : P->pas) rz::launch_patch_apply(pa, P->r, nd, P->z, nd, nc, P->st, s);
-        rz::launch_coarse_tiles(P->ca, nc, P->st, s);
-        rz::launch_dot(nd, P->r, nd, P->z, nd, P->fold, npad, P->partZ, RB, nc, P->st, s);
-        rz::launch_update_p(nd, P->pv, P->z, P->fold, npad, P->Ap, P->partZ, RB, nc, P->st, s);
+    if (P->precision == RZ_FP64) {
+      pcg_run(P, b, ld, x, ld, nc, rtol, false, false, nullptr, s);
+      for (int c = 0; c < nc; ++c) {
+        const rz::PcgState &h = P->st_host[c];
+        its[c] = h.iter;
+        cond[c] = lanczos_cond(h);
+        rel[c] = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+        if (h.status == rz::PCG_MAXIT || !h.done) code[c] = RZ_ERR_NO_CONVERGENCE;
+        if (h.status == rz::PCG_BREAKDOWN) code[c] = RZ_ERR_BREAKDOWN;
       }
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpy2DAsync(P->st_host, sizeof(rz::PcgState), P->st, sizeof(rz::PcgState), head, nc,
-                              hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      bool all = true;
-      for (int c = 0; c < nc; ++c) all = all && P->st_host[c].done;
-      if (all) break;
+    } else {
+      refine(P, b, x, ld, nc, rtol, its, outer, cond, rel, code, s);
     }
-    HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(rz::PcgState) * nc, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
     int worst = RZ_OK;
     for (int c = 0; c < nc; ++c) {
-      const rz::PcgState &h = P->st_host[c];
-      // Lanczos condition estimate from the CG coefficients
-      double cond = 1.0;
-      const int kk = std::min(h.iter, rz::kMaxIter);
-      if (kk > 0) {
-        rz::Dense T(kk, kk);
-        for (int j = 0; j < kk; ++j) {
-          T(j, j) = 1.0 / h.alphas[j] + (j > 0 ? h.betas[j - 1] / h.alphas[j - 1] : 0.0);
-          if (j > 0) T(j, j - 1) = T(j - 1, j) = std::sqrt(std::max(0.0, h.betas[j - 1])) / h.alphas[j - 1];
-        }
-        std::vector<double> ev;
-        rz::Dense V;
-        rz::sym_eig(T, ev, V);
-        if (ev.front() > 0) cond = ev.back() / ev.front();
-      }
-      int code = RZ_OK;
-      if (h.status == rz::PCG_MAXIT || !h.done) code = RZ_ERR_NO_CONVERGENCE;
-      if (h.status == rz::PCG_BREAKDOWN) code = RZ_ERR_BREAKDOWN;
-      if (code != RZ_OK && worst == RZ_OK) worst = code;
+      if (code[c] != RZ_OK && worst == RZ_OK) worst = code[c];
       if (info) {
-        info[c].status = code;
-        info[c].iterations = h.iter;
-        info[c].rel_residual = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
-        info[c].cond_estimate = cond;
+        info[c].status = code[c];
+        info[c].iterations = its[c];
+        info[c].rel_residual = rel[c];
+        info[c].cond_estimate = cond[c];
         info[c].solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        info[c].outer_iterations = outer[c];
       }
     }
     if (worst != RZ_OK) return fail(worst, worst == RZ_ERR_BREAKDOWN ? "CG breakdown" : "no convergence");

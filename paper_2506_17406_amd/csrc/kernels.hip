@@ -437,6 +437,93 @@ __global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int64_t
 }
 
 
+// FP32 operator apply (the inner operator of mixed-precision refinement):
+// the same wave decomposition as k_apply_A with FP32 tables, weights and
+// MFMA (FP32 accumulation); y stays FP64.
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <int Q, int NB>
+__global__ __launch_bounds__(256) void k_apply_A32(int n, int NMB, int KB, int64_t nc, const float *__restrict__ Af,
+                                                   const float *__restrict__ w, const int32_t *__restrict__ cd,
+                                                   const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
+                                                   int64_t ldy, const PcgState *st) {
+  if (st && st[blockIdx.z].done) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mb = blockIdx.y * 4 + wave;
+  if (mb >= NMB) return;
+  const int li = lane & 15, lk = lane >> 4;
+  const double *xr = x + int64_t(blockIdx.z) * ldx;
+  double *yr = y + int64_t(blockIdx.z) * ldy;
+  const int64_t cell0 = int64_t(blockIdx.x) * (16 * NB);
+  const int32_t *cdp[NB];
+  float wv[NB][Q];
+  bool valid[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t c = cell0 + nb * 16 + li;
+    valid[nb] = c < nc;
+    const int64_t cc = valid[nb] ? c : nc - 1;
+    cdp[nb] = cd + cc * n;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) wv[nb][q] = valid[nb] ? w[cc * Q + q] : 0.0f;
+  }
+  f4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0, 0, 0, 0};
+  const float *Ab = Af + size_t(mb) * KB * Q * 64 + lane;
+  float a0[Q], x0[NB];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) a0[q] = Ab[q * 64];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) x0[nb] = lk < n ? float(xr[cdp[nb][lk]]) : 0.0f;
+  for (int jb = 0; jb < KB; ++jb) {
+    float a1[Q], x1[NB];
+    if (jb + 1 < KB) {
+      const float *An = Ab + size_t(jb + 1) * Q * 64;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) a1[q] = An[q * 64];
+      const int col = (jb + 1) * 4 + lk;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) x1[nb] = col < n ? float(xr[cdp[nb][col]]) : 0.0f;
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) a1[q] = 0.0f;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) x1[nb] = 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[q], wv[nb][q] * x0[nb], acc[nb], 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) a0[q] = a1[q];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) x0[nb] = x1[nb];
+  }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    if (!valid[nb]) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      // FP32 16x16x4 accumulator layout: lane l, element v holds row 4 (l/16) + v, column l%16
+      const int row = mb * 16 + lk * 4 + v;
+      if (row < n) atomicAdd(&yr[cdp[nb][row]], double(acc[nb][v]));
+    }
+  }
+}
+
+__global__ void k_to_float(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    b[i] = float(a[i]);
+}
+
+// x += d per column (refinement update)
+__global__ void k_axpy_m(int64_t n, const double *__restrict__ d, double *__restrict__ x, int64_t ldx) {
+  const int c = blockIdx.y;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    x[c * ldx + i] += d[c * n + i];
+}
+
 // -------------------------------------------------------------- apply_P
 // Work item = (patch, row range [r0, r1)) of the packed upper triangle of the
 // patch inverse (rows ~balanced by element count) and a group of G right-hand
@@ -446,7 +533,7 @@ __global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int64_t
 // reduced; column j is owned by lane j % 64.  Row sums (j >= i) and the
 // mirrored column sums (j > i) of the chunk are combined in LDS and
 // scatter-added (atomics: chunks and patches overlap).
-template <int MAXJ, int G>
+template <int MAXJ, int G, typename T>
 __global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__ chunk_patch,
                                                      const int32_t *__restrict__ chunk_rows,
                                                      const int64_t *__restrict__ patch_col,
@@ -454,7 +541,7 @@ __global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__
                                                      const int32_t *__restrict__ ent_dof,
                                                      const double *__restrict__ ent_coef,
                                                      const int64_t *__restrict__ inv_off,
-                                                     const double *__restrict__ inv, const double *__restrict__ r,
+                                                     const T *__restrict__ inv, const double *__restrict__ r,
                                                      int64_t ldr, double *__restrict__ z, int64_t ldz, int ncol,
                                                      int maxsz, const PcgState *st) {
   const int cbase = blockIdx.y * G;
@@ -483,7 +570,7 @@ __global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__
     yr[g * maxsz + j] = 0.0;
   }
   __syncthreads();
-  const double *A = inv + inv_off[p];
+  const T *A = inv + inv_off[p];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double cacc[MAXJ][G], cur[MAXJ], nxt[MAXJ];
 #pragma unroll
@@ -491,11 +578,11 @@ __global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__
 #pragma unroll
     for (int g = 0; g < G; ++g) cacc[jb][g] = 0.0;
   auto load_row = [&](int i, double *buf) {
-    const double *row = A + int64_t(i) * m - int64_t(i) * (i - 1) / 2 - i;  // row[j] = A_ij, j >= i
+    const T *row = A + int64_t(i) * m - int64_t(i) * (i - 1) / 2 - i;  // row[j] = A_ij, j >= i
 #pragma unroll
     for (int jb = 0; jb < MAXJ; ++jb) {
       const int j = jb * 64 + lane;
-      buf[jb] = (j >= i && j < m) ? row[j] : 0.0;
+      buf[jb] = (j >= i && j < m) ? double(row[j]) : 0.0;
     }
   };
   int i = r0 + wave;
@@ -542,8 +629,8 @@ __global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__
 // per tile, G right-hand sides per pass.  Lane c keeps column c of the tile in
 // registers; A_IJ^T r_I is a lane-local sum, A_IJ r_J goes through an LDS
 // transpose.  rW / zW: npad x ncol.
-template <int G>
-__global__ __launch_bounds__(64) void k_coarse_tiles(int NT, const double *__restrict__ T,
+template <int G, typename TT>
+__global__ __launch_bounds__(64) void k_coarse_tiles(int NT, const TT *__restrict__ T,
                                                      const double *__restrict__ rW, double *__restrict__ zW,
                                                      int npad, int ncol, const PcgState *st) {
   const int cbase = blockIdx.y * G;
@@ -559,7 +646,7 @@ __global__ __launch_bounds__(64) void k_coarse_tiles(int NT, const double *__res
   while (int64_t(I + 1) * NT - int64_t(I + 1) * I / 2 <= t) ++I;
   const int J = int(t - (int64_t(I) * NT - int64_t(I) * (I - 1) / 2)) + I;
   const int c = threadIdx.x;
-  const double *tile = T + t * 4096;
+  const TT *tile = T + t * 4096;
   double a[64];
 #pragma unroll
   for (int r = 0; r < 64; ++r) a[r] = tile[r * 64 + c];
@@ -777,7 +864,8 @@ __global__ __launch_bounds__(256) void k_dot_m(int64_t n, const double *__restri
 
 // PCG start: bb = ||b||^2, rr = ||r||^2 (partials in partZ / partR)
 __global__ __launch_bounds__(256) void k_pcg_start(const double *__restrict__ partB, const double *__restrict__ partR,
-                                                   int RB, double tol2, int maxit, PcgState *st) {
+                                                   int RB, double tol2, int maxit, PcgState *st,
+                                                   const PcgState *outer) {
   __shared__ double sm4[4];
   const int c = blockIdx.x;
   const double bb = sum_part(partB + c * RB, RB, sm4);
@@ -791,7 +879,8 @@ __global__ __launch_bounds__(256) void k_pcg_start(const double *__restrict__ pa
     s.maxit = maxit;
     s.status = PCG_RUNNING;
     s.done = 0;
-    if (!(bb > 0.0) || rr <= tol2 * bb) {
+    // columns already converged in an enclosing refinement loop are skipped
+    if (!(bb > 0.0) || rr <= tol2 * bb || (outer && outer[c].done)) {
       s.done = 1;
       s.status = PCG_CONVERGED;
     }
@@ -1011,26 +1100,45 @@ static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, const double *x,
                        x, ldx, y, ldy, st);
 }
 
+template <int Q>
+static void apply_A32_q(const ApplyATables &t, int NB, dim3 grid, const double *x, int64_t ldx, double *y,
+                        int64_t ldy, const PcgState *st, hipStream_t s) {
+  const int KB = t.KP / 4, NMB = t.NP / 16;
+#define RZ_A32(NBV)                                                                                          \
+  hipLaunchKernelGGL((k_apply_A32<Q, NBV>), grid, dim3(256), 0, s, t.n, NMB, KB, t.n_cells, t.Afrag32, t.w32, \
+                     t.cell_dofs, x, ldx, y, ldy, st)
+  if (NB == 4) RZ_A32(4);
+  else if (NB == 2) RZ_A32(2);
+  else RZ_A32(1);
+#undef RZ_A32
+}
+
 void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
-                    const PcgState *st, hipStream_t s) {
+                    const PcgState *st, hipStream_t s, bool lo) {
   const int NMB = t.NP / 16;
   // cells per wave: as many as keep >= 2048 waves in flight (A-fragment reuse vs occupancy)
   int NB = 4;
   while (NB > 1 && ((t.n_cells + 16 * NB - 1) / (16 * NB)) * NMB * n_rhs < 2048) NB /= 2;
   dim3 grid(unsigned((t.n_cells + 16 * NB - 1) / (16 * NB)), unsigned((NMB + 3) / 4), unsigned(n_rhs));
+  if (lo && t.Afrag32) {
+    if (t.Q == 12) apply_A32_q<12>(t, NB, grid, x, ldx, y, ldy, st, s);
+    else if (t.Q == 7) apply_A32_q<7>(t, NB, grid, x, ldx, y, ldy, st, s);
+    else apply_A32_q<4>(t, NB, grid, x, ldx, y, ldy, st, s);
+    return;
+  }
   if (t.Q == 12) apply_A_q<12>(t, NB, grid, x, ldx, y, ldy, st, s);
   else if (t.Q == 7) apply_A_q<7>(t, NB, grid, x, ldx, y, ldy, st, s);
   else apply_A_q<4>(t, NB, grid, x, ldx, y, ldy, st, s);
 }
 
 // patch apply: largest G in {8,4,2,1} with G <= ncol, LDS <= 96 KB, MAXJ * G <= 32
-template <int MJ>
-static void patch_g(const PatchApply &pa, dim3 g1, int G, size_t lds_per_g, const double *r, int64_t ldr, double *z,
-                    int64_t ldz, int ncol, const PcgState *st, hipStream_t s) {
+template <int MJ, typename T>
+static void patch_g(const PatchApply &pa, const T *inv, dim3 g1, int G, size_t lds_per_g, const double *r,
+                    int64_t ldr, double *z, int64_t ldz, int ncol, const PcgState *st, hipStream_t s) {
   dim3 g(g1.x, unsigned((ncol + G - 1) / G));
-#define RZ_PG(GG)                                                                                               \
-  hipLaunchKernelGGL((k_patch_apply<MJ, GG>), g, dim3(256), lds_per_g * GG, s, pa.chunk_patch, pa.chunk_rows,  \
-                     pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, pa.inv_off, pa.inv, r, ldr, z, ldz, ncol, \
+#define RZ_PG(GG)                                                                                                 \
+  hipLaunchKernelGGL((k_patch_apply<MJ, GG, T>), g, dim3(256), lds_per_g * GG, s, pa.chunk_patch, pa.chunk_rows, \
+                     pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, pa.inv_off, inv, r, ldr, z, ldz, ncol,     \
                      pa.max_size, st)
   if (G >= 8) RZ_PG(8);
   else if (G >= 4) RZ_PG(4);
@@ -1040,7 +1148,7 @@ static void patch_g(const PatchApply &pa, dim3 g1, int G, size_t lds_per_g, cons
 }
 
 void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
-                        const PcgState *st, hipStream_t s) {
+                        const PcgState *st, hipStream_t s, bool lo) {
   if (pa.n_chunks == 0) return;
   if (ncol >= 8 && pa.max_size <= kSmallPatch) {
     const int MP = (pa.max_size + 15) & ~15;
@@ -1061,17 +1169,24 @@ void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, doub
   int G = 8;
   while (G > 1 && (G > ncol || lds_per_g * G > 96 * 1024 || mj * G > 32)) G /= 2;
   const dim3 g1(unsigned(pa.n_chunks));
-  switch (mj) {
-    case 1: patch_g<1>(pa, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;
-    case 2: patch_g<2>(pa, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;
-    case 4: patch_g<4>(pa, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;
-    case 8: patch_g<8>(pa, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;
-    case 14: patch_g<14>(pa, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;
-    default: patch_g<24>(pa, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;
+#define RZ_PD(T, INV)                                                              \
+  switch (mj) {                                                                    \
+    case 1: patch_g<1, T>(pa, INV, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;   \
+    case 2: patch_g<2, T>(pa, INV, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;   \
+    case 4: patch_g<4, T>(pa, INV, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;   \
+    case 8: patch_g<8, T>(pa, INV, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;   \
+    case 14: patch_g<14, T>(pa, INV, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break; \
+    default: patch_g<24, T>(pa, INV, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break; \
   }
+  if (lo && pa.inv32) {
+    RZ_PD(float, pa.inv32)
+  } else {
+    RZ_PD(double, pa.inv)
+  }
+#undef RZ_PD
 }
 
-void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hipStream_t s) {
+void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hipStream_t s, bool lo) {
   const unsigned nt = unsigned(int64_t(ca.NT) * (ca.NT + 1) / 2);
   const int npad = ca.NT * 64;
   if (ncol >= 8 && ca.full) {
@@ -1085,23 +1200,31 @@ void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hi
   int G = 8;
   while (G > 1 && G > ncol) G /= 2;
   dim3 g(nt, unsigned((ncol + G - 1) / G));
-#define RZ_CT(GG) hipLaunchKernelGGL(k_coarse_tiles<GG>, g, dim3(64), 0, s, ca.NT, ca.tiles, ca.rW, ca.zW, npad, ncol, st)
-  if (G == 8) RZ_CT(8);
-  else if (G == 4) RZ_CT(4);
-  else if (G == 2) RZ_CT(2);
-  else RZ_CT(1);
+#define RZ_CT(GG, TT, TI) \
+  hipLaunchKernelGGL((k_coarse_tiles<GG, TT>), g, dim3(64), 0, s, ca.NT, TI, ca.rW, ca.zW, npad, ncol, st)
+  if (lo && ca.tiles32) {
+    if (G == 8) RZ_CT(8, float, ca.tiles32);
+    else if (G == 4) RZ_CT(4, float, ca.tiles32);
+    else if (G == 2) RZ_CT(2, float, ca.tiles32);
+    else RZ_CT(1, float, ca.tiles32);
+  } else {
+    if (G == 8) RZ_CT(8, double, ca.tiles);
+    else if (G == 4) RZ_CT(4, double, ca.tiles);
+    else if (G == 2) RZ_CT(2, double, ca.tiles);
+    else RZ_CT(1, double, ca.tiles);
+  }
 #undef RZ_CT
 }
 
 void launch_apply_P(const PatchApply *sets, int nsets, const CoarseApply &ca, int64_t n, int64_t off_I,
                     const double *dinv, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
-                    hipStream_t s) {
+                    hipStream_t s, bool lo) {
   hipLaunchKernelGGL(k_jacobi_m, dim3(grid_for(n, 256, 2048), ncol), dim3(256), 0, s, n, off_I, dinv, r, ldr, z, ldz);
-  for (int i = 0; i < nsets; ++i) launch_patch_apply(sets[i], r, ldr, z, ldz, ncol, nullptr, s);
+  for (int i = 0; i < nsets; ++i) launch_patch_apply(sets[i], r, ldr, z, ldz, ncol, nullptr, s, lo);
   const int npad = ca.NT * 64;
   hipLaunchKernelGGL(k_coarse_gather_m, dim3(grid_for(npad, 256), ncol), dim3(256), 0, s, ca.nW, npad, ca.wdofs, r,
                      ldr, ca.rW, ca.zW);
-  launch_coarse_tiles(ca, ncol, nullptr, s);
+  launch_coarse_tiles(ca, ncol, nullptr, s, lo);
   hipLaunchKernelGGL(k_coarse_scatter_m, dim3(grid_for(ca.nW, 256), ncol), dim3(256), 0, s, ca.nW, npad, ca.wdofs,
                      ca.zW, z, ldz);
 }
@@ -1120,8 +1243,8 @@ void launch_dot(int64_t n, const double *a, int64_t lda, const double *b, int64_
   hipLaunchKernelGGL(k_dot_m, dim3(RB, ncol), dim3(256), 0, s, n, a, lda, b, ldb, cf, npad, part, RB, st);
 }
 void launch_pcg_start(const double *partB, const double *partR, int RB, double tol2, int maxit, PcgState *st,
-                      int ncol, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_start, dim3(ncol), dim3(256), 0, s, partB, partR, RB, tol2, maxit, st);
+                      int ncol, hipStream_t s, const PcgState *outer) {
+  hipLaunchKernelGGL(k_pcg_start, dim3(ncol), dim3(256), 0, s, partB, partR, RB, tol2, maxit, st, outer);
 }
 void launch_update_xr(int64_t n, double *x, int64_t ldx, double *r, const double *p, const double *Ap,
                       const double *partZ, const double *partA, double *partR, int RB, int ncol, PcgState *st,
@@ -1142,6 +1265,13 @@ void launch_update_p(int64_t n, double *p, const double *z, const CoarseFold &cf
 
 void launch_coarse_expand(int NT, const double *tiles, double *full, hipStream_t s) {
   hipLaunchKernelGGL(k_coarse_expand, dim3(NT, NT), dim3(256), 0, s, NT, tiles, full);
+}
+
+void launch_to_float(int64_t n, const double *a, float *b, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_float, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, a, b);
+}
+void launch_axpy(int64_t n, const double *d, double *x, int64_t ldx, int ncol, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_m, dim3(grid_for(n, 256, 2048), ncol), dim3(256), 0, s, n, d, x, ldx);
 }
 
 }  // namespace rz

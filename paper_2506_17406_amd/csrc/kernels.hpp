@@ -39,11 +39,13 @@ struct ApplyATables {
   const double *w;          // n_cells x Q weights
   const int32_t *cell_dofs; // n_cells x n
   int64_t n_cells;
+  const float *Afrag32;     // FP32 copies for the mixed-precision inner operator (or null)
+  const float *w32;
 };
 // y += A x for n_rhs columns (y must be zeroed by the caller); st: per-column
-// state (columns that are done are skipped) or null
+// state (columns that are done are skipped) or null; lo: the FP32 copies
 void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
-                    const PcgState *st, hipStream_t s);
+                    const PcgState *st, hipStream_t s, bool lo = false);
 
 struct PatchApply {
   int64_t n_patches, n_chunks;
@@ -54,6 +56,7 @@ struct PatchApply {
   const int32_t *ent_dof;
   const double *ent_coef;
   const double *inv;        // packed upper rows per patch
+  const float *inv32;       // FP32 copy (mixed precision) or null
 };
 struct CoarseApply {
   int nW, NT;               // coarse size, tiles per side
@@ -61,6 +64,7 @@ struct CoarseApply {
   const double *tiles;      // upper tiles (I <= J), 64 x 64 each, row-major
   double *rW, *zW;          // work vectors (NT * 64 per column)
   const double *full;       // all NT x NT tiles in MFMA fragment order (many-column solves), or null
+  const float *tiles32;     // FP32 copy of the upper tiles (mixed precision) or null
 };
 // builds CoarseApply::full from the packed upper tiles
 void launch_coarse_expand(int NT, const double *tiles, double *full, hipStream_t s);
@@ -74,12 +78,14 @@ struct CoarseFold {
 
 // z += sum_patches (scatter-add; z must hold the Jacobi part already)
 void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
-                        const PcgState *st, hipStream_t s);
-void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hipStream_t s);
+                        const PcgState *st, hipStream_t s, bool lo = false);
+void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hipStream_t s, bool lo = false);
+void launch_to_float(int64_t n, const double *a, float *b, hipStream_t s);
+void launch_axpy(int64_t n, const double *d, double *x, int64_t ldx, int ncol, hipStream_t s);
 // the whole preconditioner, z = P^{-1} r (no state)
 void launch_apply_P(const PatchApply *sets, int nsets, const CoarseApply &ca, int64_t n, int64_t off_I,
                     const double *dinv, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
-                    hipStream_t s);
+                    hipStream_t s, bool lo = false);
 
 // ---- Krylov (RB block partials per column)
 void launch_fill(double *y, int64_t n, int64_t ld, int ncol, const PcgState *st, hipStream_t s);
@@ -87,8 +93,9 @@ void launch_copy(int64_t n, const double *a, int64_t lda, double *b, int64_t ldb
 void launch_residual(int64_t n, const double *b, int64_t ldb, const double *Ax, double *r, int ncol, hipStream_t s);
 void launch_dot(int64_t n, const double *a, int64_t lda, const double *b, int64_t ldb, const CoarseFold &cf,
                 int npad, double *part, int RB, int ncol, const PcgState *st, hipStream_t s);
+// outer (or null): columns whose outer state is done start as converged
 void launch_pcg_start(const double *partB, const double *partR, int RB, double tol2, int maxit, PcgState *st,
-                      int ncol, hipStream_t s);
+                      int ncol, hipStream_t s, const PcgState *outer = nullptr);
 void launch_update_xr(int64_t n, double *x, int64_t ldx, double *r, const double *p, const double *Ap,
                       const double *partZ, const double *partA, double *partR, int RB, int ncol, PcgState *st,
                       hipStream_t s);

@@ -25,13 +25,19 @@ class RzMesh(ctypes.Structure):
                 ("n_cells", ctypes.c_int64), ("cells", ctypes.POINTER(ctypes.c_int64))]
 
 
+RZ_FP64, RZ_FP32_IR = 0, 1
+PRECISIONS = {"fp64": RZ_FP64, "fp32-ir": RZ_FP32_IR}
+
+
 class RzOptions(ctypes.Structure):
-    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
 
 
 class RzInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
-                ("cond_estimate", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+                ("cond_estimate", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("outer_iterations", ctypes.c_int32)]
 
 
 class RzError(RuntimeError):
@@ -53,6 +59,8 @@ def _load():
         "rz_sizes": (ctypes.c_int, [P, pi64, pi64, pi32, pi32]),
         "rz_apply_A": (ctypes.c_int, [P, P, P, i32, i64, P]),
         "rz_apply_P": (ctypes.c_int, [P, P, P, i32, i64, P]),
+        "rz_apply_A_fp32": (ctypes.c_int, [P, P, P, i32, i64, P]),
+        "rz_apply_P_fp32": (ctypes.c_int, [P, P, P, i32, i64, P]),
         "rz_solve": (ctypes.c_int, [P, P, P, i32, i64, dbl, ctypes.POINTER(RzInfo), P]),
         "rz_export_topology": (ctypes.c_int, [P, pi32, pi64, pi64, pi64, pi32]),
         "rz_export_reference": (ctypes.c_int, [P, pdbl]),
@@ -124,9 +132,11 @@ def _stream(stream):
 class Problem:
     """A set-up Riesz-map problem on the GPU (rz_setup)."""
 
-    def __init__(self, coords, cells, degree, space, alpha=1.0, beta=1.0, max_iter=1000, stream=None):
+    def __init__(self, coords, cells, degree, space, alpha=1.0, beta=1.0, max_iter=1000, precision="fp64",
+                 inner_rtol=0.0, stream=None):
         m, keep = _mesh(coords, cells)
-        opts = RzOptions(alpha, beta, max_iter)
+        prec = PRECISIONS[precision] if isinstance(precision, str) else precision
+        opts = RzOptions(alpha, beta, max_iter, prec, inner_rtol)
         h = ctypes.c_void_p()
         self._h = None
         self.space = SPACES[space] if isinstance(space, str) else space
@@ -166,18 +176,18 @@ class Problem:
             raise ValueError("matrix must be column-major with n_dofs rows")
         return t.shape[1], t.stride(1)
 
-    def apply_A(self, x, y, stream=None):
+    def apply_A(self, x, y, stream=None, fp32=False):
         nr, ld = self._cols(x)
         self._cols(y)
-        _check(lib.rz_apply_A(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), nr, ld,
-                              _stream(stream)))
+        fn = lib.rz_apply_A_fp32 if fp32 else lib.rz_apply_A
+        _check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), nr, ld, _stream(stream)))
         return y
 
-    def apply_P(self, r, z, stream=None):
+    def apply_P(self, r, z, stream=None, fp32=False):
         nr, ld = self._cols(r)
         self._cols(z)
-        _check(lib.rz_apply_P(self._h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()), nr, ld,
-                              _stream(stream)))
+        fn = lib.rz_apply_P_fp32 if fp32 else lib.rz_apply_P
+        _check(fn(self._h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()), nr, ld, _stream(stream)))
         return z
 
     def solve(self, b, x, rtol=1e-10, stream=None, check=True):
@@ -193,7 +203,8 @@ class Problem:
         if check:
             _check(code)
         out = [dict(status=i.status, iterations=i.iterations, rel_residual=i.rel_residual,
-                    cond_estimate=i.cond_estimate, solve_ms=i.solve_ms, code=code) for i in info]
+                    cond_estimate=i.cond_estimate, solve_ms=i.solve_ms, outer_iterations=i.outer_iterations,
+                    code=code) for i in info]
         return out[0] if b.dim() == 1 else out
 
     def export_reference(self):

@@ -1,0 +1,143 @@
+"""GPU checks of the mixed-precision path (FP32 applies inside FP64
+iterative refinement) against the FP64 oracle, through the C ABI.
+
+Bars (written per check):
+* FP32 apply_A -- the first-order rounding bound of an FP32 contraction of
+  K = Q n_loc products per row from FP32-rounded inputs: elementwise
+  |y32 - A x|_i <= (K + 4) u32 (|A|_abs |x|)_i with u32 = 2^-24 and
+  |A|_abs = sum_T P_T^T (sum_q |w_Tq| |R_q|) P_T (the oracle's tables);
+  and the result must differ from the FP64 apply (the FP32 path ran);
+* FP32 apply_P -- max |z32 - z_oracle| <= 1e-4 max |z_oracle| (inverse
+  entries rounded once to FP32; accumulation in FP64);
+* refinement solve -- true residual under the oracle's A <= 1.2 rtol ||b||
+  + ||(A_lib - A_oracle) x|| at rtol 1e-10 and 1e-12, ||x - x_oracle|| <=
+  1e-10 ||x_oracle|| at rtol 1e-12, at least two refinement steps taken.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.element import element
+from oracle.mesh import Topology
+from oracle.operator import all_cell_matrices, assemble, cell_weights, reference_stack
+from oracle.pcg import pcg
+from oracle.precond import AdditiveSchwarz
+from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+CASES = [(2, "CG", 4, 4), (3, "CG", 3, 3), (3, "CG", 6, 2), (3, "Ned", 3, 2), (3, "Ned", 6, 2), (3, "RT", 4, 2),
+         (3, "RT", 1, 2), (3, "Ned", 1, 2)]
+
+_cache = {}
+
+
+def setup_case(d, fam, p, n):
+    key = (d, fam, p, n)
+    if key not in _cache:
+        from paper_2506_17406_amd import rz
+        X, C = kuhn_mesh(n, d, jitter=0.1 if d == 3 else 0.0, seed=13)
+        top = Topology(X, C, element(d, fam, p))
+        A = assemble(top, all_cell_matrices(top.el, top))
+        P = AdditiveSchwarz(A, top, fam)
+        prob = rz.Problem(X, C, p, fam, precision="fp32-ir")
+        _cache[key] = (top, A, P, prob)
+    return _cache[key]
+
+
+def ids(c):
+    return "{}d-{}{}-n{}".format(*c)
+
+
+def abs_apply(top, x):
+    """(|A|_abs x) with |A|_abs = sum_T P_T^T (sum_q |w_Tq| |R_q|) P_T."""
+    R = np.abs(reference_stack(top.el))
+    y = np.zeros(top.n_dofs)
+    for c in range(top.n_cells):
+        w = np.abs(cell_weights(top.el, top.coords[top.cells[c]]))
+        Ac = np.tensordot(w, R, axes=1)
+        dofs = top.cell_dofs[c]
+        np.add.at(y, dofs, Ac @ x[dofs])
+    return y
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_apply_A_fp32_rounding_bound(case):
+    top, A, P, prob = setup_case(*case)
+    x = load_vectors(top.n_dofs, 31)[:, 0]
+    xt = torch.from_numpy(x).cuda()
+    y32, y64 = torch.empty_like(xt), torch.empty_like(xt)
+    prob.apply_A(xt, y32, fp32=True)
+    prob.apply_A(xt, y64)
+    torch.cuda.synchronize()
+    y32, y64 = y32.cpu().numpy(), y64.cpu().numpy()
+    K = top.el.n * prob.Q
+    bound = (K + 4) * U32 * abs_apply(top, np.abs(x))
+    err = np.abs(y32 - A @ x)
+    assert np.all(err <= bound), (err / bound).max()
+    assert np.abs(y32 - y64).max() > 1e-13 * np.abs(y64).max()
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_apply_P_fp32(case):
+    top, A, P, prob = setup_case(*case)
+    r = load_vectors(top.n_dofs, 32)[:, 0]
+    zt = torch.empty(top.n_dofs, dtype=torch.float64, device="cuda")
+    prob.apply_P(torch.from_numpy(r).cuda(), zt, fp32=True)
+    torch.cuda.synchronize()
+    ref = P.apply(r)
+    assert np.abs(zt.cpu().numpy() - ref).max() <= 1e-4 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_refinement_solve(case):
+    top, A, P, prob = setup_case(*case)
+    b = load_vectors(top.n_dofs, 33)[:, 0]
+    bt = torch.from_numpy(b).cuda()
+    xo, io = pcg(lambda v: A @ v, P.apply, b, rtol=1e-12)
+    for rtol in (1e-10, 1e-12):
+        xt = torch.zeros_like(bt)
+        info = prob.solve(bt, xt, rtol=rtol)
+        x = xt.cpu().numpy()
+        assert info["status"] == 0 and info["outer_iterations"] >= 2
+        assert info["rel_residual"] <= rtol
+        # the library's FP64 operator meets rtol; under the oracle's operator
+        # the residual may also carry the (tested, ~1e-12 relative) difference
+        # of the two operators
+        yt = torch.empty_like(bt)
+        prob.apply_A(xt, yt)
+        Ax = A @ x
+        gap = np.linalg.norm(yt.cpu().numpy() - Ax)
+        assert np.linalg.norm(b - Ax) <= 1.2 * rtol * np.linalg.norm(b) + gap
+        if rtol == 1e-12:
+            assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
+            # the corrections cost at most twice the FP64 iteration count
+            assert info["iterations"] <= 2 * io["iterations"] + 4
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[5]], ids=ids)
+def test_refinement_multi_rhs(case):
+    """Columns converge independently; each meets its own true-residual test."""
+    top, A, P, prob = setup_case(*case)
+    nr = 5
+    B = load_vectors(top.n_dofs, 34, n_rhs=nr)
+    B[:, 2] *= 1e-6                       # a column with a very different scale
+    Bt = torch.from_numpy(np.ascontiguousarray(B.T)).cuda().T
+    Xt = torch.zeros_like(Bt)
+    infos = prob.solve(Bt, Xt, rtol=1e-10)
+    X = Xt.cpu().numpy()
+    for j in range(nr):
+        assert infos[j]["status"] == 0
+        assert np.linalg.norm(B[:, j] - A @ X[:, j]) <= 1.2e-10 * np.linalg.norm(B[:, j])
+
+
+def test_fp32_entry_points_need_fp32_setup():
+    from paper_2506_17406_amd import rz
+    X, C = kuhn_mesh(1, 3)
+    prob = rz.Problem(X, C, 2, "CG")
+    x = torch.zeros(prob.n_dofs, dtype=torch.float64, device="cuda")
+    with pytest.raises(rz.RzError, match="RZ_FP32_IR"):
+        prob.apply_A(x, torch.empty_like(x), fp32=True)

@@ -67,9 +67,14 @@ def test_setup_rejects_before_device_work():
     X, C = kuhn_mesh(1)
     m, keep = _mesh_struct(X, C)
     h = ctypes.c_void_p()
-    opts = rz.RzOptions(-1.0, 1.0, 100)
+    opts = rz.RzOptions(-1.0, 1.0, 100, 0, 0.0)
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
-    opts = rz.RzOptions(1.0, 0.0, 100)
+    opts = rz.RzOptions(1.0, 0.0, 100, 0, 0.0)
+    assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
+    opts = rz.RzOptions(1.0, 1.0, 100, 5, 0.0)           # unknown precision
+    assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
+    assert b"precision" in rz.lib.rz_last_error()
+    opts = rz.RzOptions(1.0, 1.0, 100, 1, 1.5)           # inner tolerance >= 1
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
     assert rz.lib.rz_setup(None, 2, 0, None, None, ctypes.byref(h)) == -1
     assert rz.lib.rz_setup(ctypes.byref(m), 12, 0, None, None, ctypes.byref(h)) == -2
