@@ -42,6 +42,7 @@ struct RzError {
 struct DevPatchSet {
   rz::PatchApply pa{};
   int64_t n_inv = 0;  // packed inverse entries
+  std::vector<int64_t> sizes;  // patch sizes (for the FP32 layout)
 };
 
 }  // namespace
@@ -141,6 +142,10 @@ void check_cells(const rz_problem &P, const double *coords) {
 void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hipStream_t s) {
   const int64_t B = ps.n_patches();
   const int maxsz = int(ps.max_size());
+  if (maxsz > rz::kMaxPatch)
+    throw RzError{RZ_ERR_UNSUPPORTED, "interface patch of " + std::to_string(maxsz) + " dofs exceeds " +
+                                          std::to_string(rz::kMaxPatch)};
+  const int E = 2;  // FP64 segment length
   const int N = std::max(32, round_up(maxsz, 32));
   std::vector<int32_t> sizes(B);
   std::vector<int64_t> off(B);
@@ -148,7 +153,7 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
   for (int64_t b = 0; b < B; ++b) {
     sizes[b] = int32_t(ps.patch_col[b + 1] - ps.patch_col[b]);
     off[b] = tot;
-    tot += int64_t(sizes[b]) * (sizes[b] + 1) / 2;
+    tot += rz::seg_size(sizes[b], E);
   }
   double *inv = P.dev<double>(tot);
   const int64_t budget = int64_t(6) << 30;  // bytes for A + L^{-1} per chunk
@@ -209,7 +214,7 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
     rz::launch_patch_assemble(i1 - i0, d_ip, d_ic, d_it, t_col, t_loc, t_coef, P.el.n, P.el.Q, P.R, P.w, N, Abuf,
                               s);
     rz::launch_chol_inverse(nb, N, Abuf, Lbuf, dstatus, s);
-    rz::launch_pack_upper(nb, N, dsizes + p0, doff + p0, Abuf, inv, s);
+    rz::launch_pack_seg(nb, N, E, dsizes + p0, doff + p0, Abuf, inv, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
   }
@@ -219,13 +224,16 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
   // work chunks: row ranges of ~equal packed-element counts
   std::vector<int64_t> chunk_patch;
   std::vector<int32_t> chunk_rows;
-  const int64_t target = 32768;
+#ifndef RZ_CHUNK
+#define RZ_CHUNK 32768
+#endif
+  const int64_t target = RZ_CHUNK;
   for (int64_t b = 0; b < B; ++b) {
     const int m = sizes[b];
     int r0 = 0;
     int64_t acc = 0;
     for (int i = 0; i < m; ++i) {
-      acc += m - i;
+      acc += (m + E - 1) / E * E - i / E * E;  // stored entries of row i
       if (acc >= target || i == m - 1) {
         chunk_patch.push_back(b);
         chunk_rows.push_back(r0);
@@ -247,6 +255,7 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
   out.pa.ent_coef = P.upload(ps.ent_coef, s);
   out.pa.inv = inv;
   out.n_inv = tot;
+  out.sizes.assign(sizes.begin(), sizes.end());
 }
 
 void setup_coarse(rz_problem &P, hipStream_t s) {
@@ -421,7 +430,18 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
       };
       P->at.Afrag32 = lo(P->Afrag, int64_t(P->at.NP) * P->at.KP * Q);
       P->at.w32 = lo(P->w, nc * Q);
-      for (auto &d : P->dps) d.pa.inv32 = lo(d.pa.inv, d.n_inv);
+      for (auto &d : P->dps) {
+        std::vector<int64_t> off32(d.sizes.size());
+        int64_t tot32 = 0;
+        for (size_t b = 0; b < d.sizes.size(); ++b) {
+          off32[b] = tot32;
+          tot32 += rz::seg_size(int(d.sizes[b]), 4);
+        }
+        float *inv32 = P->dev<float>(size_t(tot32));
+        d.pa.inv_off32 = P->upload(off32, s);
+        rz::launch_seg_to_float(d.pa.n_patches, d.pa.patch_col, d.pa.inv_off, d.pa.inv_off32, d.pa.inv, inv32, s);
+        d.pa.inv32 = inv32;
+      }
       P->ca.tiles32 = lo(P->ca.tiles, int64_t(P->ca.NT) * (P->ca.NT + 1) / 2 * 4096);
       HIPCHK(hipGetLastError());
     }

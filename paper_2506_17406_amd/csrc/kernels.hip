@@ -30,6 +30,29 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// one 64-bit DPP lane move (gfx9 DPP controls: quad_perm, row_mirror ...)
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over aligned groups of L lanes (L = 16, 32, 64); every lane of a group
+// gets the group sum.  Within a 16-lane row: quad_perm [1,0,3,2], quad_perm
+// [2,3,0,1], row_half_mirror, row_mirror; across rows: lane permutes.  Must
+// be called with all 64 lanes active.
+template <int L>
+__device__ inline double group_sum(double v) {
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  v += dpp_mov<0x140>(v);
+  if (L >= 32) v += __shfl_xor(v, 16, 64);
+  if (L >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 // deterministic block sum of 256 threads; result valid in every thread
 __device__ inline double block_sum256(double v, double *sm4) {
   v = wave_sum(v);
@@ -332,17 +355,39 @@ __global__ void k_lauum(int N, const double *__restrict__ X, double *__restrict_
   }
 }
 
-__global__ void k_pack_upper(int N, const int32_t *__restrict__ sizes, const int64_t *__restrict__ off,
-                             const double *__restrict__ A, double *__restrict__ P) {
+// Segmented upper layout of a symmetric m x m patch inverse (E elements per
+// segment, mS = m rounded up to E): row i holds the columns [s_i, mS) with
+// s_i = E floor(i / E); entries left of the diagonal and right of m are zero
+// and the diagonal is stored halved, so that the row products (j >= i) and the
+// mirrored column products (j >= i) together apply the full matrix.  Every
+// row is a whole number of E-element segments, aligned to E elements.
+__device__ __host__ inline int64_t seg_row_off(int64_t i, int64_t mS, int E) {
+  const int64_t b = i / E;
+  return E * (b * mS - E * b * (b - 1) / 2) + (i - b * E) * (mS - b * E);
+}
+
+__global__ void k_pack_seg(int N, int E, const int32_t *__restrict__ sizes, const int64_t *__restrict__ off,
+                           const double *__restrict__ A, double *__restrict__ P) {
   const int64_t b = blockIdx.x;
   const int m = sizes[b];
+  const int mS = (m + E - 1) / E * E;
   const double *M = A + b * N * N;
   double *out = P + off[b];
   for (int i = 0; i < m; ++i) {
-    const int64_t ro = int64_t(i) * m - int64_t(i) * (i - 1) / 2 - i;
-    for (int j = i + threadIdx.x; j < m; j += blockDim.x) out[ro + j] = M[int64_t(i) * N + j];
+    const int64_t ro = seg_row_off(i, mS, E);
+    const int si = i / E * E;
+    for (int k = si + threadIdx.x; k < mS; k += blockDim.x) {
+      double v = 0.0;
+      if (k >= i && k < m) v = (k == i ? 0.5 : 1.0) * M[int64_t(i) * N + k];
+      out[ro + k - si] = v;
+    }
   }
 }
+
+// Element (r, c) of a 64 x 64 coarse tile: wave ty = r / 16 of the reading
+// block loads rows 16 ty .. 16 ty + 15 as eight coalesced pairs (rows 2q,
+// 2q + 1 of its slice) per lane c.
+__device__ __host__ inline int ctile_idx(int r, int c) { return (r >> 4) * 1024 + ((r & 15) >> 1) * 128 + c * 2 + (r & 1); }
 
 __global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A, double *__restrict__ T) {
   const int64_t t = blockIdx.x;
@@ -354,7 +399,7 @@ __global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A,
   for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
     const int r = e / 64, c = e % 64;
     const int gi = I * 64 + r, gj = J * 64 + c;
-    out[e] = (gi < n && gj < n) ? A[int64_t(gi) * N + gj] : 0.0;
+    out[ctile_idx(r, c)] = (gi < n && gj < n) ? A[int64_t(gi) * N + gj] : 0.0;
   }
 }
 
@@ -524,26 +569,27 @@ __global__ void k_axpy_m(int64_t n, const double *__restrict__ d, double *__rest
     x[c * ldx + i] += d[c * n + i];
 }
 
-// -------------------------------------------------------------- apply_P
-// Work item = (patch, row range [r0, r1)) of the packed upper triangle of the
-// patch inverse (rows ~balanced by element count) and a group of G right-hand
-// sides (so each packed entry streamed from HBM serves G columns).  The patch
-// right-hand sides are gathered into LDS; each wave takes every fourth row,
-// with the next row's entries loaded before the current row's products are
-// reduced; column j is owned by lane j % 64.  Row sums (j >= i) and the
-// mirrored column sums (j > i) of the chunk are combined in LDS and
-// scatter-added (atomics: chunks and patches overlap).
-template <int MAXJ, int G, typename T>
-__global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__ chunk_patch,
-                                                     const int32_t *__restrict__ chunk_rows,
-                                                     const int64_t *__restrict__ patch_col,
-                                                     const int64_t *__restrict__ col_ent,
-                                                     const int32_t *__restrict__ ent_dof,
-                                                     const double *__restrict__ ent_coef,
-                                                     const int64_t *__restrict__ inv_off,
-                                                     const T *__restrict__ inv, const double *__restrict__ r,
-                                                     int64_t ldr, double *__restrict__ z, int64_t ldz, int ncol,
-                                                     int maxsz, const PcgState *st) {
+// Patch solves z += R_p^T A_p^{-1} R_p r for a chunk of rows of one patch
+// and G right-hand sides (blockIdx.y), the inverse in the segmented layout
+// with V-element segments (16 bytes).  A wave works on 64 / L rows at a time,
+// L lanes per row; lane t owns the columns q V L + t V + [0, V) for q < NQ,
+// so each segment load is contiguous across the lanes of a row.  Row products
+// are summed over the L lanes (DPP); the mirrored column products stay in
+// registers until the end of the chunk.  Segments left of a row's first
+// stored segment or beyond the patch are not loaded.
+template <int V, int L, int NQ, int G, int D, typename T>
+__global__ __launch_bounds__(256) void k_patch_seg(const int64_t *__restrict__ chunk_patch,
+                                                   const int32_t *__restrict__ chunk_rows,
+                                                   const int64_t *__restrict__ patch_col,
+                                                   const int64_t *__restrict__ col_ent,
+                                                   const int32_t *__restrict__ ent_dof,
+                                                   const double *__restrict__ ent_coef,
+                                                   const int64_t *__restrict__ inv_off, const T *__restrict__ inv,
+                                                   const double *__restrict__ r, int64_t ldr, double *__restrict__ z,
+                                                   int64_t ldz, int ncol, const PcgState *st) {
+  constexpr int RPW = 64 / L;        // rows per wave step
+  constexpr int W = NQ * L * V;      // columns covered (LDS stride)
+  typedef T vecV __attribute__((ext_vector_type(V)));
   const int cbase = blockIdx.y * G;
   if (st) {
     bool any = false;
@@ -552,121 +598,211 @@ __global__ __launch_bounds__(256) void k_patch_apply(const int64_t *__restrict__
     if (!any) return;
   }
   extern __shared__ double sm[];
-  double *rp = sm;                  // G x maxsz gathered right-hand sides
-  double *yr = sm + G * maxsz;      // G x maxsz row products
-  double *yc = sm + 2 * G * maxsz;  // 4 x G x maxsz column partials
+  double *rp = sm;              // G x W gathered right-hand sides (zero padded)
+  double *yr = sm + G * W;      // G x W row products
+  double *yc = sm + 2 * G * W;  // 4 waves x G x W column products
   const int64_t p = chunk_patch[blockIdx.x];
   const int r0 = chunk_rows[2 * blockIdx.x], r1 = chunk_rows[2 * blockIdx.x + 1];
   const int64_t c0 = patch_col[p];
   const int m = int(patch_col[p + 1] - c0);
-  for (int t = threadIdx.x; t < G * m; t += 256) {
-    const int g = t / m, j = t - g * m;
+  const int mS = (m + V - 1) / V * V;
+  const T *A = inv + inv_off[p];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int slot = lane / L, t = lane % L;
+  auto load_row = [&](int i, bool ok, vecV *buf) {
+    const int si = i / V * V;
+    const T *row = A + seg_row_off(i, mS, V) - si;  // row[c] = stored entry of column c
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int c = q * V * L + t * V;
+      if (ok && c >= si && c < mS) buf[q] = *reinterpret_cast<const vecV *>(row + c);
+      else buf[q] = vecV(0);
+    }
+  };
+  // rows in flight: a ring of D row buffers, D - 1 loads ahead of the
+  // products; the first loads are issued before the gather of the patch
+  // right-hand sides
+  const int step = 4 * RPW;
+  const int niter = (r1 - r0 + step - 1) / step;
+  const int i0 = r0 + wave * RPW + slot;
+  vecV buf[D][NQ];
+#pragma unroll
+  for (int u = 0; u < D - 1; ++u) load_row(i0 + u * step, i0 + u * step < r1, buf[u]);
+  for (int t2 = threadIdx.x; t2 < G * W; t2 += 256) {
+    const int g = t2 / W, j = t2 - g * W;
     double sv = 0;
-    if (cbase + g < ncol) {
+    if (j < m && cbase + g < ncol) {
       const double *rc = r + int64_t(cbase + g) * ldr;
       for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) sv += ent_coef[e] * rc[ent_dof[e]];
     }
-    rp[g * maxsz + j] = sv;
-    yr[g * maxsz + j] = 0.0;
+    rp[t2] = sv;
+    yr[t2] = 0.0;
   }
   __syncthreads();
-  const T *A = inv + inv_off[p];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double cacc[MAXJ][G], cur[MAXJ], nxt[MAXJ];
+  double rj[NQ][G][V], cacc[NQ][G][V];
 #pragma unroll
-  for (int jb = 0; jb < MAXJ; ++jb)
+  for (int q = 0; q < NQ; ++q)
 #pragma unroll
-    for (int g = 0; g < G; ++g) cacc[jb][g] = 0.0;
-  auto load_row = [&](int i, double *buf) {
-    const T *row = A + int64_t(i) * m - int64_t(i) * (i - 1) / 2 - i;  // row[j] = A_ij, j >= i
+    for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int jb = 0; jb < MAXJ; ++jb) {
-      const int j = jb * 64 + lane;
-      buf[jb] = (j >= i && j < m) ? double(row[j]) : 0.0;
-    }
-  };
-  int i = r0 + wave;
-  if (i < r1) load_row(i, cur);
-  for (; i < r1; i += 4) {
-    if (i + 4 < r1) load_row(i + 4, nxt);
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const double ri = rp[g * maxsz + i];
-      double rs = 0.0;
-#pragma unroll
-      for (int jb = 0; jb < MAXJ; ++jb) {
-        const int j = jb * 64 + lane;
-        const double a = cur[jb];
-        const double rj = j < m ? rp[g * maxsz + j] : 0.0;
-        rs += a * rj;
-        cacc[jb][g] += (j > i) ? a * ri : 0.0;
+      for (int h = 0; h < V; ++h) {
+        rj[q][g][h] = rp[g * W + q * V * L + t * V + h];
+        cacc[q][g][h] = 0.0;
       }
-      rs = wave_sum(rs);
-      if (lane == 0) yr[g * maxsz + i] = rs;
+  for (int it = 0; it < niter; it += D) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int k = it + u;
+      if (k >= niter) break;  // uniform over the block
+      const int i = i0 + k * step;
+      const int ia = i + (D - 1) * step;
+      load_row(ia, ia < r1, buf[(u + D - 1) % D]);
+      const bool ok = i < r1;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const double ri = ok ? rp[g * W + i] : 0.0;
+        double rs = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+          for (int h = 0; h < V; ++h) {
+            const double a = double(buf[u][q][h]);
+            rs += a * rj[q][g][h];
+            cacc[q][g][h] += a * ri;
+          }
+        rs = group_sum<L>(rs);
+        if (ok && t == 0) yr[g * W + i] = rs;
+      }
     }
-#pragma unroll
-    for (int jb = 0; jb < MAXJ; ++jb) cur[jb] = nxt[jb];
   }
+  // column products: sum the row slots of the wave, then one LDS row per wave
 #pragma unroll
-  for (int jb = 0; jb < MAXJ; ++jb) {
-    const int j = jb * 64 + lane;
-    if (j < m)
+  for (int q = 0; q < NQ; ++q)
 #pragma unroll
-      for (int g = 0; g < G; ++g) yc[(wave * G + g) * maxsz + j] = cacc[jb][g];
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int h = 0; h < V; ++h) {
+        double v = cacc[q][g][h];
+        if (L <= 16) v += __shfl_xor(v, 16, 64);
+        if (L <= 32) v += __shfl_xor(v, 32, 64);
+        cacc[q][g][h] = v;
+      }
+  if (slot == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int h = 0; h < V; ++h) yc[(wave * G + g) * W + q * V * L + t * V + h] = cacc[q][g][h];
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < G * m; t += 256) {
-    const int g = t / m, j = t - g * m;
+  for (int t2 = threadIdx.x; t2 < G * m; t2 += 256) {
+    const int g = t2 / m, j = t2 - g * m;
     if (j < r0 || cbase + g >= ncol) continue;
-    const double y = yr[g * maxsz + j] + ((yc[(0 * G + g) * maxsz + j] + yc[(1 * G + g) * maxsz + j]) +
-                                          (yc[(2 * G + g) * maxsz + j] + yc[(3 * G + g) * maxsz + j]));
+    const double y = yr[g * W + j] + ((yc[(0 * G + g) * W + j] + yc[(1 * G + g) * W + j]) +
+                                      (yc[(2 * G + g) * W + j] + yc[(3 * G + g) * W + j]));
     double *zc = z + int64_t(cbase + g) * ldz;
     for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) atomicAdd(&zc[ent_dof[e]], ent_coef[e] * y);
   }
 }
 
-// coarse solve: upper 64 x 64 tiles (I <= J) of the packed inverse, one wave
-// per tile, G right-hand sides per pass.  Lane c keeps column c of the tile in
-// registers; A_IJ^T r_I is a lane-local sum, A_IJ r_J goes through an LDS
-// transpose.  rW / zW: npad x ncol.
-template <int G, typename TT>
-__global__ __launch_bounds__(64) void k_coarse_tiles(int NT, const TT *__restrict__ T,
+// FP32 copy of a patch inverse: from the V = 2 to the V = 4 segmented layout
+__global__ void k_seg_to_float(const int64_t *__restrict__ patch_col, const int64_t *__restrict__ off64,
+                               const int64_t *__restrict__ off32, const double *__restrict__ A,
+                               float *__restrict__ B) {
+  const int64_t p = blockIdx.x;
+  const int m = int(patch_col[p + 1] - patch_col[p]);
+  const int m2 = (m + 1) / 2 * 2, m4 = (m + 3) / 4 * 4;
+  const double *a = A + off64[p];
+  float *b = B + off32[p];
+  for (int i = 0; i < m; ++i) {
+    const int s2 = i / 2 * 2, s4 = i / 4 * 4;
+    const double *ra = a + seg_row_off(i, m2, 2) - s2;
+    float *rb = b + seg_row_off(i, m4, 4) - s4;
+    for (int c = s4 + threadIdx.x; c < m4; c += blockDim.x) rb[c] = (c >= i && c < m) ? float(ra[c]) : 0.0f;
+  }
+}
+
+// Coarse solve zW += A_W^{-1} rW with the inverse as packed upper 64 x 64
+// tiles (I <= J; diagonal tiles full).  A block takes tiles J in [J0, J1) of
+// tile row I, G right-hand sides: thread (c, ty) holds rows 16 ty .. 16 ty + 15
+// of column c of the tile.  Row products A_IJ rW_J stay in registers for the
+// whole strip (one lane reduction at the end); column products A_IJ^T rW_I
+// are summed over the four waves in LDS and added to zW_J per tile.
+template <int G, typename T>
+__global__ __launch_bounds__(256) void k_coarse_symv(int NT, int S, const T *__restrict__ tiles,
                                                      const double *__restrict__ rW, double *__restrict__ zW,
                                                      int npad, int ncol, const PcgState *st) {
-  const int cbase = blockIdx.y * G;
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const int I = blockIdx.x;
+  const int J0 = max(I, int(blockIdx.y) * S), J1 = min(NT, int(blockIdx.y + 1) * S);
+  if (J0 >= J1) return;
+  const int cbase = blockIdx.z * G;
   if (st) {
     bool any = false;
     for (int g = 0; g < G; ++g)
       if (cbase + g < ncol && !st[cbase + g].done) any = true;
     if (!any) return;
   }
-  __shared__ double tr[64][65];
-  const int64_t t = blockIdx.x;
-  int I = 0;
-  while (int64_t(I + 1) * NT - int64_t(I + 1) * I / 2 <= t) ++I;
-  const int J = int(t - (int64_t(I) * NT - int64_t(I) * (I - 1) / 2)) + I;
-  const int c = threadIdx.x;
-  const TT *tile = T + t * 4096;
-  double a[64];
+  __shared__ double cl[2][G][4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  double rI[G][16], acc[G][16];
+  const double *rc[G];
 #pragma unroll
-  for (int r = 0; r < 64; ++r) a[r] = tile[r * 64 + c];
   for (int g = 0; g < G; ++g) {
-    if (cbase + g >= ncol) break;
-    const double *rc = rW + int64_t(cbase + g) * npad;
-    double *zc = zW + int64_t(cbase + g) * npad;
-    const double rJc = rc[J * 64 + c];
-    double col = 0;
+    rc[g] = rW + int64_t(min(cbase + g, ncol - 1)) * npad;
 #pragma unroll
-    for (int r = 0; r < 64; ++r) {
-      col += a[r] * rc[I * 64 + r];
-      tr[r][c] = a[r] * rJc;
+    for (int k = 0; k < 16; ++k) {
+      rI[g][k] = cbase + g < ncol ? rc[g][I * 64 + ty * 16 + k] : 0.0;
+      acc[g][k] = 0.0;
+    }
+  }
+  const T *row = tiles + (int64_t(I) * NT - int64_t(I) * (I - 1) / 2 - I) * 4096 + ty * 1024 + tx * 2;
+  auto load = [&](int J, v2 *buf) {
+    const T *tp = row + int64_t(J) * 4096;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) buf[q] = *reinterpret_cast<const v2 *>(tp + q * 128);
+  };
+  v2 cur[8], nxt[8];
+  load(J0, cur);
+  int pb = 0;
+  for (int J = J0; J < J1; ++J) {
+    if (J + 1 < J1) load(J + 1, nxt);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const double rJ = rc[g][J * 64 + tx];
+      double colp = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double a0 = double(cur[q].x), a1 = double(cur[q].y);
+        acc[g][2 * q] += a0 * rJ;
+        acc[g][2 * q + 1] += a1 * rJ;
+        colp += a0 * rI[g][2 * q] + a1 * rI[g][2 * q + 1];
+      }
+      cl[pb][g][ty][tx] = colp;
     }
     __syncthreads();
-    double row = 0;
-    for (int cc = 0; cc < 64; ++cc) row += tr[c][cc];
-    atomicAdd(&zc[I * 64 + c], row);
-    if (I < J) atomicAdd(&zc[J * 64 + c], col);
-    __syncthreads();
+    if (J > I && ty == 0) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (cbase + g < ncol)
+          atomicAdd(&zW[int64_t(cbase + g) * npad + J * 64 + tx],
+                    (cl[pb][g][0][tx] + cl[pb][g][1][tx]) + (cl[pb][g][2][tx] + cl[pb][g][3][tx]));
+    }
+    pb ^= 1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
+  }
+  // row products: sum over the 64 columns (lanes); lane k keeps row 16 ty + k
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    double mine = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const double v = group_sum<64>(acc[g][k]);
+      if (tx == k) mine = v;
+    }
+    if (tx < 16 && cbase + g < ncol) atomicAdd(&zW[int64_t(cbase + g) * npad + I * 64 + ty * 16 + tx], mine);
   }
 }
 
@@ -683,10 +819,10 @@ __global__ void k_coarse_expand(int NT, const double *__restrict__ T, double *__
     double v;
     if (I <= J) {
       const int64_t t = int64_t(I) * NT - int64_t(I) * (I - 1) / 2 + (J - I);
-      v = T[t * 4096 + r * 64 + c];
+      v = T[t * 4096 + ctile_idx(r, c)];
     } else {
       const int64_t t = int64_t(J) * NT - int64_t(J) * (J - 1) / 2 + (I - J);
-      v = T[t * 4096 + c * 64 + r];
+      v = T[t * 4096 + ctile_idx(c, r)];
     }
     out[e] = v;
   }
@@ -760,8 +896,9 @@ __global__ __launch_bounds__(256) void k_patch_gemm(const int64_t *__restrict__ 
                                                     const int32_t *__restrict__ ent_dof,
                                                     const double *__restrict__ ent_coef,
                                                     const int64_t *__restrict__ inv_off,
-                                                    const double *__restrict__ inv, const double *__restrict__ r,
-                                                    int64_t ldr, double *__restrict__ z, int64_t ldz, int ncol,
+                                                    const double *__restrict__ inv, int E,
+                                                    const double *__restrict__ r, int64_t ldr,
+                                                    double *__restrict__ z, int64_t ldz, int ncol,
                                                     const PcgState *st) {
   const int64_t p = blockIdx.x;
   const int c0 = blockIdx.y * 64;
@@ -778,12 +915,13 @@ __global__ __launch_bounds__(256) void k_patch_gemm(const int64_t *__restrict__ 
   double *A = sm;              // MP x (MP + 1)
   double *R = sm + MP * (MP + 1);  // MP x 65 (row k, column c)
   const double *P = inv + inv_off[p];
+  const int mS = (m + E - 1) / E * E;
   for (int t = threadIdx.x; t < MP * MP; t += 256) {
     const int i = t / MP, j = t - i * MP;
     double v = 0.0;
     if (i < m && j < m) {
       const int a = min(i, j), b = max(i, j);
-      v = P[int64_t(a) * m - int64_t(a) * (a - 1) / 2 + (b - a)];
+      v = (a == b ? 2.0 : 1.0) * P[seg_row_off(a, mS, E) + b - a / E * E];
     }
     A[i * (MP + 1) + j] = v;
   }
@@ -1074,9 +1212,9 @@ void launch_chol_inverse(int64_t B, int N, double *A, double *Linv, int *status,
   hipLaunchKernelGGL(k_lauum, dim3(unsigned(int64_t(NB) * (NB + 1) / 2), unsigned(B)), dim3(256), 0, s, N, Linv, A);
 }
 
-void launch_pack_upper(int64_t B, int N, const int32_t *sizes, const int64_t *off, const double *Ainv,
-                       double *packed, hipStream_t s) {
-  hipLaunchKernelGGL(k_pack_upper, dim3(unsigned(B)), dim3(256), 0, s, N, sizes, off, Ainv, packed);
+void launch_pack_seg(int64_t B, int N, int E, const int32_t *sizes, const int64_t *off, const double *Ainv,
+                     double *packed, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_seg, dim3(unsigned(B)), dim3(256), 0, s, N, E, sizes, off, Ainv, packed);
 }
 
 void launch_pack_tiles(int N, int n, const double *Ainv, double *tiles, hipStream_t s) {
@@ -1132,24 +1270,73 @@ void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double 
 }
 
 // patch apply: largest G in {8,4,2,1} with G <= ncol, LDS <= 96 KB, MAXJ * G <= 32
-template <int MJ, typename T>
-static void patch_g(const PatchApply &pa, const T *inv, dim3 g1, int G, size_t lds_per_g, const double *r,
-                    int64_t ldr, double *z, int64_t ldz, int ncol, const PcgState *st, hipStream_t s) {
-  dim3 g(g1.x, unsigned((ncol + G - 1) / G));
-#define RZ_PG(GG)                                                                                                 \
-  hipLaunchKernelGGL((k_patch_apply<MJ, GG, T>), g, dim3(256), lds_per_g * GG, s, pa.chunk_patch, pa.chunk_rows, \
-                     pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, pa.inv_off, inv, r, ldr, z, ldz, ncol,     \
-                     pa.max_size, st)
-  if (G >= 8) RZ_PG(8);
-  else if (G >= 4) RZ_PG(4);
-  else if (G >= 2) RZ_PG(2);
-  else RZ_PG(1);
-#undef RZ_PG
+int64_t seg_size(int m, int V) {
+  const int64_t mS = (m + V - 1) / V * V;
+  return seg_row_off(m, mS, V);
+}
+
+void launch_seg_to_float(int64_t n_patches, const int64_t *patch_col, const int64_t *off64, const int64_t *off32,
+                         const double *A, float *B, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_to_float, dim3(unsigned(n_patches)), dim3(256), 0, s, patch_col, off64, off32, A, B);
+}
+
+// rows in flight per lane group: deeper for short rows
+template <int VQ, typename T>
+constexpr int patch_depth() {
+  return VQ <= 8 ? 4 : 2;
+}
+
+template <int V, int L, int NQ, int G, typename T>
+static void patch_seg_g(const PatchApply &pa, const int64_t *off, const T *inv, dim3 grid, size_t lds,
+                        const double *r, int64_t ldr, double *z, int64_t ldz, int ncol, const PcgState *st,
+                        hipStream_t s) {
+  constexpr int D = patch_depth<NQ * V, T>();
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_patch_seg<V, L, NQ, G, D, T>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_patch_seg<V, L, NQ, G, D, T>), grid, dim3(256), lds, s, pa.chunk_patch, pa.chunk_rows,
+                     pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, off, inv, r, ldr, z, ldz, ncol, st);
+}
+
+template <int V, int L, int NQ, typename T>
+static void patch_seg(const PatchApply &pa, const int64_t *off, const T *inv, const double *r, int64_t ldr,
+                      double *z, int64_t ldz, int ncol, const PcgState *st, hipStream_t s) {
+  constexpr int W = NQ * L * V;
+  constexpr int VQ = NQ * V;
+  const size_t lds_per_g = size_t(6) * W * sizeof(double);
+  int G = 4;
+  while (G > 1 && (G > ncol || lds_per_g * G > 96 * 1024 || VQ * G > 32)) G /= 2;
+  const dim3 grid(unsigned(pa.n_chunks), unsigned((ncol + G - 1) / G));
+  if (G == 4) patch_seg_g<V, L, NQ, (VQ <= 8 ? 4 : 1), T>(pa, off, inv, grid, lds_per_g * G, r, ldr, z, ldz, ncol, st, s);
+  else if (G == 2) patch_seg_g<V, L, NQ, (VQ <= 16 ? 2 : 1), T>(pa, off, inv, grid, lds_per_g * G, r, ldr, z, ldz, ncol, st, s);
+  else patch_seg_g<V, L, NQ, 1, T>(pa, off, inv, grid, lds_per_g, r, ldr, z, ldz, ncol, st, s);
+}
+
+// lanes per row and column stripes for the largest patch of a set
+template <typename T>
+static void patch_dispatch(const PatchApply &pa, const int64_t *off, const T *inv, const double *r, int64_t ldr,
+                           double *z, int64_t ldz, int ncol, const PcgState *st, hipStream_t s) {
+  constexpr int V = 16 / sizeof(T);
+  const int m = pa.max_size;
+  const int L = m <= 48 ? 16 : (m <= 160 ? 32 : 64);
+  const int mS = (m + V - 1) / V * V;
+  const int nq = (mS + V * L - 1) / (V * L);
+  const int NQ = nq <= 1 ? 1 : nq <= 2 ? 2 : nq <= 4 ? 4 : nq <= 8 ? 8 : 16;
+#define RZ_PQ(LL, QQ) \
+  if (L == LL && NQ == QQ) return patch_seg<V, LL, QQ, T>(pa, off, inv, r, ldr, z, ldz, ncol, st, s)
+  RZ_PQ(16, 1); RZ_PQ(16, 2); RZ_PQ(16, 4);
+  RZ_PQ(32, 1); RZ_PQ(32, 2); RZ_PQ(32, 4);
+  RZ_PQ(64, 1); RZ_PQ(64, 2); RZ_PQ(64, 4); RZ_PQ(64, 8); RZ_PQ(64, 16);
+#undef RZ_PQ
 }
 
 void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
                         const PcgState *st, hipStream_t s, bool lo) {
   if (pa.n_chunks == 0) return;
+  if (lo && pa.inv32) return patch_dispatch<float>(pa, pa.inv_off32, pa.inv32, r, ldr, z, ldz, ncol, st, s);
   if (ncol >= 8 && pa.max_size <= kSmallPatch) {
     const int MP = (pa.max_size + 15) & ~15;
     const size_t lds = size_t(MP * (MP + 1) + MP * 65) * sizeof(double);
@@ -1159,31 +1346,11 @@ void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, doub
       attr = true;
     }
     hipLaunchKernelGGL(k_patch_gemm, dim3(unsigned(pa.n_patches), unsigned((ncol + 63) / 64)), dim3(256), lds, s,
-                       pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, pa.inv_off, pa.inv, r, ldr, z, ldz, ncol,
-                       st);
+                       pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, pa.inv_off, pa.inv, 2, r, ldr, z, ldz,
+                       ncol, st);
     return;
   }
-  const size_t lds_per_g = size_t(6) * pa.max_size * sizeof(double);
-  const int nj = (pa.max_size + 63) / 64;
-  const int mj = nj <= 1 ? 1 : nj <= 2 ? 2 : nj <= 4 ? 4 : nj <= 8 ? 8 : nj <= 14 ? 14 : 24;
-  int G = 8;
-  while (G > 1 && (G > ncol || lds_per_g * G > 96 * 1024 || mj * G > 32)) G /= 2;
-  const dim3 g1(unsigned(pa.n_chunks));
-#define RZ_PD(T, INV)                                                              \
-  switch (mj) {                                                                    \
-    case 1: patch_g<1, T>(pa, INV, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;   \
-    case 2: patch_g<2, T>(pa, INV, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;   \
-    case 4: patch_g<4, T>(pa, INV, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;   \
-    case 8: patch_g<8, T>(pa, INV, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break;   \
-    case 14: patch_g<14, T>(pa, INV, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break; \
-    default: patch_g<24, T>(pa, INV, g1, G, lds_per_g, r, ldr, z, ldz, ncol, st, s); break; \
-  }
-  if (lo && pa.inv32) {
-    RZ_PD(float, pa.inv32)
-  } else {
-    RZ_PD(double, pa.inv)
-  }
-#undef RZ_PD
+  patch_dispatch<double>(pa, pa.inv_off, pa.inv, r, ldr, z, ldz, ncol, st, s);
 }
 
 void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hipStream_t s, bool lo) {
@@ -1197,20 +1364,17 @@ void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hi
                        ca.zW, npad, ncol, st);
     return;
   }
-  int G = 8;
-  while (G > 1 && G > ncol) G /= 2;
-  dim3 g(nt, unsigned((ncol + G - 1) / G));
+  // strips of S tiles per block, >= ~2048 blocks where the matrix allows
+  const int S = int(std::max<int64_t>(1, std::min<int64_t>(16, int64_t(nt) / 2048)));
+  const int G = ncol >= 2 ? 2 : 1;
+  const dim3 g(unsigned(ca.NT), unsigned((ca.NT + S - 1) / S), unsigned((ncol + G - 1) / G));
 #define RZ_CT(GG, TT, TI) \
-  hipLaunchKernelGGL((k_coarse_tiles<GG, TT>), g, dim3(64), 0, s, ca.NT, TI, ca.rW, ca.zW, npad, ncol, st)
+  hipLaunchKernelGGL((k_coarse_symv<GG, TT>), g, dim3(256), 0, s, ca.NT, S, TI, ca.rW, ca.zW, npad, ncol, st)
   if (lo && ca.tiles32) {
-    if (G == 8) RZ_CT(8, float, ca.tiles32);
-    else if (G == 4) RZ_CT(4, float, ca.tiles32);
-    else if (G == 2) RZ_CT(2, float, ca.tiles32);
+    if (G == 2) RZ_CT(2, float, ca.tiles32);
     else RZ_CT(1, float, ca.tiles32);
   } else {
-    if (G == 8) RZ_CT(8, double, ca.tiles);
-    else if (G == 4) RZ_CT(4, double, ca.tiles);
-    else if (G == 2) RZ_CT(2, double, ca.tiles);
+    if (G == 2) RZ_CT(2, double, ca.tiles);
     else RZ_CT(1, double, ca.tiles);
   }
 #undef RZ_CT

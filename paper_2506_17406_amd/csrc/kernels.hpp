@@ -28,8 +28,9 @@ void launch_patch_assemble(int64_t n_items, const int32_t *item_patch, const int
                            double *A, hipStream_t s);
 // batched blocked Cholesky + inverse of B uniform N x N SPD matrices (N % 32 == 0)
 void launch_chol_inverse(int64_t B, int N, double *A, double *Linv, int *status, hipStream_t s);
-void launch_pack_upper(int64_t B, int N, const int32_t *sizes, const int64_t *off, const double *Ainv,
-                       double *packed, hipStream_t s);
+// patch inverses in the segmented upper layout (see seg_size)
+void launch_pack_seg(int64_t B, int N, int E, const int32_t *sizes, const int64_t *off, const double *Ainv,
+                     double *packed, hipStream_t s);
 void launch_pack_tiles(int N, int n, const double *Ainv, double *tiles, hipStream_t s);
 
 // ---- hot path (multi-column: column c of a vector at base + c * ld)
@@ -47,6 +48,15 @@ struct ApplyATables {
 void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
                     const PcgState *st, hipStream_t s, bool lo = false);
 
+// Patch inverse storage: row i of a patch of size m holds the columns
+// [V floor(i/V), V ceil(m/V)) -- zero left of the diagonal and beyond m, the
+// diagonal halved -- so every row is a whole number of aligned V-element
+// (16-byte) segments: V = 2 for the FP64 inverses, V = 4 for their FP32 copies.
+constexpr int kMaxPatch = 2048;
+int64_t seg_size(int m, int V);  // stored entries of one patch
+void launch_seg_to_float(int64_t n_patches, const int64_t *patch_col, const int64_t *off64, const int64_t *off32,
+                         const double *A, float *B, hipStream_t s);
+
 struct PatchApply {
   int64_t n_patches, n_chunks;
   int max_size;
@@ -55,8 +65,9 @@ struct PatchApply {
   const int64_t *patch_col, *col_ent, *inv_off;
   const int32_t *ent_dof;
   const double *ent_coef;
-  const double *inv;        // packed upper rows per patch
-  const float *inv32;       // FP32 copy (mixed precision) or null
+  const double *inv;        // segmented upper rows per patch (V = 2)
+  const float *inv32;       // FP32 copy (V = 4) for mixed precision, or null
+  const int64_t *inv_off32; // its patch offsets
 };
 struct CoarseApply {
   int nW, NT;               // coarse size, tiles per side
