@@ -1,8 +1,8 @@
-"""The interior-interface split Schwarz preconditioners of Sec. 6.
+"""The interior-interface split Schwarz preconditioners of Sec. 6, in the
+additive form of the theory and in the symmetric multiplicative hybrid form
+the experiments use (Sec. 7.1).
 
-Additive form (reading R8: the theory of Sec. 6 is stated for the additive
-Schwarz method; the experiments' symmetric multiplicative hybrid is a
-separate variant):
+Additive form (AdditiveSchwarz):
 
     P^{-1} r = D_I^{-1} r_I + sum_m R_m^T A_m^{-1} R_m r + R_W^T A_W^{-1} R_W r
 
@@ -20,6 +20,18 @@ separate variant):
   an exact solve with the principal submatrix A[W, W] in place of the
   paper's geometric multigrid V-cycle.
 
+Hybrid form (HybridSchwarz, Sec. 7.1, eq:generic-subspace-splitting-mult):
+the three groups X_1 = X^k_I (point-Jacobi), X_2 = X^k_Gamma (the additive
+interface patch solver above, coarse space excluded) and X_3 = W^k (exact)
+are applied multiplicatively in the order X_1, X_2, X_3, X_2, X_1, each
+correction z += rho_m^{-1} B_m (r - A z).  The weight of a group is
+rho_m = (lambda_min + 3 lambda_max) / 4 from the extreme Ritz values of 10
+CG steps on A restricted to X_m, preconditioned by B_m, with a random
+right-hand side.  Reading R17: the right-hand side is 2u - 1 per subspace
+dof (ascending global order) with u from SplitMix64 seeded SEED_INTERIOR /
+SEED_INTERFACE; the CG steps stop early once ||r|| <= 1e-12 ||b||; an empty
+subspace has rho = 1; the exact coarse solver has rho_3 = 1.
+
 The discrete gradient G_V maps the CG_p vertex-star dofs into Ned_p:
 grad of the vertex function lambda_V is sum_E (+1 if V is the larger vertex
 of E else -1) times the Whitney function of E, and grad of a CG type-I
@@ -29,6 +41,12 @@ function is the Ned type-II function with the same entity and index
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+
+from .pcg import lanczos_extremes, pcg
+from .simplex import splitmix64_stream
+
+SEED_INTERIOR = 0x5EED1000
+SEED_INTERFACE = 0x5EED2000
 
 
 def interior_dofs(top):
@@ -138,3 +156,76 @@ class AdditiveSchwarz:
     def sizes(self):
         s = [len(i) for i, _ in self.patches] + [G.shape[1] for G, _ in self.potentials]
         return s
+
+
+def subspace_extremes(A, idx, solve, seed, steps=10):
+    """Estimates (lambda_min, lambda_max) of the generalized eigenproblem
+    a(u, v) = lambda a_m(u, v) on the subspace spanned by the dofs idx: the
+    extreme Ritz values of `steps` CG iterations on A[idx, idx]
+    preconditioned by `solve` (acting on full-length vectors supported on
+    idx) with a SplitMix64 right-hand side (Sec. 7.1)."""
+    if len(idx) == 0:
+        return 1.0, 1.0
+    n = A.shape[0]
+    gen = splitmix64_stream(seed)
+    b = np.array([2.0 * next(gen) - 1.0 for _ in range(len(idx))])
+    Am = A[idx][:, idx]
+
+    def Bm(r):
+        f = np.zeros(n)
+        f[idx] = r
+        return solve(f)[idx]
+
+    _, info = pcg(lambda v: Am @ v, Bm, b, rtol=1e-12, maxit=steps)
+    return lanczos_extremes(info["alphas"], info["betas"])
+
+
+def subspace_weight(A, idx, solve, seed, steps=10):
+    """rho = (lambda_min + 3 lambda_max) / 4 from subspace_extremes."""
+    lo, hi = subspace_extremes(A, idx, solve, seed, steps)
+    return (lo + 3.0 * hi) / 4.0
+
+
+class HybridSchwarz:
+    """Symmetric multiplicative hybrid of the three groups of the
+    interior-interface split (Sec. 7.1): z = 0, then for m in 1, 2, 3, 2, 1:
+    z += rho_m^{-1} B_m (r - A z)."""
+
+    def __init__(self, A, top, family, additive=None):
+        self.A = A
+        self.add = additive if additive is not None else AdditiveSchwarz(A, top, family)
+        n = top.n_dofs
+        mask = np.zeros(n, dtype=bool)
+        mask[self.add.I] = True
+        self.Gamma = np.flatnonzero(~mask)
+        self.rho_I = subspace_weight(A, self.add.I, self.B_interior, SEED_INTERIOR)
+        self.rho_Gamma = subspace_weight(A, self.Gamma, self.B_interface, SEED_INTERFACE)
+
+    def B_interior(self, r):
+        z = np.zeros_like(r)
+        z[self.add.I] = r[self.add.I] / self.add.dI
+        return z
+
+    def B_interface(self, r):
+        z = np.zeros_like(r)
+        for idx, F in self.add.patches:
+            z[idx] += sla.cho_solve(F, r[idx])
+        for G, F in self.add.potentials:
+            z += G @ sla.cho_solve(F, G.T @ r)
+        return z
+
+    def B_coarse(self, r):
+        z = np.zeros_like(r)
+        z[self.add.W] = sla.cho_solve(self.add.coarse, r[self.add.W])
+        return z
+
+    def groups(self):
+        return [(self.B_interior, self.rho_I), (self.B_interface, self.rho_Gamma), (self.B_coarse, 1.0)]
+
+    def apply(self, r):
+        (b1, w1), (b2, w2), (b3, w3) = self.groups()
+        z = np.zeros_like(r)
+        for B, w in ((b1, w1), (b2, w2), (b3, w3), (b2, w2), (b1, w1)):
+            z = z + B(r - self.A @ z) / w
+        return z
+
