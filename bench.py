@@ -44,6 +44,9 @@ def parse():
                          "12^3x6 mesh with 64 right-hand sides, one batched solve vs 64 single solves; mixed: "
                          "H(curl) Ned_6 on the 16^3x6 mesh, FP32 refinement vs plain FP64 PCG")
     ap.add_argument("--inner-rtol", type=float, default=0.0)
+    ap.add_argument("--pc", choices=["hybrid", "additive"], default="hybrid",
+                    help="preconditioner form: the symmetric multiplicative hybrid of the paper's experiments "
+                         "(default) or the additive Schwarz form")
     ap.add_argument("--nrhs", type=int, default=64)
     return ap.parse_args()
 
@@ -58,7 +61,7 @@ def multirhs(args):
     torch.cuda.set_device(0)
     X, C = kuhn_mesh(12, 3, jitter=0.1, seed=6)
     t0 = time.perf_counter()
-    prob = rz.Problem(X, C, 5, "RT")
+    prob = rz.Problem(X, C, 5, "RT", pc=args.pc)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     nr = args.nrhs
@@ -92,7 +95,7 @@ def multirhs(args):
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"H(div) RT_5 Riesz map, jittered Kuhn 12^3x6 = 10368 tets, {nr} right-hand sides "
-                               f"solved together, rtol 1e-10", "dofs": prob.n_dofs, "n_rhs": nr,
+                               f"solved together, rtol 1e-10", "dofs": prob.n_dofs, "n_rhs": nr, "preconditioner": args.pc,
                    "setup_s": round(t_setup, 2)},
         "iterations": {"min": min(its), "max": max(its)},
         "max_rel_residual": max(i["rel_residual"] for i in infos),
@@ -128,11 +131,11 @@ def mixed(args):
     stream = torch.cuda.current_stream()
     X, C = kuhn_mesh(16, 3, jitter=0.1, seed=4)
     t0 = time.perf_counter()
-    pm = rz.Problem(X, C, 6, "Ned", precision="fp32-ir", inner_rtol=args.inner_rtol)
+    pm = rz.Problem(X, C, 6, "Ned", precision="fp32-ir", inner_rtol=args.inner_rtol, pc=args.pc)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     print(f"setup Ned6 n=16 (FP64 + FP32 copies): {pm.n_dofs} dofs in {t_setup:.1f}s", file=sys.stderr, flush=True)
-    p64 = rz.Problem(X, C, 6, "Ned")
+    p64 = rz.Problem(X, C, 6, "Ned", pc=args.pc)
     torch.cuda.synchronize()
     print("setup FP64 handle done", file=sys.stderr, flush=True)
     b = torch.from_numpy(load_vectors(pm.n_dofs, 5)[:, 0]).cuda()
@@ -180,6 +183,7 @@ def mixed(args):
         "dtype": "f32 applies, f64 refinement", "data": "synthetic",
         "config": {"workload": "H(curl) Ned_6 Riesz map, jittered Kuhn 16^3x6 = 24576 tets, FP32 iterative "
                                "refinement to true FP64 rel. residual 1e-10", "dofs": pm.n_dofs,
+                   "preconditioner": args.pc,
                    "setup_s": round(t_setup, 2)},
         "roofline": {"kernel": "apply_A FP32 (Ned6)", "bound": "mfma", "achieved": tf32, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": tf32 / PEAK_FP32_TFLOPS, "traffic": None,
@@ -195,7 +199,7 @@ def mixed(args):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline():
+def cpu_baseline(pc="hybrid"):
     """The oracle, as it stands, on a bounded sample of the workload: the
     H(grad) p=4 and H(curl) p=3 problems of the sweep (same mesh and load
     vectors); CPU DOF/s = dofs / PCG time, setup excluded."""
@@ -204,14 +208,14 @@ def cpu_baseline():
     from oracle.mesh import Topology
     from oracle.operator import all_cell_matrices, assemble
     from oracle.pcg import pcg
-    from oracle.precond import AdditiveSchwarz
+    from oracle.precond import AdditiveSchwarz, HybridSchwarz
     from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
     X, C = kuhn_mesh(8, 3, jitter=0.1, seed=2)
     dofs, t = 0, 0.0
     for fam, p in (("CG", 4), ("Ned", 3)):
         top = Topology(X, C, element(3, fam, p))
         A = assemble(top, all_cell_matrices(top.el, top))
-        P = AdditiveSchwarz(A, top, fam)
+        P = HybridSchwarz(A, top, fam) if pc == "hybrid" else AdditiveSchwarz(A, top, fam)
         b = load_vectors(top.n_dofs, 3)[:, 0]
         with threadpool_limits(1):
             t0 = time.perf_counter()
@@ -219,9 +223,9 @@ def cpu_baseline():
             t += time.perf_counter() - t0
         dofs += top.n_dofs
     return {"value": dofs / t, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle PCG (NumPy/SciPy FP64, assembled CSR SpMV, dense Cholesky patch solves, BLAS "
-                      "limited to 1 thread) on the H(grad) p=4 and H(curl) p=3 problems of the same sweep "
-                      "(129,857 dofs); setup excluded",
+            "sample": f"oracle PCG with the {pc} preconditioner (NumPy/SciPy FP64, assembled CSR SpMV, dense "
+                      "Cholesky patch solves, BLAS limited to 1 thread) on the H(grad) p=4 and H(curl) p=3 problems "
+                      "of the same sweep (96,873 dofs); setup excluded",
             "seconds": t}
 
 
@@ -249,7 +253,7 @@ def main():
     for fam in spaces:
         for p in degrees:
             t0 = time.perf_counter()
-            prob = rz.Problem(X, C, p, fam)
+            prob = rz.Problem(X, C, p, fam, pc=args.pc)
             b = torch.from_numpy(load_vectors(prob.n_dofs, 3)[:, 0]).cuda()
             x = torch.zeros_like(b)
             torch.cuda.synchronize()
@@ -317,7 +321,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3D plain FP64 PCG sweep: H(grad)/H(curl)/H(div) x p={args.degrees} on the "
                                f"jittered Kuhn mesh {args.n}^3x6 = {6 * args.n ** 3} tets, rtol 1e-10",
-                   "problems": len(probs), "total_dofs": total_dofs, "setup_s": round(t_setup, 2)},
+                   "problems": len(probs), "total_dofs": total_dofs, "setup_s": round(t_setup, 2),
+                   "preconditioner": args.pc},
         "roofline": {"kernel": f"apply_A ({big['fam']}{big['p']})", "bound": "mfma",
                      "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / PEAK_FP64_TFLOPS, "traffic": None,
@@ -326,7 +331,7 @@ def main():
         "per_problem": per,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"] = cpu_baseline(args.pc)
     print(json.dumps(line), flush=True)
 
 

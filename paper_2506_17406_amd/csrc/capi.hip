@@ -57,6 +57,11 @@ struct rz_problem {
   int max_iter = 1000;
   int precision = RZ_FP64;
   double inner_rtol = 1e-4;
+  // preconditioner form; hybrid: group weights and local column ranges
+  int pc = RZ_PC_ADDITIVE;
+  double rho_I = 1.0, rho_G = 1.0;
+  int col_int = 0;            // local interior columns [col_int, n)
+  int col_w0 = 0, col_w1 = 0; // local columns of the entities that carry the Whitney dofs
   // device data
   std::vector<void *> mem;
   double *R = nullptr, *Afrag = nullptr, *w = nullptr, *dinv = nullptr;
@@ -74,6 +79,8 @@ struct rz_problem {
   // refinement: outer state (true residual), outer residual and correction
   rz::PcgState *sto = nullptr, *sto_host = nullptr;
   double *ro = nullptr, *dx = nullptr;
+  // hybrid sweep: tracked residual and group correction
+  double *hs = nullptr, *hd = nullptr;
   rz::CoarseFold fold{};
   std::vector<rz::PatchApply> pas;  // patch sets for the launchers
 
@@ -101,6 +108,7 @@ struct rz_problem {
     st_host = sto_host = nullptr;
     sto = nullptr;
     ro = dx = nullptr;
+    hs = hd = nullptr;
     ws_cols = 0;
   }
   ~rz_problem() {
@@ -350,6 +358,9 @@ void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
 
 }  // namespace
 
+static void ensure_ws(rz_problem *P, int ncol);
+static void estimate_weights(rz_problem *P, hipStream_t s);
+
 extern "C" {
 
 const char *rz_last_error(void) { return g_err.c_str(); }
@@ -375,6 +386,8 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     if (!(opts->inner_rtol < 1.0)) return fail(RZ_ERR_ARG, "inner_rtol must be below 1");
     P->precision = opts->precision;
     if (opts->inner_rtol > 0.0) P->inner_rtol = opts->inner_rtol;
+    if (opts->pc != RZ_PC_ADDITIVE && opts->pc != RZ_PC_HYBRID) return fail(RZ_ERR_ARG, "unknown preconditioner");
+    P->pc = opts->pc;
   }
   P->fam = space == RZ_HGRAD ? rz::FAM_CG : (space == RZ_HCURL ? rz::FAM_NED : rz::FAM_RT);
   try {
@@ -449,7 +462,23 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     P->fold.off = P->top.offset[P->k];
     P->fold.N = P->el.per_entity[P->k];
     P->fold.span = P->top.n_ent[P->k] * P->fold.N;
+    // local column ranges of the hybrid sweep's restricted applies (the
+    // element numbering is entity-major, so each range is contiguous)
+    {
+      int w0 = n, w1 = 0;
+      for (int i = 0; i < n; ++i)
+        if (P->el.dofs[i].entity_dim == P->k) w0 = std::min(w0, i), w1 = std::max(w1, i + 1);
+      P->col_int = n - int(loc_int.size());
+      P->col_w0 = w0 < w1 ? w0 : 0;
+      P->col_w1 = w0 < w1 ? w1 : 0;
+      for (int i = 0; i < n; ++i) {
+        const bool in_int = P->el.dofs[i].entity_dim == d, in_w = i >= P->col_w0 && i < P->col_w1;
+        if (in_int != (i >= P->col_int) || in_w != (P->el.dofs[i].entity_dim == P->k))
+          throw RzError{RZ_ERR_UNSUPPORTED, "element numbering is not entity-major"};
+      }
+    }
     HIPCHK(hipStreamSynchronize(s));
+    if (P->pc == RZ_PC_HYBRID) estimate_weights(P.get(), s);
   } catch (const RzError &e) {
     return fail(e.code, e.msg);
   } catch (const std::invalid_argument &e) {
@@ -469,6 +498,14 @@ int rz_sizes(const rz_problem *P, int64_t *n_dofs, int64_t *n_interior, int32_t 
   if (n_interior) *n_interior = P->top.n_interior;
   if (n_loc) *n_loc = P->el.n;
   if (Q) *Q = P->el.Q;
+  return RZ_OK;
+}
+
+int rz_pc_weights(const rz_problem *P, double *rho) {
+  if (!P || !rho) return fail(RZ_ERR_ARG, "null argument");
+  rho[0] = P->rho_I;
+  rho[1] = P->rho_G;
+  rho[2] = 1.0;
   return RZ_OK;
 }
 
@@ -502,6 +539,10 @@ static void ensure_ws(rz_problem *P, int ncol) {
   P->ca.rW = static_cast<double *>(alloc(sizeof(double) * npad * ncol));
   P->ca.zW = static_cast<double *>(alloc(sizeof(double) * npad * ncol));
   P->fold.zW = P->ca.zW;
+  if (P->pc == RZ_PC_HYBRID) {
+    P->hs = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
+    P->hd = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
+  }
   if (P->precision != RZ_FP64) {
     P->sto = static_cast<rz::PcgState *>(alloc(sizeof(rz::PcgState) * ncol));
     HIPCHK(hipHostMalloc((void **)&P->sto_host, sizeof(rz::PcgState) * ncol, hipHostMallocDefault));
@@ -517,6 +558,119 @@ static void ensure_ws(rz_problem *P, int ncol) {
     HIPCHK(hipDeviceSynchronize());
     P->ca.full = full;
   }
+}
+
+// Symmetric multiplicative hybrid (Sec. 7.1): groups X_I (point-Jacobi),
+// X_Gamma (additive interface patches) and W (exact coarse solve), swept
+// I, Gamma, W, Gamma, I with z += rho_m^{-1} B_m (b - A z).  The residual
+// s = r - A z is tracked: each correction d is applied to A restricted to
+// the local columns it lives on (interior, interface, or the entities that
+// carry the Whitney dofs) and subtracted from s.  With st the first kernel
+// also takes the PCG convergence test (partR: block partials of ||r||^2).
+static void hybrid_apply(rz_problem *P, const double *r, int64_t ldr, double *z, int64_t ldz, int nc,
+                         rz::PcgState *st, const double *partR, int RB, bool lo, hipStream_t s) {
+  const int64_t nd = P->top.n_dofs;
+  const int n = P->el.n;
+  const double w1 = 1.0 / P->rho_I, w2 = 1.0 / P->rho_G;
+  double *sres = P->hs, *d = P->hd;
+  rz::launch_hyb_init(nd, P->off_I, P->dinv, w1, r, ldr, z, ldz, sres, partR, RB, nc, st, s);
+  if (P->col_int < n) rz::launch_apply_A(P->at, z, ldz, sres, nd, nc, st, s, lo, P->col_int, n, -1.0);
+  auto interface = [&]() {
+    rz::launch_fill(d, nd, nd, nc, st, s);
+    for (auto &pa : P->pas) rz::launch_patch_apply(pa, sres, nd, d, nd, nc, st, s, lo, w2);
+    rz::launch_add(nd, d, z, ldz, nc, st, s);
+    rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, lo, 0, P->col_int, -1.0);
+  };
+  interface();
+  rz::launch_coarse_gather(P->ca, sres, nd, nc, s);
+  rz::launch_coarse_tiles(P->ca, nc, st, s, lo);
+  rz::launch_fill(d, nd, nd, nc, st, s);
+  rz::launch_coarse_scatter2(P->ca, nd, d, z, ldz, nc, st, s);
+  rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, lo, P->col_w0, P->col_w1, -1.0);
+  interface();
+  rz::launch_jacobi_add(nd, P->off_I, P->dinv, w1, sres, z, ldz, nc, st, s);
+}
+
+static double host_dot(rz_problem *P, const double *a, const double *b, hipStream_t s) {
+  const int RB = 64;
+  const rz::CoarseFold nofold{nullptr, 0, 0, 1};
+  rz::launch_dot(P->top.n_dofs, a, P->top.n_dofs, b, P->top.n_dofs, nofold, P->ca.NT * 64, P->partA, RB, 1, nullptr, s);
+  double part[RB];
+  HIPCHK(hipMemcpyAsync(part, P->partA, sizeof(part), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double v = 0.0;
+  for (int i = 0; i < RB; ++i) v += part[i];
+  return v;
+}
+
+// Weights rho = (lambda_min + 3 lambda_max) / 4 of the interior and
+// interface groups (Sec. 7.1): extreme Ritz values of up to 10 CG steps on A
+// restricted to the group's dofs [lo, hi), preconditioned by the group's
+// solver, from b = 2u - 1 with u from SplitMix64 (seed 0x5EED1000 interior,
+// 0x5EED2000 interface) per dof in ascending order; the steps stop early
+// once ||r|| <= 1e-12 ||b||.  An empty group has rho = 1.
+static double group_weight(rz_problem *P, int64_t lo, int64_t hi, uint64_t seed, bool interior, hipStream_t s) {
+  const int64_t nd = P->top.n_dofs;
+  if (hi <= lo) return 1.0;
+  std::vector<double> hb(nd, 0.0);
+  uint64_t state = seed;
+  for (int64_t i = lo; i < hi; ++i) {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t zz = state;
+    zz = (zz ^ (zz >> 30)) * 0xBF58476D1CE4E5B9ull;
+    zz = (zz ^ (zz >> 27)) * 0x94D049BB133111EBull;
+    zz ^= zz >> 31;
+    hb[i] = 2.0 * (double(zz >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+  }
+  double *r = P->r, *z = P->z, *p = P->pv, *q = P->Ap;
+  HIPCHK(hipMemcpy(r, hb.data(), nd * 8, hipMemcpyHostToDevice));
+  auto apply_M = [&]() {
+    rz::launch_fill(z, nd, nd, 1, nullptr, s);
+    if (interior) {
+      rz::launch_jacobi_add(nd, P->off_I, P->dinv, 1.0, r, z, nd, 1, nullptr, s);
+    } else {
+      for (auto &pa : P->pas) rz::launch_patch_apply(pa, r, nd, z, nd, 1, nullptr, s, false, 1.0);
+      rz::launch_mask(nd, lo, hi, z, s);
+    }
+  };
+  const double bb = host_dot(P, r, r, s);
+  apply_M();
+  HIPCHK(hipMemcpyAsync(p, z, nd * 8, hipMemcpyDeviceToDevice, s));
+  double rz = host_dot(P, r, z, s);
+  std::vector<double> al, be;
+  for (int it = 0; it < 10 && rz > 0.0; ++it) {
+    rz::launch_fill(q, nd, nd, 1, nullptr, s);
+    rz::launch_apply_A(P->at, p, nd, q, nd, 1, nullptr, s);
+    rz::launch_mask(nd, lo, hi, q, s);
+    const double pq = host_dot(P, p, q, s);
+    if (!(pq > 0.0)) throw RzError{RZ_ERR_NOT_SPD, "weight estimate: p^T A p <= 0"};
+    const double a = rz / pq;
+    al.push_back(a);
+    rz::launch_axpby(nd, -a, q, 1.0, r, s);
+    if (host_dot(P, r, r, s) <= 1e-24 * bb) break;
+    apply_M();
+    const double rz_new = host_dot(P, r, z, s);
+    be.push_back(rz_new / rz);
+    rz = rz_new;
+    rz::launch_axpby(nd, 1.0, z, be.back(), p, s);
+  }
+  const int k = int(al.size());
+  if (k == 0) return 1.0;
+  rz::Dense T(k, k);
+  for (int j = 0; j < k; ++j) {
+    T(j, j) = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j > 0) T(j, j - 1) = T(j - 1, j) = std::sqrt(be[j - 1]) / al[j - 1];
+  }
+  std::vector<double> ev;
+  rz::Dense V;
+  rz::sym_eig(T, ev, V);
+  return (ev.front() + 3.0 * ev.back()) / 4.0;
+}
+
+static void estimate_weights(rz_problem *P, hipStream_t s) {
+  ensure_ws(P, 1);
+  P->rho_I = group_weight(P, P->off_I, P->top.n_dofs, 0x5EED1000ull, true, s);
+  P->rho_G = group_weight(P, 0, P->off_I, 0x5EED2000ull, false, s);
 }
 
 static int apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream,
@@ -543,8 +697,11 @@ static int apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int
   } catch (const RzError &e) {
     return fail(e.code, e.msg);
   }
-  rz::launch_apply_P(P->pas.data(), int(P->pas.size()), P->ca, P->top.n_dofs, P->off_I, P->dinv, r, ld, z, ld, n_rhs,
-                     s, lo);
+  if (P->pc == RZ_PC_HYBRID)
+    hybrid_apply(P, r, ld, z, ld, n_rhs, nullptr, nullptr, 0, lo, s);
+  else
+    rz::launch_apply_P(P->pas.data(), int(P->pas.size()), P->ca, P->top.n_dofs, P->off_I, P->dinv, r, ld, z, ld,
+                       n_rhs, s, lo);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RZ_ERR_DEVICE, hipGetErrorString(e));
   return RZ_OK;
@@ -605,7 +762,12 @@ static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int6
     rz::launch_pcg_start(P->partB, P->partR, RB, tol * tol, maxit, P->st, nc, s, outer);
   }
   // z = P^{-1} r, (r, z), p = z, Ap = 0
-  rz::launch_apply_P(P->pas.data(), int(P->pas.size()), P->ca, nd, P->off_I, P->dinv, P->r, nd, P->z, nd, nc, s, lo);
+  const bool hyb = P->pc == RZ_PC_HYBRID;
+  if (hyb)
+    hybrid_apply(P, P->r, nd, P->z, nd, nc, nullptr, nullptr, RB, lo, s);
+  else
+    rz::launch_apply_P(P->pas.data(), int(P->pas.size()), P->ca, nd, P->off_I, P->dinv, P->r, nd, P->z, nd, nc, s,
+                       lo);
   rz::launch_dot(nd, P->r, nd, P->z, nd, nofold, npad, P->partZ, RB, nc, P->st, s);
   rz::launch_copy(nd, P->z, nd, P->pv, nd, nc, s);
   rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
@@ -618,6 +780,13 @@ static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int6
       rz::launch_apply_A(P->at, P->pv, nd, P->Ap, nd, nc, P->st, s, lo);
       rz::launch_dot(nd, P->pv, nd, P->Ap, nd, nofold, npad, P->partA, RB, nc, P->st, s);
       rz::launch_update_xr(nd, x, ldx, P->r, P->pv, P->Ap, P->partZ, P->partA, P->partR, RB, nc, P->st, s);
+      if (hyb) {
+        // convergence test and the hybrid sweep z = B r
+        hybrid_apply(P, P->r, nd, P->z, nd, nc, P->st, P->partR, RB, lo, s);
+        rz::launch_dot(nd, P->r, nd, P->z, nd, nofold, npad, P->partZ, RB, nc, P->st, s);
+        rz::launch_update_p(nd, P->pv, P->z, nofold, npad, P->Ap, P->partZ, RB, nc, P->st, s);
+        continue;
+      }
       // convergence test, then z = P^{-1} r with the coarse part left in zW
       rz::launch_check_jacobi(nd, P->off_I, P->dinv, P->r, P->z, P->ca, P->partR, RB, nc, P->st, s);
       for (auto &pa : P->pas) rz::launch_patch_apply(pa, P->r, nd, P->z, nd, nc, P->st, s, lo);

@@ -411,10 +411,10 @@ __global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A,
 // order (mb, jb, q, lane)).  The next k-step's fragments and x values are
 // loaded before the current step's Q*NB MFMAs are issued.
 template <int Q, int NB>
-__global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int64_t nc, const double *__restrict__ Af,
+__global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int kb0, int kb1, int64_t nc, const double *__restrict__ Af,
                                                  const double *__restrict__ w, const int32_t *__restrict__ cd,
                                                  const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
-                                                 int64_t ldy, const PcgState *st) {
+                                                 int64_t ldy, double alpha, const PcgState *st) {
   if (st && st[blockIdx.z].done) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mb = blockIdx.y * 4 + wave;
@@ -441,12 +441,12 @@ __global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int64_t
   const double *Ab = Af + size_t(mb) * KB * Q * 64 + lane;
   double a0[Q], x0[NB];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) a0[q] = Ab[q * 64];
+  for (int q = 0; q < Q; ++q) a0[q] = Ab[size_t(kb0) * Q * 64 + q * 64];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) x0[nb] = lk < n ? xr[cdp[nb][lk]] : 0.0;
-  for (int jb = 0; jb < KB; ++jb) {
+  for (int nb = 0; nb < NB; ++nb) x0[nb] = kb0 * 4 + lk < n ? xr[cdp[nb][kb0 * 4 + lk]] : 0.0;
+  for (int jb = kb0; jb < kb1; ++jb) {
     double a1[Q], x1[NB];
-    if (jb + 1 < KB) {
+    if (jb + 1 < kb1) {
       const double *An = Ab + size_t(jb + 1) * Q * 64;
 #pragma unroll
       for (int q = 0; q < Q; ++q) a1[q] = An[q * 64];
@@ -476,7 +476,7 @@ __global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int64_t
     for (int v = 0; v < 4; ++v) {
       // FP64 16x16x4 accumulator layout: lane l, element v holds row l/16 + 4v, column l%16
       const int row = mb * 16 + lk + 4 * v;
-      if (row < n) atomicAdd(&yr[cdp[nb][row]], acc[nb][v]);
+      if (row < n) atomicAdd(&yr[cdp[nb][row]], alpha * acc[nb][v]);
     }
   }
 }
@@ -487,10 +487,10 @@ __global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int64_t
 // MFMA (FP32 accumulation); y stays FP64.
 typedef float f4 __attribute__((ext_vector_type(4)));
 template <int Q, int NB>
-__global__ __launch_bounds__(256) void k_apply_A32(int n, int NMB, int KB, int64_t nc, const float *__restrict__ Af,
+__global__ __launch_bounds__(256) void k_apply_A32(int n, int NMB, int KB, int kb0, int kb1, int64_t nc, const float *__restrict__ Af,
                                                    const float *__restrict__ w, const int32_t *__restrict__ cd,
                                                    const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
-                                                   int64_t ldy, const PcgState *st) {
+                                                   int64_t ldy, double alpha, const PcgState *st) {
   if (st && st[blockIdx.z].done) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mb = blockIdx.y * 4 + wave;
@@ -517,12 +517,12 @@ __global__ __launch_bounds__(256) void k_apply_A32(int n, int NMB, int KB, int64
   const float *Ab = Af + size_t(mb) * KB * Q * 64 + lane;
   float a0[Q], x0[NB];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) a0[q] = Ab[q * 64];
+  for (int q = 0; q < Q; ++q) a0[q] = Ab[size_t(kb0) * Q * 64 + q * 64];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) x0[nb] = lk < n ? float(xr[cdp[nb][lk]]) : 0.0f;
-  for (int jb = 0; jb < KB; ++jb) {
+  for (int nb = 0; nb < NB; ++nb) x0[nb] = kb0 * 4 + lk < n ? float(xr[cdp[nb][kb0 * 4 + lk]]) : 0.0f;
+  for (int jb = kb0; jb < kb1; ++jb) {
     float a1[Q], x1[NB];
-    if (jb + 1 < KB) {
+    if (jb + 1 < kb1) {
       const float *An = Ab + size_t(jb + 1) * Q * 64;
 #pragma unroll
       for (int q = 0; q < Q; ++q) a1[q] = An[q * 64];
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(256) void k_apply_A32(int n, int NMB, int KB, int64
     for (int v = 0; v < 4; ++v) {
       // FP32 16x16x4 accumulator layout: lane l, element v holds row 4 (l/16) + v, column l%16
       const int row = mb * 16 + lk * 4 + v;
-      if (row < n) atomicAdd(&yr[cdp[nb][row]], double(acc[nb][v]));
+      if (row < n) atomicAdd(&yr[cdp[nb][row]], alpha * double(acc[nb][v]));
     }
   }
 }
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(256) void k_patch_seg(const int64_t *__restrict__ c
                                                    const double *__restrict__ ent_coef,
                                                    const int64_t *__restrict__ inv_off, const T *__restrict__ inv,
                                                    const double *__restrict__ r, int64_t ldr, double *__restrict__ z,
-                                                   int64_t ldz, int ncol, const PcgState *st) {
+                                                   int64_t ldz, int ncol, double scale, const PcgState *st) {
   constexpr int RPW = 64 / L;        // rows per wave step
   constexpr int W = NQ * L * V;      // columns covered (LDS stride)
   typedef T vecV __attribute__((ext_vector_type(V)));
@@ -699,8 +699,8 @@ __global__ __launch_bounds__(256) void k_patch_seg(const int64_t *__restrict__ c
   for (int t2 = threadIdx.x; t2 < G * m; t2 += 256) {
     const int g = t2 / m, j = t2 - g * m;
     if (j < r0 || cbase + g >= ncol) continue;
-    const double y = yr[g * W + j] + ((yc[(0 * G + g) * W + j] + yc[(1 * G + g) * W + j]) +
-                                      (yc[(2 * G + g) * W + j] + yc[(3 * G + g) * W + j]));
+    const double y = scale * (yr[g * W + j] + ((yc[(0 * G + g) * W + j] + yc[(1 * G + g) * W + j]) +
+                                               (yc[(2 * G + g) * W + j] + yc[(3 * G + g) * W + j])));
     double *zc = z + int64_t(cbase + g) * ldz;
     for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) atomicAdd(&zc[ent_dof[e]], ent_coef[e] * y);
   }
@@ -898,7 +898,7 @@ __global__ __launch_bounds__(256) void k_patch_gemm(const int64_t *__restrict__ 
                                                     const int64_t *__restrict__ inv_off,
                                                     const double *__restrict__ inv, int E,
                                                     const double *__restrict__ r, int64_t ldr,
-                                                    double *__restrict__ z, int64_t ldz, int ncol,
+                                                    double *__restrict__ z, int64_t ldz, int ncol, double scale,
                                                     const PcgState *st) {
   const int64_t p = blockIdx.x;
   const int c0 = blockIdx.y * 64;
@@ -957,7 +957,7 @@ __global__ __launch_bounds__(256) void k_patch_gemm(const int64_t *__restrict__ 
         const int row = mb * 16 + lk + 4 * v;
         if (row < m)
           for (int64_t e = col_ent[cb + row]; e < col_ent[cb + row + 1]; ++e)
-            atomicAdd(&zc[ent_dof[e]], ent_coef[e] * acc[nb][v]);
+            atomicAdd(&zc[ent_dof[e]], scale * ent_coef[e] * acc[nb][v]);
       }
     }
   }
@@ -1167,6 +1167,85 @@ __global__ void k_jacobi_m(int64_t n, int64_t offI, const double *__restrict__ d
     z[c * ldz + i] = i >= offI ? r[c * ldr + i] * dinv[i - offI] : 0.0;
 }
 
+// ---- symmetric multiplicative hybrid (Sec. 7.1): the sweep's small kernels
+// First group of the sweep: z = rho_1^{-1} D_I^{-1} r on the interior, zero
+// on the interface, and the tracked residual s = r.  With check set (inside
+// PCG) it first takes the convergence test of k_check_jacobi_m.
+__global__ __launch_bounds__(256) void k_hyb_init_m(int64_t n, int64_t offI, const double *__restrict__ dinv,
+                                                    double w1, const double *__restrict__ r, int64_t ldr,
+                                                    double *__restrict__ z, int64_t ldz, double *__restrict__ sres,
+                                                    const double *__restrict__ partR, int RB, PcgState *st) {
+  const int c = blockIdx.y;
+  if (st) {
+    if (st[c].done) return;
+    __shared__ double sm4[4];
+    const double rr = sum_part(partR + c * RB, RB, sm4);
+    const bool bad = !isfinite(rr), conv = rr <= st[c].tol2 * st[c].bb;  // identical in every block
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      const int it = st[c].iter + 1;
+      st[c].rr = rr;
+      st[c].iter = it;
+      if (bad || conv || it >= st[c].maxit) {
+        st[c].status = bad ? PCG_BREAKDOWN : (conv ? PCG_CONVERGED : PCG_MAXIT);
+        st[c].done = 1;
+      }
+    }
+    if (bad || conv) return;
+  }
+  const double *rc = r + c * ldr;
+  double *zc = z + c * ldz, *sc = sres + c * n;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const double ri = rc[i];
+    zc[i] = i >= offI ? w1 * ri * dinv[i - offI] : 0.0;
+    sc[i] = ri;
+  }
+}
+
+// z += d (per column; columns that are done are skipped)
+__global__ void k_add_m(int64_t n, const double *__restrict__ d, double *__restrict__ z, int64_t ldz,
+                        const PcgState *st) {
+  const int c = blockIdx.y;
+  if (st && st[c].done) return;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    z[c * ldz + i] += d[c * n + i];
+}
+
+// last group of the sweep: z += rho_1^{-1} D_I^{-1} s on the interior
+__global__ void k_jacobi_add_m(int64_t n, int64_t offI, const double *__restrict__ dinv, double w1,
+                               const double *__restrict__ sres, double *__restrict__ z, int64_t ldz,
+                               const PcgState *st) {
+  const int c = blockIdx.y;
+  if (st && st[c].done) return;
+  for (int64_t i = offI + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    z[c * ldz + i] += w1 * sres[c * n + i] * dinv[i - offI];
+}
+
+// coarse correction d = R_W^T zW (d zero elsewhere beforehand), z += d
+__global__ void k_coarse_scatter2_m(int nW, int npad, const int32_t *__restrict__ wd, const double *__restrict__ zW,
+                                    int64_t n, double *__restrict__ d, double *__restrict__ z, int64_t ldz,
+                                    const PcgState *st) {
+  const int c = blockIdx.y;
+  if (st && st[c].done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nW) {
+    const double v = zW[int64_t(c) * npad + i];
+    d[c * n + wd[i]] = v;
+    z[c * ldz + wd[i]] += v;
+  }
+}
+
+// y = a x + b y on one vector (setup-time Krylov steps)
+__global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, double b, double *__restrict__ y) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+
+// zero y outside [lo, hi)
+__global__ void k_mask(int64_t n, int64_t lo, int64_t hi, double *__restrict__ y) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    if (i < lo || i >= hi) y[i] = 0.0;
+}
+
 }  // namespace
 
 // ================================================================ launchers
@@ -1224,27 +1303,25 @@ void launch_pack_tiles(int N, int n, const double *Ainv, double *tiles, hipStrea
 }
 
 template <int Q>
-static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, const double *x, int64_t ldx, double *y,
-                      int64_t ldy, const PcgState *st, hipStream_t s) {
+static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1, const double *x, int64_t ldx,
+                      double *y, int64_t ldy, double alpha, const PcgState *st, hipStream_t s) {
   const int KB = t.KP / 4, NMB = t.NP / 16;
-  if (NB == 4)
-    hipLaunchKernelGGL((k_apply_A<Q, 4>), grid, dim3(256), 0, s, t.n, NMB, KB, t.n_cells, t.Afrag, t.w, t.cell_dofs,
-                       x, ldx, y, ldy, st);
-  else if (NB == 2)
-    hipLaunchKernelGGL((k_apply_A<Q, 2>), grid, dim3(256), 0, s, t.n, NMB, KB, t.n_cells, t.Afrag, t.w, t.cell_dofs,
-                       x, ldx, y, ldy, st);
-  else
-    hipLaunchKernelGGL((k_apply_A<Q, 1>), grid, dim3(256), 0, s, t.n, NMB, KB, t.n_cells, t.Afrag, t.w, t.cell_dofs,
-                       x, ldx, y, ldy, st);
+#define RZ_A64(NBV)                                                                                         \
+  hipLaunchKernelGGL((k_apply_A<Q, NBV>), grid, dim3(256), 0, s, t.n, NMB, KB, kb0, kb1, t.n_cells, t.Afrag, \
+                     t.w, t.cell_dofs, x, ldx, y, ldy, alpha, st)
+  if (NB == 4) RZ_A64(4);
+  else if (NB == 2) RZ_A64(2);
+  else RZ_A64(1);
+#undef RZ_A64
 }
 
 template <int Q>
-static void apply_A32_q(const ApplyATables &t, int NB, dim3 grid, const double *x, int64_t ldx, double *y,
-                        int64_t ldy, const PcgState *st, hipStream_t s) {
+static void apply_A32_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1, const double *x, int64_t ldx,
+                        double *y, int64_t ldy, double alpha, const PcgState *st, hipStream_t s) {
   const int KB = t.KP / 4, NMB = t.NP / 16;
-#define RZ_A32(NBV)                                                                                          \
-  hipLaunchKernelGGL((k_apply_A32<Q, NBV>), grid, dim3(256), 0, s, t.n, NMB, KB, t.n_cells, t.Afrag32, t.w32, \
-                     t.cell_dofs, x, ldx, y, ldy, st)
+#define RZ_A32(NBV)                                                                                             \
+  hipLaunchKernelGGL((k_apply_A32<Q, NBV>), grid, dim3(256), 0, s, t.n, NMB, KB, kb0, kb1, t.n_cells, t.Afrag32, \
+                     t.w32, t.cell_dofs, x, ldx, y, ldy, alpha, st)
   if (NB == 4) RZ_A32(4);
   else if (NB == 2) RZ_A32(2);
   else RZ_A32(1);
@@ -1252,21 +1329,24 @@ static void apply_A32_q(const ApplyATables &t, int NB, dim3 grid, const double *
 }
 
 void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
-                    const PcgState *st, hipStream_t s, bool lo) {
+                    const PcgState *st, hipStream_t s, bool lo, int col0, int col1, double alpha) {
+  if (col1 < 0) col1 = t.n;
+  if (col0 >= col1) return;
+  const int kb0 = col0 / 4, kb1 = (col1 + 3) / 4;
   const int NMB = t.NP / 16;
   // cells per wave: as many as keep >= 2048 waves in flight (A-fragment reuse vs occupancy)
   int NB = 4;
   while (NB > 1 && ((t.n_cells + 16 * NB - 1) / (16 * NB)) * NMB * n_rhs < 2048) NB /= 2;
   dim3 grid(unsigned((t.n_cells + 16 * NB - 1) / (16 * NB)), unsigned((NMB + 3) / 4), unsigned(n_rhs));
   if (lo && t.Afrag32) {
-    if (t.Q == 12) apply_A32_q<12>(t, NB, grid, x, ldx, y, ldy, st, s);
-    else if (t.Q == 7) apply_A32_q<7>(t, NB, grid, x, ldx, y, ldy, st, s);
-    else apply_A32_q<4>(t, NB, grid, x, ldx, y, ldy, st, s);
+    if (t.Q == 12) apply_A32_q<12>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
+    else if (t.Q == 7) apply_A32_q<7>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
+    else apply_A32_q<4>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
     return;
   }
-  if (t.Q == 12) apply_A_q<12>(t, NB, grid, x, ldx, y, ldy, st, s);
-  else if (t.Q == 7) apply_A_q<7>(t, NB, grid, x, ldx, y, ldy, st, s);
-  else apply_A_q<4>(t, NB, grid, x, ldx, y, ldy, st, s);
+  if (t.Q == 12) apply_A_q<12>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
+  else if (t.Q == 7) apply_A_q<7>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
+  else apply_A_q<4>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
 }
 
 // patch apply: largest G in {8,4,2,1} with G <= ncol, LDS <= 96 KB, MAXJ * G <= 32
@@ -1288,8 +1368,8 @@ constexpr int patch_depth() {
 
 template <int V, int L, int NQ, int G, typename T>
 static void patch_seg_g(const PatchApply &pa, const int64_t *off, const T *inv, dim3 grid, size_t lds,
-                        const double *r, int64_t ldr, double *z, int64_t ldz, int ncol, const PcgState *st,
-                        hipStream_t s) {
+                        const double *r, int64_t ldr, double *z, int64_t ldz, int ncol, double scale,
+                        const PcgState *st, hipStream_t s) {
   constexpr int D = patch_depth<NQ * V, T>();
   static bool attr = false;
   if (!attr) {
@@ -1298,27 +1378,27 @@ static void patch_seg_g(const PatchApply &pa, const int64_t *off, const T *inv, 
     attr = true;
   }
   hipLaunchKernelGGL((k_patch_seg<V, L, NQ, G, D, T>), grid, dim3(256), lds, s, pa.chunk_patch, pa.chunk_rows,
-                     pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, off, inv, r, ldr, z, ldz, ncol, st);
+                     pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, off, inv, r, ldr, z, ldz, ncol, scale, st);
 }
 
 template <int V, int L, int NQ, typename T>
 static void patch_seg(const PatchApply &pa, const int64_t *off, const T *inv, const double *r, int64_t ldr,
-                      double *z, int64_t ldz, int ncol, const PcgState *st, hipStream_t s) {
+                      double *z, int64_t ldz, int ncol, double scale, const PcgState *st, hipStream_t s) {
   constexpr int W = NQ * L * V;
   constexpr int VQ = NQ * V;
   const size_t lds_per_g = size_t(6) * W * sizeof(double);
   int G = 4;
   while (G > 1 && (G > ncol || lds_per_g * G > 96 * 1024 || VQ * G > 32)) G /= 2;
   const dim3 grid(unsigned(pa.n_chunks), unsigned((ncol + G - 1) / G));
-  if (G == 4) patch_seg_g<V, L, NQ, (VQ <= 8 ? 4 : 1), T>(pa, off, inv, grid, lds_per_g * G, r, ldr, z, ldz, ncol, st, s);
-  else if (G == 2) patch_seg_g<V, L, NQ, (VQ <= 16 ? 2 : 1), T>(pa, off, inv, grid, lds_per_g * G, r, ldr, z, ldz, ncol, st, s);
-  else patch_seg_g<V, L, NQ, 1, T>(pa, off, inv, grid, lds_per_g, r, ldr, z, ldz, ncol, st, s);
+  if (G == 4) patch_seg_g<V, L, NQ, (VQ <= 8 ? 4 : 1), T>(pa, off, inv, grid, lds_per_g * G, r, ldr, z, ldz, ncol, scale, st, s);
+  else if (G == 2) patch_seg_g<V, L, NQ, (VQ <= 16 ? 2 : 1), T>(pa, off, inv, grid, lds_per_g * G, r, ldr, z, ldz, ncol, scale, st, s);
+  else patch_seg_g<V, L, NQ, 1, T>(pa, off, inv, grid, lds_per_g, r, ldr, z, ldz, ncol, scale, st, s);
 }
 
 // lanes per row and column stripes for the largest patch of a set
 template <typename T>
 static void patch_dispatch(const PatchApply &pa, const int64_t *off, const T *inv, const double *r, int64_t ldr,
-                           double *z, int64_t ldz, int ncol, const PcgState *st, hipStream_t s) {
+                           double *z, int64_t ldz, int ncol, double scale, const PcgState *st, hipStream_t s) {
   constexpr int V = 16 / sizeof(T);
   const int m = pa.max_size;
   const int L = m <= 48 ? 16 : (m <= 160 ? 32 : 64);
@@ -1326,7 +1406,7 @@ static void patch_dispatch(const PatchApply &pa, const int64_t *off, const T *in
   const int nq = (mS + V * L - 1) / (V * L);
   const int NQ = nq <= 1 ? 1 : nq <= 2 ? 2 : nq <= 4 ? 4 : nq <= 8 ? 8 : 16;
 #define RZ_PQ(LL, QQ) \
-  if (L == LL && NQ == QQ) return patch_seg<V, LL, QQ, T>(pa, off, inv, r, ldr, z, ldz, ncol, st, s)
+  if (L == LL && NQ == QQ) return patch_seg<V, LL, QQ, T>(pa, off, inv, r, ldr, z, ldz, ncol, scale, st, s)
   RZ_PQ(16, 1); RZ_PQ(16, 2); RZ_PQ(16, 4);
   RZ_PQ(32, 1); RZ_PQ(32, 2); RZ_PQ(32, 4);
   RZ_PQ(64, 1); RZ_PQ(64, 2); RZ_PQ(64, 4); RZ_PQ(64, 8); RZ_PQ(64, 16);
@@ -1334,9 +1414,10 @@ static void patch_dispatch(const PatchApply &pa, const int64_t *off, const T *in
 }
 
 void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
-                        const PcgState *st, hipStream_t s, bool lo) {
+                        const PcgState *st, hipStream_t s, bool lo, double scale) {
   if (pa.n_chunks == 0) return;
-  if (lo && pa.inv32) return patch_dispatch<float>(pa, pa.inv_off32, pa.inv32, r, ldr, z, ldz, ncol, st, s);
+  if (lo && pa.inv32)
+    return patch_dispatch<float>(pa, pa.inv_off32, pa.inv32, r, ldr, z, ldz, ncol, scale, st, s);
   if (ncol >= 8 && pa.max_size <= kSmallPatch) {
     const int MP = (pa.max_size + 15) & ~15;
     const size_t lds = size_t(MP * (MP + 1) + MP * 65) * sizeof(double);
@@ -1347,10 +1428,10 @@ void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, doub
     }
     hipLaunchKernelGGL(k_patch_gemm, dim3(unsigned(pa.n_patches), unsigned((ncol + 63) / 64)), dim3(256), lds, s,
                        pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, pa.inv_off, pa.inv, 2, r, ldr, z, ldz,
-                       ncol, st);
+                       ncol, scale, st);
     return;
   }
-  patch_dispatch<double>(pa, pa.inv_off, pa.inv, r, ldr, z, ldz, ncol, st, s);
+  patch_dispatch<double>(pa, pa.inv_off, pa.inv, r, ldr, z, ldz, ncol, scale, st, s);
 }
 
 void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hipStream_t s, bool lo) {
@@ -1436,6 +1517,39 @@ void launch_to_float(int64_t n, const double *a, float *b, hipStream_t s) {
 }
 void launch_axpy(int64_t n, const double *d, double *x, int64_t ldx, int ncol, hipStream_t s) {
   hipLaunchKernelGGL(k_axpy_m, dim3(grid_for(n, 256, 2048), ncol), dim3(256), 0, s, n, d, x, ldx);
+}
+
+// ---- hybrid sweep
+void launch_hyb_init(int64_t n, int64_t off_I, const double *dinv, double w1, const double *r, int64_t ldr, double *z,
+                     int64_t ldz, double *sres, const double *partR, int RB, int ncol, PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_hyb_init_m, dim3(grid_for(n, 256, std::max(1, 2048 / ncol)), ncol), dim3(256), 0, s, n, off_I,
+                     dinv, w1, r, ldr, z, ldz, sres, partR, RB, st);
+}
+void launch_add(int64_t n, const double *d, double *z, int64_t ldz, int ncol, const PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_m, dim3(grid_for(n, 256, std::max(1, 2048 / ncol)), ncol), dim3(256), 0, s, n, d, z, ldz,
+                     st);
+}
+void launch_jacobi_add(int64_t n, int64_t off_I, const double *dinv, double w1, const double *sres, double *z,
+                       int64_t ldz, int ncol, const PcgState *st, hipStream_t s) {
+  if (off_I >= n) return;
+  hipLaunchKernelGGL(k_jacobi_add_m, dim3(grid_for(n - off_I, 256, std::max(1, 2048 / ncol)), ncol), dim3(256), 0, s,
+                     n, off_I, dinv, w1, sres, z, ldz, st);
+}
+void launch_coarse_gather(const CoarseApply &ca, const double *r, int64_t ldr, int ncol, hipStream_t s) {
+  const int npad = ca.NT * 64;
+  hipLaunchKernelGGL(k_coarse_gather_m, dim3(grid_for(npad, 256), ncol), dim3(256), 0, s, ca.nW, npad, ca.wdofs, r,
+                     ldr, ca.rW, ca.zW);
+}
+void launch_coarse_scatter2(const CoarseApply &ca, int64_t n, double *d, double *z, int64_t ldz, int ncol,
+                            const PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_scatter2_m, dim3(grid_for(ca.nW, 256), ncol), dim3(256), 0, s, ca.nW, ca.NT * 64,
+                     ca.wdofs, ca.zW, n, d, z, ldz, st);
+}
+void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, a, x, b, y);
+}
+void launch_mask(int64_t n, int64_t lo, int64_t hi, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, lo, hi, y);
 }
 
 }  // namespace rz

@@ -45,8 +45,11 @@ struct ApplyATables {
 };
 // y += A x for n_rhs columns (y must be zeroed by the caller); st: per-column
 // state (columns that are done are skipped) or null; lo: the FP32 copies
+// [col0, col1): only these local columns of A_T take part (x is zero on the
+// others: a restricted apply); y += alpha A x.
 void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
-                    const PcgState *st, hipStream_t s, bool lo = false);
+                    const PcgState *st, hipStream_t s, bool lo = false, int col0 = 0, int col1 = -1,
+                    double alpha = 1.0);
 
 // Patch inverse storage: row i of a patch of size m holds the columns
 // [V floor(i/V), V ceil(m/V)) -- zero left of the diagonal and beyond m, the
@@ -89,7 +92,7 @@ struct CoarseFold {
 
 // z += sum_patches (scatter-add; z must hold the Jacobi part already)
 void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
-                        const PcgState *st, hipStream_t s, bool lo = false);
+                        const PcgState *st, hipStream_t s, bool lo = false, double scale = 1.0);
 void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hipStream_t s, bool lo = false);
 void launch_to_float(int64_t n, const double *a, float *b, hipStream_t s);
 void launch_axpy(int64_t n, const double *d, double *x, int64_t ldx, int ncol, hipStream_t s);
@@ -114,5 +117,20 @@ void launch_check_jacobi(int64_t n, int64_t off_I, const double *dinv, const dou
                          const CoarseApply &ca, const double *partR, int RB, int ncol, PcgState *st, hipStream_t s);
 void launch_update_p(int64_t n, double *p, const double *z, const CoarseFold &cf, int npad, double *Ap,
                      const double *partZ, int RB, int ncol, PcgState *st, hipStream_t s);
+
+// ---- symmetric multiplicative hybrid sweep (Sec. 7.1)
+// z = w1 D_I^{-1} r (interior), s = r; with st, after the convergence test
+void launch_hyb_init(int64_t n, int64_t off_I, const double *dinv, double w1, const double *r, int64_t ldr, double *z,
+                     int64_t ldz, double *sres, const double *partR, int RB, int ncol, PcgState *st, hipStream_t s);
+void launch_add(int64_t n, const double *d, double *z, int64_t ldz, int ncol, const PcgState *st, hipStream_t s);
+void launch_jacobi_add(int64_t n, int64_t off_I, const double *dinv, double w1, const double *sres, double *z,
+                       int64_t ldz, int ncol, const PcgState *st, hipStream_t s);
+// rW = R_W r, zW = 0
+void launch_coarse_gather(const CoarseApply &ca, const double *r, int64_t ldr, int ncol, hipStream_t s);
+// d = R_W^T zW (d zero elsewhere beforehand), z += d
+void launch_coarse_scatter2(const CoarseApply &ca, int64_t n, double *d, double *z, int64_t ldz, int ncol,
+                            const PcgState *st, hipStream_t s);
+void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+void launch_mask(int64_t n, int64_t lo, int64_t hi, double *y, hipStream_t s);
 
 }  // namespace rz

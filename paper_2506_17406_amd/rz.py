@@ -27,11 +27,13 @@ class RzMesh(ctypes.Structure):
 
 RZ_FP64, RZ_FP32_IR = 0, 1
 PRECISIONS = {"fp64": RZ_FP64, "fp32-ir": RZ_FP32_IR}
+RZ_PC_ADDITIVE, RZ_PC_HYBRID = 0, 1
+PCS = {"additive": RZ_PC_ADDITIVE, "hybrid": RZ_PC_HYBRID}
 
 
 class RzOptions(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
+                ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("pc", ctypes.c_int32)]
 
 
 class RzInfo(ctypes.Structure):
@@ -62,6 +64,7 @@ def _load():
         "rz_apply_A_fp32": (ctypes.c_int, [P, P, P, i32, i64, P]),
         "rz_apply_P_fp32": (ctypes.c_int, [P, P, P, i32, i64, P]),
         "rz_solve": (ctypes.c_int, [P, P, P, i32, i64, dbl, ctypes.POINTER(RzInfo), P]),
+        "rz_pc_weights": (ctypes.c_int, [P, pdbl]),
         "rz_export_topology": (ctypes.c_int, [P, pi32, pi64, pi64, pi64, pi32]),
         "rz_export_reference": (ctypes.c_int, [P, pdbl]),
         "rz_reference": (ctypes.c_int, [i32, i32, ctypes.c_int, pi32, pi32, pdbl]),
@@ -133,10 +136,10 @@ class Problem:
     """A set-up Riesz-map problem on the GPU (rz_setup)."""
 
     def __init__(self, coords, cells, degree, space, alpha=1.0, beta=1.0, max_iter=1000, precision="fp64",
-                 inner_rtol=0.0, stream=None):
+                 inner_rtol=0.0, pc="hybrid", stream=None):
         m, keep = _mesh(coords, cells)
         prec = PRECISIONS[precision] if isinstance(precision, str) else precision
-        opts = RzOptions(alpha, beta, max_iter, prec, inner_rtol)
+        opts = RzOptions(alpha, beta, max_iter, prec, inner_rtol, PCS[pc] if isinstance(pc, str) else pc)
         h = ctypes.c_void_p()
         self._h = None
         self.space = SPACES[space] if isinstance(space, str) else space
@@ -206,6 +209,11 @@ class Problem:
                     cond_estimate=i.cond_estimate, solve_ms=i.solve_ms, outer_iterations=i.outer_iterations,
                     code=code) for i in info]
         return out[0] if b.dim() == 1 else out
+
+    def pc_weights(self):
+        rho = np.empty(3)
+        _check(lib.rz_pc_weights(self._h, _ptr(rho, ctypes.c_double)))
+        return rho
 
     def export_reference(self):
         out = np.empty((self.Q, self.n_loc, self.n_loc))

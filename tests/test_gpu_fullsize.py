@@ -4,8 +4,11 @@ sampled outputs one by one, and properties that hold at any size.
 
 * apply_A: sampled rows (A x)_i from the oracle's stacked reference form
   (itself pinned to the direct definition) within 1e-12 max |y|;
-* apply_P: symmetry r1.P^{-1}r2 = r2.P^{-1}r1 (1e-12 relative), positivity,
-  linearity (1e-12);
+* apply_P: symmetry r1.P^{-1}r2 = r2.P^{-1}r1, positivity, linearity --
+  1e-12 relative for the additive form; 1e-10 for the hybrid sweep, whose
+  result passes through four operator applies (FP64 atomic scatter in a
+  varying order), so rounding breaks exact symmetry and linearity at a few
+  1e-12;
 * solve: the library's recursive residual <= 1e-10 and the oracle's residual
   rows b_i - (A x)_i of the returned x within 2e-10 ||b||_2 (each entry of a
   vector is bounded by its 2-norm).
@@ -26,16 +29,16 @@ FULL = [("CG", 8), ("Ned", 6), ("Ned", 8), ("RT", 8)]
 _cache = {}
 
 
-def setup_full(fam, p):
-    if (fam, p) not in _cache:
+def setup_full(fam, p, pc="hybrid"):
+    if (fam, p, pc) not in _cache:
         from paper_2506_17406_amd import rz
         X, C = kuhn_mesh(8, 3, jitter=0.1, seed=2)
         el = element(3, fam, p)
         top = Topology(X, C, el)
-        prob = rz.Problem(X, C, p, fam)
+        prob = rz.Problem(X, C, p, fam, pc=pc)
         assert prob.n_dofs == top.n_dofs
-        _cache[(fam, p)] = (el, top, reference_stack(el), prob)
-    return _cache[(fam, p)]
+        _cache[(fam, p, pc)] = (el, top, reference_stack(el), prob)
+    return _cache[(fam, p, pc)]
 
 
 def sample_dofs(top, per_block=12, seed=0):
@@ -71,9 +74,11 @@ def test_apply_A_sampled(fam, p):
     assert np.abs(y[rows] - ref).max() <= 1e-12 * np.abs(y).max()
 
 
+@pytest.mark.parametrize("pc", ["additive", "hybrid"])
 @pytest.mark.parametrize("fam,p", FULL)
-def test_apply_P_properties(fam, p):
-    el, top, R, prob = setup_full(fam, p)
+def test_apply_P_properties(fam, p, pc):
+    el, top, R, prob = setup_full(fam, p, pc)
+    tol = 1e-12 if pc == "additive" else 1e-10
     r = load_vectors(top.n_dofs, 8, n_rhs=2)
     rt = torch.from_numpy(np.ascontiguousarray(r.T)).cuda()
     z1, z2, z3 = (torch.empty(top.n_dofs, dtype=torch.float64, device="cuda") for _ in range(3))
@@ -83,10 +88,10 @@ def test_apply_P_properties(fam, p):
     torch.cuda.synchronize()
     a = float(torch.dot(rt[0], z2))
     b = float(torch.dot(rt[1], z1))
-    assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+    assert abs(a - b) <= tol * max(abs(a), abs(b))
     assert float(torch.dot(rt[0], z1)) > 0 and float(torch.dot(rt[1], z2)) > 0
     lin = z1 + 2.0 * z2
-    assert float((z3 - lin).abs().max()) <= 1e-12 * float(lin.abs().max())
+    assert float((z3 - lin).abs().max()) <= tol * float(lin.abs().max())
 
 
 @pytest.mark.parametrize("fam,p", FULL)

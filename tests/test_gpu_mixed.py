@@ -7,8 +7,9 @@ Bars (written per check):
   |y32 - A x|_i <= (K + 4) u32 (|A|_abs |x|)_i with u32 = 2^-24 and
   |A|_abs = sum_T P_T^T (sum_q |w_Tq| |R_q|) P_T (the oracle's tables);
   and the result must differ from the FP64 apply (the FP32 path ran);
-* FP32 apply_P -- max |z32 - z_oracle| <= 1e-4 max |z_oracle| (inverse
-  entries rounded once to FP32; accumulation in FP64);
+* FP32 apply_P -- the hybrid sweep with the FP32 operator and inverses:
+  max |z32 - z_oracle| <= 1e-4 max |z_oracle| (entries rounded once to
+  FP32; accumulation in FP64);
 * refinement solve -- true residual under the oracle's A <= 1.2 rtol ||b||
   + ||(A_lib - A_oracle) x|| at rtol 1e-10 and 1e-12, ||x - x_oracle|| <=
   1e-10 ||x_oracle|| at rtol 1e-12, at least two refinement steps taken.
@@ -22,7 +23,7 @@ from oracle.element import element
 from oracle.mesh import Topology
 from oracle.operator import all_cell_matrices, assemble, cell_weights, reference_stack
 from oracle.pcg import pcg
-from oracle.precond import AdditiveSchwarz
+from oracle.precond import HybridSchwarz
 from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
 
 pytestmark = pytest.mark.gpu
@@ -42,7 +43,7 @@ def setup_case(d, fam, p, n):
         X, C = kuhn_mesh(n, d, jitter=0.1 if d == 3 else 0.0, seed=13)
         top = Topology(X, C, element(d, fam, p))
         A = assemble(top, all_cell_matrices(top.el, top))
-        P = AdditiveSchwarz(A, top, fam)
+        P = HybridSchwarz(A, top, fam)
         prob = rz.Problem(X, C, p, fam, precision="fp32-ir")
         _cache[key] = (top, A, P, prob)
     return _cache[key]

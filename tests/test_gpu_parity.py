@@ -1,7 +1,9 @@
 """GPU parity of the HIP library against the FP64 oracle (through the C ABI).
 
 Sizes: meshes with 32-162 cells (several apply_A tiles and a ragged last
-tile), every space, degrees 3-5, seeded jitter and load vectors.
+tile), every space, degrees 3-5, seeded jitter and load vectors; both
+preconditioner forms (additive; symmetric multiplicative hybrid, whose group
+weights must agree with the oracle's to 1e-10).
 Bars (written per check):
 * apply_A  -- max |y_gpu - y_oracle| <= 1e-12 max |y_oracle| (1e-11 at p > 8,
               where the library's and the oracle's reference tables agree to
@@ -22,7 +24,7 @@ from oracle.element import element
 from oracle.mesh import Topology
 from oracle.operator import all_cell_matrices, assemble
 from oracle.pcg import pcg
-from oracle.precond import AdditiveSchwarz
+from oracle.precond import AdditiveSchwarz, HybridSchwarz
 from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
 
 pytestmark = pytest.mark.gpu
@@ -39,10 +41,11 @@ CASES = [(2, "CG", 4, 4, 0.0), (3, "CG", 3, 3, 0.1), (3, "CG", 5, 2, 0.1), (3, "
          (3, "CG", 8, 2, 0.1), (3, "CG", 10, 2, 0.1), (3, "Ned", 7, 2, 0.1)]
 
 _cache = {}
+PCS = ["additive", "hybrid"]
 
 
-def setup_case(d, fam, p, n, jit):
-    key = (d, fam, p, n, jit)
+def setup_case(d, fam, p, n, jit, pc="additive"):
+    key = (d, fam, p, n, jit, pc)
     if key not in _cache:
         from paper_2506_17406_amd import rz
         if n == 0:
@@ -50,10 +53,15 @@ def setup_case(d, fam, p, n, jit):
             C = np.array([[2, 0, 3, 1]])
         else:
             X, C = kuhn_mesh(n, d, jitter=jit, seed=11)
-        top = Topology(X, C, element(d, fam, p))
-        A = assemble(top, all_cell_matrices(top.el, top))
-        P = AdditiveSchwarz(A, top, fam)
-        prob = rz.Problem(X, C, p, fam)
+        base = (d, fam, p, n, jit, "additive")
+        if base in _cache:
+            top, A, P_add = _cache[base][:3]
+        else:
+            top = Topology(X, C, element(d, fam, p))
+            A = assemble(top, all_cell_matrices(top.el, top))
+            P_add = AdditiveSchwarz(A, top, fam)
+        P = P_add if pc == "additive" else HybridSchwarz(A, top, fam, additive=P_add)
+        prob = rz.Problem(X, C, p, fam, pc=pc)
         assert prob.n_dofs == top.n_dofs
         _cache[key] = (top, A, P, prob)
     return _cache[key]
@@ -79,9 +87,13 @@ def test_apply_A(case):
     assert np.abs(y - ref).max() <= tol * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("pc", PCS)
 @pytest.mark.parametrize("case", CASES, ids=ids)
-def test_apply_P(case):
-    top, A, P, prob = setup_case(*case)
+def test_apply_P(case, pc):
+    top, A, P, prob = setup_case(*case, pc=pc)
+    if pc == "hybrid":
+        rho = prob.pc_weights()
+        assert abs(rho[0] / P.rho_I - 1) <= 1e-10 and abs(rho[1] / P.rho_Gamma - 1) <= 1e-10 and rho[2] == 1.0
     r = load_vectors(top.n_dofs, 6)[:, 0]
     zt = torch.empty(top.n_dofs, dtype=torch.float64, device="cuda")
     prob.apply_P(torch.from_numpy(r).cuda(), zt)
@@ -90,9 +102,10 @@ def test_apply_P(case):
     assert np.abs(zt.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("pc", PCS)
 @pytest.mark.parametrize("case", CASES, ids=ids)
-def test_solve(case):
-    top, A, P, prob = setup_case(*case)
+def test_solve(case, pc):
+    top, A, P, prob = setup_case(*case, pc=pc)
     b = load_vectors(top.n_dofs, 7)[:, 0]
     bt = torch.from_numpy(b).cuda()
     for rtol in (1e-10, 1e-12):
@@ -117,12 +130,13 @@ def test_reference_export_matches_host_build():
 MULTI = [(3, "CG", 4, 2, 0.1), (3, "Ned", 3, 2, 0.1), (3, "RT", 3, 2, 0.1), (2, "CG", 4, 4, 0.0)]
 
 
+@pytest.mark.parametrize("pc", PCS)
 @pytest.mark.parametrize("case", MULTI, ids=ids)
 @pytest.mark.parametrize("nr", [3, 9])
-def test_multi_rhs_apply_P_and_solve(case, nr):
+def test_multi_rhs_apply_P_and_solve(case, nr, pc):
     """Several right-hand sides at once (column groups of 8, 4, 2, 1 and a
     ragged last group) give the oracle's per-column results."""
-    top, A, P, prob = setup_case(*case)
+    top, A, P, prob = setup_case(*case, pc=pc)
     B = load_vectors(top.n_dofs, 21, n_rhs=nr)
     Bt = torch.from_numpy(np.ascontiguousarray(B.T)).cuda().T      # column-major view
     Zt = torch.zeros_like(Bt)
