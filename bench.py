@@ -136,10 +136,11 @@ def mixed(args):
     t_setup = time.perf_counter() - t0
     print(f"setup Ned6 n=16 (FP64 + FP32 copies): {pm.n_dofs} dofs in {t_setup:.1f}s", file=sys.stderr, flush=True)
     p64 = rz.Problem(X, C, 6, "Ned", pc=args.pc)
+    ppc = rz.Problem(X, C, 6, "Ned", precision="fp32-pc", pc=args.pc)
     torch.cuda.synchronize()
-    print("setup FP64 handle done", file=sys.stderr, flush=True)
+    print("setup FP64 and FP32-preconditioner handles done", file=sys.stderr, flush=True)
     b = torch.from_numpy(load_vectors(pm.n_dofs, 5)[:, 0]).cuda()
-    xm, x64 = torch.zeros_like(b), torch.zeros_like(b)
+    xm, x64, xpc = torch.zeros_like(b), torch.zeros_like(b), torch.zeros_like(b)
 
     def timed(prob, x):
         for _ in range(args.warmup):
@@ -158,14 +159,19 @@ def mixed(args):
           file=sys.stderr, flush=True)
     dt_64, info_64 = timed(p64, x64)
     print(f"FP64: {dt_64 * 1e3:.1f} ms, {info_64['iterations']} its", file=sys.stderr, flush=True)
-    # true FP64 residuals and the distance between the two solutions
+    dt_pc, info_pc = timed(ppc, xpc)
+    print(f"FP32 preconditioner: {dt_pc * 1e3:.1f} ms, {info_pc['iterations']} its", file=sys.stderr, flush=True)
+    # true FP64 residuals and the distance between the solutions
     r = torch.empty_like(b)
     nb = b.norm().item()
-    p64.apply_A(x64, r)
-    res64 = (b - r).norm().item() / nb
-    p64.apply_A(xm, r)
-    res_m = (b - r).norm().item() / nb
+
+    def true_res(x):
+        p64.apply_A(x, r)
+        return (b - r).norm().item() / nb
+
+    res64, res_m, res_pc = true_res(x64), true_res(xm), true_res(xpc)
     diff = (xm - x64).norm().item() / x64.norm().item()
+    diff_pc = (xpc - x64).norm().item() / x64.norm().item()
     # dominant kernels: the FP32 and FP64 operator applies, the two preconditioner applies
     xa = torch.rand(pm.n_dofs, dtype=torch.float64, device="cuda")
     ya = torch.empty_like(xa)
@@ -176,24 +182,32 @@ def mixed(args):
     t_p64 = _apply_time(pm.apply_P, xa, ya, reps, stream)
     flops = 2.0 * pm.Q * pm.n_loc ** 2 * pm.n_cells
     tf32 = flops / t_a32 / 1e12
+    best_pc = dt_pc <= dt_m
+    dt_best = dt_pc if best_pc else dt_m
     line = {
         "metric": "Riesz-map solve DOFs/s to rel. residual 1e-10 (mixed precision)",
-        "value": pm.n_dofs / dt_m, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": dt_m * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 applies, f64 refinement", "data": "synthetic",
-        "config": {"workload": "H(curl) Ned_6 Riesz map, jittered Kuhn 16^3x6 = 24576 tets, FP32 iterative "
-                               "refinement to true FP64 rel. residual 1e-10", "dofs": pm.n_dofs,
-                   "preconditioner": args.pc,
+        "value": pm.n_dofs / dt_best, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt_best * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": ("f64 operator, f32-stored preconditioner" if best_pc else "f32 applies, f64 refinement"),
+        "data": "synthetic",
+        "config": {"workload": "H(curl) Ned_6 Riesz map, jittered Kuhn 16^3x6 = 24576 tets, mixed precision to "
+                               "true FP64 rel. residual 1e-10", "dofs": pm.n_dofs,
+                   "mode": "fp32-pc" if best_pc else "fp32-ir", "preconditioner": args.pc,
                    "setup_s": round(t_setup, 2)},
-        "roofline": {"kernel": "apply_A FP32 (Ned6)", "bound": "mfma", "achieved": tf32, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": tf32 / PEAK_FP32_TFLOPS, "traffic": None,
-                     "flops_per_launch": flops, "launch_us": t_a32 * 1e6},
-        "iterations": info_m["iterations"], "outer_iterations": info_m["outer_iterations"],
-        "true_rel_residual": res_m,
-        "rel_diff_vs_fp64_solution": diff,
+        "roofline": ({"kernel": "apply_A FP64 (Ned6)", "bound": "mfma", "achieved": flops / t_a64 / 1e12,
+                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": flops / t_a64 / 1e12 / PEAK_FP64_TFLOPS,
+                      "traffic": None, "flops_per_launch": flops, "launch_us": t_a64 * 1e6} if best_pc else
+                     {"kernel": "apply_A FP32 (Ned6)", "bound": "mfma", "achieved": tf32, "peak": PEAK_FP32_TFLOPS,
+                      "unit": "TFLOP/s", "frac": tf32 / PEAK_FP32_TFLOPS, "traffic": None,
+                      "flops_per_launch": flops, "launch_us": t_a32 * 1e6}),
+        "fp32_pc": {"value": pm.n_dofs / dt_pc, "ms": dt_pc * 1e3, "iterations": info_pc["iterations"],
+                    "true_rel_residual": res_pc, "rel_diff_vs_fp64_solution": diff_pc},
+        "fp32_ir": {"value": pm.n_dofs / dt_m, "ms": dt_m * 1e3, "iterations": info_m["iterations"],
+                    "outer_iterations": info_m["outer_iterations"], "true_rel_residual": res_m,
+                    "rel_diff_vs_fp64_solution": diff},
         "fp64": {"value": pm.n_dofs / dt_64, "ms": dt_64 * 1e3, "iterations": info_64["iterations"],
                  "true_rel_residual": res64},
-        "speedup_vs_fp64": dt_64 / dt_m,
+        "speedup_vs_fp64": dt_64 / dt_best,
         "apply_us": {"A_fp32": t_a32 * 1e6, "A_fp64": t_a64 * 1e6, "P_fp32": t_p32 * 1e6, "P_fp64": t_p64 * 1e6},
     }
     print(json.dumps(line), flush=True)

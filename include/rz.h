@@ -70,7 +70,10 @@ typedef struct {
   const int64_t *cells;   /* host, n_cells x (dim+1) vertex numbers, any order */
 } rz_mesh;
 
-/* Arithmetic of rz_solve.  RZ_FP64: PCG entirely in FP64.  RZ_FP32_IR:
+/* Arithmetic of rz_solve.  RZ_FP64: PCG entirely in FP64.  RZ_FP32_PC: PCG
+ * with the FP64 operator and vectors; the preconditioner reads FP32 copies
+ * of the patch and coarse inverses (accumulating in FP64), so it is a fixed
+ * symmetric operator and no refinement is needed.  RZ_FP32_IR:
  * iterative refinement -- the residual b - A x and the update x += d are
  * FP64; each correction d solves A d = r by PCG to inner_rtol whose operator
  * and preconditioner applies read FP32 copies of the reference tables,
@@ -79,7 +82,7 @@ typedef struct {
  * The copies are rounded from the FP64 factors built at setup.  If an outer
  * step contracts the true residual by less than a factor 2 the remaining
  * corrections use the FP64 applies. */
-typedef enum { RZ_FP64 = 0, RZ_FP32_IR = 1 } rz_precision;
+typedef enum { RZ_FP64 = 0, RZ_FP32_IR = 1, RZ_FP32_PC = 2 } rz_precision;
 
 /* Preconditioner form (Sec. 6 and Sec. 7.1).  RZ_PC_ADDITIVE: the additive
  * Schwarz method of the theory, Jacobi + interface patches + coarse summed.
@@ -139,12 +142,14 @@ int rz_apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t
  * r, z: device, n_dofs x n_rhs, leading dimension ld; z is overwritten. */
 int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream);
 
-/* The FP32-copy applies that the RZ_FP32_IR correction solves use, with the
- * rz_apply_A / rz_apply_P argument conventions (FP64 vectors in and out):
- * the reference tables, weights and x are rounded to FP32 and contracted by
- * FP32 MFMA, cell results are scatter-added in FP64; the preconditioner
- * reads FP32 patch and coarse inverses and accumulates in FP64.  RZ_ERR_ARG
- * for a handle set up without RZ_FP32_IR. */
+/* The FP32-copy applies, with the rz_apply_A / rz_apply_P argument
+ * conventions (FP64 vectors in and out).  rz_apply_A_fp32 (RZ_FP32_IR
+ * handles): the reference tables, weights and x are rounded to FP32 and
+ * contracted by FP32 MFMA, cell results are scatter-added in FP64.
+ * rz_apply_P_fp32 (RZ_FP32_IR and RZ_FP32_PC handles): the preconditioner
+ * of rz_solve's inner iteration -- FP32 patch and coarse inverses with FP64
+ * accumulation, and under RZ_FP32_IR also the FP32 operator inside the
+ * hybrid sweep.  RZ_ERR_ARG for a handle without the copies. */
 int rz_apply_A_fp32(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream);
 int rz_apply_P_fp32(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream);
 

@@ -382,7 +382,8 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
   P->p = degree;
   if (opts && opts->max_iter > 0) P->max_iter = std::min<int>(opts->max_iter, rz::kMaxIter);
   if (opts) {
-    if (opts->precision != RZ_FP64 && opts->precision != RZ_FP32_IR) return fail(RZ_ERR_ARG, "unknown precision");
+    if (opts->precision != RZ_FP64 && opts->precision != RZ_FP32_IR && opts->precision != RZ_FP32_PC)
+      return fail(RZ_ERR_ARG, "unknown precision");
     if (!(opts->inner_rtol < 1.0)) return fail(RZ_ERR_ARG, "inner_rtol must be below 1");
     P->precision = opts->precision;
     if (opts->inner_rtol > 0.0) P->inner_rtol = opts->inner_rtol;
@@ -434,15 +435,17 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     P->dps.resize(P->patches.size());
     for (size_t i = 0; i < P->patches.size(); ++i) setup_patch_set(*P, P->patches[i], P->dps[i], s);
     setup_coarse(*P, s);
-    if (P->precision == RZ_FP32_IR) {
-      // FP32 copies of everything the correction solves read
+    if (P->precision != RZ_FP64) {
+      // FP32 copies: the inverses (both modes) and the operator tables (refinement)
       auto lo = [&](const double *a, int64_t count) {
         float *b = P->dev<float>(size_t(count));
         rz::launch_to_float(count, a, b, s);
         return static_cast<const float *>(b);
       };
-      P->at.Afrag32 = lo(P->Afrag, int64_t(P->at.NP) * P->at.KP * Q);
-      P->at.w32 = lo(P->w, nc * Q);
+      if (P->precision == RZ_FP32_IR) {
+        P->at.Afrag32 = lo(P->Afrag, int64_t(P->at.NP) * P->at.KP * Q);
+        P->at.w32 = lo(P->w, nc * Q);
+      }
       for (auto &d : P->dps) {
         std::vector<int64_t> off32(d.sizes.size());
         int64_t tot32 = 0;
@@ -543,7 +546,7 @@ static void ensure_ws(rz_problem *P, int ncol) {
     P->hs = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
     P->hd = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
   }
-  if (P->precision != RZ_FP64) {
+  if (P->precision == RZ_FP32_IR) {
     P->sto = static_cast<rz::PcgState *>(alloc(sizeof(rz::PcgState) * ncol));
     HIPCHK(hipHostMalloc((void **)&P->sto_host, sizeof(rz::PcgState) * ncol, hipHostMallocDefault));
     P->ro = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
@@ -560,6 +563,9 @@ static void ensure_ws(rz_problem *P, int ncol) {
   }
 }
 
+// which pieces read the FP32 copies: the operator, the patch/coarse inverses
+constexpr unsigned kLoA = 1, kLoP = 2;
+
 // Symmetric multiplicative hybrid (Sec. 7.1): groups X_I (point-Jacobi),
 // X_Gamma (additive interface patches) and W (exact coarse solve), swept
 // I, Gamma, W, Gamma, I with z += rho_m^{-1} B_m (b - A z).  The residual
@@ -568,25 +574,26 @@ static void ensure_ws(rz_problem *P, int ncol) {
 // carry the Whitney dofs) and subtracted from s.  With st the first kernel
 // also takes the PCG convergence test (partR: block partials of ||r||^2).
 static void hybrid_apply(rz_problem *P, const double *r, int64_t ldr, double *z, int64_t ldz, int nc,
-                         rz::PcgState *st, const double *partR, int RB, bool lo, hipStream_t s) {
+                         rz::PcgState *st, const double *partR, int RB, unsigned lo, hipStream_t s) {
+  const bool loA = lo & kLoA, loP = lo & kLoP;
   const int64_t nd = P->top.n_dofs;
   const int n = P->el.n;
   const double w1 = 1.0 / P->rho_I, w2 = 1.0 / P->rho_G;
   double *sres = P->hs, *d = P->hd;
   rz::launch_hyb_init(nd, P->off_I, P->dinv, w1, r, ldr, z, ldz, sres, partR, RB, nc, st, s);
-  if (P->col_int < n) rz::launch_apply_A(P->at, z, ldz, sres, nd, nc, st, s, lo, P->col_int, n, -1.0);
+  if (P->col_int < n) rz::launch_apply_A(P->at, z, ldz, sres, nd, nc, st, s, loA, P->col_int, n, -1.0);
   auto interface = [&]() {
     rz::launch_fill(d, nd, nd, nc, st, s);
-    for (auto &pa : P->pas) rz::launch_patch_apply(pa, sres, nd, d, nd, nc, st, s, lo, w2);
+    for (auto &pa : P->pas) rz::launch_patch_apply(pa, sres, nd, d, nd, nc, st, s, loP, w2);
     rz::launch_add(nd, d, z, ldz, nc, st, s);
-    rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, lo, 0, P->col_int, -1.0);
+    rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, loA, 0, P->col_int, -1.0);
   };
   interface();
   rz::launch_coarse_gather(P->ca, sres, nd, nc, s);
-  rz::launch_coarse_tiles(P->ca, nc, st, s, lo);
+  rz::launch_coarse_tiles(P->ca, nc, st, s, loP);
   rz::launch_fill(d, nd, nd, nc, st, s);
   rz::launch_coarse_scatter2(P->ca, nd, d, z, ldz, nc, st, s);
-  rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, lo, P->col_w0, P->col_w1, -1.0);
+  rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, loA, P->col_w0, P->col_w1, -1.0);
   interface();
   rz::launch_jacobi_add(nd, P->off_I, P->dinv, w1, sres, z, ldz, nc, st, s);
 }
@@ -677,7 +684,7 @@ static int apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int
                    bool lo) {
   if (!P || !x || !y) return fail(RZ_ERR_ARG, "null argument");
   if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
-  if (lo && !P->at.Afrag32) return fail(RZ_ERR_ARG, "FP32 copies exist only for handles set up with RZ_FP32_IR");
+  if (lo && !P->at.Afrag32) return fail(RZ_ERR_ARG, "FP32 operator copies exist only for RZ_FP32_IR handles");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   rz::launch_fill(y, P->top.n_dofs, ld, n_rhs, nullptr, s);
   rz::launch_apply_A(P->at, x, ld, y, ld, n_rhs, nullptr, s, lo);
@@ -690,15 +697,19 @@ static int apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int
                    bool lo) {
   if (!P || !r || !z) return fail(RZ_ERR_ARG, "null argument");
   if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
-  if (lo && !P->at.Afrag32) return fail(RZ_ERR_ARG, "FP32 copies exist only for handles set up with RZ_FP32_IR");
+  if (lo && !P->ca.tiles32)
+    return fail(RZ_ERR_ARG, "FP32 inverse copies exist only for RZ_FP32_IR and RZ_FP32_PC handles");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   try {
     ensure_ws(P, n_rhs);
   } catch (const RzError &e) {
     return fail(e.code, e.msg);
   }
+  // the FP32 preconditioner of the handle's precision: inverses, plus the
+  // operator inside the hybrid sweep under refinement
+  const unsigned m = lo ? (kLoP | (P->at.Afrag32 ? kLoA : 0u)) : 0u;
   if (P->pc == RZ_PC_HYBRID)
-    hybrid_apply(P, r, ld, z, ld, n_rhs, nullptr, nullptr, 0, lo, s);
+    hybrid_apply(P, r, ld, z, ld, n_rhs, nullptr, nullptr, 0, m, s);
   else
     rz::launch_apply_P(P->pas.data(), int(P->pas.size()), P->ca, P->top.n_dofs, P->off_I, P->dinv, r, ld, z, ld,
                        n_rhs, s, lo);
@@ -736,10 +747,10 @@ static double lanczos_cond(const rz::PcgState &h) {
 }
 
 // PCG (Sec. 7.1) on A x = b over nc columns to ||r_j|| <= tol ||b_j||, from x
-// (or from zero when x_zero).  lo: FP32 operator and preconditioner copies.
+// (or from zero when x_zero).  lo: kLoA / kLoP, which pieces read FP32 copies.
 // outer (or null): columns whose outer state is done are skipped.  On return
 // st_host holds every column's final state.
-static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int64_t ldx, int nc, double tol, bool lo,
+static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int64_t ldx, int nc, double tol, unsigned lo,
                     bool x_zero, const rz::PcgState *outer, hipStream_t s) {
   const int64_t nd = P->top.n_dofs;
   const int maxit = P->max_iter;
@@ -755,7 +766,7 @@ static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int6
   } else {
     // r = b - A x, convergence reference ||b||
     rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
-    rz::launch_apply_A(P->at, x, ldx, P->Ap, nd, nc, nullptr, s, lo);
+    rz::launch_apply_A(P->at, x, ldx, P->Ap, nd, nc, nullptr, s, lo & kLoA);
     rz::launch_residual(nd, b, ldb, P->Ap, P->r, nc, s);
     rz::launch_dot(nd, b, ldb, b, ldb, nofold, npad, P->partB, RB, nc, nullptr, s);
     rz::launch_dot(nd, P->r, nd, P->r, nd, nofold, npad, P->partR, RB, nc, nullptr, s);
@@ -767,7 +778,7 @@ static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int6
     hybrid_apply(P, P->r, nd, P->z, nd, nc, nullptr, nullptr, RB, lo, s);
   else
     rz::launch_apply_P(P->pas.data(), int(P->pas.size()), P->ca, nd, P->off_I, P->dinv, P->r, nd, P->z, nd, nc, s,
-                       lo);
+                       lo & kLoP);
   rz::launch_dot(nd, P->r, nd, P->z, nd, nofold, npad, P->partZ, RB, nc, P->st, s);
   rz::launch_copy(nd, P->z, nd, P->pv, nd, nc, s);
   rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
@@ -777,7 +788,7 @@ static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int6
   for (int it0 = 0; it0 < maxit; it0 += chunk) {
     for (int it = 0; it < chunk; ++it) {
       // Ap was cleared by the previous p update; partZ holds the partials of (r, z)
-      rz::launch_apply_A(P->at, P->pv, nd, P->Ap, nd, nc, P->st, s, lo);
+      rz::launch_apply_A(P->at, P->pv, nd, P->Ap, nd, nc, P->st, s, lo & kLoA);
       rz::launch_dot(nd, P->pv, nd, P->Ap, nd, nofold, npad, P->partA, RB, nc, P->st, s);
       rz::launch_update_xr(nd, x, ldx, P->r, P->pv, P->Ap, P->partZ, P->partA, P->partR, RB, nc, P->st, s);
       if (hyb) {
@@ -789,8 +800,8 @@ static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int6
       }
       // convergence test, then z = P^{-1} r with the coarse part left in zW
       rz::launch_check_jacobi(nd, P->off_I, P->dinv, P->r, P->z, P->ca, P->partR, RB, nc, P->st, s);
-      for (auto &pa : P->pas) rz::launch_patch_apply(pa, P->r, nd, P->z, nd, nc, P->st, s, lo);
-      rz::launch_coarse_tiles(P->ca, nc, P->st, s, lo);
+      for (auto &pa : P->pas) rz::launch_patch_apply(pa, P->r, nd, P->z, nd, nc, P->st, s, lo & kLoP);
+      rz::launch_coarse_tiles(P->ca, nc, P->st, s, lo & kLoP);
       rz::launch_dot(nd, P->r, nd, P->z, nd, P->fold, npad, P->partZ, RB, nc, P->st, s);
       rz::launch_update_p(nd, P->pv, P->z, P->fold, npad, P->Ap, P->partZ, RB, nc, P->st, s);
     }
@@ -819,7 +830,7 @@ static void refine(rz_problem *P, const double *b, double *x, int64_t ld, int nc
   const rz::CoarseFold nofold{nullptr, 0, 0, 1};
   const size_t head = offsetof(rz::PcgState, alphas);
   const int max_outer = 40;
-  bool lo = true;
+  unsigned lo = kLoA | kLoP;
   std::vector<double> prev(nc, 0.0);
   for (int k = 0;; ++k) {
     // true residual and the outer convergence test
@@ -843,7 +854,7 @@ static void refine(rz_problem *P, const double *b, double *x, int64_t ld, int nc
       prev[c] = rel[c];
     }
     if (all || k == max_outer) break;
-    if (worst_ratio > 0.5) lo = false;
+    if (worst_ratio > 0.5) lo = 0;
     // correction solve from zero on the columns that are not yet converged
     pcg_run(P, P->ro, nd, P->dx, nd, nc, P->inner_rtol, lo, true, P->sto, s);
     bool broke = false;
@@ -859,7 +870,7 @@ static void refine(rz_problem *P, const double *b, double *x, int64_t ld, int nc
       }
     }
     if (broke && !lo) break;
-    if (broke) lo = false;
+    if (broke) lo = 0;
     rz::launch_axpy(nd, P->dx, x, ld, nc, s);
   }
   for (int c = 0; c < nc; ++c)
@@ -879,8 +890,9 @@ int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t l
     std::vector<double> cond(nc, 1.0), rel(nc, 0.0);
     std::vector<int> code(nc, RZ_OK);
     auto t0 = std::chrono::steady_clock::now();
-    if (P->precision == RZ_FP64) {
-      pcg_run(P, b, ld, x, ld, nc, rtol, false, false, nullptr, s);
+    if (P->precision != RZ_FP32_IR) {
+      // FP64 operator; FP32 inverses in the preconditioner for RZ_FP32_PC
+      pcg_run(P, b, ld, x, ld, nc, rtol, P->precision == RZ_FP32_PC ? kLoP : 0u, false, nullptr, s);
       for (int c = 0; c < nc; ++c) {
         const rz::PcgState &h = P->st_host[c];
         its[c] = h.iter;

@@ -1,5 +1,6 @@
-"""GPU checks of the mixed-precision path (FP32 applies inside FP64
-iterative refinement) against the FP64 oracle, through the C ABI.
+"""GPU checks of the mixed-precision paths against the FP64 oracle, through
+the C ABI: FP32 applies inside FP64 iterative refinement (RZ_FP32_IR), and
+plain FP64 PCG with an FP32-stored preconditioner (RZ_FP32_PC).
 
 Bars (written per check):
 * FP32 apply_A -- the first-order rounding bound of an FP32 contraction of
@@ -10,6 +11,8 @@ Bars (written per check):
 * FP32 apply_P -- the hybrid sweep with the FP32 operator and inverses:
   max |z32 - z_oracle| <= 1e-4 max |z_oracle| (entries rounded once to
   FP32; accumulation in FP64);
+* FP32-preconditioner solve -- the same residual and solution bars, and
+  at most two iterations more than the oracle's FP64 hybrid PCG;
 * refinement solve -- true residual under the oracle's A <= 1.2 rtol ||b||
   + ||(A_lib - A_oracle) x|| at rtol 1e-10 and 1e-12, ||x - x_oracle|| <=
   1e-10 ||x_oracle|| at rtol 1e-12, at least two refinement steps taken.
@@ -142,3 +145,40 @@ def test_fp32_entry_points_need_fp32_setup():
     x = torch.zeros(prob.n_dofs, dtype=torch.float64, device="cuda")
     with pytest.raises(rz.RzError, match="RZ_FP32_IR"):
         prob.apply_A(x, torch.empty_like(x), fp32=True)
+
+
+_pc_cache = {}
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_fp32_preconditioner_solve(case):
+    from paper_2506_17406_amd import rz
+    top, A, P, _ = setup_case(*case)
+    if case not in _pc_cache:
+        d, fam, p, n = case
+        X, C = kuhn_mesh(n, d, jitter=0.1 if d == 3 else 0.0, seed=13)
+        _pc_cache[case] = rz.Problem(X, C, p, fam, precision="fp32-pc")
+    prob = _pc_cache[case]
+    r = load_vectors(top.n_dofs, 35)[:, 0]
+    zt = torch.empty(top.n_dofs, dtype=torch.float64, device="cuda")
+    prob.apply_P(torch.from_numpy(r).cuda(), zt, fp32=True)
+    torch.cuda.synchronize()
+    ref = P.apply(r)
+    assert np.abs(zt.cpu().numpy() - ref).max() <= 1e-4 * np.abs(ref).max()
+    b = load_vectors(top.n_dofs, 36)[:, 0]
+    bt = torch.from_numpy(b).cuda()
+    xo, io = pcg(lambda v: A @ v, P.apply, b, rtol=1e-12)
+    for rtol in (1e-10, 1e-12):
+        xt = torch.zeros_like(bt)
+        info = prob.solve(bt, xt, rtol=rtol)
+        x = xt.cpu().numpy()
+        assert info["status"] == 0 and info["rel_residual"] <= rtol
+        yt = torch.empty_like(bt)
+        prob.apply_A(xt, yt)
+        Ax = A @ x
+        gap = np.linalg.norm(yt.cpu().numpy() - Ax)
+        assert np.linalg.norm(b - Ax) <= 1.2 * rtol * np.linalg.norm(b) + gap
+        if rtol == 1e-12:
+            assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
+            assert info["iterations"] <= io["iterations"] + 2
+
