@@ -39,10 +39,14 @@ def parse():
     ap.add_argument("--spaces", type=str, default="CG,Ned,RT")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=20)
-    ap.add_argument("--workload", choices=["sweep", "multirhs", "mixed"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "multirhs", "mixed", "batch"], default="sweep",
                     help="sweep: the 3D FP64 sweep (default, the headline line); multirhs: H(div) RT_5 on the "
                          "12^3x6 mesh with 64 right-hand sides, one batched solve vs 64 single solves; mixed: "
-                         "H(curl) Ned_6 on the 16^3x6 mesh, FP32 refinement vs plain FP64 PCG")
+                         "H(curl) Ned_6 on the 16^3x6 mesh, FP32 refinement vs plain FP64 PCG; batch: 32 uneven "
+                         "H(grad)/H(curl) problems solved together vs one by one")
+    ap.add_argument("--batch-count", type=int, default=32)
+    ap.add_argument("--batch-max-gb", type=float, default=240.0)
+    ap.add_argument("--batch-precision", choices=["fp64", "fp32-pc"], default="fp32-pc")
     ap.add_argument("--inner-rtol", type=float, default=0.0)
     ap.add_argument("--pc", choices=["hybrid", "additive"], default="hybrid",
                     help="preconditioner form: the symmetric multiplicative hybrid of the paper's experiments "
@@ -213,6 +217,95 @@ def mixed(args):
     print(json.dumps(line), flush=True)
 
 
+def _batch_bytes(sp, n, p):
+    """Device bytes of one problem, from the largest-patch sizes (interior
+    stars; boundary stars are smaller): FP64 + FP32 patch and coarse
+    inverses, tables and about 16 work vectors."""
+    V, E, F, C = (n + 1) ** 3, 7 * n ** 3 + 9 * n ** 2 + 3 * n, 12 * n ** 3 + 6 * n ** 2, 6 * n ** 3
+    mv = 1 + 14 * (p - 1) + 18 * (p - 1) * (p - 2)
+    if sp == "CG":
+        dofs = V + E * (p - 1) + F * (p - 1) * (p - 2) // 2 + C * (p - 1) * (p - 2) * (p - 3) // 6
+        patches, nW = V * mv * mv / 2, V
+    else:
+        me = 1 + 3 * (p - 1) * (p + 2)
+        dofs = p * E + F * (p - 1) * p + C * (p - 1) * (p - 2) * (p + 1) // 2
+        patches, nW = V * mv * mv / 2 + E * me * me / 2, E
+    return 12.0 * (patches + nW * nW / 2) + 16 * 8 * dofs, dofs
+
+
+def batch(args):
+    """The uneven batch: 32 H(grad)/H(curl) problems with n in 4..16 and p
+    in 2..10 drawn from default_rng(8) (a draw is redrawn while the batch
+    would exceed the memory budget), jittered Kuhn meshes (seed 100 + i),
+    load vectors seed 200 + i, solved together to 1e-10 with captured
+    iteration graphs, against the same problems solved one by one."""
+    import torch
+    from paper_2506_17406_amd import rz
+    from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors, uneven_batch
+    torch.cuda.set_device(0)
+    draws, rng = uneven_batch(8, args.batch_count)
+    budget = args.batch_max_gb * 1e9
+    while sum(_batch_bytes(d[0], d[1], d[2])[0] for d in draws) > budget:
+        # redraw the largest problem from the continuing generator
+        j = max(range(len(draws)), key=lambda k: _batch_bytes(*draws[k][:3])[0])
+        sp = ("CG", "Ned")[int(rng.integers(2))]
+        draws[j] = (sp, int(rng.integers(4, 17)), int(rng.integers(2, 11)), draws[j][3], draws[j][4])
+    probs, bs, xs = [], [], []
+    t0 = time.perf_counter()
+    for sp, n, p, ms, rs in draws:
+        X, C = kuhn_mesh(n, 3, jitter=0.1, seed=ms)
+        t1 = time.perf_counter()
+        prob = rz.Problem(X, C, p, sp, pc=args.pc, precision=args.batch_precision)
+        torch.cuda.synchronize()
+        probs.append(prob)
+        bs.append(torch.from_numpy(load_vectors(prob.n_dofs, rs)[:, 0]).cuda())
+        xs.append(torch.zeros_like(bs[-1]))
+        print(f"setup {sp}{p} n={n}: {prob.n_dofs} dofs in {time.perf_counter() - t1:.1f}s", file=sys.stderr,
+              flush=True)
+    t_setup = time.perf_counter() - t0
+    total = sum(p.n_dofs for p in probs)
+    t1 = time.perf_counter()
+    B = rz.Batch(probs)
+    t_tune = time.perf_counter() - t1
+    for _ in range(args.warmup):
+        for x in xs:
+            x.zero_()
+        B.solve(bs, xs, rtol=1e-10)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        for x in xs:
+            x.zero_()
+        infos = B.solve(bs, xs, rtol=1e-10)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / args.steps
+    print(f"batch: {dt * 1e3:.1f} ms for {total} dofs", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    seq = []
+    for prob, b, x in zip(probs, bs, xs):
+        x.zero_()
+        seq.append(prob.solve(b, x, rtol=1e-10)["iterations"])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t1
+    line = {
+        "metric": "Riesz-map solve DOFs/s to rel. residual 1e-10 (uneven batch)",
+        "value": total / dt, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 operator, f32-stored preconditioner" if args.batch_precision == "fp32-pc" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"uneven batch of {len(probs)} H(grad)/H(curl) Riesz maps, n in 4..16, p in 2..10, "
+                               "jittered Kuhn meshes, rtol 1e-10", "total_dofs": total,
+                   "problems": [f"{d[0]}{d[2]} n={d[1]}" for d in draws], "preconditioner": args.pc,
+                   "setup_s": round(t_setup, 1), "tune_s": round(t_tune, 2)},
+        "iterations": {"min": min(i["iterations"] for i in infos), "max": max(i["iterations"] for i in infos)},
+        "max_rel_residual": max(i["rel_residual"] for i in infos),
+        "sequential": {"value": total / t_seq, "seconds": t_seq},
+        "speedup_vs_sequential": t_seq / dt,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(pc="hybrid"):
     """The oracle, as it stands, on a bounded sample of the workload: the
     H(grad) p=4 and H(curl) p=3 problems of the sweep (same mesh and load
@@ -253,6 +346,8 @@ def main():
         return multirhs(args)
     if args.workload == "mixed":
         return mixed(args)
+    if args.workload == "batch":
+        return batch(args)
     import torch
     from paper_2506_17406_amd import rz
     from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors

@@ -201,6 +201,26 @@ int rz_numbering(const rz_mesh *mesh, int32_t degree, rz_space space, int64_t *n
 
 void rz_destroy(rz_problem *P);
 
+/* Batches of problems of uneven size (different meshes, spaces, degrees),
+ * solved together: each problem runs on a stream of the batch, its PCG
+ * iterations in chunks of 8 that are captured into a HIP graph once per
+ * problem and solution vector and then replayed; at creation the operator
+ * apply of each problem is tuned (cells per wave, by timing).  The problems
+ * stay owned by the caller, must outlive the batch, and must not be used by
+ * other calls while the batch solves.  Not thread-safe. */
+typedef struct rz_batch rz_batch;
+int rz_batch_create(rz_problem *const *problems, int32_t n, rz_batch **out);
+
+/* Solves A_i x_i = b_i for every problem i (one right-hand side each) to
+ * ||r_i|| <= rtol ||b_i||, from the initial guesses in x_i, each with its
+ * handle's precision and preconditioner.  b, x: host arrays of n device
+ * pointers (n_dofs_i doubles each).  Work starts after earlier work on
+ * hip_stream and later work on hip_stream waits for it; returns when done.
+ * info: host, n entries, may be NULL.  Returns the first non-OK status. */
+int rz_batch_solve(rz_batch *B, const double *const *b, double *const *x, double rtol, rz_info *info,
+                   void *hip_stream);
+void rz_batch_destroy(rz_batch *B);
+
 const char *rz_last_error(void);
 
 #ifdef __cplusplus

@@ -69,8 +69,10 @@ struct rz_problem {
   rz::ApplyATables at{};
   std::vector<DevPatchSet> dps;
   rz::CoarseApply ca{};
-  // Krylov workspace for up to ws_cols right-hand sides (grown on demand)
+  // Krylov workspace for up to ws_cols right-hand sides (grown on demand;
+  // ws_gen counts reallocations, so captured graphs can tell they are stale)
   int ws_cols = 0;
+  int ws_gen = 0;
   std::vector<void *> ws;
   rz::PcgState *st = nullptr;
   rz::PcgState *st_host = nullptr;
@@ -518,6 +520,7 @@ static int reduction_blocks(int ncol) { return std::max(4, 512 / std::max(1, nco
 static void ensure_ws(rz_problem *P, int ncol) {
   if (ncol <= P->ws_cols) return;
   P->free_ws();
+  ++P->ws_gen;
   const int64_t nd = P->top.n_dofs;
   const int RB = reduction_blocks(ncol);
   auto alloc = [&](size_t bytes) {
@@ -750,8 +753,9 @@ static double lanczos_cond(const rz::PcgState &h) {
 // (or from zero when x_zero).  lo: kLoA / kLoP, which pieces read FP32 copies.
 // outer (or null): columns whose outer state is done are skipped.  On return
 // st_host holds every column's final state.
-static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int64_t ldx, int nc, double tol, unsigned lo,
-                    bool x_zero, const rz::PcgState *outer, hipStream_t s) {
+// PCG set-up part: r, ||b||, the per-column state, z = P^{-1} r, p = z.
+static void pcg_begin(rz_problem *P, const double *b, int64_t ldb, double *x, int64_t ldx, int nc, double tol,
+                      unsigned lo, bool x_zero, const rz::PcgState *outer, hipStream_t s) {
   const int64_t nd = P->top.n_dofs;
   const int maxit = P->max_iter;
   const int RB = reduction_blocks(nc);
@@ -773,8 +777,7 @@ static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int6
     rz::launch_pcg_start(P->partB, P->partR, RB, tol * tol, maxit, P->st, nc, s, outer);
   }
   // z = P^{-1} r, (r, z), p = z, Ap = 0
-  const bool hyb = P->pc == RZ_PC_HYBRID;
-  if (hyb)
+  if (P->pc == RZ_PC_HYBRID)
     hybrid_apply(P, P->r, nd, P->z, nd, nc, nullptr, nullptr, RB, lo, s);
   else
     rz::launch_apply_P(P->pas.data(), int(P->pas.size()), P->ca, nd, P->off_I, P->dinv, P->r, nd, P->z, nd, nc, s,
@@ -782,32 +785,52 @@ static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int6
   rz::launch_dot(nd, P->r, nd, P->z, nd, nofold, npad, P->partZ, RB, nc, P->st, s);
   rz::launch_copy(nd, P->z, nd, P->pv, nd, nc, s);
   rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
-  HIPCHK(hipGetLastError());
-  const int chunk = 8;
-  const size_t head = offsetof(rz::PcgState, alphas);
-  for (int it0 = 0; it0 < maxit; it0 += chunk) {
-    for (int it = 0; it < chunk; ++it) {
-      // Ap was cleared by the previous p update; partZ holds the partials of (r, z)
-      rz::launch_apply_A(P->at, P->pv, nd, P->Ap, nd, nc, P->st, s, lo & kLoA);
-      rz::launch_dot(nd, P->pv, nd, P->Ap, nd, nofold, npad, P->partA, RB, nc, P->st, s);
-      rz::launch_update_xr(nd, x, ldx, P->r, P->pv, P->Ap, P->partZ, P->partA, P->partR, RB, nc, P->st, s);
-      if (hyb) {
-        // convergence test and the hybrid sweep z = B r
-        hybrid_apply(P, P->r, nd, P->z, nd, nc, P->st, P->partR, RB, lo, s);
-        rz::launch_dot(nd, P->r, nd, P->z, nd, nofold, npad, P->partZ, RB, nc, P->st, s);
-        rz::launch_update_p(nd, P->pv, P->z, nofold, npad, P->Ap, P->partZ, RB, nc, P->st, s);
-        continue;
-      }
-      // convergence test, then z = P^{-1} r with the coarse part left in zW
-      rz::launch_check_jacobi(nd, P->off_I, P->dinv, P->r, P->z, P->ca, P->partR, RB, nc, P->st, s);
-      for (auto &pa : P->pas) rz::launch_patch_apply(pa, P->r, nd, P->z, nd, nc, P->st, s, lo & kLoP);
-      rz::launch_coarse_tiles(P->ca, nc, P->st, s, lo & kLoP);
-      rz::launch_dot(nd, P->r, nd, P->z, nd, P->fold, npad, P->partZ, RB, nc, P->st, s);
-      rz::launch_update_p(nd, P->pv, P->z, P->fold, npad, P->Ap, P->partZ, RB, nc, P->st, s);
+}
+
+// kPcgChunk PCG iterations: kernel launches only (no copies or host
+// work), so the sequence can be captured into a HIP graph.
+constexpr int kPcgChunk = 8;
+static void pcg_chunk(rz_problem *P, double *x, int64_t ldx, int nc, unsigned lo, hipStream_t s) {
+  const int64_t nd = P->top.n_dofs;
+  const int RB = reduction_blocks(nc);
+  const int npad = P->ca.NT * 64;
+  const rz::CoarseFold nofold{nullptr, 0, 0, 1};
+  const bool hyb = P->pc == RZ_PC_HYBRID;
+  for (int it = 0; it < kPcgChunk; ++it) {
+    // Ap was cleared by the previous p update; partZ holds the partials of (r, z)
+    rz::launch_apply_A(P->at, P->pv, nd, P->Ap, nd, nc, P->st, s, lo & kLoA);
+    rz::launch_dot(nd, P->pv, nd, P->Ap, nd, nofold, npad, P->partA, RB, nc, P->st, s);
+    rz::launch_update_xr(nd, x, ldx, P->r, P->pv, P->Ap, P->partZ, P->partA, P->partR, RB, nc, P->st, s);
+    if (hyb) {
+      // convergence test and the hybrid sweep z = B r
+      hybrid_apply(P, P->r, nd, P->z, nd, nc, P->st, P->partR, RB, lo, s);
+      rz::launch_dot(nd, P->r, nd, P->z, nd, nofold, npad, P->partZ, RB, nc, P->st, s);
+      rz::launch_update_p(nd, P->pv, P->z, nofold, npad, P->Ap, P->partZ, RB, nc, P->st, s);
+      continue;
     }
+    // convergence test, then z = P^{-1} r with the coarse part left in zW
+    rz::launch_check_jacobi(nd, P->off_I, P->dinv, P->r, P->z, P->ca, P->partR, RB, nc, P->st, s);
+    for (auto &pa : P->pas) rz::launch_patch_apply(pa, P->r, nd, P->z, nd, nc, P->st, s, lo & kLoP);
+    rz::launch_coarse_tiles(P->ca, nc, P->st, s, lo & kLoP);
+    rz::launch_dot(nd, P->r, nd, P->z, nd, P->fold, npad, P->partZ, RB, nc, P->st, s);
+    rz::launch_update_p(nd, P->pv, P->z, P->fold, npad, P->Ap, P->partZ, RB, nc, P->st, s);
+  }
+}
+
+static void pcg_read_head(rz_problem *P, int nc, hipStream_t s) {
+  const size_t head = offsetof(rz::PcgState, alphas);
+  HIPCHK(hipMemcpy2DAsync(P->st_host, sizeof(rz::PcgState), P->st, sizeof(rz::PcgState), head, nc,
+                          hipMemcpyDeviceToHost, s));
+}
+
+static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int64_t ldx, int nc, double tol, unsigned lo,
+                    bool x_zero, const rz::PcgState *outer, hipStream_t s) {
+  pcg_begin(P, b, ldb, x, ldx, nc, tol, lo, x_zero, outer, s);
+  HIPCHK(hipGetLastError());
+  for (int it0 = 0; it0 < P->max_iter; it0 += kPcgChunk) {
+    pcg_chunk(P, x, ldx, nc, lo, s);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpy2DAsync(P->st_host, sizeof(rz::PcgState), P->st, sizeof(rz::PcgState), head, nc,
-                            hipMemcpyDeviceToHost, s));
+    pcg_read_head(P, nc, s);
     HIPCHK(hipStreamSynchronize(s));
     bool all = true;
     for (int c = 0; c < nc; ++c) all = all && P->st_host[c].done;
@@ -877,6 +900,16 @@ static void refine(rz_problem *P, const double *b, double *x, int64_t ld, int nc
     if (code[c] == RZ_OK && !P->sto_host[c].done) code[c] = RZ_ERR_NO_CONVERGENCE;
 }
 
+// outcome of one PCG column from its final state
+static void column_info(const rz::PcgState &h, int &its, double &cond, double &rel, int &code) {
+  its = h.iter;
+  cond = lanczos_cond(h);
+  rel = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+  code = RZ_OK;
+  if (h.status == rz::PCG_MAXIT || !h.done) code = RZ_ERR_NO_CONVERGENCE;
+  if (h.status == rz::PCG_BREAKDOWN) code = RZ_ERR_BREAKDOWN;
+}
+
 int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t ld, double rtol, rz_info *info,
              void *hip_stream) {
   if (!P || !b || !x) return fail(RZ_ERR_ARG, "null argument");
@@ -893,14 +926,7 @@ int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t l
     if (P->precision != RZ_FP32_IR) {
       // FP64 operator; FP32 inverses in the preconditioner for RZ_FP32_PC
       pcg_run(P, b, ld, x, ld, nc, rtol, P->precision == RZ_FP32_PC ? kLoP : 0u, false, nullptr, s);
-      for (int c = 0; c < nc; ++c) {
-        const rz::PcgState &h = P->st_host[c];
-        its[c] = h.iter;
-        cond[c] = lanczos_cond(h);
-        rel[c] = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
-        if (h.status == rz::PCG_MAXIT || !h.done) code[c] = RZ_ERR_NO_CONVERGENCE;
-        if (h.status == rz::PCG_BREAKDOWN) code[c] = RZ_ERR_BREAKDOWN;
-      }
+      for (int c = 0; c < nc; ++c) column_info(P->st_host[c], its[c], cond[c], rel[c], code[c]);
     } else {
       refine(P, b, x, ld, nc, rtol, its, outer, cond, rel, code, s);
     }
@@ -999,5 +1025,184 @@ int rz_numbering(const rz_mesh *m, int32_t degree, rz_space space, int64_t *n_do
 }
 
 void rz_destroy(rz_problem *P) { delete P; }
+
+}  // extern "C"
+
+// A batch of independent problems solved together: one HIP stream per
+// problem; each problem's PCG iterations run in chunks of kPcgChunk that
+// are captured once into a HIP graph (per problem and solution vector) and
+// replayed, with one host check of the done flags per chunk round.
+struct rz_batch {
+  std::vector<rz_problem *> P;
+  std::vector<hipStream_t> streams;
+  std::vector<hipGraphExec_t> graphs;
+  std::vector<double *> graph_x;  // solution vector each graph was captured for
+  std::vector<int> graph_gen;      // and the problem's workspace generation
+  std::vector<hipEvent_t> done_ev;
+  hipEvent_t start_ev = nullptr;
+  ~rz_batch() {
+    for (auto g : graphs)
+      if (g) (void)hipGraphExecDestroy(g);
+    for (auto e : done_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (start_ev) (void)hipEventDestroy(start_ev);
+    for (auto st : streams)
+      if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+// cells per wave of the single-column operator apply, chosen by timing
+// 16, 32 and 64 cells per wave on the problem itself
+static void autotune_apply(rz_problem *P, hipStream_t s) {
+  const int64_t nd = P->top.n_dofs;
+  ensure_ws(P, 1);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  rz::launch_fill(P->r, nd, nd, 1, nullptr, s);
+  float best = 1e30f;
+  int best_nb = 0;
+  for (int nb : {1, 2, 4}) {
+    P->at.nb1 = nb;
+    rz::launch_apply_A(P->at, P->r, nd, P->Ap, nd, 1, nullptr, s);  // warm-up
+    HIPCHK(hipEventRecord(e0, s));
+    for (int rep = 0; rep < 5; ++rep) rz::launch_apply_A(P->at, P->r, nd, P->Ap, nd, 1, nullptr, s);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) best = ms, best_nb = nb;
+  }
+  P->at.nb1 = best_nb;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+extern "C" {
+
+int rz_batch_create(rz_problem *const *problems, int32_t n, rz_batch **out) {
+  if (!problems || !out || n < 1) return fail(RZ_ERR_ARG, "null argument or empty batch");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i)
+    if (!problems[i]) return fail(RZ_ERR_ARG, "null problem in batch");
+  auto B = std::make_unique<rz_batch>();
+  try {
+    B->P.assign(problems, problems + n);
+    B->streams.assign(n, nullptr);
+    B->graphs.assign(n, nullptr);
+    B->graph_x.assign(n, nullptr);
+    B->graph_gen.assign(n, -1);
+    B->done_ev.assign(n, nullptr);
+    HIPCHK(hipEventCreateWithFlags(&B->start_ev, hipEventDisableTiming));
+    for (int i = 0; i < n; ++i) {
+      HIPCHK(hipStreamCreateWithFlags(&B->streams[i], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&B->done_ev[i], hipEventDisableTiming));
+      autotune_apply(B->P[i], B->streams[i]);
+    }
+  } catch (const RzError &e) {
+    return fail(e.code, e.msg);
+  }
+  *out = B.release();
+  return RZ_OK;
+}
+
+int rz_batch_solve(rz_batch *B, const double *const *b, double *const *x, double rtol, rz_info *info,
+                   void *hip_stream) {
+  if (!B || !b || !x) return fail(RZ_ERR_ARG, "null argument");
+  if (!(rtol > 0.0)) return fail(RZ_ERR_ARG, "rtol must be positive");
+  const int n = int(B->P.size());
+  for (int i = 0; i < n; ++i)
+    if (!b[i] || !x[i]) return fail(RZ_ERR_ARG, "null vector in batch");
+  hipStream_t user = static_cast<hipStream_t>(hip_stream);
+  int worst = RZ_OK;
+  try {
+    auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(hipEventRecord(B->start_ev, user));
+    std::vector<int> active;
+    std::vector<unsigned> lo(n, 0);
+    for (int i = 0; i < n; ++i) {
+      rz_problem *P = B->P[i];
+      hipStream_t s = B->streams[i];
+      HIPCHK(hipStreamWaitEvent(s, B->start_ev, 0));
+      ensure_ws(P, 1);
+      if (P->precision == RZ_FP32_IR) {
+        // refinement drives its own solves; it runs on the problem's stream
+        rz_info inf{};
+        const int code = rz_solve(P, b[i], x[i], 1, P->top.n_dofs, rtol, &inf, s);
+        if (info) info[i] = inf;
+        if (code != RZ_OK && worst == RZ_OK) worst = code;
+        continue;
+      }
+      lo[i] = P->precision == RZ_FP32_PC ? kLoP : 0u;
+      pcg_begin(P, b[i], P->top.n_dofs, x[i], P->top.n_dofs, 1, rtol, lo[i], false, nullptr, s);
+      HIPCHK(hipGetLastError());
+      active.push_back(i);
+    }
+    std::vector<int> rounds(n, 0);
+    while (!active.empty()) {
+      for (int i : active) {
+        rz_problem *P = B->P[i];
+        hipStream_t s = B->streams[i];
+        if (rounds[i] == 0) {
+          // the first chunk runs eagerly (one-time kernel attribute set-up)
+          pcg_chunk(P, x[i], P->top.n_dofs, 1, lo[i], s);
+        } else {
+          if (!B->graphs[i] || B->graph_x[i] != x[i] || B->graph_gen[i] != P->ws_gen) {
+            if (B->graphs[i]) HIPCHK(hipGraphExecDestroy(B->graphs[i]));
+            B->graphs[i] = nullptr;
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            pcg_chunk(P, x[i], P->top.n_dofs, 1, lo[i], s);
+            HIPCHK(hipStreamEndCapture(s, &g));
+            const hipError_t e = hipGraphInstantiate(&B->graphs[i], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) throw RzError{RZ_ERR_DEVICE, hipGetErrorString(e)};
+            B->graph_x[i] = x[i];
+            B->graph_gen[i] = P->ws_gen;
+          }
+          HIPCHK(hipGraphLaunch(B->graphs[i], s));
+        }
+        HIPCHK(hipGetLastError());
+        pcg_read_head(P, 1, s);
+        ++rounds[i];
+      }
+      std::vector<int> next;
+      for (int i : active) {
+        HIPCHK(hipStreamSynchronize(B->streams[i]));
+        if (!B->P[i]->st_host[0].done && rounds[i] * kPcgChunk < B->P[i]->max_iter) next.push_back(i);
+      }
+      active.swap(next);
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    for (int i = 0; i < n; ++i) {
+      rz_problem *P = B->P[i];
+      hipStream_t s = B->streams[i];
+      if (P->precision != RZ_FP32_IR) {
+        HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(rz::PcgState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int its, code;
+        double cond, rel;
+        column_info(P->st_host[0], its, cond, rel, code);
+        if (code != RZ_OK && worst == RZ_OK) worst = code;
+        if (info) {
+          info[i].status = code;
+          info[i].iterations = its;
+          info[i].rel_residual = rel;
+          info[i].cond_estimate = cond;
+          info[i].solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+          info[i].outer_iterations = 0;
+        }
+      }
+      HIPCHK(hipEventRecord(B->done_ev[i], s));
+      HIPCHK(hipStreamWaitEvent(user, B->done_ev[i], 0));
+    }
+  } catch (const RzError &e) {
+    return fail(e.code, e.msg);
+  }
+  if (worst != RZ_OK) return fail(worst, worst == RZ_ERR_BREAKDOWN ? "CG breakdown" : "no convergence");
+  return RZ_OK;
+}
+
+void rz_batch_destroy(rz_batch *B) { delete B; }
 
 }  // extern "C"

@@ -1337,6 +1337,7 @@ void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double 
   // cells per wave: as many as keep >= 2048 waves in flight (A-fragment reuse vs occupancy)
   int NB = 4;
   while (NB > 1 && ((t.n_cells + 16 * NB - 1) / (16 * NB)) * NMB * n_rhs < 2048) NB /= 2;
+  if (n_rhs == 1 && (t.nb1 == 1 || t.nb1 == 2 || t.nb1 == 4)) NB = t.nb1;
   dim3 grid(unsigned((t.n_cells + 16 * NB - 1) / (16 * NB)), unsigned((NMB + 3) / 4), unsigned(n_rhs));
   if (lo && t.Afrag32) {
     if (t.Q == 12) apply_A32_q<12>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);

@@ -42,6 +42,7 @@ struct ApplyATables {
   int64_t n_cells;
   const float *Afrag32;     // FP32 copies for the mixed-precision inner operator (or null)
   const float *w32;
+  int nb1;                  // cells per wave (16 nb1) for single-column applies; 0: by occupancy
 };
 // y += A x for n_rhs columns (y must be zeroed by the caller); st: per-column
 // state (columns that are done are skipped) or null; lo: the FP32 copies

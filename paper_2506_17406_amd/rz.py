@@ -71,6 +71,9 @@ def _load():
         "rz_numbering": (ctypes.c_int, [ctypes.POINTER(RzMesh), i32, ctypes.c_int, pi64, pi32, pi64, pi64, pi64,
                                         pi32]),
         "rz_destroy": (None, [P]),
+        "rz_batch_create": (ctypes.c_int, [ctypes.POINTER(P), i32, ctypes.POINTER(P)]),
+        "rz_batch_solve": (ctypes.c_int, [P, ctypes.POINTER(P), ctypes.POINTER(P), dbl, ctypes.POINTER(RzInfo), P]),
+        "rz_batch_destroy": (None, [P]),
         "rz_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -229,3 +232,47 @@ class Problem:
         _check(lib.rz_export_topology(self._h, _ptr(cd, ctypes.c_int32), None, None, _ptr(ptr, ctypes.c_int64),
                                       _ptr(dofs, ctypes.c_int32)))
         return cd, ptr, dofs
+
+
+class Batch:
+    """Several set-up problems solved together (rz_batch_create / rz_batch_solve)."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        hs = (ctypes.c_void_p * len(self.problems))(*[p._h.value for p in self.problems])
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(lib.rz_batch_create(hs, len(self.problems), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            lib.rz_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, bs, xs, rtol=1e-10, stream=None, check=True):
+        """bs, xs: lists of contiguous float64 device vectors, one per problem."""
+        n = len(self.problems)
+        if len(bs) != n or len(xs) != n:
+            raise ValueError("one b and one x per problem")
+        for p, b, x in zip(self.problems, bs, xs):
+            for v in (b, x):
+                Problem._dev(v)
+                if v.dim() != 1 or not v.is_contiguous() or v.numel() != p.n_dofs:
+                    raise ValueError("vectors must be contiguous with n_dofs entries")
+        bp = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
+        xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        info = (RzInfo * n)()
+        code = lib.rz_batch_solve(self._h, bp, xp, rtol, info, _stream(stream))
+        if check:
+            _check(code)
+        return [dict(status=i.status, iterations=i.iterations, rel_residual=i.rel_residual,
+                     cond_estimate=i.cond_estimate, solve_ms=i.solve_ms, outer_iterations=i.outer_iterations,
+                     code=code) for i in info]
+

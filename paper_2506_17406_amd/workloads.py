@@ -70,3 +70,20 @@ def kuhn_counts(n, dim=3):
     if dim == 3:
         return ((n + 1) ** 3, 7 * n ** 3 + 9 * n ** 2 + 3 * n, 12 * n ** 3 + 6 * n ** 2, 6 * n ** 3)
     return ((n + 1) ** 2, 3 * n ** 2 + 2 * n, 2 * n ** 2)
+
+
+def uneven_batch(seed=8, count=32, spaces=("CG", "Ned"), n_range=(4, 16), p_range=(2, 10)):
+    """Draws of the uneven batch: `count` problems, each (space, n, p,
+    mesh_seed, rhs_seed) with space, n and p uniform from default_rng(seed)
+    in that order per problem, mesh seed 100 + i and load-vector seed
+    200 + i.  Further draws continue the same generator (for re-drawing a
+    problem that does not fit)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        sp = spaces[int(rng.integers(len(spaces)))]
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        p = int(rng.integers(p_range[0], p_range[1] + 1))
+        out.append((sp, n, p, 100 + i, 200 + i))
+    return out, rng
+
