@@ -52,6 +52,9 @@ def parse():
                     help="preconditioner form: the symmetric multiplicative hybrid of the paper's experiments "
                          "(default) or the additive Schwarz form")
     ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--profile-copy-bytes", type=int, default=0,
+                    help="after the measurement, one plain device copy of this many bytes (a known-size kernel "
+                         "that calibrates HBM counters in profiler runs)")
     return ap.parse_args()
 
 
@@ -412,6 +415,11 @@ def main():
     torch.cuda.synchronize()
     t_prec = ev0.elapsed_time(ev1) / 1e3 / args.apply_reps
 
+    # HBM traffic of the roofline kernel from committed counter runs, if they
+    # were taken on the current kernel source
+    from paper_2506_17406_amd.profile_summary import read_traffic
+    tr = read_traffic(os.path.join(ROOT, "profiles", "apply_A_Ned8_sweep_traffic.md"))
+    traffic = float(tr["traffic_bytes_per_launch"]) if tr and big["fam"] == "Ned" and big["p"] == 8 else None
     per = [dict(space=e["fam"], p=e["p"], dofs=e["prob"].n_dofs, its=i["iterations"],
                 rel_res=i["rel_residual"], cond=round(i["cond_estimate"], 3), solve_ms=round(i["solve_ms"], 3))
            for e, i in zip(probs, infos)]
@@ -434,7 +442,7 @@ def main():
                    "preconditioner": args.pc},
         "roofline": {"kernel": f"apply_A ({big['fam']}{big['p']})", "bound": "mfma",
                      "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops, "launch_us": t_apply * 1e6},
         "apply_P_us": t_prec * 1e6,
         "per_problem": per,
@@ -442,6 +450,11 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.pc)
     print(json.dumps(line), flush=True)
+    if args.profile_copy_bytes > 0:
+        src = torch.empty(args.profile_copy_bytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

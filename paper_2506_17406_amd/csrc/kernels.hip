@@ -410,12 +410,14 @@ __global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A,
 // matrices; the A fragments of all q for one k-step are contiguous (fragment
 // order (mb, jb, q, lane)).  The next k-step's fragments and x values are
 // loaded before the current step's Q*NB MFMAs are issued.
-template <int Q, int NB>
-__global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int kb0, int kb1, int64_t nc, const double *__restrict__ Af,
+template <int Q, int NB, bool FULL>
+__global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int kb0_, int kb1_, int64_t nc, const double *__restrict__ Af,
                                                  const double *__restrict__ w, const int32_t *__restrict__ cd,
                                                  const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
                                                  int64_t ldy, double alpha, const PcgState *st) {
   if (st && st[blockIdx.z].done) return;
+  // the k-block range: all of them, or the columns of a restricted apply
+  const int kb0 = FULL ? 0 : kb0_, kb1 = FULL ? KB : kb1_;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mb = blockIdx.y * 4 + wave;
   if (mb >= NMB) return;
@@ -486,12 +488,14 @@ __global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int kb0
 // the same wave decomposition as k_apply_A with FP32 tables, weights and
 // MFMA (FP32 accumulation); y stays FP64.
 typedef float f4 __attribute__((ext_vector_type(4)));
-template <int Q, int NB>
-__global__ __launch_bounds__(256) void k_apply_A32(int n, int NMB, int KB, int kb0, int kb1, int64_t nc, const float *__restrict__ Af,
+template <int Q, int NB, bool FULL>
+__global__ __launch_bounds__(256) void k_apply_A32(int n, int NMB, int KB, int kb0_, int kb1_, int64_t nc, const float *__restrict__ Af,
                                                    const float *__restrict__ w, const int32_t *__restrict__ cd,
                                                    const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
                                                    int64_t ldy, double alpha, const PcgState *st) {
   if (st && st[blockIdx.z].done) return;
+  // the k-block range: all of them, or the columns of a restricted apply
+  const int kb0 = FULL ? 0 : kb0_, kb1 = FULL ? KB : kb1_;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mb = blockIdx.y * 4 + wave;
   if (mb >= NMB) return;
@@ -1306,12 +1310,19 @@ template <int Q>
 static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1, const double *x, int64_t ldx,
                       double *y, int64_t ldy, double alpha, const PcgState *st, hipStream_t s) {
   const int KB = t.KP / 4, NMB = t.NP / 16;
-#define RZ_A64(NBV)                                                                                         \
-  hipLaunchKernelGGL((k_apply_A<Q, NBV>), grid, dim3(256), 0, s, t.n, NMB, KB, kb0, kb1, t.n_cells, t.Afrag, \
+  const bool full = kb0 == 0 && kb1 == KB;
+#define RZ_A64(NBV, F)                                                                                          \
+  hipLaunchKernelGGL((k_apply_A<Q, NBV, F>), grid, dim3(256), 0, s, t.n, NMB, KB, kb0, kb1, t.n_cells, t.Afrag, \
                      t.w, t.cell_dofs, x, ldx, y, ldy, alpha, st)
-  if (NB == 4) RZ_A64(4);
-  else if (NB == 2) RZ_A64(2);
-  else RZ_A64(1);
+  if (full) {
+    if (NB == 4) RZ_A64(4, true);
+    else if (NB == 2) RZ_A64(2, true);
+    else RZ_A64(1, true);
+  } else {
+    if (NB == 4) RZ_A64(4, false);
+    else if (NB == 2) RZ_A64(2, false);
+    else RZ_A64(1, false);
+  }
 #undef RZ_A64
 }
 
@@ -1319,12 +1330,19 @@ template <int Q>
 static void apply_A32_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1, const double *x, int64_t ldx,
                         double *y, int64_t ldy, double alpha, const PcgState *st, hipStream_t s) {
   const int KB = t.KP / 4, NMB = t.NP / 16;
-#define RZ_A32(NBV)                                                                                             \
-  hipLaunchKernelGGL((k_apply_A32<Q, NBV>), grid, dim3(256), 0, s, t.n, NMB, KB, kb0, kb1, t.n_cells, t.Afrag32, \
-                     t.w32, t.cell_dofs, x, ldx, y, ldy, alpha, st)
-  if (NB == 4) RZ_A32(4);
-  else if (NB == 2) RZ_A32(2);
-  else RZ_A32(1);
+  const bool full = kb0 == 0 && kb1 == KB;
+#define RZ_A32(NBV, F)                                                                                            \
+  hipLaunchKernelGGL((k_apply_A32<Q, NBV, F>), grid, dim3(256), 0, s, t.n, NMB, KB, kb0, kb1, t.n_cells,         \
+                     t.Afrag32, t.w32, t.cell_dofs, x, ldx, y, ldy, alpha, st)
+  if (full) {
+    if (NB == 4) RZ_A32(4, true);
+    else if (NB == 2) RZ_A32(2, true);
+    else RZ_A32(1, true);
+  } else {
+    if (NB == 4) RZ_A32(4, false);
+    else if (NB == 2) RZ_A32(2, false);
+    else RZ_A32(1, false);
+  }
 #undef RZ_A32
 }
 
