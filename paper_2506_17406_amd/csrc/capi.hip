@@ -433,6 +433,25 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     P->at.w = P->w;
     P->at.cell_dofs = P->cell_dofs;
     P->at.n_cells = nc;
+    // assembly lists of the three-stage apply: for every dof, the positions
+    // of its (cell, local row) results in Yc, cells ascending
+    {
+      const int64_t ncp = (nc + 63) / 64 * 64;
+      const int64_t nd = P->top.n_dofs;
+      if (int64_t(P->at.NP) * ncp >= (int64_t(1) << 31))
+        throw RzError{RZ_ERR_UNSUPPORTED, "mesh too large for 32-bit cell-local indices"};
+      std::vector<int64_t> ptr(nd + 1, 0);
+      for (int64_t e = 0; e < nc * n; ++e) ++ptr[P->top.cell_dofs[e] + 1];
+      for (int64_t i = 0; i < nd; ++i) ptr[i + 1] += ptr[i];
+      std::vector<int32_t> ent(size_t(nc) * n);
+      std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+      for (int64_t c = 0; c < nc; ++c)
+        for (int r = 0; r < n; ++r) ent[fill[P->top.cell_dofs[c * n + r]]++] = int32_t(rz::yc_index(ncp, c, r));
+      P->at.ncp = ncp;
+      P->at.n_dofs = nd;
+      P->at.asm_ptr = P->upload(ptr, s);
+      P->at.asm_ent = P->upload(ent, s);
+    }
     // interface patches and coarse space
     P->dps.resize(P->patches.size());
     for (size_t i = 0; i < P->patches.size(); ++i) setup_patch_set(*P, P->patches[i], P->dps[i], s);
@@ -545,6 +564,10 @@ static void ensure_ws(rz_problem *P, int ncol) {
   P->ca.rW = static_cast<double *>(alloc(sizeof(double) * npad * ncol));
   P->ca.zW = static_cast<double *>(alloc(sizeof(double) * npad * ncol));
   P->fold.zW = P->ca.zW;
+  // cell-local work vectors of the three-stage operator apply
+  P->at.Xc = static_cast<double *>(alloc(sizeof(double) * size_t(P->at.KP) * P->at.ncp * ncol));
+  P->at.Yc = static_cast<double *>(alloc(sizeof(double) * size_t(P->at.NP) * P->at.ncp * ncol));
+  P->at.ws_cols = ncol;
   if (P->pc == RZ_PC_HYBRID) {
     P->hs = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
     P->hd = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
@@ -689,6 +712,11 @@ static int apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int
   if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
   if (lo && !P->at.Afrag32) return fail(RZ_ERR_ARG, "FP32 operator copies exist only for RZ_FP32_IR handles");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  try {
+    ensure_ws(P, n_rhs);
+  } catch (const RzError &e) {
+    return fail(e.code, e.msg);
+  }
   rz::launch_fill(y, P->top.n_dofs, ld, n_rhs, nullptr, s);
   rz::launch_apply_A(P->at, x, ld, y, ld, n_rhs, nullptr, s, lo);
   hipError_t e = hipGetLastError();

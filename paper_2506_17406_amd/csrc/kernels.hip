@@ -410,11 +410,44 @@ __global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A,
 // matrices; the A fragments of all q for one k-step are contiguous (fragment
 // order (mb, jb, q, lane)).  The next k-step's fragments and x values are
 // loaded before the current step's Q*NB MFMAs are issued.
+// ---- FP64 operator apply in three stages: cell gather, GEMM, assembly.
+// Cell-local vectors in MFMA fragment order (ncp = cells rounded up to 64; per
+// column KP ncp doubles of Xc and NP ncp of Yc):
+//   Xc[(kb ncp + c16) 4 + kk 16 + ci] = x[cell_dofs[cell][4 kb + kk]]
+//     (cell = c16 + ci, c16 a multiple of 16; zero beyond n and for padding
+//     cells): lane l of a B fragment reads kk = l / 16, ci = l % 16;
+//   Yc[yc_index(ncp, cell, r)] = (A_T x_T)_r, with the accumulator element v
+//     of lane l (row 16 mb + l/16 + 4v, cell c16 + l % 16) at
+//     (mb ncp + c16) 16 + 64 v + l: 16 rows x 16 cells per (mb, c16) block.
+__global__ void k_gather_cells(int n, int KP, int64_t nc, int64_t ncp, int kb0, int kb1,
+                               const int32_t *__restrict__ cd, const double *__restrict__ x, int64_t ldx,
+                               double *__restrict__ Xc, const PcgState *st) {
+  const int c = blockIdx.y;
+  if (st && st[c].done) return;
+  const double *xc = x + int64_t(c) * ldx;
+  double *X = Xc + int64_t(c) * KP * ncp + int64_t(kb0) * ncp * 4;
+  const int64_t nblk = ncp / 16;
+  const int64_t total = int64_t(kb1 - kb0) * ncp * 4;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int ci = int(t & 15), kk = int((t >> 4) & 3);
+    const int64_t b = t >> 6;
+    const int64_t cell = (b % nblk) * 16 + ci;
+    const int k = (kb0 + int(b / nblk)) * 4 + kk;
+    X[t] = (cell < nc && k < n) ? xc[cd[cell * n + k]] : 0.0;
+  }
+}
+
+// Yc = sum_q w_q R_q Xc over the k-blocks [kb0, kb1), per cell: one wave owns
+// a 16-row block of 16 NB cells; per k-step the A fragments of all Q
+// reference matrices and the B fragments (w_q x) are in registers, and the
+// next k-step's are loaded before the current MFMAs.  All loads are plain
+// (no indirection), so the prefetch is never serialised behind a dependent
+// load.
 template <int Q, int NB, bool FULL>
-__global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int kb0_, int kb1_, int64_t nc, const double *__restrict__ Af,
-                                                 const double *__restrict__ w, const int32_t *__restrict__ cd,
-                                                 const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
-                                                 int64_t ldy, double alpha, const PcgState *st) {
+__global__ __launch_bounds__(256) void k_apply_A(int NMB, int KB, int kb0_, int kb1_, int64_t nc, int64_t ncp,
+                                                 const double *__restrict__ Af, const double *__restrict__ w,
+                                                 const double *__restrict__ Xc, double *__restrict__ Yc, int KP,
+                                                 int NP, const PcgState *st) {
   if (st && st[blockIdx.z].done) return;
   // the k-block range: all of them, or the columns of a restricted apply
   const int kb0 = FULL ? 0 : kb0_, kb1 = FULL ? KB : kb1_;
@@ -422,45 +455,35 @@ __global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int kb0
   const int mb = blockIdx.y * 4 + wave;
   if (mb >= NMB) return;
   const int li = lane & 15, lk = lane >> 4;
-  const double *xr = x + int64_t(blockIdx.z) * ldx;
-  double *yr = y + int64_t(blockIdx.z) * ldy;
+  const double *X = Xc + int64_t(blockIdx.z) * KP * ncp + lane;
+  double *Y = Yc + int64_t(blockIdx.z) * NP * ncp + lane;
   const int64_t cell0 = int64_t(blockIdx.x) * (16 * NB);
-  const int32_t *cdp[NB];
   double wv[NB][Q];
-  bool valid[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int64_t c = cell0 + nb * 16 + li;
-    valid[nb] = c < nc;
-    const int64_t cc = valid[nb] ? c : nc - 1;
-    cdp[nb] = cd + cc * n;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) wv[nb][q] = valid[nb] ? w[cc * Q + q] : 0.0;
+    for (int q = 0; q < Q; ++q) wv[nb][q] = c < nc ? w[c * Q + q] : 0.0;
   }
   d4 acc[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) acc[nb] = d4{0, 0, 0, 0};
   const double *Ab = Af + size_t(mb) * KB * Q * 64 + lane;
+  // B fragment of cells cell0 + 16 nb .. + 15 at k-block kb: 64 consecutive doubles
+  auto xfrag = [&](int kb, int nb) { return X[(int64_t(kb) * ncp + cell0 + nb * 16) * 4]; };
   double a0[Q], x0[NB];
 #pragma unroll
   for (int q = 0; q < Q; ++q) a0[q] = Ab[size_t(kb0) * Q * 64 + q * 64];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) x0[nb] = kb0 * 4 + lk < n ? xr[cdp[nb][kb0 * 4 + lk]] : 0.0;
+  for (int nb = 0; nb < NB; ++nb) x0[nb] = xfrag(kb0, nb);
   for (int jb = kb0; jb < kb1; ++jb) {
     double a1[Q], x1[NB];
-    if (jb + 1 < kb1) {
-      const double *An = Ab + size_t(jb + 1) * Q * 64;
+    const int jn = jb + 1 < kb1 ? jb + 1 : jb;  // the last step reloads its own (unused) fragments
+    const double *An = Ab + size_t(jn) * Q * 64;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) a1[q] = An[q * 64];
-      const int col = (jb + 1) * 4 + lk;
+    for (int q = 0; q < Q; ++q) a1[q] = An[q * 64];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) x1[nb] = col < n ? xr[cdp[nb][col]] : 0.0;
-    } else {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) a1[q] = 0.0;
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) x1[nb] = 0.0;
-    }
+    for (int nb = 0; nb < NB; ++nb) x1[nb] = xfrag(jn, nb);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -471,15 +494,27 @@ __global__ __launch_bounds__(256) void k_apply_A(int n, int NMB, int KB, int kb0
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) x0[nb] = x1[nb];
   }
+  // FP64 16x16x4 accumulator layout: lane l, element v holds row l/16 + 4v,
+  // column (cell) l%16; stored whole, 64 consecutive doubles per (nb, v)
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    if (!valid[nb]) continue;
+  for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      // FP64 16x16x4 accumulator layout: lane l, element v holds row l/16 + 4v, column l%16
-      const int row = mb * 16 + lk + 4 * v;
-      if (row < n) atomicAdd(&yr[cdp[nb][row]], alpha * acc[nb][v]);
-    }
+    for (int v = 0; v < 4; ++v) Y[(int64_t(mb) * ncp + cell0 + nb * 16) * 16 + 64 * v] = acc[nb][v];
+}
+
+// y_i += alpha sum over the (cell, local row) pairs of dof i of Yc (a fixed
+// order: deterministic, no atomics)
+__global__ void k_assemble(int64_t nd, const int64_t *__restrict__ ptr, const int32_t *__restrict__ ent,
+                           int64_t ystride, const double *__restrict__ Yc, double *__restrict__ y, int64_t ldy,
+                           double alpha, const PcgState *st) {
+  const int c = blockIdx.y;
+  if (st && st[c].done) return;
+  const double *Y = Yc + int64_t(c) * ystride;
+  double *yc = y + int64_t(c) * ldy;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nd; i += int64_t(gridDim.x) * blockDim.x) {
+    double sum = 0.0;
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) sum += Y[ent[e]];
+    yc[i] += alpha * sum;
   }
 }
 
@@ -497,12 +532,13 @@ __global__ __launch_bounds__(256) void k_apply_A32(int n, int NMB, int KB, int k
   // the k-block range: all of them, or the columns of a restricted apply
   const int kb0 = FULL ? 0 : kb0_, kb1 = FULL ? KB : kb1_;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int mb = blockIdx.y * 4 + wave;
+  const int2 bxy = make_int2(blockIdx.x, blockIdx.y);
+  const int mb = bxy.y * 4 + wave;
   if (mb >= NMB) return;
   const int li = lane & 15, lk = lane >> 4;
   const double *xr = x + int64_t(blockIdx.z) * ldx;
   double *yr = y + int64_t(blockIdx.z) * ldy;
-  const int64_t cell0 = int64_t(blockIdx.x) * (16 * NB);
+  const int64_t cell0 = int64_t(bxy.x) * (16 * NB);
   const int32_t *cdp[NB];
   float wv[NB][Q];
   bool valid[NB];
@@ -1311,9 +1347,12 @@ static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1
                       double *y, int64_t ldy, double alpha, const PcgState *st, hipStream_t s) {
   const int KB = t.KP / 4, NMB = t.NP / 16;
   const bool full = kb0 == 0 && kb1 == KB;
-#define RZ_A64(NBV, F)                                                                                          \
-  hipLaunchKernelGGL((k_apply_A<Q, NBV, F>), grid, dim3(256), 0, s, t.n, NMB, KB, kb0, kb1, t.n_cells, t.Afrag, \
-                     t.w, t.cell_dofs, x, ldx, y, ldy, alpha, st)
+  const int ncol = int(grid.z);
+  hipLaunchKernelGGL(k_gather_cells, dim3(grid_for(int64_t(kb1 - kb0) * t.ncp * 4, 256, 4096), ncol), dim3(256), 0,
+                     s, t.n, t.KP, t.n_cells, t.ncp, kb0, kb1, t.cell_dofs, x, ldx, t.Xc, st);
+#define RZ_A64(NBV, F)                                                                                        \
+  hipLaunchKernelGGL((k_apply_A<Q, NBV, F>), grid, dim3(256), 0, s, NMB, KB, kb0, kb1, t.n_cells, t.ncp,     \
+                     t.Afrag, t.w, t.Xc, t.Yc, t.KP, t.NP, st)
   if (full) {
     if (NB == 4) RZ_A64(4, true);
     else if (NB == 2) RZ_A64(2, true);
@@ -1324,6 +1363,8 @@ static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1
     else RZ_A64(1, false);
   }
 #undef RZ_A64
+  hipLaunchKernelGGL(k_assemble, dim3(grid_for(t.n_dofs, 256, 4096), ncol), dim3(256), 0, s, t.n_dofs, t.asm_ptr,
+                     t.asm_ent, int64_t(t.NP) * t.ncp, t.Yc, y, ldy, alpha, st);
 }
 
 template <int Q>

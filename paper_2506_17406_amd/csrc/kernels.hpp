@@ -34,6 +34,11 @@ void launch_pack_seg(int64_t B, int N, int E, const int32_t *sizes, const int64_
 void launch_pack_tiles(int N, int n, const double *Ainv, double *tiles, hipStream_t s);
 
 // ---- hot path (multi-column: column c of a vector at base + c * ld)
+// position of row r of cell `cell` in the operator's cell-local result Yc
+inline int64_t yc_index(int64_t ncp, int64_t cell, int r) {
+  const int mb = r / 16, rr = r % 16;
+  return (int64_t(mb) * ncp + (cell & ~int64_t(15))) * 16 + 64 * (rr / 4) + (cell & 15) + 16 * (rr % 4);
+}
 struct ApplyATables {
   int n, Q, NP, KP;         // local dofs, stacked matrices, padded rows, padded k
   const double *Afrag;      // fragment-ordered reference stack
@@ -43,6 +48,14 @@ struct ApplyATables {
   const float *Afrag32;     // FP32 copies for the mixed-precision inner operator (or null)
   const float *w32;
   int nb1;                  // cells per wave (16 nb1) for single-column applies; 0: by occupancy
+  // FP64 three-stage apply: cell-local work vectors (per column KP ncp and
+  // NP ncp doubles, for up to ws_cols columns) and the dof -> (cell, row)
+  // assembly lists (CSR over dofs, entries index Yc)
+  int64_t ncp, n_dofs;
+  double *Xc, *Yc;
+  int ws_cols;
+  const int64_t *asm_ptr;
+  const int32_t *asm_ent;
 };
 // y += A x for n_rhs columns (y must be zeroed by the caller); st: per-column
 // state (columns that are done are skipped) or null; lo: the FP32 copies
