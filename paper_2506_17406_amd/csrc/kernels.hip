@@ -469,31 +469,39 @@ __global__ __launch_bounds__(256) void k_apply_A(int NMB, int KB, int kb0_, int 
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) acc[nb] = d4{0, 0, 0, 0};
   const double *Ab = Af + size_t(mb) * KB * Q * 64 + lane;
-  // B fragment of cells cell0 + 16 nb .. + 15 at k-block kb: 64 consecutive doubles
-  auto xfrag = [&](int kb, int nb) { return X[(int64_t(kb) * ncp + cell0 + nb * 16) * 4]; };
-  double a0[Q], x0[NB];
+  // fragments of k-block kb: the A fragments of all Q matrices and the B
+  // fragments of cells cell0 + 16 nb .. + 15 (64 consecutive doubles each)
+  auto load = [&](int kb, double *a, double *xv) {
+    const double *An = Ab + size_t(kb) * Q * 64;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) a0[q] = Ab[size_t(kb0) * Q * 64 + q * 64];
+    for (int q = 0; q < Q; ++q) a[q] = An[q * 64];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) x0[nb] = xfrag(kb0, nb);
-  for (int jb = kb0; jb < kb1; ++jb) {
-    double a1[Q], x1[NB];
-    const int jn = jb + 1 < kb1 ? jb + 1 : jb;  // the last step reloads its own (unused) fragments
-    const double *An = Ab + size_t(jn) * Q * 64;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) a1[q] = An[q * 64];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) x1[nb] = xfrag(jn, nb);
+    for (int nb = 0; nb < NB; ++nb) xv[nb] = X[(int64_t(kb) * ncp + cell0 + nb * 16) * 4];
+  };
+  auto step = [&](const double *a, const double *xv) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[q], wv[nb][q] * x0[nb], acc[nb], 0, 0, 0);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) a0[q] = a1[q];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) x0[nb] = x1[nb];
+        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], wv[nb][q] * xv[nb], acc[nb], 0, 0, 0);
+  };
+  // two register sets in turn: the loads of one k-block are in flight while
+  // the MFMAs of the other run (no register copies between steps)
+  // (scheduling barriers keep each set's loads ahead of the other's MFMAs)
+  double aA[Q], xA[NB], aB[Q], xB[NB];
+  load(kb0, aA, xA);
+  int jb = kb0;
+  for (; jb + 1 < kb1; jb += 2) {
+    load(jb + 1, aB, xB);
+    __builtin_amdgcn_sched_barrier(0);
+    step(aA, xA);
+    __builtin_amdgcn_sched_barrier(0);
+    load(jb + 2 < kb1 ? jb + 2 : kb1 - 1, aA, xA);  // unconditional: keeps the load waits exact
+    __builtin_amdgcn_sched_barrier(0);
+    step(aB, xB);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  if (jb < kb1) step(aA, xA);
   // FP64 16x16x4 accumulator layout: lane l, element v holds row l/16 + 4v,
   // column (cell) l%16; stored whole, 64 consecutive doubles per (nb, v)
 #pragma unroll
