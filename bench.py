@@ -5,9 +5,12 @@ Workload (one step): the 3D plain-FP64 sweep -- H(grad) (CG_p), H(curl)
 Freudenthal mesh of the unit cube with 8 cells per edge (3072 tetrahedra),
 interior vertices jittered by U(-0.1h, 0.1h) (seed 2), p = 3..8, one
 uniform[-1, 1] load vector per problem (seed 3), each solved from x = 0 to
-||r|| <= 1e-10 ||b||.  Inputs are resident in HBM before timing; setup
-(reference build, numbering, patch and coarse factorisation) is timed
-separately.  value = total dofs solved per step / step time.
+||r|| <= 1e-10 ||b|| with the hybrid preconditioner.  By default the 18
+problems are solved together through the batch interface (a stream per
+problem); the one-after-another time is reported beside it.  Inputs are
+resident in HBM before timing; setup (reference build, numbering, patch and
+coarse factorisation) is timed separately.  value = total dofs solved per
+step / step time.
 
 Also reported: the operator apply (the dominant kernel) against the FP64
 matrix peak, timed with HIP events on the launch stream, and the oracle
@@ -39,6 +42,9 @@ def parse():
     ap.add_argument("--spaces", type=str, default="CG,Ned,RT")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--sweep-mode", choices=["batched", "sequential"], default="batched",
+                    help="sweep step: the 18 problems solved one after another, or together as one batch "
+                         "(a stream per problem, captured iteration graphs)")
     ap.add_argument("--workload", choices=["sweep", "multirhs", "mixed", "batch"], default="sweep",
                     help="sweep: the 3D FP64 sweep (default, the headline line); multirhs: H(div) RT_5 on the "
                          "12^3x6 mesh with 64 right-hand sides, one batched solve vs 64 single solves; mixed: "
@@ -374,22 +380,31 @@ def main():
     t_setup = time.perf_counter() - t_setup
     total_dofs = sum(e["prob"].n_dofs for e in probs)
 
-    def step():
-        out = []
+    batch = rz.Batch([e["prob"] for e in probs])
+
+    def step(batched):
         for e in probs:
             e["x"].zero_()
-            out.append(e["prob"].solve(e["b"], e["x"], rtol=1e-10))
-        return out
+        if batched:
+            return batch.solve([e["b"] for e in probs], [e["x"] for e in probs], rtol=1e-10)
+        return [e["prob"].solve(e["b"], e["x"], rtol=1e-10) for e in probs]
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        infos = step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    print(f"timed {args.steps} steps: {dt * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    def timed(batched):
+        for _ in range(args.warmup):
+            step(batched)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            infos = step(batched)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, infos
+
+    # the headline mode last, so that its solutions are the ones reported
+    other = args.sweep_mode != "batched"
+    dt_other, infos_other = timed(other)
+    dt, infos = timed(not other)
+    print(f"timed {args.steps} steps: {dt * 1e3:.1f} ms/step ({args.sweep_mode}); other mode "
+          f"{dt_other * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
 
     # operator apply on the largest-flop problem, HIP events on the launch stream
     big = max(probs, key=lambda e: e["prob"].Q * e["prob"].n_loc ** 2)
@@ -439,12 +454,15 @@ def main():
         "config": {"workload": f"3D plain FP64 PCG sweep: H(grad)/H(curl)/H(div) x p={args.degrees} on the "
                                f"jittered Kuhn mesh {args.n}^3x6 = {6 * args.n ** 3} tets, rtol 1e-10",
                    "problems": len(probs), "total_dofs": total_dofs, "setup_s": round(t_setup, 2),
-                   "preconditioner": args.pc},
+                   "preconditioner": args.pc, "mode": args.sweep_mode},
         "roofline": {"kernel": f"apply_A ({big['fam']}{big['p']})", "bound": "mfma",
                      "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops, "launch_us": t_apply * 1e6},
         "apply_P_us": t_prec * 1e6,
+        ("sequential" if args.sweep_mode == "batched" else "batched"): {
+            "value": total_dofs / dt_other, "ms_per_step": dt_other * 1e3,
+            "iterations": [i["iterations"] for i in infos_other]},
         "per_problem": per,
     }
     if not args.no_cpu_baseline:

@@ -104,6 +104,10 @@ typedef struct {
   int32_t precision;      /* rz_precision */
   double inner_rtol;      /* refinement: relative residual of each correction solve (<= 0: 1e-4) */
   int32_t pc;             /* rz_pc */
+  int32_t eager;          /* nonzero: rz_solve launches every kernel directly; 0: its PCG iteration
+                             chunks are captured into HIP graphs (per solution vector and column
+                             count) and replayed, on a stream of the handle ordered after and
+                             before the caller's stream */
 } rz_options;
 
 typedef struct {

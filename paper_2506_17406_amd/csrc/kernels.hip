@@ -411,7 +411,7 @@ __global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A,
 // order (mb, jb, q, lane)).  The next k-step's fragments and x values are
 // loaded before the current step's Q*NB MFMAs are issued.
 // ---- FP64 operator apply in three stages: cell gather, GEMM, assembly.
-// Cell-local vectors in MFMA fragment order (ncp = cells rounded up to 64; per
+// Cell-local vectors in MFMA fragment order (ncp = cells rounded up to 256; per
 // column KP ncp doubles of Xc and NP ncp of Yc):
 //   Xc[(kb ncp + c16) 4 + kk 16 + ci] = x[cell_dofs[cell][4 kb + kk]]
 //     (cell = c16 + ci, c16 a multiple of 16; zero beyond n and for padding
@@ -452,12 +452,14 @@ __global__ __launch_bounds__(256) void k_apply_A(int NMB, int KB, int kb0_, int 
   // the k-block range: all of them, or the columns of a restricted apply
   const int kb0 = FULL ? 0 : kb0_, kb1 = FULL ? KB : kb1_;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int mb = blockIdx.y * 4 + wave;
-  if (mb >= NMB) return;
+  // the four waves of a block share the row block (and so the A fragments,
+  // which the vector L1 then serves once) and take consecutive cell groups
+  const int mb = blockIdx.y;
+  (void)NMB;
   const int li = lane & 15, lk = lane >> 4;
   const double *X = Xc + int64_t(blockIdx.z) * KP * ncp + lane;
   double *Y = Yc + int64_t(blockIdx.z) * NP * ncp + lane;
-  const int64_t cell0 = int64_t(blockIdx.x) * (16 * NB);
+  const int64_t cell0 = (int64_t(blockIdx.x) * 4 + wave) * (16 * NB);
   double wv[NB][Q];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
@@ -1412,9 +1414,11 @@ void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double 
     else apply_A32_q<4>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
     return;
   }
-  if (t.Q == 12) apply_A_q<12>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
-  else if (t.Q == 7) apply_A_q<7>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
-  else apply_A_q<4>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
+  // FP64 GEMM: a block is one row block x 4 waves x 16 NB cells
+  const dim3 g64(unsigned((t.n_cells + 64 * NB - 1) / (64 * NB)), unsigned(NMB), unsigned(n_rhs));
+  if (t.Q == 12) apply_A_q<12>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
+  else if (t.Q == 7) apply_A_q<7>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
+  else apply_A_q<4>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
 }
 
 // patch apply: largest G in {8,4,2,1} with G <= ncol, LDS <= 96 KB, MAXJ * G <= 32

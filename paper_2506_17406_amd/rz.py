@@ -33,7 +33,8 @@ PCS = {"additive": RZ_PC_ADDITIVE, "hybrid": RZ_PC_HYBRID}
 
 class RzOptions(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("pc", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("pc", ctypes.c_int32),
+                ("eager", ctypes.c_int32)]
 
 
 class RzInfo(ctypes.Structure):
@@ -139,10 +140,11 @@ class Problem:
     """A set-up Riesz-map problem on the GPU (rz_setup)."""
 
     def __init__(self, coords, cells, degree, space, alpha=1.0, beta=1.0, max_iter=1000, precision="fp64",
-                 inner_rtol=0.0, pc="hybrid", stream=None):
+                 inner_rtol=0.0, pc="hybrid", graphs=True, stream=None):
         m, keep = _mesh(coords, cells)
         prec = PRECISIONS[precision] if isinstance(precision, str) else precision
-        opts = RzOptions(alpha, beta, max_iter, prec, inner_rtol, PCS[pc] if isinstance(pc, str) else pc)
+        opts = RzOptions(alpha, beta, max_iter, prec, inner_rtol, PCS[pc] if isinstance(pc, str) else pc,
+                         0 if graphs else 1)
         h = ctypes.c_void_p()
         self._h = None
         self.space = SPACES[space] if isinstance(space, str) else space

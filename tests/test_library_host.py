@@ -67,16 +67,16 @@ def test_setup_rejects_before_device_work():
     X, C = kuhn_mesh(1)
     m, keep = _mesh_struct(X, C)
     h = ctypes.c_void_p()
-    opts = rz.RzOptions(-1.0, 1.0, 100, 0, 0.0, 0)
+    opts = rz.RzOptions(-1.0, 1.0, 100, 0, 0.0, 0, 0)
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
-    opts = rz.RzOptions(1.0, 0.0, 100, 0, 0.0, 0)
+    opts = rz.RzOptions(1.0, 0.0, 100, 0, 0.0, 0, 0)
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
-    opts = rz.RzOptions(1.0, 1.0, 100, 5, 0.0, 0)           # unknown precision
+    opts = rz.RzOptions(1.0, 1.0, 100, 5, 0.0, 0, 0)           # unknown precision
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
     assert b"precision" in rz.lib.rz_last_error()
-    opts = rz.RzOptions(1.0, 1.0, 100, 1, 1.5, 0)           # inner tolerance >= 1
+    opts = rz.RzOptions(1.0, 1.0, 100, 1, 1.5, 0, 0)           # inner tolerance >= 1
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
-    opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 3)           # unknown preconditioner form
+    opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 3, 0)           # unknown preconditioner form
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
     assert b"preconditioner" in rz.lib.rz_last_error()
     assert rz.lib.rz_setup(None, 2, 0, None, None, ctypes.byref(h)) == -1
