@@ -632,19 +632,26 @@ static void hybrid_apply(rz_problem *P, const double *r, int64_t ldr, double *z,
   double *sres = P->hs, *d = P->hd;
   rz::launch_hyb_init(nd, P->off_I, P->dinv, w1, r, ldr, z, ldz, sres, partR, RB, nc, st, s);
   if (P->col_int < n) rz::launch_apply_A(P->at, z, ldz, sres, nd, nc, st, s, loA, P->col_int, n, -1.0);
-  auto interface = [&]() {
+  // last: only the interior rows of the tracked residual are read afterwards
+  // (by the final Jacobi step), so the second interface correction is
+  // applied with A[I, Gamma] alone (FP64 path)
+  auto interface = [&](bool last) {
     rz::launch_fill(d, nd, nd, nc, st, s);
     for (auto &pa : P->pas) rz::launch_patch_apply(pa, sres, nd, d, nd, nc, st, s, loP, w2);
     rz::launch_add(nd, d, z, ldz, nc, st, s);
-    rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, loA, 0, P->col_int, -1.0);
+    if (last && !loA) {
+      if (P->col_int < n)  // no interior rows: nothing reads the residual again
+        rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, false, 0, P->col_int, -1.0, P->col_int, P->off_I);
+    } else
+      rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, loA, 0, P->col_int, -1.0);
   };
-  interface();
+  interface(false);
   rz::launch_coarse_gather(P->ca, sres, nd, nc, s);
   rz::launch_coarse_tiles(P->ca, nc, st, s, loP);
   rz::launch_fill(d, nd, nd, nc, st, s);
   rz::launch_coarse_scatter2(P->ca, nd, d, z, ldz, nc, st, s);
   rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, loA, P->col_w0, P->col_w1, -1.0);
-  interface();
+  interface(true);
   rz::launch_jacobi_add(nd, P->off_I, P->dinv, w1, sres, z, ldz, nc, st, s);
 }
 

@@ -444,7 +444,7 @@ __global__ void k_gather_cells(int n, int KP, int64_t nc, int64_t ncp, int kb0, 
 // (no indirection), so the prefetch is never serialised behind a dependent
 // load.
 template <int Q, int NB, bool FULL>
-__global__ __launch_bounds__(256) void k_apply_A(int NMB, int KB, int kb0_, int kb1_, int64_t nc, int64_t ncp,
+__global__ __launch_bounds__(256) void k_apply_A(int mb0, int KB, int kb0_, int kb1_, int64_t nc, int64_t ncp,
                                                  const double *__restrict__ Af, const double *__restrict__ w,
                                                  const double *__restrict__ Xc, double *__restrict__ Yc, int KP,
                                                  int NP, const PcgState *st) {
@@ -454,8 +454,7 @@ __global__ __launch_bounds__(256) void k_apply_A(int NMB, int KB, int kb0_, int 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // the four waves of a block share the row block (and so the A fragments,
   // which the vector L1 then serves once) and take consecutive cell groups
-  const int mb = blockIdx.y;
-  (void)NMB;
+  const int mb = mb0 + blockIdx.y;  // row blocks from mb0 (a row-restricted apply starts later)
   const int li = lane & 15, lk = lane >> 4;
   const double *X = Xc + int64_t(blockIdx.z) * KP * ncp + lane;
   double *Y = Yc + int64_t(blockIdx.z) * NP * ncp + lane;
@@ -514,14 +513,14 @@ __global__ __launch_bounds__(256) void k_apply_A(int NMB, int KB, int kb0_, int 
 
 // y_i += alpha sum over the (cell, local row) pairs of dof i of Yc (a fixed
 // order: deterministic, no atomics)
-__global__ void k_assemble(int64_t nd, const int64_t *__restrict__ ptr, const int32_t *__restrict__ ent,
+__global__ void k_assemble(int64_t d0, int64_t d1, const int64_t *__restrict__ ptr, const int32_t *__restrict__ ent,
                            int64_t ystride, const double *__restrict__ Yc, double *__restrict__ y, int64_t ldy,
                            double alpha, const PcgState *st) {
   const int c = blockIdx.y;
   if (st && st[c].done) return;
   const double *Y = Yc + int64_t(c) * ystride;
   double *yc = y + int64_t(c) * ldy;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nd; i += int64_t(gridDim.x) * blockDim.x) {
+  for (int64_t i = d0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < d1; i += int64_t(gridDim.x) * blockDim.x) {
     double sum = 0.0;
     for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) sum += Y[ent[e]];
     yc[i] += alpha * sum;
@@ -1354,14 +1353,16 @@ void launch_pack_tiles(int N, int n, const double *Ainv, double *tiles, hipStrea
 
 template <int Q>
 static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1, const double *x, int64_t ldx,
-                      double *y, int64_t ldy, double alpha, const PcgState *st, hipStream_t s) {
-  const int KB = t.KP / 4, NMB = t.NP / 16;
-  const bool full = kb0 == 0 && kb1 == KB;
+                      double *y, int64_t ldy, double alpha, const PcgState *st, hipStream_t s, int mb0 = 0,
+                      int64_t d0 = 0, int64_t d1 = -1) {
+  const int KB = t.KP / 4;
+  const bool full = kb0 == 0 && kb1 == KB && mb0 == 0;
   const int ncol = int(grid.z);
+  if (d1 < 0) d1 = t.n_dofs;
   hipLaunchKernelGGL(k_gather_cells, dim3(grid_for(int64_t(kb1 - kb0) * t.ncp * 4, 256, 4096), ncol), dim3(256), 0,
                      s, t.n, t.KP, t.n_cells, t.ncp, kb0, kb1, t.cell_dofs, x, ldx, t.Xc, st);
 #define RZ_A64(NBV, F)                                                                                        \
-  hipLaunchKernelGGL((k_apply_A<Q, NBV, F>), grid, dim3(256), 0, s, NMB, KB, kb0, kb1, t.n_cells, t.ncp,     \
+  hipLaunchKernelGGL((k_apply_A<Q, NBV, F>), grid, dim3(256), 0, s, mb0, KB, kb0, kb1, t.n_cells, t.ncp,     \
                      t.Afrag, t.w, t.Xc, t.Yc, t.KP, t.NP, st)
   if (full) {
     if (NB == 4) RZ_A64(4, true);
@@ -1373,8 +1374,9 @@ static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1
     else RZ_A64(1, false);
   }
 #undef RZ_A64
-  hipLaunchKernelGGL(k_assemble, dim3(grid_for(t.n_dofs, 256, 4096), ncol), dim3(256), 0, s, t.n_dofs, t.asm_ptr,
-                     t.asm_ent, int64_t(t.NP) * t.ncp, t.Yc, y, ldy, alpha, st);
+  if (d1 > d0)
+    hipLaunchKernelGGL(k_assemble, dim3(grid_for(d1 - d0, 256, 4096), ncol), dim3(256), 0, s, d0, d1, t.asm_ptr,
+                       t.asm_ent, int64_t(t.NP) * t.ncp, t.Yc, y, ldy, alpha, st);
 }
 
 template <int Q>
@@ -1398,7 +1400,8 @@ static void apply_A32_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int k
 }
 
 void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
-                    const PcgState *st, hipStream_t s, bool lo, int col0, int col1, double alpha) {
+                    const PcgState *st, hipStream_t s, bool lo, int col0, int col1, double alpha, int row0,
+                    int64_t dof0) {
   if (col1 < 0) col1 = t.n;
   if (col0 >= col1) return;
   const int kb0 = col0 / 4, kb1 = (col1 + 3) / 4;
@@ -1414,11 +1417,14 @@ void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double 
     else apply_A32_q<4>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
     return;
   }
-  // FP64 GEMM: a block is one row block x 4 waves x 16 NB cells
-  const dim3 g64(unsigned((t.n_cells + 64 * NB - 1) / (64 * NB)), unsigned(NMB), unsigned(n_rhs));
-  if (t.Q == 12) apply_A_q<12>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
-  else if (t.Q == 7) apply_A_q<7>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
-  else apply_A_q<4>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
+  // FP64 GEMM: a block is one row block x 4 waves x 16 NB cells; a row-
+  // restricted apply starts at the row block of row0 and assembles the dofs
+  // from dof0 on (the interior rows and dofs: both are trailing blocks)
+  const int mb0 = row0 / 16;
+  const dim3 g64(unsigned((t.n_cells + 64 * NB - 1) / (64 * NB)), unsigned(NMB - mb0), unsigned(n_rhs));
+  if (t.Q == 12) apply_A_q<12>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0);
+  else if (t.Q == 7) apply_A_q<7>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0);
+  else apply_A_q<4>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0);
 }
 
 // patch apply: largest G in {8,4,2,1} with G <= ncol, LDS <= 96 KB, MAXJ * G <= 32

@@ -60,10 +60,12 @@ struct ApplyATables {
 // y += A x for n_rhs columns (y must be zeroed by the caller); st: per-column
 // state (columns that are done are skipped) or null; lo: the FP32 copies
 // [col0, col1): only these local columns of A_T take part (x is zero on the
-// others: a restricted apply); y += alpha A x.
+// others: a restricted apply); y += alpha A x.  row0 > 0 (FP64 only): only
+// the local rows from row0 and the global dofs from dof0 are updated (the
+// trailing interior blocks of the local and global numberings).
 void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
                     const PcgState *st, hipStream_t s, bool lo = false, int col0 = 0, int col1 = -1,
-                    double alpha = 1.0);
+                    double alpha = 1.0, int row0 = 0, int64_t dof0 = 0);
 
 // Patch inverse storage: row i of a patch of size m holds the columns
 // [V floor(i/V), V ceil(m/V)) -- zero left of the diagonal and beyond m, the
