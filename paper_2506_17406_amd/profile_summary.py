@@ -4,10 +4,14 @@
         per-kernel calls and durations of a --kernel-trace --stats run
         (rocpd SQLite) as a Markdown table;
     python -m paper_2506_17406_amd.profile_summary traffic <fetch.csv> <write.csv> <kernel> <copy_bytes>
-        HBM bytes per dispatch of <kernel> from two --pmc runs (FETCH_SIZE,
-        then WRITE_SIZE; counter_collection CSVs), each scaled by what the
-        same counter reads for the plain copy kernel of copy_bytes bytes
-        read and written in the same run.  Prints key: value lines.
+        HBM bytes per operator apply whose GEMM is <kernel> (with the fill,
+        gather and assembly dispatched around it) from two --pmc runs
+        (FETCH_SIZE, then WRITE_SIZE; counter_collection CSVs), each scaled by
+        what the same counter reads for the plain copy kernel of copy_bytes
+        bytes read and written in the same run.  Prints key: value lines;
+    python -m paper_2506_17406_amd.profile_summary applies <results.db> <kernel>
+        mean duration of those applies (fill start to assembly end) and of
+        their GEMM kernel in a kernel trace.
 """
 import csv
 import hashlib
@@ -39,31 +43,64 @@ def kernels_sha256():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def _per_dispatch(path, counter):
-    vals = {}
+# one operator apply = fill of y, cell gather, the GEMM kernel, assembly
+APPLY_PARTS = ("k_fill_m", "k_gather_cells", "GEMM", "k_assemble")
+
+
+def _dispatches(path, counter):
+    """(dispatch id, short kernel name, value) in dispatch order."""
+    out = []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] == counter:
-            vals.setdefault(short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
-    return vals
+            out.append((int(r["Dispatch_Id"]), short(r["Kernel_Name"]), float(r["Counter_Value"])))
+    return sorted(out)
+
+
+def _apply_sums(rows, kernel):
+    """Counter sums over each operator apply whose GEMM is `kernel`: the fill
+    and gather dispatched just before it and the assembly just after."""
+    sums = []
+    for i, (_, name, v) in enumerate(rows):
+        if name != kernel or i < 2 or i + 1 >= len(rows):
+            continue
+        parts = [rows[i - 2][1], rows[i - 1][1], name, rows[i + 1][1]]
+        if parts[0] == APPLY_PARTS[0] and parts[1] == APPLY_PARTS[1] and parts[3] == APPLY_PARTS[3]:
+            sums.append(rows[i - 2][2] + rows[i - 1][2] + v + rows[i + 1][2])
+    return sums
 
 
 def traffic(fetch_csv, write_csv, kernel, copy_bytes):
-    f = _per_dispatch(fetch_csv, "FETCH_SIZE")
-    w = _per_dispatch(write_csv, "WRITE_SIZE")
+    f = _dispatches(fetch_csv, "FETCH_SIZE")
+    w = _dispatches(write_csv, "WRITE_SIZE")
 
-    def copy_kib(vals):
+    def copy_kib(rows):
         # the copy kernel: the dispatch whose counter is closest to copy_bytes
-        cands = [v for name, vs in vals.items() if "copy" in name.lower() or "elementwise" in name.lower() for v in vs]
+        cands = [v for _, name, v in rows if "copy" in name.lower() or "elementwise" in name.lower()]
         return min(cands, key=lambda v: abs(v * 1024 - copy_bytes))
 
     ff = copy_bytes / (copy_kib(f) * 1024)
     fw = copy_bytes / (copy_kib(w) * 1024)
-    fk = sum(f[kernel]) / len(f[kernel])
-    wk = sum(w[kernel]) / len(w[kernel])
+    fs, ws = _apply_sums(f, kernel), _apply_sums(w, kernel)
+    fk, wk = sum(fs) / len(fs), sum(ws) / len(ws)
     t = fk * 1024 * ff + wk * 1024 * fw
-    return {"kernel": kernel, "kernels_hip_sha256": kernels_sha256(), "fetch_kib_per_dispatch": fk,
-            "write_kib_per_dispatch": wk, "dispatches": len(f[kernel]), "copy_bytes": copy_bytes,
+    return {"kernel": kernel + " with its fill, gather and assembly", "kernels_hip_sha256": kernels_sha256(),
+            "fetch_kib_per_apply": fk, "write_kib_per_apply": wk, "applies": len(fs), "copy_bytes": copy_bytes,
             "copy_fetch_factor": ff, "copy_write_factor": fw, "traffic_bytes_per_launch": t}
+
+
+def apply_durations(db, kernel):
+    """Durations (us) of the operator applies whose GEMM is `kernel` in a
+    kernel trace: from the start of the fill to the end of the assembly."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, end from kernels order by start").fetchall()
+    rows = [(short(n), s, e) for n, s, e in rows]
+    out = []
+    for i, (name, s, e) in enumerate(rows):
+        if name != kernel or i < 2 or i + 1 >= len(rows):
+            continue
+        if rows[i - 2][0] == APPLY_PARTS[0] and rows[i - 1][0] == APPLY_PARTS[1] and rows[i + 1][0] == APPLY_PARTS[3]:
+            out.append(((rows[i + 1][2] - rows[i - 2][1]) / 1e3, (e - s) / 1e3))
+    return out
 
 
 def read_traffic(path):
@@ -87,3 +124,8 @@ if __name__ == "__main__":
     elif sys.argv[1] == "traffic":
         for k, v in traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5])).items():
             print(f"{k}: {v}")
+    elif sys.argv[1] == "applies":
+        d = [a for a in apply_durations(sys.argv[2], sys.argv[3]) if a[1] > 10.0]
+        print(f"applies: {len(d)}")
+        print(f"apply_us_mean: {sum(a[0] for a in d) / len(d):.1f}")
+        print(f"gemm_us_mean: {sum(a[1] for a in d) / len(d):.1f}")
