@@ -48,11 +48,12 @@ def parse():
     ap.add_argument("--workload", choices=["sweep", "multirhs", "mixed", "batch"], default="sweep",
                     help="sweep: the 3D FP64 sweep (default, the headline line); multirhs: H(div) RT_5 on the "
                          "12^3x6 mesh with 64 right-hand sides, one batched solve vs 64 single solves; mixed: "
-                         "H(curl) Ned_6 on the 16^3x6 mesh, FP32 refinement vs plain FP64 PCG; batch: 32 uneven "
+                         "H(curl) Ned_6 on the 16^3x6 mesh, FP32 refinement and FP32/BF16-stored preconditioners vs "
+                         "plain FP64 PCG; batch: 32 uneven "
                          "H(grad)/H(curl) problems solved together vs one by one")
     ap.add_argument("--batch-count", type=int, default=32)
     ap.add_argument("--batch-max-gb", type=float, default=240.0)
-    ap.add_argument("--batch-precision", choices=["fp64", "fp32-pc"], default="fp32-pc")
+    ap.add_argument("--batch-precision", choices=["fp64", "fp32-pc", "bf16-pc"], default="fp32-pc")
     ap.add_argument("--inner-rtol", type=float, default=0.0)
     ap.add_argument("--pc", choices=["hybrid", "additive"], default="hybrid",
                     help="preconditioner form: the symmetric multiplicative hybrid of the paper's experiments "
@@ -150,10 +151,11 @@ def mixed(args):
     print(f"setup Ned6 n=16 (FP64 + FP32 copies): {pm.n_dofs} dofs in {t_setup:.1f}s", file=sys.stderr, flush=True)
     p64 = rz.Problem(X, C, 6, "Ned", pc=args.pc)
     ppc = rz.Problem(X, C, 6, "Ned", precision="fp32-pc", pc=args.pc)
+    pbf = rz.Problem(X, C, 6, "Ned", precision="bf16-pc", pc=args.pc)
     torch.cuda.synchronize()
-    print("setup FP64 and FP32-preconditioner handles done", file=sys.stderr, flush=True)
+    print("setup FP64, FP32- and BF16-preconditioner handles done", file=sys.stderr, flush=True)
     b = torch.from_numpy(load_vectors(pm.n_dofs, 5)[:, 0]).cuda()
-    xm, x64, xpc = torch.zeros_like(b), torch.zeros_like(b), torch.zeros_like(b)
+    xm, x64, xpc, xbf = torch.zeros_like(b), torch.zeros_like(b), torch.zeros_like(b), torch.zeros_like(b)
 
     def timed(prob, x):
         for _ in range(args.warmup):
@@ -174,6 +176,8 @@ def mixed(args):
     print(f"FP64: {dt_64 * 1e3:.1f} ms, {info_64['iterations']} its", file=sys.stderr, flush=True)
     dt_pc, info_pc = timed(ppc, xpc)
     print(f"FP32 preconditioner: {dt_pc * 1e3:.1f} ms, {info_pc['iterations']} its", file=sys.stderr, flush=True)
+    dt_bf, info_bf = timed(pbf, xbf)
+    print(f"BF16 preconditioner: {dt_bf * 1e3:.1f} ms, {info_bf['iterations']} its", file=sys.stderr, flush=True)
     # true FP64 residuals and the distance between the solutions
     r = torch.empty_like(b)
     nb = b.norm().item()
@@ -182,9 +186,10 @@ def mixed(args):
         p64.apply_A(x, r)
         return (b - r).norm().item() / nb
 
-    res64, res_m, res_pc = true_res(x64), true_res(xm), true_res(xpc)
+    res64, res_m, res_pc, res_bf = true_res(x64), true_res(xm), true_res(xpc), true_res(xbf)
     diff = (xm - x64).norm().item() / x64.norm().item()
     diff_pc = (xpc - x64).norm().item() / x64.norm().item()
+    diff_bf = (xbf - x64).norm().item() / x64.norm().item()
     # dominant kernels: the FP32 and FP64 operator applies, the two preconditioner applies
     xa = torch.rand(pm.n_dofs, dtype=torch.float64, device="cuda")
     ya = torch.empty_like(xa)
@@ -193,19 +198,24 @@ def mixed(args):
     t_a64 = _apply_time(pm.apply_A, xa, ya, reps, stream)
     t_p32 = _apply_time(lambda u, v: pm.apply_P(u, v, fp32=True), xa, ya, reps, stream)
     t_p64 = _apply_time(pm.apply_P, xa, ya, reps, stream)
+    t_pbf = _apply_time(lambda u, v: pbf.apply_P(u, v, fp32=True), xa, ya, reps, stream)
     flops = 2.0 * pm.Q * pm.n_loc ** 2 * pm.n_cells
     tf32 = flops / t_a32 / 1e12
-    best_pc = dt_pc <= dt_m
-    dt_best = dt_pc if best_pc else dt_m
+    # the fastest mode whose true residual meets the target
+    modes = [("bf16-pc", dt_bf, res_bf), ("fp32-pc", dt_pc, res_pc), ("fp32-ir", dt_m, res_m)]
+    mode, dt_best, _ = min((m for m in modes if m[2] <= 1.2e-10), key=lambda m: m[1], default=modes[1])
+    best_pc = mode != "fp32-ir"
     line = {
         "metric": "Riesz-map solve DOFs/s to rel. residual 1e-10 (mixed precision)",
         "value": pm.n_dofs / dt_best, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt_best * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": ("f64 operator, f32-stored preconditioner" if best_pc else "f32 applies, f64 refinement"),
+        "dtype": {"bf16-pc": "f64 operator, bf16-stored preconditioner",
+                  "fp32-pc": "f64 operator, f32-stored preconditioner",
+                  "fp32-ir": "f32 applies, f64 refinement"}[mode],
         "data": "synthetic",
         "config": {"workload": "H(curl) Ned_6 Riesz map, jittered Kuhn 16^3x6 = 24576 tets, mixed precision to "
                                "true FP64 rel. residual 1e-10", "dofs": pm.n_dofs,
-                   "mode": "fp32-pc" if best_pc else "fp32-ir", "preconditioner": args.pc,
+                   "mode": mode, "preconditioner": args.pc,
                    "setup_s": round(t_setup, 2)},
         "roofline": ({"kernel": "apply_A FP64 (Ned6)", "bound": "mfma", "achieved": flops / t_a64 / 1e12,
                       "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": flops / t_a64 / 1e12 / PEAK_FP64_TFLOPS,
@@ -213,6 +223,8 @@ def mixed(args):
                      {"kernel": "apply_A FP32 (Ned6)", "bound": "mfma", "achieved": tf32, "peak": PEAK_FP32_TFLOPS,
                       "unit": "TFLOP/s", "frac": tf32 / PEAK_FP32_TFLOPS, "traffic": None,
                       "flops_per_launch": flops, "launch_us": t_a32 * 1e6}),
+        "bf16_pc": {"value": pm.n_dofs / dt_bf, "ms": dt_bf * 1e3, "iterations": info_bf["iterations"],
+                    "true_rel_residual": res_bf, "rel_diff_vs_fp64_solution": diff_bf},
         "fp32_pc": {"value": pm.n_dofs / dt_pc, "ms": dt_pc * 1e3, "iterations": info_pc["iterations"],
                     "true_rel_residual": res_pc, "rel_diff_vs_fp64_solution": diff_pc},
         "fp32_ir": {"value": pm.n_dofs / dt_m, "ms": dt_m * 1e3, "iterations": info_m["iterations"],
@@ -221,7 +233,8 @@ def mixed(args):
         "fp64": {"value": pm.n_dofs / dt_64, "ms": dt_64 * 1e3, "iterations": info_64["iterations"],
                  "true_rel_residual": res64},
         "speedup_vs_fp64": dt_64 / dt_best,
-        "apply_us": {"A_fp32": t_a32 * 1e6, "A_fp64": t_a64 * 1e6, "P_fp32": t_p32 * 1e6, "P_fp64": t_p64 * 1e6},
+        "apply_us": {"A_fp32": t_a32 * 1e6, "A_fp64": t_a64 * 1e6, "P_fp32": t_p32 * 1e6, "P_fp64": t_p64 * 1e6,
+                     "P_bf16": t_pbf * 1e6},
     }
     print(json.dumps(line), flush=True)
 
@@ -301,7 +314,8 @@ def batch(args):
         "metric": "Riesz-map solve DOFs/s to rel. residual 1e-10 (uneven batch)",
         "value": total / dt, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 operator, f32-stored preconditioner" if args.batch_precision == "fp32-pc" else "f64",
+        "dtype": {"fp32-pc": "f64 operator, f32-stored preconditioner",
+                  "bf16-pc": "f64 operator, bf16-stored preconditioner", "fp64": "f64"}[args.batch_precision],
         "data": "synthetic",
         "config": {"workload": f"uneven batch of {len(probs)} H(grad)/H(curl) Riesz maps, n in 4..16, p in 2..10, "
                                "jittered Kuhn meshes, rtol 1e-10", "total_dofs": total,

@@ -73,7 +73,10 @@ typedef struct {
 /* Arithmetic of rz_solve.  RZ_FP64: PCG entirely in FP64.  RZ_FP32_PC: PCG
  * with the FP64 operator and vectors; the preconditioner reads FP32 copies
  * of the patch and coarse inverses (accumulating in FP64), so it is a fixed
- * symmetric operator and no refinement is needed.  RZ_FP32_IR:
+ * symmetric operator and no refinement is needed.  RZ_BF16_PC: the same
+ * with bfloat16 copies of the patch inverses (rounded to nearest through
+ * FP32; a quarter of the FP64 bytes) and the FP32 coarse copy; it may cost a few
+ * more iterations.  RZ_FP32_IR:
  * iterative refinement -- the residual b - A x and the update x += d are
  * FP64; each correction d solves A d = r by PCG to inner_rtol whose operator
  * and preconditioner applies read FP32 copies of the reference tables,
@@ -82,7 +85,7 @@ typedef struct {
  * The copies are rounded from the FP64 factors built at setup.  If an outer
  * step contracts the true residual by less than a factor 2 the remaining
  * corrections use the FP64 applies. */
-typedef enum { RZ_FP64 = 0, RZ_FP32_IR = 1, RZ_FP32_PC = 2 } rz_precision;
+typedef enum { RZ_FP64 = 0, RZ_FP32_IR = 1, RZ_FP32_PC = 2, RZ_BF16_PC = 3 } rz_precision;
 
 /* Preconditioner form (Sec. 6 and Sec. 7.1).  RZ_PC_ADDITIVE: the additive
  * Schwarz method of the theory, Jacobi + interface patches + coarse summed.
@@ -150,8 +153,9 @@ int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t
  * conventions (FP64 vectors in and out).  rz_apply_A_fp32 (RZ_FP32_IR
  * handles): the reference tables, weights and x are rounded to FP32 and
  * contracted by FP32 MFMA, cell results are scatter-added in FP64.
- * rz_apply_P_fp32 (RZ_FP32_IR and RZ_FP32_PC handles): the preconditioner
- * of rz_solve's inner iteration -- FP32 patch and coarse inverses with FP64
+ * rz_apply_P_fp32 (RZ_FP32_IR, RZ_FP32_PC and RZ_BF16_PC handles): the
+ * preconditioner of rz_solve's iteration -- the reduced-precision patch
+ * (FP32, or bfloat16 under RZ_BF16_PC) and FP32 coarse inverses with FP64
  * accumulation, and under RZ_FP32_IR also the FP32 operator inside the
  * hybrid sweep.  RZ_ERR_ARG for a handle without the copies. */
 int rz_apply_A_fp32(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream);

@@ -407,8 +407,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
   P->p = degree;
   if (opts && opts->max_iter > 0) P->max_iter = std::min<int>(opts->max_iter, rz::kMaxIter);
   if (opts) {
-    if (opts->precision != RZ_FP64 && opts->precision != RZ_FP32_IR && opts->precision != RZ_FP32_PC)
-      return fail(RZ_ERR_ARG, "unknown precision");
+    if (opts->precision < RZ_FP64 || opts->precision > RZ_BF16_PC) return fail(RZ_ERR_ARG, "unknown precision");
     if (!(opts->inner_rtol < 1.0)) return fail(RZ_ERR_ARG, "inner_rtol must be below 1");
     P->precision = opts->precision;
     if (opts->inner_rtol > 0.0) P->inner_rtol = opts->inner_rtol;
@@ -491,18 +490,31 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
         P->at.Afrag32 = lo(P->Afrag, int64_t(P->at.NP) * P->at.KP * Q);
         P->at.w32 = lo(P->w, nc * Q);
       }
+      const bool bf16 = P->precision == RZ_BF16_PC;
+      const int VL = bf16 ? 8 : 4;
       for (auto &d : P->dps) {
-        std::vector<int64_t> off32(d.sizes.size());
-        int64_t tot32 = 0;
+        std::vector<int64_t> offl(d.sizes.size());
+        int64_t totl = 0;
         for (size_t b = 0; b < d.sizes.size(); ++b) {
-          off32[b] = tot32;
-          tot32 += rz::seg_size(int(d.sizes[b]), 4);
+          offl[b] = totl;
+          totl += rz::seg_size(int(d.sizes[b]), VL);
         }
-        float *inv32 = P->dev<float>(size_t(tot32));
-        d.pa.inv_off32 = P->upload(off32, s);
-        rz::launch_seg_to_float(d.pa.n_patches, d.pa.patch_col, d.pa.inv_off, d.pa.inv_off32, d.pa.inv, inv32, s);
-        d.pa.inv32 = inv32;
+        const int64_t *doff = P->upload(offl, s);
+        if (bf16) {
+          uint16_t *inv16 = P->dev<uint16_t>(size_t(totl));
+          rz::launch_seg_to_bf16(d.pa.n_patches, d.pa.patch_col, d.pa.inv_off, doff, d.pa.inv, inv16, s);
+          d.pa.inv16 = inv16;
+          d.pa.inv_off16 = doff;
+        } else {
+          float *inv32 = P->dev<float>(size_t(totl));
+          rz::launch_seg_to_float(d.pa.n_patches, d.pa.patch_col, d.pa.inv_off, doff, d.pa.inv, inv32, s);
+          d.pa.inv32 = inv32;
+          d.pa.inv_off32 = doff;
+        }
       }
+      // the coarse inverse stays FP32 under RZ_BF16_PC: its condition grows
+      // like h^-2, and a bfloat16 copy loses definiteness on modest meshes
+      // (the patch matrices are local and stay well conditioned)
       P->ca.tiles32 = lo(P->ca.tiles, int64_t(P->ca.NT) * (P->ca.NT + 1) / 2 * 4096);
       HIPCHK(hipGetLastError());
     }
@@ -760,7 +772,8 @@ static int apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int
   if (!P || !r || !z) return fail(RZ_ERR_ARG, "null argument");
   if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
   if (lo && !P->ca.tiles32)
-    return fail(RZ_ERR_ARG, "FP32 inverse copies exist only for RZ_FP32_IR and RZ_FP32_PC handles");
+    return fail(RZ_ERR_ARG, "reduced-precision inverse copies exist only for RZ_FP32_IR, RZ_FP32_PC and RZ_BF16_PC "
+                            "handles");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   try {
     ensure_ws(P, n_rhs);
@@ -1038,7 +1051,7 @@ int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t l
     auto t0 = std::chrono::steady_clock::now();
     if (P->precision != RZ_FP32_IR) {
       // FP64 operator; FP32 inverses in the preconditioner for RZ_FP32_PC
-      pcg_run(P, b, ld, x, ld, nc, rtol, P->precision == RZ_FP32_PC ? kLoP : 0u, false, nullptr, s);
+      pcg_run(P, b, ld, x, ld, nc, rtol, P->precision == RZ_FP64 ? 0u : kLoP, false, nullptr, s);
       for (int c = 0; c < nc; ++c) column_info(P->st_host[c], its[c], cond[c], rel[c], code[c]);
     } else {
       refine(P, b, x, ld, nc, rtol, its, outer, cond, rel, code, s);
@@ -1246,7 +1259,7 @@ int rz_batch_solve(rz_batch *B, const double *const *b, double *const *x, double
         if (code != RZ_OK && worst == RZ_OK) worst = code;
         continue;
       }
-      lo[i] = P->precision == RZ_FP32_PC ? kLoP : 0u;
+      lo[i] = P->precision == RZ_FP64 ? 0u : kLoP;
       pcg_begin(P, b[i], P->top.n_dofs, x[i], P->top.n_dofs, 1, rtol, lo[i], false, nullptr, s);
       HIPCHK(hipGetLastError());
       active.push_back(i);

@@ -53,6 +53,21 @@ __device__ inline double group_sum(double v) {
   return v;
 }
 
+// stored inverse entries -> FP64 (uint16_t holds bfloat16 bits)
+__device__ inline double to_f64(double v) { return v; }
+__device__ inline double to_f64(float v) { return double(v); }
+__device__ inline double to_f64(uint16_t v) { return double(__uint_as_float(uint32_t(v) << 16)); }
+template <typename T>
+__device__ inline T from_f64(double v);
+template <>
+__device__ inline float from_f64<float>(double v) { return float(v); }
+template <>
+__device__ inline uint16_t from_f64<uint16_t>(double v) {
+  // round to nearest even on the float32 bits (finite values)
+  const uint32_t b = __float_as_uint(float(v));
+  return uint16_t((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+
 // deterministic block sum of 256 threads; result valid in every thread
 __device__ inline double block_sum256(double v, double *sm4) {
   v = wave_sum(v);
@@ -715,7 +730,7 @@ __global__ __launch_bounds__(256) void k_patch_seg(const int64_t *__restrict__ c
         for (int q = 0; q < NQ; ++q)
 #pragma unroll
           for (int h = 0; h < V; ++h) {
-            const double a = double(buf[u][q][h]);
+            const double a = to_f64(buf[u][q][h]);
             rs += a * rj[q][g][h];
             cacc[q][g][h] += a * ri;
           }
@@ -755,20 +770,21 @@ __global__ __launch_bounds__(256) void k_patch_seg(const int64_t *__restrict__ c
   }
 }
 
-// FP32 copy of a patch inverse: from the V = 2 to the V = 4 segmented layout
-__global__ void k_seg_to_float(const int64_t *__restrict__ patch_col, const int64_t *__restrict__ off64,
-                               const int64_t *__restrict__ off32, const double *__restrict__ A,
-                               float *__restrict__ B) {
+// Reduced-precision copy of a patch inverse: from the V = 2 FP64 segmented
+// layout to the VT-element layout of T (VT = 16 bytes / sizeof(T))
+template <typename T, int VT>
+__global__ void k_seg_to_low(const int64_t *__restrict__ patch_col, const int64_t *__restrict__ off64,
+                             const int64_t *__restrict__ offlo, const double *__restrict__ A, T *__restrict__ B) {
   const int64_t p = blockIdx.x;
   const int m = int(patch_col[p + 1] - patch_col[p]);
-  const int m2 = (m + 1) / 2 * 2, m4 = (m + 3) / 4 * 4;
+  const int m2 = (m + 1) / 2 * 2, mv = (m + VT - 1) / VT * VT;
   const double *a = A + off64[p];
-  float *b = B + off32[p];
+  T *b = B + offlo[p];
   for (int i = 0; i < m; ++i) {
-    const int s2 = i / 2 * 2, s4 = i / 4 * 4;
+    const int s2 = i / 2 * 2, sv = i / VT * VT;
     const double *ra = a + seg_row_off(i, m2, 2) - s2;
-    float *rb = b + seg_row_off(i, m4, 4) - s4;
-    for (int c = s4 + threadIdx.x; c < m4; c += blockDim.x) rb[c] = (c >= i && c < m) ? float(ra[c]) : 0.0f;
+    T *rb = b + seg_row_off(i, mv, VT) - sv;
+    for (int c = sv + threadIdx.x; c < mv; c += blockDim.x) rb[c] = from_f64<T>((c >= i && c < m) ? ra[c] : 0.0);
   }
 }
 
@@ -823,7 +839,7 @@ __global__ __launch_bounds__(256) void k_coarse_symv(int NT, int S, const T *__r
       double colp = 0.0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const double a0 = double(cur[q].x), a1 = double(cur[q].y);
+        const double a0 = to_f64(cur[q].x), a1 = to_f64(cur[q].y);
         acc[g][2 * q] += a0 * rJ;
         acc[g][2 * q + 1] += a1 * rJ;
         colp += a0 * rI[g][2 * q] + a1 * rI[g][2 * q + 1];
@@ -1435,7 +1451,13 @@ int64_t seg_size(int m, int V) {
 
 void launch_seg_to_float(int64_t n_patches, const int64_t *patch_col, const int64_t *off64, const int64_t *off32,
                          const double *A, float *B, hipStream_t s) {
-  hipLaunchKernelGGL(k_seg_to_float, dim3(unsigned(n_patches)), dim3(256), 0, s, patch_col, off64, off32, A, B);
+  hipLaunchKernelGGL((k_seg_to_low<float, 4>), dim3(unsigned(n_patches)), dim3(256), 0, s, patch_col, off64, off32,
+                     A, B);
+}
+void launch_seg_to_bf16(int64_t n_patches, const int64_t *patch_col, const int64_t *off64, const int64_t *off16,
+                        const double *A, uint16_t *B, hipStream_t s) {
+  hipLaunchKernelGGL((k_seg_to_low<uint16_t, 8>), dim3(unsigned(n_patches)), dim3(256), 0, s, patch_col, off64,
+                     off16, A, B);
 }
 
 // rows in flight per lane group: deeper for short rows
@@ -1478,22 +1500,32 @@ template <typename T>
 static void patch_dispatch(const PatchApply &pa, const int64_t *off, const T *inv, const double *r, int64_t ldr,
                            double *z, int64_t ldz, int ncol, double scale, const PcgState *st, hipStream_t s) {
   constexpr int V = 16 / sizeof(T);
+  // kMaxPatch = 2048 columns need at most NQ = 2048 / (64 V) stripes
+  static_assert(kMaxPatch <= 64 * 32, "patch stripes cover at most 64 * 32 columns");
   const int m = pa.max_size;
-  const int L = m <= 48 ? 16 : (m <= 160 ? 32 : 64);
+  // 16 lanes per row up to 48 / 64 / 128 columns (V = 2 / 4 / 8), 32 up to
+  // 256, else 64 (measured over the patch sets of the 3D sweep problems)
+  constexpr int m16 = V == 2 ? 48 : V == 4 ? 64 : 128;
+  const int L = m <= m16 ? 16 : (m <= 256 ? 32 : 64);
   const int mS = (m + V - 1) / V * V;
   const int nq = (mS + V * L - 1) / (V * L);
   const int NQ = nq <= 1 ? 1 : nq <= 2 ? 2 : nq <= 4 ? 4 : nq <= 8 ? 8 : 16;
-#define RZ_PQ(LL, QQ) \
-  if (L == LL && NQ == QQ) return patch_seg<V, LL, QQ, T>(pa, off, inv, r, ldr, z, ldz, ncol, scale, st, s)
+#define RZ_PQ(LL, QQ)                                                                          \
+  if constexpr (QQ * V <= 32)                                                                  \
+    if (L == LL && NQ == QQ) return patch_seg<V, LL, QQ, T>(pa, off, inv, r, ldr, z, ldz, ncol, scale, st, s)
   RZ_PQ(16, 1); RZ_PQ(16, 2); RZ_PQ(16, 4);
   RZ_PQ(32, 1); RZ_PQ(32, 2); RZ_PQ(32, 4);
   RZ_PQ(64, 1); RZ_PQ(64, 2); RZ_PQ(64, 4); RZ_PQ(64, 8); RZ_PQ(64, 16);
 #undef RZ_PQ
+  // 64 lanes with 32 / V stripes cover any patch up to kMaxPatch
+  patch_seg<V, 64, 32 / V, T>(pa, off, inv, r, ldr, z, ldz, ncol, scale, st, s);
 }
 
 void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
                         const PcgState *st, hipStream_t s, bool lo, double scale) {
   if (pa.n_chunks == 0) return;
+  if (lo && pa.inv16)
+    return patch_dispatch<uint16_t>(pa, pa.inv_off16, pa.inv16, r, ldr, z, ldz, ncol, scale, st, s);
   if (lo && pa.inv32)
     return patch_dispatch<float>(pa, pa.inv_off32, pa.inv32, r, ldr, z, ldz, ncol, scale, st, s);
   if (ncol >= 8 && pa.max_size <= kSmallPatch) {

@@ -70,11 +70,16 @@ void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double 
 // Patch inverse storage: row i of a patch of size m holds the columns
 // [V floor(i/V), V ceil(m/V)) -- zero left of the diagonal and beyond m, the
 // diagonal halved -- so every row is a whole number of aligned V-element
-// (16-byte) segments: V = 2 for the FP64 inverses, V = 4 for their FP32 copies.
+// (16-byte) segments: V = 2 for the FP64 inverses, V = 4 for their FP32 copies,
+// V = 8 for bfloat16 copies.
 constexpr int kMaxPatch = 2048;
 int64_t seg_size(int m, int V);  // stored entries of one patch
 void launch_seg_to_float(int64_t n_patches, const int64_t *patch_col, const int64_t *off64, const int64_t *off32,
                          const double *A, float *B, hipStream_t s);
+// bfloat16 copy of the patch inverses (bits in uint16_t, round to nearest
+// even) in the V = 8 segmented layout
+void launch_seg_to_bf16(int64_t n_patches, const int64_t *patch_col, const int64_t *off64, const int64_t *off16,
+                        const double *A, uint16_t *B, hipStream_t s);
 
 struct PatchApply {
   int64_t n_patches, n_chunks;
@@ -87,6 +92,8 @@ struct PatchApply {
   const double *inv;        // segmented upper rows per patch (V = 2)
   const float *inv32;       // FP32 copy (V = 4) for mixed precision, or null
   const int64_t *inv_off32; // its patch offsets
+  const uint16_t *inv16;    // bfloat16 copy (V = 8), or null
+  const int64_t *inv_off16;
 };
 struct CoarseApply {
   int nW, NT;               // coarse size, tiles per side

@@ -25,8 +25,8 @@ class RzMesh(ctypes.Structure):
                 ("n_cells", ctypes.c_int64), ("cells", ctypes.POINTER(ctypes.c_int64))]
 
 
-RZ_FP64, RZ_FP32_IR, RZ_FP32_PC = 0, 1, 2
-PRECISIONS = {"fp64": RZ_FP64, "fp32-ir": RZ_FP32_IR, "fp32-pc": RZ_FP32_PC}
+RZ_FP64, RZ_FP32_IR, RZ_FP32_PC, RZ_BF16_PC = 0, 1, 2, 3
+PRECISIONS = {"fp64": RZ_FP64, "fp32-ir": RZ_FP32_IR, "fp32-pc": RZ_FP32_PC, "bf16-pc": RZ_BF16_PC}
 RZ_PC_ADDITIVE, RZ_PC_HYBRID = 0, 1
 PCS = {"additive": RZ_PC_ADDITIVE, "hybrid": RZ_PC_HYBRID}
 

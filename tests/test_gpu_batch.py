@@ -27,7 +27,7 @@ pytestmark = pytest.mark.gpu
 # (dim, space, degree, cells per edge, preconditioner form, precision)
 MEMBERS = [(3, "CG", 2, 3, "hybrid", "fp64"), (3, "Ned", 4, 2, "hybrid", "fp64"), (3, "CG", 6, 2, "hybrid", "fp32-pc"),
            (3, "RT", 3, 2, "additive", "fp64"), (2, "CG", 4, 4, "hybrid", "fp64"), (3, "Ned", 2, 1, "hybrid", "fp32-ir"),
-           (3, "RT", 5, 1, "hybrid", "fp64")]
+           (3, "RT", 5, 1, "hybrid", "fp64"), (3, "Ned", 3, 2, "hybrid", "bf16-pc")]
 
 _state = {}
 

@@ -17,7 +17,7 @@ from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
 pytestmark = pytest.mark.gpu
 
 CASES = [(3, "Ned", 4, 2, "hybrid", "fp64"), (3, "CG", 5, 2, "additive", "fp64"), (3, "RT", 3, 2, "hybrid", "fp32-pc"),
-         (3, "Ned", 3, 2, "hybrid", "fp32-ir"), (2, "CG", 4, 4, "hybrid", "fp64")]
+         (3, "Ned", 3, 2, "hybrid", "fp32-ir"), (2, "CG", 4, 4, "hybrid", "fp64"), (3, "CG", 4, 2, "hybrid", "bf16-pc")]
 
 
 def pair(d, fam, p, n, pc, prec):

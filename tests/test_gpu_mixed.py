@@ -1,6 +1,7 @@
 """GPU checks of the mixed-precision paths against the FP64 oracle, through
 the C ABI: FP32 applies inside FP64 iterative refinement (RZ_FP32_IR), and
-plain FP64 PCG with an FP32-stored preconditioner (RZ_FP32_PC).
+plain FP64 PCG with an FP32- or bfloat16-stored preconditioner (RZ_FP32_PC,
+RZ_BF16_PC).
 
 Bars (written per check):
 * FP32 apply_A -- the first-order rounding bound of an FP32 contraction of
@@ -13,6 +14,14 @@ Bars (written per check):
   FP32; accumulation in FP64);
 * FP32-preconditioner solve -- the same residual and solution bars, and
   at most two iterations more than the oracle's FP64 hybrid PCG;
+* BF16-preconditioner solve (RZ_BF16_PC: bfloat16 patch inverses, FP32
+  coarse inverse) -- apply_P within 1e-2 max |z| of the oracle (patch
+  entries rounded once to bfloat16, unit roundoff 2^-9; a CPU emulation
+  that rounds the oracle's inverses the same way stays below 1.3e-3 on
+  these cases) and, for p > 1, at least 1e-5 away
+  (the bfloat16 copy ran, not the FP32 one); the solve meets the same
+  residual, solution and iteration bars as the FP32 one (the emulation
+  takes the FP64 count on every case but the exact p = 1 ones, one more);
 * refinement solve -- true residual under the oracle's A <= 1.2 rtol ||b||
   + ||(A_lib - A_oracle) x|| at rtol 1e-10 and 1e-12, ||x - x_oracle|| <=
   1e-10 ||x_oracle|| at rtol 1e-12, at least two refinement steps taken.
@@ -150,21 +159,28 @@ def test_fp32_entry_points_need_fp32_setup():
 _pc_cache = {}
 
 
+@pytest.mark.parametrize("prec", ["fp32-pc", "bf16-pc"])
 @pytest.mark.parametrize("case", CASES, ids=ids)
-def test_fp32_preconditioner_solve(case):
+def test_reduced_preconditioner_solve(case, prec):
     from paper_2506_17406_amd import rz
     top, A, P, _ = setup_case(*case)
-    if case not in _pc_cache:
+    if (case, prec) not in _pc_cache:
         d, fam, p, n = case
         X, C = kuhn_mesh(n, d, jitter=0.1 if d == 3 else 0.0, seed=13)
-        _pc_cache[case] = rz.Problem(X, C, p, fam, precision="fp32-pc")
-    prob = _pc_cache[case]
+        _pc_cache[(case, prec)] = rz.Problem(X, C, p, fam, precision=prec)
+    prob = _pc_cache[(case, prec)]
     r = load_vectors(top.n_dofs, 35)[:, 0]
     zt = torch.empty(top.n_dofs, dtype=torch.float64, device="cuda")
     prob.apply_P(torch.from_numpy(r).cuda(), zt, fp32=True)
     torch.cuda.synchronize()
     ref = P.apply(r)
-    assert np.abs(zt.cpu().numpy() - ref).max() <= 1e-4 * np.abs(ref).max()
+    err = np.abs(zt.cpu().numpy() - ref).max() / np.abs(ref).max()
+    if prec == "fp32-pc":
+        assert err <= 1e-4
+    else:
+        assert err <= 1e-2
+        # p = 1: the exact coarse solve spans the space and wipes the patch error
+        assert err >= 1e-5 or case[2] == 1
     b = load_vectors(top.n_dofs, 36)[:, 0]
     bt = torch.from_numpy(b).cuda()
     xo, io = pcg(lambda v: A @ v, P.apply, b, rtol=1e-12)
