@@ -255,7 +255,7 @@ def _batch_bytes(sp, n, p):
     return 12.0 * (patches + nW * nW / 2) + 16 * 8 * dofs, dofs
 
 
-def batch(args):
+def batch_workload(args):
     """The uneven batch: 32 H(grad)/H(curl) problems with n in 4..16 and p
     in 2..10 drawn from default_rng(8) (a draw is redrawn while the batch
     would exceed the memory budget), jittered Kuhn meshes (seed 100 + i),
@@ -362,15 +362,15 @@ def cpu_baseline(pc="hybrid"):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only "
-                                   "(see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this solver runs on one GPU only; sharding across GPUs is not built",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "multirhs":
         return multirhs(args)
     if args.workload == "mixed":
         return mixed(args)
     if args.workload == "batch":
-        return batch(args)
+        return batch_workload(args)
     import torch
     from paper_2506_17406_amd import rz
     from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors

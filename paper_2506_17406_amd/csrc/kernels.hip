@@ -641,8 +641,8 @@ __global__ void k_axpy_m(int64_t n, const double *__restrict__ d, double *__rest
 // are summed over the L lanes (DPP); the mirrored column products stay in
 // registers until the end of the chunk.  Segments left of a row's first
 // stored segment or beyond the patch are not loaded.
-template <int V, int L, int NQ, int G, int D, typename T>
-__global__ __launch_bounds__(256) void k_patch_seg(const int64_t *__restrict__ chunk_patch,
+template <int V, int L, int NQ, int G, int D, typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_patch_seg(const int64_t *__restrict__ chunk_patch,
                                                    const int32_t *__restrict__ chunk_rows,
                                                    const int64_t *__restrict__ patch_col,
                                                    const int64_t *__restrict__ col_ent,
@@ -662,9 +662,9 @@ __global__ __launch_bounds__(256) void k_patch_seg(const int64_t *__restrict__ c
     if (!any) return;
   }
   extern __shared__ double sm[];
-  double *rp = sm;              // G x W gathered right-hand sides (zero padded)
-  double *yr = sm + G * W;      // G x W row products
-  double *yc = sm + 2 * G * W;  // 4 waves x G x W column products
+  double *yr = sm;           // G x W row products
+  double *rp = sm + G * W;   // G x W gathered right-hand sides (zero padded)
+  double *yc = rp;           // after the rows: NW waves x G x W column products
   const int64_t p = chunk_patch[blockIdx.x];
   const int r0 = chunk_rows[2 * blockIdx.x], r1 = chunk_rows[2 * blockIdx.x + 1];
   const int64_t c0 = patch_col[p];
@@ -686,13 +686,13 @@ __global__ __launch_bounds__(256) void k_patch_seg(const int64_t *__restrict__ c
   // rows in flight: a ring of D row buffers, D - 1 loads ahead of the
   // products; the first loads are issued before the gather of the patch
   // right-hand sides
-  const int step = 4 * RPW;
+  const int step = NW * RPW;
   const int niter = (r1 - r0 + step - 1) / step;
   const int i0 = r0 + wave * RPW + slot;
   vecV buf[D][NQ];
 #pragma unroll
   for (int u = 0; u < D - 1; ++u) load_row(i0 + u * step, i0 + u * step < r1, buf[u]);
-  for (int t2 = threadIdx.x; t2 < G * W; t2 += 256) {
+  for (int t2 = threadIdx.x; t2 < G * W; t2 += 64 * NW) {
     const int g = t2 / W, j = t2 - g * W;
     double sv = 0;
     if (j < m && cbase + g < ncol) {
@@ -751,6 +751,7 @@ __global__ __launch_bounds__(256) void k_patch_seg(const int64_t *__restrict__ c
         if (L <= 32) v += __shfl_xor(v, 32, 64);
         cacc[q][g][h] = v;
       }
+  __syncthreads();  // the column products overwrite the right-hand sides
   if (slot == 0) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
@@ -760,11 +761,13 @@ __global__ __launch_bounds__(256) void k_patch_seg(const int64_t *__restrict__ c
         for (int h = 0; h < V; ++h) yc[(wave * G + g) * W + q * V * L + t * V + h] = cacc[q][g][h];
   }
   __syncthreads();
-  for (int t2 = threadIdx.x; t2 < G * m; t2 += 256) {
+  for (int t2 = threadIdx.x; t2 < G * m; t2 += 64 * NW) {
     const int g = t2 / m, j = t2 - g * m;
     if (j < r0 || cbase + g >= ncol) continue;
-    const double y = scale * (yr[g * W + j] + ((yc[(0 * G + g) * W + j] + yc[(1 * G + g) * W + j]) +
-                                               (yc[(2 * G + g) * W + j] + yc[(3 * G + g) * W + j])));
+    double cs = yc[g * W + j];
+    if (NW == 4)
+      cs = (cs + yc[(1 * G + g) * W + j]) + (yc[(2 * G + g) * W + j] + yc[(3 * G + g) * W + j]);
+    const double y = scale * (yr[g * W + j] + cs);
     double *zc = z + int64_t(cbase + g) * ldz;
     for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) atomicAdd(&zc[ent_dof[e]], ent_coef[e] * y);
   }
@@ -1422,10 +1425,13 @@ void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double 
   if (col0 >= col1) return;
   const int kb0 = col0 / 4, kb1 = (col1 + 3) / 4;
   const int NMB = t.NP / 16;
-  // cells per wave: as many as keep >= 2048 waves in flight (A-fragment reuse vs occupancy)
+  const int mb0 = lo && t.Afrag32 ? 0 : row0 / 16;
+  // cells per wave: as many as keep >= 2048 waves in flight (A-fragment reuse
+  // vs occupancy), counting the row blocks this launch covers; an apply over
+  // all rows of one column takes the tuned value where there is one
   int NB = 4;
-  while (NB > 1 && ((t.n_cells + 16 * NB - 1) / (16 * NB)) * NMB * n_rhs < 2048) NB /= 2;
-  if (n_rhs == 1 && (t.nb1 == 1 || t.nb1 == 2 || t.nb1 == 4)) NB = t.nb1;
+  while (NB > 1 && ((t.n_cells + 16 * NB - 1) / (16 * NB)) * (NMB - mb0) * n_rhs < 2048) NB /= 2;
+  if (n_rhs == 1 && mb0 == 0 && (t.nb1 == 1 || t.nb1 == 2 || t.nb1 == 4)) NB = t.nb1;
   dim3 grid(unsigned((t.n_cells + 16 * NB - 1) / (16 * NB)), unsigned((NMB + 3) / 4), unsigned(n_rhs));
   if (lo && t.Afrag32) {
     if (t.Q == 12) apply_A32_q<12>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
@@ -1436,7 +1442,6 @@ void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double 
   // FP64 GEMM: a block is one row block x 4 waves x 16 NB cells; a row-
   // restricted apply starts at the row block of row0 and assembles the dofs
   // from dof0 on (the interior rows and dofs: both are trailing blocks)
-  const int mb0 = row0 / 16;
   const dim3 g64(unsigned((t.n_cells + 64 * NB - 1) / (64 * NB)), unsigned(NMB - mb0), unsigned(n_rhs));
   if (t.Q == 12) apply_A_q<12>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0);
   else if (t.Q == 7) apply_A_q<7>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0);
@@ -1466,33 +1471,50 @@ constexpr int patch_depth() {
   return VQ <= 8 ? 4 : 2;
 }
 
-template <int V, int L, int NQ, int G, typename T>
+template <int V, int L, int NQ, int G, typename T, int NW>
 static void patch_seg_g(const PatchApply &pa, const int64_t *off, const T *inv, dim3 grid, size_t lds,
                         const double *r, int64_t ldr, double *z, int64_t ldz, int ncol, double scale,
                         const PcgState *st, hipStream_t s) {
   constexpr int D = patch_depth<NQ * V, T>();
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_patch_seg<V, L, NQ, G, D, T>,
+    (void)hipFuncSetAttribute((const void *)k_patch_seg<V, L, NQ, G, D, T, NW>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
-  hipLaunchKernelGGL((k_patch_seg<V, L, NQ, G, D, T>), grid, dim3(256), lds, s, pa.chunk_patch, pa.chunk_rows,
-                     pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, off, inv, r, ldr, z, ldz, ncol, scale, st);
+  hipLaunchKernelGGL((k_patch_seg<V, L, NQ, G, D, T, NW>), grid, dim3(64 * NW), lds, s, pa.chunk_patch,
+                     pa.chunk_rows, pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, off, inv, r, ldr, z, ldz,
+                     ncol, scale, st);
 }
 
-template <int V, int L, int NQ, typename T>
-static void patch_seg(const PatchApply &pa, const int64_t *off, const T *inv, const double *r, int64_t ldr,
-                      double *z, int64_t ldz, int ncol, double scale, const PcgState *st, hipStream_t s) {
+template <int V, int L, int NQ, typename T, int NW>
+static void patch_seg_w(const PatchApply &pa, const int64_t *off, const T *inv, const double *r, int64_t ldr,
+                        double *z, int64_t ldz, int ncol, double scale, const PcgState *st, hipStream_t s) {
   constexpr int W = NQ * L * V;
   constexpr int VQ = NQ * V;
-  const size_t lds_per_g = size_t(6) * W * sizeof(double);
+  const size_t lds_per_g = size_t(1 + NW) * W * sizeof(double);
   int G = 4;
   while (G > 1 && (G > ncol || lds_per_g * G > 96 * 1024 || VQ * G > 32)) G /= 2;
   const dim3 grid(unsigned(pa.n_chunks), unsigned((ncol + G - 1) / G));
-  if (G == 4) patch_seg_g<V, L, NQ, (VQ <= 8 ? 4 : 1), T>(pa, off, inv, grid, lds_per_g * G, r, ldr, z, ldz, ncol, scale, st, s);
-  else if (G == 2) patch_seg_g<V, L, NQ, (VQ <= 16 ? 2 : 1), T>(pa, off, inv, grid, lds_per_g * G, r, ldr, z, ldz, ncol, scale, st, s);
-  else patch_seg_g<V, L, NQ, 1, T>(pa, off, inv, grid, lds_per_g, r, ldr, z, ldz, ncol, scale, st, s);
+  if (G == 4)
+    patch_seg_g<V, L, NQ, (VQ <= 8 ? 4 : 1), T, NW>(pa, off, inv, grid, lds_per_g * G, r, ldr, z, ldz, ncol, scale,
+                                                    st, s);
+  else if (G == 2)
+    patch_seg_g<V, L, NQ, (VQ <= 16 ? 2 : 1), T, NW>(pa, off, inv, grid, lds_per_g * G, r, ldr, z, ldz, ncol,
+                                                     scale, st, s);
+  else patch_seg_g<V, L, NQ, 1, T, NW>(pa, off, inv, grid, lds_per_g, r, ldr, z, ldz, ncol, scale, st, s);
+}
+
+// bfloat16 patches of up to 128 columns: one wave per block (four times the
+// independent patches in flight per CU, hiding the latency of the gather and
+// scatter chains that dominate such short streams); else four waves
+template <int V, int L, int NQ, typename T>
+static void patch_seg(const PatchApply &pa, const int64_t *off, const T *inv, const double *r, int64_t ldr,
+                      double *z, int64_t ldz, int ncol, double scale, const PcgState *st, hipStream_t s) {
+  if constexpr (sizeof(T) == 2 && L == 16)
+    return patch_seg_w<V, L, NQ, T, 1>(pa, off, inv, r, ldr, z, ldz, ncol, scale, st, s);
+  else
+    patch_seg_w<V, L, NQ, T, 4>(pa, off, inv, r, ldr, z, ldz, ncol, scale, st, s);
 }
 
 // lanes per row and column stripes for the largest patch of a set
