@@ -469,7 +469,7 @@ def main():
                                f"jittered Kuhn mesh {args.n}^3x6 = {6 * args.n ** 3} tets, rtol 1e-10",
                    "problems": len(probs), "total_dofs": total_dofs, "setup_s": round(t_setup, 2),
                    "preconditioner": args.pc, "mode": args.sweep_mode},
-        "roofline": {"kernel": f"apply_A ({big['fam']}{big['p']}): y fill, cell gather, GEMM, assembly",
+        "roofline": {"kernel": f"apply_A ({big['fam']}{big['p']}): cell gather, GEMM, assembly",
                      "bound": "mfma",
                      "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,

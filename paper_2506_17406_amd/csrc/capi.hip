@@ -642,27 +642,27 @@ static void hybrid_apply(rz_problem *P, const double *r, int64_t ldr, double *z,
   const int n = P->el.n;
   const double w1 = 1.0 / P->rho_I, w2 = 1.0 / P->rho_G;
   double *sres = P->hs, *d = P->hd;
-  rz::launch_hyb_init(nd, P->off_I, P->dinv, w1, r, ldr, z, ldz, sres, partR, RB, nc, st, s);
+  // d = 0 from here on before each correction: hyb_init clears it, and each
+  // restricted apply of a correction clears it once it has read it
+  rz::launch_hyb_init(nd, P->off_I, P->dinv, w1, r, ldr, z, ldz, sres, d, partR, RB, nc, st, s);
   if (P->col_int < n) rz::launch_apply_A(P->at, z, ldz, sres, nd, nc, st, s, loA, P->col_int, n, -1.0);
   // last: only the interior rows of the tracked residual are read afterwards
   // (by the final Jacobi step), so the second interface correction is
   // applied with A[I, Gamma] alone (FP64 path)
   auto interface = [&](bool last) {
-    rz::launch_fill(d, nd, nd, nc, st, s);
     for (auto &pa : P->pas) rz::launch_patch_apply(pa, sres, nd, d, nd, nc, st, s, loP, w2);
     rz::launch_add(nd, d, z, ldz, nc, st, s);
     if (last && !loA) {
       if (P->col_int < n)  // no interior rows: nothing reads the residual again
         rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, false, 0, P->col_int, -1.0, P->col_int, P->off_I);
     } else
-      rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, loA, 0, P->col_int, -1.0);
+      rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, loA, 0, P->col_int, -1.0, 0, 0, false, !last);
   };
   interface(false);
   rz::launch_coarse_gather(P->ca, sres, nd, nc, s);
   rz::launch_coarse_tiles(P->ca, nc, st, s, loP);
-  rz::launch_fill(d, nd, nd, nc, st, s);
   rz::launch_coarse_scatter2(P->ca, nd, d, z, ldz, nc, st, s);
-  rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, loA, P->col_w0, P->col_w1, -1.0);
+  rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, loA, P->col_w0, P->col_w1, -1.0, 0, 0, false, true);
   interface(true);
   rz::launch_jacobi_add(nd, P->off_I, P->dinv, w1, sres, z, ldz, nc, st, s);
 }
@@ -715,8 +715,7 @@ static double group_weight(rz_problem *P, int64_t lo, int64_t hi, uint64_t seed,
   double rz = host_dot(P, r, z, s);
   std::vector<double> al, be;
   for (int it = 0; it < 10 && rz > 0.0; ++it) {
-    rz::launch_fill(q, nd, nd, 1, nullptr, s);
-    rz::launch_apply_A(P->at, p, nd, q, nd, 1, nullptr, s);
+    rz::launch_apply_A(P->at, p, nd, q, nd, 1, nullptr, s, false, 0, -1, 1.0, 0, 0, true);
     rz::launch_mask(nd, lo, hi, q, s);
     const double pq = host_dot(P, p, q, s);
     if (!(pq > 0.0)) throw RzError{RZ_ERR_NOT_SPD, "weight estimate: p^T A p <= 0"};
@@ -760,8 +759,7 @@ static int apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int
   } catch (const RzError &e) {
     return fail(e.code, e.msg);
   }
-  rz::launch_fill(y, P->top.n_dofs, ld, n_rhs, nullptr, s);
-  rz::launch_apply_A(P->at, x, ld, y, ld, n_rhs, nullptr, s, lo);
+  rz::launch_apply_A(P->at, x, ld, y, ld, n_rhs, nullptr, s, lo, 0, -1, 1.0, 0, 0, true);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RZ_ERR_DEVICE, hipGetErrorString(e));
   return RZ_OK;
@@ -841,8 +839,7 @@ static void pcg_begin(rz_problem *P, const double *b, int64_t ldb, double *x, in
     rz::launch_pcg_start(P->partB, P->partB, RB, tol * tol, maxit, P->st, nc, s, outer);
   } else {
     // r = b - A x, convergence reference ||b||
-    rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
-    rz::launch_apply_A(P->at, x, ldx, P->Ap, nd, nc, nullptr, s, lo & kLoA);
+    rz::launch_apply_A(P->at, x, ldx, P->Ap, nd, nc, nullptr, s, lo & kLoA, 0, -1, 1.0, 0, 0, true);
     rz::launch_residual(nd, b, ldb, P->Ap, P->r, nc, s);
     rz::launch_dot(nd, b, ldb, b, ldb, nofold, npad, P->partB, RB, nc, nullptr, s);
     rz::launch_dot(nd, P->r, nd, P->r, nd, nofold, npad, P->partR, RB, nc, nullptr, s);
@@ -983,8 +980,7 @@ static void refine(rz_problem *P, const double *b, double *x, int64_t ld, int nc
   std::vector<double> prev(nc, 0.0);
   for (int k = 0;; ++k) {
     // true residual and the outer convergence test
-    rz::launch_fill(P->Ap, nd, nd, nc, nullptr, s);
-    rz::launch_apply_A(P->at, x, ld, P->Ap, nd, nc, nullptr, s, false);
+    rz::launch_apply_A(P->at, x, ld, P->Ap, nd, nc, nullptr, s, false, 0, -1, 1.0, 0, 0, true);
     rz::launch_residual(nd, b, ld, P->Ap, P->ro, nc, s);
     rz::launch_dot(nd, b, ld, b, ld, nofold, npad, P->partB, RB, nc, nullptr, s);
     rz::launch_dot(nd, P->ro, nd, P->ro, nd, nofold, npad, P->partR, RB, nc, nullptr, s);

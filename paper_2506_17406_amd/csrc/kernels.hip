@@ -528,17 +528,21 @@ __global__ __launch_bounds__(256) void k_apply_A(int mb0, int KB, int kb0_, int 
 
 // y_i += alpha sum over the (cell, local row) pairs of dof i of Yc (a fixed
 // order: deterministic, no atomics)
+// y[i] (+)= alpha sum of dof i's cell products, i in [d0, d1); with xclr,
+// also x[i] = 0 (the gather that read x has completed)
 __global__ void k_assemble(int64_t d0, int64_t d1, const int64_t *__restrict__ ptr, const int32_t *__restrict__ ent,
                            int64_t ystride, const double *__restrict__ Yc, double *__restrict__ y, int64_t ldy,
-                           double alpha, const PcgState *st) {
+                           double alpha, int overwrite, double *__restrict__ xclr, int64_t ldx, const PcgState *st) {
   const int c = blockIdx.y;
   if (st && st[c].done) return;
   const double *Y = Yc + int64_t(c) * ystride;
   double *yc = y + int64_t(c) * ldy;
+  double *xc = xclr ? xclr + int64_t(c) * ldx : nullptr;
   for (int64_t i = d0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < d1; i += int64_t(gridDim.x) * blockDim.x) {
     double sum = 0.0;
     for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) sum += Y[ent[e]];
-    yc[i] += alpha * sum;
+    yc[i] = overwrite ? alpha * sum : yc[i] + alpha * sum;
+    if (xc) xc[i] = 0.0;
   }
 }
 
@@ -1242,7 +1246,8 @@ __global__ void k_jacobi_m(int64_t n, int64_t offI, const double *__restrict__ d
 __global__ __launch_bounds__(256) void k_hyb_init_m(int64_t n, int64_t offI, const double *__restrict__ dinv,
                                                     double w1, const double *__restrict__ r, int64_t ldr,
                                                     double *__restrict__ z, int64_t ldz, double *__restrict__ sres,
-                                                    const double *__restrict__ partR, int RB, PcgState *st) {
+                                                    double *__restrict__ d, const double *__restrict__ partR, int RB,
+                                                    PcgState *st) {
   const int c = blockIdx.y;
   if (st) {
     if (st[c].done) return;
@@ -1261,11 +1266,12 @@ __global__ __launch_bounds__(256) void k_hyb_init_m(int64_t n, int64_t offI, con
     if (bad || conv) return;
   }
   const double *rc = r + c * ldr;
-  double *zc = z + c * ldz, *sc = sres + c * n;
+  double *zc = z + c * ldz, *sc = sres + c * n, *dc = d + c * n;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
     const double ri = rc[i];
     zc[i] = i >= offI ? w1 * ri * dinv[i - offI] : 0.0;
     sc[i] = ri;
+    dc[i] = 0.0;
   }
 }
 
@@ -1372,12 +1378,12 @@ void launch_pack_tiles(int N, int n, const double *Ainv, double *tiles, hipStrea
 
 template <int Q>
 static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1, const double *x, int64_t ldx,
-                      double *y, int64_t ldy, double alpha, const PcgState *st, hipStream_t s, int mb0 = 0,
-                      int64_t d0 = 0, int64_t d1 = -1) {
+                      double *y, int64_t ldy, double alpha, const PcgState *st, hipStream_t s, int mb0, int64_t d0,
+                      bool overwrite, double *xclr) {
+  const int64_t d1 = t.n_dofs;
   const int KB = t.KP / 4;
   const bool full = kb0 == 0 && kb1 == KB && mb0 == 0;
   const int ncol = int(grid.z);
-  if (d1 < 0) d1 = t.n_dofs;
   hipLaunchKernelGGL(k_gather_cells, dim3(grid_for(int64_t(kb1 - kb0) * t.ncp * 4, 256, 4096), ncol), dim3(256), 0,
                      s, t.n, t.KP, t.n_cells, t.ncp, kb0, kb1, t.cell_dofs, x, ldx, t.Xc, st);
 #define RZ_A64(NBV, F)                                                                                        \
@@ -1395,7 +1401,7 @@ static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1
 #undef RZ_A64
   if (d1 > d0)
     hipLaunchKernelGGL(k_assemble, dim3(grid_for(d1 - d0, 256, 4096), ncol), dim3(256), 0, s, d0, d1, t.asm_ptr,
-                       t.asm_ent, int64_t(t.NP) * t.ncp, t.Yc, y, ldy, alpha, st);
+                       t.asm_ent, int64_t(t.NP) * t.ncp, t.Yc, y, ldy, alpha, overwrite ? 1 : 0, xclr, ldx, st);
 }
 
 template <int Q>
@@ -1420,9 +1426,13 @@ static void apply_A32_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int k
 
 void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
                     const PcgState *st, hipStream_t s, bool lo, int col0, int col1, double alpha, int row0,
-                    int64_t dof0) {
+                    int64_t dof0, bool overwrite, bool clear_x) {
   if (col1 < 0) col1 = t.n;
-  if (col0 >= col1) return;
+  if (col0 >= col1) {
+    if (overwrite) launch_fill(y, t.n_dofs, ldy, n_rhs, st, s);
+    if (clear_x) launch_fill(const_cast<double *>(x), t.n_dofs, ldx, n_rhs, st, s);
+    return;
+  }
   const int kb0 = col0 / 4, kb1 = (col1 + 3) / 4;
   const int NMB = t.NP / 16;
   const int mb0 = lo && t.Afrag32 ? 0 : row0 / 16;
@@ -1434,18 +1444,22 @@ void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double 
   if (n_rhs == 1 && mb0 == 0 && (t.nb1 == 1 || t.nb1 == 2 || t.nb1 == 4)) NB = t.nb1;
   dim3 grid(unsigned((t.n_cells + 16 * NB - 1) / (16 * NB)), unsigned((NMB + 3) / 4), unsigned(n_rhs));
   if (lo && t.Afrag32) {
+    // one kernel with an atomic scatter: clear y before, x after
+    if (overwrite) launch_fill(y, t.n_dofs, ldy, n_rhs, st, s);
     if (t.Q == 12) apply_A32_q<12>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
     else if (t.Q == 7) apply_A32_q<7>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
     else apply_A32_q<4>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
+    if (clear_x) launch_fill(const_cast<double *>(x), t.n_dofs, ldx, n_rhs, st, s);
     return;
   }
   // FP64 GEMM: a block is one row block x 4 waves x 16 NB cells; a row-
   // restricted apply starts at the row block of row0 and assembles the dofs
   // from dof0 on (the interior rows and dofs: both are trailing blocks)
   const dim3 g64(unsigned((t.n_cells + 64 * NB - 1) / (64 * NB)), unsigned(NMB - mb0), unsigned(n_rhs));
-  if (t.Q == 12) apply_A_q<12>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0);
-  else if (t.Q == 7) apply_A_q<7>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0);
-  else apply_A_q<4>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0);
+  double *xclr = clear_x ? const_cast<double *>(x) : nullptr;
+  if (t.Q == 12) apply_A_q<12>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0, overwrite, xclr);
+  else if (t.Q == 7) apply_A_q<7>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0, overwrite, xclr);
+  else apply_A_q<4>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0, overwrite, xclr);
 }
 
 // patch apply: largest G in {8,4,2,1} with G <= ncol, LDS <= 96 KB, MAXJ * G <= 32
@@ -1653,9 +1667,10 @@ void launch_axpy(int64_t n, const double *d, double *x, int64_t ldx, int ncol, h
 
 // ---- hybrid sweep
 void launch_hyb_init(int64_t n, int64_t off_I, const double *dinv, double w1, const double *r, int64_t ldr, double *z,
-                     int64_t ldz, double *sres, const double *partR, int RB, int ncol, PcgState *st, hipStream_t s) {
+                     int64_t ldz, double *sres, double *d, const double *partR, int RB, int ncol, PcgState *st,
+                     hipStream_t s) {
   hipLaunchKernelGGL(k_hyb_init_m, dim3(grid_for(n, 256, std::max(1, 2048 / ncol)), ncol), dim3(256), 0, s, n, off_I,
-                     dinv, w1, r, ldr, z, ldz, sres, partR, RB, st);
+                     dinv, w1, r, ldr, z, ldz, sres, d, partR, RB, st);
 }
 void launch_add(int64_t n, const double *d, double *z, int64_t ldz, int ncol, const PcgState *st, hipStream_t s) {
   hipLaunchKernelGGL(k_add_m, dim3(grid_for(n, 256, std::max(1, 2048 / ncol)), ncol), dim3(256), 0, s, n, d, z, ldz,

@@ -57,15 +57,18 @@ struct ApplyATables {
   const int64_t *asm_ptr;
   const int32_t *asm_ent;
 };
-// y += A x for n_rhs columns (y must be zeroed by the caller); st: per-column
-// state (columns that are done are skipped) or null; lo: the FP32 copies
-// [col0, col1): only these local columns of A_T take part (x is zero on the
-// others: a restricted apply); y += alpha A x.  row0 > 0 (FP64 only): only
-// the local rows from row0 and the global dofs from dof0 are updated (the
-// trailing interior blocks of the local and global numberings).
+// y += A x for n_rhs columns (y zeroed by the caller), or y = A x with
+// overwrite; st: per-column state (columns that are done are skipped) or
+// null; lo: the FP32 copies.  [col0, col1): only these local columns of A_T
+// take part (x is zero on the others: a restricted apply); y += alpha A x.
+// row0 > 0 (FP64 only): only the local rows from row0 and the global dofs
+// from dof0 are updated (the trailing interior blocks of the local and
+// global numberings).  clear_x: x is zeroed once the apply has read it (x
+// must be writable; not with dof0 > 0).
 void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
                     const PcgState *st, hipStream_t s, bool lo = false, int col0 = 0, int col1 = -1,
-                    double alpha = 1.0, int row0 = 0, int64_t dof0 = 0);
+                    double alpha = 1.0, int row0 = 0, int64_t dof0 = 0, bool overwrite = false,
+                    bool clear_x = false);
 
 // Patch inverse storage: row i of a patch of size m holds the columns
 // [V floor(i/V), V ceil(m/V)) -- zero left of the diagonal and beyond m, the
@@ -143,8 +146,11 @@ void launch_update_p(int64_t n, double *p, const double *z, const CoarseFold &cf
 
 // ---- symmetric multiplicative hybrid sweep (Sec. 7.1)
 // z = w1 D_I^{-1} r (interior), s = r; with st, after the convergence test
+// hybrid sweep start: z = w1 D^-1 r on the interior (0 elsewhere), s = r,
+// d = 0 (d and s have leading dimension n)
 void launch_hyb_init(int64_t n, int64_t off_I, const double *dinv, double w1, const double *r, int64_t ldr, double *z,
-                     int64_t ldz, double *sres, const double *partR, int RB, int ncol, PcgState *st, hipStream_t s);
+                     int64_t ldz, double *sres, double *d, const double *partR, int RB, int ncol, PcgState *st,
+                     hipStream_t s);
 void launch_add(int64_t n, const double *d, double *z, int64_t ldz, int ncol, const PcgState *st, hipStream_t s);
 void launch_jacobi_add(int64_t n, int64_t off_I, const double *dinv, double w1, const double *sres, double *z,
                        int64_t ldz, int ncol, const PcgState *st, hipStream_t s);

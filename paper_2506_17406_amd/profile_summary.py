@@ -3,15 +3,17 @@
     python -m paper_2506_17406_amd.profile_summary stats <results.db> [top]
         per-kernel calls and durations of a --kernel-trace --stats run
         (rocpd SQLite) as a Markdown table;
-    python -m paper_2506_17406_amd.profile_summary traffic <fetch.csv> <write.csv> <kernel> <copy_bytes>
-        HBM bytes per operator apply whose GEMM is <kernel> (with the fill,
-        gather and assembly dispatched around it) from two --pmc runs
+    python -m paper_2506_17406_amd.profile_summary traffic <fetch.csv> <write.csv> <kernel> <copy_bytes> [grid]
+        HBM bytes per operator apply whose GEMM is <kernel> (with the gather
+        and assembly dispatched around it; with grid, only GEMM dispatches of
+        that many work-items, i.e. one problem's applies) from two --pmc runs
         (FETCH_SIZE, then WRITE_SIZE; counter_collection CSVs), each scaled by
         what the same counter reads for the plain copy kernel of copy_bytes
         bytes read and written in the same run.  Prints key: value lines;
-    python -m paper_2506_17406_amd.profile_summary applies <results.db> <kernel>
-        mean duration of those applies (fill start to assembly end) and of
-        their GEMM kernel in a kernel trace.
+    python -m paper_2506_17406_amd.profile_summary applies <results.db> <kernel> [grid_y]
+        mean duration of those applies (gather start to assembly end) and of
+        their GEMM kernel in a kernel trace (with grid_y, only GEMM dispatches
+        of that many row blocks).
 """
 import csv
 import hashlib
@@ -43,63 +45,67 @@ def kernels_sha256():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-# one operator apply = fill of y, cell gather, the GEMM kernel, assembly
-APPLY_PARTS = ("k_fill_m", "k_gather_cells", "GEMM", "k_assemble")
+# one operator apply = cell gather, the GEMM kernel, assembly
+APPLY_PARTS = ("k_gather_cells", "GEMM", "k_assemble")
 
 
 def _dispatches(path, counter):
-    """(dispatch id, short kernel name, value) in dispatch order."""
+    """(dispatch id, short kernel name, value, grid work-items) in dispatch order."""
     out = []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] == counter:
-            out.append((int(r["Dispatch_Id"]), short(r["Kernel_Name"]), float(r["Counter_Value"])))
+            out.append((int(r["Dispatch_Id"]), short(r["Kernel_Name"]), float(r["Counter_Value"]),
+                        int(r["Grid_Size"])))
     return sorted(out)
 
 
-def _apply_sums(rows, kernel):
-    """Counter sums over each operator apply whose GEMM is `kernel`: the fill
-    and gather dispatched just before it and the assembly just after."""
+def _apply_sums(rows, kernel, grid=None):
+    """Counter sums over each operator apply whose GEMM is `kernel` (of
+    `grid` work-items if given): the gather dispatched just before it and the
+    assembly just after."""
     sums = []
-    for i, (_, name, v) in enumerate(rows):
-        if name != kernel or i < 2 or i + 1 >= len(rows):
+    for i, (_, name, v, g) in enumerate(rows):
+        if name != kernel or i < 1 or i + 1 >= len(rows) or (grid and g != grid):
             continue
-        parts = [rows[i - 2][1], rows[i - 1][1], name, rows[i + 1][1]]
-        if parts[0] == APPLY_PARTS[0] and parts[1] == APPLY_PARTS[1] and parts[3] == APPLY_PARTS[3]:
-            sums.append(rows[i - 2][2] + rows[i - 1][2] + v + rows[i + 1][2])
+        if rows[i - 1][1] == APPLY_PARTS[0] and rows[i + 1][1] == APPLY_PARTS[2]:
+            sums.append(rows[i - 1][2] + v + rows[i + 1][2])
     return sums
 
 
-def traffic(fetch_csv, write_csv, kernel, copy_bytes):
+def traffic(fetch_csv, write_csv, kernel, copy_bytes, grid=None):
     f = _dispatches(fetch_csv, "FETCH_SIZE")
     w = _dispatches(write_csv, "WRITE_SIZE")
 
     def copy_kib(rows):
         # the copy kernel: the dispatch whose counter is closest to copy_bytes
-        cands = [v for _, name, v in rows if "copy" in name.lower() or "elementwise" in name.lower()]
+        cands = [v for _, name, v, _ in rows if "copy" in name.lower() or "elementwise" in name.lower()]
         return min(cands, key=lambda v: abs(v * 1024 - copy_bytes))
 
     ff = copy_bytes / (copy_kib(f) * 1024)
     fw = copy_bytes / (copy_kib(w) * 1024)
-    fs, ws = _apply_sums(f, kernel), _apply_sums(w, kernel)
+    fs, ws = _apply_sums(f, kernel, grid), _apply_sums(w, kernel, grid)
     fk, wk = sum(fs) / len(fs), sum(ws) / len(ws)
     t = fk * 1024 * ff + wk * 1024 * fw
-    return {"kernel": kernel + " with its fill, gather and assembly", "kernels_hip_sha256": kernels_sha256(),
+    return {"kernel": kernel + " with its gather and assembly" + (f", GEMM grid {grid}" if grid else ""),
+            "kernels_hip_sha256": kernels_sha256(),
             "fetch_kib_per_apply": fk, "write_kib_per_apply": wk, "applies": len(fs), "copy_bytes": copy_bytes,
             "copy_fetch_factor": ff, "copy_write_factor": fw, "traffic_bytes_per_launch": t}
 
 
-def apply_durations(db, kernel):
-    """Durations (us) of the operator applies whose GEMM is `kernel` in a
-    kernel trace: from the start of the fill to the end of the assembly."""
+def apply_durations(db, kernel, grid_y=None):
+    """Durations (us) of the operator applies whose GEMM is `kernel` (with
+    grid_y row blocks if given) in a kernel trace: from the start of the
+    gather to the end of the assembly."""
     con = sqlite3.connect(db)
-    rows = con.execute("select name, start, end from kernels order by start").fetchall()
-    rows = [(short(n), s, e) for n, s, e in rows]
+    rows = con.execute("select name, start, end, grid_y from kernels order by start").fetchall()
     out = []
+    gys = [gy for _, _, _, gy in rows]
+    rows = [(short(n), s, e) for n, s, e, _ in rows]
     for i, (name, s, e) in enumerate(rows):
-        if name != kernel or i < 2 or i + 1 >= len(rows):
+        if name != kernel or i < 1 or i + 1 >= len(rows) or (grid_y and gys[i] != grid_y):
             continue
-        if rows[i - 2][0] == APPLY_PARTS[0] and rows[i - 1][0] == APPLY_PARTS[1] and rows[i + 1][0] == APPLY_PARTS[3]:
-            out.append(((rows[i + 1][2] - rows[i - 2][1]) / 1e3, (e - s) / 1e3))
+        if rows[i - 1][0] == APPLY_PARTS[0] and rows[i + 1][0] == APPLY_PARTS[2]:
+            out.append(((rows[i + 1][2] - rows[i - 1][1]) / 1e3, (e - s) / 1e3))
     return out
 
 
@@ -122,10 +128,12 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(summarise(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 30))
     elif sys.argv[1] == "traffic":
-        for k, v in traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5])).items():
+        grid = int(sys.argv[6]) if len(sys.argv) > 6 else None
+        for k, v in traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), grid).items():
             print(f"{k}: {v}")
     elif sys.argv[1] == "applies":
-        d = [a for a in apply_durations(sys.argv[2], sys.argv[3]) if a[1] > 10.0]
+        gy = int(sys.argv[4]) if len(sys.argv) > 4 else None
+        d = [a for a in apply_durations(sys.argv[2], sys.argv[3], gy) if a[1] > 10.0]
         print(f"applies: {len(d)}")
         print(f"apply_us_mean: {sum(a[0] for a in d) / len(d):.1f}")
         print(f"gemm_us_mean: {sum(a[1] for a in d) / len(d):.1f}")
