@@ -53,7 +53,9 @@ def parse():
                          "H(grad)/H(curl) problems solved together vs one by one")
     ap.add_argument("--batch-count", type=int, default=32)
     ap.add_argument("--batch-max-gb", type=float, default=240.0)
-    ap.add_argument("--batch-precision", choices=["fp64", "fp32-pc", "bf16-pc"], default="fp32-pc")
+    ap.add_argument("--batch-precision", choices=["fp64", "fp32-pc", "bf16-pc"], default="bf16-pc")
+    ap.add_argument("--batch-no-fp64", action="store_true",
+                    help="skip the plain FP64 batch run that the reduced-precision batch is compared with")
     ap.add_argument("--inner-rtol", type=float, default=0.0)
     ap.add_argument("--pc", choices=["hybrid", "additive"], default="hybrid",
                     help="preconditioner form: the symmetric multiplicative hybrid of the paper's experiments "
@@ -260,7 +262,8 @@ def batch_workload(args):
     in 2..10 drawn from default_rng(8) (a draw is redrawn while the batch
     would exceed the memory budget), jittered Kuhn meshes (seed 100 + i),
     load vectors seed 200 + i, solved together to 1e-10 with captured
-    iteration graphs, against the same problems solved one by one."""
+    iteration graphs, against the same problems solved one by one and the
+    same batch with plain FP64 handles."""
     import torch
     from paper_2506_17406_amd import rz
     from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors, uneven_batch
@@ -310,6 +313,37 @@ def batch_workload(args):
         seq.append(prob.solve(b, x, rtol=1e-10)["iterations"])
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t1
+    print(f"one by one: {t_seq * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    # the plain FP64 reference: the same problems as an FP64 batch (the
+    # reduced-precision handles are released first)
+    fp64 = None
+    if args.batch_precision != "fp64" and not args.batch_no_fp64:
+        B.close()
+        for prob in probs:
+            prob.close()
+        probs = []
+        torch.cuda.empty_cache()
+        for sp, n, p, ms, rs in draws:
+            X, C = kuhn_mesh(n, 3, jitter=0.1, seed=ms)
+            probs.append(rz.Problem(X, C, p, sp, pc=args.pc))
+        torch.cuda.synchronize()
+        B64 = rz.Batch(probs)
+        for x in xs:
+            x.zero_()
+        B64.solve(bs, xs, rtol=1e-10)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            for x in xs:
+                x.zero_()
+            infos64 = B64.solve(bs, xs, rtol=1e-10)
+        torch.cuda.synchronize()
+        dt64 = (time.perf_counter() - t1) / args.steps
+        print(f"FP64 batch: {dt64 * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        fp64 = {"value": total / dt64, "ms": dt64 * 1e3,
+                "iterations": {"min": min(i["iterations"] for i in infos64),
+                               "max": max(i["iterations"] for i in infos64)},
+                "max_rel_residual": max(i["rel_residual"] for i in infos64)}
     line = {
         "metric": "Riesz-map solve DOFs/s to rel. residual 1e-10 (uneven batch)",
         "value": total / dt, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -325,6 +359,8 @@ def batch_workload(args):
         "max_rel_residual": max(i["rel_residual"] for i in infos),
         "sequential": {"value": total / t_seq, "seconds": t_seq},
         "speedup_vs_sequential": t_seq / dt,
+        "fp64_batch": fp64,
+        "speedup_vs_fp64_batch": fp64["ms"] / (dt * 1e3) if fp64 else None,
     }
     print(json.dumps(line), flush=True)
 

@@ -75,8 +75,9 @@ typedef struct {
  * of the patch and coarse inverses (accumulating in FP64), so it is a fixed
  * symmetric operator and no refinement is needed.  RZ_BF16_PC: the same
  * with bfloat16 copies of the patch inverses (rounded to nearest through
- * FP32; a quarter of the FP64 bytes) and the FP32 coarse copy; it may cost a few
- * more iterations.  RZ_FP32_IR:
+ * FP32; a quarter of the FP64 bytes; each patch product accumulates in
+ * FP32, far below the 2^-9 rounding of the entries) and the FP32 coarse
+ * copy; it may cost a few more iterations.  RZ_FP32_IR:
  * iterative refinement -- the residual b - A x and the update x += d are
  * FP64; each correction d solves A d = r by PCG to inner_rtol whose operator
  * and preconditioner applies read FP32 copies of the reference tables,
@@ -156,8 +157,9 @@ int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t
  * rz_apply_P_fp32 (RZ_FP32_IR, RZ_FP32_PC and RZ_BF16_PC handles): the
  * preconditioner of rz_solve's iteration -- the reduced-precision patch
  * (FP32, or bfloat16 under RZ_BF16_PC) and FP32 coarse inverses with FP64
- * accumulation, and under RZ_FP32_IR also the FP32 operator inside the
- * hybrid sweep.  RZ_ERR_ARG for a handle without the copies. */
+ * accumulation (FP32 within a bfloat16 patch), and under RZ_FP32_IR also
+ * the FP32 operator inside the hybrid sweep.  RZ_ERR_ARG for a handle
+ * without the copies. */
 int rz_apply_A_fp32(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream);
 int rz_apply_P_fp32(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream);
 

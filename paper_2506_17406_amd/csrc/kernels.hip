@@ -42,8 +42,13 @@ __device__ inline double dpp_mov(double v) {
 // gets the group sum.  Within a 16-lane row: quad_perm [1,0,3,2], quad_perm
 // [2,3,0,1], row_half_mirror, row_mirror; across rows: lane permutes.  Must
 // be called with all 64 lanes active.
-template <int L>
-__device__ inline double group_sum(double v) {
+template <int CTRL>
+__device__ inline float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int L, typename C>
+__device__ inline C group_sum(C v) {
   v += dpp_mov<0xB1>(v);
   v += dpp_mov<0x4E>(v);
   v += dpp_mov<0x141>(v);
@@ -53,10 +58,13 @@ __device__ inline double group_sum(double v) {
   return v;
 }
 
-// stored inverse entries -> FP64 (uint16_t holds bfloat16 bits)
+// stored inverse entries -> the patch kernels' arithmetic type (uint16_t
+// holds bfloat16 bits, which widen exactly to FP32)
+__device__ inline double widen(double v) { return v; }
+__device__ inline double widen(float v) { return double(v); }
+__device__ inline float widen(uint16_t v) { return __uint_as_float(uint32_t(v) << 16); }
 __device__ inline double to_f64(double v) { return v; }
 __device__ inline double to_f64(float v) { return double(v); }
-__device__ inline double to_f64(uint16_t v) { return double(__uint_as_float(uint32_t(v) << 16)); }
 template <typename T>
 __device__ inline T from_f64(double v);
 template <>
@@ -655,6 +663,9 @@ __global__ __launch_bounds__(64 * NW) void k_patch_seg(const int64_t *__restrict
                                                    const int64_t *__restrict__ inv_off, const T *__restrict__ inv,
                                                    const double *__restrict__ r, int64_t ldr, double *__restrict__ z,
                                                    int64_t ldz, int ncol, double scale, const PcgState *st) {
+  // arithmetic: FP64 for FP64/FP32 entries; FP32 for bfloat16 entries (their
+  // rounding, 2^-9, dwarfs FP32 accumulation error)
+  typedef decltype(widen(T())) C;
   constexpr int RPW = 64 / L;        // rows per wave step
   constexpr int W = NQ * L * V;      // columns covered (LDS stride)
   typedef T vecV __attribute__((ext_vector_type(V)));
@@ -707,15 +718,15 @@ __global__ __launch_bounds__(64 * NW) void k_patch_seg(const int64_t *__restrict
     yr[t2] = 0.0;
   }
   __syncthreads();
-  double rj[NQ][G][V], cacc[NQ][G][V];
+  C rj[NQ][G][V], cacc[NQ][G][V];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
       for (int h = 0; h < V; ++h) {
-        rj[q][g][h] = rp[g * W + q * V * L + t * V + h];
-        cacc[q][g][h] = 0.0;
+        rj[q][g][h] = C(rp[g * W + q * V * L + t * V + h]);
+        cacc[q][g][h] = C(0);
       }
   for (int it = 0; it < niter; it += D) {
 #pragma unroll
@@ -728,18 +739,18 @@ __global__ __launch_bounds__(64 * NW) void k_patch_seg(const int64_t *__restrict
       const bool ok = i < r1;
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        const double ri = ok ? rp[g * W + i] : 0.0;
-        double rs = 0.0;
+        const C ri = ok ? C(rp[g * W + i]) : C(0);
+        C rs = C(0);
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
 #pragma unroll
           for (int h = 0; h < V; ++h) {
-            const double a = to_f64(buf[u][q][h]);
+            const C a = widen(buf[u][q][h]);
             rs += a * rj[q][g][h];
             cacc[q][g][h] += a * ri;
           }
         rs = group_sum<L>(rs);
-        if (ok && t == 0) yr[g * W + i] = rs;
+        if (ok && t == 0) yr[g * W + i] = double(rs);
       }
     }
   }
@@ -750,7 +761,7 @@ __global__ __launch_bounds__(64 * NW) void k_patch_seg(const int64_t *__restrict
     for (int g = 0; g < G; ++g)
 #pragma unroll
       for (int h = 0; h < V; ++h) {
-        double v = cacc[q][g][h];
+        C v = cacc[q][g][h];
         if (L <= 16) v += __shfl_xor(v, 16, 64);
         if (L <= 32) v += __shfl_xor(v, 32, 64);
         cacc[q][g][h] = v;
@@ -762,7 +773,7 @@ __global__ __launch_bounds__(64 * NW) void k_patch_seg(const int64_t *__restrict
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int h = 0; h < V; ++h) yc[(wave * G + g) * W + q * V * L + t * V + h] = cacc[q][g][h];
+        for (int h = 0; h < V; ++h) yc[(wave * G + g) * W + q * V * L + t * V + h] = double(cacc[q][g][h]);
   }
   __syncthreads();
   for (int t2 = threadIdx.x; t2 < G * m; t2 += 64 * NW) {

@@ -14,11 +14,11 @@ Bars (written per check):
   FP32; accumulation in FP64);
 * FP32-preconditioner solve -- the same residual and solution bars, and
   at most two iterations more than the oracle's FP64 hybrid PCG;
-* BF16-preconditioner solve (RZ_BF16_PC: bfloat16 patch inverses, FP32
-  coarse inverse) -- apply_P within 1e-2 max |z| of the oracle (patch
-  entries rounded once to bfloat16, unit roundoff 2^-9; a CPU emulation
-  that rounds the oracle's inverses the same way stays below 1.3e-3 on
-  these cases) and, for p > 1, at least 1e-5 away
+* BF16-preconditioner solve (RZ_BF16_PC: bfloat16 patch inverses with FP32
+  arithmetic inside a patch, FP32 coarse inverse) -- apply_P within 1e-2
+  max |z| of the oracle (patch entries rounded once to bfloat16, unit
+  roundoff 2^-9; a CPU emulation that rounds the oracle's inverses the same
+  way stays below 1.3e-3 on these cases) and, for p > 1, at least 1e-5 away
   (the bfloat16 copy ran, not the FP32 one); the solve meets the same
   residual, solution and iteration bars as the FP32 one (the emulation
   takes the FP64 count on every case but the exact p = 1 ones, one more);
