@@ -82,7 +82,7 @@ typedef struct {
  * FP64; each correction d solves A d = r by PCG to inner_rtol whose operator
  * and preconditioner applies read FP32 copies of the reference tables,
  * weights, patch inverses and coarse inverse (FP32 MFMA, FP32 accumulation
- * inside a cell, FP64 scatter and FP64 Krylov vectors and inner products).
+ * inside a cell, FP64 assembly and FP64 Krylov vectors and inner products).
  * The copies are rounded from the FP64 factors built at setup.  If an outer
  * step contracts the true residual by less than a factor 2 the remaining
  * corrections use the FP64 applies. */
@@ -106,7 +106,8 @@ typedef struct {
   double beta;            /* coefficient of (u, v), > 0 */
   int32_t max_iter;       /* PCG iteration cap, per inner solve under refinement (<= 0: 1000) */
   int32_t precision;      /* rz_precision */
-  double inner_rtol;      /* refinement: relative residual of each correction solve (<= 0: 1e-4) */
+  double inner_rtol;      /* refinement: relative residual of each correction solve (<= 0: 3e-3,
+                           * about the contraction one FP32-operator correction can give) */
   int32_t pc;             /* rz_pc */
   int32_t eager;          /* nonzero: rz_solve launches every kernel directly; 0: its PCG iteration
                              chunks are captured into HIP graphs (per solution vector and column
@@ -153,7 +154,8 @@ int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t
 /* The FP32-copy applies, with the rz_apply_A / rz_apply_P argument
  * conventions (FP64 vectors in and out).  rz_apply_A_fp32 (RZ_FP32_IR
  * handles): the reference tables, weights and x are rounded to FP32 and
- * contracted by FP32 MFMA, cell results are scatter-added in FP64.
+ * contracted by FP32 MFMA (FP32 accumulation per cell); the cell results
+ * are summed into each dof in FP64 in a fixed order.
  * rz_apply_P_fp32 (RZ_FP32_IR, RZ_FP32_PC and RZ_BF16_PC handles): the
  * preconditioner of rz_solve's iteration -- the reduced-precision patch
  * (FP32, or bfloat16 under RZ_BF16_PC) and FP32 coarse inverses with FP64

@@ -56,7 +56,10 @@ struct rz_problem {
   int64_t off_I = 0;
   int max_iter = 1000;
   int precision = RZ_FP64;
-  double inner_rtol = 1e-4;
+  // correction solves to 3e-3: an outer step cannot contract the true
+  // residual by much more than ~1e-3 (the FP32 operator's error times the
+  // condition number), so tighter inner solves only add iterations
+  double inner_rtol = 3e-3;
   // preconditioner form; hybrid: group weights and local column ranges
   int pc = RZ_PC_ADDITIVE;
   double rho_I = 1.0, rho_G = 1.0;
@@ -648,15 +651,15 @@ static void hybrid_apply(rz_problem *P, const double *r, int64_t ldr, double *z,
   if (P->col_int < n) rz::launch_apply_A(P->at, z, ldz, sres, nd, nc, st, s, loA, P->col_int, n, -1.0);
   // last: only the interior rows of the tracked residual are read afterwards
   // (by the final Jacobi step), so the second interface correction is
-  // applied with A[I, Gamma] alone (FP64 path)
+  // applied with A[I, Gamma] alone
   auto interface = [&](bool last) {
     for (auto &pa : P->pas) rz::launch_patch_apply(pa, sres, nd, d, nd, nc, st, s, loP, w2);
     rz::launch_add(nd, d, z, ldz, nc, st, s);
-    if (last && !loA) {
+    if (last) {
       if (P->col_int < n)  // no interior rows: nothing reads the residual again
-        rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, false, 0, P->col_int, -1.0, P->col_int, P->off_I);
+        rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, loA, 0, P->col_int, -1.0, P->col_int, P->off_I);
     } else
-      rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, loA, 0, P->col_int, -1.0, 0, 0, false, !last);
+      rz::launch_apply_A(P->at, d, nd, sres, nd, nc, st, s, loA, 0, P->col_int, -1.0, 0, 0, false, true);
   };
   interface(false);
   rz::launch_coarse_gather(P->ca, sres, nd, nc, s);

@@ -433,22 +433,27 @@ __global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A,
 // matrices; the A fragments of all q for one k-step are contiguous (fragment
 // order (mb, jb, q, lane)).  The next k-step's fragments and x values are
 // loaded before the current step's Q*NB MFMAs are issued.
-// ---- FP64 operator apply in three stages: cell gather, GEMM, assembly.
+// ---- Operator apply in three stages: cell gather, GEMM, assembly (FP64, or
+// FP32 with FP32 tables: T is the type of the cell vectors and the MFMA).
 // Cell-local vectors in MFMA fragment order (ncp = cells rounded up to 256; per
-// column KP ncp doubles of Xc and NP ncp of Yc):
+// column KP ncp entries of Xc and NP ncp of Yc):
 //   Xc[(kb ncp + c16) 4 + kk 16 + ci] = x[cell_dofs[cell][4 kb + kk]]
 //     (cell = c16 + ci, c16 a multiple of 16; zero beyond n and for padding
-//     cells): lane l of a B fragment reads kk = l / 16, ci = l % 16;
-//   Yc[yc_index(ncp, cell, r)] = (A_T x_T)_r, with the accumulator element v
-//     of lane l (row 16 mb + l/16 + 4v, cell c16 + l % 16) at
-//     (mb ncp + c16) 16 + 64 v + l: 16 rows x 16 cells per (mb, c16) block.
+//     cells): lane l of a B fragment reads kk = l / 16, ci = l % 16 (the
+//     same for the FP64 and FP32 16x16x4 MFMA);
+//   Yc[yc_index(ncp, cell, r)] = (A_T x_T)_r: row rr = r % 16 of row block
+//     mb = r / 16 and cell c16 + ci at (mb ncp + c16) 16 + 64 (rr / 4) +
+//     16 (rr % 4) + ci, 16 rows x 16 cells per (mb, c16) block.  The FP64
+//     accumulator element v of lane l (row l/16 + 4v, cell l % 16) lands at
+//     64 v + l; the FP32 one (row 4 (l/16) + v) at 64 (l/16) + 16 v + l % 16.
+template <typename T>
 __global__ void k_gather_cells(int n, int KP, int64_t nc, int64_t ncp, int kb0, int kb1,
                                const int32_t *__restrict__ cd, const double *__restrict__ x, int64_t ldx,
-                               double *__restrict__ Xc, const PcgState *st) {
+                               T *__restrict__ Xc, const PcgState *st) {
   const int c = blockIdx.y;
   if (st && st[c].done) return;
   const double *xc = x + int64_t(c) * ldx;
-  double *X = Xc + int64_t(c) * KP * ncp + int64_t(kb0) * ncp * 4;
+  T *X = Xc + int64_t(c) * KP * ncp + int64_t(kb0) * ncp * 4;
   const int64_t nblk = ncp / 16;
   const int64_t total = int64_t(kb1 - kb0) * ncp * 4;
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
@@ -456,8 +461,16 @@ __global__ void k_gather_cells(int n, int KP, int64_t nc, int64_t ncp, int kb0, 
     const int64_t b = t >> 6;
     const int64_t cell = (b % nblk) * 16 + ci;
     const int k = (kb0 + int(b / nblk)) * 4 + kk;
-    X[t] = (cell < nc && k < n) ? xc[cd[cell * n + k]] : 0.0;
+    X[t] = (cell < nc && k < n) ? T(xc[cd[cell * n + k]]) : T(0);
   }
+}
+
+__device__ inline d4 mfma16x16x4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+typedef float f4 __attribute__((ext_vector_type(4)));
+__device__ inline f4 mfma16x16x4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 // Yc = sum_q w_q R_q Xc over the k-blocks [kb0, kb1), per cell: one wave owns
@@ -466,11 +479,12 @@ __global__ void k_gather_cells(int n, int KP, int64_t nc, int64_t ncp, int kb0, 
 // next k-step's are loaded before the current MFMAs.  All loads are plain
 // (no indirection), so the prefetch is never serialised behind a dependent
 // load.
-template <int Q, int NB, bool FULL>
+template <typename T, int Q, int NB, bool FULL>
 __global__ __launch_bounds__(256) void k_apply_A(int mb0, int KB, int kb0_, int kb1_, int64_t nc, int64_t ncp,
-                                                 const double *__restrict__ Af, const double *__restrict__ w,
-                                                 const double *__restrict__ Xc, double *__restrict__ Yc, int KP,
+                                                 const T *__restrict__ Af, const T *__restrict__ w,
+                                                 const T *__restrict__ Xc, T *__restrict__ Yc, int KP,
                                                  int NP, const PcgState *st) {
+  typedef T acc_t __attribute__((ext_vector_type(4)));
   if (st && st[blockIdx.z].done) return;
   // the k-block range: all of them, or the columns of a restricted apply
   const int kb0 = FULL ? 0 : kb0_, kb1 = FULL ? KB : kb1_;
@@ -479,40 +493,39 @@ __global__ __launch_bounds__(256) void k_apply_A(int mb0, int KB, int kb0_, int 
   // which the vector L1 then serves once) and take consecutive cell groups
   const int mb = mb0 + blockIdx.y;  // row blocks from mb0 (a row-restricted apply starts later)
   const int li = lane & 15, lk = lane >> 4;
-  const double *X = Xc + int64_t(blockIdx.z) * KP * ncp + lane;
-  double *Y = Yc + int64_t(blockIdx.z) * NP * ncp + lane;
+  const T *X = Xc + int64_t(blockIdx.z) * KP * ncp + lane;
+  T *Y = Yc + int64_t(blockIdx.z) * NP * ncp;
   const int64_t cell0 = (int64_t(blockIdx.x) * 4 + wave) * (16 * NB);
-  double wv[NB][Q];
+  T wv[NB][Q];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int64_t c = cell0 + nb * 16 + li;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) wv[nb][q] = c < nc ? w[c * Q + q] : 0.0;
+    for (int q = 0; q < Q; ++q) wv[nb][q] = c < nc ? w[c * Q + q] : T(0);
   }
-  d4 acc[NB];
+  acc_t acc[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = d4{0, 0, 0, 0};
-  const double *Ab = Af + size_t(mb) * KB * Q * 64 + lane;
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = acc_t{0, 0, 0, 0};
+  const T *Ab = Af + size_t(mb) * KB * Q * 64 + lane;
   // fragments of k-block kb: the A fragments of all Q matrices and the B
-  // fragments of cells cell0 + 16 nb .. + 15 (64 consecutive doubles each)
-  auto load = [&](int kb, double *a, double *xv) {
-    const double *An = Ab + size_t(kb) * Q * 64;
+  // fragments of cells cell0 + 16 nb .. + 15 (64 consecutive entries each)
+  auto load = [&](int kb, T *a, T *xv) {
+    const T *An = Ab + size_t(kb) * Q * 64;
 #pragma unroll
     for (int q = 0; q < Q; ++q) a[q] = An[q * 64];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) xv[nb] = X[(int64_t(kb) * ncp + cell0 + nb * 16) * 4];
   };
-  auto step = [&](const double *a, const double *xv) {
+  auto step = [&](const T *a, const T *xv) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], wv[nb][q] * xv[nb], acc[nb], 0, 0, 0);
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma16x16x4(a[q], wv[nb][q] * xv[nb], acc[nb]);
   };
   // two register sets in turn: the loads of one k-block are in flight while
   // the MFMAs of the other run (no register copies between steps)
   // (scheduling barriers keep each set's loads ahead of the other's MFMAs)
-  double aA[Q], xA[NB], aB[Q], xB[NB];
+  T aA[Q], xA[NB], aB[Q], xB[NB];
   load(kb0, aA, xA);
   int jb = kb0;
   for (; jb + 1 < kb1; jb += 2) {
@@ -526,112 +539,37 @@ __global__ __launch_bounds__(256) void k_apply_A(int mb0, int KB, int kb0_, int 
     __builtin_amdgcn_sched_barrier(0);
   }
   if (jb < kb1) step(aA, xA);
-  // FP64 16x16x4 accumulator layout: lane l, element v holds row l/16 + 4v,
-  // column (cell) l%16; stored whole, 64 consecutive doubles per (nb, v)
+  // accumulator layouts: FP64 16x16x4, lane l, element v holds row l/16 + 4v
+  // (64 consecutive entries per (nb, v)); FP32, row 4 (l/16) + v (16-entry
+  // runs); column (cell) l%16 in both
+  const int off = sizeof(T) == 8 ? lane : 64 * (lane >> 4) + li;
+  const int vstep = sizeof(T) == 8 ? 64 : 16;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Y[(int64_t(mb) * ncp + cell0 + nb * 16) * 16 + 64 * v] = acc[nb][v];
+    for (int v = 0; v < 4; ++v) Y[(int64_t(mb) * ncp + cell0 + nb * 16) * 16 + off + vstep * v] = acc[nb][v];
 }
 
-// y_i += alpha sum over the (cell, local row) pairs of dof i of Yc (a fixed
-// order: deterministic, no atomics)
-// y[i] (+)= alpha sum of dof i's cell products, i in [d0, d1); with xclr,
-// also x[i] = 0 (the gather that read x has completed)
+// y[i] (+)= alpha sum over the (cell, local row) pairs of dof i of Yc, in
+// FP64 and a fixed order (deterministic, no atomics), i in [d0, d1); with
+// xclr, also x[i] = 0 (the gather that read x has completed)
+template <typename T>
 __global__ void k_assemble(int64_t d0, int64_t d1, const int64_t *__restrict__ ptr, const int32_t *__restrict__ ent,
-                           int64_t ystride, const double *__restrict__ Yc, double *__restrict__ y, int64_t ldy,
+                           int64_t ystride, const T *__restrict__ Yc, double *__restrict__ y, int64_t ldy,
                            double alpha, int overwrite, double *__restrict__ xclr, int64_t ldx, const PcgState *st) {
   const int c = blockIdx.y;
   if (st && st[c].done) return;
-  const double *Y = Yc + int64_t(c) * ystride;
+  const T *Y = Yc + int64_t(c) * ystride;
   double *yc = y + int64_t(c) * ldy;
   double *xc = xclr ? xclr + int64_t(c) * ldx : nullptr;
   for (int64_t i = d0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < d1; i += int64_t(gridDim.x) * blockDim.x) {
     double sum = 0.0;
-    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) sum += Y[ent[e]];
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) sum += double(Y[ent[e]]);
     yc[i] = overwrite ? alpha * sum : yc[i] + alpha * sum;
     if (xc) xc[i] = 0.0;
   }
 }
 
-
-// FP32 operator apply (the inner operator of mixed-precision refinement):
-// the same wave decomposition as k_apply_A with FP32 tables, weights and
-// MFMA (FP32 accumulation); y stays FP64.
-typedef float f4 __attribute__((ext_vector_type(4)));
-template <int Q, int NB, bool FULL>
-__global__ __launch_bounds__(256) void k_apply_A32(int n, int NMB, int KB, int kb0_, int kb1_, int64_t nc, const float *__restrict__ Af,
-                                                   const float *__restrict__ w, const int32_t *__restrict__ cd,
-                                                   const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
-                                                   int64_t ldy, double alpha, const PcgState *st) {
-  if (st && st[blockIdx.z].done) return;
-  // the k-block range: all of them, or the columns of a restricted apply
-  const int kb0 = FULL ? 0 : kb0_, kb1 = FULL ? KB : kb1_;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int2 bxy = make_int2(blockIdx.x, blockIdx.y);
-  const int mb = bxy.y * 4 + wave;
-  if (mb >= NMB) return;
-  const int li = lane & 15, lk = lane >> 4;
-  const double *xr = x + int64_t(blockIdx.z) * ldx;
-  double *yr = y + int64_t(blockIdx.z) * ldy;
-  const int64_t cell0 = int64_t(bxy.x) * (16 * NB);
-  const int32_t *cdp[NB];
-  float wv[NB][Q];
-  bool valid[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int64_t c = cell0 + nb * 16 + li;
-    valid[nb] = c < nc;
-    const int64_t cc = valid[nb] ? c : nc - 1;
-    cdp[nb] = cd + cc * n;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) wv[nb][q] = valid[nb] ? w[cc * Q + q] : 0.0f;
-  }
-  f4 acc[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0, 0, 0, 0};
-  const float *Ab = Af + size_t(mb) * KB * Q * 64 + lane;
-  float a0[Q], x0[NB];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) a0[q] = Ab[size_t(kb0) * Q * 64 + q * 64];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) x0[nb] = kb0 * 4 + lk < n ? float(xr[cdp[nb][kb0 * 4 + lk]]) : 0.0f;
-  for (int jb = kb0; jb < kb1; ++jb) {
-    float a1[Q], x1[NB];
-    if (jb + 1 < kb1) {
-      const float *An = Ab + size_t(jb + 1) * Q * 64;
-#pragma unroll
-      for (int q = 0; q < Q; ++q) a1[q] = An[q * 64];
-      const int col = (jb + 1) * 4 + lk;
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) x1[nb] = col < n ? float(xr[cdp[nb][col]]) : 0.0f;
-    } else {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) a1[q] = 0.0f;
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) x1[nb] = 0.0f;
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[q], wv[nb][q] * x0[nb], acc[nb], 0, 0, 0);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) a0[q] = a1[q];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) x0[nb] = x1[nb];
-  }
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    if (!valid[nb]) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      // FP32 16x16x4 accumulator layout: lane l, element v holds row 4 (l/16) + v, column l%16
-      const int row = mb * 16 + lk * 4 + v;
-      if (row < n) atomicAdd(&yr[cdp[nb][row]], alpha * double(acc[nb][v]));
-    }
-  }
-}
 
 __global__ void k_to_float(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
@@ -1387,7 +1325,7 @@ void launch_pack_tiles(int N, int n, const double *Ainv, double *tiles, hipStrea
                      tiles);
 }
 
-template <int Q>
+template <typename T, int Q>
 static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1, const double *x, int64_t ldx,
                       double *y, int64_t ldy, double alpha, const PcgState *st, hipStream_t s, int mb0, int64_t d0,
                       bool overwrite, double *xclr) {
@@ -1395,11 +1333,16 @@ static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1
   const int KB = t.KP / 4;
   const bool full = kb0 == 0 && kb1 == KB && mb0 == 0;
   const int ncol = int(grid.z);
-  hipLaunchKernelGGL(k_gather_cells, dim3(grid_for(int64_t(kb1 - kb0) * t.ncp * 4, 256, 4096), ncol), dim3(256), 0,
-                     s, t.n, t.KP, t.n_cells, t.ncp, kb0, kb1, t.cell_dofs, x, ldx, t.Xc, st);
+  // FP32: the tables' FP32 copies, and the cell vectors in the first half of
+  // the FP64 work buffers
+  const T *Af = sizeof(T) == 8 ? (const T *)t.Afrag : (const T *)t.Afrag32;
+  const T *w = sizeof(T) == 8 ? (const T *)t.w : (const T *)t.w32;
+  T *Xc = reinterpret_cast<T *>(t.Xc), *Yc = reinterpret_cast<T *>(t.Yc);
+  hipLaunchKernelGGL(k_gather_cells<T>, dim3(grid_for(int64_t(kb1 - kb0) * t.ncp * 4, 256, 4096), ncol), dim3(256),
+                     0, s, t.n, t.KP, t.n_cells, t.ncp, kb0, kb1, t.cell_dofs, x, ldx, Xc, st);
 #define RZ_A64(NBV, F)                                                                                        \
-  hipLaunchKernelGGL((k_apply_A<Q, NBV, F>), grid, dim3(256), 0, s, mb0, KB, kb0, kb1, t.n_cells, t.ncp,     \
-                     t.Afrag, t.w, t.Xc, t.Yc, t.KP, t.NP, st)
+  hipLaunchKernelGGL((k_apply_A<T, Q, NBV, F>), grid, dim3(256), 0, s, mb0, KB, kb0, kb1, t.n_cells, t.ncp,  \
+                     Af, w, Xc, Yc, t.KP, t.NP, st)
   if (full) {
     if (NB == 4) RZ_A64(4, true);
     else if (NB == 2) RZ_A64(2, true);
@@ -1411,28 +1354,8 @@ static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1
   }
 #undef RZ_A64
   if (d1 > d0)
-    hipLaunchKernelGGL(k_assemble, dim3(grid_for(d1 - d0, 256, 4096), ncol), dim3(256), 0, s, d0, d1, t.asm_ptr,
-                       t.asm_ent, int64_t(t.NP) * t.ncp, t.Yc, y, ldy, alpha, overwrite ? 1 : 0, xclr, ldx, st);
-}
-
-template <int Q>
-static void apply_A32_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1, const double *x, int64_t ldx,
-                        double *y, int64_t ldy, double alpha, const PcgState *st, hipStream_t s) {
-  const int KB = t.KP / 4, NMB = t.NP / 16;
-  const bool full = kb0 == 0 && kb1 == KB;
-#define RZ_A32(NBV, F)                                                                                            \
-  hipLaunchKernelGGL((k_apply_A32<Q, NBV, F>), grid, dim3(256), 0, s, t.n, NMB, KB, kb0, kb1, t.n_cells,         \
-                     t.Afrag32, t.w32, t.cell_dofs, x, ldx, y, ldy, alpha, st)
-  if (full) {
-    if (NB == 4) RZ_A32(4, true);
-    else if (NB == 2) RZ_A32(2, true);
-    else RZ_A32(1, true);
-  } else {
-    if (NB == 4) RZ_A32(4, false);
-    else if (NB == 2) RZ_A32(2, false);
-    else RZ_A32(1, false);
-  }
-#undef RZ_A32
+    hipLaunchKernelGGL(k_assemble<T>, dim3(grid_for(d1 - d0, 256, 4096), ncol), dim3(256), 0, s, d0, d1, t.asm_ptr,
+                       t.asm_ent, int64_t(t.NP) * t.ncp, Yc, y, ldy, alpha, overwrite ? 1 : 0, xclr, ldx, st);
 }
 
 void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
@@ -1446,31 +1369,27 @@ void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double 
   }
   const int kb0 = col0 / 4, kb1 = (col1 + 3) / 4;
   const int NMB = t.NP / 16;
-  const int mb0 = lo && t.Afrag32 ? 0 : row0 / 16;
+  const int mb0 = row0 / 16;
   // cells per wave: as many as keep >= 2048 waves in flight (A-fragment reuse
   // vs occupancy), counting the row blocks this launch covers; an apply over
   // all rows of one column takes the tuned value where there is one
   int NB = 4;
   while (NB > 1 && ((t.n_cells + 16 * NB - 1) / (16 * NB)) * (NMB - mb0) * n_rhs < 2048) NB /= 2;
   if (n_rhs == 1 && mb0 == 0 && (t.nb1 == 1 || t.nb1 == 2 || t.nb1 == 4)) NB = t.nb1;
-  dim3 grid(unsigned((t.n_cells + 16 * NB - 1) / (16 * NB)), unsigned((NMB + 3) / 4), unsigned(n_rhs));
-  if (lo && t.Afrag32) {
-    // one kernel with an atomic scatter: clear y before, x after
-    if (overwrite) launch_fill(y, t.n_dofs, ldy, n_rhs, st, s);
-    if (t.Q == 12) apply_A32_q<12>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
-    else if (t.Q == 7) apply_A32_q<7>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
-    else apply_A32_q<4>(t, NB, grid, kb0, kb1, x, ldx, y, ldy, alpha, st, s);
-    if (clear_x) launch_fill(const_cast<double *>(x), t.n_dofs, ldx, n_rhs, st, s);
-    return;
-  }
-  // FP64 GEMM: a block is one row block x 4 waves x 16 NB cells; a row-
+  // GEMM: a block is one row block x 4 waves x 16 NB cells; a row-
   // restricted apply starts at the row block of row0 and assembles the dofs
   // from dof0 on (the interior rows and dofs: both are trailing blocks)
   const dim3 g64(unsigned((t.n_cells + 64 * NB - 1) / (64 * NB)), unsigned(NMB - mb0), unsigned(n_rhs));
   double *xclr = clear_x ? const_cast<double *>(x) : nullptr;
-  if (t.Q == 12) apply_A_q<12>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0, overwrite, xclr);
-  else if (t.Q == 7) apply_A_q<7>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0, overwrite, xclr);
-  else apply_A_q<4>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0, overwrite, xclr);
+#define RZ_AQ(TT)                                                                                               \
+  do {                                                                                                          \
+    if (t.Q == 12) apply_A_q<TT, 12>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0, overwrite, xclr); \
+    else if (t.Q == 7) apply_A_q<TT, 7>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0, overwrite, xclr); \
+    else apply_A_q<TT, 4>(t, NB, g64, kb0, kb1, x, ldx, y, ldy, alpha, st, s, mb0, dof0, overwrite, xclr);      \
+  } while (0)
+  if (lo && t.Afrag32) RZ_AQ(float);
+  else RZ_AQ(double);
+#undef RZ_AQ
 }
 
 // patch apply: largest G in {8,4,2,1} with G <= ncol, LDS <= 96 KB, MAXJ * G <= 32

@@ -61,7 +61,7 @@ struct ApplyATables {
 // overwrite; st: per-column state (columns that are done are skipped) or
 // null; lo: the FP32 copies.  [col0, col1): only these local columns of A_T
 // take part (x is zero on the others: a restricted apply); y += alpha A x.
-// row0 > 0 (FP64 only): only the local rows from row0 and the global dofs
+// row0 > 0: only the local rows from row0 and the global dofs
 // from dof0 are updated (the trailing interior blocks of the local and
 // global numberings).  clear_x: x is zeroed once the apply has read it (x
 // must be writable; not with dof0 > 0).
