@@ -10,11 +10,21 @@
         (FETCH_SIZE, then WRITE_SIZE; counter_collection CSVs), each scaled by
         what the same counter reads for the plain copy kernel of copy_bytes
         bytes read and written in the same run.  Prints key: value lines;
+    python -m paper_2506_17406_amd.profile_summary mfma <counters.csv> <kernel> [grid]
+        MFMA use of <kernel> (of grid work-items if given) from a --pmc run of
+        SQ_VALU_MFMA_BUSY_CYCLES and SQ_INSTS_VALU_MFMA_MOPS_F64: the FP64
+        MFMA flops counted (512 per MOP) over each dispatch's own duration
+        (its start/end timestamps) against the 78.6 TFLOP/s FP64 peak, and
+        the busy cycles over duration x 2.4 GHz x 1024 SIMDs;
+    python -m paper_2506_17406_amd.profile_summary bandwidth <fetch.csv> <write.csv> <results.db> <copy_bytes> [top]
+        per kernel name: mean HBM bytes per dispatch (counters scaled by the
+        copy kernel, as for traffic) over mean duration in a kernel trace;
     python -m paper_2506_17406_amd.profile_summary applies <results.db> <kernel> [grid_y]
         mean duration of those applies (gather start to assembly end) and of
         their GEMM kernel in a kernel trace (with grid_y, only GEMM dispatches
         of that many row blocks).
 """
+import collections
 import csv
 import hashlib
 import os
@@ -45,8 +55,13 @@ def kernels_sha256():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-# one operator apply = cell gather, the GEMM kernel, assembly
+# one operator apply = cell gather, the GEMM kernel, assembly (base names,
+# template arguments dropped)
 APPLY_PARTS = ("k_gather_cells", "GEMM", "k_assemble")
+
+
+def base(name):
+    return name.split("<")[0]
 
 
 def _dispatches(path, counter):
@@ -67,7 +82,7 @@ def _apply_sums(rows, kernel, grid=None):
     for i, (_, name, v, g) in enumerate(rows):
         if name != kernel or i < 1 or i + 1 >= len(rows) or (grid and g != grid):
             continue
-        if rows[i - 1][1] == APPLY_PARTS[0] and rows[i + 1][1] == APPLY_PARTS[2]:
+        if base(rows[i - 1][1]) == APPLY_PARTS[0] and base(rows[i + 1][1]) == APPLY_PARTS[2]:
             sums.append(rows[i - 1][2] + v + rows[i + 1][2])
     return sums
 
@@ -104,9 +119,68 @@ def apply_durations(db, kernel, grid_y=None):
     for i, (name, s, e) in enumerate(rows):
         if name != kernel or i < 1 or i + 1 >= len(rows) or (grid_y and gys[i] != grid_y):
             continue
-        if rows[i - 1][0] == APPLY_PARTS[0] and rows[i + 1][0] == APPLY_PARTS[2]:
+        if base(rows[i - 1][0]) == APPLY_PARTS[0] and base(rows[i + 1][0]) == APPLY_PARTS[2]:
             out.append(((rows[i + 1][2] - rows[i - 1][1]) / 1e3, (e - s) / 1e3))
     return out
+
+
+SIMDS = 256 * 4  # MI355X: 256 CUs of 4 SIMDs, 2.4 GHz, FP64 MFMA 78.6 TFLOP/s
+CLOCK_HZ = 2.4e9
+PEAK_FP64 = 78.6e12
+
+
+def mfma(path, kernel, grid=None):
+    per = collections.defaultdict(dict)
+    for r in csv.DictReader(open(path)):
+        if short(r["Kernel_Name"]) != kernel or (grid and int(r["Grid_Size"]) != grid):
+            continue
+        d = per[int(r["Dispatch_Id"])]
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+        d["ns"] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+    # dispatches that did work (launches that found their column converged exit at once)
+    rows = [d for d in per.values() if d.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0) > 0 and d["ns"] > 10e3]
+    flops = sum(d["SQ_INSTS_VALU_MFMA_MOPS_F64"] * 512 for d in rows) / len(rows)
+    ns = sum(d["ns"] for d in rows) / len(rows)
+    busy = sum(d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0) / (d["ns"] * 1e-9 * CLOCK_HZ * SIMDS) for d in rows) / len(rows)
+    return {"kernel": kernel + (f", grid {grid}" if grid else ""), "dispatches": len(rows),
+            "fp64_mfma_flops_per_dispatch": flops, "mean_duration_us": ns / 1e3,
+            "fp64_mfma_tflops": flops / (ns * 1e-9) / 1e12, "fraction_of_fp64_peak": flops / (ns * 1e-9) / PEAK_FP64,
+            "mfma_busy_cycles_fraction": busy}
+
+
+def bandwidth(fetch_csv, write_csv, db, copy_bytes, top=20):
+    f = _dispatches(fetch_csv, "FETCH_SIZE")
+    w = _dispatches(write_csv, "WRITE_SIZE")
+
+    def copy_kib(rows):
+        cands = [v for _, name, v, _ in rows if "copy" in name.lower() or "elementwise" in name.lower()]
+        return min(cands, key=lambda v: abs(v * 1024 - copy_bytes))
+
+    ff, fw = copy_bytes / (copy_kib(f) * 1024), copy_bytes / (copy_kib(w) * 1024)
+    by = collections.defaultdict(lambda: [0.0, 0])
+    for rows, fac in ((f, ff), (w, fw)):
+        for _, name, v, _ in rows:
+            by[name][0] += v * 1024 * fac
+    for _, name, _, _ in f:
+        by[name][1] += 1
+    con = sqlite3.connect(db)
+    dur = collections.defaultdict(list)
+    for n, d in con.execute("select name, duration from kernels").fetchall():
+        dur[short(n)].append(d)
+    out = ["| kernel | dispatches (counters) | mean MB per dispatch | mean duration (us) | GB/s |",
+           "|---|---|---|---|---|"]
+    rows = []
+    for name, (b, n) in by.items():
+        ds = [d for d in dur.get(name, []) if d > 0]
+        if not ds or n == 0:
+            continue
+        mb = b / n / 1e6
+        us = sum(ds) / len(ds) / 1e3
+        rows.append((b / n / (us * 1e-6) / 1e9 * (us > 0), name, n, mb, us))
+    tot = {name: sum(dur.get(name, [0])) for name in by}
+    for gbs, name, n, mb, us in sorted(rows, key=lambda r: -tot[r[1]])[:top]:
+        out.append(f"| {name} | {n} | {mb:.2f} | {us:.1f} | {gbs:.0f} |")
+    return "\n".join(out)
 
 
 def read_traffic(path):
@@ -131,6 +205,13 @@ if __name__ == "__main__":
         grid = int(sys.argv[6]) if len(sys.argv) > 6 else None
         for k, v in traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), grid).items():
             print(f"{k}: {v}")
+    elif sys.argv[1] == "mfma":
+        grid = int(sys.argv[4]) if len(sys.argv) > 4 else None
+        for k, v in mfma(sys.argv[2], sys.argv[3], grid).items():
+            print(f"{k}: {v}")
+    elif sys.argv[1] == "bandwidth":
+        print(bandwidth(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]),
+                        int(sys.argv[6]) if len(sys.argv) > 6 else 20))
     elif sys.argv[1] == "applies":
         gy = int(sys.argv[4]) if len(sys.argv) > 4 else None
         d = [a for a in apply_durations(sys.argv[2], sys.argv[3], gy) if a[1] > 10.0]
