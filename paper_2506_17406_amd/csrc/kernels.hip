@@ -198,6 +198,22 @@ __global__ void k_patch_assemble(const int32_t *__restrict__ item_patch, const i
 // ---- batched blocked Cholesky (lower) and inverse, block size 32
 constexpr int BS = 32;
 
+// acc += op(A) op(B) for the 16 x 16 quadrant (wave >> 1, wave & 1) of a
+// 32 x 32 tile product over K = 32 (FP64 MFMA 16x16x4; A and B are LDS
+// tiles, op = transpose where asked).  acc element v of lane l is row
+// 16 (wave >> 1) + l/16 + 4v, column 16 (wave & 1) + l%16.
+template <bool TA, bool TB>
+__device__ inline void tile_mfma(const double (*A)[BS + 1], const double (*B)[BS + 1], d4 &acc) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ri = 16 * (wave >> 1) + (lane & 15), cj = 16 * (wave & 1) + (lane & 15), lk = lane >> 4;
+#pragma unroll
+  for (int k0 = 0; k0 < BS; k0 += 4) {
+    const double a = TA ? A[k0 + lk][ri] : A[ri][k0 + lk];
+    const double b = TB ? B[cj][k0 + lk] : B[k0 + lk][cj];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+}
+
 __global__ void k_chol_diag(int N, int kb, double *__restrict__ A, int *__restrict__ status) {
   __shared__ double L[BS][BS + 1];
   __shared__ double piv;
@@ -281,12 +297,13 @@ __global__ void k_chol_update(int N, int kb, double *__restrict__ A) {
     Lb[i][j] = M[int64_t(oj + i) * N + o + j];
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
-    const int i = t / BS, j = t % BS;
-    double s = 0;
-#pragma unroll 8
-    for (int m = 0; m < BS; ++m) s += La[i][m] * Lb[j][m];
-    M[int64_t(oi + i) * N + oj + j] -= s;
+  d4 acc = {0, 0, 0, 0};
+  tile_mfma<false, true>(La, Lb, acc);  // La Lb^T
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 16 * (wave >> 1) + (lane >> 4) + 4 * v, j = 16 * (wave & 1) + (lane & 15);
+    M[int64_t(oi + i) * N + oj + j] -= acc[v];
   }
 }
 
@@ -301,10 +318,7 @@ __global__ void k_trtri_step(int N, int s, const double *__restrict__ A, double 
   const double *M = A + int64_t(blockIdx.y) * N * N;
   double *Y = X + int64_t(blockIdx.y) * N * N;
   const int oi = ib * BS, oj = jb * BS;
-  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
-    const int i = t / BS, j = t % BS;
-    S[i][j] = (s == 0 && i == j) ? 1.0 : 0.0;
-  }
+  d4 acc = {0, 0, 0, 0};  // sum over mb of L[ib][mb] X[mb][jb] (this wave's quadrant)
   for (int mb = jb; mb < ib; ++mb) {
     __syncthreads();
     for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
@@ -313,12 +327,14 @@ __global__ void k_trtri_step(int N, int s, const double *__restrict__ A, double 
       Xt[i][j] = Y[int64_t(mb * BS + i) * N + oj + j];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
-      const int i = t / BS, j = t % BS;
-      double acc = 0;
-#pragma unroll 8
-      for (int m = 0; m < BS; ++m) acc += Lt[i][m] * Xt[m][j];
-      S[i][j] -= acc;
+    tile_mfma<false, false>(Lt, Xt, acc);
+  }
+  {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * (wave >> 1) + (lane >> 4) + 4 * v, j = 16 * (wave & 1) + (lane & 15);
+      S[i][j] = ((s == 0 && i == j) ? 1.0 : 0.0) - acc[v];
     }
   }
   __syncthreads();
@@ -351,8 +367,7 @@ __global__ void k_lauum(int N, const double *__restrict__ X, double *__restrict_
   tri_decode(blockIdx.x, I, J);
   const double *Y = X + int64_t(blockIdx.y) * N * N;
   double *M = A + int64_t(blockIdx.y) * N * N;
-  double acc[(BS * BS) / 256];
-  for (int e = 0; e < (BS * BS) / 256; ++e) acc[e] = 0;
+  d4 acc = {0, 0, 0, 0};
   for (int K = I; K < NB; ++K) {
     __syncthreads();
     for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
@@ -361,20 +376,14 @@ __global__ void k_lauum(int N, const double *__restrict__ X, double *__restrict_
       Xb[i][j] = Y[int64_t(K * BS + i) * N + J * BS + j];
     }
     __syncthreads();
-    for (int e = 0; e < (BS * BS) / 256; ++e) {
-      const int t = threadIdx.x + e * 256;
-      const int i = t / BS, j = t % BS;
-      double s = 0;
-#pragma unroll 8
-      for (int m = 0; m < BS; ++m) s += Xa[m][i] * Xb[m][j];
-      acc[e] += s;
-    }
+    tile_mfma<true, false>(Xa, Xb, acc);  // X[K][I]^T X[K][J]
   }
-  for (int e = 0; e < (BS * BS) / 256; ++e) {
-    const int t = threadIdx.x + e * 256;
-    const int i = t / BS, j = t % BS;
-    M[int64_t(I * BS + i) * N + J * BS + j] = acc[e];
-    M[int64_t(J * BS + j) * N + I * BS + i] = acc[e];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 16 * (wave >> 1) + (lane >> 4) + 4 * v, j = 16 * (wave & 1) + (lane & 15);
+    M[int64_t(I * BS + i) * N + J * BS + j] = acc[v];
+    M[int64_t(J * BS + j) * N + I * BS + i] = acc[v];
   }
 }
 
