@@ -284,6 +284,7 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
   out.pa.chunk_patch = P.upload(chunk_patch, s);
   out.pa.chunk_rows = P.upload(chunk_rows, s);
   out.pa.max_size = maxsz;
+  out.pa.n_entries = tot;
   out.pa.patch_col = P.upload(ps.patch_col, s);
   out.pa.col_ent = P.upload(ps.col_ent, s);
   out.pa.inv_off = P.upload(off, s);

@@ -592,7 +592,15 @@ __global__ void k_axpy_m(int64_t n, const double *__restrict__ d, double *__rest
     x[c * ldx + i] += d[c * n + i];
 }
 
+// Streams of more than 192 MiB (three quarters of the 256 MiB last-level
+// cache) are read with non-temporal loads; smaller ones may stay cached
+// from one apply to the next (measured over the sweep's patch sets and
+// coarse inverses).
+constexpr int64_t kStreamBytes = int64_t(192) << 20;
+
 // Patch solves z += R_p^T A_p^{-1} R_p r for a chunk of rows of one patch
+// (NT: the rows are read with non-temporal loads, for sets too large to stay
+// in the last-level cache between applies)
 // and G right-hand sides (blockIdx.y), the inverse in the segmented layout
 // with V-element segments (16 bytes).  A wave works on 64 / L rows at a time,
 // L lanes per row; lane t owns the columns q V L + t V + [0, V) for q < NQ,
@@ -600,7 +608,7 @@ __global__ void k_axpy_m(int64_t n, const double *__restrict__ d, double *__rest
 // are summed over the L lanes (DPP); the mirrored column products stay in
 // registers until the end of the chunk.  Segments left of a row's first
 // stored segment or beyond the patch are not loaded.
-template <int V, int L, int NQ, int G, int D, typename T, int NW>
+template <int V, int L, int NQ, int G, int D, typename T, int NW, bool NT>
 __global__ __launch_bounds__(64 * NW) void k_patch_seg(const int64_t *__restrict__ chunk_patch,
                                                    const int32_t *__restrict__ chunk_rows,
                                                    const int64_t *__restrict__ patch_col,
@@ -641,7 +649,9 @@ __global__ __launch_bounds__(64 * NW) void k_patch_seg(const int64_t *__restrict
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int c = q * V * L + t * V;
-      if (ok && c >= si && c < mS) buf[q] = *reinterpret_cast<const vecV *>(row + c);
+      if (ok && c >= si && c < mS)
+        buf[q] = NT ? __builtin_nontemporal_load(reinterpret_cast<const vecV *>(row + c))
+                    : *reinterpret_cast<const vecV *>(row + c);
       else buf[q] = vecV(0);
     }
   };
@@ -759,7 +769,7 @@ __global__ void k_seg_to_low(const int64_t *__restrict__ patch_col, const int64_
 // of column c of the tile.  Row products A_IJ rW_J stay in registers for the
 // whole strip (one lane reduction at the end); column products A_IJ^T rW_I
 // are summed over the four waves in LDS and added to zW_J per tile.
-template <int G, typename T>
+template <int G, typename T, bool NTL>
 __global__ __launch_bounds__(256) void k_coarse_symv(int NT, int S, const T *__restrict__ tiles,
                                                      const double *__restrict__ rW, double *__restrict__ zW,
                                                      int npad, int ncol, const PcgState *st) {
@@ -791,7 +801,9 @@ __global__ __launch_bounds__(256) void k_coarse_symv(int NT, int S, const T *__r
   auto load = [&](int J, v2 *buf) {
     const T *tp = row + int64_t(J) * 4096;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) buf[q] = *reinterpret_cast<const v2 *>(tp + q * 128);
+    for (int q = 0; q < 8; ++q)
+      buf[q] = NTL ? __builtin_nontemporal_load(reinterpret_cast<const v2 *>(tp + q * 128))
+                   : *reinterpret_cast<const v2 *>(tp + q * 128);
   };
   v2 cur[8], nxt[8];
   load(J0, cur);
@@ -1424,20 +1436,31 @@ constexpr int patch_depth() {
   return VQ <= 8 ? 4 : 2;
 }
 
+template <int V, int L, int NQ, int G, typename T, int NW, bool NT>
+static void patch_seg_nt(const PatchApply &pa, const int64_t *off, const T *inv, dim3 grid, size_t lds,
+                         const double *r, int64_t ldr, double *z, int64_t ldz, int ncol, double scale,
+                         const PcgState *st, hipStream_t s) {
+  constexpr int D = patch_depth<NQ * V, T>();
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_patch_seg<V, L, NQ, G, D, T, NW, NT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_patch_seg<V, L, NQ, G, D, T, NW, NT>), grid, dim3(64 * NW), lds, s, pa.chunk_patch,
+                     pa.chunk_rows, pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, off, inv, r, ldr, z, ldz,
+                     ncol, scale, st);
+}
+
+
 template <int V, int L, int NQ, int G, typename T, int NW>
 static void patch_seg_g(const PatchApply &pa, const int64_t *off, const T *inv, dim3 grid, size_t lds,
                         const double *r, int64_t ldr, double *z, int64_t ldz, int ncol, double scale,
                         const PcgState *st, hipStream_t s) {
-  constexpr int D = patch_depth<NQ * V, T>();
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_patch_seg<V, L, NQ, G, D, T, NW>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr = true;
-  }
-  hipLaunchKernelGGL((k_patch_seg<V, L, NQ, G, D, T, NW>), grid, dim3(64 * NW), lds, s, pa.chunk_patch,
-                     pa.chunk_rows, pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, off, inv, r, ldr, z, ldz,
-                     ncol, scale, st);
+  if (pa.n_entries * int64_t(sizeof(T)) > kStreamBytes)
+    patch_seg_nt<V, L, NQ, G, T, NW, true>(pa, off, inv, grid, lds, r, ldr, z, ldz, ncol, scale, st, s);
+  else
+    patch_seg_nt<V, L, NQ, G, T, NW, false>(pa, off, inv, grid, lds, r, ldr, z, ldz, ncol, scale, st, s);
 }
 
 template <int V, int L, int NQ, typename T, int NW>
@@ -1534,9 +1557,18 @@ void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hi
   const int S = int(std::max<int64_t>(1, std::min<int64_t>(16, int64_t(nt) / 2048)));
   const int G = ncol >= 2 ? 2 : 1;
   const dim3 g(unsigned(ca.NT), unsigned((ca.NT + S - 1) / S), unsigned((ncol + G - 1) / G));
-#define RZ_CT(GG, TT, TI) \
-  hipLaunchKernelGGL((k_coarse_symv<GG, TT>), g, dim3(256), 0, s, ca.NT, S, TI, ca.rW, ca.zW, npad, ncol, st)
-  if (lo && ca.tiles32) {
+  const bool f32 = lo && ca.tiles32;
+  const bool nts = int64_t(nt) * 4096 * (f32 ? 4 : 8) > kStreamBytes;
+#define RZ_CT(GG, TT, TI)                                                                                        \
+  do {                                                                                                           \
+    if (nts)                                                                                                     \
+      hipLaunchKernelGGL((k_coarse_symv<GG, TT, true>), g, dim3(256), 0, s, ca.NT, S, TI, ca.rW, ca.zW, npad, ncol, \
+                         st);                                                                                    \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_coarse_symv<GG, TT, false>), g, dim3(256), 0, s, ca.NT, S, TI, ca.rW, ca.zW, npad,  \
+                         ncol, st);                                                                              \
+  } while (0)
+  if (f32) {
     if (G == 2) RZ_CT(2, float, ca.tiles32);
     else RZ_CT(1, float, ca.tiles32);
   } else {

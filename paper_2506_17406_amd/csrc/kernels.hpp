@@ -86,6 +86,7 @@ void launch_seg_to_bf16(int64_t n_patches, const int64_t *patch_col, const int64
 
 struct PatchApply {
   int64_t n_patches, n_chunks;
+  int64_t n_entries;        // stored entries of the set (FP64 copy)
   int max_size;
   const int64_t *chunk_patch;  // patch of each work chunk
   const int32_t *chunk_rows;   // [r0, r1) row range of each chunk
