@@ -69,6 +69,12 @@ struct rz_problem {
   std::vector<void *> mem;
   double *R = nullptr, *Afrag = nullptr, *w = nullptr, *dinv = nullptr;
   int32_t *cell_dofs = nullptr;
+  // local order of the operator apply: the Whitney dofs of the k-entities,
+  // the other interface dofs, the interior dofs (apply position -> element
+  // index); the apply's cell->dof map and reference fragments follow it
+  std::vector<int> perm;
+  int n_whitney = 0;
+  int32_t *cell_dofs_apply = nullptr;
   rz::ApplyATables at{};
   std::vector<DevPatchSet> dps;
   rz::CoarseApply ca{};
@@ -368,7 +374,19 @@ void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
   P.patches = rz::build_patches(P.top, P.el);
   P.off_I = P.top.offset[P.d];
   const int n = P.el.n, Q = P.el.Q, d = P.d;
-  // reference tables: plain and in MFMA fragment order
+  // the apply's local order: Whitney dofs of the k-entities first, so the
+  // hybrid's coarse correction (nonzero only there) is applied with a
+  // column range of one or two k-blocks; interior dofs stay last
+  P.perm.clear();
+  for (int i = 0; i < n; ++i)
+    if (P.el.dofs[i].entity_dim == P.el.k && P.el.dofs[i].kind == rz::KIND_W) P.perm.push_back(i);
+  P.n_whitney = int(P.perm.size());
+  for (int i = 0; i < n; ++i)
+    if (P.el.dofs[i].entity_dim != d && !(P.el.dofs[i].entity_dim == P.el.k && P.el.dofs[i].kind == rz::KIND_W))
+      P.perm.push_back(i);
+  for (int i = 0; i < n; ++i)
+    if (P.el.dofs[i].entity_dim == d) P.perm.push_back(i);
+  // reference tables: plain (element order) and in MFMA fragment order (apply order)
   P.R = P.upload(P.el.R, s);
   const int NP = round_up(n, 16), KP = round_up(n, 4), KB = KP / 4, NMB = NP / 16;
   std::vector<double> frag(size_t(NMB) * Q * KB * 64, 0.0);
@@ -378,10 +396,15 @@ void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
         for (int lane = 0; lane < 64; ++lane) {
           const int row = mb * 16 + (lane & 15), col = kb * 4 + (lane >> 4);
           if (row < n && col < n)
-            frag[((size_t(mb) * KB + kb) * Q + q) * 64 + lane] = P.el.R[(size_t(q) * n + row) * n + col];
+            frag[((size_t(mb) * KB + kb) * Q + q) * 64 + lane] =
+                P.el.R[(size_t(q) * n + P.perm[row]) * n + P.perm[col]];
         }
   P.Afrag = P.upload(frag, s);
   P.cell_dofs = P.upload(P.top.cell_dofs, s);
+  std::vector<int32_t> cda(P.top.cell_dofs.size());
+  for (int64_t c = 0; c < int64_t(P.top.n_cells); ++c)
+    for (int j = 0; j < n; ++j) cda[c * n + j] = P.top.cell_dofs[c * n + P.perm[j]];
+  P.cell_dofs_apply = P.upload(cda, s);
   P.w = P.dev<double>(size_t(P.top.n_cells) * Q);
 }
 
@@ -458,7 +481,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     P->at.KP = round_up(n, 4);
     P->at.Afrag = P->Afrag;
     P->at.w = P->w;
-    P->at.cell_dofs = P->cell_dofs;
+    P->at.cell_dofs = P->cell_dofs_apply;
     P->at.n_cells = nc;
     // assembly lists of the three-stage apply: for every dof, the positions
     // of its (cell, local row) results in Yc, cells ascending
@@ -467,13 +490,15 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
       const int64_t nd = P->top.n_dofs;
       if (int64_t(P->at.NP) * ncp >= (int64_t(1) << 31))
         throw RzError{RZ_ERR_UNSUPPORTED, "mesh too large for 32-bit cell-local indices"};
+      // (cell, row r of the apply order) holds dof cell_dofs[cell][perm[r]]
+      const std::vector<int> &pm = P->perm;
       std::vector<int64_t> ptr(nd + 1, 0);
       for (int64_t e = 0; e < nc * n; ++e) ++ptr[P->top.cell_dofs[e] + 1];
       for (int64_t i = 0; i < nd; ++i) ptr[i + 1] += ptr[i];
       std::vector<int32_t> ent(size_t(nc) * n);
       std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
       for (int64_t c = 0; c < nc; ++c)
-        for (int r = 0; r < n; ++r) ent[fill[P->top.cell_dofs[c * n + r]]++] = int32_t(rz::yc_index(ncp, c, r));
+        for (int r = 0; r < n; ++r) ent[fill[P->top.cell_dofs[c * n + pm[r]]]++] = int32_t(rz::yc_index(ncp, c, r));
       P->at.ncp = ncp;
       P->at.n_dofs = nd;
       P->at.asm_ptr = P->upload(ptr, s);
@@ -526,19 +551,18 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     P->fold.off = P->top.offset[P->k];
     P->fold.N = P->el.per_entity[P->k];
     P->fold.span = P->top.n_ent[P->k] * P->fold.N;
-    // local column ranges of the hybrid sweep's restricted applies (the
-    // element numbering is entity-major, so each range is contiguous)
+    // local column ranges (apply order) of the hybrid sweep's restricted
+    // applies: the Whitney dofs [0, n_whitney), the interface [0, col_int),
+    // the interior [col_int, n)
     {
-      int w0 = n, w1 = 0;
-      for (int i = 0; i < n; ++i)
-        if (P->el.dofs[i].entity_dim == P->k) w0 = std::min(w0, i), w1 = std::max(w1, i + 1);
       P->col_int = n - int(loc_int.size());
-      P->col_w0 = w0 < w1 ? w0 : 0;
-      P->col_w1 = w0 < w1 ? w1 : 0;
+      P->col_w0 = 0;
+      P->col_w1 = P->n_whitney;
       for (int i = 0; i < n; ++i) {
-        const bool in_int = P->el.dofs[i].entity_dim == d, in_w = i >= P->col_w0 && i < P->col_w1;
-        if (in_int != (i >= P->col_int) || in_w != (P->el.dofs[i].entity_dim == P->k))
-          throw RzError{RZ_ERR_UNSUPPORTED, "element numbering is not entity-major"};
+        const rz::LocalDof &ld = P->el.dofs[P->perm[i]];
+        const bool in_int = ld.entity_dim == d, in_w = i < P->col_w1;
+        if (in_int != (i >= P->col_int) || in_w != (ld.entity_dim == P->k && ld.kind == rz::KIND_W))
+          throw RzError{RZ_ERR_UNSUPPORTED, "unexpected local dof order"};
       }
     }
     HIPCHK(hipStreamSynchronize(s));
