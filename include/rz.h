@@ -73,11 +73,14 @@ typedef struct {
 /* Arithmetic of rz_solve.  RZ_FP64: PCG entirely in FP64.  RZ_FP32_PC: PCG
  * with the FP64 operator and vectors; the preconditioner reads FP32 copies
  * of the patch and coarse inverses (accumulating in FP64), so it is a fixed
- * symmetric operator and no refinement is needed.  RZ_BF16_PC: the same
- * with bfloat16 copies of the patch inverses (rounded to nearest through
- * FP32; a quarter of the FP64 bytes; each patch product accumulates in
- * FP32, far below the 2^-9 rounding of the entries) and the FP32 coarse
- * copy; it may cost a few more iterations.  RZ_FP32_IR:
+ * symmetric operator and no refinement is needed.  RZ_BF16_PC: FP64 PCG
+ * (FP64 operator, vectors and inner products) whose preconditioner reads
+ * bfloat16 copies of the patch inverses (rounded to nearest through FP32; a
+ * quarter of the FP64 bytes; each patch product accumulates in FP32, far
+ * below the 2^-9 rounding of the entries), the FP32 coarse copy, and applies
+ * the FP32 operator copies inside the hybrid sweep; the preconditioner is
+ * then SPD only up to FP32 rounding, which may cost a few iterations.
+ * RZ_FP32_IR:
  * iterative refinement -- the residual b - A x and the update x += d are
  * FP64; each correction d solves A d = r by PCG to inner_rtol whose operator
  * and preconditioner applies read FP32 copies of the reference tables,
@@ -130,8 +133,8 @@ typedef struct rz_problem rz_problem;
 
 /* Builds the reference element (Sec. 3-4) on the host, the numbering and the
  * patches (Sec. 6), uploads them, and assembles and factors the patch and
- * coarse matrices on the device in FP64 (plus their FP32 copies when
- * opts->precision is RZ_FP32_IR).  opts may be NULL (alpha = beta = 1, FP64).
+ * coarse matrices on the device in FP64 (plus the reduced-precision copies
+ * that opts->precision reads).  opts may be NULL (alpha = beta = 1, FP64).
  * On success *out receives a new handle. */
 int rz_setup(const rz_mesh *mesh, int32_t degree, rz_space space, const rz_options *opts,
              void *hip_stream, rz_problem **out);
@@ -152,16 +155,16 @@ int rz_apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t
 int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream);
 
 /* The FP32-copy applies, with the rz_apply_A / rz_apply_P argument
- * conventions (FP64 vectors in and out).  rz_apply_A_fp32 (RZ_FP32_IR
- * handles): the reference tables, weights and x are rounded to FP32 and
+ * conventions (FP64 vectors in and out).  rz_apply_A_fp32 (RZ_FP32_IR and
+ * RZ_BF16_PC handles): the reference tables, weights and x are rounded to FP32 and
  * contracted by FP32 MFMA (FP32 accumulation per cell); the cell results
  * are summed into each dof in FP64 in a fixed order.
  * rz_apply_P_fp32 (RZ_FP32_IR, RZ_FP32_PC and RZ_BF16_PC handles): the
  * preconditioner of rz_solve's iteration -- the reduced-precision patch
  * (FP32, or bfloat16 under RZ_BF16_PC) and FP32 coarse inverses with FP64
- * accumulation (FP32 within a bfloat16 patch), and under RZ_FP32_IR also
- * the FP32 operator inside the hybrid sweep.  RZ_ERR_ARG for a handle
- * without the copies. */
+ * accumulation (FP32 within a bfloat16 patch), and under RZ_FP32_IR and
+ * RZ_BF16_PC also the FP32 operator inside the hybrid sweep.  RZ_ERR_ARG for
+ * a handle without the copies. */
 int rz_apply_A_fp32(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream);
 int rz_apply_P_fp32(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream);
 

@@ -515,7 +515,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
         rz::launch_to_float(count, a, b, s);
         return static_cast<const float *>(b);
       };
-      if (P->precision == RZ_FP32_IR) {
+      if (P->precision == RZ_FP32_IR || P->precision == RZ_BF16_PC) {
         P->at.Afrag32 = lo(P->Afrag, int64_t(P->at.NP) * P->at.KP * Q);
         P->at.w32 = lo(P->w, nc * Q);
       }
@@ -654,7 +654,15 @@ static void ensure_ws(rz_problem *P, int ncol) {
 }
 
 // which pieces read the FP32 copies: the operator, the patch/coarse inverses
-constexpr unsigned kLoA = 1, kLoP = 2;
+// reduced-precision pieces: kLoA the operator (everywhere: refinement's
+// inner solves), kLoP the patch/coarse inverses, kLoH the operator inside
+// the hybrid sweep only (the PCG operator stays FP64)
+constexpr unsigned kLoA = 1, kLoP = 2, kLoH = 4;
+// the pieces of plain (not refined) PCG that read reduced-precision copies
+static unsigned pc_lo(const rz_problem *P) {
+  if (P->precision == RZ_FP64) return 0u;
+  return kLoP | (P->precision == RZ_BF16_PC ? kLoH : 0u);
+}
 
 // Symmetric multiplicative hybrid (Sec. 7.1): groups X_I (point-Jacobi),
 // X_Gamma (additive interface patches) and W (exact coarse solve), swept
@@ -665,7 +673,7 @@ constexpr unsigned kLoA = 1, kLoP = 2;
 // also takes the PCG convergence test (partR: block partials of ||r||^2).
 static void hybrid_apply(rz_problem *P, const double *r, int64_t ldr, double *z, int64_t ldz, int nc,
                          rz::PcgState *st, const double *partR, int RB, unsigned lo, hipStream_t s) {
-  const bool loA = lo & kLoA, loP = lo & kLoP;
+  const bool loA = lo & (kLoA | kLoH), loP = lo & kLoP;
   const int64_t nd = P->top.n_dofs;
   const int n = P->el.n;
   const double w1 = 1.0 / P->rho_I, w2 = 1.0 / P->rho_G;
@@ -780,7 +788,8 @@ static int apply_A(rz_problem *P, const double *x, double *y, int32_t n_rhs, int
                    bool lo) {
   if (!P || !x || !y) return fail(RZ_ERR_ARG, "null argument");
   if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
-  if (lo && !P->at.Afrag32) return fail(RZ_ERR_ARG, "FP32 operator copies exist only for RZ_FP32_IR handles");
+  if (lo && !P->at.Afrag32)
+    return fail(RZ_ERR_ARG, "FP32 operator copies exist only for RZ_FP32_IR and RZ_BF16_PC handles");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   try {
     ensure_ws(P, n_rhs);
@@ -808,7 +817,7 @@ static int apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int
   }
   // the FP32 preconditioner of the handle's precision: inverses, plus the
   // operator inside the hybrid sweep under refinement
-  const unsigned m = lo ? (kLoP | (P->at.Afrag32 ? kLoA : 0u)) : 0u;
+  const unsigned m = lo ? (kLoP | (P->at.Afrag32 ? kLoH : 0u)) : 0u;
   if (P->pc == RZ_PC_HYBRID)
     hybrid_apply(P, r, ld, z, ld, n_rhs, nullptr, nullptr, 0, m, s);
   else
@@ -1075,7 +1084,7 @@ int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t l
     auto t0 = std::chrono::steady_clock::now();
     if (P->precision != RZ_FP32_IR) {
       // FP64 operator; FP32 inverses in the preconditioner for RZ_FP32_PC
-      pcg_run(P, b, ld, x, ld, nc, rtol, P->precision == RZ_FP64 ? 0u : kLoP, false, nullptr, s);
+      pcg_run(P, b, ld, x, ld, nc, rtol, pc_lo(P), false, nullptr, s);
       for (int c = 0; c < nc; ++c) column_info(P->st_host[c], its[c], cond[c], rel[c], code[c]);
     } else {
       refine(P, b, x, ld, nc, rtol, its, outer, cond, rel, code, s);
@@ -1283,7 +1292,7 @@ int rz_batch_solve(rz_batch *B, const double *const *b, double *const *x, double
         if (code != RZ_OK && worst == RZ_OK) worst = code;
         continue;
       }
-      lo[i] = P->precision == RZ_FP64 ? 0u : kLoP;
+      lo[i] = pc_lo(P);
       pcg_begin(P, b[i], P->top.n_dofs, x[i], P->top.n_dofs, 1, rtol, lo[i], false, nullptr, s);
       HIPCHK(hipGetLastError());
       active.push_back(i);

@@ -15,7 +15,8 @@ Bars (written per check):
 * FP32-preconditioner solve -- the same residual and solution bars, and
   at most two iterations more than the oracle's FP64 hybrid PCG;
 * BF16-preconditioner solve (RZ_BF16_PC: bfloat16 patch inverses with FP32
-  arithmetic inside a patch, FP32 coarse inverse) -- apply_P within 1e-2
+  arithmetic inside a patch, FP32 coarse inverse, FP32 operator inside the
+  hybrid sweep) -- apply_P within 1e-2
   max |z| of the oracle (patch entries rounded once to bfloat16, unit
   roundoff 2^-9; a CPU emulation that rounds the oracle's inverses the same
   way stays below 1.3e-3 on these cases) and, for p > 1, at least 1e-5 away
