@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -1297,9 +1298,12 @@ int rz_batch_solve(rz_batch *B, const double *const *b, double *const *x, double
       HIPCHK(hipGetLastError());
       active.push_back(i);
     }
+    // each problem runs chunk after chunk on its own stream; the next chunk
+    // of a problem is launched as soon as its previous one (and the copy of
+    // its convergence state) has completed, without waiting for the others
     std::vector<int> rounds(n, 0);
-    while (!active.empty()) {
-      for (int i : active) {
+    auto launch_chunk = [&](int i) {
+      {
         rz_problem *P = B->P[i];
         hipStream_t s = B->streams[i];
         if (rounds[i] == 0) {
@@ -1325,12 +1329,26 @@ int rz_batch_solve(rz_batch *B, const double *const *b, double *const *x, double
         pcg_read_head(P, 1, s);
         ++rounds[i];
       }
+    };
+    for (int i : active) launch_chunk(i);
+    while (!active.empty()) {
       std::vector<int> next;
+      bool progress = false;
       for (int i : active) {
-        HIPCHK(hipStreamSynchronize(B->streams[i]));
-        if (!B->P[i]->st_host[0].done && rounds[i] * kPcgChunk < B->P[i]->max_iter) next.push_back(i);
+        const hipError_t q = hipStreamQuery(B->streams[i]);
+        if (q == hipErrorNotReady) {
+          next.push_back(i);
+          continue;
+        }
+        if (q != hipSuccess) throw RzError{RZ_ERR_DEVICE, hipGetErrorString(q)};
+        progress = true;
+        if (!B->P[i]->st_host[0].done && rounds[i] * kPcgChunk < B->P[i]->max_iter) {
+          launch_chunk(i);
+          next.push_back(i);
+        }
       }
       active.swap(next);
+      if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(10));
     }
     auto t1 = std::chrono::steady_clock::now();
     for (int i = 0; i < n; ++i) {
