@@ -51,7 +51,7 @@ class RzError(RuntimeError):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (python -m paper_2506_17406_amd.build)")
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
