@@ -139,9 +139,145 @@ inline Dense null_space(const Dense &C) {
   return columns(f.Q, f.rank, f.Q.r);
 }
 
-// Cyclic Jacobi method for a symmetric matrix: eigenvalues ascending, and
-// the corresponding orthonormal eigenvectors as columns of V.
+// Symmetric eigenproblem: eigenvalues ascending, and the corresponding
+// orthonormal eigenvectors as columns of V.  Householder reduction to
+// tridiagonal form (the reflections accumulated), then the implicit QL
+// iteration with Wilkinson shifts on the tridiagonal matrix, the plane
+// rotations applied to the accumulated basis.
 inline void sym_eig(Dense A, std::vector<double> &w, Dense &V) {
+  const int n = A.r;
+  w.assign(n, 0.0);
+  if (n == 0) {
+    V = Dense(0, 0);
+    return;
+  }
+  std::vector<double> d(n), e(n, 0.0);
+  // Householder: for i = n-1 .. 1 annihilate A(i, 0 .. i-2)
+  std::vector<std::vector<double>> hv;  // reflection vectors u_i (length i), scaled
+  std::vector<double> hh;               // their H = u^T u / 2
+  for (int i = n - 1; i >= 1; --i) {
+    const int l = i - 1;
+    double scale = 0.0, h = 0.0;
+    for (int k = 0; k <= l; ++k) scale += std::fabs(A(i, k));
+    std::vector<double> u(i, 0.0);
+    if (l == 0 || scale == 0.0) {
+      e[i] = A(i, l);
+      hv.push_back(u);
+      hh.push_back(0.0);
+      continue;
+    }
+    for (int k = 0; k <= l; ++k) {
+      u[k] = A(i, k) / scale;
+      h += u[k] * u[k];
+    }
+    const double f = u[l];
+    const double g = f >= 0 ? -std::sqrt(h) : std::sqrt(h);
+    e[i] = scale * g;
+    h -= f * g;
+    u[l] = f - g;
+    // p = A u / h; K = u^T p / 2h; q = p - K u; A -= u q^T + q u^T (leading i x i block)
+    std::vector<double> pvec(i, 0.0);
+    for (int j = 0; j <= l; ++j) {
+      double sacc = 0.0;
+      const double *aj = &A.a[size_t(j) * n];
+      for (int k = 0; k <= l; ++k) sacc += aj[k] * u[k];
+      pvec[j] = sacc / h;
+    }
+    double K = 0.0;
+    for (int j = 0; j <= l; ++j) K += u[j] * pvec[j];
+    K /= (h + h);
+    for (int j = 0; j <= l; ++j) pvec[j] -= K * u[j];
+    for (int j = 0; j <= l; ++j) {
+      double *aj = &A.a[size_t(j) * n];
+      const double uj = u[j], qj = pvec[j];
+      for (int k = 0; k <= l; ++k) aj[k] -= uj * pvec[k] + qj * u[k];
+    }
+    hv.push_back(u);
+    hh.push_back(h);
+  }
+  for (int i = 0; i < n; ++i) d[i] = A(i, i);
+  // accumulate Q = H_{n-1} ... H_1 applied to the identity (rows of Z)
+  Dense Z = Dense::eye(n);
+  for (int idx = int(hv.size()) - 1; idx >= 0; --idx) {
+    const int i = n - 1 - idx;  // reflection acting on coordinates 0 .. i-1
+    const double h = hh[idx];
+    if (h == 0.0) continue;
+    const std::vector<double> &u = hv[idx];
+    // Z_rows: for every row r of Z (an eigenbasis vector), z[0..i-1] -= (u . z) u / h
+    for (int r = 0; r < n; ++r) {
+      double *zr = &Z.a[size_t(r) * n];
+      double sacc = 0.0;
+      for (int k = 0; k < i; ++k) sacc += u[k] * zr[k];
+      if (sacc == 0.0) continue;
+      sacc /= h;
+      for (int k = 0; k < i; ++k) zr[k] -= sacc * u[k];
+    }
+  }
+  // row r of Z now holds column r of Q = H_{n-1} ... H_1: the basis in which
+  // the matrix is tridiagonal, one vector per row
+  Dense &Qt = Z;
+  // implicit QL on (d, e): e[i] couples i-1 and i; shift to e[i-1] convention
+  for (int i = 1; i < n; ++i) e[i - 1] = e[i];
+  e[n - 1] = 0.0;
+  for (int l = 0; l < n; ++l) {
+    int iter = 0;
+    for (;;) {
+      int m = l;
+      for (; m < n - 1; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= 1e-17 * dd) break;
+      }
+      if (m == l) break;
+      if (++iter > 60) throw std::runtime_error("symmetric eigensolver did not converge");
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? std::fabs(r) : -std::fabs(r)));
+      double s = 1.0, c = 1.0, p = 0.0;
+      int i = m - 1;
+      for (; i >= l; --i) {
+        double f = s * e[i];
+        const double b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {
+          d[i + 1] -= p;
+          e[m] = 0.0;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+        // rotate basis vectors i and i+1 (rows of Qt)
+        double *qa = &Qt.a[size_t(i) * n], *qb = &Qt.a[size_t(i + 1) * n];
+        for (int k = 0; k < n; ++k) {
+          f = qb[k];
+          qb[k] = s * qa[k] + c * f;
+          qa[k] = c * qa[k] - s * f;
+        }
+      }
+      if (r == 0.0 && i >= l) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return d[a] < d[b]; });
+  V = Dense(n, n);
+  for (int j = 0; j < n; ++j) {
+    w[j] = d[order[j]];
+    const double *q = &Qt.a[size_t(order[j]) * n];
+    for (int i = 0; i < n; ++i) V(i, j) = q[i];
+  }
+}
+
+// Cyclic Jacobi method (the earlier solver, kept as a cross-check).
+inline void sym_eig_jacobi(Dense A, std::vector<double> &w, Dense &V) {
   const int n = A.r;
   V = Dense::eye(n);
   double fro = 0;

@@ -28,16 +28,34 @@
 //    affine cell's matrix (Sec. 2, eq:pullback-3d-def).
 #include "refelem.hpp"
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
+#include <thread>
 
 namespace rz {
 
 namespace {
+
+// runs f(0 .. count-1) on up to 16 host threads (independent work items)
+template <typename F>
+void parallel_for(int count, F f) {
+  const int nt = std::max(1, std::min({count, 16, int(std::thread::hardware_concurrency())}));
+  if (nt <= 1) {
+    for (int i = 0; i < count; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int w = 0; w < nt; ++w)
+    th.emplace_back([&, w]() {
+      for (int i = w; i < count; i += nt) f(i);
+    });
+  for (auto &t : th) t.join();
+}
 
 constexpr double kClusterTol = 1e-7;
 
@@ -350,19 +368,23 @@ struct Space {
     poly.eval(x, npts, V.data(), l > 0 ? G.data() : nullptr);
     vals.assign(size_t(npts) * c * m, 0.0);
     jac.assign(size_t(npts) * c * std::max(l, 1) * m, 0.0);
-    for (int t = 0; t < npts; ++t)
-      for (int comp = 0; comp < c; ++comp)
-        for (int b = 0; b < n; ++b) {
-          const double *crow = &coef.a[size_t(comp * n + b) * m];
-          const double vb = V[size_t(t) * n + b];
-          double *vo = &vals[(size_t(t) * c + comp) * m];
-          for (int j = 0; j < m; ++j) vo[j] += vb * crow[j];
-          for (int a = 0; a < l; ++a) {
-            const double gb = G[(size_t(t) * l + a) * n + b];
-            double *jo = &jac[((size_t(t) * c + comp) * l + a) * m];
-            for (int j = 0; j < m; ++j) jo[j] += gb * crow[j];
+    // points in chunks of 16 on host threads (each point's values are its own)
+    const int nch = (npts + 15) / 16;
+    parallel_for(nch, [&](int ch) {
+      for (int t = ch * 16; t < std::min(npts, ch * 16 + 16); ++t)
+        for (int comp = 0; comp < c; ++comp)
+          for (int b = 0; b < n; ++b) {
+            const double *crow = &coef.a[size_t(comp * n + b) * m];
+            const double vb = V[size_t(t) * n + b];
+            double *vo = &vals[(size_t(t) * c + comp) * m];
+            for (int j = 0; j < m; ++j) vo[j] += vb * crow[j];
+            for (int a = 0; a < l; ++a) {
+              const double gb = G[(size_t(t) * l + a) * n + b];
+              double *jo = &jac[((size_t(t) * c + comp) * l + a) * m];
+              for (int j = 0; j < m; ++j) jo[j] += gb * crow[j];
+            }
           }
-        }
+    });
   }
 };
 
@@ -880,36 +902,43 @@ RefElement build_reference(int d, Family fam, int p) {
   std::vector<std::pair<int, int>> pairs;
   if (d == 3) pairs = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
   else pairs = {{0, 0}, {1, 1}, {0, 1}};
-  std::vector<Dense> stack;
-  auto family_mats = [&](const std::vector<double> &F, int cf) {
-    auto prod = [&](int a, int b) {
-      Dense R(n, n);
-      for (int t = 0; t < nq; ++t) {
-        const double *fa = &F[(size_t(t) * cf + a) * n];
-        const double *fb = &F[(size_t(t) * cf + b) * n];
-        for (int i = 0; i < n; ++i) {
-          const double wi = q.w[t] * fa[i];
-          double *rr = &R.a[size_t(i) * n];
-          for (int j = 0; j < n; ++j) rr[j] += wi * fb[j];
+  // R_ab = sum_t w_t F_a(t) F_b(t)^T, in 64 x 64 tiles of R (each entry
+  // still sums over t in ascending order); the products run on threads
+  auto prod = [&](const std::vector<double> &F, int cf, int a, int b) {
+    Dense R(n, n);
+    constexpr int TB = 64;
+    for (int i0 = 0; i0 < n; i0 += TB)
+      for (int j0 = 0; j0 < n; j0 += TB) {
+        const int i1 = std::min(n, i0 + TB), j1 = std::min(n, j0 + TB);
+        for (int t = 0; t < nq; ++t) {
+          const double *fa = &F[(size_t(t) * cf + a) * n];
+          const double *fb = &F[(size_t(t) * cf + b) * n];
+          for (int i = i0; i < i1; ++i) {
+            const double wi = q.w[t] * fa[i];
+            double *rr = &R.a[size_t(i) * n];
+            for (int j = j0; j < j1; ++j) rr[j] += wi * fb[j];
+          }
         }
       }
-      return R;
-    };
-    if (cf == 1) {
-      stack.push_back(prod(0, 0));
-    } else {
-      for (auto &pr : pairs) {
-        Dense R = prod(pr.first, pr.second);
-        if (pr.first != pr.second) {
-          Dense Rt = transpose(R);
-          for (size_t i = 0; i < R.a.size(); ++i) R.a[i] += Rt.a[i];
-        }
-        stack.push_back(R);
-      }
+    if (a != b) {
+      Dense Rt = transpose(R);
+      for (size_t i = 0; i < R.a.size(); ++i) R.a[i] += Rt.a[i];
     }
+    return R;
   };
-  family_mats(vals, c);
-  family_mats(dv, cd);
+  struct Job {
+    const std::vector<double> *F;
+    int cf, a, b;
+  };
+  std::vector<Job> jobs;
+  for (const auto *F : {&vals, &dv}) {
+    const int cf = F == &vals ? c : cd;
+    if (cf == 1) jobs.push_back({F, cf, 0, 0});
+    else
+      for (auto &pr : pairs) jobs.push_back({F, cf, pr.first, pr.second});
+  }
+  std::vector<Dense> stack(jobs.size());
+  parallel_for(int(jobs.size()), [&](int i) { stack[i] = prod(*jobs[i].F, jobs[i].cf, jobs[i].a, jobs[i].b); });
   el.Q = int(stack.size());
   el.R.resize(size_t(el.Q) * n * n);
   for (int qi = 0; qi < el.Q; ++qi)
