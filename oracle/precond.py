@@ -20,11 +20,23 @@ Additive form (AdditiveSchwarz):
   an exact solve with the principal submatrix A[W, W] in place of the
   paper's geometric multigrid V-cycle.
 
+The vertex-star comparators of Sec. 6.1 (decomposition="vertex" and
+"vertex-full"), for every space:
+  - "vertex": PAFW(0)(X^k_Gamma) + J(X^k_I) (eq:approx-sc-pafw): a patch per
+    vertex holding the dofs of the vertex, edges and faces containing it;
+    the same Jacobi and coarse parts as above;
+  - "vertex-full": PAFW(0)(X^k) (eq:pafw): the vertex-star patches also hold
+    the interior dofs of the cells containing the vertex, and there is no
+    Jacobi part (the interior group is empty).
+  For H(grad) "vertex" is the default decomposition.
+
 Hybrid form (HybridSchwarz, Sec. 7.1, eq:generic-subspace-splitting-mult):
 the three groups X_1 = X^k_I (point-Jacobi), X_2 = X^k_Gamma (the additive
 interface patch solver above, coarse space excluded) and X_3 = W^k (exact)
 are applied multiplicatively in the order X_1, X_2, X_3, X_2, X_1, each
-correction z += rho_m^{-1} B_m (r - A z).  The weight of a group is
+correction z += rho_m^{-1} B_m (r - A z).  Under "vertex-full" X_1 is empty
+and X_2 (the full vertex stars) spans every dof, so the sweep is X_2, X_3,
+X_2.  The weight of a group is
 rho_m = (lambda_min + 3 lambda_max) / 4 from the extreme Ritz values of 10
 CG steps on A restricted to X_m, preconditioned by B_m, with a random
 right-hand side.  Reading R17: the right-hand side is 2u - 1 per subspace
@@ -89,6 +101,34 @@ def patch_lists(top, family):
     return out
 
 
+def vertex_star_lists(top, full):
+    """PAFW(0) patches (eq:pafw, eq:approx-sc-pafw): per vertex, the global
+    dofs (ascending) of the entities that contain it -- the vertex, its edges
+    and faces -- and, for the full star X^k|star V, also its cells.  A space
+    with no dofs on some entity dimension simply contributes none there."""
+    d = top.d
+    edges_of, faces_of = top.vertex_star()
+    cells_of = [[] for _ in range(top.n_vertices)]
+    for c, t in enumerate(top.cells):
+        for v in t:
+            cells_of[v].append(c)
+    out = []
+    for v in range(top.n_vertices):
+        idx = list(top.entity_dofs(0, v))
+        for e in edges_of[v]:
+            idx += top.entity_dofs(1, e)
+        for f in faces_of[v]:
+            idx += top.entity_dofs(2, f)
+        if full:
+            for c in cells_of[v]:
+                idx += top.entity_dofs(d, c)
+        out.append(np.array(sorted(idx), dtype=np.int64))
+    return out
+
+
+DECOMPOSITIONS = ("paper", "vertex", "vertex-full")
+
+
 def potential_patches(top, cg_N):
     """H(curl) vertex potentials: sparse G_V (n_dofs x n_V) per vertex.
     cg_N = dofs per entity of the CG_p potential space (vertex, edge, face).
@@ -120,20 +160,28 @@ def potential_patches(top, cg_N):
 
 
 class AdditiveSchwarz:
-    def __init__(self, A, top, family):
+    def __init__(self, A, top, family, decomposition="paper"):
+        if decomposition not in DECOMPOSITIONS:
+            raise ValueError(decomposition)
         self.A = A
         self.top = top
         self.family = family
+        self.decomposition = decomposition
         k = {"CG": 0, "Ned": 1, "RT": 2}[family]
         diag = A.diagonal()
-        self.I = interior_dofs(top)
+        full = decomposition == "vertex-full"
+        self.I = np.zeros(0, dtype=np.int64) if full else interior_dofs(top)
         self.dI = diag[self.I]
         self.patches = []       # (index array, cho factor)
-        for idx in patch_lists(top, family):
+        if decomposition == "paper":
+            lists = patch_lists(top, family)
+        else:
+            lists = vertex_star_lists(top, full)
+        for idx in lists:
             Ap = A[idx][:, idx].toarray()
             self.patches.append((idx, sla.cho_factor(Ap, lower=True)))
         self.potentials = []    # (G_V, cho factor)
-        if family == "Ned":
+        if family == "Ned" and decomposition == "paper":
             p = top.el.p
             cg_N = (1, p - 1, (p - 1) * (p - 2) // 2)
             for G in potential_patches(top, cg_N):
@@ -191,9 +239,9 @@ class HybridSchwarz:
     interior-interface split (Sec. 7.1): z = 0, then for m in 1, 2, 3, 2, 1:
     z += rho_m^{-1} B_m (r - A z)."""
 
-    def __init__(self, A, top, family, additive=None):
+    def __init__(self, A, top, family, additive=None, decomposition="paper"):
         self.A = A
-        self.add = additive if additive is not None else AdditiveSchwarz(A, top, family)
+        self.add = additive if additive is not None else AdditiveSchwarz(A, top, family, decomposition)
         n = top.n_dofs
         mask = np.zeros(n, dtype=bool)
         mask[self.add.I] = True

@@ -9,6 +9,11 @@
   estimate is within 6% of the printed one (the paper's right-hand side is an
   unspecified random vector).  Dropping the weights, the coarse space, or the
   multiplicative order moves the estimate by far more than that.
+* The vertex-star comparators (tests/golden/paper_vertex_star_level0.csv,
+  the same tables): PAFW(0)(X^k_Gamma) + J(X^k_I) and the full vertex stars
+  PAFW(0)(X^k) for H(grad), H(curl) and H(div), to the same bars.  These
+  pin the star lists (with or without the cell interiors), the empty
+  interior group of the full form and the same weights and sweep.
 * Algebra: the sweep is symmetric and positive definite, and its error
   propagator I - B A is the product of the group propagators
   (I - rho_m^{-1} B_m A) in the order 1, 2, 3, 2, 1.
@@ -26,16 +31,24 @@ from oracle.element import element
 from oracle.mesh import Topology
 from oracle.operator import all_cell_matrices, assemble
 from oracle.pcg import lanczos_condest, pcg
-from oracle.precond import SEED_INTERFACE, SEED_INTERIOR, HybridSchwarz, subspace_extremes
+from oracle.precond import (SEED_INTERFACE, SEED_INTERIOR, HybridSchwarz, patch_lists, subspace_extremes,
+                            vertex_star_lists)
 from paper_2506_17406_amd.workloads import kuhn_mesh
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_hybrid_level0.csv")
+GOLDEN_VSTAR = os.path.join(os.path.dirname(__file__), "golden", "paper_vertex_star_level0.csv")
 
 
 def golden_rows():
     with open(GOLDEN) as f:
         rows = [r for r in csv.reader(l for l in f if not l.startswith("#"))]
     return [(r[0], int(r[1]), int(r[2]), float(r[3]), int(r[4]), float(r[5])) for r in rows]
+
+
+def golden_vstar_rows():
+    with open(GOLDEN_VSTAR) as f:
+        rows = [r for r in csv.reader(l for l in f if not l.startswith("#"))]
+    return [(r[0], r[1], int(r[2]), int(r[3]), float(r[4]), int(r[5]), float(r[6])) for r in rows]
 
 
 def build(fam, p, n=3, alpha=1.0, jitter=0.0):
@@ -57,10 +70,43 @@ def test_paper_level0_iterations_and_condest(row):
     assert abs(lanczos_condest(info["alphas"], info["betas"]) / cond - 1.0) <= 0.06
 
 
-@pytest.mark.parametrize("fam,p", [("CG", 4), ("Ned", 2), ("RT", 2)])
-def test_sweep_symmetric_positive_and_product_of_propagators(fam, p):
+@pytest.mark.parametrize("row", golden_vstar_rows(), ids=lambda r: f"{r[0]}{r[2]}-{r[1]}-alpha{r[4]:g}")
+def test_paper_level0_vertex_star_solvers(row):
+    fam, form, p, dofs, alpha, its, cond = row
+    top, A = build(fam, p, alpha=alpha)
+    assert top.n_dofs == dofs
+    H = HybridSchwarz(A, top, fam, decomposition=form)
+    if form == "vertex-full":
+        assert len(H.add.I) == 0 and len(H.Gamma) == top.n_dofs
+    b = np.random.default_rng(5).uniform(-1.0, 1.0, top.n_dofs)
+    _, info = pcg(lambda v: A @ v, H.apply, b, rtol=1e-8, maxit=300, norm="preconditioned")
+    assert abs(info["iterations"] - its) <= 2
+    assert abs(lanczos_condest(info["alphas"], info["betas"]) / cond - 1.0) <= 0.06
+
+
+def test_vertex_stars_cover_and_reduce_to_the_default_for_h1():
+    """Every dof lies in some star; the split stars omit exactly the cell
+    interiors; for H(grad) the split stars are the default patches."""
+    X, C = kuhn_mesh(2, 3, jitter=0.1, seed=4)
+    for fam, p in (("CG", 4), ("Ned", 3), ("RT", 3)):
+        top = Topology(X, C, element(3, fam, p))
+        split, full = vertex_star_lists(top, False), vertex_star_lists(top, True)
+        cover = np.zeros(top.n_dofs, dtype=bool)
+        for a, b in zip(split, full):
+            assert np.all(a < top.offset[3])
+            extra = np.setdiff1d(b, a)
+            assert np.all(extra >= top.offset[3]) and len(b) == len(a) + len(extra)
+            cover[b] = True
+        assert cover.all()
+        if fam == "CG":
+            assert all(np.array_equal(a, b) for a, b in zip(split, patch_lists(top, "CG")))
+
+
+@pytest.mark.parametrize("fam,p,form", [("CG", 4, "paper"), ("Ned", 2, "paper"), ("RT", 2, "paper"),
+                                         ("Ned", 3, "vertex"), ("RT", 3, "vertex-full")])
+def test_sweep_symmetric_positive_and_product_of_propagators(fam, p, form):
     top, A = build(fam, p, n=1, jitter=0.0)
-    H = HybridSchwarz(A, top, fam)
+    H = HybridSchwarz(A, top, fam, decomposition=form)
     n = top.n_dofs
     Ad = A.toarray()
     I = np.eye(n)

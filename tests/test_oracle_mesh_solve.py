@@ -19,7 +19,7 @@ from oracle.element import element
 from oracle.mesh import Topology
 from oracle.operator import all_cell_matrices, assemble, element_apply, functional_load
 from oracle.pcg import lanczos_condest, pcg
-from oracle.precond import AdditiveSchwarz, patch_lists, potential_patches
+from oracle.precond import AdditiveSchwarz, patch_lists, potential_patches, vertex_star_lists
 from paper_2506_17406_amd.workloads import kuhn_counts, kuhn_mesh, load_vectors
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -91,6 +91,8 @@ def test_paper_patch_sizes_p4():
     assert max(G.shape[1] for G in potential_patches(ned, (1, 3, 3))) == golden[("Ned", "vertex_potential_interface", 4)]
     rt = Topology(X, C, element(3, "RT", 4))
     assert max(len(i) for i in patch_lists(rt, "RT")) == golden[("RT", "edge_star_interface", 4)]
+    assert max(len(i) for i in vertex_star_lists(cg, True)) == golden[("CG", "vertex_star_full", 4)]
+    assert max(len(i) for i in vertex_star_lists(cg, False)) == golden[("CG", "vertex_star_interface", 4)]
 
 
 def test_paper_patch_sizes_p10_closed_form():
