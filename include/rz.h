@@ -104,6 +104,23 @@ typedef enum { RZ_FP64 = 0, RZ_FP32_IR = 1, RZ_FP32_PC = 2, RZ_BF16_PC = 3 } rz_
  * application; takes 2-3 times fewer PCG iterations. */
 typedef enum { RZ_PC_ADDITIVE = 0, RZ_PC_HYBRID = 1 } rz_pc;
 
+/* Space decomposition of the preconditioner (Sec. 6).  RZ_DECOMP_PAPER: the
+ * interior-interface split solvers the paper recommends -- H(grad)
+ * PAFW(0)(X^0_Gamma) + J(X^0_I) (eq:approx-sc-pafw), H(curl)
+ * PH(X^0_Gamma, X^{1,I}_Gamma) + J(X^1_I) (vertex-star potentials through
+ * the discrete gradient plus type-I edge stars, eq:hcurl-decomp), H(div)
+ * PAFW(1)(X^2_Gamma) + J(X^2_I) (edge stars, eq:hdiv-decomp).
+ * RZ_DECOMP_VERTEX: the comparator PAFW(0)(X^k_Gamma) + J(X^k_I) for every
+ * space -- one patch per vertex with the dofs of the vertex and of the edges
+ * and faces containing it (for H(grad) the same as RZ_DECOMP_PAPER).
+ * RZ_DECOMP_VERTEX_FULL: the comparator without the split, PAFW(0)(X^k)
+ * (eq:pafw) -- the vertex stars also hold the interior dofs of the cells
+ * containing the vertex, and there is no Jacobi group (the hybrid sweep is
+ * stars, W, stars).  Its patches grow like p^d rather than p^(d-1): a patch
+ * larger than 2048 dofs (3D: H(grad) p > 8, H(curl) and H(div) p > 5) is
+ * RZ_ERR_UNSUPPORTED.  The coarse space W^k is the same in all three. */
+typedef enum { RZ_DECOMP_PAPER = 0, RZ_DECOMP_VERTEX = 1, RZ_DECOMP_VERTEX_FULL = 2 } rz_decomposition;
+
 typedef struct {
   double alpha;           /* coefficient of (d u, d v), >= 0 */
   double beta;            /* coefficient of (u, v), > 0 */
@@ -116,6 +133,7 @@ typedef struct {
                              chunks are captured into HIP graphs (per solution vector and column
                              count) and replayed, on a stream of the handle ordered after and
                              before the caller's stream */
+  int32_t decomposition;  /* rz_decomposition (0: RZ_DECOMP_PAPER) */
 } rz_options;
 
 typedef struct {
@@ -213,6 +231,15 @@ int rz_reference(int32_t dim, int32_t degree, rz_space space, int32_t *n_loc, in
  * first; cell_dofs needs n_cells x n_loc entries. */
 int rz_numbering(const rz_mesh *mesh, int32_t degree, rz_space space, int64_t *n_dofs, int32_t *cell_dofs,
                  int64_t *n_patches, int64_t *n_patch_entries, int64_t *patch_ptr, int32_t *patch_dofs);
+
+/* Host-only (no device work): the patch lists of the first patch family
+ * that rz_setup builds under the given rz_decomposition, in the
+ * rz_export_topology layout (ascending dofs per patch; for H(curl) under
+ * RZ_DECOMP_PAPER the edge patches).  Pass NULL patch_ptr / patch_dofs to
+ * query *n_patches and *n_patch_entries first.  Errors as rz_numbering, and
+ * RZ_ERR_ARG for an unknown decomposition. */
+int rz_patch_lists(const rz_mesh *mesh, int32_t degree, rz_space space, int32_t decomposition, int64_t *n_patches,
+                   int64_t *n_patch_entries, int64_t *patch_ptr, int32_t *patch_dofs);
 
 void rz_destroy(rz_problem *P);
 

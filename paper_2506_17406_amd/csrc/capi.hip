@@ -63,6 +63,7 @@ struct rz_problem {
   double inner_rtol = 3e-3;
   // preconditioner form; hybrid: group weights and local column ranges
   int pc = RZ_PC_ADDITIVE;
+  int decomp = RZ_DECOMP_PAPER;  // rz_decomposition of the patches
   double rho_I = 1.0, rho_G = 1.0;
   int col_int = 0;            // local interior columns [col_int, n)
   int col_w0 = 0, col_w1 = 0; // local columns of the entities that carry the Whitney dofs
@@ -372,8 +373,10 @@ void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
   // numbering, patches
   P.top = rz::build_topology(P.d, m->n_vertices, m->n_cells, m->cells, P.el);
   check_cells(P, m->coords);
-  P.patches = rz::build_patches(P.top, P.el);
-  P.off_I = P.top.offset[P.d];
+  P.patches = rz::build_patches(P.top, P.el, rz::Decomposition(P.decomp));
+  // first dof of the Jacobi group: the interior dofs, or none when the full
+  // vertex stars (eq:pafw) hold them
+  P.off_I = P.decomp == RZ_DECOMP_VERTEX_FULL ? P.top.n_dofs : P.top.offset[P.d];
   const int n = P.el.n, Q = P.el.Q, d = P.d;
   // the apply's local order: Whitney dofs of the k-entities first, so the
   // hybrid's coarse correction (nonzero only there) is applied with a
@@ -442,6 +445,9 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     if (opts->pc != RZ_PC_ADDITIVE && opts->pc != RZ_PC_HYBRID) return fail(RZ_ERR_ARG, "unknown preconditioner");
     P->pc = opts->pc;
     P->graphs = opts->eager == 0;
+    if (opts->decomposition < RZ_DECOMP_PAPER || opts->decomposition > RZ_DECOMP_VERTEX_FULL)
+      return fail(RZ_ERR_ARG, "unknown decomposition");
+    P->decomp = opts->decomposition;
   }
   P->fam = space == RZ_HGRAD ? rz::FAM_CG : (space == RZ_HCURL ? rz::FAM_NED : rz::FAM_RT);
   try {
@@ -467,13 +473,18 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
       double *dEi = P->upload(Ei.a, s);
       rz::launch_weights(d, P->k, nc, dX, dEi, alpha, beta, P->w, Q, s);
     }
-    // interior diagonal (Jacobi on X^k_I)
+    // interior diagonal (Jacobi on X^k_I; an empty group under the full
+    // vertex stars)
+    const bool full_stars = P->decomp == RZ_DECOMP_VERTEX_FULL;
     std::vector<int32_t> loc_int;
     for (int i = 0; i < n; ++i)
       if (P->el.dofs[i].entity_dim == d) loc_int.push_back(i);
     P->dinv = P->dev<double>(std::max<int64_t>(1, P->top.n_interior));
-    int32_t *dloc = P->upload(loc_int, s);
-    rz::launch_interior_diag(nc, n, Q, P->R, P->w, P->cell_dofs, dloc, int(loc_int.size()), P->off_I, P->dinv, s);
+    if (!full_stars) {
+      int32_t *dloc = P->upload(loc_int, s);
+      rz::launch_interior_diag(nc, n, Q, P->R, P->w, P->cell_dofs, dloc, int(loc_int.size()), P->off_I, P->dinv,
+                               s);
+    }
     HIPCHK(hipGetLastError());
     // apply_A tables
     P->at.n = n;
@@ -565,6 +576,9 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
         if (in_int != (i >= P->col_int) || in_w != (ld.entity_dim == P->k && ld.kind == rz::KIND_W))
           throw RzError{RZ_ERR_UNSUPPORTED, "unexpected local dof order"};
       }
+      // the full vertex stars cover the interior too: the patch group's
+      // corrections live on every local column, and no rows are interior
+      if (full_stars) P->col_int = n;
     }
     HIPCHK(hipStreamSynchronize(s));
     if (P->pc == RZ_PC_HYBRID) estimate_weights(P.get(), s);
@@ -1154,9 +1168,11 @@ int rz_reference(int32_t dim, int32_t degree, rz_space space, int32_t *n_loc, in
   return RZ_OK;
 }
 
-int rz_numbering(const rz_mesh *m, int32_t degree, rz_space space, int64_t *n_dofs, int32_t *cell_dofs,
-                 int64_t *n_patches, int64_t *n_patch_entries, int64_t *patch_ptr, int32_t *patch_dofs) {
+static int numbering_impl(const rz_mesh *m, int32_t degree, rz_space space, int32_t dec, int64_t *n_dofs,
+                          int32_t *cell_dofs, int64_t *n_patches, int64_t *n_patch_entries, int64_t *patch_ptr,
+                          int32_t *patch_dofs) {
   if (!m || !m->cells) return fail(RZ_ERR_ARG, "null argument");
+  if (dec < RZ_DECOMP_PAPER || dec > RZ_DECOMP_VERTEX_FULL) return fail(RZ_ERR_ARG, "unknown decomposition");
   rz::Family fam;
   if (int e = check_space(m->dim, degree, space, fam)) return e;
   if (m->n_vertices <= 0 || m->n_cells <= 0) return fail(RZ_ERR_ARG, "empty mesh");
@@ -1166,7 +1182,7 @@ int rz_numbering(const rz_mesh *m, int32_t degree, rz_space space, int64_t *n_do
     if (n_dofs) *n_dofs = top.n_dofs;
     if (cell_dofs) std::memcpy(cell_dofs, top.cell_dofs.data(), top.cell_dofs.size() * 4);
     if (n_patches || n_patch_entries || (patch_ptr && patch_dofs)) {
-      auto sets = rz::build_patches(top, el);
+      auto sets = rz::build_patches(top, el, rz::Decomposition(dec));
       const rz::PatchSet &ps = sets.at(0);
       const int64_t np = ps.n_patches();
       if (n_patches) *n_patches = np;
@@ -1182,6 +1198,18 @@ int rz_numbering(const rz_mesh *m, int32_t degree, rz_space space, int64_t *n_do
     return fail(RZ_ERR_UNSUPPORTED, e.what());
   }
   return RZ_OK;
+}
+
+int rz_numbering(const rz_mesh *m, int32_t degree, rz_space space, int64_t *n_dofs, int32_t *cell_dofs,
+                 int64_t *n_patches, int64_t *n_patch_entries, int64_t *patch_ptr, int32_t *patch_dofs) {
+  return numbering_impl(m, degree, space, RZ_DECOMP_PAPER, n_dofs, cell_dofs, n_patches, n_patch_entries, patch_ptr,
+                        patch_dofs);
+}
+
+int rz_patch_lists(const rz_mesh *m, int32_t degree, rz_space space, int32_t decomposition, int64_t *n_patches,
+                   int64_t *n_patch_entries, int64_t *patch_ptr, int32_t *patch_dofs) {
+  return numbering_impl(m, degree, space, decomposition, nullptr, nullptr, n_patches, n_patch_entries, patch_ptr,
+                        patch_dofs);
 }
 
 void rz_destroy(rz_problem *P) { delete P; }

@@ -218,7 +218,7 @@ PatchSet empty_set() {
 
 }  // namespace
 
-std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el) {
+std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Decomposition dec) {
   const int d = t.d;
   Incidence in = incidence(t);
   std::vector<int32_t> mark_col(t.n_dofs, -1);
@@ -230,6 +230,24 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el) {
     for (int32_t g : dofs) cols.push_back({{g, 1.0}});
     return cols;
   };
+  if (dec != DECOMP_PAPER) {
+    // vertex stars (eq:approx-sc-pafw; with the cell interiors, eq:pafw):
+    // the entities containing the vertex carry the dofs whose support lies
+    // in its star; entity_dofs adds nothing where the space has no dofs
+    PatchSet ps = empty_set();
+    for (int64_t v = 0; v < t.n_vertices; ++v) {
+      std::vector<int32_t> dofs;
+      entity_dofs(t, el, 0, v, -1, dofs);
+      for (int64_t e : in.v_edges[v]) entity_dofs(t, el, 1, e, -1, dofs);
+      if (d == 3)
+        for (int64_t f : in.v_faces[v]) entity_dofs(t, el, 2, f, -1, dofs);
+      if (dec == DECOMP_VERTEX_FULL)
+        for (int64_t c : in.v_cells[v]) entity_dofs(t, el, d, c, -1, dofs);
+      add_patch(ps, t, el, plain_cols(dofs), in.v_cells[v], mark_col, mark_coef);
+    }
+    out.push_back(std::move(ps));
+    return out;
+  }
   if (el.fam == FAM_CG) {
     // vertex stars of the interface space X^0_Gamma (eq:approx-sc-pafw)
     PatchSet ps = empty_set();

@@ -42,11 +42,17 @@ struct PatchSet {
   int64_t max_size() const;
 };
 
-// The interface patches of Sec. 6 for the element's space:
-//  H(grad): vertex stars of X^0_Gamma; H(curl): edge stars of X^{1,I}_Gamma
-//  (plain) and vertex-star potentials through the discrete gradient;
-//  H(div): edge stars of X^2_Gamma.
-std::vector<PatchSet> build_patches(const Topology &top, const RefElement &el);
+// Which space decomposition the patches follow (Sec. 6).
+//  DECOMP_PAPER: the interface patches of the default solvers -- H(grad):
+//  vertex stars of X^0_Gamma; H(curl): edge stars of X^{1,I}_Gamma (plain)
+//  and vertex-star potentials through the discrete gradient; H(div): edge
+//  stars of X^2_Gamma.
+//  DECOMP_VERTEX: PAFW(0)(X^k_Gamma) (eq:approx-sc-pafw) for every space:
+//  per vertex, the dofs of the vertex and of the edges and faces containing it.
+//  DECOMP_VERTEX_FULL: PAFW(0)(X^k) (eq:pafw): those vertex stars together
+//  with the interior dofs of the cells containing the vertex.
+enum Decomposition { DECOMP_PAPER = 0, DECOMP_VERTEX = 1, DECOMP_VERTEX_FULL = 2 };
+std::vector<PatchSet> build_patches(const Topology &top, const RefElement &el, Decomposition dec = DECOMP_PAPER);
 
 // Whitney dofs (one per k-subsimplex, lem:basis-contains-whitney), ascending,
 // and per cell the local Whitney dofs with their coarse indices.

@@ -29,12 +29,14 @@ RZ_FP64, RZ_FP32_IR, RZ_FP32_PC, RZ_BF16_PC = 0, 1, 2, 3
 PRECISIONS = {"fp64": RZ_FP64, "fp32-ir": RZ_FP32_IR, "fp32-pc": RZ_FP32_PC, "bf16-pc": RZ_BF16_PC}
 RZ_PC_ADDITIVE, RZ_PC_HYBRID = 0, 1
 PCS = {"additive": RZ_PC_ADDITIVE, "hybrid": RZ_PC_HYBRID}
+RZ_DECOMP_PAPER, RZ_DECOMP_VERTEX, RZ_DECOMP_VERTEX_FULL = 0, 1, 2
+DECOMPOSITIONS = {"paper": RZ_DECOMP_PAPER, "vertex": RZ_DECOMP_VERTEX, "vertex-full": RZ_DECOMP_VERTEX_FULL}
 
 
 class RzOptions(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("pc", ctypes.c_int32),
-                ("eager", ctypes.c_int32)]
+                ("eager", ctypes.c_int32), ("decomposition", ctypes.c_int32)]
 
 
 class RzInfo(ctypes.Structure):
@@ -71,6 +73,7 @@ def _load():
         "rz_reference": (ctypes.c_int, [i32, i32, ctypes.c_int, pi32, pi32, pdbl]),
         "rz_numbering": (ctypes.c_int, [ctypes.POINTER(RzMesh), i32, ctypes.c_int, pi64, pi32, pi64, pi64, pi64,
                                         pi32]),
+        "rz_patch_lists": (ctypes.c_int, [ctypes.POINTER(RzMesh), i32, ctypes.c_int, i32, pi64, pi64, pi64, pi32]),
         "rz_destroy": (None, [P]),
         "rz_batch_create": (ctypes.c_int, [ctypes.POINTER(P), i32, ctypes.POINTER(P)]),
         "rz_batch_solve": (ctypes.c_int, [P, ctypes.POINTER(P), ctypes.POINTER(P), dbl, ctypes.POINTER(RzInfo), P]),
@@ -129,6 +132,21 @@ def numbering(coords, cells, degree, space, n_loc):
     return nd.value, cd, ptr, dofs
 
 
+def patch_lists(coords, cells, degree, space, decomposition="paper"):
+    """(patch_ptr, patch_dofs) of the first patch family rz_setup builds
+    under `decomposition`, host only."""
+    m, keep = _mesh(coords, cells)
+    sp = SPACES[space] if isinstance(space, str) else space
+    dec = DECOMPOSITIONS[decomposition] if isinstance(decomposition, str) else decomposition
+    npat, nent = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.rz_patch_lists(ctypes.byref(m), degree, sp, dec, ctypes.byref(npat), ctypes.byref(nent), None, None))
+    ptr = np.empty(npat.value + 1, dtype=np.int64)
+    dofs = np.empty(nent.value, dtype=np.int32)
+    _check(lib.rz_patch_lists(ctypes.byref(m), degree, sp, dec, None, None, _ptr(ptr, ctypes.c_int64),
+                              _ptr(dofs, ctypes.c_int32)))
+    return ptr, dofs
+
+
 def _stream(stream):
     if stream is not None:
         return ctypes.c_void_p(stream)
@@ -140,11 +158,12 @@ class Problem:
     """A set-up Riesz-map problem on the GPU (rz_setup)."""
 
     def __init__(self, coords, cells, degree, space, alpha=1.0, beta=1.0, max_iter=1000, precision="fp64",
-                 inner_rtol=0.0, pc="hybrid", graphs=True, stream=None):
+                 inner_rtol=0.0, pc="hybrid", graphs=True, stream=None, decomposition="paper"):
         m, keep = _mesh(coords, cells)
         prec = PRECISIONS[precision] if isinstance(precision, str) else precision
+        dec = DECOMPOSITIONS[decomposition] if isinstance(decomposition, str) else decomposition
         opts = RzOptions(alpha, beta, max_iter, prec, inner_rtol, PCS[pc] if isinstance(pc, str) else pc,
-                         0 if graphs else 1)
+                         0 if graphs else 1, dec)
         h = ctypes.c_void_p()
         self._h = None
         self.space = SPACES[space] if isinstance(space, str) else space

@@ -1,0 +1,113 @@
+"""GPU parity of the vertex-star comparators (Sec. 6.1) against the oracle,
+through the C ABI: PAFW(0)(X^k_Gamma) + J(X^k_I) ("vertex") and the full
+vertex stars PAFW(0)(X^k) ("vertex-full"), for every space, in the additive
+and the symmetric multiplicative hybrid form.
+
+Sizes: meshes of 6-162 cells, degrees 2-8, seeded jitter and load vectors;
+the largest full stars near the 2048-dof patch limit (H(grad) p = 8: 1695,
+H(curl) p = 5: 1510, H(div) p = 5: 1980); degenerate cases: no interior dofs
+(both forms coincide), a single cell, a mesh without interior vertices.
+Bars, as for the default decompositions:
+* group weights equal to the oracle's within 1e-10 (the full form's empty
+  Jacobi group has weight 1);
+* apply_P -- max |z_gpu - z_oracle| <= 1e-10 max |z_oracle|;
+* solve   -- iteration counts within one, true residual under the oracle's A
+             <= 1e-10, ||x_gpu - x_oracle|| <= 1e-10 ||x_oracle|| at rtol 1e-12.
+A full star above 2048 dofs is refused with RZ_ERR_UNSUPPORTED at setup.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.element import element
+from oracle.mesh import Topology
+from oracle.operator import all_cell_matrices, assemble
+from oracle.pcg import pcg
+from oracle.precond import AdditiveSchwarz, HybridSchwarz
+from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
+
+pytestmark = pytest.mark.gpu
+
+# (dim, space, degree, cells per edge (0 = a single tetrahedron), jitter)
+CASES = [(3, "CG", 4, 2, 0.1), (3, "Ned", 3, 2, 0.1), (3, "Ned", 4, 2, 0.1), (3, "RT", 3, 2, 0.1),
+         (3, "RT", 4, 3, 0.0), (2, "CG", 4, 3, 0.1),
+         # no interior dofs, no interior vertex, a single cell
+         (3, "Ned", 2, 2, 0.1), (3, "CG", 5, 1, 0.0), (3, "RT", 3, 0, 0.0),
+         # the largest full stars below the patch limit
+         (3, "CG", 8, 2, 0.1), (3, "Ned", 5, 2, 0.1), (3, "RT", 5, 2, 0.1)]
+FORMS = ["vertex", "vertex-full"]
+PCS = ["additive", "hybrid"]
+_cache = {}
+
+
+def setup_case(d, fam, p, n, jit, form, pc):
+    key = (d, fam, p, n, jit, form, pc)
+    if key not in _cache:
+        from paper_2506_17406_amd import rz
+        if n == 0:
+            X = np.array([[0.1, 0.0, 0.05], [1.0, 0.2, 0.0], [0.3, 0.9, 0.1], [0.2, 0.3, 1.1]])
+            C = np.array([[2, 0, 3, 1]])
+        else:
+            X, C = kuhn_mesh(n, d, jitter=jit, seed=13)
+        base = (d, fam, p, n, jit, form, "additive")
+        if base in _cache:
+            top, A, P_add = _cache[base][:3]
+        else:
+            top = Topology(X, C, element(d, fam, p))
+            A = assemble(top, all_cell_matrices(top.el, top))
+            P_add = AdditiveSchwarz(A, top, fam, decomposition=form)
+        P = P_add if pc == "additive" else HybridSchwarz(A, top, fam, additive=P_add)
+        print(f"setup {fam}{p} n={n} {form} {pc} dofs={top.n_dofs}", flush=True)
+        prob = rz.Problem(X, C, p, fam, pc=pc, decomposition=form)
+        assert prob.n_dofs == top.n_dofs
+        _cache[key] = (top, A, P, prob)
+    return _cache[key]
+
+
+def ids(c):
+    return "{}d-{}{}-n{}".format(*c[:4]) if c[3] else "{}d-{}{}-tet".format(*c[:3])
+
+
+@pytest.mark.parametrize("pc", PCS)
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_apply_P(case, form, pc):
+    top, A, P, prob = setup_case(*case, form, pc)
+    if pc == "hybrid":
+        rho = prob.pc_weights()
+        assert abs(rho[0] / P.rho_I - 1) <= 1e-10 and abs(rho[1] / P.rho_Gamma - 1) <= 1e-10 and rho[2] == 1.0
+        if form == "vertex-full":
+            assert rho[0] == 1.0
+    r = load_vectors(top.n_dofs, 16)[:, 0]
+    zt = torch.empty(top.n_dofs, dtype=torch.float64, device="cuda")
+    prob.apply_P(torch.from_numpy(r).cuda(), zt)
+    torch.cuda.synchronize()
+    ref = P.apply(r)
+    assert np.abs(zt.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("pc", PCS)
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_solve(case, form, pc):
+    top, A, P, prob = setup_case(*case, form, pc)
+    b = load_vectors(top.n_dofs, 17)[:, 0]
+    bt = torch.from_numpy(b).cuda()
+    xt = torch.zeros_like(bt)
+    info = prob.solve(bt, xt, rtol=1e-12)
+    x = xt.cpu().numpy()
+    xo, io = pcg(lambda v: A @ v, P.apply, b, rtol=1e-12)
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_full_star_above_patch_limit_is_refused():
+    from paper_2506_17406_amd import rz
+    X, C = kuhn_mesh(2, 3, jitter=0.1, seed=13)
+    with pytest.raises(rz.RzError) as e:
+        rz.Problem(X, C, 6, "Ned", decomposition="vertex-full")   # interior star: 2604 dofs
+    assert e.value.code == -2 and "2048" in str(e.value)
+    prob = rz.Problem(X, C, 6, "Ned", decomposition="vertex")      # split star: 1164 dofs
+    assert prob.n_dofs > 0

@@ -6,7 +6,8 @@
 * the library's independently built reference tables match the oracle's
   (relative 1e-11);
 * the library's numbering and patch lists are bit-identical to the oracle's,
-  also for permuted cell-vertex orders and shuffled cell orders.
+  also for permuted cell-vertex orders and shuffled cell orders, for the
+  default decompositions and the vertex-star ones (split and full).
 """
 import ctypes
 import os
@@ -18,7 +19,7 @@ import pytest
 from oracle.element import element
 from oracle.mesh import Topology
 from oracle.operator import reference_stack
-from oracle.precond import patch_lists
+from oracle.precond import patch_lists, vertex_star_lists
 from paper_2506_17406_amd.workloads import kuhn_mesh
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -79,6 +80,9 @@ def test_setup_rejects_before_device_work():
     opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 3, 0)           # unknown preconditioner form
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
     assert b"preconditioner" in rz.lib.rz_last_error()
+    opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 1, 0, 3)        # unknown decomposition
+    assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
+    assert b"decomposition" in rz.lib.rz_last_error()
     assert rz.lib.rz_setup(None, 2, 0, None, None, ctypes.byref(h)) == -1
     assert rz.lib.rz_setup(ctypes.byref(m), 12, 0, None, None, ctypes.byref(h)) == -2
     # a flat tetrahedron: all four vertices in one plane
@@ -124,3 +128,28 @@ def test_numbering_bit_exact(d, fam, p, n, shuffle):
     assert len(ptr) - 1 == len(pl)
     for i, idx in enumerate(pl):
         assert np.array_equal(dofs[ptr[i]:ptr[i + 1]], idx)
+
+
+VSTAR_CASES = [(2, "CG", 4, 3), (3, "CG", 4, 2), (3, "Ned", 3, 2), (3, "RT", 3, 2), (3, "Ned", 1, 2)]
+
+
+@pytest.mark.parametrize("d,fam,p,n", VSTAR_CASES, ids=lambda v: str(v))
+@pytest.mark.parametrize("form", ["vertex", "vertex-full"])
+def test_vertex_star_lists_bit_exact(d, fam, p, n, form):
+    X, C = kuhn_mesh(n, d, jitter=0.1, seed=6)
+    rng = np.random.default_rng(11)
+    C = C[rng.permutation(len(C))]
+    C = np.array([row[rng.permutation(d + 1)] for row in C])
+    top = Topology(X, C, element(d, fam, p))
+    ptr, dofs = rz.patch_lists(X, C, p, fam, form)
+    pl = vertex_star_lists(top, form == "vertex-full")
+    assert len(ptr) - 1 == len(pl) == top.n_vertices
+    for i, idx in enumerate(pl):
+        assert np.array_equal(dofs[ptr[i]:ptr[i + 1]], idx)
+    # the default decomposition through the same entry point is rz_numbering's
+    if form == "vertex":
+        ptr0, dofs0 = rz.patch_lists(X, C, p, fam, "paper")
+        _, _, ptr1, dofs1 = rz.numbering(X, C, p, fam, top.el.n)
+        assert np.array_equal(ptr0, ptr1) and np.array_equal(dofs0, dofs1)
+    with pytest.raises(rz.RzError):
+        rz.patch_lists(X, C, p, fam, 5)
