@@ -45,12 +45,14 @@ def parse():
     ap.add_argument("--sweep-mode", choices=["batched", "sequential"], default="batched",
                     help="sweep step: the 18 problems solved one after another, or together as one batch "
                          "(a stream per problem, captured iteration graphs)")
-    ap.add_argument("--workload", choices=["sweep", "multirhs", "mixed", "batch"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "multirhs", "mixed", "batch", "decompositions"], default="sweep",
                     help="sweep: the 3D FP64 sweep (default, the headline line); multirhs: H(div) RT_5 on the "
                          "12^3x6 mesh with 64 right-hand sides, one batched solve vs 64 single solves; mixed: "
                          "H(curl) Ned_6 on the 16^3x6 mesh, FP32 refinement and FP32/BF16-stored preconditioners vs "
                          "plain FP64 PCG; batch: 32 uneven "
-                         "H(grad)/H(curl) problems solved together vs one by one")
+                         "H(grad)/H(curl) problems solved together vs one by one; decompositions: the default "
+                         "split solvers against the vertex-star comparators PAFW(0)(X^k_Gamma)+J and "
+                         "PAFW(0)(X^k) on the sweep mesh (--degrees, default 4,5 for this workload)")
     ap.add_argument("--batch-count", type=int, default=32)
     ap.add_argument("--batch-max-gb", type=float, default=240.0)
     ap.add_argument("--batch-precision", choices=["fp64", "fp32-pc", "bf16-pc"], default="bf16-pc")
@@ -396,6 +398,98 @@ def batch_workload(args):
     print(json.dumps(line), flush=True)
 
 
+def decompositions(args):
+    """The space decompositions of Sec. 6 side by side on the sweep's mesh
+    (jittered 8^3x6, mesh seed 2, load seed 3), FP64 PCG to 1e-10: the
+    default split solvers, the vertex-star split PAFW(0)(X^k_Gamma)+J, and
+    the full vertex stars PAFW(0)(X^k).  Per problem: setup, iterations,
+    solve time, patch sizes.  Roofline: the additive full-star
+    preconditioner apply of the largest problem, an HBM stream of the packed
+    patch and coarse inverses."""
+    import torch
+    from paper_2506_17406_amd import rz
+    from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    X, C = kuhn_mesh(args.n, 3, jitter=0.1, seed=2)
+    spaces = args.spaces.split(",")
+    degrees = [4, 5] if args.degrees == "3,4,5,6,7,8" else [int(p) for p in args.degrees.split(",")]
+    forms = ["paper", "vertex", "vertex-full"]
+    # Whitney (coarse) dof counts: vertices, edges or faces of the mesh
+    Cs = np.sort(C, axis=1)
+    n_sub = {0: X.shape[0],
+             1: len(np.unique(Cs[:, [[0, 1], [0, 2], [0, 3], [1, 2], [1, 3], [2, 3]]].reshape(-1, 2), axis=0)),
+             2: len(np.unique(Cs[:, [[0, 1, 2], [0, 1, 3], [0, 2, 3], [1, 2, 3]]].reshape(-1, 3), axis=0))}
+    rows, tot = [], {f: [0, 0.0] for f in forms}
+    for fam in spaces:
+        for p in degrees:
+            for form in forms:
+                t0 = time.perf_counter()
+                prob = rz.Problem(X, C, p, fam, pc=args.pc, decomposition=form)
+                torch.cuda.synchronize()
+                t_set = time.perf_counter() - t0
+                b = torch.from_numpy(load_vectors(prob.n_dofs, 3)[:, 0]).cuda()
+                x = torch.zeros_like(b)
+                for _ in range(args.warmup):
+                    x.zero_()
+                    prob.solve(b, x, rtol=1e-10)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    x.zero_()
+                    info = prob.solve(b, x, rtol=1e-10)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / args.steps
+                ptr, _ = rz.patch_lists(X, C, p, fam, form)
+                m = np.diff(ptr)
+                t_p = _apply_time(prob.apply_P, b, x, args.apply_reps, stream)
+                rows.append(dict(space=fam, p=p, decomposition=form, dofs=prob.n_dofs, its=info["iterations"],
+                                 rel_res=info["rel_residual"], cond=round(info["cond_estimate"], 3),
+                                 solve_ms=round(dt * 1e3, 3), apply_P_us=round(t_p * 1e6, 1),
+                                 setup_s=round(t_set, 2), max_patch=int(m.max()),
+                                 patch_mb=round(float((m * (m + 1) // 2).sum()) * 8 / 1e6, 1)))
+                tot[form][0] += prob.n_dofs
+                tot[form][1] += dt
+                print(f"{fam}{p} {form}: {prob.n_dofs} dofs, setup {t_set:.2f}s, {info['iterations']} its, "
+                      f"{dt * 1e3:.1f} ms, apply_P {t_p * 1e6:.0f} us, max patch {m.max()}", file=sys.stderr,
+                      flush=True)
+                prob.close()
+                del prob
+                torch.cuda.empty_cache()
+    # roofline: additive full-star apply_P of the largest problem
+    big = max((r for r in rows if r["decomposition"] == "vertex-full"), key=lambda r: r["patch_mb"])
+    prob = rz.Problem(X, C, big["p"], big["space"], pc="additive", decomposition="vertex-full")
+    ptr, _ = rz.patch_lists(X, C, big["p"], big["space"], "vertex-full")
+    m = np.diff(ptr).astype(np.float64)
+    nW = n_sub[{"CG": 0, "Ned": 1, "RT": 2}[big["space"]]]
+    # packed patch inverses, packed coarse inverse, r read and z written
+    nbytes = 8.0 * ((m * (m + 1) / 2).sum() + nW * (nW + 1) / 2 + 2 * prob.n_dofs)
+    r = torch.from_numpy(load_vectors(prob.n_dofs, 3)[:, 0]).cuda()
+    z = torch.empty_like(r)
+    t_add = _apply_time(prob.apply_P, r, z, args.apply_reps, stream)
+    gbs = nbytes / t_add / 1e9
+    d_paper, d_full = tot["paper"], tot["vertex-full"]
+    line = {
+        "metric": "Riesz-map solve DOFs/s to rel. residual 1e-10 (decomposition comparison)",
+        "value": d_paper[0] / d_paper[1], "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": d_paper[1] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"Sec. 6 decompositions: {'/'.join(spaces)} x p={','.join(map(str, degrees))} on the "
+                               f"jittered Kuhn {args.n}^3x6 mesh, rtol 1e-10, {args.pc} preconditioner; value is the "
+                               "default split solvers, the comparators beside it",
+                   "preconditioner": args.pc},
+        "per_decomposition": {f: {"dofs": tot[f][0], "solve_s": round(tot[f][1], 4),
+                                  "value": tot[f][0] / tot[f][1]} for f in forms},
+        "full_over_split_time": d_full[1] / d_paper[1],
+        "roofline": {"kernel": f"additive apply_P, full vertex stars ({big['space']}{big['p']}): patch and coarse "
+                               "inverse streams", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None, "bytes_per_launch": nbytes,
+                     "launch_us": t_add * 1e6},
+        "per_problem": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(pc="hybrid"):
     """The oracle, as it stands, on a bounded sample of the workload: the
     H(grad) p=4 and H(curl) p=3 problems of the sweep (same mesh and load
@@ -438,6 +532,8 @@ def main():
         return mixed(args)
     if args.workload == "batch":
         return batch_workload(args)
+    if args.workload == "decompositions":
+        return decompositions(args)
     import torch
     from paper_2506_17406_amd import rz
     from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
