@@ -29,6 +29,18 @@ The vertex-star comparators of Sec. 6.1 (decomposition="vertex" and
     the interior dofs of the cells containing the vertex, and there is no
     Jacobi part (the interior group is empty).
   For H(grad) "vertex" is the default decomposition.
+The other comparators of the paper's tables:
+  - "paper-full": the default decomposition without the split -- the
+    stars also hold the cell interiors (of the kinds the patch keeps) and the
+    Jacobi group is empty: H(grad) PAFW(0)(X^0) (= "vertex-full"), H(curl)
+    PH(X^0, X^{1,I}) (eq:hcurl-decomp without the split), H(div) PAFW(1)(X^2);
+  - "hiptmair" (H(curl) only): the standard Hiptmair-Toselli decomposition
+    PH(X^0_Gamma, X^1_Gamma) + J(X^1_I) (eq:pavarino_hiptmair with the
+    split): vertex-star potentials as above and edge stars of every kind
+    of interface dof;
+  - "hiptmair-full" (H(curl) only): PH(X^0, X^1) (eq:pavarino_hiptmair):
+    the potentials also hold the CG cell interiors (mapped to the Ned type-II
+    cell dofs) and the edge stars every dof of the cells containing the edge.
 
 Hybrid form (HybridSchwarz, Sec. 7.1, eq:generic-subspace-splitting-mult):
 the three groups X_1 = X^k_I (point-Jacobi), X_2 = X^k_Gamma (the additive
@@ -69,32 +81,53 @@ def whitney_dofs(top, k):
     return np.array([top.offset[k] + e * top.N[k] for e in range(top.n_ent[k])], dtype=np.int64)
 
 
-def patch_lists(top, family):
-    """Plain patches: list of ascending global dof arrays."""
+def cells_containing(top, l):
+    """For each entity of dimension l: the cells that contain it."""
+    out = [[] for _ in range(top.n_ent[l])]
+    for c in range(top.n_cells):
+        for e in sorted(set(top.cell_ent[l][c].tolist())):
+            out[e].append(c)
+    return out
+
+
+def patch_lists(top, family, decomposition="paper"):
+    """Plain patches of a decomposition: list of ascending global dof
+    arrays (the H(curl) potentials are separate, potential_patches)."""
+    if decomposition in ("vertex", "vertex-full"):
+        return vertex_star_lists(top, decomposition == "vertex-full")
+    if decomposition not in ("paper", "paper-full", "hiptmair", "hiptmair-full"):
+        raise ValueError(decomposition)
+    if decomposition.startswith("hiptmair") and family != "Ned":
+        raise ValueError("the Hiptmair-Toselli comparators are built for H(curl) only")
+    full = decomposition.endswith("full")
     d = top.d
     out = []
     if family == "CG":
-        edges_of, faces_of = top.vertex_star()
-        for v in range(top.n_vertices):
-            idx = [top.offset[0] + v]
-            for e in edges_of[v]:
-                idx += top.entity_dofs(1, e)
-            for f in faces_of[v]:
-                idx += top.entity_dofs(2, f)
-            out.append(np.array(sorted(idx), dtype=np.int64))
+        return vertex_star_lists(top, full)
     elif family == "Ned":
+        # type-I stars: the edge's Whitney dof and the type-I dofs of the faces
+        # (and cells) containing it; Hiptmair stars: every dof of those
+        typeI = decomposition.startswith("paper")
         faces_of = top.edge_faces()
+        cells_of = cells_containing(top, 1)
         for e in range(top.n_ent[1]):
-            idx = top.entity_dofs(1, e, kinds=("W",))
+            idx = top.entity_dofs(1, e, kinds=("W",) if typeI else None)
             for f in faces_of[e]:
-                idx += top.entity_dofs(2, f, kinds=("I",))
+                idx += top.entity_dofs(2, f, kinds=("I",) if typeI else None)
+            if full:
+                for c in cells_of[e]:
+                    idx += top.entity_dofs(3, c, kinds=("I",) if typeI else None)
             out.append(np.array(sorted(idx), dtype=np.int64))
     elif family == "RT":
         faces_of = top.edge_faces()
+        cells_of = cells_containing(top, 1)
         for e in range(top.n_ent[1]):
             idx = []
             for f in faces_of[e]:
                 idx += top.entity_dofs(2, f)
+            if full:
+                for c in cells_of[e]:
+                    idx += top.entity_dofs(3, c)
             out.append(np.array(sorted(idx), dtype=np.int64))
     else:
         raise ValueError(family)
@@ -126,15 +159,17 @@ def vertex_star_lists(top, full):
     return out
 
 
-DECOMPOSITIONS = ("paper", "vertex", "vertex-full")
+DECOMPOSITIONS = ("paper", "vertex", "vertex-full", "paper-full", "hiptmair", "hiptmair-full")
 
 
-def potential_patches(top, cg_N):
+def potential_patches(top, cg_N, full=False):
     """H(curl) vertex potentials: sparse G_V (n_dofs x n_V) per vertex.
-    cg_N = dofs per entity of the CG_p potential space (vertex, edge, face).
-    Columns: the vertex, then the CG dofs of its edges (ascending edge id,
-    then index), then of its faces."""
+    cg_N = dofs per entity of the CG_p potential space (vertex, edge, face,
+    and cell when full).  Columns: the vertex, then the CG dofs of its edges
+    (ascending edge id, then index), then of its faces, then (full) of its
+    cells."""
     edges_of, faces_of = top.vertex_star()
+    cells_of = cells_containing(top, 0) if full else None
     out = []
     for v in range(top.n_vertices):
         rows, cols, vals = [], [], []
@@ -155,6 +190,12 @@ def potential_patches(top, cg_N):
             assert len(ii) == cg_N[2]
             for j in ii:
                 rows.append(j); cols.append(col); vals.append(1.0); col += 1
+        if full:
+            for c in cells_of[v]:
+                ii = top.entity_dofs(3, c, kinds=("II",))
+                assert len(ii) == cg_N[3]
+                for j in ii:
+                    rows.append(j); cols.append(col); vals.append(1.0); col += 1
         out.append(sp.csc_matrix((vals, (rows, cols)), shape=(top.n_dofs, col)))
     return out
 
@@ -169,22 +210,18 @@ class AdditiveSchwarz:
         self.decomposition = decomposition
         k = {"CG": 0, "Ned": 1, "RT": 2}[family]
         diag = A.diagonal()
-        full = decomposition == "vertex-full"
+        full = decomposition.endswith("full")
         self.I = np.zeros(0, dtype=np.int64) if full else interior_dofs(top)
         self.dI = diag[self.I]
         self.patches = []       # (index array, cho factor)
-        if decomposition == "paper":
-            lists = patch_lists(top, family)
-        else:
-            lists = vertex_star_lists(top, full)
-        for idx in lists:
+        for idx in patch_lists(top, family, decomposition):
             Ap = A[idx][:, idx].toarray()
             self.patches.append((idx, sla.cho_factor(Ap, lower=True)))
         self.potentials = []    # (G_V, cho factor)
-        if family == "Ned" and decomposition == "paper":
+        if family == "Ned" and not decomposition.startswith("vertex"):
             p = top.el.p
-            cg_N = (1, p - 1, (p - 1) * (p - 2) // 2)
-            for G in potential_patches(top, cg_N):
+            cg_N = (1, p - 1, (p - 1) * (p - 2) // 2, (p - 1) * (p - 2) * (p - 3) // 6)
+            for G in potential_patches(top, cg_N, full):
                 Ap = (G.T @ (A @ G)).toarray()
                 self.potentials.append((G, sla.cho_factor(Ap, lower=True)))
         self.W = whitney_dofs(top, k)

@@ -9,11 +9,14 @@
   estimate is within 6% of the printed one (the paper's right-hand side is an
   unspecified random vector).  Dropping the weights, the coarse space, or the
   multiplicative order moves the estimate by far more than that.
-* The vertex-star comparators (tests/golden/paper_vertex_star_level0.csv,
-  the same tables): PAFW(0)(X^k_Gamma) + J(X^k_I) and the full vertex stars
-  PAFW(0)(X^k) for H(grad), H(curl) and H(div), to the same bars.  These
-  pin the star lists (with or without the cell interiors), the empty
-  interior group of the full form and the same weights and sweep.
+* The comparators (tests/golden/paper_vertex_star_level0.csv and
+  paper_comparators_level0.csv, the same tables): PAFW(0)(X^k_Gamma) +
+  J(X^k_I) and the full vertex stars PAFW(0)(X^k) for every space; for
+  H(curl) PH(X^0, X^{1,I}), PH(X^0_Gamma, X^1_Gamma) + J(X^1_I) and
+  PH(X^0, X^1); for H(div) PAFW(1)(X^2) -- to the same bars.  These pin the
+  star lists (with or without the cell interiors, type-I or every kind),
+  the full potentials, the empty interior group of the full forms and the
+  same weights and sweep.
 * Algebra: the sweep is symmetric and positive definite, and its error
   propagator I - B A is the product of the group propagators
   (I - rho_m^{-1} B_m A) in the order 1, 2, 3, 2, 1.
@@ -31,12 +34,13 @@ from oracle.element import element
 from oracle.mesh import Topology
 from oracle.operator import all_cell_matrices, assemble
 from oracle.pcg import lanczos_condest, pcg
-from oracle.precond import (SEED_INTERFACE, SEED_INTERIOR, HybridSchwarz, patch_lists, subspace_extremes,
-                            vertex_star_lists)
+from oracle.precond import (SEED_INTERFACE, SEED_INTERIOR, HybridSchwarz, patch_lists, potential_patches,
+                            subspace_extremes, vertex_star_lists)
 from paper_2506_17406_amd.workloads import kuhn_mesh
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_hybrid_level0.csv")
 GOLDEN_VSTAR = os.path.join(os.path.dirname(__file__), "golden", "paper_vertex_star_level0.csv")
+GOLDEN_COMP = os.path.join(os.path.dirname(__file__), "golden", "paper_comparators_level0.csv")
 
 
 def golden_rows():
@@ -46,8 +50,10 @@ def golden_rows():
 
 
 def golden_vstar_rows():
-    with open(GOLDEN_VSTAR) as f:
-        rows = [r for r in csv.reader(l for l in f if not l.startswith("#"))]
+    rows = []
+    for path in (GOLDEN_VSTAR, GOLDEN_COMP):
+        with open(path) as f:
+            rows += [r for r in csv.reader(l for l in f if not l.startswith("#"))]
     return [(r[0], r[1], int(r[2]), int(r[3]), float(r[4]), int(r[5]), float(r[6])) for r in rows]
 
 
@@ -71,12 +77,12 @@ def test_paper_level0_iterations_and_condest(row):
 
 
 @pytest.mark.parametrize("row", golden_vstar_rows(), ids=lambda r: f"{r[0]}{r[2]}-{r[1]}-alpha{r[4]:g}")
-def test_paper_level0_vertex_star_solvers(row):
+def test_paper_level0_comparator_solvers(row):
     fam, form, p, dofs, alpha, its, cond = row
     top, A = build(fam, p, alpha=alpha)
     assert top.n_dofs == dofs
     H = HybridSchwarz(A, top, fam, decomposition=form)
-    if form == "vertex-full":
+    if form.endswith("full"):
         assert len(H.add.I) == 0 and len(H.Gamma) == top.n_dofs
     b = np.random.default_rng(5).uniform(-1.0, 1.0, top.n_dofs)
     _, info = pcg(lambda v: A @ v, H.apply, b, rtol=1e-8, maxit=300, norm="preconditioned")
@@ -102,8 +108,31 @@ def test_vertex_stars_cover_and_reduce_to_the_default_for_h1():
             assert all(np.array_equal(a, b) for a, b in zip(split, patch_lists(top, "CG")))
 
 
+def test_comparator_lists_nest():
+    """Type-I stars lie inside the every-kind (Hiptmair) stars, split stars
+    inside full ones, and the full forms add only cell-interior dofs; the
+    full potentials add the CG cell interiors as Ned type-II cell dofs."""
+    X, C = kuhn_mesh(2, 3, jitter=0.1, seed=4)
+    p = 4
+    top = Topology(X, C, element(3, "Ned", p))
+    forms = ("paper", "paper-full", "hiptmair", "hiptmair-full")
+    L = {f: patch_lists(top, "Ned", f) for f in forms}
+    for e in range(top.n_ent[1]):
+        a, b, c, d = (set(L[f][e].tolist()) for f in forms)
+        assert a <= b <= d and a <= c <= d
+        assert all(i >= top.offset[3] for i in (b - a) | (d - c))
+    cg_N = (1, p - 1, (p - 1) * (p - 2) // 2, (p - 1) * (p - 2) * (p - 3) // 6)
+    split, full = potential_patches(top, cg_N), potential_patches(top, cg_N, full=True)
+    for v, (Gs, Gf) in enumerate(zip(split, full)):
+        n_cells = sum(1 for c in range(top.n_cells) if v in top.cells[c])
+        assert Gf.shape[1] == Gs.shape[1] + n_cells * cg_N[3]
+        assert abs(Gf[:, :Gs.shape[1]] - Gs).max() == 0
+        assert np.all(Gf[:, Gs.shape[1]:].nonzero()[0] >= top.offset[3])
+
+
 @pytest.mark.parametrize("fam,p,form", [("CG", 4, "paper"), ("Ned", 2, "paper"), ("RT", 2, "paper"),
-                                         ("Ned", 3, "vertex"), ("RT", 3, "vertex-full")])
+                                         ("Ned", 3, "vertex"), ("RT", 3, "vertex-full"),
+                                         ("Ned", 3, "hiptmair-full"), ("RT", 3, "paper-full")])
 def test_sweep_symmetric_positive_and_product_of_propagators(fam, p, form):
     top, A = build(fam, p, n=1, jitter=0.0)
     H = HybridSchwarz(A, top, fam, decomposition=form)
