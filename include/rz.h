@@ -118,8 +118,26 @@ typedef enum { RZ_PC_ADDITIVE = 0, RZ_PC_HYBRID = 1 } rz_pc;
  * containing the vertex, and there is no Jacobi group (the hybrid sweep is
  * stars, W, stars).  Its patches grow like p^d rather than p^(d-1): a patch
  * larger than 2048 dofs (3D: H(grad) p > 8, H(curl) and H(div) p > 5) is
- * RZ_ERR_UNSUPPORTED.  The coarse space W^k is the same in all three. */
-typedef enum { RZ_DECOMP_PAPER = 0, RZ_DECOMP_VERTEX = 1, RZ_DECOMP_VERTEX_FULL = 2 } rz_decomposition;
+ * RZ_ERR_UNSUPPORTED.
+ * RZ_DECOMP_PAPER_FULL: RZ_DECOMP_PAPER without the split -- each star also
+ * holds the dofs (of the kinds it keeps) of the cells containing its centre,
+ * the H(curl) potentials the CG cell interiors, and there is no Jacobi group:
+ * H(grad) PAFW(0)(X^0), H(curl) PH(X^0, X^{1,I}), H(div) PAFW(1)(X^2).
+ * RZ_DECOMP_HIPTMAIR (H(curl) only, else RZ_ERR_UNSUPPORTED): the standard
+ * Hiptmair-Toselli decomposition with the split, PH(X^0_Gamma, X^1_Gamma) +
+ * J(X^1_I) (eq:pavarino_hiptmair): the vertex-star potentials of
+ * RZ_DECOMP_PAPER and edge stars of every kind of interface dof.
+ * RZ_DECOMP_HIPTMAIR_FULL (H(curl) only): PH(X^0, X^1), the same with the
+ * cell interiors and no Jacobi group.
+ * The coarse space W^k is the same in all of them. */
+typedef enum {
+  RZ_DECOMP_PAPER = 0,
+  RZ_DECOMP_VERTEX = 1,
+  RZ_DECOMP_VERTEX_FULL = 2,
+  RZ_DECOMP_PAPER_FULL = 3,
+  RZ_DECOMP_HIPTMAIR = 4,
+  RZ_DECOMP_HIPTMAIR_FULL = 5
+} rz_decomposition;
 
 typedef struct {
   double alpha;           /* coefficient of (d u, d v), >= 0 */
@@ -235,9 +253,10 @@ int rz_numbering(const rz_mesh *mesh, int32_t degree, rz_space space, int64_t *n
 /* Host-only (no device work): the patch lists of the first patch family
  * that rz_setup builds under the given rz_decomposition, in the
  * rz_export_topology layout (ascending dofs per patch; for H(curl) under
- * RZ_DECOMP_PAPER the edge patches).  Pass NULL patch_ptr / patch_dofs to
- * query *n_patches and *n_patch_entries first.  Errors as rz_numbering, and
- * RZ_ERR_ARG for an unknown decomposition. */
+ * the potential-space decompositions the edge patches).  Pass NULL patch_ptr / patch_dofs to
+ * query *n_patches and *n_patch_entries first.  Errors as rz_numbering,
+ * RZ_ERR_ARG for an unknown decomposition, and RZ_ERR_UNSUPPORTED for a
+ * Hiptmair-Toselli decomposition outside H(curl). */
 int rz_patch_lists(const rz_mesh *mesh, int32_t degree, rz_space space, int32_t decomposition, int64_t *n_patches,
                    int64_t *n_patch_entries, int64_t *patch_ptr, int32_t *patch_dofs);
 

@@ -385,7 +385,7 @@ void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
   P.patches = rz::build_patches(P.top, P.el, rz::Decomposition(P.decomp));
   // first dof of the Jacobi group: the interior dofs, or none when the full
   // vertex stars (eq:pafw) hold them
-  P.off_I = P.decomp == RZ_DECOMP_VERTEX_FULL ? P.top.n_dofs : P.top.offset[P.d];
+  P.off_I = rz::decomposition_full(P.decomp) ? P.top.n_dofs : P.top.offset[P.d];
   const int n = P.el.n, Q = P.el.Q, d = P.d;
   // the apply's local order: Whitney dofs of the k-entities first, so the
   // hybrid's coarse correction (nonzero only there) is applied with a
@@ -454,8 +454,10 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     if (opts->pc != RZ_PC_ADDITIVE && opts->pc != RZ_PC_HYBRID) return fail(RZ_ERR_ARG, "unknown preconditioner");
     P->pc = opts->pc;
     P->graphs = opts->eager == 0;
-    if (opts->decomposition < RZ_DECOMP_PAPER || opts->decomposition > RZ_DECOMP_VERTEX_FULL)
+    if (opts->decomposition < RZ_DECOMP_PAPER || opts->decomposition > RZ_DECOMP_HIPTMAIR_FULL)
       return fail(RZ_ERR_ARG, "unknown decomposition");
+    if (opts->decomposition >= RZ_DECOMP_HIPTMAIR && space != RZ_HCURL)
+      return fail(RZ_ERR_UNSUPPORTED, "the Hiptmair-Toselli decompositions are built for H(curl) only");
     P->decomp = opts->decomposition;
   }
   P->fam = space == RZ_HGRAD ? rz::FAM_CG : (space == RZ_HCURL ? rz::FAM_NED : rz::FAM_RT);
@@ -484,7 +486,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     }
     // interior diagonal (Jacobi on X^k_I; an empty group under the full
     // vertex stars)
-    const bool full_stars = P->decomp == RZ_DECOMP_VERTEX_FULL;
+    const bool full_stars = rz::decomposition_full(P->decomp);
     std::vector<int32_t> loc_int;
     for (int i = 0; i < n; ++i)
       if (P->el.dofs[i].entity_dim == d) loc_int.push_back(i);
@@ -1181,7 +1183,9 @@ static int numbering_impl(const rz_mesh *m, int32_t degree, rz_space space, int3
                           int32_t *cell_dofs, int64_t *n_patches, int64_t *n_patch_entries, int64_t *patch_ptr,
                           int32_t *patch_dofs) {
   if (!m || !m->cells) return fail(RZ_ERR_ARG, "null argument");
-  if (dec < RZ_DECOMP_PAPER || dec > RZ_DECOMP_VERTEX_FULL) return fail(RZ_ERR_ARG, "unknown decomposition");
+  if (dec < RZ_DECOMP_PAPER || dec > RZ_DECOMP_HIPTMAIR_FULL) return fail(RZ_ERR_ARG, "unknown decomposition");
+  if (dec >= RZ_DECOMP_HIPTMAIR && space != RZ_HCURL)
+    return fail(RZ_ERR_UNSUPPORTED, "the Hiptmair-Toselli decompositions are built for H(curl) only");
   rz::Family fam;
   if (int e = check_space(m->dim, degree, space, fam)) return e;
   if (m->n_vertices <= 0 || m->n_cells <= 0) return fail(RZ_ERR_ARG, "empty mesh");

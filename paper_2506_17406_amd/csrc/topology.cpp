@@ -230,7 +230,11 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
     for (int32_t g : dofs) cols.push_back({{g, 1.0}});
     return cols;
   };
-  if (dec != DECOMP_PAPER) {
+  const bool full = decomposition_full(dec);
+  const bool hiptmair = dec == DECOMP_HIPTMAIR || dec == DECOMP_HIPTMAIR_FULL;
+  if (hiptmair && el.fam != FAM_NED)
+    throw std::runtime_error("the Hiptmair-Toselli decompositions are built for H(curl) only");
+  if (dec == DECOMP_VERTEX || dec == DECOMP_VERTEX_FULL || el.fam == FAM_CG) {
     // vertex stars (eq:approx-sc-pafw; with the cell interiors, eq:pafw):
     // the entities containing the vertex carry the dofs whose support lies
     // in its star; entity_dofs adds nothing where the space has no dofs
@@ -241,32 +245,25 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
       for (int64_t e : in.v_edges[v]) entity_dofs(t, el, 1, e, -1, dofs);
       if (d == 3)
         for (int64_t f : in.v_faces[v]) entity_dofs(t, el, 2, f, -1, dofs);
-      if (dec == DECOMP_VERTEX_FULL)
+      if (full)
         for (int64_t c : in.v_cells[v]) entity_dofs(t, el, d, c, -1, dofs);
       add_patch(ps, t, el, plain_cols(dofs), in.v_cells[v], mark_col, mark_coef);
     }
     out.push_back(std::move(ps));
     return out;
   }
-  if (el.fam == FAM_CG) {
-    // vertex stars of the interface space X^0_Gamma (eq:approx-sc-pafw)
-    PatchSet ps = empty_set();
-    for (int64_t v = 0; v < t.n_vertices; ++v) {
-      std::vector<int32_t> dofs;
-      entity_dofs(t, el, 0, v, -1, dofs);
-      for (int64_t e : in.v_edges[v]) entity_dofs(t, el, 1, e, -1, dofs);
-      if (d == 3)
-        for (int64_t f : in.v_faces[v]) entity_dofs(t, el, 2, f, -1, dofs);
-      add_patch(ps, t, el, plain_cols(dofs), in.v_cells[v], mark_col, mark_coef);
-    }
-    out.push_back(std::move(ps));
-  } else if (el.fam == FAM_NED) {
-    // edge stars of the type-I interface space X^{1,I}_Gamma (eq:hcurl-decomp)
+  if (el.fam == FAM_NED) {
+    // edge stars of the type-I interface space X^{1,I}_Gamma (eq:hcurl-decomp),
+    // or of every kind of dof (eq:pavarino_hiptmair); the full forms add the
+    // dofs of those kinds of the cells containing the edge
+    const int kw = hiptmair ? -1 : KIND_W, ki = hiptmair ? -1 : KIND_I;
     PatchSet pe = empty_set();
     for (int64_t e = 0; e < t.n_ent[1]; ++e) {
       std::vector<int32_t> dofs;
-      entity_dofs(t, el, 1, e, KIND_W, dofs);
-      for (int64_t f : in.e_faces[e]) entity_dofs(t, el, 2, f, KIND_I, dofs);
+      entity_dofs(t, el, 1, e, kw, dofs);
+      for (int64_t f : in.e_faces[e]) entity_dofs(t, el, 2, f, ki, dofs);
+      if (full)
+        for (int64_t c : in.e_cells[e]) entity_dofs(t, el, 3, c, ki, dofs);
       add_patch(pe, t, el, plain_cols(dofs), in.e_cells[e], mark_col, mark_coef);
     }
     out.push_back(std::move(pe));
@@ -292,15 +289,23 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
         entity_dofs(t, el, 2, f, KIND_II, ii);
         for (int32_t g : ii) cols.push_back({{g, 1.0}});
       }
+      if (full)  // the CG cell interiors: the Ned type-II cell dofs
+        for (int64_t c : in.v_cells[v]) {
+          std::vector<int32_t> ii;
+          entity_dofs(t, el, 3, c, KIND_II, ii);
+          for (int32_t g : ii) cols.push_back({{g, 1.0}});
+        }
       add_patch(pv, t, el, cols, in.v_cells[v], mark_col, mark_coef);
     }
     out.push_back(std::move(pv));
   } else if (el.fam == FAM_RT) {
-    // edge stars of X^2_Gamma (eq:hdiv-decomp)
+    // edge stars of X^2_Gamma (eq:hdiv-decomp); full: PAFW(1)(X^2)
     PatchSet ps = empty_set();
     for (int64_t e = 0; e < t.n_ent[1]; ++e) {
       std::vector<int32_t> dofs;
       for (int64_t f : in.e_faces[e]) entity_dofs(t, el, 2, f, -1, dofs);
+      if (full)
+        for (int64_t c : in.e_cells[e]) entity_dofs(t, el, 3, c, -1, dofs);
       add_patch(ps, t, el, plain_cols(dofs), in.e_cells[e], mark_col, mark_coef);
     }
     out.push_back(std::move(ps));

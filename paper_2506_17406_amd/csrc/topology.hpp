@@ -51,7 +51,26 @@ struct PatchSet {
 //  per vertex, the dofs of the vertex and of the edges and faces containing it.
 //  DECOMP_VERTEX_FULL: PAFW(0)(X^k) (eq:pafw): those vertex stars together
 //  with the interior dofs of the cells containing the vertex.
-enum Decomposition { DECOMP_PAPER = 0, DECOMP_VERTEX = 1, DECOMP_VERTEX_FULL = 2 };
+//  DECOMP_PAPER_FULL: DECOMP_PAPER without the split -- every star also
+//  holds the dofs (of the kinds it keeps) of the cells containing its centre,
+//  and the H(curl) potentials the CG cell interiors: H(grad) PAFW(0)(X^0),
+//  H(curl) PH(X^0, X^{1,I}), H(div) PAFW(1)(X^2).
+//  DECOMP_HIPTMAIR (H(curl) only): PH(X^0_Gamma, X^1_Gamma)
+//  (eq:pavarino_hiptmair with the split): the DECOMP_PAPER potentials and
+//  edge stars of every kind of interface dof; DECOMP_HIPTMAIR_FULL:
+//  PH(X^0, X^1), the same with the cell interiors.
+enum Decomposition {
+  DECOMP_PAPER = 0,
+  DECOMP_VERTEX = 1,
+  DECOMP_VERTEX_FULL = 2,
+  DECOMP_PAPER_FULL = 3,
+  DECOMP_HIPTMAIR = 4,
+  DECOMP_HIPTMAIR_FULL = 5
+};
+// whether the decomposition keeps no interior-interface split (no Jacobi group)
+inline bool decomposition_full(int dec) {
+  return dec == DECOMP_VERTEX_FULL || dec == DECOMP_PAPER_FULL || dec == DECOMP_HIPTMAIR_FULL;
+}
 std::vector<PatchSet> build_patches(const Topology &top, const RefElement &el, Decomposition dec = DECOMP_PAPER);
 
 // Whitney dofs (one per k-subsimplex, lem:basis-contains-whitney), ascending,

@@ -30,7 +30,10 @@ PRECISIONS = {"fp64": RZ_FP64, "fp32-ir": RZ_FP32_IR, "fp32-pc": RZ_FP32_PC, "bf
 RZ_PC_ADDITIVE, RZ_PC_HYBRID = 0, 1
 PCS = {"additive": RZ_PC_ADDITIVE, "hybrid": RZ_PC_HYBRID}
 RZ_DECOMP_PAPER, RZ_DECOMP_VERTEX, RZ_DECOMP_VERTEX_FULL = 0, 1, 2
-DECOMPOSITIONS = {"paper": RZ_DECOMP_PAPER, "vertex": RZ_DECOMP_VERTEX, "vertex-full": RZ_DECOMP_VERTEX_FULL}
+RZ_DECOMP_PAPER_FULL, RZ_DECOMP_HIPTMAIR, RZ_DECOMP_HIPTMAIR_FULL = 3, 4, 5
+DECOMPOSITIONS = {"paper": RZ_DECOMP_PAPER, "vertex": RZ_DECOMP_VERTEX, "vertex-full": RZ_DECOMP_VERTEX_FULL,
+                  "paper-full": RZ_DECOMP_PAPER_FULL, "hiptmair": RZ_DECOMP_HIPTMAIR,
+                  "hiptmair-full": RZ_DECOMP_HIPTMAIR_FULL}
 
 
 class RzOptions(ctypes.Structure):

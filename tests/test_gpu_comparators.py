@@ -1,7 +1,11 @@
-"""GPU parity of the vertex-star comparators (Sec. 6.1) against the oracle,
-through the C ABI: PAFW(0)(X^k_Gamma) + J(X^k_I) ("vertex") and the full
-vertex stars PAFW(0)(X^k) ("vertex-full"), for every space, in the additive
-and the symmetric multiplicative hybrid form.
+"""GPU parity of the comparator decompositions of Sec. 6 against the
+oracle, through the C ABI, in the additive and the symmetric multiplicative
+hybrid form: PAFW(0)(X^k_Gamma) + J(X^k_I) ("vertex") and the full vertex
+stars PAFW(0)(X^k) ("vertex-full") for every space; the default
+decompositions without the split ("paper-full": H(curl) PH(X^0, X^{1,I}),
+H(div) PAFW(1)(X^2)); the standard Hiptmair-Toselli decompositions of
+H(curl) PH(X^0_Gamma, X^1_Gamma) + J ("hiptmair") and PH(X^0, X^1)
+("hiptmair-full").
 
 Sizes: meshes of 6-162 cells, degrees 2-8, seeded jitter and load vectors;
 the largest full stars near the 2048-dof patch limit (H(grad) p = 8: 1695,
@@ -13,7 +17,8 @@ Bars, as for the default decompositions:
 * apply_P -- max |z_gpu - z_oracle| <= 1e-10 max |z_oracle|;
 * solve   -- iteration counts within one, true residual under the oracle's A
              <= 1e-10, ||x_gpu - x_oracle|| <= 1e-10 ||x_oracle|| at rtol 1e-12.
-A full star above 2048 dofs is refused with RZ_ERR_UNSUPPORTED at setup.
+A full star above 2048 dofs is refused with RZ_ERR_UNSUPPORTED at setup,
+and so are the Hiptmair-Toselli forms outside H(curl) (before device work).
 """
 import numpy as np
 import pytest
@@ -36,7 +41,12 @@ CASES = [(3, "CG", 4, 2, 0.1), (3, "Ned", 3, 2, 0.1), (3, "Ned", 4, 2, 0.1), (3,
          (3, "Ned", 2, 2, 0.1), (3, "CG", 5, 1, 0.0), (3, "RT", 3, 0, 0.0),
          # the largest full stars below the patch limit
          (3, "CG", 8, 2, 0.1), (3, "Ned", 5, 2, 0.1), (3, "RT", 5, 2, 0.1)]
-FORMS = ["vertex", "vertex-full"]
+OTHER = [(3, "Ned", 3, 2, 0.1), (3, "Ned", 4, 2, 0.1), (3, "Ned", 2, 2, 0.1), (3, "Ned", 3, 0, 0.0),
+         (3, "Ned", 6, 2, 0.1)]
+SETS = ([(c, f) for f in ("vertex", "vertex-full") for c in CASES] +
+        [(c, "paper-full") for c in [(3, "CG", 4, 2, 0.1), (2, "CG", 4, 3, 0.1), (3, "RT", 4, 2, 0.1),
+                                     (3, "RT", 3, 0, 0.0), (3, "RT", 6, 2, 0.1)] + OTHER] +
+        [(c, f) for f in ("hiptmair", "hiptmair-full") for c in OTHER])
 PCS = ["additive", "hybrid"]
 _cache = {}
 
@@ -65,19 +75,20 @@ def setup_case(d, fam, p, n, jit, form, pc):
     return _cache[key]
 
 
-def ids(c):
-    return "{}d-{}{}-n{}".format(*c[:4]) if c[3] else "{}d-{}{}-tet".format(*c[:3])
+def ids(v):
+    c, f = v
+    return ("{}d-{}{}-n{}".format(*c[:4]) if c[3] else "{}d-{}{}-tet".format(*c[:3])) + "-" + f
 
 
 @pytest.mark.parametrize("pc", PCS)
-@pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("case", CASES, ids=ids)
-def test_apply_P(case, form, pc):
+@pytest.mark.parametrize("cf", SETS, ids=ids)
+def test_apply_P(cf, pc):
+    case, form = cf
     top, A, P, prob = setup_case(*case, form, pc)
     if pc == "hybrid":
         rho = prob.pc_weights()
         assert abs(rho[0] / P.rho_I - 1) <= 1e-10 and abs(rho[1] / P.rho_Gamma - 1) <= 1e-10 and rho[2] == 1.0
-        if form == "vertex-full":
+        if form.endswith("full"):
             assert rho[0] == 1.0
     r = load_vectors(top.n_dofs, 16)[:, 0]
     zt = torch.empty(top.n_dofs, dtype=torch.float64, device="cuda")
@@ -88,9 +99,9 @@ def test_apply_P(case, form, pc):
 
 
 @pytest.mark.parametrize("pc", PCS)
-@pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("case", CASES, ids=ids)
-def test_solve(case, form, pc):
+@pytest.mark.parametrize("cf", SETS, ids=ids)
+def test_solve(cf, pc):
+    case, form = cf
     top, A, P, prob = setup_case(*case, form, pc)
     b = load_vectors(top.n_dofs, 17)[:, 0]
     bt = torch.from_numpy(b).cuda()

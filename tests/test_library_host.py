@@ -80,7 +80,7 @@ def test_setup_rejects_before_device_work():
     opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 3, 0)           # unknown preconditioner form
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
     assert b"preconditioner" in rz.lib.rz_last_error()
-    opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 1, 0, 3)        # unknown decomposition
+    opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 1, 0, 7)        # unknown decomposition
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
     assert b"decomposition" in rz.lib.rz_last_error()
     assert rz.lib.rz_setup(None, 2, 0, None, None, ctypes.byref(h)) == -1
@@ -152,4 +152,37 @@ def test_vertex_star_lists_bit_exact(d, fam, p, n, form):
         _, _, ptr1, dofs1 = rz.numbering(X, C, p, fam, top.el.n)
         assert np.array_equal(ptr0, ptr1) and np.array_equal(dofs0, dofs1)
     with pytest.raises(rz.RzError):
-        rz.patch_lists(X, C, p, fam, 5)
+        rz.patch_lists(X, C, p, fam, 9)
+
+
+COMP_CASES = [(3, "CG", 4, 2, "paper-full"), (2, "CG", 4, 3, "paper-full"), (3, "Ned", 4, 2, "paper-full"),
+              (3, "Ned", 4, 2, "hiptmair"), (3, "Ned", 4, 2, "hiptmair-full"), (3, "Ned", 2, 2, "hiptmair-full"),
+              (3, "RT", 4, 2, "paper-full")]
+
+
+@pytest.mark.parametrize("d,fam,p,n,form", COMP_CASES, ids=lambda v: str(v))
+def test_comparator_lists_bit_exact(d, fam, p, n, form):
+    X, C = kuhn_mesh(n, d, jitter=0.1, seed=7)
+    rng = np.random.default_rng(12)
+    C = C[rng.permutation(len(C))]
+    C = np.array([row[rng.permutation(d + 1)] for row in C])
+    top = Topology(X, C, element(d, fam, p))
+    ptr, dofs = rz.patch_lists(X, C, p, fam, form)
+    pl = patch_lists(top, fam, form)
+    assert len(ptr) - 1 == len(pl)
+    for i, idx in enumerate(pl):
+        assert np.array_equal(dofs[ptr[i]:ptr[i + 1]], idx)
+
+
+def test_hiptmair_only_for_hcurl():
+    X, C = kuhn_mesh(1, 3)
+    for fam in ("CG", "RT"):
+        for form in ("hiptmair", "hiptmair-full"):
+            with pytest.raises(rz.RzError) as e:
+                rz.patch_lists(X, C, 2, fam, form)
+            assert e.value.code == -2
+    m, keep = rz._mesh(X, C)
+    h = ctypes.c_void_p()
+    opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 1, 0, 4)
+    assert rz.lib.rz_setup(ctypes.byref(m), 2, 2, ctypes.byref(opts), None, ctypes.byref(h)) == -2
+    assert b"H(curl)" in rz.lib.rz_last_error()
