@@ -401,9 +401,11 @@ def batch_workload(args):
 def decompositions(args):
     """The space decompositions of Sec. 6 side by side on the sweep's mesh
     (jittered 8^3x6, mesh seed 2, load seed 3), FP64 PCG to 1e-10: the
-    default split solvers, the vertex-star split PAFW(0)(X^k_Gamma)+J, and
-    the full vertex stars PAFW(0)(X^k).  Per problem: setup, iterations,
-    solve time, patch sizes.  Roofline: the additive full-star
+    default split solvers, the vertex-star split PAFW(0)(X^k_Gamma)+J, the
+    full vertex stars PAFW(0)(X^k), the defaults without the split
+    (H(curl) PH(X^0, X^{1,I}), H(div) PAFW(1)(X^2)) and, for H(curl), the
+    standard Hiptmair-Toselli PH(X^0_Gamma, X^1_Gamma)+J and PH(X^0, X^1).
+    Per problem: setup, iterations, solve time, patch sizes.  Roofline: the additive full-star
     preconditioner apply of the largest problem, an HBM stream of the packed
     patch and coarse inverses."""
     import torch
@@ -414,16 +416,19 @@ def decompositions(args):
     X, C = kuhn_mesh(args.n, 3, jitter=0.1, seed=2)
     spaces = args.spaces.split(",")
     degrees = [4, 5] if args.degrees == "3,4,5,6,7,8" else [int(p) for p in args.degrees.split(",")]
-    forms = ["paper", "vertex", "vertex-full"]
+    forms_of = {"CG": ["paper", "vertex", "vertex-full"],
+                "Ned": ["paper", "paper-full", "hiptmair", "hiptmair-full", "vertex", "vertex-full"],
+                "RT": ["paper", "paper-full", "vertex", "vertex-full"]}
+    forms = ["paper", "vertex", "vertex-full", "paper-full", "hiptmair", "hiptmair-full"]
     # Whitney (coarse) dof counts: vertices, edges or faces of the mesh
     Cs = np.sort(C, axis=1)
     n_sub = {0: X.shape[0],
              1: len(np.unique(Cs[:, [[0, 1], [0, 2], [0, 3], [1, 2], [1, 3], [2, 3]]].reshape(-1, 2), axis=0)),
              2: len(np.unique(Cs[:, [[0, 1, 2], [0, 1, 3], [0, 2, 3], [1, 2, 3]]].reshape(-1, 3), axis=0))}
-    rows, tot = [], {f: [0, 0.0] for f in forms}
+    rows, tot = [], {f: [0, 0.0, []] for f in forms}
     for fam in spaces:
         for p in degrees:
-            for form in forms:
+            for form in forms_of[fam]:
                 t0 = time.perf_counter()
                 prob = rz.Problem(X, C, p, fam, pc=args.pc, decomposition=form)
                 torch.cuda.synchronize()
@@ -450,6 +455,8 @@ def decompositions(args):
                                  patch_mb=round(float((m * (m + 1) // 2).sum()) * 8 / 1e6, 1)))
                 tot[form][0] += prob.n_dofs
                 tot[form][1] += dt
+                if fam not in tot[form][2]:
+                    tot[form][2].append(fam)
                 print(f"{fam}{p} {form}: {prob.n_dofs} dofs, setup {t_set:.2f}s, {info['iterations']} its, "
                       f"{dt * 1e3:.1f} ms, apply_P {t_p * 1e6:.0f} us, max patch {m.max()}", file=sys.stderr,
                       flush=True)
@@ -478,8 +485,8 @@ def decompositions(args):
                                f"jittered Kuhn {args.n}^3x6 mesh, rtol 1e-10, {args.pc} preconditioner; value is the "
                                "default split solvers, the comparators beside it",
                    "preconditioner": args.pc},
-        "per_decomposition": {f: {"dofs": tot[f][0], "solve_s": round(tot[f][1], 4),
-                                  "value": tot[f][0] / tot[f][1]} for f in forms},
+        "per_decomposition": {f: {"spaces": tot[f][2], "dofs": tot[f][0], "solve_s": round(tot[f][1], 4),
+                                  "value": tot[f][0] / tot[f][1]} for f in forms if tot[f][0]},
         "full_over_split_time": d_full[1] / d_paper[1],
         "roofline": {"kernel": f"additive apply_P, full vertex stars ({big['space']}{big['p']}): patch and coarse "
                                "inverse streams", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
