@@ -40,7 +40,16 @@ The other comparators of the paper's tables:
     of interface dof;
   - "hiptmair-full" (H(curl) only): PH(X^0, X^1) (eq:pavarino_hiptmair):
     the potentials also hold the CG cell interiors (mapped to the Ned type-II
-    cell dofs) and the edge stars every dof of the cells containing the edge.
+    cell dofs) and the edge stars every dof of the cells containing the edge;
+  - "typeI" / "typeI-full" (H(curl), H(div)): the type-I Hiptmair-Toselli
+    decomposition PH(X^{k-1,I}, X^{k,I}) (eq:pavarino_hiptmair-novel) with
+    and without the split.  For H(curl) these are "paper" / "paper-full".
+    For H(div) the split form is eq:hdiv-ph-reduced: W^2 + J(X^2_I) + edge-
+    star potentials curl X^{1,I}_Gamma|star E, with no face stars (the type-I
+    interface space is W^2).  The full form adds to each potential the curls
+    of the NedTwo type-I functions of the cells containing the edge, and the
+    face stars X^{2,I}|star F (the Whitney dof of the face and the type-I
+    dofs of its cells), and drops the Jacobi group.
 
 Hybrid form (HybridSchwarz, Sec. 7.1, eq:generic-subspace-splitting-mult):
 the three groups X_1 = X^k_I (point-Jacobi), X_2 = X^k_Gamma (the additive
@@ -90,13 +99,62 @@ def cells_containing(top, l):
     return out
 
 
+def face_stars_typeI(top):
+    """Face stars of the type-I space X^{2,I}|star F: the Whitney dof of the
+    face and the type-I dofs of the cells containing it (H(div))."""
+    cells_of = cells_containing(top, 2)
+    out = []
+    for f in range(top.n_ent[2]):
+        idx = top.entity_dofs(2, f, kinds=("W",))
+        for c in cells_of[f]:
+            idx += top.entity_dofs(3, c, kinds=("I",))
+        out.append(np.array(sorted(idx), dtype=np.int64))
+    return out
+
+
+def curl_potential_patches(top, full=False):
+    """H(div) edge-star potentials curl X^{1,I}|star E as sparse G_E
+    (n_dofs x n_E) in RT coefficients.  Column 0 is the curl of the Whitney
+    edge function: by Stokes' theorem the sum over the faces F containing E
+    of s phi^W_F, with s = -1 if E is the edge (a, c) of F = (a, b, c)
+    (ascending) and +1 otherwise (tangents and normals from sorted vertices;
+    the basis holds the Whitney forms, lem:basis-contains-whitney).  Then the
+    RT type-II dofs of the faces (and, full, of the cells) containing E: the
+    curls of the NedTwo type-I functions of the same entity and index
+    (lem:d-preserves-basis-functions)."""
+    faces_of = top.edge_faces()
+    cells_of = cells_containing(top, 1) if full else None
+    out = []
+    for e, (a0, b0) in enumerate(top.ent_tuples[1]):
+        rows, cols, vals = [], [], []
+        for f in faces_of[e]:
+            a, b, c = top.ent_tuples[2][f]
+            rows.append(top.entity_dofs(2, f, kinds=("W",))[0])
+            cols.append(0)
+            vals.append(-1.0 if (a0, b0) == (a, c) else 1.0)
+        col = 1
+        ents = [(2, f) for f in faces_of[e]] + ([(3, c) for c in cells_of[e]] if full else [])
+        for l, ent in ents:
+            for j in top.entity_dofs(l, ent, kinds=("II",)):
+                rows.append(j); cols.append(col); vals.append(1.0); col += 1
+        out.append(sp.csc_matrix((vals, (rows, cols)), shape=(top.n_dofs, col)))
+    return out
+
+
 def patch_lists(top, family, decomposition="paper"):
     """Plain patches of a decomposition: list of ascending global dof
-    arrays (the H(curl) potentials are separate, potential_patches)."""
+    arrays (the potentials are separate: potential_patches,
+    curl_potential_patches)."""
     if decomposition in ("vertex", "vertex-full"):
         return vertex_star_lists(top, decomposition == "vertex-full")
-    if decomposition not in ("paper", "paper-full", "hiptmair", "hiptmair-full"):
+    if decomposition not in DECOMPOSITIONS:
         raise ValueError(decomposition)
+    if decomposition.startswith("typeI"):
+        if family == "CG":
+            raise ValueError("the type-I Hiptmair-Toselli decompositions need k >= 1")
+        if family == "RT":
+            return face_stars_typeI(top) if decomposition == "typeI-full" else []
+        decomposition = decomposition.replace("typeI", "paper")
     if decomposition.startswith("hiptmair") and family != "Ned":
         raise ValueError("the Hiptmair-Toselli comparators are built for H(curl) only")
     full = decomposition.endswith("full")
@@ -159,7 +217,7 @@ def vertex_star_lists(top, full):
     return out
 
 
-DECOMPOSITIONS = ("paper", "vertex", "vertex-full", "paper-full", "hiptmair", "hiptmair-full")
+DECOMPOSITIONS = ("paper", "vertex", "vertex-full", "paper-full", "hiptmair", "hiptmair-full", "typeI", "typeI-full")
 
 
 def potential_patches(top, cg_N, full=False):
@@ -222,6 +280,10 @@ class AdditiveSchwarz:
             p = top.el.p
             cg_N = (1, p - 1, (p - 1) * (p - 2) // 2, (p - 1) * (p - 2) * (p - 3) // 6)
             for G in potential_patches(top, cg_N, full):
+                Ap = (G.T @ (A @ G)).toarray()
+                self.potentials.append((G, sla.cho_factor(Ap, lower=True)))
+        if family == "RT" and decomposition.startswith("typeI"):
+            for G in curl_potential_patches(top, full):
                 Ap = (G.T @ (A @ G)).toarray()
                 self.potentials.append((G, sla.cho_factor(Ap, lower=True)))
         self.W = whitney_dofs(top, k)

@@ -13,7 +13,8 @@
   paper_comparators_level0.csv, the same tables): PAFW(0)(X^k_Gamma) +
   J(X^k_I) and the full vertex stars PAFW(0)(X^k) for every space; for
   H(curl) PH(X^0, X^{1,I}), PH(X^0_Gamma, X^1_Gamma) + J(X^1_I) and
-  PH(X^0, X^1); for H(div) PAFW(1)(X^2) -- to the same bars.  These pin the
+  PH(X^0, X^1); for H(div) PAFW(1)(X^2), PH(X^{1,I}_Gamma, X^{2,I}_Gamma) +
+  J(X^2_I) and PH(X^{1,I}, X^{2,I}) -- to the same bars.  These pin the
   star lists (with or without the cell interiors, type-I or every kind),
   the full potentials, the empty interior group of the full forms and the
   same weights and sweep.
@@ -34,8 +35,8 @@ from oracle.element import element
 from oracle.mesh import Topology
 from oracle.operator import all_cell_matrices, assemble
 from oracle.pcg import lanczos_condest, pcg
-from oracle.precond import (SEED_INTERFACE, SEED_INTERIOR, HybridSchwarz, patch_lists, potential_patches,
-                            subspace_extremes, vertex_star_lists)
+from oracle.precond import (SEED_INTERFACE, SEED_INTERIOR, HybridSchwarz, curl_potential_patches, patch_lists,
+                            potential_patches, subspace_extremes, vertex_star_lists)
 from paper_2506_17406_amd.workloads import kuhn_mesh
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_hybrid_level0.csv")
@@ -130,9 +131,30 @@ def test_comparator_lists_nest():
         assert np.all(Gf[:, Gs.shape[1]:].nonzero()[0] >= top.offset[3])
 
 
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_curl_potentials_are_divergence_free(p):
+    """The H(div) type-I potential columns are curls: div-div stiffness times
+    every column vanishes (a wrong orientation sign or a non-curl column
+    would not), and the Whitney column has unit fluxes on the (two or more)
+    faces containing the edge."""
+    X, C = kuhn_mesh(2, 3, jitter=0.1, seed=5)
+    top = Topology(X, C, element(3, "RT", p))
+    K = assemble(top, all_cell_matrices(top.el, top, alpha=1.0, beta=0.0))
+    M = assemble(top, all_cell_matrices(top.el, top, alpha=0.0, beta=1.0))
+    for full in (False, True):
+        for G in curl_potential_patches(top, full):
+            KG = (K @ G).toarray()
+            assert abs(KG).max() <= 1e-11 * abs(K).max()
+            assert (G.T @ M @ G).diagonal().min() > 0
+            w = G[:, 0].toarray().ravel()
+            w = w[w != 0]
+            assert len(w) >= 2 and np.all(np.abs(w) == 1.0)
+
+
 @pytest.mark.parametrize("fam,p,form", [("CG", 4, "paper"), ("Ned", 2, "paper"), ("RT", 2, "paper"),
                                          ("Ned", 3, "vertex"), ("RT", 3, "vertex-full"),
-                                         ("Ned", 3, "hiptmair-full"), ("RT", 3, "paper-full")])
+                                         ("Ned", 3, "hiptmair-full"), ("RT", 3, "paper-full"),
+                                         ("RT", 3, "typeI"), ("RT", 3, "typeI-full")])
 def test_sweep_symmetric_positive_and_product_of_propagators(fam, p, form):
     top, A = build(fam, p, n=1, jitter=0.0)
     H = HybridSchwarz(A, top, fam, decomposition=form)
