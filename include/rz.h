@@ -129,6 +129,17 @@ typedef enum { RZ_PC_ADDITIVE = 0, RZ_PC_HYBRID = 1 } rz_pc;
  * RZ_DECOMP_PAPER and edge stars of every kind of interface dof.
  * RZ_DECOMP_HIPTMAIR_FULL (H(curl) only): PH(X^0, X^1), the same with the
  * cell interiors and no Jacobi group.
+ * RZ_DECOMP_TYPEI / RZ_DECOMP_TYPEI_FULL (H(curl) and H(div), else
+ * RZ_ERR_UNSUPPORTED): the type-I Hiptmair-Toselli decomposition
+ * PH(X^{k-1,I}, X^{k,I}) (eq:pavarino_hiptmair-novel) with / without the
+ * split.  For H(curl) these equal RZ_DECOMP_PAPER / RZ_DECOMP_PAPER_FULL.
+ * For H(div), split (eq:hdiv-ph-reduced): W^2 + J(X^2_I) + edge-star
+ * potentials curl X^{1,I}_Gamma|star E -- the curl of the Whitney edge
+ * function (signed face Whitney dofs) and the RT type-II dofs of the faces
+ * containing the edge; full: the potentials also hold the RT type-II dofs of
+ * the cells containing the edge, there are face stars X^{2,I}|star F (the
+ * face's Whitney dof and the type-I dofs of its two cells), and no Jacobi
+ * group.
  * The coarse space W^k is the same in all of them. */
 typedef enum {
   RZ_DECOMP_PAPER = 0,
@@ -136,7 +147,9 @@ typedef enum {
   RZ_DECOMP_VERTEX_FULL = 2,
   RZ_DECOMP_PAPER_FULL = 3,
   RZ_DECOMP_HIPTMAIR = 4,
-  RZ_DECOMP_HIPTMAIR_FULL = 5
+  RZ_DECOMP_HIPTMAIR_FULL = 5,
+  RZ_DECOMP_TYPEI = 6,
+  RZ_DECOMP_TYPEI_FULL = 7
 } rz_decomposition;
 
 typedef struct {
@@ -256,7 +269,9 @@ int rz_numbering(const rz_mesh *mesh, int32_t degree, rz_space space, int64_t *n
  * the potential-space decompositions the edge patches).  Pass NULL patch_ptr / patch_dofs to
  * query *n_patches and *n_patch_entries first.  Errors as rz_numbering,
  * RZ_ERR_ARG for an unknown decomposition, and RZ_ERR_UNSUPPORTED for a
- * Hiptmair-Toselli decomposition outside H(curl). */
+ * decomposition not built for the space.  Under RZ_DECOMP_TYPEI for H(div)
+ * the first family is the potentials: each patch lists the dofs its columns
+ * combine, column by column. */
 int rz_patch_lists(const rz_mesh *mesh, int32_t degree, rz_space space, int32_t decomposition, int64_t *n_patches,
                    int64_t *n_patch_entries, int64_t *patch_ptr, int32_t *patch_dofs);
 

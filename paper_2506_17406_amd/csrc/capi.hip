@@ -426,6 +426,16 @@ void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
 static void ensure_ws(rz_problem *P, int ncol);
 static void estimate_weights(rz_problem *P, hipStream_t s);
 
+// rz_decomposition values and the spaces they are built for
+static int check_decomposition(int32_t dec, int space) {
+  if (dec < RZ_DECOMP_PAPER || dec > RZ_DECOMP_TYPEI_FULL) return fail(RZ_ERR_ARG, "unknown decomposition");
+  if ((dec == RZ_DECOMP_HIPTMAIR || dec == RZ_DECOMP_HIPTMAIR_FULL) && space != RZ_HCURL)
+    return fail(RZ_ERR_UNSUPPORTED, "the standard Hiptmair-Toselli decompositions are built for H(curl) only");
+  if ((dec == RZ_DECOMP_TYPEI || dec == RZ_DECOMP_TYPEI_FULL) && space == RZ_HGRAD)
+    return fail(RZ_ERR_UNSUPPORTED, "the type-I Hiptmair-Toselli decompositions need H(curl) or H(div)");
+  return RZ_OK;
+}
+
 extern "C" {
 
 const char *rz_last_error(void) { return g_err.c_str(); }
@@ -454,10 +464,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     if (opts->pc != RZ_PC_ADDITIVE && opts->pc != RZ_PC_HYBRID) return fail(RZ_ERR_ARG, "unknown preconditioner");
     P->pc = opts->pc;
     P->graphs = opts->eager == 0;
-    if (opts->decomposition < RZ_DECOMP_PAPER || opts->decomposition > RZ_DECOMP_HIPTMAIR_FULL)
-      return fail(RZ_ERR_ARG, "unknown decomposition");
-    if (opts->decomposition >= RZ_DECOMP_HIPTMAIR && space != RZ_HCURL)
-      return fail(RZ_ERR_UNSUPPORTED, "the Hiptmair-Toselli decompositions are built for H(curl) only");
+    if (int e = check_decomposition(opts->decomposition, space)) return e;
     P->decomp = opts->decomposition;
   }
   P->fam = space == RZ_HGRAD ? rz::FAM_CG : (space == RZ_HCURL ? rz::FAM_NED : rz::FAM_RT);
@@ -1183,9 +1190,7 @@ static int numbering_impl(const rz_mesh *m, int32_t degree, rz_space space, int3
                           int32_t *cell_dofs, int64_t *n_patches, int64_t *n_patch_entries, int64_t *patch_ptr,
                           int32_t *patch_dofs) {
   if (!m || !m->cells) return fail(RZ_ERR_ARG, "null argument");
-  if (dec < RZ_DECOMP_PAPER || dec > RZ_DECOMP_HIPTMAIR_FULL) return fail(RZ_ERR_ARG, "unknown decomposition");
-  if (dec >= RZ_DECOMP_HIPTMAIR && space != RZ_HCURL)
-    return fail(RZ_ERR_UNSUPPORTED, "the Hiptmair-Toselli decompositions are built for H(curl) only");
+  if (int e = check_decomposition(dec, space)) return e;
   rz::Family fam;
   if (int e = check_space(m->dim, degree, space, fam)) return e;
   if (m->n_vertices <= 0 || m->n_cells <= 0) return fail(RZ_ERR_ARG, "empty mesh");

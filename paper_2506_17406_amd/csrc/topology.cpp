@@ -134,7 +134,7 @@ void entity_dofs(const Topology &t, const RefElement &el, int l, int64_t e, int 
 }
 
 struct Incidence {
-  std::vector<std::vector<int64_t>> v_edges, v_faces, v_cells, e_faces, e_cells;
+  std::vector<std::vector<int64_t>> v_edges, v_faces, v_cells, e_faces, e_cells, f_cells;
 };
 
 Incidence incidence(const Topology &t) {
@@ -168,6 +168,9 @@ Incidence incidence(const Topology &t) {
     }
     for (int64_t c = 0; c < t.n_cells; ++c)
       for (int s = 0; s < 6; ++s) in.e_cells[t.cell_ent[1][c * 6 + s]].push_back(c);
+    in.f_cells.resize(t.n_ent[2]);
+    for (int64_t c = 0; c < t.n_cells; ++c)
+      for (int s = 0; s < 4; ++s) in.f_cells[t.cell_ent[2][c * 4 + s]].push_back(c);
   }
   return in;
 }
@@ -232,8 +235,54 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
   };
   const bool full = decomposition_full(dec);
   const bool hiptmair = dec == DECOMP_HIPTMAIR || dec == DECOMP_HIPTMAIR_FULL;
+  const bool typeI = dec == DECOMP_TYPEI || dec == DECOMP_TYPEI_FULL;
   if (hiptmair && el.fam != FAM_NED)
     throw std::runtime_error("the Hiptmair-Toselli decompositions are built for H(curl) only");
+  if (typeI && el.fam == FAM_CG)
+    throw std::runtime_error("the type-I Hiptmair-Toselli decompositions need H(curl) or H(div)");
+  if (typeI && el.fam == FAM_RT) {
+    // PH(X^{1,I}, X^{2,I}) (eq:pavarino_hiptmair-novel; split: eq:hdiv-ph-reduced)
+    if (full) {
+      // face stars X^{2,I}|star F: the face's Whitney dof and the type-I
+      // dofs of the cells containing it
+      PatchSet pf = empty_set();
+      for (int64_t f = 0; f < t.n_ent[2]; ++f) {
+        std::vector<int32_t> dofs;
+        entity_dofs(t, el, 2, f, KIND_W, dofs);
+        for (int64_t c : in.f_cells[f]) entity_dofs(t, el, 3, c, KIND_I, dofs);
+        add_patch(pf, t, el, plain_cols(dofs), in.f_cells[f], mark_col, mark_coef);
+      }
+      out.push_back(std::move(pf));
+    }
+    // edge-star potentials curl X^{1,I}|star E in RT coefficients: the curl of
+    // the Whitney edge function is, by Stokes, the signed sum of the Whitney
+    // functions of the faces containing the edge (-1 where the edge is (a, c)
+    // of the face (a, b, c), vertices ascending); the curls of the NedTwo
+    // type-I functions are the RT type-II functions of the same entity and
+    // index (lem:d-preserves-basis-functions)
+    PatchSet pv = empty_set();
+    for (int64_t e = 0; e < t.n_ent[1]; ++e) {
+      const int64_t a0 = t.ent[1][e * 2], b0 = t.ent[1][e * 2 + 1];
+      std::vector<std::vector<std::pair<int32_t, double>>> cols(1);
+      for (int64_t f : in.e_faces[e]) {
+        std::vector<int32_t> w;
+        entity_dofs(t, el, 2, f, KIND_W, w);
+        const int64_t *v = &t.ent[2][f * 3];
+        cols[0].push_back({w[0], (a0 == v[0] && b0 == v[2]) ? -1.0 : 1.0});
+      }
+      auto add_typeII = [&](int l, int64_t ent) {
+        std::vector<int32_t> ii;
+        entity_dofs(t, el, l, ent, KIND_II, ii);
+        for (int32_t g : ii) cols.push_back({{g, 1.0}});
+      };
+      for (int64_t f : in.e_faces[e]) add_typeII(2, f);
+      if (full)
+        for (int64_t c : in.e_cells[e]) add_typeII(3, c);
+      add_patch(pv, t, el, cols, in.e_cells[e], mark_col, mark_coef);
+    }
+    out.push_back(std::move(pv));
+    return out;
+  }
   if (dec == DECOMP_VERTEX || dec == DECOMP_VERTEX_FULL || el.fam == FAM_CG) {
     // vertex stars (eq:approx-sc-pafw; with the cell interiors, eq:pafw):
     // the entities containing the vertex carry the dofs whose support lies
@@ -256,7 +305,7 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
     // edge stars of the type-I interface space X^{1,I}_Gamma (eq:hcurl-decomp),
     // or of every kind of dof (eq:pavarino_hiptmair); the full forms add the
     // dofs of those kinds of the cells containing the edge
-    const int kw = hiptmair ? -1 : KIND_W, ki = hiptmair ? -1 : KIND_I;
+    const int kw = hiptmair ? -1 : KIND_W, ki = hiptmair ? -1 : KIND_I;  // type-I forms: as DECOMP_PAPER
     PatchSet pe = empty_set();
     for (int64_t e = 0; e < t.n_ent[1]; ++e) {
       std::vector<int32_t> dofs;

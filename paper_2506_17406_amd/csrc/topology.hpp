@@ -59,17 +59,26 @@ struct PatchSet {
 //  (eq:pavarino_hiptmair with the split): the DECOMP_PAPER potentials and
 //  edge stars of every kind of interface dof; DECOMP_HIPTMAIR_FULL:
 //  PH(X^0, X^1), the same with the cell interiors.
+//  DECOMP_TYPEI / DECOMP_TYPEI_FULL (H(curl), H(div)): the type-I
+//  Hiptmair-Toselli decomposition PH(X^{k-1,I}, X^{k,I})
+//  (eq:pavarino_hiptmair-novel) with / without the split.  H(curl): the same
+//  as DECOMP_PAPER / DECOMP_PAPER_FULL.  H(div): edge-star potentials
+//  curl X^{1,I}|star E (eq:hdiv-ph-reduced), and, full, the cell type-I
+//  curls in them and the face stars X^{2,I}|star F.
 enum Decomposition {
   DECOMP_PAPER = 0,
   DECOMP_VERTEX = 1,
   DECOMP_VERTEX_FULL = 2,
   DECOMP_PAPER_FULL = 3,
   DECOMP_HIPTMAIR = 4,
-  DECOMP_HIPTMAIR_FULL = 5
+  DECOMP_HIPTMAIR_FULL = 5,
+  DECOMP_TYPEI = 6,
+  DECOMP_TYPEI_FULL = 7
 };
 // whether the decomposition keeps no interior-interface split (no Jacobi group)
 inline bool decomposition_full(int dec) {
-  return dec == DECOMP_VERTEX_FULL || dec == DECOMP_PAPER_FULL || dec == DECOMP_HIPTMAIR_FULL;
+  return dec == DECOMP_VERTEX_FULL || dec == DECOMP_PAPER_FULL || dec == DECOMP_HIPTMAIR_FULL ||
+         dec == DECOMP_TYPEI_FULL;
 }
 std::vector<PatchSet> build_patches(const Topology &top, const RefElement &el, Decomposition dec = DECOMP_PAPER);
 

@@ -31,9 +31,11 @@ RZ_PC_ADDITIVE, RZ_PC_HYBRID = 0, 1
 PCS = {"additive": RZ_PC_ADDITIVE, "hybrid": RZ_PC_HYBRID}
 RZ_DECOMP_PAPER, RZ_DECOMP_VERTEX, RZ_DECOMP_VERTEX_FULL = 0, 1, 2
 RZ_DECOMP_PAPER_FULL, RZ_DECOMP_HIPTMAIR, RZ_DECOMP_HIPTMAIR_FULL = 3, 4, 5
+RZ_DECOMP_TYPEI, RZ_DECOMP_TYPEI_FULL = 6, 7
 DECOMPOSITIONS = {"paper": RZ_DECOMP_PAPER, "vertex": RZ_DECOMP_VERTEX, "vertex-full": RZ_DECOMP_VERTEX_FULL,
                   "paper-full": RZ_DECOMP_PAPER_FULL, "hiptmair": RZ_DECOMP_HIPTMAIR,
-                  "hiptmair-full": RZ_DECOMP_HIPTMAIR_FULL}
+                  "hiptmair-full": RZ_DECOMP_HIPTMAIR_FULL, "typeI": RZ_DECOMP_TYPEI,
+                  "typeI-full": RZ_DECOMP_TYPEI_FULL}
 
 
 class RzOptions(ctypes.Structure):

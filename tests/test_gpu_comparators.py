@@ -5,7 +5,9 @@ stars PAFW(0)(X^k) ("vertex-full") for every space; the default
 decompositions without the split ("paper-full": H(curl) PH(X^0, X^{1,I}),
 H(div) PAFW(1)(X^2)); the standard Hiptmair-Toselli decompositions of
 H(curl) PH(X^0_Gamma, X^1_Gamma) + J ("hiptmair") and PH(X^0, X^1)
-("hiptmair-full").
+("hiptmair-full"); the type-I Hiptmair-Toselli decompositions
+PH(X^{k-1,I}, X^{k,I}) with and without the split ("typeI", "typeI-full";
+for H(div) built from curl potentials).
 
 Sizes: meshes of 6-162 cells, degrees 2-8, seeded jitter and load vectors;
 the largest full stars near the 2048-dof patch limit (H(grad) p = 8: 1695,
@@ -18,7 +20,7 @@ Bars, as for the default decompositions:
 * solve   -- iteration counts within one, true residual under the oracle's A
              <= 1e-10, ||x_gpu - x_oracle|| <= 1e-10 ||x_oracle|| at rtol 1e-12.
 A full star above 2048 dofs is refused with RZ_ERR_UNSUPPORTED at setup,
-and so are the Hiptmair-Toselli forms outside H(curl) (before device work).
+and so are decompositions not built for the space (before device work).
 """
 import numpy as np
 import pytest
@@ -46,7 +48,10 @@ OTHER = [(3, "Ned", 3, 2, 0.1), (3, "Ned", 4, 2, 0.1), (3, "Ned", 2, 2, 0.1), (3
 SETS = ([(c, f) for f in ("vertex", "vertex-full") for c in CASES] +
         [(c, "paper-full") for c in [(3, "CG", 4, 2, 0.1), (2, "CG", 4, 3, 0.1), (3, "RT", 4, 2, 0.1),
                                      (3, "RT", 3, 0, 0.0), (3, "RT", 6, 2, 0.1)] + OTHER] +
-        [(c, f) for f in ("hiptmair", "hiptmair-full") for c in OTHER])
+        [(c, f) for f in ("hiptmair", "hiptmair-full") for c in OTHER] +
+        [(c, f) for f in ("typeI", "typeI-full")
+         for c in [(3, "RT", 3, 2, 0.1), (3, "RT", 4, 3, 0.0), (3, "RT", 2, 2, 0.1), (3, "RT", 3, 0, 0.0),
+                   (3, "RT", 6, 2, 0.1), (3, "Ned", 3, 2, 0.1)]])
 PCS = ["additive", "hybrid"]
 _cache = {}
 

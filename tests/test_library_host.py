@@ -19,7 +19,7 @@ import pytest
 from oracle.element import element
 from oracle.mesh import Topology
 from oracle.operator import reference_stack
-from oracle.precond import patch_lists, vertex_star_lists
+from oracle.precond import curl_potential_patches, patch_lists, vertex_star_lists
 from paper_2506_17406_amd.workloads import kuhn_mesh
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -80,7 +80,7 @@ def test_setup_rejects_before_device_work():
     opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 3, 0)           # unknown preconditioner form
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
     assert b"preconditioner" in rz.lib.rz_last_error()
-    opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 1, 0, 7)        # unknown decomposition
+    opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 1, 0, 99)       # unknown decomposition
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -1
     assert b"decomposition" in rz.lib.rz_last_error()
     assert rz.lib.rz_setup(None, 2, 0, None, None, ctypes.byref(h)) == -1
@@ -152,12 +152,13 @@ def test_vertex_star_lists_bit_exact(d, fam, p, n, form):
         _, _, ptr1, dofs1 = rz.numbering(X, C, p, fam, top.el.n)
         assert np.array_equal(ptr0, ptr1) and np.array_equal(dofs0, dofs1)
     with pytest.raises(rz.RzError):
-        rz.patch_lists(X, C, p, fam, 9)
+        rz.patch_lists(X, C, p, fam, 99)
 
 
 COMP_CASES = [(3, "CG", 4, 2, "paper-full"), (2, "CG", 4, 3, "paper-full"), (3, "Ned", 4, 2, "paper-full"),
               (3, "Ned", 4, 2, "hiptmair"), (3, "Ned", 4, 2, "hiptmair-full"), (3, "Ned", 2, 2, "hiptmair-full"),
-              (3, "RT", 4, 2, "paper-full")]
+              (3, "RT", 4, 2, "paper-full"), (3, "RT", 4, 2, "typeI-full"), (3, "Ned", 3, 2, "typeI"),
+              (3, "Ned", 3, 2, "typeI-full")]
 
 
 @pytest.mark.parametrize("d,fam,p,n,form", COMP_CASES, ids=lambda v: str(v))
@@ -174,6 +175,22 @@ def test_comparator_lists_bit_exact(d, fam, p, n, form):
         assert np.array_equal(dofs[ptr[i]:ptr[i + 1]], idx)
 
 
+def test_hdiv_curl_potential_entries():
+    """H(div) type-I potentials (the first family of the split form): per
+    edge, the dofs the columns combine are the oracle's, column by column
+    (the Whitney column first)."""
+    X, C = kuhn_mesh(2, 3, jitter=0.1, seed=8)
+    top = Topology(X, C, element(3, "RT", 3))
+    G = curl_potential_patches(top, False)
+    ptr, dofs = rz.patch_lists(X, C, 3, "RT", "typeI")
+    assert len(ptr) - 1 == len(G) == top.n_ent[1]
+    for e, Ge in enumerate(G):
+        got = dofs[ptr[e]:ptr[e + 1]]
+        w = np.sort(Ge[:, 0].nonzero()[0])
+        assert np.array_equal(np.sort(got[:len(w)]), w)
+        assert np.array_equal(got[len(w):], np.sort(Ge[:, 1:].nonzero()[0]))
+
+
 def test_hiptmair_only_for_hcurl():
     X, C = kuhn_mesh(1, 3)
     for fam in ("CG", "RT"):
@@ -181,6 +198,10 @@ def test_hiptmair_only_for_hcurl():
             with pytest.raises(rz.RzError) as e:
                 rz.patch_lists(X, C, 2, fam, form)
             assert e.value.code == -2
+    for form in ("typeI", "typeI-full"):
+        with pytest.raises(rz.RzError) as e:
+            rz.patch_lists(X, C, 2, "CG", form)
+        assert e.value.code == -2
     m, keep = rz._mesh(X, C)
     h = ctypes.c_void_p()
     opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 1, 0, 4)
