@@ -403,8 +403,10 @@ def decompositions(args):
     (jittered 8^3x6, mesh seed 2, load seed 3), FP64 PCG to 1e-10: the
     default split solvers, the vertex-star split PAFW(0)(X^k_Gamma)+J, the
     full vertex stars PAFW(0)(X^k), the defaults without the split
-    (H(curl) PH(X^0, X^{1,I}), H(div) PAFW(1)(X^2)) and, for H(curl), the
-    standard Hiptmair-Toselli PH(X^0_Gamma, X^1_Gamma)+J and PH(X^0, X^1).
+    (H(curl) PH(X^0, X^{1,I}), H(div) PAFW(1)(X^2)), for H(curl) the
+    standard Hiptmair-Toselli PH(X^0_Gamma, X^1_Gamma)+J and PH(X^0, X^1),
+    and for H(div) the type-I Hiptmair-Toselli PH(X^{1,I}_Gamma,
+    X^{2,I}_Gamma)+J and PH(X^{1,I}, X^{2,I}).
     Per problem: setup, iterations, solve time, patch sizes.  Roofline: the additive full-star
     preconditioner apply of the largest problem, an HBM stream of the packed
     patch and coarse inverses."""
@@ -418,8 +420,8 @@ def decompositions(args):
     degrees = [4, 5] if args.degrees == "3,4,5,6,7,8" else [int(p) for p in args.degrees.split(",")]
     forms_of = {"CG": ["paper", "vertex", "vertex-full"],
                 "Ned": ["paper", "paper-full", "hiptmair", "hiptmair-full", "vertex", "vertex-full"],
-                "RT": ["paper", "paper-full", "vertex", "vertex-full"]}
-    forms = ["paper", "vertex", "vertex-full", "paper-full", "hiptmair", "hiptmair-full"]
+                "RT": ["paper", "paper-full", "typeI", "typeI-full", "vertex", "vertex-full"]}
+    forms = ["paper", "vertex", "vertex-full", "paper-full", "hiptmair", "hiptmair-full", "typeI", "typeI-full"]
     # Whitney (coarse) dof counts: vertices, edges or faces of the mesh
     Cs = np.sort(C, axis=1)
     n_sub = {0: X.shape[0],
