@@ -127,3 +127,33 @@ def test_full_star_above_patch_limit_is_refused():
     assert e.value.code == -2 and "2048" in str(e.value)
     prob = rz.Problem(X, C, 6, "Ned", decomposition="vertex")      # split star: 1164 dofs
     assert prob.n_dofs > 0
+
+
+MULTI = [((3, "RT", 5, 2, 0.1), "vertex-full"), ((3, "CG", 8, 2, 0.1), "vertex-full"),
+         ((3, "Ned", 4, 2, 0.1), "hiptmair-full"), ((3, "RT", 3, 2, 0.1), "typeI"),
+         ((3, "RT", 4, 3, 0.0), "typeI-full")]
+
+
+@pytest.mark.parametrize("pc", PCS)
+@pytest.mark.parametrize("cf", MULTI, ids=ids)
+@pytest.mark.parametrize("nr", [3, 9])
+def test_multi_rhs(cf, nr, pc):
+    """Several right-hand sides at once: the large-patch kernel one column
+    group at a time, the small potentials through the patch GEMM at >= 8
+    columns; per-column results are the oracle's."""
+    case, form = cf
+    top, A, P, prob = setup_case(*case, form, pc)
+    B = load_vectors(top.n_dofs, 27, n_rhs=nr)
+    Bt = torch.from_numpy(np.ascontiguousarray(B.T)).cuda().T
+    Zt = torch.zeros_like(Bt)
+    prob.apply_P(Bt, Zt)
+    Xt = torch.zeros_like(Bt)
+    infos = prob.solve(Bt, Xt, rtol=1e-12)
+    torch.cuda.synchronize()
+    Z, X = Zt.cpu().numpy(), Xt.cpu().numpy()
+    for j in range(nr):
+        ref = P.apply(B[:, j])
+        assert np.abs(Z[:, j] - ref).max() <= 1e-10 * np.abs(ref).max()
+        xo, io = pcg(lambda v: A @ v, P.apply, B[:, j], rtol=1e-12)
+        assert abs(infos[j]["iterations"] - io["iterations"]) <= 1
+        assert np.linalg.norm(X[:, j] - xo) <= 1e-10 * np.linalg.norm(xo)
