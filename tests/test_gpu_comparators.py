@@ -157,3 +157,38 @@ def test_multi_rhs(cf, nr, pc):
         xo, io = pcg(lambda v: A @ v, P.apply, B[:, j], rtol=1e-12)
         assert abs(infos[j]["iterations"] - io["iterations"]) <= 1
         assert np.linalg.norm(X[:, j] - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+REDUCED = [((3, "RT", 5, 2, 0.1), "vertex-full"), ((3, "CG", 8, 2, 0.1), "vertex-full"),
+           ((3, "Ned", 4, 2, 0.1), "hiptmair"), ((3, "RT", 4, 3, 0.0), "typeI-full")]
+
+
+@pytest.mark.parametrize("prec", ["fp32-pc", "bf16-pc", "fp32-ir"])
+@pytest.mark.parametrize("cf", REDUCED, ids=ids)
+def test_reduced_precision(cf, prec):
+    """The comparators under the reduced-precision modes (FP32 and bfloat16
+    patch copies of up to 1980-dof patches, FP32 refinement): the
+    preconditioner within the copies' rounding of the oracle's (1e-4 FP32,
+    1e-2 bfloat16), and solves to the FP64 tolerance whose solution is the
+    oracle's within 1e-10."""
+    from paper_2506_17406_amd import rz
+    case, form = cf
+    top, A, P, _ = setup_case(*case, form, "hybrid")
+    d, fam, p, n, jit = case
+    X, C = kuhn_mesh(n, d, jitter=jit, seed=13)
+    prob = rz.Problem(X, C, p, fam, precision=prec, decomposition=form)
+    r = load_vectors(top.n_dofs, 37)[:, 0]
+    zt = torch.empty(top.n_dofs, dtype=torch.float64, device="cuda")
+    prob.apply_P(torch.from_numpy(r).cuda(), zt, fp32=True)
+    torch.cuda.synchronize()
+    ref = P.apply(r)
+    err = np.abs(zt.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err <= (1e-2 if prec == "bf16-pc" else 1e-4)
+    b = load_vectors(top.n_dofs, 38)[:, 0]
+    bt = torch.from_numpy(b).cuda()
+    xt = torch.zeros_like(bt)
+    info = prob.solve(bt, xt, rtol=1e-12)
+    x = xt.cpu().numpy()
+    assert info["status"] == 0
+    xo, _ = pcg(lambda v: A @ v, P.apply, b, rtol=1e-12)
+    assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
