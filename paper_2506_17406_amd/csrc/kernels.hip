@@ -1433,11 +1433,13 @@ void launch_seg_to_bf16(int64_t n_patches, const int64_t *patch_col, const int64
 // rows in flight per lane group: deeper for short rows
 template <int VQ, typename T>
 constexpr int patch_depth() {
-  // the widest FP64 variant (16 column stripes, patches of 1025-2048 dofs)
-  // keeps no row in flight ahead: its two row buffers took 256 VGPRs and
-  // spilled to AGPRs, one wave per SIMD; with one buffer it holds 228 VGPRs
-  // and two waves per SIMD, and its applies run 24-37% faster
-  return VQ <= 8 ? 4 : (VQ >= 32 && sizeof(T) == 8 ? 1 : 2);
+  // the two widest FP64 variants (8 and 16 column stripes: patches of
+  // 513-2048 dofs) keep no row in flight ahead.  Their two row buffers cost
+  // occupancy: 16 stripes took 256 VGPRs and spilled to AGPRs (one wave per
+  // SIMD; with one buffer 228 VGPRs, two waves, applies 24-37% faster), 8
+  // stripes 160 VGPRs (three waves; with one buffer 119 VGPRs, four waves,
+  // applies 1.5-2.5% faster)
+  return VQ <= 8 ? 4 : (VQ >= 16 && sizeof(T) == 8 ? 1 : 2);
 }
 
 template <int V, int L, int NQ, int G, typename T, int NW, bool NT>
