@@ -1433,15 +1433,16 @@ void launch_seg_to_bf16(int64_t n_patches, const int64_t *patch_col, const int64
 // rows in flight per lane group: deeper for short rows
 template <int VQ, typename T>
 constexpr int patch_depth() {
-  // the two widest FP64 variants (8 and 16 column stripes: patches of
-  // 513-2048 dofs) and the widest FP32 one (1025-2048 dofs) keep no row in
-  // flight ahead.  Their two row buffers cost occupancy: FP64 16 stripes
-  // took 256 VGPRs and spilled to AGPRs (one wave per SIMD; with one buffer
-  // 228 VGPRs, two waves, applies 24-37% faster), FP64 8 stripes 160 VGPRs
-  // (three waves; with one buffer 119, four waves, 1.5-2.5% faster); the
-  // FP32 variant's applies got 23-35% faster.  The widest bfloat16 variant
-  // keeps its two buffers: with one it ran 11% slower.
-  return VQ <= 8 ? 4 : (VQ >= 16 && sizeof(T) == 8 ? 1 : (VQ >= 32 && sizeof(T) == 4 ? 1 : 2));
+  // FP64 and FP32 variants with 16 or more values per lane per row (patches
+  // of 513-2048 dofs) keep no row in flight ahead: their two row buffers cost
+  // occupancy.  FP64 with 16 stripes took 256 VGPRs and spilled to AGPRs (one
+  // wave per SIMD; with one buffer 228 VGPRs, two waves, applies 24-37%
+  // faster); FP64 with 8 stripes 160 VGPRs (three waves; with one buffer 119,
+  // four waves, 1.5-2.5% faster); FP32 applies got 23-35% (1025-2048 dofs)
+  // and 1.5-3% (513-1024 dofs) faster.  bfloat16 rows are a quarter of the
+  // bytes and keep their two buffers: with one the widest variant ran 11%
+  // slower.
+  return VQ <= 8 ? 4 : (sizeof(T) >= 4 ? 1 : 2);
 }
 
 template <int V, int L, int NQ, int G, typename T, int NW, bool NT>
