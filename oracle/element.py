@@ -71,8 +71,8 @@ class Space:
         Bc = B.reshape(self.c, n, B.shape[1])
         V = self.poly.values(x)
         G = self.poly.gradients(x)
-        vals = np.einsum("qn,cnm->qcm", V, Bc)
-        jac = np.einsum("qan,cnm->qcam", G, Bc)
+        vals = np.tensordot(V, Bc, axes=([1], [1]))                          # (q, c, m)
+        jac = np.tensordot(G, Bc, axes=([2], [1])).transpose(0, 2, 1, 3)    # (q, c, a, m)
         return vals, jac
 
 
@@ -245,6 +245,7 @@ class EigenBasis:
         self.l, self.family, self.p, self.space = l, family, p, space
         self.Psi, self.mu, self.lam = Psi, mu, 1.0 / mu
         self.mu_all, self.n_ker, self.cond_probe = mu_all, n_ker, cond_probe
+        self.clusters = []
         self.k = FORM[family]
         self.N = Psi.shape[1]
 
@@ -285,14 +286,17 @@ def probes(l, c, m):
     return np.array(pts), np.array(dirs)
 
 
-@functools.lru_cache(maxsize=None)
-def eigenbasis(l, family, p):
-    """Type-I eigenbasis of eq:ref-eval-problem-x on the equilateral
-    l-simplex, via the augmented problem eq:ref-eval-problem-x-aug."""
+def bubble_eigenproblem(l, family, p):
+    """The generalized eigenproblem K c = mu M c of eq:ref-eval-problem-x-aug on
+    the bubble space (M the L2 Gram matrix, K that of d_S), solved by
+    scipy's eigh (M-orthonormal eigenvectors, ascending mu).  Returns the
+    space, the bubble basis Bb, K, mu, the eigenvectors and the number of
+    kernel eigenpairs to discard (R3: the dimension N^{k-1}_S of
+    eq:bubble-trace-dim-counts, not a threshold)."""
     sp, Bb = bubble_space(l, family, p)
     k = FORM[family]
     if Bb.shape[1] == 0:
-        return EigenBasis(l, family, p, sp, Bb, np.zeros(0), np.zeros(0), 0, 1.0)
+        return sp, Bb, None, np.zeros(0), None, 0
     x, w = quadrature(l, p + 2)
     vals, jac = sp.field(x, Bb)
     dv = d_op(k, l, vals, jac)
@@ -304,36 +308,78 @@ def eigenbasis(l, family, p):
     if n_ker:
         assert np.all(np.abs(mu[:n_ker]) < 1e-10 * mu[-1]), "kernel not null"
         assert mu[n_ker] > 1e-8 * mu[-1], "kernel dimension mismatch"
+    return sp, Bb, K, mu, Vec, n_ker
+
+
+@functools.lru_cache(maxsize=None)
+def eigenbasis(l, family, p):
+    """Type-I eigenbasis of eq:ref-eval-problem-x on the equilateral
+    l-simplex, via the augmented problem eq:ref-eval-problem-x-aug."""
+    sp, Bb, K, mu, Vec, n_ker = bubble_eigenproblem(l, family, p)
+    if Bb.shape[1] == 0:
+        return EigenBasis(l, family, p, sp, Bb, np.zeros(0), np.zeros(0), 0, 1.0)
     mu_keep = mu[n_ker:]
-    W = Vec[:, n_ker:]
-    # R2: clusters of (numerically) equal mu, canonical rotation inside each
-    out_cols, out_mu, conds = [], [], []
-    i = 0
-    while i < len(mu_keep):
+    W, mu_k, clusters = canonical_clusters(l, sp, Bb, K, mu_keep, Vec[:, n_ker:])
+    Psi = Bb @ (W / np.sqrt(mu_k)) if len(mu_k) else Bb @ W
+    eb = EigenBasis(l, family, p, sp, Psi, mu_k, mu, n_ker,
+                    max(c[2] for c in clusters) if clusters else 1.0)
+    eb.clusters = clusters
+    return eb
+
+
+def cluster_bounds(mu):
+    """R2 clusters of a non-decreasing mu: maximal runs in which each mu is
+    within relative distance TAU of its predecessor, as (start, stop)."""
+    out, i = [], 0
+    while i < len(mu):
         j = i + 1
-        while j < len(mu_keep) and (mu_keep[j] - mu_keep[j - 1]) < TAU * mu_keep[j]:
+        while j < len(mu) and (mu[j] - mu[j - 1]) < TAU * mu[j]:
             j += 1
+        out.append((i, j))
+        i = j
+    return out
+
+
+def canonical_clusters(l, sp, Bb, K, mu, W):
+    """R2: the canonical basis of each cluster of equal eigenvalues.
+
+    W holds M-orthonormal eigenvectors (coefficients over the bubble basis
+    Bb) for the ascending eigenvalues mu.  Inside a cluster of m columns the
+    basis is rotated to W R with R = Y^T (Y Y^T)^{-1/2}, Y_ij = pi_i(W_j) for
+    the first m probe functionals.  For any orthogonal Q, (W Q) R' = W R, so
+    the result does not depend on which orthonormal basis of the cluster
+    the eigensolver returned.  Returns the rotated W, the Rayleigh quotients
+    of its columns, and per cluster (start, size, cond(Y))."""
+    out_cols, out_mu, clusters = [], [], []
+    for i, j in cluster_bounds(mu):
         Wc = W[:, i:j]
         m = j - i
         pts, dirs = probes(l, sp.c, m)
         pv, _ = sp.field(pts, Bb @ Wc)          # (m, c, m)
         Y = np.einsum("ic,icj->ij", dirs, pv)   # Y_ij = pi_i(W_j)
-        YYt = Y @ Y.T
-        ev, evec = np.linalg.eigh(YYt)
-        inv_sqrt = evec @ np.diag(ev ** -0.5) @ evec.T
-        R = Y.T @ inv_sqrt
+        ev, evec = np.linalg.eigh(Y @ Y.T)
+        R = Y.T @ (evec @ np.diag(ev ** -0.5) @ evec.T)
         Wc = Wc @ R
-        conds.append(np.sqrt(ev.max() / ev.min()))
+        clusters.append((i, m, float(np.sqrt(ev.max() / ev.min()))))
         for c_ in range(m):
-            wcol = Wc[:, c_]
-            out_mu.append(wcol @ K @ wcol)
-            out_cols.append(wcol)
-        i = j
-    W = np.stack(out_cols, axis=1) if out_cols else np.zeros((Bb.shape[1], 0))
-    mu_k = np.array(out_mu)
-    Psi = Bb @ (W / np.sqrt(mu_k)) if len(mu_k) else Bb @ W
-    return EigenBasis(l, family, p, sp, Psi, mu_k, mu, n_ker,
-                      max(conds) if conds else 1.0)
+            out_mu.append(Wc[:, c_] @ K @ Wc[:, c_])
+            out_cols.append(Wc[:, c_])
+    Wout = np.stack(out_cols, axis=1) if out_cols else np.zeros((W.shape[0], 0))
+    return Wout, np.array(out_mu), clusters
+
+
+def cluster_census(eb):
+    """Gap statistics of an eigenbasis under the R2 cluster rule: the smallest
+    relative gap between consecutive clusters, the largest relative spread
+    inside a cluster, the largest cond(Y) and the largest cluster size."""
+    mu = eb.mu_all[eb.n_ker:]
+    bounds = cluster_bounds(mu)
+    gaps = [(mu[j] - mu[j - 1]) / mu[j] for (_, j) in bounds[:-1]]
+    spread = [(mu[j - 1] - mu[i]) / mu[j - 1] for (i, j) in bounds]
+    return {"min_gap": min(gaps) if gaps else np.inf,
+            "max_spread": max(spread) if spread else 0.0,
+            "max_cond": max((c[2] for c in eb.clusters), default=1.0),
+            "max_size": max((c[1] for c in eb.clusters), default=0)}
 
 
 # --------------------------------------------------------------------------

@@ -95,16 +95,36 @@ def test_setup_rejects_before_device_work():
     assert b"degenerate" in rz.lib.rz_last_error()
 
 
-REF_CASES = [(2, "CG", p) for p in (1, 2, 4, 6)] + [(3, "CG", p) for p in (1, 3, 6)] + \
-            [(3, "Ned", p) for p in (1, 2, 4, 6)] + [(3, "RT", p) for p in (1, 2, 4, 6)]
+# every (space, degree) the library supports; the oracle's elements above
+# p = 8 in 3D take 20-80 s each, so Ned_9, Ned_10 and RT_9, RT_10 are
+# "heavy" (run with RZ_HEAVY_TESTS=1)
+HEAVY = pytest.mark.heavy
+REF_CASES = [(2, "CG", p) for p in range(1, 11)] + [(3, "CG", p) for p in range(1, 11)] + \
+            [(3, f, p) for f in ("Ned", "RT") for p in range(1, 9)] + \
+            [pytest.param(3, f, p, marks=HEAVY) for f in ("Ned", "RT") for p in (9, 10)]
 
 
+def table_tolerance(d, fam, p):
+    """Relative agreement of the two independent reference builds (both FP64;
+    they differ in quadrature, eigensolver, dual-basis solve and derivative
+    evaluation).  Observed: <= 2.6e-12 up to p = 8 (Ned_5), 6.1e-12 at
+    Ned_8, 2.8e-11 at Ned_9 / Ned_10, 3.0e-11 at CG_10.  RT_9 / RT_10 agree to
+    2.1e-10: their type-II dofs use the NedTwo cell eigenbasis, whose
+    canonical cluster rotation has the census's worst probe conditioning
+    (cond(Y) = 3.3e3 at p = 9), which amplifies the rounding of each
+    eigensolver's cluster subspace."""
+    if p <= 8:
+        return 1e-11
+    return 5e-10 if fam == "RT" else 5e-11
+
+
+@pytest.mark.slow
 @pytest.mark.parametrize("d,fam,p", REF_CASES, ids=lambda v: str(v))
 def test_reference_tables_match_oracle(d, fam, p):
     R = rz.reference(d, p, fam)
     Ro = reference_stack(element(d, fam, p))
     assert R.shape == Ro.shape
-    assert np.abs(R - Ro).max() <= 1e-11 * np.abs(Ro).max()
+    assert np.abs(R - Ro).max() <= table_tolerance(d, fam, p) * np.abs(Ro).max()
 
 
 NUM_CASES = [(2, "CG", 4, 4), (2, "CG", 2, 3), (3, "CG", 1, 2), (3, "CG", 4, 2), (3, "Ned", 1, 2),
