@@ -97,3 +97,36 @@ class Topology:
             for a, b in combinations(t, 2):
                 faces_of[lookup[(a, b)]].append(f)
         return faces_of
+
+
+def dirichlet_dofs(top, cells_in, facet_flags):
+    """Global dofs removed by a Dirichlet boundary Gamma_D (Sec. 5): every
+    basis function tied to a subsimplex of Gamma_D -- the facets marked in
+    facet_flags and their vertices, edges (and, in 3D, the faces themselves).
+    The remaining functions span X^k_{p,D}: a function tied to an entity
+    outside Gamma_D has zero trace (value, tangential or normal component)
+    on every facet of Gamma_D, because the dofs of a facet's subentities are
+    unisolvent for the trace space on that facet (Sec. 3.3).
+
+    cells_in: the cells in the caller's vertex order; facet_flags (n_cells,
+    d+1): a nonzero (c, j) marks the facet of cell c opposite its j-th vertex.
+    A marked facet must lie on the boundary (belong to one cell).  Returns the
+    ascending removed dofs."""
+    d = top.d
+    cells_in = np.asarray(cells_in, dtype=np.int64)
+    flags = np.asarray(facet_flags).reshape(top.n_cells, d + 1)
+    lookup = [{tuple(t): e for e, t in enumerate(top.ent_tuples[l])} for l in range(d)]
+    count = {}
+    for c in range(top.n_cells):
+        for j in range(d + 1):
+            f = tuple(sorted(np.delete(cells_in[c], j).tolist()))
+            count[f] = count.get(f, 0) + 1
+    out = set()
+    for c, j in zip(*np.nonzero(flags)):
+        f = tuple(sorted(np.delete(cells_in[c], j).tolist()))
+        if count[f] != 1:
+            raise ValueError(f"facet {f} of cell {c} is not on the boundary")
+        for l in range(d):
+            for sub in combinations(f, l + 1):
+                out.update(top.entity_dofs(l, lookup[l][sub]))
+    return np.array(sorted(out), dtype=np.int64)

@@ -258,14 +258,36 @@ def potential_patches(top, cg_N, full=False):
     return out
 
 
+def restrict_columns(G, removed):
+    """The columns of a sparse potential basis G that lie in X^k_{p,D}: those
+    with no entry on a removed (Dirichlet) dof.  A potential whose function
+    has a nonzero trace on Gamma_D (the gradient of a vertex function of a
+    vertex on Gamma_D, the image of a CG dof on Gamma_D) touches one."""
+    if removed is None or len(removed) == 0:
+        return G
+    hit = np.asarray(abs(G[removed, :]).sum(axis=0)).ravel() > 0
+    return G[:, np.flatnonzero(~hit)]
+
+
 class AdditiveSchwarz:
-    def __init__(self, A, top, family, decomposition="paper"):
+    """P^{-1} = D_I^{-1} + sum R^T A_m^{-1} R + R_W^T A_W^{-1} R_W on X^k_{p,D}.
+
+    dirichlet (ascending removed dofs, see mesh.dirichlet_dofs) restricts
+    every subspace to the functions that remain (Sec. 5): the patches lose
+    their removed dofs, the potentials their columns that touch one, the
+    coarse space its removed Whitney dofs; the cell interiors are never on
+    the boundary.  The result is zero on the removed dofs."""
+
+    def __init__(self, A, top, family, decomposition="paper", dirichlet=None):
         if decomposition not in DECOMPOSITIONS:
             raise ValueError(decomposition)
         self.A = A
         self.top = top
         self.family = family
         self.decomposition = decomposition
+        self.removed = np.zeros(0, dtype=np.int64) if dirichlet is None else np.asarray(dirichlet, dtype=np.int64)
+        keep = np.ones(top.n_dofs, dtype=bool)
+        keep[self.removed] = False
         k = {"CG": 0, "Ned": 1, "RT": 2}[family]
         diag = A.diagonal()
         full = decomposition.endswith("full")
@@ -273,20 +295,27 @@ class AdditiveSchwarz:
         self.dI = diag[self.I]
         self.patches = []       # (index array, cho factor)
         for idx in patch_lists(top, family, decomposition):
+            idx = idx[keep[idx]]
+            if len(idx) == 0:
+                continue
             Ap = A[idx][:, idx].toarray()
             self.patches.append((idx, sla.cho_factor(Ap, lower=True)))
         self.potentials = []    # (G_V, cho factor)
+        pots = []
         if family == "Ned" and not decomposition.startswith("vertex"):
             p = top.el.p
             cg_N = (1, p - 1, (p - 1) * (p - 2) // 2, (p - 1) * (p - 2) * (p - 3) // 6)
-            for G in potential_patches(top, cg_N, full):
-                Ap = (G.T @ (A @ G)).toarray()
-                self.potentials.append((G, sla.cho_factor(Ap, lower=True)))
+            pots = potential_patches(top, cg_N, full)
         if family == "RT" and decomposition.startswith("typeI"):
-            for G in curl_potential_patches(top, full):
-                Ap = (G.T @ (A @ G)).toarray()
-                self.potentials.append((G, sla.cho_factor(Ap, lower=True)))
-        self.W = whitney_dofs(top, k)
+            pots = curl_potential_patches(top, full)
+        for G in pots:
+            G = restrict_columns(G, self.removed)
+            if G.shape[1] == 0:
+                continue
+            Ap = (G.T @ (A @ G)).toarray()
+            self.potentials.append((G, sla.cho_factor(Ap, lower=True)))
+        W = whitney_dofs(top, k)
+        self.W = W[keep[W]]
         AW = A[self.W][:, self.W].toarray()
         self.coarse = sla.cho_factor(AW, lower=True)
 
@@ -338,12 +367,13 @@ class HybridSchwarz:
     interior-interface split (Sec. 7.1): z = 0, then for m in 1, 2, 3, 2, 1:
     z += rho_m^{-1} B_m (r - A z)."""
 
-    def __init__(self, A, top, family, additive=None, decomposition="paper"):
+    def __init__(self, A, top, family, additive=None, decomposition="paper", dirichlet=None):
         self.A = A
-        self.add = additive if additive is not None else AdditiveSchwarz(A, top, family, decomposition)
+        self.add = additive if additive is not None else AdditiveSchwarz(A, top, family, decomposition, dirichlet)
         n = top.n_dofs
         mask = np.zeros(n, dtype=bool)
         mask[self.add.I] = True
+        mask[self.add.removed] = True       # X_Gamma of X^k_{p,D}: no removed dofs
         self.Gamma = np.flatnonzero(~mask)
         self.rho_I = subspace_weight(A, self.add.I, self.B_interior, SEED_INTERIOR)
         self.rho_Gamma = subspace_weight(A, self.Gamma, self.B_interface, SEED_INTERFACE)
