@@ -12,9 +12,13 @@ resident in HBM before timing; setup (reference build, numbering, patch and
 coarse factorisation) is timed separately.  value = total dofs solved per
 step / step time.
 
-Also reported: the operator apply (the dominant kernel) against the FP64
-matrix peak, timed with HIP events on the launch stream, and the oracle
-(plain NumPy/SciPy FP64) timed on the host cores on a bounded sample.
+Also reported: the operator apply (the dominant kernel by flops) against
+the FP64 matrix peak and the largest patch stream of the preconditioner
+against HBM bandwidth, both timed with HIP events on the launch stream; two
+compact comparisons (mixed precision on H(curl) Ned_6 16^3x6 to a true
+FP64 residual of 1e-10, and 64 right-hand sides on H(div) RT_5 12^3x6
+batched against one by one); and the oracle (plain NumPy/SciPy FP64) timed
+on the host cores on a bounded sample.
 """
 import argparse
 import json
@@ -65,6 +69,10 @@ def parse():
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--multirhs-modes", type=str, default="fp64,fp32-ir,bf16-pc",
                     help="precision modes timed by the multirhs workload (fp64 always runs)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="sweep workload: skip the compact mixed-precision (Ned_6 16^3x6) and 64-column (RT_5 "
+                         "12^3x6) comparisons that the default line carries")
+    ap.add_argument("--leg-steps", type=int, default=3)
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
                     help="after the measurement, one plain device copy of this many bytes (a known-size kernel "
                          "that calibrates HBM counters in profiler runs)")
@@ -499,6 +507,100 @@ def decompositions(args):
     print(json.dumps(line), flush=True)
 
 
+def _timed_solve(prob, b, x, steps, warmup=1):
+    import torch
+    for _ in range(warmup):
+        x.zero_()
+        prob.solve(b, x, rtol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x.zero_()
+        info = prob.solve(b, x, rtol=1e-10)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, info
+
+
+def mixed_leg(args):
+    """Compact mixed-precision comparison for the default line: H(curl) Ned_6
+    on the jittered 16^3x6 mesh (mesh seed 4, load seed 5), plain FP64 PCG
+    against FP32 refinement and the bfloat16-stored preconditioner, each to
+    a true FP64 relative residual of 1e-10 (checked with the FP64 operator)."""
+    import torch
+    from paper_2506_17406_amd import rz
+    from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
+    X, C = kuhn_mesh(16, 3, jitter=0.1, seed=4)
+    out, ref = {}, None
+    for mode in ("fp64", "fp32-ir", "bf16-pc"):
+        prob = rz.Problem(X, C, 6, "Ned", pc=args.pc, precision=mode)
+        b = torch.from_numpy(load_vectors(prob.n_dofs, 5)[:, 0]).cuda()
+        x = torch.zeros_like(b)
+        dt, info = _timed_solve(prob, b, x, args.leg_steps)
+        y = torch.empty_like(b)
+        prob.apply_A(x, y)
+        res = ((b - y).norm() / b.norm()).item()
+        out[mode] = {"ms": dt * 1e3, "value": prob.n_dofs / dt, "iterations": info["iterations"],
+                     "outer_iterations": info["outer_iterations"], "true_rel_residual": res,
+                     "setup_ms": round(info["setup_ms"], 1)}
+        if ref is None:
+            ref = x.clone()
+        else:
+            out[mode]["rel_diff_vs_fp64_solution"] = ((x - ref).norm() / ref.norm()).item()
+        print(f"mixed leg {mode}: {dt * 1e3:.1f} ms, {info['iterations']} its, true residual {res:.2e}",
+              file=sys.stderr, flush=True)
+        prob.close()
+        del b, x, y
+        torch.cuda.empty_cache()
+    ok = [m for m in ("fp32-ir", "bf16-pc") if out[m]["true_rel_residual"] <= 1.2e-10]
+    best = min(ok, key=lambda m: out[m]["ms"]) if ok else "fp64"
+    return {"workload": "H(curl) Ned_6 Riesz map, jittered Kuhn 16^3x6 = 24576 tets, 3,181,344 dofs, to a true "
+                        "FP64 rel. residual 1e-10", "modes": out, "best": best,
+            "speedup_vs_fp64": out["fp64"]["ms"] / out[best]["ms"]}
+
+
+def multirhs_leg(args):
+    """Compact multi-RHS comparison for the default line: H(div) RT_5 on the
+    jittered 12^3x6 mesh (mesh seed 6), 64 load vectors (seed 7): one
+    batched solve of the 64 columns (FP64 and with the bfloat16-stored
+    preconditioner) against the 64 columns solved one by one in FP64."""
+    import torch
+    from paper_2506_17406_amd import rz
+    from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
+    X, C = kuhn_mesh(12, 3, jitter=0.1, seed=6)
+    nr = args.nrhs
+    out = {}
+    for mode in ("fp64", "bf16-pc"):
+        prob = rz.Problem(X, C, 5, "RT", pc=args.pc, precision=mode)
+        B = torch.from_numpy(np.ascontiguousarray(load_vectors(prob.n_dofs, 7, n_rhs=nr).T)).cuda().T
+        Xs = torch.zeros_like(B)
+        dt, infos = _timed_solve(prob, B, Xs, args.leg_steps)
+        Y = torch.empty_like(B)
+        prob.apply_A(Xs, Y)
+        res = float(((B - Y).norm(dim=0) / B.norm(dim=0)).max())
+        its = [i["iterations"] for i in infos]
+        out[mode] = {"ms": dt * 1e3, "value": prob.n_dofs * nr / dt, "iterations": {"min": min(its), "max": max(its)},
+                     "max_true_rel_residual": res}
+        print(f"multi-RHS leg {mode}: {dt * 1e3:.1f} ms for {nr} columns, true residual <= {res:.2e}",
+              file=sys.stderr, flush=True)
+        if mode == "fp64":
+            xs = torch.zeros(prob.n_dofs, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for j in range(nr):
+                xs.zero_()
+                prob.solve(B[:, j].contiguous(), xs, rtol=1e-10)
+            torch.cuda.synchronize()
+            t_seq = time.perf_counter() - t0
+            out["fp64_one_by_one"] = {"ms": t_seq * 1e3, "value": prob.n_dofs * nr / t_seq}
+        prob.close()
+        del B, Xs, Y
+        torch.cuda.empty_cache()
+    return {"workload": f"H(div) RT_5 Riesz map, jittered Kuhn 12^3x6 = 10368 tets, 946,080 dofs x {nr} right-hand "
+                        "sides, rtol 1e-10", "modes": out,
+            "speedup_batched_fp64_vs_one_by_one": out["fp64_one_by_one"]["ms"] / out["fp64"]["ms"],
+            "speedup_batched_bf16pc_vs_one_by_one": out["fp64_one_by_one"]["ms"] / out["bf16-pc"]["ms"]}
+
+
 def cpu_baseline(pc="hybrid"):
     """The oracle, as it stands, on a bounded sample of the workload: the
     p = 3 and p = 4 problems of all three spaces of the sweep (same mesh and
@@ -522,7 +624,16 @@ def cpu_baseline(pc="hybrid"):
             _, info = pcg(lambda v: A @ v, P.apply, b, rtol=1e-10)
             t += time.perf_counter() - t0
         dofs += top.n_dofs
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": dofs / t, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "host_cpus": len(os.sched_getaffinity(0)),
             "sample": f"oracle PCG with the {pc} preconditioner (NumPy/SciPy FP64, assembled CSR SpMV, dense "
                       "Cholesky patch solves, BLAS limited to 1 thread) on the p=3 and p=4 problems of H(grad), "
                       f"H(curl) and H(div) of the same sweep ({dofs:,} dofs); setup excluded",
@@ -616,13 +727,38 @@ def main():
     torch.cuda.synchronize()
     t_prec = ev0.elapsed_time(ev1) / 1e3 / args.apply_reps
 
+    # the preconditioner's largest patch stream: one pass of the family with
+    # the most stored inverse bytes, timed on the launch stream
+    fam_best = max(((e, k, info) for e in probs for k, info in enumerate(e["prob"].patch_sets())),
+                   key=lambda t: t[2]["stored_entries"])
+    pe, pk, pinfo = fam_best
+    xr = torch.rand(pe["prob"].n_dofs, dtype=torch.float64, device="cuda")
+    zr = torch.zeros_like(xr)
+    t_patch = _apply_time(lambda u, v: pe["prob"].patch_set_apply(pk, u, v), xr, zr, args.apply_reps, stream)
+    # algorithmic bytes: the packed upper triangles (8 bytes per entry), the
+    # gathered right-hand side and the read-modify-write of z per patch dof
+    patch_bytes = 8.0 * pinfo["packed_entries"] + 24.0 * pinfo["sum_size"]
+    fam_names = {("CG", 0): "vertex stars", ("Ned", 0): "edge stars", ("Ned", 1): "vertex-star potentials",
+                 ("RT", 0): "edge stars"}
+    roofline_patch = {
+        "kernel": f"patch solves ({pe['fam']}{pe['p']} {fam_names.get((pe['fam'], pk), 'family %d' % pk)}, "
+                  f"{pinfo['n_patches']} patches of <= {pinfo['max_size']} dofs): one pass",
+        "bound": "hbm", "achieved": patch_bytes / t_patch / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "frac": patch_bytes / t_patch / 1e9 / PEAK_HBM_GBS, "traffic": None, "bytes_per_launch": patch_bytes,
+        "stored_bytes": 8.0 * pinfo["stored_entries"], "launch_us": t_patch * 1e6}
+    legs = {}
+    if not args.no_legs:
+        legs["mixed_precision"] = mixed_leg(args)
+        legs["multi_rhs"] = multirhs_leg(args)
+
     # HBM traffic of the roofline kernel from committed counter runs, if they
     # were taken on the current kernel source
     from paper_2506_17406_amd.profile_summary import read_traffic
     tr = read_traffic(os.path.join(ROOT, "profiles", "apply_A_Ned8_sweep_traffic.md"))
     traffic = float(tr["traffic_bytes_per_launch"]) if tr and big["fam"] == "Ned" and big["p"] == 8 else None
     per = [dict(space=e["fam"], p=e["p"], dofs=e["prob"].n_dofs, its=i["iterations"],
-                rel_res=i["rel_residual"], cond=round(i["cond_estimate"], 3), solve_ms=round(i["solve_ms"], 3))
+                rel_res=i["rel_residual"], cond=round(i["cond_estimate"], 3), solve_ms=round(i["solve_ms"], 3),
+                setup_ms=round(i["setup_ms"], 1), cells_per_wave=e["prob"].apply_tiles())
            for e, i in zip(probs, infos)]
     line = {
         "metric": "Riesz-map solve DOFs/s to rel. residual 1e-10",
@@ -646,12 +782,14 @@ def main():
                      "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops, "launch_us": t_apply * 1e6},
+        "roofline_patch": roofline_patch,
         "apply_P_us": t_prec * 1e6,
         ("sequential" if args.sweep_mode == "batched" else "batched"): {
             "value": total_dofs / dt_other, "ms_per_step": dt_other * 1e3,
             "iterations": [i["iterations"] for i in infos_other]},
         "per_problem": per,
     }
+    line.update(legs)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.pc)
     print(json.dumps(line), flush=True)

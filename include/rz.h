@@ -8,8 +8,10 @@
  * for k = 0 (H(grad), CG_p), k = 1 (H(curl), Ned_p first kind) and k = 2
  * (H(div), RT_p first kind), on a conforming simplicial mesh (triangles for
  * k = 0 in 2D, tetrahedra in 3D), with natural (pure Neumann) boundary
- * conditions.  F is given as its load vector b_i = F(phi_i) in the paper's
- * orthogonality-promoting basis (Sec. 3, eq:abstract-dofs; Sec. 4,
+ * conditions, or on X^k_{p,D} with a Dirichlet part Gamma_D of the
+ * boundary (rz_options.dirichlet_facet; Sec. 5).  F is given as its load
+ * vector b_i = F(phi_i) in the paper's orthogonality-promoting basis
+ * (Sec. 3, eq:abstract-dofs; Sec. 4,
  * eq:reference-basis).  The discrete system A x = b is solved by
  * preconditioned conjugate gradients (Sec. 7.1) with the interior-interface
  * split additive Schwarz preconditioners of Sec. 6:
@@ -165,6 +167,17 @@ typedef struct {
                              count) and replayed, on a stream of the handle ordered after and
                              before the caller's stream */
   int32_t decomposition;  /* rz_decomposition (0: RZ_DECOMP_PAPER) */
+  const uint8_t *dirichlet_facet; /* NULL: pure Neumann.  Else host, n_cells x (dim+1): a nonzero entry
+                             (c, j) puts the facet of cell c opposite its j-th vertex (in the order of
+                             mesh->cells) on the Dirichlet boundary Gamma_D; it must be a boundary facet
+                             (RZ_ERR_MESH otherwise).  The problem is then posed on X^k_{p,D}: as in
+                             Sec. 5, every basis function tied to a subsimplex of Gamma_D (the facets, their
+                             edges and vertices) is removed -- the remaining functions are those with zero
+                             trace on Gamma_D.  The removed dofs keep their numbers (rz_dirichlet_dofs lists
+                             them); rz_apply_A and rz_apply_P read their entries as zero and write zero
+                             there, and rz_solve ignores b and returns x = 0 on them.  The preconditioner's
+                             patches, potentials and coarse space are restricted the same way (columns that
+                             touch a removed dof are dropped). */
 } rz_options;
 
 typedef struct {
@@ -174,8 +187,11 @@ typedef struct {
                              refinement: ||b - A x||_2 / ||b||_2 with the FP64 operator */
   double cond_estimate;   /* Lanczos estimate of kappa(P^{-1} A) from the CG coefficients
                              (of the first correction solve under refinement) */
-  double solve_ms;        /* wall time of the iteration loop */
+  double solve_ms;        /* wall time of the iteration loop (rz_batch_solve: from the start of the batch
+                             to the host seeing this problem finish) */
   int32_t outer_iterations; /* refinement steps (0 for RZ_FP64) */
+  double setup_ms;        /* wall time of the handle's rz_setup (reference build, numbering, patch and
+                             coarse assembly and factorisation, hybrid weights) */
 } rz_info;
 
 typedef struct rz_problem rz_problem;
@@ -230,6 +246,27 @@ int rz_apply_P_fp32(rz_problem *P, const double *r, double *z, int32_t n_rhs, in
 int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t ld, double rtol, rz_info *info,
              void *hip_stream);
 
+/* The preconditioner's patch families (the stream that dominates its
+ * apply), one at a time.  rz_patch_set_info: the number of families of the
+ * handle (*n_sets; H(curl) under RZ_DECOMP_PAPER: the edge stars, then the
+ * vertex-star potentials), and for family `set` its patch count, largest
+ * patch, the FP64 entries stored for its inverses (segmented upper rows:
+ * row i holds the columns from its 16-byte segment on) and the entries of the
+ * packed upper triangles sum m (m + 1) / 2, and sum m.  Any output pointer
+ * may be NULL; with only n_sets requested any `set` is accepted.
+ * rz_patch_set_apply: z += sum over the patches m of the family of
+ * R_m^T A_m^{-1} R_m r (the FP64 inverses; one pass of that family's solves
+ * as inside rz_apply_P, Sec. 6).  r, z, n_rhs, ld, stream as rz_apply_P. */
+int rz_patch_set_info(const rz_problem *P, int32_t set, int32_t *n_sets, int64_t *n_patches, int32_t *max_size,
+                      int64_t *stored_entries, int64_t *packed_entries, int64_t *sum_size);
+int rz_patch_set_apply(rz_problem *P, int32_t set, const double *r, double *z, int32_t n_rhs, int64_t ld,
+                       void *hip_stream);
+
+/* The dofs removed by the handle's Dirichlet boundary (rz_options.
+ * dirichlet_facet), ascending.  Pass dofs = NULL to query *n first; n = 0
+ * for a pure Neumann problem. */
+int rz_dirichlet_dofs(const rz_problem *P, int64_t *n, int32_t *dofs);
+
 /* The hybrid group weights rho (host, 3 entries: interior, interface,
  * coarse); all 1 for an additive handle. */
 int rz_pc_weights(const rz_problem *P, double *rho);
@@ -277,13 +314,36 @@ int rz_patch_lists(const rz_mesh *mesh, int32_t degree, rz_space space, int32_t 
 
 void rz_destroy(rz_problem *P);
 
-/* Batches of problems of uneven size (different meshes, spaces, degrees),
- * solved together: each problem runs on a stream of the batch, its PCG
- * iterations in chunks of 8 that are captured into a HIP graph once per
- * problem and solution vector and then replayed; at creation the operator
- * apply of each problem is tuned (cells per wave, by timing).  The problems
- * stay owned by the caller, must outlive the batch, and must not be used by
- * other calls while the batch solves.  Not thread-safe. */
+/* Tile shape of the operator apply's contraction: each wave multiplies the
+ * reference stack into 16, 32 or 64 cells (more cells reuse each loaded
+ * reference fragment more often, fewer keep more waves in flight).  The
+ * default takes the largest that keeps >= 2048 waves in flight over the row
+ * blocks an apply covers.  rz_set_apply_tiles(P, c, 0) fixes c cells per
+ * wave for the single-column applies over all rows (the choice
+ * rz_batch_create's autotuner makes; 0 restores the default);
+ * rz_set_apply_tiles(P, c, 1) fixes it for every apply of the handle,
+ * including the restricted applies of the hybrid sweep and multi-column
+ * applies (0 restores the per-apply rule).  RZ_ERR_ARG unless c is 0, 16,
+ * 32 or 64.  rz_get_apply_tiles returns the single-column choice (0: the
+ * default rule). */
+int rz_set_apply_tiles(rz_problem *P, int32_t cells_per_wave, int32_t every_apply);
+int rz_get_apply_tiles(const rz_problem *P, int32_t *cells_per_wave);
+
+/* Batches of problems of uneven size (different meshes, spaces, degrees,
+ * precisions), solved together: each problem runs on a stream of the batch,
+ * its PCG iterations in chunks of 8 that are captured into a HIP graph once
+ * per problem and solution vector and then replayed (under RZ_FP32_IR the
+ * outer residual checks run between the chunks of the correction solves);
+ * the host starts a problem's next chunk as soon as its previous one has
+ * completed.  At creation the operator apply of each problem without a
+ * tile choice (rz_set_apply_tiles) is tuned: 16, 32 and 64 cells per wave
+ * are timed and the fastest is kept if it beats the default rule by more
+ * than 3%; the choice is reused for every later problem of the same (dim,
+ * space, degree, cells, dofs, precision) in the process and, if the
+ * environment variable RZ_TUNING_FILE names a writable file, read from and
+ * appended to that file.  The problems stay owned by the caller, must
+ * outlive the batch, and must not be used by other calls while the batch
+ * solves.  Not thread-safe. */
 typedef struct rz_batch rz_batch;
 int rz_batch_create(rz_problem *const *problems, int32_t n, rz_batch **out);
 

@@ -5,12 +5,17 @@
 
 #include <algorithm>
 #include <chrono>
-#include <thread>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/rz.h"
@@ -57,6 +62,14 @@ struct rz_problem {
   int64_t off_I = 0;
   int max_iter = 1000;
   int precision = RZ_FP64;
+  double setup_ms = 0.0;  // wall time of rz_setup
+  // Dirichlet boundary: input facet flags, the removed dofs (ascending), their
+  // device mask (n_dofs bytes) and list; bm holds the masked right-hand sides
+  std::vector<uint8_t> dir_flags;
+  std::vector<int32_t> dir_dofs;
+  const uint8_t *dmask = nullptr;
+  const int32_t *dlist = nullptr;
+  double *bm = nullptr;
   // correction solves to 3e-3: an outer step cannot contract the true
   // residual by much more than ~1e-3 (the FP32 operator's error times the
   // condition number), so tighter inner solves only add iterations
@@ -141,6 +154,7 @@ struct rz_problem {
     sto = nullptr;
     ro = dx = nullptr;
     hs = hd = nullptr;
+    bm = nullptr;
     ws_cols = 0;
   }
   ~rz_problem() {
@@ -324,9 +338,17 @@ void setup_coarse(rz_problem &P, hipStream_t s) {
   std::vector<int32_t> item_patch(nc, 0), item_cell(nc), tr_col, tr_loc;
   std::vector<int64_t> item_trip(nc + 1, 0);
   std::vector<double> tr_coef;
+  // removed (Dirichlet) Whitney dofs keep their coarse index but are
+  // decoupled: no cell couples them and their diagonal is one
+  std::vector<uint8_t> wrem(nW, 0);
+  std::vector<int32_t> wrem_idx;
+  if (!P.dir_dofs.empty())
+    for (int i = 0; i < nW; ++i)
+      if (std::binary_search(P.dir_dofs.begin(), P.dir_dofs.end(), wdofs[i])) wrem[i] = 1, wrem_idx.push_back(i);
   for (int64_t c = 0; c < nc; ++c) {
     item_cell[c] = int32_t(c);
     for (int a = 0; a < nwl; ++a) {
+      if (wrem[widx[c * nwl + a]]) continue;
       tr_col.push_back(widx[c * nwl + a]);
       tr_loc.push_back(wloc[a]);
       tr_coef.push_back(1.0);
@@ -364,6 +386,7 @@ void setup_coarse(rz_problem &P, hipStream_t s) {
   HIPCHK(hipMemcpy(dsz, &nW, 4, hipMemcpyHostToDevice));
   rz::launch_pad_identity(1, N, dsz, Abuf, s);
   rz::launch_patch_assemble(nc, d_ip, d_ic, d_it, d_col, d_loc, d_coef, P.el.n, P.el.Q, P.R, P.w, N, Abuf, s);
+  if (!wrem_idx.empty()) rz::launch_set_diag(N, up(wrem_idx), int(wrem_idx.size()), Abuf, s);
   rz::launch_chol_inverse(1, N, Abuf, Lbuf, dstatus, s);
   double *tiles = P.dev<double>(size_t(NT) * (NT + 1) / 2 * 4096);
   rz::launch_pack_tiles(N, nW, Abuf, tiles, s);
@@ -383,6 +406,15 @@ void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
   P.top = rz::build_topology(P.d, m->n_vertices, m->n_cells, m->cells, P.el);
   check_cells(P, m->coords);
   P.patches = rz::build_patches(P.top, P.el, rz::Decomposition(P.decomp));
+  if (!P.dir_flags.empty()) {
+    // X^k_{p,D} (Sec. 5): remove the functions tied to subsimplices of Gamma_D
+    P.dir_dofs = rz::dirichlet_dofs(P.top, P.el, m->cells, P.dir_flags.data());
+    std::vector<uint8_t> removed(P.top.n_dofs, 0);
+    for (int32_t g : P.dir_dofs) removed[g] = 1;
+    for (auto &ps : P.patches) rz::restrict_patches(ps, removed);
+    P.dmask = P.upload(removed, s);
+    P.dlist = P.upload(P.dir_dofs, s);
+  }
   // first dof of the Jacobi group: the interior dofs, or none when the full
   // vertex stars (eq:pafw) hold them
   P.off_I = rz::decomposition_full(P.decomp) ? P.top.n_dofs : P.top.offset[P.d];
@@ -452,6 +484,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
   if (space < RZ_HGRAD || space > RZ_HDIV) return fail(RZ_ERR_ARG, "unknown space");
   if (m->dim == 2 && space != RZ_HGRAD) return fail(RZ_ERR_UNSUPPORTED, "2D supports H(grad) only");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const auto t_setup = std::chrono::steady_clock::now();
   auto P = std::make_unique<rz_problem>();
   P->d = m->dim;
   P->p = degree;
@@ -466,6 +499,8 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     P->graphs = opts->eager == 0;
     if (int e = check_decomposition(opts->decomposition, space)) return e;
     P->decomp = opts->decomposition;
+    if (opts->dirichlet_facet)
+      P->dir_flags.assign(opts->dirichlet_facet, opts->dirichlet_facet + m->n_cells * (m->dim + 1));
   }
   P->fam = space == RZ_HGRAD ? rz::FAM_CG : (space == RZ_HCURL ? rz::FAM_NED : rz::FAM_RT);
   try {
@@ -513,6 +548,8 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     P->at.w = P->w;
     P->at.cell_dofs = P->cell_dofs_apply;
     P->at.n_cells = nc;
+    P->at.dmask = P->dmask;
+    P->ca.dmask = P->dmask;
     // assembly lists of the three-stage apply: for every dof, the positions
     // of its (cell, local row) results in Yc, cells ascending
     {
@@ -609,6 +646,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
   } catch (const std::exception &e) {
     return fail(RZ_ERR_UNSUPPORTED, e.what());
   }
+  P->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_setup).count();
   *out = P.release();
   return RZ_OK;
 }
@@ -627,6 +665,44 @@ int rz_pc_weights(const rz_problem *P, double *rho) {
   rho[0] = P->rho_I;
   rho[1] = P->rho_G;
   rho[2] = 1.0;
+  return RZ_OK;
+}
+
+int rz_patch_set_info(const rz_problem *P, int32_t set, int32_t *n_sets, int64_t *n_patches, int32_t *max_size,
+                      int64_t *stored_entries, int64_t *packed_entries, int64_t *sum_size) {
+  if (!P) return fail(RZ_ERR_ARG, "null argument");
+  if (n_sets) *n_sets = int32_t(P->dps.size());
+  if (set < 0 || set >= int32_t(P->dps.size())) {
+    if (n_patches || max_size || stored_entries || packed_entries || sum_size)
+      return fail(RZ_ERR_ARG, "no such patch family");
+    return RZ_OK;
+  }
+  const DevPatchSet &d = P->dps[set];
+  int64_t packed = 0, msum = 0, mmax = 0;
+  for (int64_t m : d.sizes) packed += m * (m + 1) / 2, msum += m, mmax = std::max(mmax, m);
+  if (n_patches) *n_patches = int64_t(d.sizes.size());
+  if (max_size) *max_size = int32_t(mmax);
+  if (stored_entries) *stored_entries = d.n_inv;
+  if (packed_entries) *packed_entries = packed;
+  if (sum_size) *sum_size = msum;
+  return RZ_OK;
+}
+
+int rz_patch_set_apply(rz_problem *P, int32_t set, const double *r, double *z, int32_t n_rhs, int64_t ld,
+                       void *hip_stream) {
+  if (!P || !r || !z) return fail(RZ_ERR_ARG, "null argument");
+  if (set < 0 || set >= int32_t(P->pas.size())) return fail(RZ_ERR_ARG, "no such patch family");
+  if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
+  rz::launch_patch_apply(P->pas[set], r, ld, z, ld, n_rhs, nullptr, static_cast<hipStream_t>(hip_stream), false, 1.0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RZ_ERR_DEVICE, hipGetErrorString(e));
+  return RZ_OK;
+}
+
+int rz_dirichlet_dofs(const rz_problem *P, int64_t *n, int32_t *dofs) {
+  if (!P) return fail(RZ_ERR_ARG, "null argument");
+  if (n) *n = int64_t(P->dir_dofs.size());
+  if (dofs) std::copy(P->dir_dofs.begin(), P->dir_dofs.end(), dofs);
   return RZ_OK;
 }
 
@@ -675,6 +751,7 @@ static void ensure_ws(rz_problem *P, int ncol) {
     P->ro = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
     P->dx = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
   }
+  if (P->dlist) P->bm = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
   P->ws_cols = ncol;
   if (ncol >= 8 && !P->ca.full) {
     // many columns: the coarse solve becomes a GEMM over a full copy of the inverse
@@ -759,7 +836,10 @@ static double group_weight(rz_problem *P, int64_t lo, int64_t hi, uint64_t seed,
   if (hi <= lo) return 1.0;
   std::vector<double> hb(nd, 0.0);
   uint64_t state = seed;
+  std::vector<uint8_t> removed(nd, 0);
+  for (int32_t g : P->dir_dofs) removed[g] = 1;
   for (int64_t i = lo; i < hi; ++i) {
+    if (removed[i]) continue;  // not in X^k_{p,D}: no draw
     state += 0x9E3779B97F4A7C15ull;
     uint64_t zz = state;
     zz = (zz ^ (zz >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -1033,12 +1113,21 @@ static void pcg_run(rz_problem *P, const double *b, int64_t ldb, double *x, int6
   }
 }
 
+// Dirichlet boundary: bm = b with zeros on the removed dofs, and x = 0 there
+static void mask_rhs(rz_problem *P, const double *b, int64_t ldb, double *x, int64_t ldx, int nc, hipStream_t s) {
+  const int64_t nd = P->top.n_dofs;
+  const int64_t nr = int64_t(P->dir_dofs.size());
+  rz::launch_copy(nd, b, ldb, P->bm, nd, nc, s);
+  rz::launch_zero_rows(P->dlist, nr, P->bm, nd, nc, s);
+  rz::launch_zero_rows(P->dlist, nr, x, ldx, nc, s);
+}
+
 // Iterative refinement: r = b - A x in FP64, d from PCG on A d = r with the
 // FP32 applies to inner_rtol, x += d, until ||b - A x|| <= rtol ||b|| per
 // column.  A step that fails to halve the largest outer residual switches
 // the remaining corrections to the FP64 applies.
-static void refine(rz_problem *P, const double *b, double *x, int64_t ld, int nc, double rtol, std::vector<int> &its,
-                   std::vector<int> &outer, std::vector<double> &cond, std::vector<double> &rel,
+static void refine(rz_problem *P, const double *b, int64_t ldb, double *x, int64_t ld, int nc, double rtol,
+                   std::vector<int> &its, std::vector<int> &outer, std::vector<double> &cond, std::vector<double> &rel,
                    std::vector<int> &code, hipStream_t s) {
   const int64_t nd = P->top.n_dofs;
   const int RB = reduction_blocks(nc);
@@ -1051,8 +1140,8 @@ static void refine(rz_problem *P, const double *b, double *x, int64_t ld, int nc
   for (int k = 0;; ++k) {
     // true residual and the outer convergence test
     rz::launch_apply_A(P->at, x, ld, P->Ap, nd, nc, nullptr, s, false, 0, -1, 1.0, 0, 0, true);
-    rz::launch_residual(nd, b, ld, P->Ap, P->ro, nc, s);
-    rz::launch_dot(nd, b, ld, b, ld, nofold, npad, P->partB, RB, nc, nullptr, s);
+    rz::launch_residual(nd, b, ldb, P->Ap, P->ro, nc, s);
+    rz::launch_dot(nd, b, ldb, b, ldb, nofold, npad, P->partB, RB, nc, nullptr, s);
     rz::launch_dot(nd, P->ro, nd, P->ro, nd, nofold, npad, P->partR, RB, nc, nullptr, s);
     rz::launch_pcg_start(P->partB, P->partR, RB, rtol * rtol, P->max_iter, P->sto, nc, s);
     HIPCHK(hipGetLastError());
@@ -1115,12 +1204,21 @@ int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t l
     std::vector<double> cond(nc, 1.0), rel(nc, 0.0);
     std::vector<int> code(nc, RZ_OK);
     auto t0 = std::chrono::steady_clock::now();
+    // Dirichlet boundary: the removed dofs of b are ignored (a masked copy)
+    // and x starts (and stays) zero on them
+    const double *bb = b;
+    int64_t ldb = ld;
+    if (P->dlist) {
+      mask_rhs(P, b, ld, x, ld, nc, s);
+      bb = P->bm;
+      ldb = P->top.n_dofs;
+    }
     if (P->precision != RZ_FP32_IR) {
       // FP64 operator; FP32 inverses in the preconditioner for RZ_FP32_PC
-      pcg_run(P, b, ld, x, ld, nc, rtol, pc_lo(P), false, nullptr, s);
+      pcg_run(P, bb, ldb, x, ld, nc, rtol, pc_lo(P), false, nullptr, s);
       for (int c = 0; c < nc; ++c) column_info(P->st_host[c], its[c], cond[c], rel[c], code[c]);
     } else {
-      refine(P, b, x, ld, nc, rtol, its, outer, cond, rel, code, s);
+      refine(P, bb, ldb, x, ld, nc, rtol, its, outer, cond, rel, code, s);
     }
     auto t1 = std::chrono::steady_clock::now();
     int worst = RZ_OK;
@@ -1133,6 +1231,7 @@ int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t l
         info[c].cond_estimate = cond[c];
         info[c].solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
         info[c].outer_iterations = outer[c];
+        info[c].setup_ms = P->setup_ms;
       }
     }
     if (worst != RZ_OK) return fail(worst, worst == RZ_ERR_BREAKDOWN ? "CG breakdown" : "no convergence");
@@ -1235,20 +1334,17 @@ void rz_destroy(rz_problem *P) { delete P; }
 }  // extern "C"
 
 // A batch of independent problems solved together: one HIP stream per
-// problem; each problem's PCG iterations run in chunks of kPcgChunk that
-// are captured once into a HIP graph (per problem and solution vector) and
-// replayed, with one host check of the done flags per chunk round.
+// problem.  Each problem advances chunk by chunk on its own stream (PCG
+// iterations in chunks of kPcgChunk replayed from the problem's captured
+// graphs; under RZ_FP32_IR also the outer residual checks between the
+// correction solves); the host launches a problem's next step as soon as its
+// previous one has completed, without waiting for the others.
 struct rz_batch {
   std::vector<rz_problem *> P;
   std::vector<hipStream_t> streams;
-  std::vector<hipGraphExec_t> graphs;
-  std::vector<double *> graph_x;  // solution vector each graph was captured for
-  std::vector<int> graph_gen;      // and the problem's workspace generation
   std::vector<hipEvent_t> done_ev;
   hipEvent_t start_ev = nullptr;
   ~rz_batch() {
-    for (auto g : graphs)
-      if (g) (void)hipGraphExecDestroy(g);
     for (auto e : done_ev)
       if (e) (void)hipEventDestroy(e);
     if (start_ev) (void)hipEventDestroy(start_ev);
@@ -1257,34 +1353,119 @@ struct rz_batch {
   }
 };
 
-// cells per wave of the single-column operator apply, chosen by timing
-// 16, 32 and 64 cells per wave on the problem itself
+// Autotuned cells per wave of the single-column operator apply, kept per
+// (dim, space, degree, cells, dofs, precision) for the life of the process
+// and, when the environment names a file in RZ_TUNING_FILE, in that file
+// (one "dim space degree cells dofs precision cells_per_wave" line per
+// key), so later batches and processes reuse the choice instead of timing
+// again.
+namespace {
+struct TuneKey {
+  int d, k, p, prec;
+  int64_t n_cells, n_dofs;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(d, k, p, prec, n_cells, n_dofs) < std::tie(o.d, o.k, o.p, o.prec, o.n_cells, o.n_dofs);
+  }
+};
+std::map<TuneKey, int> g_tune;
+std::mutex g_tune_mu;
+bool g_tune_loaded = false;
+
+void tune_file_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *path = std::getenv("RZ_TUNING_FILE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  TuneKey k{};
+  long long nc = 0, nd = 0;
+  int cpw = 0;
+  while (std::fscanf(f, "%d %d %d %lld %lld %d %d", &k.d, &k.k, &k.p, &nc, &nd, &k.prec, &cpw) == 7) {
+    k.n_cells = nc;
+    k.n_dofs = nd;
+    if (cpw == 16 || cpw == 32 || cpw == 64) g_tune[k] = cpw / 16;
+  }
+  std::fclose(f);
+}
+
+void tune_file_append(const TuneKey &k, int nb) {
+  const char *path = std::getenv("RZ_TUNING_FILE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%d %d %d %lld %lld %d %d\n", k.d, k.k, k.p, (long long)k.n_cells, (long long)k.n_dofs, k.prec,
+               16 * nb);
+  std::fclose(f);
+}
+}  // namespace
+
+// cells per wave of the single-column operator apply: a value set with
+// rz_set_apply_tiles is kept; else the process's choice for the same key;
+// else 16, 32 and 64 cells per wave are timed (best of three rounds of five
+// applies each) and the fastest is kept only if it beats the occupancy
+// default by more than 3% (timing noise does not flip the choice).
 static void autotune_apply(rz_problem *P, hipStream_t s) {
+  if (P->at.nb1 != 0) return;
+  const TuneKey key{P->d, P->k, P->p, P->precision, P->top.n_cells, P->top.n_dofs};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_file_load();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      P->at.nb1 = it->second;
+      return;
+    }
+  }
   const int64_t nd = P->top.n_dofs;
   ensure_ws(P, 1);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   rz::launch_fill(P->r, nd, nd, 1, nullptr, s);
-  float best = 1e30f;
-  int best_nb = 0;
-  for (int nb : {1, 2, 4}) {
-    P->at.nb1 = nb;
-    rz::launch_apply_A(P->at, P->r, nd, P->Ap, nd, 1, nullptr, s);  // warm-up
-    HIPCHK(hipEventRecord(e0, s));
-    for (int rep = 0; rep < 5; ++rep) rz::launch_apply_A(P->at, P->r, nd, P->Ap, nd, 1, nullptr, s);
-    HIPCHK(hipEventRecord(e1, s));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) best = ms, best_nb = nb;
-  }
-  P->at.nb1 = best_nb;
+  float t[5] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
+  for (int round = 0; round < 3; ++round)
+    for (int nb : {0, 1, 2, 4}) {
+      P->at.nb1 = nb;
+      rz::launch_apply_A(P->at, P->r, nd, P->Ap, nd, 1, nullptr, s);  // warm-up
+      HIPCHK(hipEventRecord(e0, s));
+      for (int rep = 0; rep < 5; ++rep) rz::launch_apply_A(P->at, P->r, nd, P->Ap, nd, 1, nullptr, s);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      t[nb] = std::min(t[nb], ms);
+    }
+  int best = 0;
+  for (int nb : {1, 2, 4})
+    if (t[nb] < 0.97f * t[0] && t[nb] < t[best] * (best == 0 ? 1.0f / 0.97f : 1.0f)) best = nb;
+  P->at.nb1 = best;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tune.emplace(key, best).second && best != 0) tune_file_append(key, best);
 }
 
 extern "C" {
+
+int rz_set_apply_tiles(rz_problem *P, int32_t cells_per_wave, int32_t every_apply) {
+  if (!P) return fail(RZ_ERR_ARG, "null argument");
+  if (cells_per_wave != 0 && cells_per_wave != 16 && cells_per_wave != 32 && cells_per_wave != 64)
+    return fail(RZ_ERR_ARG, "cells_per_wave must be 0, 16, 32 or 64");
+  if (every_apply) {
+    P->at.nb_all = cells_per_wave / 16;
+    P->free_graphs();  // captured chunks baked in the old launch shapes
+  } else {
+    P->at.nb1 = cells_per_wave / 16;
+  }
+  return RZ_OK;
+}
+
+int rz_get_apply_tiles(const rz_problem *P, int32_t *cells_per_wave) {
+  if (!P || !cells_per_wave) return fail(RZ_ERR_ARG, "null argument");
+  *cells_per_wave = 16 * P->at.nb1;
+  return RZ_OK;
+}
 
 int rz_batch_create(rz_problem *const *problems, int32_t n, rz_batch **out) {
   if (!problems || !out || n < 1) return fail(RZ_ERR_ARG, "null argument or empty batch");
@@ -1295,15 +1476,13 @@ int rz_batch_create(rz_problem *const *problems, int32_t n, rz_batch **out) {
   try {
     B->P.assign(problems, problems + n);
     B->streams.assign(n, nullptr);
-    B->graphs.assign(n, nullptr);
-    B->graph_x.assign(n, nullptr);
-    B->graph_gen.assign(n, -1);
     B->done_ev.assign(n, nullptr);
     HIPCHK(hipEventCreateWithFlags(&B->start_ev, hipEventDisableTiming));
     for (int i = 0; i < n; ++i) {
       HIPCHK(hipStreamCreateWithFlags(&B->streams[i], hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&B->done_ev[i], hipEventDisableTiming));
       autotune_apply(B->P[i], B->streams[i]);
+      B->P[i]->free_graphs();  // the tuned shape changes what a chunk launches
     }
   } catch (const RzError &e) {
     return fail(e.code, e.msg);
@@ -1311,6 +1490,20 @@ int rz_batch_create(rz_problem *const *problems, int32_t n, rz_batch **out) {
   *out = B.release();
   return RZ_OK;
 }
+
+namespace {
+// one batch member's progress: plain PCG chunks, or refinement alternating
+// an outer residual check with the chunks of a correction solve
+struct Member {
+  enum Phase { PCG, OUTER, INNER, DONE } phase = PCG;
+  unsigned lo = 0;          // reduced-precision pieces of the current solve
+  int rounds = 0;           // chunks of the current (correction) solve
+  int k = 0;                // refinement: outer checks so far
+  double prev = 0.0;        // refinement: previous outer relative residual
+  bool cond_pending = false;
+  rz_info info{};
+};
+}  // namespace
 
 int rz_batch_solve(rz_batch *B, const double *const *b, double *const *x, double rtol, rz_info *info,
                    void *hip_stream) {
@@ -1321,62 +1514,131 @@ int rz_batch_solve(rz_batch *B, const double *const *b, double *const *x, double
     if (!b[i] || !x[i]) return fail(RZ_ERR_ARG, "null vector in batch");
   hipStream_t user = static_cast<hipStream_t>(hip_stream);
   int worst = RZ_OK;
+  const size_t head = offsetof(rz::PcgState, alphas);
+  const int max_outer = 40;
   try {
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(hipEventRecord(B->start_ev, user));
+    std::vector<Member> M(n);
+    std::vector<const double *> bv(b, b + n);  // right-hand sides as solved (masked under Gamma_D)
+    // refinement: FP64 true residual of x and its convergence state in sto
+    auto outer_check = [&](int i) {
+      rz_problem *P = B->P[i];
+      hipStream_t s = B->streams[i];
+      const int64_t nd = P->top.n_dofs;
+      const int RB = reduction_blocks(1);
+      const int npad = P->ca.NT * 64;
+      const rz::CoarseFold nofold{nullptr, 0, 0, 1};
+      rz::launch_apply_A(P->at, x[i], nd, P->Ap, nd, 1, nullptr, s, false, 0, -1, 1.0, 0, 0, true);
+      rz::launch_residual(nd, bv[i], nd, P->Ap, P->ro, 1, s);
+      rz::launch_dot(nd, bv[i], nd, bv[i], nd, nofold, npad, P->partB, RB, 1, nullptr, s);
+      rz::launch_dot(nd, P->ro, nd, P->ro, nd, nofold, npad, P->partR, RB, 1, nullptr, s);
+      rz::launch_pcg_start(P->partB, P->partR, RB, rtol * rtol, P->max_iter, P->sto, 1, s);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(P->sto_host, P->sto, head, hipMemcpyDeviceToHost, s));
+      M[i].phase = Member::OUTER;
+    };
+    auto chunk = [&](int i, double *xv) {
+      rz_problem *P = B->P[i];
+      run_chunk(P, xv, P->top.n_dofs, 1, M[i].lo, B->streams[i]);
+      HIPCHK(hipGetLastError());
+      pcg_read_head(P, 1, B->streams[i]);
+      ++M[i].rounds;
+    };
     std::vector<int> active;
-    std::vector<unsigned> lo(n, 0);
     for (int i = 0; i < n; ++i) {
       rz_problem *P = B->P[i];
       hipStream_t s = B->streams[i];
       HIPCHK(hipStreamWaitEvent(s, B->start_ev, 0));
       ensure_ws(P, 1);
-      if (P->precision == RZ_FP32_IR) {
-        // refinement drives its own solves; it runs on the problem's stream
-        rz_info inf{};
-        const int code = rz_solve(P, b[i], x[i], 1, P->top.n_dofs, rtol, &inf, s);
-        if (info) info[i] = inf;
-        if (code != RZ_OK && worst == RZ_OK) worst = code;
-        continue;
+      if (P->dlist) {  // Dirichlet boundary: solve with the masked right-hand side
+        mask_rhs(P, bv[i], P->top.n_dofs, x[i], P->top.n_dofs, 1, s);
+        bv[i] = P->bm;
       }
-      lo[i] = pc_lo(P);
-      pcg_begin(P, b[i], P->top.n_dofs, x[i], P->top.n_dofs, 1, rtol, lo[i], false, nullptr, s);
-      HIPCHK(hipGetLastError());
+      if (P->precision == RZ_FP32_IR) {
+        M[i].lo = kLoA | kLoP;
+        outer_check(i);
+      } else {
+        M[i].lo = pc_lo(P);
+        pcg_begin(P, bv[i], P->top.n_dofs, x[i], P->top.n_dofs, 1, rtol, M[i].lo, false, nullptr, s);
+        HIPCHK(hipGetLastError());
+        chunk(i, x[i]);
+      }
       active.push_back(i);
     }
-    // each problem runs chunk after chunk on its own stream; the next chunk
-    // of a problem is launched as soon as its previous one (and the copy of
-    // its convergence state) has completed, without waiting for the others
-    std::vector<int> rounds(n, 0);
-    auto launch_chunk = [&](int i) {
-      {
-        rz_problem *P = B->P[i];
-        hipStream_t s = B->streams[i];
-        if (rounds[i] == 0) {
-          // the first chunk runs eagerly (one-time kernel attribute set-up)
-          pcg_chunk(P, x[i], P->top.n_dofs, 1, lo[i], s);
-        } else {
-          if (!B->graphs[i] || B->graph_x[i] != x[i] || B->graph_gen[i] != P->ws_gen) {
-            if (B->graphs[i]) HIPCHK(hipGraphExecDestroy(B->graphs[i]));
-            B->graphs[i] = nullptr;
-            hipGraph_t g = nullptr;
-            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            pcg_chunk(P, x[i], P->top.n_dofs, 1, lo[i], s);
-            HIPCHK(hipStreamEndCapture(s, &g));
-            const hipError_t e = hipGraphInstantiate(&B->graphs[i], g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) throw RzError{RZ_ERR_DEVICE, hipGetErrorString(e)};
-            B->graph_x[i] = x[i];
-            B->graph_gen[i] = P->ws_gen;
-          }
-          HIPCHK(hipGraphLaunch(B->graphs[i], s));
+    // the next step of a member whose stream has drained; false when it is done
+    auto advance = [&](int i) -> bool {
+      rz_problem *P = B->P[i];
+      hipStream_t s = B->streams[i];
+      Member &m = M[i];
+      const int64_t nd = P->top.n_dofs;
+      if (m.phase == Member::PCG) {
+        if (!P->st_host[0].done && m.rounds * kPcgChunk < P->max_iter) {
+          chunk(i, x[i]);
+          return true;
         }
-        HIPCHK(hipGetLastError());
-        pcg_read_head(P, 1, s);
-        ++rounds[i];
+        HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(rz::PcgState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int its, code;
+        double cond, rel;
+        column_info(P->st_host[0], its, cond, rel, code);
+        m.info.status = code;
+        m.info.iterations = its;
+        m.info.rel_residual = rel;
+        m.info.cond_estimate = cond;
+        m.phase = Member::DONE;
+        return false;
       }
+      if (m.phase == Member::OUTER) {
+        if (m.cond_pending) {  // the first correction solve's full state has arrived
+          m.info.cond_estimate = lanczos_cond(P->st_host[0]);
+          m.cond_pending = false;
+        }
+        const rz::PcgState &h = P->sto_host[0];
+        const double rel = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+        m.info.rel_residual = rel;
+        if (h.done || m.k == max_outer || m.info.status == RZ_ERR_BREAKDOWN) {
+          if (m.info.status == RZ_OK && !h.done) m.info.status = RZ_ERR_NO_CONVERGENCE;
+          m.phase = Member::DONE;
+          return false;
+        }
+        if (m.k > 0 && m.prev > 0 && rel / m.prev > 0.5) m.lo = 0;
+        m.prev = rel;
+        ++m.k;
+        pcg_begin(P, P->ro, nd, P->dx, nd, 1, P->inner_rtol, m.lo, true, P->sto, s);
+        HIPCHK(hipGetLastError());
+        m.rounds = 0;
+        m.phase = Member::INNER;
+        chunk(i, P->dx);
+        return true;
+      }
+      // INNER: next chunk of the correction solve, or its end
+      const rz::PcgState &h = P->st_host[0];
+      if (!h.done && m.rounds * kPcgChunk < P->max_iter) {
+        chunk(i, P->dx);
+        return true;
+      }
+      m.info.iterations += h.iter;
+      m.info.outer_iterations += 1;
+      if (m.info.outer_iterations == 1) {
+        HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(rz::PcgState), hipMemcpyDeviceToHost, s));
+        m.cond_pending = true;
+      }
+      if (h.status == rz::PCG_BREAKDOWN) {
+        if (!m.lo) {
+          m.info.status = RZ_ERR_BREAKDOWN;
+          HIPCHK(hipStreamSynchronize(s));
+          if (m.cond_pending) m.info.cond_estimate = lanczos_cond(P->st_host[0]);
+          m.phase = Member::DONE;
+          return false;
+        }
+        m.lo = 0;
+      }
+      rz::launch_axpy(nd, P->dx, x[i], nd, 1, s);
+      outer_check(i);
+      return true;
     };
-    for (int i : active) launch_chunk(i);
+    std::vector<double> t_done(n, 0.0);
     while (!active.empty()) {
       std::vector<int> next;
       bool progress = false;
@@ -1388,35 +1650,23 @@ int rz_batch_solve(rz_batch *B, const double *const *b, double *const *x, double
         }
         if (q != hipSuccess) throw RzError{RZ_ERR_DEVICE, hipGetErrorString(q)};
         progress = true;
-        if (!B->P[i]->st_host[0].done && rounds[i] * kPcgChunk < B->P[i]->max_iter) {
-          launch_chunk(i);
+        if (advance(i)) {
           next.push_back(i);
+        } else {
+          t_done[i] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }
       }
       active.swap(next);
       if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(10));
     }
-    auto t1 = std::chrono::steady_clock::now();
     for (int i = 0; i < n; ++i) {
-      rz_problem *P = B->P[i];
-      hipStream_t s = B->streams[i];
-      if (P->precision != RZ_FP32_IR) {
-        HIPCHK(hipMemcpyAsync(P->st_host, P->st, sizeof(rz::PcgState), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        int its, code;
-        double cond, rel;
-        column_info(P->st_host[0], its, cond, rel, code);
-        if (code != RZ_OK && worst == RZ_OK) worst = code;
-        if (info) {
-          info[i].status = code;
-          info[i].iterations = its;
-          info[i].rel_residual = rel;
-          info[i].cond_estimate = cond;
-          info[i].solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-          info[i].outer_iterations = 0;
-        }
+      if (M[i].info.status != RZ_OK && worst == RZ_OK) worst = M[i].info.status;
+      if (info) {
+        info[i] = M[i].info;
+        info[i].solve_ms = t_done[i];
+        info[i].setup_ms = B->P[i]->setup_ms;
       }
-      HIPCHK(hipEventRecord(B->done_ev[i], s));
+      HIPCHK(hipEventRecord(B->done_ev[i], B->streams[i]));
       HIPCHK(hipStreamWaitEvent(user, B->done_ev[i], 0));
     }
   } catch (const RzError &e) {

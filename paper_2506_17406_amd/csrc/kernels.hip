@@ -458,7 +458,7 @@ __global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A,
 template <typename T>
 __global__ void k_gather_cells(int n, int KP, int64_t nc, int64_t ncp, int kb0, int kb1,
                                const int32_t *__restrict__ cd, const double *__restrict__ x, int64_t ldx,
-                               T *__restrict__ Xc, const PcgState *st) {
+                               T *__restrict__ Xc, const PcgState *st, const uint8_t *__restrict__ dm) {
   const int c = blockIdx.y;
   if (st && st[c].done) return;
   const double *xc = x + int64_t(c) * ldx;
@@ -470,7 +470,12 @@ __global__ void k_gather_cells(int n, int KP, int64_t nc, int64_t ncp, int kb0, 
     const int64_t b = t >> 6;
     const int64_t cell = (b % nblk) * 16 + ci;
     const int k = (kb0 + int(b / nblk)) * 4 + kk;
-    X[t] = (cell < nc && k < n) ? T(xc[cd[cell * n + k]]) : T(0);
+    T v = T(0);
+    if (cell < nc && k < n) {
+      const int32_t g = cd[cell * n + k];
+      if (!dm || !dm[g]) v = T(xc[g]);
+    }
+    X[t] = v;
   }
 }
 
@@ -565,13 +570,19 @@ __global__ __launch_bounds__(256) void k_apply_A(int mb0, int KB, int kb0_, int 
 template <typename T>
 __global__ void k_assemble(int64_t d0, int64_t d1, const int64_t *__restrict__ ptr, const int32_t *__restrict__ ent,
                            int64_t ystride, const T *__restrict__ Yc, double *__restrict__ y, int64_t ldy,
-                           double alpha, int overwrite, double *__restrict__ xclr, int64_t ldx, const PcgState *st) {
+                           double alpha, int overwrite, double *__restrict__ xclr, int64_t ldx, const PcgState *st,
+                           const uint8_t *__restrict__ dm) {
   const int c = blockIdx.y;
   if (st && st[c].done) return;
   const T *Y = Yc + int64_t(c) * ystride;
   double *yc = y + int64_t(c) * ldy;
   double *xc = xclr ? xclr + int64_t(c) * ldx : nullptr;
   for (int64_t i = d0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < d1; i += int64_t(gridDim.x) * blockDim.x) {
+    if (dm && dm[i]) {  // a removed dof: the row of the restricted operator is zero
+      if (overwrite) yc[i] = 0.0;
+      if (xc) xc[i] = 0.0;
+      continue;
+    }
     double sum = 0.0;
     for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) sum += double(Y[ent[e]]);
     yc[i] = overwrite ? alpha * sum : yc[i] + alpha * sum;
@@ -1187,11 +1198,12 @@ __global__ void k_copy_m(int64_t n, const double *__restrict__ a, int64_t lda, d
 
 // coarse: rW = R_W r (all columns), zW = 0; and z += R_W^T zW
 __global__ void k_coarse_gather_m(int nW, int npad, const int32_t *__restrict__ wd, const double *__restrict__ r,
-                                  int64_t ldr, double *__restrict__ rW, double *__restrict__ zW) {
+                                  int64_t ldr, double *__restrict__ rW, double *__restrict__ zW,
+                                  const uint8_t *__restrict__ dm) {
   const int c = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npad) return;
-  rW[int64_t(c) * npad + i] = i < nW ? r[c * ldr + wd[i]] : 0.0;
+  rW[int64_t(c) * npad + i] = (i < nW && !(dm && dm[wd[i]])) ? r[c * ldr + wd[i]] : 0.0;
   zW[int64_t(c) * npad + i] = 0.0;
 }
 
@@ -1360,7 +1372,7 @@ static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1
   const T *w = sizeof(T) == 8 ? (const T *)t.w : (const T *)t.w32;
   T *Xc = reinterpret_cast<T *>(t.Xc), *Yc = reinterpret_cast<T *>(t.Yc);
   hipLaunchKernelGGL(k_gather_cells<T>, dim3(grid_for(int64_t(kb1 - kb0) * t.ncp * 4, 256, 4096), ncol), dim3(256),
-                     0, s, t.n, t.KP, t.n_cells, t.ncp, kb0, kb1, t.cell_dofs, x, ldx, Xc, st);
+                     0, s, t.n, t.KP, t.n_cells, t.ncp, kb0, kb1, t.cell_dofs, x, ldx, Xc, st, t.dmask);
 #define RZ_A64(NBV, F)                                                                                        \
   hipLaunchKernelGGL((k_apply_A<T, Q, NBV, F>), grid, dim3(256), 0, s, mb0, KB, kb0, kb1, t.n_cells, t.ncp,  \
                      Af, w, Xc, Yc, t.KP, t.NP, st)
@@ -1376,7 +1388,8 @@ static void apply_A_q(const ApplyATables &t, int NB, dim3 grid, int kb0, int kb1
 #undef RZ_A64
   if (d1 > d0)
     hipLaunchKernelGGL(k_assemble<T>, dim3(grid_for(d1 - d0, 256, 4096), ncol), dim3(256), 0, s, d0, d1, t.asm_ptr,
-                       t.asm_ent, int64_t(t.NP) * t.ncp, Yc, y, ldy, alpha, overwrite ? 1 : 0, xclr, ldx, st);
+                       t.asm_ent, int64_t(t.NP) * t.ncp, Yc, y, ldy, alpha, overwrite ? 1 : 0, xclr, ldx, st,
+                       t.dmask);
 }
 
 void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double *y, int64_t ldy, int n_rhs,
@@ -1397,6 +1410,7 @@ void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double 
   int NB = 4;
   while (NB > 1 && ((t.n_cells + 16 * NB - 1) / (16 * NB)) * (NMB - mb0) * n_rhs < 2048) NB /= 2;
   if (n_rhs == 1 && mb0 == 0 && (t.nb1 == 1 || t.nb1 == 2 || t.nb1 == 4)) NB = t.nb1;
+  if (t.nb_all == 1 || t.nb_all == 2 || t.nb_all == 4) NB = t.nb_all;
   // GEMM: a block is one row block x 4 waves x 16 NB cells; a row-
   // restricted apply starts at the row block of row0 and assembles the dofs
   // from dof0 on (the interior rows and dofs: both are trailing blocks)
@@ -1594,7 +1608,7 @@ void launch_apply_P(const PatchApply *sets, int nsets, const CoarseApply &ca, in
   for (int i = 0; i < nsets; ++i) launch_patch_apply(sets[i], r, ldr, z, ldz, ncol, nullptr, s, lo);
   const int npad = ca.NT * 64;
   hipLaunchKernelGGL(k_coarse_gather_m, dim3(grid_for(npad, 256), ncol), dim3(256), 0, s, ca.nW, npad, ca.wdofs, r,
-                     ldr, ca.rW, ca.zW);
+                     ldr, ca.rW, ca.zW, ca.dmask);
   launch_coarse_tiles(ca, ncol, nullptr, s, lo);
   hipLaunchKernelGGL(k_coarse_scatter_m, dim3(grid_for(ca.nW, 256), ncol), dim3(256), 0, s, ca.nW, npad, ca.wdofs,
                      ca.zW, z, ldz);
@@ -1665,12 +1679,29 @@ void launch_jacobi_add(int64_t n, int64_t off_I, const double *dinv, double w1, 
 void launch_coarse_gather(const CoarseApply &ca, const double *r, int64_t ldr, int ncol, hipStream_t s) {
   const int npad = ca.NT * 64;
   hipLaunchKernelGGL(k_coarse_gather_m, dim3(grid_for(npad, 256), ncol), dim3(256), 0, s, ca.nW, npad, ca.wdofs, r,
-                     ldr, ca.rW, ca.zW);
+                     ldr, ca.rW, ca.zW, ca.dmask);
 }
 void launch_coarse_scatter2(const CoarseApply &ca, int64_t n, double *d, double *z, int64_t ldz, int ncol,
                             const PcgState *st, hipStream_t s) {
   hipLaunchKernelGGL(k_coarse_scatter2_m, dim3(grid_for(ca.nW, 256), ncol), dim3(256), 0, s, ca.nW, ca.NT * 64,
                      ca.wdofs, ca.zW, n, d, z, ldz, st);
+}
+__global__ void k_zero_rows(const int32_t *__restrict__ rows, int64_t nrows, double *__restrict__ y, int64_t ld) {
+  const int c = blockIdx.y;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nrows; i += int64_t(gridDim.x) * blockDim.x)
+    y[c * ld + rows[i]] = 0.0;
+}
+void launch_zero_rows(const int32_t *rows, int64_t nrows, double *y, int64_t ld, int ncol, hipStream_t s) {
+  if (nrows == 0) return;
+  hipLaunchKernelGGL(k_zero_rows, dim3(grid_for(nrows, 256, 1024), ncol), dim3(256), 0, s, rows, nrows, y, ld);
+}
+__global__ void k_set_diag(int N, const int32_t *__restrict__ idx, int n, double *__restrict__ A) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) A[int64_t(idx[i]) * N + idx[i]] = 1.0;
+}
+void launch_set_diag(int N, const int32_t *idx, int n, double *A, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_set_diag, dim3(grid_for(n, 256)), dim3(256), 0, s, N, idx, n, A);
 }
 void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
   hipLaunchKernelGGL(k_axpby, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, a, x, b, y);

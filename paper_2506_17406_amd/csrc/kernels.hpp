@@ -48,6 +48,7 @@ struct ApplyATables {
   const float *Afrag32;     // FP32 copies for the mixed-precision inner operator (or null)
   const float *w32;
   int nb1;                  // cells per wave (16 nb1) for single-column applies; 0: by occupancy
+  int nb_all;               // cells per wave (16 nb_all) for every apply; 0: none
   // FP64 three-stage apply: cell-local work vectors (per column KP ncp and
   // NP ncp doubles, for up to ws_cols columns) and the dof -> (cell, row)
   // assembly lists (CSR over dofs, entries index Yc)
@@ -56,6 +57,10 @@ struct ApplyATables {
   int ws_cols;
   const int64_t *asm_ptr;
   const int32_t *asm_ent;
+  // Dirichlet boundary (or null): nonzero for the removed dofs, which the
+  // gather reads as zero and the assembly leaves at zero (overwrite) or
+  // untouched (accumulate)
+  const uint8_t *dmask;
 };
 // y += A x for n_rhs columns (y zeroed by the caller), or y = A x with
 // overwrite; st: per-column state (columns that are done are skipped) or
@@ -106,6 +111,7 @@ struct CoarseApply {
   double *rW, *zW;          // work vectors (NT * 64 per column)
   const double *full;       // all NT x NT tiles in MFMA fragment order (many-column solves), or null
   const float *tiles32;     // FP32 copy of the upper tiles (mixed precision) or null
+  const uint8_t *dmask;     // removed (Dirichlet) dofs read as zero by the coarse gather, or null
 };
 // builds CoarseApply::full from the packed upper tiles
 void launch_coarse_expand(int NT, const double *tiles, double *full, hipStream_t s);
@@ -161,6 +167,10 @@ void launch_coarse_gather(const CoarseApply &ca, const double *r, int64_t ldr, i
 void launch_coarse_scatter2(const CoarseApply &ca, int64_t n, double *d, double *z, int64_t ldz, int ncol,
                             const PcgState *st, hipStream_t s);
 void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+// y[rows[i]] = 0 for every column (the removed dofs of a Dirichlet boundary)
+void launch_zero_rows(const int32_t *rows, int64_t nrows, double *y, int64_t ld, int ncol, hipStream_t s);
+// A[idx[i]][idx[i]] = 1 in an N x N matrix (decoupled coarse rows of removed dofs)
+void launch_set_diag(int N, const int32_t *idx, int n, double *A, hipStream_t s);
 void launch_mask(int64_t n, int64_t lo, int64_t hi, double *y, hipStream_t s);
 
 }  // namespace rz

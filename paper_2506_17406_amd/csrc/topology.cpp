@@ -10,6 +10,7 @@
 #include "topology.hpp"
 
 #include <algorithm>
+#include <map>
 #include <numeric>
 #include <stdexcept>
 
@@ -360,6 +361,86 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
     out.push_back(std::move(ps));
   }
   return out;
+}
+
+std::vector<int32_t> dirichlet_dofs(const Topology &t, const RefElement &el, const int64_t *cells_in,
+                                    const uint8_t *flags) {
+  const int d = t.d;
+  // facet (sorted tuple) -> number of cells containing it, and its entity id
+  std::map<std::vector<int64_t>, int> count;
+  auto facet = [&](int64_t c, int j) {
+    std::vector<int64_t> f;
+    for (int a = 0; a <= d; ++a)
+      if (a != j) f.push_back(cells_in[c * (d + 1) + a]);
+    std::sort(f.begin(), f.end());
+    return f;
+  };
+  for (int64_t c = 0; c < t.n_cells; ++c)
+    for (int j = 0; j <= d; ++j) ++count[facet(c, j)];
+  std::vector<std::map<std::vector<int64_t>, int64_t>> id(d);
+  for (int l = 0; l < d; ++l)
+    for (int64_t e = 0; e < t.n_ent[l]; ++e)
+      id[l][std::vector<int64_t>(t.ent[l].begin() + e * (l + 1), t.ent[l].begin() + (e + 1) * (l + 1))] = e;
+  std::vector<uint8_t> mark(t.n_dofs, 0);
+  for (int64_t c = 0; c < t.n_cells; ++c)
+    for (int j = 0; j <= d; ++j) {
+      if (!flags[c * (d + 1) + j]) continue;
+      const std::vector<int64_t> f = facet(c, j);
+      if (count[f] != 1)
+        throw std::invalid_argument("Dirichlet facet " + std::to_string(j) + " of cell " + std::to_string(c) +
+                                    " is not on the boundary");
+      // every subsimplex of the facet: vertex subsets of size 1 .. d
+      for (int l = 0; l < d; ++l)
+        for (const auto &sub : combos(d, l + 1)) {
+          std::vector<int64_t> key;
+          for (int a : sub) key.push_back(f[a]);
+          std::vector<int32_t> dofs;
+          entity_dofs(t, el, l, id[l].at(key), -1, dofs);
+          for (int32_t g : dofs) mark[g] = 1;
+        }
+    }
+  std::vector<int32_t> out;
+  for (int64_t g = 0; g < t.n_dofs; ++g)
+    if (mark[g]) out.push_back(int32_t(g));
+  return out;
+}
+
+void restrict_patches(PatchSet &ps, const std::vector<uint8_t> &removed) {
+  PatchSet out = empty_set();
+  for (int64_t p = 0; p < ps.n_patches(); ++p) {
+    // kept columns and their new numbers
+    std::vector<int32_t> newcol(ps.patch_col[p + 1] - ps.patch_col[p], -1);
+    int32_t nk = 0;
+    for (int64_t j = ps.patch_col[p]; j < ps.patch_col[p + 1]; ++j) {
+      bool ok = true;
+      for (int64_t e = ps.col_ent[j]; e < ps.col_ent[j + 1]; ++e) ok = ok && !removed[ps.ent_dof[e]];
+      if (!ok) continue;
+      newcol[j - ps.patch_col[p]] = nk++;
+      for (int64_t e = ps.col_ent[j]; e < ps.col_ent[j + 1]; ++e) {
+        out.ent_dof.push_back(ps.ent_dof[e]);
+        out.ent_coef.push_back(ps.ent_coef[e]);
+      }
+      out.col_ent.push_back(int64_t(out.ent_dof.size()));
+    }
+    if (nk == 0) continue;
+    out.patch_col.push_back(int64_t(out.col_ent.size()) - 1);
+    for (int64_t it = ps.pc_ptr[p]; it < ps.pc_ptr[p + 1]; ++it) {
+      const int64_t before = int64_t(out.tr_col.size());
+      for (int64_t q = ps.pc_trip[it]; q < ps.pc_trip[it + 1]; ++q) {
+        const int32_t nc = newcol[ps.tr_col[q]];
+        if (nc < 0) continue;
+        out.tr_col.push_back(nc);
+        out.tr_loc.push_back(ps.tr_loc[q]);
+        out.tr_coef.push_back(ps.tr_coef[q]);
+      }
+      if (int64_t(out.tr_col.size()) > before) {
+        out.pc_cell.push_back(ps.pc_cell[it]);
+        out.pc_trip.push_back(int64_t(out.tr_col.size()));
+      }
+    }
+    out.pc_ptr.push_back(int64_t(out.pc_cell.size()));
+  }
+  ps = std::move(out);
 }
 
 void whitney_dofs(const Topology &t, const RefElement &el, std::vector<int32_t> &wdofs,

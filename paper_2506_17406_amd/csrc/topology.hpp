@@ -82,6 +82,17 @@ inline bool decomposition_full(int dec) {
 }
 std::vector<PatchSet> build_patches(const Topology &top, const RefElement &el, Decomposition dec = DECOMP_PAPER);
 
+// Dirichlet boundary (Sec. 5): the dofs of every subsimplex of the marked
+// facets (the facet, its edges and vertices), ascending.  flags: n_cells x
+// (d+1), nonzero (c, j) marks the facet of input cell c (cells_in, the
+// caller's vertex order) opposite its j-th vertex.  Throws
+// std::invalid_argument when a marked facet belongs to two cells.
+std::vector<int32_t> dirichlet_dofs(const Topology &top, const RefElement &el, const int64_t *cells_in,
+                                    const uint8_t *flags);
+// Restricts a patch family to X^k_{p,D}: drops every column with an entry on
+// a removed dof (removed[g] != 0) and the patches left without columns.
+void restrict_patches(PatchSet &ps, const std::vector<uint8_t> &removed);
+
 // Whitney dofs (one per k-subsimplex, lem:basis-contains-whitney), ascending,
 // and per cell the local Whitney dofs with their coarse indices.
 void whitney_dofs(const Topology &top, const RefElement &el, std::vector<int32_t> &wdofs,

@@ -41,13 +41,14 @@ DECOMPOSITIONS = {"paper": RZ_DECOMP_PAPER, "vertex": RZ_DECOMP_VERTEX, "vertex-
 class RzOptions(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("pc", ctypes.c_int32),
-                ("eager", ctypes.c_int32), ("decomposition", ctypes.c_int32)]
+                ("eager", ctypes.c_int32), ("decomposition", ctypes.c_int32),
+                ("dirichlet_facet", ctypes.POINTER(ctypes.c_uint8))]
 
 
 class RzInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("cond_estimate", ctypes.c_double), ("solve_ms", ctypes.c_double),
-                ("outer_iterations", ctypes.c_int32)]
+                ("outer_iterations", ctypes.c_int32), ("setup_ms", ctypes.c_double)]
 
 
 class RzError(RuntimeError):
@@ -73,6 +74,9 @@ def _load():
         "rz_apply_P_fp32": (ctypes.c_int, [P, P, P, i32, i64, P]),
         "rz_solve": (ctypes.c_int, [P, P, P, i32, i64, dbl, ctypes.POINTER(RzInfo), P]),
         "rz_pc_weights": (ctypes.c_int, [P, pdbl]),
+        "rz_dirichlet_dofs": (ctypes.c_int, [P, pi64, pi32]),
+        "rz_patch_set_info": (ctypes.c_int, [P, i32, pi32, pi64, pi32, pi64, pi64, pi64]),
+        "rz_patch_set_apply": (ctypes.c_int, [P, i32, P, P, i32, i64, P]),
         "rz_export_topology": (ctypes.c_int, [P, pi32, pi64, pi64, pi64, pi32]),
         "rz_export_reference": (ctypes.c_int, [P, pdbl]),
         "rz_reference": (ctypes.c_int, [i32, i32, ctypes.c_int, pi32, pi32, pdbl]),
@@ -80,6 +84,8 @@ def _load():
                                         pi32]),
         "rz_patch_lists": (ctypes.c_int, [ctypes.POINTER(RzMesh), i32, ctypes.c_int, i32, pi64, pi64, pi64, pi32]),
         "rz_destroy": (None, [P]),
+        "rz_set_apply_tiles": (ctypes.c_int, [P, i32, i32]),
+        "rz_get_apply_tiles": (ctypes.c_int, [P, pi32]),
         "rz_batch_create": (ctypes.c_int, [ctypes.POINTER(P), i32, ctypes.POINTER(P)]),
         "rz_batch_solve": (ctypes.c_int, [P, ctypes.POINTER(P), ctypes.POINTER(P), dbl, ctypes.POINTER(RzInfo), P]),
         "rz_batch_destroy": (None, [P]),
@@ -152,6 +158,11 @@ def patch_lists(coords, cells, degree, space, decomposition="paper"):
     return ptr, dofs
 
 
+def _info_dict(i, code):
+    return dict(status=i.status, iterations=i.iterations, rel_residual=i.rel_residual, cond_estimate=i.cond_estimate,
+                solve_ms=i.solve_ms, outer_iterations=i.outer_iterations, setup_ms=i.setup_ms, code=code)
+
+
 def _stream(stream):
     if stream is not None:
         return ctypes.c_void_p(stream)
@@ -163,12 +174,20 @@ class Problem:
     """A set-up Riesz-map problem on the GPU (rz_setup)."""
 
     def __init__(self, coords, cells, degree, space, alpha=1.0, beta=1.0, max_iter=1000, precision="fp64",
-                 inner_rtol=0.0, pc="hybrid", graphs=True, stream=None, decomposition="paper"):
+                 inner_rtol=0.0, pc="hybrid", graphs=True, stream=None, decomposition="paper",
+                 dirichlet_facet=None):
+        """dirichlet_facet: None (pure Neumann) or (n_cells, dim + 1) flags, entry
+        (c, j) marking the facet of cell c opposite its j-th vertex as Gamma_D."""
         m, keep = _mesh(coords, cells)
         prec = PRECISIONS[precision] if isinstance(precision, str) else precision
         dec = DECOMPOSITIONS[decomposition] if isinstance(decomposition, str) else decomposition
+        flags = None
+        if dirichlet_facet is not None:
+            flags = np.ascontiguousarray(dirichlet_facet, dtype=np.uint8)
+            if flags.shape != (m.n_cells, m.dim + 1):
+                raise ValueError("dirichlet_facet must have shape (n_cells, dim + 1)")
         opts = RzOptions(alpha, beta, max_iter, prec, inner_rtol, PCS[pc] if isinstance(pc, str) else pc,
-                         0 if graphs else 1, dec)
+                         0 if graphs else 1, dec, None if flags is None else _ptr(flags, ctypes.c_uint8))
         h = ctypes.c_void_p()
         self._h = None
         self.space = SPACES[space] if isinstance(space, str) else space
@@ -234,10 +253,47 @@ class Problem:
                             info, _stream(stream))
         if check:
             _check(code)
-        out = [dict(status=i.status, iterations=i.iterations, rel_residual=i.rel_residual,
-                    cond_estimate=i.cond_estimate, solve_ms=i.solve_ms, outer_iterations=i.outer_iterations,
-                    code=code) for i in info]
+        out = [_info_dict(i, code) for i in info]
         return out[0] if b.dim() == 1 else out
+
+    def set_apply_tiles(self, cells_per_wave, every_apply=False):
+        """rz_set_apply_tiles: 16, 32 or 64 cells per wave (0: the default rule)."""
+        _check(lib.rz_set_apply_tiles(self._h, int(cells_per_wave), 1 if every_apply else 0))
+
+    def apply_tiles(self):
+        c = ctypes.c_int32()
+        _check(lib.rz_get_apply_tiles(self._h, ctypes.byref(c)))
+        return c.value
+
+    def patch_sets(self):
+        """Per patch family: dict(n_patches, max_size, stored_entries, packed_entries, sum_size)."""
+        ns = ctypes.c_int32()
+        _check(lib.rz_patch_set_info(self._h, 0, ctypes.byref(ns), None, None, None, None, None))
+        out = []
+        for k in range(ns.value):
+            npat, mx, st, pk, sm = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), \
+                ctypes.c_int64()
+            _check(lib.rz_patch_set_info(self._h, k, None, ctypes.byref(npat), ctypes.byref(mx), ctypes.byref(st),
+                                         ctypes.byref(pk), ctypes.byref(sm)))
+            out.append(dict(n_patches=npat.value, max_size=mx.value, stored_entries=st.value,
+                            packed_entries=pk.value, sum_size=sm.value))
+        return out
+
+    def patch_set_apply(self, k, r, z, stream=None):
+        """rz_patch_set_apply: z += the patch solves of family k applied to r."""
+        nr, ld = self._cols(r)
+        self._cols(z)
+        _check(lib.rz_patch_set_apply(self._h, k, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()), nr,
+                                      ld, _stream(stream)))
+        return z
+
+    def dirichlet_dofs(self):
+        """The dofs removed by the Dirichlet boundary, ascending."""
+        n = ctypes.c_int64()
+        _check(lib.rz_dirichlet_dofs(self._h, ctypes.byref(n), None))
+        out = np.empty(n.value, dtype=np.int32)
+        _check(lib.rz_dirichlet_dofs(self._h, None, _ptr(out, ctypes.c_int32)))
+        return out
 
     def pc_weights(self):
         rho = np.empty(3)
@@ -298,7 +354,5 @@ class Batch:
         code = lib.rz_batch_solve(self._h, bp, xp, rtol, info, _stream(stream))
         if check:
             _check(code)
-        return [dict(status=i.status, iterations=i.iterations, rel_residual=i.rel_residual,
-                     cond_estimate=i.cond_estimate, solve_ms=i.solve_ms, outer_iterations=i.outer_iterations,
-                     code=code) for i in info]
+        return [_info_dict(i, code) for i in info]
 

@@ -10,6 +10,8 @@ replayed several times with eager work in between (separate solves, a
 workspace reallocation that must force a re-capture, new solution vectors)
 and every replay is checked.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -72,9 +74,18 @@ def test_batch_matches_oracle_and_own_solves():
         x = torch.zeros_like(b)
         own.append(prob.solve(b, x, rtol=1e-12)["iterations"])
     xs = [torch.zeros_like(b) for b in bs]
+    t0 = time.perf_counter()
     infos = batch.solve(bs, xs, rtol=1e-12)
     torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
     check(ms, xs, infos, 50, own)
+    # each member reports its own completion time and its handle's setup time
+    assert all(0 < i["solve_ms"] <= wall_ms for i in infos)
+    assert len({round(i["solve_ms"], 6) for i in infos}) > 1
+    assert all(i["setup_ms"] > 0 for i in infos)
+    # the refinement member ran its correction solves inside the batch
+    ir = [i for (d, f, p, n, pc, prec), i in zip(MEMBERS, infos) if prec == "fp32-ir"]
+    assert ir and all(i["outer_iterations"] >= 2 for i in ir)
     _state["xs"], _state["own"] = xs, own
 
 

@@ -1,0 +1,262 @@
+"""GPU parity, against the FP64 oracle, of everything the benchmark
+workloads run that the basic parity cases do not reach (through the C ABI).
+
+* Every (space, degree) of the workloads: H(grad) and H(curl) p = 2..10,
+  H(div) p = 2..8 (3D), on jittered meshes of 6-48 cells: apply_A, apply_P
+  and the solve, hybrid preconditioner.
+* Every tile instance of the operator contraction (16, 32 and 64 cells per
+  wave), forced on every apply of the handle (also the hybrid sweep's
+  restricted applies), for Q = 4, 7 and 12 stacked matrices, in FP64 and in
+  the FP32 refinement copy.
+* Coefficients away from alpha = beta = 1, one case per space.
+
+Bars: apply_A, two checks that separate the two error sources -- the
+kernels' arithmetic: max |y - A_lib x| <= 1e-12 max |A_lib x|, where A_lib
+is assembled by the oracle from its own geometric weights and the
+library's exported reference tables; and the whole path against the
+oracle's operator: max |y - A x| <= tol max |A x| with tol = 1e-12 up to
+p = 6, 1e-11 for p = 7, 8 and 5e-11 above (the two independent
+reference-table builds agree to 3e-13 at p <= 6 except Ned_5 (2.6e-12), to
+6.1e-12 at p = 7, 8 and to 3e-11 at p = 9, 10); apply_P max(1e-10, 10 u
+kappa_pc) max |z| (the library applies explicit inverses, accurate to
+O(kappa u) relative to their norm, where kappa_pc is the largest condition
+number of the patch, potential and coarse matrices, u = 2^-53; it matters
+only away from alpha = beta = 1: 7.7e5 at alpha = 1e3); solve: true
+residual under the oracle's A <= max(1e-10, 20 u kappa(A)) ||b|| (the
+attainable accuracy of the FP64 recursion), ||x - x_oracle|| <=
+max(1e-10, 2 kappa(A) rtol) ||x_oracle|| at rtol 1e-12 (each solution is
+within kappa(A) rtol of A^{-1} b; kappa(A) from a dense eigensolve),
+iteration counts within one.  FP32 apply: the
+elementwise first-order rounding bound (K + 4) u32 (|A|_abs |x|)_i of the
+mixed-precision tests.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.element import element
+from oracle.mesh import Topology
+from oracle.operator import all_cell_matrices, assemble, cell_weights, reference_stack
+from oracle.pcg import pcg
+from oracle.precond import AdditiveSchwarz, HybridSchwarz
+from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+_cache = {}
+
+
+def setup(d, fam, p, n, alpha=1.0, beta=1.0, pc="hybrid", precision="fp64"):
+    key = (d, fam, p, n, alpha, beta, pc, precision)
+    if key not in _cache:
+        from paper_2506_17406_amd import rz
+        print(f"setup {key}", flush=True)
+        X, C = kuhn_mesh(n, d, jitter=0.1 if d == 3 else 0.0, seed=31)
+        okey = (d, fam, p, n, alpha, beta)
+        if okey not in _cache:
+            top = Topology(X, C, element(d, fam, p))
+            A = assemble(top, all_cell_matrices(top.el, top, alpha, beta))
+            _cache[okey] = (top, A, AdditiveSchwarz(A, top, fam), {})
+        top, A, P_add, pcs = _cache[okey]
+        if pc not in pcs:
+            pcs[pc] = P_add if pc == "additive" else HybridSchwarz(A, top, fam, additive=P_add)
+        prob = rz.Problem(X, C, p, fam, alpha=alpha, beta=beta, pc=pc, precision=precision)
+        assert prob.n_dofs == top.n_dofs
+        _cache[key] = (top, A, pcs[pc], prob)
+    return _cache[key]
+
+
+def apply_tol(p):
+    return 1e-12 if p <= 6 else (1e-11 if p <= 8 else 5e-11)
+
+
+def library_table_operator(top, prob, alpha=1.0, beta=1.0):
+    """sum_T P_T^T (sum_q w_Tq R_q^lib) P_T: the oracle's weights and assembly
+    with the library's own reference tables (isolates the kernels' arithmetic
+    from the difference of the two table builds)."""
+    R = prob.export_reference()
+    Ac = np.empty((top.n_cells, top.el.n, top.el.n))
+    for c in range(top.n_cells):
+        Ac[c] = np.tensordot(cell_weights(top.el, top.coords[top.cells[c]], alpha, beta), R, axes=1)
+    return assemble(top, Ac)
+
+
+def check_apply_A(top, A, prob, p, seed=5, alpha=1.0, beta=1.0):
+    x = load_vectors(top.n_dofs, seed)[:, 0]
+    yt = torch.empty(top.n_dofs, dtype=torch.float64, device="cuda")
+    prob.apply_A(torch.from_numpy(x).cuda(), yt)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()
+    ref_k = library_table_operator(top, prob, alpha, beta) @ x
+    err_k = np.abs(y - ref_k).max() / np.abs(ref_k).max()
+    assert err_k <= 1e-12, ("kernel arithmetic", err_k)
+    ref = A @ x
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    assert err <= apply_tol(p), ("against the oracle's tables", err)
+
+
+U64 = 2.0 ** -53
+_kappa = {}
+
+
+def kappa_pc(P):
+    """Largest 2-norm condition number of the matrices the preconditioner
+    inverts (patches, potentials, coarse)."""
+    add = getattr(P, "add", P)
+    if id(add) not in _kappa:
+        # cond(L L^T) = cond(L)^2 for the Cholesky factors (lower triangles)
+        ks = [np.linalg.cond(np.tril(F[0])) ** 2 for _, F in add.patches + add.potentials]
+        ks.append(np.linalg.cond(np.tril(add.coarse[0])) ** 2)
+        _kappa[id(add)] = max(ks)
+    return _kappa[id(add)]
+
+
+def kappa_A(A):
+    if ("A", id(A)) not in _kappa:
+        ev = np.linalg.eigvalsh(A.toarray())
+        _kappa[("A", id(A))] = ev[-1] / ev[0]
+    return _kappa[("A", id(A))]
+
+
+def check_apply_P(top, P, prob, seed=6):
+    r = load_vectors(top.n_dofs, seed)[:, 0]
+    zt = torch.empty(top.n_dofs, dtype=torch.float64, device="cuda")
+    prob.apply_P(torch.from_numpy(r).cuda(), zt)
+    torch.cuda.synchronize()
+    ref = P.apply(r)
+    err = np.abs(zt.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err <= max(1e-10, 10 * U64 * kappa_pc(P)), err
+
+
+def check_solve(top, A, P, prob, seed=7, rtol=1e-12, scaled=False):
+    b = load_vectors(top.n_dofs, seed)[:, 0]
+    bt = torch.from_numpy(b).cuda()
+    xt = torch.zeros_like(bt)
+    info = prob.solve(bt, xt, rtol=rtol)
+    x = xt.cpu().numpy()
+    xo, io = pcg(lambda v: A @ v, P.apply, b, rtol=rtol)
+    assert abs(info["iterations"] - io["iterations"]) <= 1, (info["iterations"], io["iterations"])
+    # attainable true residual of an FP64 recursion: O(u kappa(A)) relative
+    res_tol = max(1e-10, 20 * U64 * kappa_A(A)) if scaled else 1e-10
+    assert np.linalg.norm(b - A @ x) <= res_tol * np.linalg.norm(b)
+    tol = max(1e-10, 2 * kappa_A(A) * rtol) if scaled else 1e-10
+    assert np.linalg.norm(x - xo) <= tol * np.linalg.norm(xo)
+
+
+# ---- every (space, degree) the workloads solve -----------------------------
+DEGREES = [("CG", p) for p in range(2, 11)] + [("Ned", p) for p in range(2, 11)] + [("RT", p) for p in range(2, 9)]
+
+
+def mesh_n(p):
+    return 2 if p <= 8 else 1
+
+
+@pytest.mark.parametrize("fam,p", DEGREES, ids=lambda v: str(v))
+def test_degree_apply_A(fam, p):
+    top, A, P, prob = setup(3, fam, p, mesh_n(p))
+    check_apply_A(top, A, prob, p)
+
+
+@pytest.mark.parametrize("fam,p", DEGREES, ids=lambda v: str(v))
+def test_degree_apply_P(fam, p):
+    top, A, P, prob = setup(3, fam, p, mesh_n(p))
+    rho = prob.pc_weights()
+    assert abs(rho[0] / P.rho_I - 1) <= 1e-10 and abs(rho[1] / P.rho_Gamma - 1) <= 1e-10
+    check_apply_P(top, P, prob)
+
+
+@pytest.mark.parametrize("fam,p", DEGREES, ids=lambda v: str(v))
+def test_degree_solve(fam, p):
+    top, A, P, prob = setup(3, fam, p, mesh_n(p))
+    check_solve(top, A, P, prob)
+
+
+# ---- every tile instance of the contraction ---------------------------------
+TILE_CASES = [(2, "CG", 4, 4), (3, "CG", 5, 2), (3, "RT", 4, 2), (3, "Ned", 4, 2)]
+
+
+def tile_ids(v):
+    return "{}d-{}{}-n{}".format(*v) if isinstance(v, tuple) else str(v)
+
+
+@pytest.mark.parametrize("cpw", [16, 32, 64])
+@pytest.mark.parametrize("case", TILE_CASES, ids=tile_ids)
+def test_tiles_fp64_apply_and_sweep(case, cpw):
+    top, A, P, prob = setup(*case)
+    prob.set_apply_tiles(cpw, every_apply=True)
+    try:
+        check_apply_A(top, A, prob, case[2])
+        check_apply_P(top, P, prob)
+        check_solve(top, A, P, prob)
+    finally:
+        prob.set_apply_tiles(0, every_apply=True)
+
+
+def abs_apply(top, x):
+    """(|A|_abs x) with |A|_abs = sum_T P_T^T (sum_q |w_Tq| |R_q|) P_T."""
+    R = np.abs(reference_stack(top.el))
+    y = np.zeros(top.n_dofs)
+    for c in range(top.n_cells):
+        w = np.abs(cell_weights(top.el, top.coords[top.cells[c]]))
+        dofs = top.cell_dofs[c]
+        np.add.at(y, dofs, np.tensordot(w, R, axes=1) @ x[dofs])
+    return y
+
+
+@pytest.mark.parametrize("cpw", [16, 32, 64])
+@pytest.mark.parametrize("case", TILE_CASES, ids=tile_ids)
+def test_tiles_fp32_apply(case, cpw):
+    top, A, P, prob = setup(*case, precision="fp32-ir")
+    prob.set_apply_tiles(cpw, every_apply=True)
+    try:
+        x = load_vectors(top.n_dofs, 9)[:, 0]
+        xt = torch.from_numpy(x).cuda()
+        y32, y64 = (torch.empty_like(xt) for _ in range(2))
+        prob.apply_A(xt, y32, fp32=True)
+        prob.apply_A(xt, y64)
+        torch.cuda.synchronize()
+        y32, y64 = y32.cpu().numpy(), y64.cpu().numpy()
+        K = prob.Q * prob.n_loc
+        bound = (K + 4) * U32 * abs_apply(top, np.abs(x))
+        assert np.all(np.abs(y32 - A @ x) <= bound)
+        assert np.abs(y32 - y64).max() > 0          # the FP32 path ran
+        np.testing.assert_allclose(y64, A @ x, rtol=0, atol=apply_tol(case[2]) * np.abs(A @ x).max())
+    finally:
+        prob.set_apply_tiles(0, every_apply=True)
+
+
+def test_tile_argument_errors():
+    from paper_2506_17406_amd import rz
+    top, A, P, prob = setup(*TILE_CASES[0])
+    with pytest.raises(rz.RzError):
+        prob.set_apply_tiles(48)
+    prob.set_apply_tiles(32)
+    assert prob.apply_tiles() == 32
+    prob.set_apply_tiles(0)
+    assert prob.apply_tiles() == 0
+
+
+# ---- coefficients away from one ---------------------------------------------
+COEFF_CASES = [(2, "CG", 4, 4), (3, "CG", 4, 2), (3, "Ned", 4, 2), (3, "RT", 4, 2)]
+COEFFS = [(1e3, 1.0), (1e-3, 1.0), (1.0, 0.25)]
+
+
+@pytest.mark.parametrize("ab", COEFFS, ids=lambda v: "a{}-b{}".format(*v))
+@pytest.mark.parametrize("case", COEFF_CASES, ids=tile_ids)
+def test_coefficients_apply_A(case, ab):
+    top, A, P, prob = setup(*case, alpha=ab[0], beta=ab[1], pc="additive")
+    check_apply_A(top, A, prob, case[2], alpha=ab[0], beta=ab[1])
+
+
+@pytest.mark.parametrize("pc", ["additive", "hybrid"])
+@pytest.mark.parametrize("ab", COEFFS, ids=lambda v: "a{}-b{}".format(*v))
+@pytest.mark.parametrize("case", COEFF_CASES, ids=tile_ids)
+def test_coefficients_apply_P_and_solve(case, ab, pc):
+    top, A, P, prob = setup(*case, alpha=ab[0], beta=ab[1], pc=pc)
+    if pc == "hybrid":
+        rho = prob.pc_weights()
+        assert abs(rho[0] / P.rho_I - 1) <= 1e-10 and abs(rho[1] / P.rho_Gamma - 1) <= 1e-10
+    check_apply_P(top, P, prob)
+    check_solve(top, A, P, prob, scaled=True)
