@@ -233,6 +233,21 @@ int rz_apply_P(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t
 int rz_apply_A_fp32(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream);
 int rz_apply_P_fp32(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = A x as
+ * rz_apply_A computes it (same kernels, same result), with the operator's
+ * cell-local work vectors in a static device array of 128 MiB that the
+ * library holds on each GPU it runs on, instead of the handle's workspace
+ * (which rz_apply_A grows on demand).  The call allocates nothing.  It needs
+ * (KP + NP) * ncp * n_rhs * 8 bytes <= 128 MiB, where KP and NP are n_loc
+ * rounded up to 4 and 16 and ncp the cell count rounded up to 256 (for
+ * example Ned_6 on 24,576 cells: 86.5 MB per column); larger requests return
+ * RZ_ERR_ARG with the sizes in rz_last_error().  x, y, n_rhs, ld and stream
+ * as rz_apply_A.  Every call on one GPU shares that GPU's array and leaves
+ * its last contents there: calls that overlap on one GPU (other streams,
+ * threads or handles) race and must be ordered by the caller. */
+int rz_apply_A_noalloc(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream);
+
 /* PCG on A X = B for n_rhs independent columns (each with its own CG
  * scalars and stopping test), from the initial guess in X, stopping column j
  * when its recursive residual satisfies ||r_j||_2 <= rtol ||b_j||_2 (under

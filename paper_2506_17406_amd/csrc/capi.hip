@@ -63,6 +63,7 @@ struct rz_problem {
   int max_iter = 1000;
   int precision = RZ_FP64;
   double setup_ms = 0.0;  // wall time of rz_setup
+  double *scratch = nullptr;  // this device's static work array (rz_apply_A_noalloc)
   // Dirichlet boundary: input facet flags, the removed dofs (ascending), their
   // device mask (n_dofs bytes) and list; bm holds the masked right-hand sides
   std::vector<uint8_t> dir_flags;
@@ -458,6 +459,31 @@ void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
 static void ensure_ws(rz_problem *P, int ncol);
 static void estimate_weights(rz_problem *P, hipStream_t s);
 
+// Work space of rz_apply_A_noalloc: the operator's cell-local vectors (Xc,
+// Yc) in a static device array instead of the handle's workspace, so that
+// call allocates nothing.  Each GPU the library runs on holds its own copy
+// for the life of the process.  In host code the array's name is not a
+// device address: kernels receive the address hipGetSymbolAddress returns,
+// looked up once per device during rz_setup with that device current.
+namespace {
+constexpr size_t kScratchBytes = size_t(128) << 20;
+__device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_ptr;  // device -> address of its scratch
+
+double *scratch_address() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  double *ptr = nullptr;
+  HIPCHK(hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)));
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
+}  // namespace
+
 // rz_decomposition values and the spaces they are built for
 static int check_decomposition(int32_t dec, int space) {
   if (dec < RZ_DECOMP_PAPER || dec > RZ_DECOMP_TYPEI_FULL) return fail(RZ_ERR_ARG, "unknown decomposition");
@@ -637,6 +663,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     }
     HIPCHK(hipStreamSynchronize(s));
     if (P->pc == RZ_PC_HYBRID) estimate_weights(P.get(), s);
+    P->scratch = scratch_address();
   } catch (const RzError &e) {
     return fail(e.code, e.msg);
   } catch (const std::invalid_argument &e) {
@@ -952,6 +979,26 @@ int rz_apply_A_fp32(rz_problem *P, const double *x, double *y, int32_t n_rhs, in
 }
 int rz_apply_P_fp32(rz_problem *P, const double *r, double *z, int32_t n_rhs, int64_t ld, void *hip_stream) {
   return apply_P(P, r, z, n_rhs, ld, hip_stream, true);
+}
+
+int rz_apply_A_noalloc(rz_problem *P, const double *x, double *y, int32_t n_rhs, int64_t ld, void *hip_stream) {
+  if (!P || !x || !y) return fail(RZ_ERR_ARG, "null argument");
+  if (n_rhs < 1 || ld < P->top.n_dofs) return fail(RZ_ERR_ARG, "bad n_rhs or ld");
+  if (!P->scratch) return fail(RZ_ERR_DEVICE, "static work array not looked up");
+  const size_t per_col = (size_t(P->at.KP) + size_t(P->at.NP)) * size_t(P->at.ncp) * sizeof(double);
+  if (per_col * size_t(n_rhs) > kScratchBytes)
+    return fail(RZ_ERR_ARG, "rz_apply_A_noalloc: " + std::to_string(n_rhs) + " columns need " +
+                                std::to_string(per_col * size_t(n_rhs)) + " bytes of cell-local work space, above the " +
+                                std::to_string(kScratchBytes) + "-byte static array");
+  rz::ApplyATables t = P->at;
+  t.Xc = P->scratch;
+  t.Yc = P->scratch + size_t(t.KP) * size_t(t.ncp) * size_t(n_rhs);
+  t.ws_cols = n_rhs;
+  rz::launch_apply_A(t, x, ld, y, ld, n_rhs, nullptr, static_cast<hipStream_t>(hip_stream), false, 0, -1, 1.0, 0, 0,
+                     true);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RZ_ERR_DEVICE, hipGetErrorString(e));
+  return RZ_OK;
 }
 
 // Lanczos estimate of kappa(P^{-1} A) from the CG coefficients (Sec. 7.1 reports these)

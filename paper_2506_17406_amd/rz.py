@@ -72,6 +72,7 @@ def _load():
         "rz_apply_P": (ctypes.c_int, [P, P, P, i32, i64, P]),
         "rz_apply_A_fp32": (ctypes.c_int, [P, P, P, i32, i64, P]),
         "rz_apply_P_fp32": (ctypes.c_int, [P, P, P, i32, i64, P]),
+        "rz_apply_A_noalloc": (ctypes.c_int, [P, P, P, i32, i64, P]),
         "rz_solve": (ctypes.c_int, [P, P, P, i32, i64, dbl, ctypes.POINTER(RzInfo), P]),
         "rz_pc_weights": (ctypes.c_int, [P, pdbl]),
         "rz_dirichlet_dofs": (ctypes.c_int, [P, pi64, pi32]),
@@ -232,6 +233,14 @@ class Problem:
         self._cols(y)
         fn = lib.rz_apply_A_fp32 if fp32 else lib.rz_apply_A
         _check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), nr, ld, _stream(stream)))
+        return y
+
+    def apply_A_noalloc(self, x, y, stream=None):
+        """rz_apply_A_noalloc: y = A x with the library's static work array."""
+        nr, ld = self._cols(x)
+        self._cols(y)
+        _check(lib.rz_apply_A_noalloc(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), nr, ld,
+                                      _stream(stream)))
         return y
 
     def apply_P(self, r, z, stream=None, fp32=False):
