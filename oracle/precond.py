@@ -80,6 +80,7 @@ from .simplex import splitmix64_stream
 
 SEED_INTERIOR = 0x5EED1000
 SEED_INTERFACE = 0x5EED2000
+SEED_COARSE = 0x5EED4000
 
 
 def interior_dofs(top):
@@ -278,7 +279,10 @@ class AdditiveSchwarz:
     coarse space its removed Whitney dofs; the cell interiors are never on
     the boundary.  The result is zero on the removed dofs."""
 
-    def __init__(self, A, top, family, decomposition="paper", dirichlet=None):
+    def __init__(self, A, top, family, decomposition="paper", dirichlet=None, coarse_mg=None):
+        """coarse_mg: None for the exact coarse solve (reading R9), or the
+        cells per edge n of the Kuhn mesh for the geometric multigrid V-cycle
+        on W^k of the experiments (oracle.multigrid)."""
         if decomposition not in DECOMPOSITIONS:
             raise ValueError(decomposition)
         self.A = A
@@ -316,8 +320,20 @@ class AdditiveSchwarz:
             self.potentials.append((G, sla.cho_factor(Ap, lower=True)))
         W = whitney_dofs(top, k)
         self.W = W[keep[W]]
-        AW = A[self.W][:, self.W].toarray()
-        self.coarse = sla.cho_factor(AW, lower=True)
+        self.mg = None
+        if coarse_mg is not None:
+            if len(self.removed):
+                raise ValueError("the multigrid coarse solver is built for pure Neumann problems")
+            from .multigrid import WhitneyMultigrid
+            self.mg = WhitneyMultigrid(A[self.W][:, self.W], coarse_mg, k)
+            self.coarse = None
+        else:
+            AW = A[self.W][:, self.W].toarray()
+            self.coarse = sla.cho_factor(AW, lower=True)
+
+    def coarse_solve(self, rW):
+        """The W^k solver: exact Cholesky, or one V-cycle."""
+        return self.mg.cycle(rW) if self.mg is not None else sla.cho_solve(self.coarse, rW)
 
     def apply(self, r):
         z = np.zeros_like(r)
@@ -326,7 +342,7 @@ class AdditiveSchwarz:
             z[idx] += sla.cho_solve(F, r[idx])
         for G, F in self.potentials:
             z += G @ sla.cho_solve(F, G.T @ r)
-        z[self.W] += sla.cho_solve(self.coarse, r[self.W])
+        z[self.W] += self.coarse_solve(r[self.W])
         return z
 
     def sizes(self):
@@ -367,9 +383,10 @@ class HybridSchwarz:
     interior-interface split (Sec. 7.1): z = 0, then for m in 1, 2, 3, 2, 1:
     z += rho_m^{-1} B_m (r - A z)."""
 
-    def __init__(self, A, top, family, additive=None, decomposition="paper", dirichlet=None):
+    def __init__(self, A, top, family, additive=None, decomposition="paper", dirichlet=None, coarse_mg=None):
         self.A = A
-        self.add = additive if additive is not None else AdditiveSchwarz(A, top, family, decomposition, dirichlet)
+        self.add = additive if additive is not None else AdditiveSchwarz(A, top, family, decomposition, dirichlet,
+                                                                         coarse_mg)
         n = top.n_dofs
         mask = np.zeros(n, dtype=bool)
         mask[self.add.I] = True
@@ -377,6 +394,9 @@ class HybridSchwarz:
         self.Gamma = np.flatnonzero(~mask)
         self.rho_I = subspace_weight(A, self.add.I, self.B_interior, SEED_INTERIOR)
         self.rho_Gamma = subspace_weight(A, self.Gamma, self.B_interface, SEED_INTERFACE)
+        # the exact coarse solver has weight 1; the V-cycle is an inexact
+        # solver and gets the same estimated weight as the other groups
+        self.rho_W = 1.0 if self.add.mg is None else subspace_weight(A, self.add.W, self.B_coarse, SEED_COARSE)
 
     def B_interior(self, r):
         z = np.zeros_like(r)
@@ -393,11 +413,11 @@ class HybridSchwarz:
 
     def B_coarse(self, r):
         z = np.zeros_like(r)
-        z[self.add.W] = sla.cho_solve(self.add.coarse, r[self.add.W])
+        z[self.add.W] = self.add.coarse_solve(r[self.add.W])
         return z
 
     def groups(self):
-        return [(self.B_interior, self.rho_I), (self.B_interface, self.rho_Gamma), (self.B_coarse, 1.0)]
+        return [(self.B_interior, self.rho_I), (self.B_interface, self.rho_Gamma), (self.B_coarse, self.rho_W)]
 
     def apply(self, r):
         (b1, w1), (b2, w2), (b3, w3) = self.groups()
