@@ -397,7 +397,7 @@ class Element:
     """The Ciarlet element (T_hat, X^k_p, L) of Sec. 3.3 and its dual basis."""
 
     def __init__(self, d, family, p):
-        if family not in ("CG", "Ned", "RT"):
+        if family not in ("CG", "Ned", "RT", "NedTwo"):
             raise ValueError(family)
         self.d, self.family, self.p, self.k = d, family, p, FORM[family]
         self.space = make_space(d, family, p)
@@ -406,7 +406,9 @@ class Element:
         k = self.k
         # functionals act on the whole primal space P_p^c (identity basis)
         full = np.eye(self.space.B.shape[0])
-        typeII_family = {1: "CG", 2: "NedTwo"}.get(k)
+        # the (k-1)-form family whose bubble derivatives give the type-II dofs:
+        # CG_p for Ned_p, NedTwo_p for RT_p (R4), CG_{p+1} for NedTwo_p
+        typeII = kernel_family(family, p)
         for l, ents in enumerate(entities(d)):
             for ei, verts in enumerate(ents):
                 o, A, y0 = entity_map(d, verts)
@@ -434,7 +436,7 @@ class Element:
                         self.dofs.append(DofInfo(l, ei, verts, "I", j))
                 if l >= k and k >= 1 and l >= 1:
                     # type-II: (d_S psi^{k-1}_j, tr v)_S
-                    eb = eigenbasis(l, typeII_family, p)
+                    eb = eigenbasis(l, *typeII)
                     dpsi = eb.dvalues(yq)
                     tr = trace(k, A, vals)
                     for j in range(eb.N):

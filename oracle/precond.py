@@ -113,6 +113,63 @@ def face_stars_typeI(top):
     return out
 
 
+def face_stars(top, full):
+    """The k-stars of the standard H(div) Hiptmair-Toselli decomposition
+    (eq:pavarino_hiptmair, k = 2): per face, X^2_Gamma|star F -- the dofs of
+    the face -- and, full (X^2|star F), also the dofs of its two cells."""
+    cells_of = cells_containing(top, 2)
+    out = []
+    for f in range(top.n_ent[2]):
+        idx = top.entity_dofs(2, f)
+        if full:
+            for c in cells_of[f]:
+                idx += top.entity_dofs(3, c)
+        out.append(np.array(sorted(idx), dtype=np.int64))
+    return out
+
+
+def nedtwo_curl_potentials(top, top2, full):
+    """The potentials of the standard H(div) Hiptmair-Toselli decomposition
+    d X^1|star E (eq:pavarino_hiptmair, k = 2) with X^1 = NedTwo_p, the space
+    whose eigenfunctions define the RT_p type-II dofs (R4): per edge, the
+    NedTwo dofs of the entities containing it (the edge and its faces; full:
+    also its cells) as (S_E, G_E): S_E the NedTwo global dofs (numbering of
+    top2) and G_E (n_RT x |S_E|) the curls of those functions in RT
+    coefficients -- the Whitney edge function to the signed face Whitney
+    functions (as in curl_potential_patches), a type-I function of a face or
+    cell to the RT type-II function of the same entity and index
+    (lem:d-preserves-basis-functions), a type-II (gradient) function to
+    zero."""
+    faces_of = top.edge_faces()
+    cells_of = cells_containing(top, 1) if full else None
+    out = []
+    for e, (a0, b0) in enumerate(top.ent_tuples[1]):
+        S, rows, cols, vals = [], [], [], []
+        ents = [(1, e)] + [(2, f) for f in faces_of[e]] + ([(3, c) for c in cells_of[e]] if full else [])
+        for l, ent in ents:
+            base = top2.offset[l] + ent * top2.N[l]
+            typeI = [top.entity_dofs(l, ent, kinds=("II",))] if l >= 2 else None
+            nI = 0
+            for j in range(top2.N[l]):
+                col = len(S)
+                S.append(base + j)
+                kind = top2.kinds[l][j]
+                if kind == "W":
+                    for f in faces_of[e]:
+                        a, b, c = top.ent_tuples[2][f]
+                        rows.append(top.entity_dofs(2, f, kinds=("W",))[0])
+                        cols.append(col)
+                        vals.append(-1.0 if (a0, b0) == (a, c) else 1.0)
+                elif kind == "I":
+                    rows.append(typeI[0][nI])
+                    cols.append(col)
+                    vals.append(1.0)
+                    nI += 1
+        G = sp.csc_matrix((vals, (rows, cols)), shape=(top.n_dofs, len(S)))
+        out.append((np.array(S, dtype=np.int64), G))
+    return out
+
+
 def curl_potential_patches(top, full=False):
     """H(div) edge-star potentials curl X^{1,I}|star E as sparse G_E
     (n_dofs x n_E) in RT coefficients.  Column 0 is the curl of the Whitney
@@ -156,8 +213,10 @@ def patch_lists(top, family, decomposition="paper"):
         if family == "RT":
             return face_stars_typeI(top) if decomposition == "typeI-full" else []
         decomposition = decomposition.replace("typeI", "paper")
-    if decomposition.startswith("hiptmair") and family != "Ned":
-        raise ValueError("the Hiptmair-Toselli comparators are built for H(curl) only")
+    if decomposition.startswith("hiptmair") and family == "CG":
+        raise ValueError("the Hiptmair-Toselli decompositions need k >= 1")
+    if decomposition.startswith("hiptmair") and family == "RT":
+        return face_stars(top, decomposition == "hiptmair-full")
     full = decomposition.endswith("full")
     d = top.d
     out = []
@@ -279,10 +338,12 @@ class AdditiveSchwarz:
     coarse space its removed Whitney dofs; the cell interiors are never on
     the boundary.  The result is zero on the removed dofs."""
 
-    def __init__(self, A, top, family, decomposition="paper", dirichlet=None, coarse_mg=None):
+    def __init__(self, A, top, family, decomposition="paper", dirichlet=None, coarse_mg=None, beta=1.0):
         """coarse_mg: None for the exact coarse solve (reading R9), or the
         cells per edge n of the Kuhn mesh for the geometric multigrid V-cycle
-        on W^k of the experiments (oracle.multigrid)."""
+        on W^k of the experiments (oracle.multigrid).  beta: the mass
+        coefficient of A (it scales the regularisation of the H(div)
+        Hiptmair-Toselli potentials)."""
         if decomposition not in DECOMPOSITIONS:
             raise ValueError(decomposition)
         self.A = A
@@ -318,6 +379,23 @@ class AdditiveSchwarz:
                 continue
             Ap = (G.T @ (A @ G)).toarray()
             self.potentials.append((G, sla.cho_factor(Ap, lower=True)))
+        if family == "RT" and decomposition.startswith("hiptmair"):
+            # NedTwo_p edge-star potentials with the regularised local problem
+            # eq:local-potential-problem-added-mass: (phi, eps psi) +
+            # a(d phi, d psi), eps = 1e-8 beta (curl grad = 0 makes the
+            # unregularised problem singular)
+            if len(self.removed):
+                raise ValueError("the H(div) Hiptmair-Toselli potentials are built for pure Neumann problems")
+            from .element import element
+            from .mesh import Topology
+            from .operator import all_cell_matrices, assemble
+            el2 = element(top.d, "NedTwo", top.el.p)
+            top2 = Topology(top.coords, top.cells, el2)
+            M2 = assemble(top2, all_cell_matrices(el2, top2, alpha=0.0, beta=1.0))
+            eps = 1e-8 * beta
+            for S, G in nedtwo_curl_potentials(top, top2, full):
+                Ap = eps * M2[S][:, S].toarray() + (G.T @ (A @ G)).toarray()
+                self.potentials.append((G, sla.cho_factor(Ap, lower=True)))
         W = whitney_dofs(top, k)
         self.W = W[keep[W]]
         self.mg = None

@@ -14,7 +14,9 @@
   J(X^k_I) and the full vertex stars PAFW(0)(X^k) for every space; for
   H(curl) PH(X^0, X^{1,I}), PH(X^0_Gamma, X^1_Gamma) + J(X^1_I) and
   PH(X^0, X^1); for H(div) PAFW(1)(X^2), PH(X^{1,I}_Gamma, X^{2,I}_Gamma) +
-  J(X^2_I) and PH(X^{1,I}, X^{2,I}) -- to the same bars.  These pin the
+  J(X^2_I) and PH(X^{1,I}, X^{2,I}), and the standard Hiptmair-Toselli
+  PH(X^1_Gamma, X^2_Gamma) + J(X^2_I) and PH(X^1, X^2) with the
+  epsilon-regularised NedTwo potentials -- to the same bars.  These pin the
   star lists (with or without the cell interiors, type-I or every kind),
   the full potentials, the empty interior group of the full forms and the
   same weights and sweep.
