@@ -154,6 +154,26 @@ typedef enum {
   RZ_DECOMP_TYPEI_FULL = 7
 } rz_decomposition;
 
+/* Solver on the Whitney space W^k (the coarse space of every decomposition).
+ * RZ_COARSE_EXACT: an exact solve with the explicit dense inverse of the
+ * Whitney principal submatrix A[W, W] (weight 1 in the hybrid sweep).
+ * RZ_COARSE_MG: the geometric multigrid V-cycle of the paper's experiments
+ * (Sec. 7.1, fig:solver-diagram-PAFW, fig:solver-diagram-PH) over the mesh
+ * hierarchy in rz_options.mg_meshes: Whitney prolongations between the
+ * nested meshes (exact, since Whitney forms are nested), Galerkin operators
+ * P^T A P below A[W, W], two damped relaxation steps before and after the
+ * coarse correction -- point-Jacobi (W^0), Hiptmair-Jacobi, i.e. the
+ * vertex-hat gradients plus point-Jacobi on the Whitney edge functions
+ * (W^1, eq:hiptmair-smoothing at lowest order), edge-star patches (W^2) --
+ * each step x += omega S (b - A x) with omega = 1 / rho, rho = (lambda_min +
+ * 3 lambda_max) / 4 of S A from 10 CG steps (SplitMix64 right-hand side
+ * seeded 0x5EED3000 + level); an explicit inverse on the coarsest mesh.  In
+ * the hybrid sweep the cycle gets its own weight rho_W by the same rule
+ * (seed 0x5EED4000).  3D only, pure Neumann only (RZ_ERR_UNSUPPORTED
+ * otherwise); RZ_ERR_MESH when the hierarchy does not match the problem's
+ * mesh or is not nested. */
+typedef enum { RZ_COARSE_EXACT = 0, RZ_COARSE_MG = 1 } rz_coarse;
+
 typedef struct {
   double alpha;           /* coefficient of (d u, d v), >= 0 */
   double beta;            /* coefficient of (u, v), > 0 */
@@ -178,6 +198,14 @@ typedef struct {
                              there, and rz_solve ignores b and returns x = 0 on them.  The preconditioner's
                              patches, potentials and coarse space are restricted the same way (columns that
                              touch a removed dof are dropped). */
+  int32_t coarse;         /* rz_coarse: the solver on the Whitney space W^k (0: RZ_COARSE_EXACT) */
+  int32_t mg_levels;      /* RZ_COARSE_MG: number of meshes in mg_meshes (>= 2) */
+  const rz_mesh *mg_meshes; /* RZ_COARSE_MG: the nested hierarchy, finest first, host.  mg_meshes[0] has the
+                             problem's vertices (same count and numbering) and cells (same list), with the
+                             vertex positions at which the hierarchy is nested (the problem's own
+                             coordinates may be a perturbation of them); every entity of mesh l lies in a
+                             cell of mesh l + 1.  Only the coordinates of these meshes and the cells of the
+                             coarser ones are read. */
 } rz_options;
 
 typedef struct {
@@ -283,7 +311,8 @@ int rz_patch_set_apply(rz_problem *P, int32_t set, const double *r, double *z, i
 int rz_dirichlet_dofs(const rz_problem *P, int64_t *n, int32_t *dofs);
 
 /* The hybrid group weights rho (host, 3 entries: interior, interface,
- * coarse); all 1 for an additive handle. */
+ * coarse; the coarse weight is 1 for the exact coarse solve); all 1 for an
+ * additive handle. */
 int rz_pc_weights(const rz_problem *P, double *rho);
 
 /* Host copies of the numbering for parity checks: cell_dofs (n_cells x n_loc

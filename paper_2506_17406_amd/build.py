@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librz.so")
-SOURCES = ["csrc/refelem.cpp", "csrc/topology.cpp", "csrc/kernels.hip", "csrc/capi.hip"]
+SOURCES = ["csrc/refelem.cpp", "csrc/topology.cpp", "csrc/multigrid.cpp", "csrc/kernels.hip", "csrc/capi.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

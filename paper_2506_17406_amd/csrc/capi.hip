@@ -20,6 +20,7 @@
 
 #include "../../include/rz.h"
 #include "kernels.hpp"
+#include "multigrid.hpp"
 #include "refelem.hpp"
 #include "topology.hpp"
 
@@ -66,6 +67,10 @@ struct rz_problem {
   double *scratch = nullptr;  // this device's static work array (rz_apply_A_noalloc)
   // Dirichlet boundary: input facet flags, the removed dofs (ascending), their
   // device mask (n_dofs bytes) and list; bm holds the masked right-hand sides
+  // the W^k solver: exact (dense inverse) or the multigrid V-cycle
+  int coarse = RZ_COARSE_EXACT;
+  rz::MgDev mgdev{};
+  double rho_W = 1.0;
   std::vector<uint8_t> dir_flags;
   std::vector<int32_t> dir_dofs;
   const uint8_t *dmask = nullptr;
@@ -400,6 +405,112 @@ void setup_coarse(rz_problem &P, hipStream_t s) {
   P.ca.NT = NT;
   P.ca.wdofs = P.upload(wdofs, s);
   P.ca.tiles = tiles;
+  P.ca.mg = nullptr;
+  P.ca.wscale = 1.0;
+}
+
+// The geometric multigrid V-cycle on W^k over the caller's mesh hierarchy
+// (in place of the dense coarse inverse): host set-up of the levels, then
+// upload.  The Whitney block A[W, W] is assembled on the host from the
+// element's Whitney sub-blocks and the geometric weights.
+void setup_multigrid(rz_problem &P, const rz_mesh *m, const rz_options *o, hipStream_t s) {
+  if (P.d != 3) throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for tetrahedral meshes"};
+  if (!P.dir_dofs.empty())
+    throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for pure Neumann problems"};
+  if (o->mg_levels < 2 || !o->mg_meshes) throw RzError{RZ_ERR_ARG, "multigrid needs mg_levels >= 2 meshes"};
+  const rz_mesh *H = o->mg_meshes;
+  for (int l = 0; l < o->mg_levels; ++l)
+    if (H[l].dim != 3 || !H[l].coords || !H[l].cells || H[l].n_vertices <= 0 || H[l].n_cells <= 0)
+      throw RzError{RZ_ERR_ARG, "bad mesh in the multigrid hierarchy"};
+  if (H[0].n_vertices != m->n_vertices || H[0].n_cells != m->n_cells ||
+      std::memcmp(H[0].cells, m->cells, sizeof(int64_t) * 4 * m->n_cells) != 0)
+    throw RzError{RZ_ERR_MESH, "the finest hierarchy mesh must have the problem's vertices and cells"};
+  const int k = P.k;
+  // level topologies (entity lists of the lowest-order element)
+  rz::RefElement el1 = rz::build_reference(3, P.fam, 1);
+  std::vector<rz::Topology> coarse_tops;
+  coarse_tops.reserve(o->mg_levels);
+  std::vector<const rz::Topology *> tops{&P.top};
+  std::vector<const double *> X{H[0].coords};
+  for (int l = 1; l < o->mg_levels; ++l) {
+    coarse_tops.push_back(rz::build_topology(3, H[l].n_vertices, H[l].n_cells, H[l].cells, el1));
+    tops.push_back(&coarse_tops.back());
+    X.push_back(H[l].coords);
+  }
+  // A[W, W] from the Whitney sub-blocks of the cell matrices
+  std::vector<int32_t> wdofs, wloc, widx;
+  int nwl = 0;
+  rz::whitney_dofs(P.top, P.el, wdofs, wloc, widx, nwl);
+  const int nW = int(wdofs.size());
+  const int64_t nc = P.top.n_cells;
+  const int Q = P.el.Q, n = P.el.n;
+  std::vector<double> w(size_t(nc) * Q);
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpy(w.data(), P.w, w.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<int64_t> tr;
+  std::vector<int32_t> tc;
+  std::vector<double> tv;
+  for (int64_t c = 0; c < nc; ++c)
+    for (int a = 0; a < nwl; ++a)
+      for (int b = 0; b < nwl; ++b) {
+        double v = 0.0;
+        for (int q = 0; q < Q; ++q) v += w[c * Q + q] * P.el.R[(size_t(q) * n + wloc[a]) * n + wloc[b]];
+        tr.push_back(widx[c * nwl + a]);
+        tc.push_back(widx[c * nwl + b]);
+        tv.push_back(v);
+      }
+  const rz::Csr AW = rz::csr_from_triplets(nW, nW, tr, tc, tv);
+  rz::MgHierarchy Hm;
+  try {
+    Hm = rz::build_multigrid(k, AW, tops, X, 2);
+  } catch (const std::invalid_argument &e) {
+    throw RzError{RZ_ERR_MESH, e.what()};
+  }
+  if (int(Hm.lev.size()) > 12) throw RzError{RZ_ERR_UNSUPPORTED, "at most 12 multigrid levels"};
+  rz::MgDev &D = P.mgdev;
+  D.k = k;
+  D.nu = Hm.nu;
+  D.L = int(Hm.lev.size());
+  for (int l = 0; l < D.L; ++l) {
+    const rz::MgLevel &lv = Hm.lev[l];
+    rz::MgDevLevel &dl = D.lev[l];
+    dl.n = lv.A.n_rows;
+    dl.Ap = P.upload(lv.A.ptr, s), dl.Ac = P.upload(lv.A.col, s), dl.Av = P.upload(lv.A.val, s);
+    if (l + 1 == D.L) break;
+    dl.Pp = P.upload(lv.P.ptr, s), dl.Pc = P.upload(lv.P.col, s), dl.Pv = P.upload(lv.P.val, s);
+    dl.Rp = P.upload(lv.R.ptr, s), dl.Rc = P.upload(lv.R.col, s), dl.Rv = P.upload(lv.R.val, s);
+    dl.omega = lv.omega;
+    if (!lv.dinv.empty()) dl.dinv = P.upload(lv.dinv, s);
+    if (k == 1) {
+      dl.nv = lv.Gt.n_rows;
+      dl.Gp = P.upload(lv.G.ptr, s), dl.Gc = P.upload(lv.G.col, s), dl.Gv = P.upload(lv.G.val, s);
+      dl.Gtp = P.upload(lv.Gt.ptr, s), dl.Gtc = P.upload(lv.Gt.col, s), dl.Gtv = P.upload(lv.Gt.val, s);
+      dl.gdiag = P.upload(lv.gdiag, s);
+    }
+    if (k == 2) {
+      for (size_t e = 0; e + 1 < lv.star_ptr.size(); ++e)
+        if (lv.star_ptr[e + 1] - lv.star_ptr[e] > 8)
+          throw RzError{RZ_ERR_UNSUPPORTED, "multigrid: an edge with more than 8 faces"};
+      dl.nstar = int64_t(lv.star_ptr.size()) - 1;
+      dl.sp = P.upload(lv.star_ptr, s), dl.sf = P.upload(lv.star_face, s), dl.so = P.upload(lv.inv_off, s);
+      dl.sinv = P.upload(lv.inv, s);
+    }
+  }
+  D.cinv = P.upload(Hm.coarse_inv, s);
+  P.ca.nW = nW;
+  P.ca.NT = std::max(1, (nW + 63) / 64);
+  P.ca.wdofs = P.upload(wdofs, s);
+  P.ca.tiles = nullptr;
+  P.ca.mg = &P.mgdev;
+  P.ca.wscale = 1.0;
+  P.coarse = RZ_COARSE_MG;
+  if (P.pc == RZ_PC_HYBRID) {
+    // the V-cycle is an inexact solver: its own weight, as for the other groups
+    P.rho_W = rz::lanczos_weight(
+        nW, [&](const double *x, double *y) { rz::csr_apply(AW, x, y); },
+        [&](const double *r, double *z) { rz::mg_cycle_host(Hm, r, z); }, 0x5EED4000ull);
+    P.ca.wscale = 1.0 / P.rho_W;
+  }
 }
 
 void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
@@ -527,6 +638,8 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     P->decomp = opts->decomposition;
     if (opts->dirichlet_facet)
       P->dir_flags.assign(opts->dirichlet_facet, opts->dirichlet_facet + m->n_cells * (m->dim + 1));
+    if (opts->coarse != RZ_COARSE_EXACT && opts->coarse != RZ_COARSE_MG)
+      return fail(RZ_ERR_ARG, "unknown coarse solver");
   }
   P->fam = space == RZ_HGRAD ? rz::FAM_CG : (space == RZ_HCURL ? rz::FAM_NED : rz::FAM_RT);
   try {
@@ -600,7 +713,10 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     // interface patches and coarse space
     P->dps.resize(P->patches.size());
     for (size_t i = 0; i < P->patches.size(); ++i) setup_patch_set(*P, P->patches[i], P->dps[i], s);
-    setup_coarse(*P, s);
+    if (opts && opts->coarse == RZ_COARSE_MG)
+      setup_multigrid(*P, m, opts, s);
+    else
+      setup_coarse(*P, s);
     if (P->precision != RZ_FP64) {
       // FP32 copies: the inverses (both modes) and the operator tables (refinement)
       auto lo = [&](const double *a, int64_t count) {
@@ -637,7 +753,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
       // the coarse inverse stays FP32 under RZ_BF16_PC: its condition grows
       // like h^-2, and a bfloat16 copy loses definiteness on modest meshes
       // (the patch matrices are local and stay well conditioned)
-      P->ca.tiles32 = lo(P->ca.tiles, int64_t(P->ca.NT) * (P->ca.NT + 1) / 2 * 4096);
+      if (P->ca.tiles) P->ca.tiles32 = lo(P->ca.tiles, int64_t(P->ca.NT) * (P->ca.NT + 1) / 2 * 4096);
       HIPCHK(hipGetLastError());
     }
     for (auto &d : P->dps) P->pas.push_back(d.pa);
@@ -691,7 +807,7 @@ int rz_pc_weights(const rz_problem *P, double *rho) {
   if (!P || !rho) return fail(RZ_ERR_ARG, "null argument");
   rho[0] = P->rho_I;
   rho[1] = P->rho_G;
-  rho[2] = 1.0;
+  rho[2] = P->rho_W;
   return RZ_OK;
 }
 
@@ -779,8 +895,18 @@ static void ensure_ws(rz_problem *P, int ncol) {
     P->dx = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
   }
   if (P->dlist) P->bm = static_cast<double *>(alloc(sizeof(double) * nd * ncol));
+  for (int l = 0; l < P->mgdev.L; ++l) {
+    rz::MgDevLevel &dl = P->mgdev.lev[l];
+    if (l > 0) {
+      dl.b = static_cast<double *>(alloc(sizeof(double) * dl.n * ncol));
+      dl.x = static_cast<double *>(alloc(sizeof(double) * dl.n * ncol));
+    }
+    dl.t = static_cast<double *>(alloc(sizeof(double) * dl.n * ncol));
+    dl.z = static_cast<double *>(alloc(sizeof(double) * dl.n * ncol));
+    if (dl.nv) dl.u = static_cast<double *>(alloc(sizeof(double) * dl.nv * ncol));
+  }
   P->ws_cols = ncol;
-  if (ncol >= 8 && !P->ca.full) {
+  if (ncol >= 8 && !P->ca.full && P->ca.tiles) {
     // many columns: the coarse solve becomes a GEMM over a full copy of the inverse
     const int NT = P->ca.NT;
     double *full = P->dev<double>(size_t(NT) * NT * 4096);

@@ -1279,12 +1279,12 @@ __global__ void k_jacobi_add_m(int64_t n, int64_t offI, const double *__restrict
 // coarse correction d = R_W^T zW (d zero elsewhere beforehand), z += d
 __global__ void k_coarse_scatter2_m(int nW, int npad, const int32_t *__restrict__ wd, const double *__restrict__ zW,
                                     int64_t n, double *__restrict__ d, double *__restrict__ z, int64_t ldz,
-                                    const PcgState *st) {
+                                    const PcgState *st, double wscale) {
   const int c = blockIdx.y;
   if (st && st[c].done) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nW) {
-    const double v = zW[int64_t(c) * npad + i];
+    const double v = wscale * zW[int64_t(c) * npad + i];
     d[c * n + wd[i]] = v;
     z[c * ldz + wd[i]] += v;
   }
@@ -1565,7 +1565,143 @@ void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, doub
   patch_dispatch<double>(pa, pa.inv_off, pa.inv, r, ldr, z, ldz, ncol, scale, st, s);
 }
 
+// ---- geometric multigrid V-cycle on W^k (small sparse levels; one thread
+// per row, columns in blockIdx.y)
+// t = b - A x (and z = 0 when zero_z: the edge-star relaxation accumulates there)
+__global__ void k_mg_resid(int64_t n, const int64_t *__restrict__ ap, const int32_t *__restrict__ ac,
+                           const double *__restrict__ av, const double *__restrict__ b, int64_t ldb,
+                           const double *__restrict__ x, int64_t ldx, double *__restrict__ t, double *__restrict__ z) {
+  const int c = blockIdx.y;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double *xc = x + c * ldx;
+  double sum = 0.0;
+  for (int64_t e = ap[i]; e < ap[i + 1]; ++e) sum += av[e] * xc[ac[e]];
+  t[c * n + i] = b[c * ldb + i] - sum;
+  if (z) z[c * n + i] = 0.0;
+}
+// y = A x (add: y += A x), y with leading dimension ldy
+__global__ void k_mg_spmv(int64_t n, int64_t nx, const int64_t *__restrict__ ap, const int32_t *__restrict__ ac,
+                          const double *__restrict__ av, const double *__restrict__ x, double *__restrict__ y,
+                          int64_t ldy, int add) {
+  const int c = blockIdx.y;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double *xc = x + c * nx;
+  double sum = 0.0;
+  for (int64_t e = ap[i]; e < ap[i + 1]; ++e) sum += av[e] * xc[ac[e]];
+  y[c * ldy + i] = add ? y[c * ldy + i] + sum : sum;
+}
+// point-Jacobi step x += omega dinv t
+__global__ void k_mg_jacobi(int64_t n, const double *__restrict__ dinv, double omega, const double *__restrict__ t,
+                            double *__restrict__ x, int64_t ldx) {
+  const int c = blockIdx.y;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[c * ldx + i] += omega * dinv[i] * t[c * n + i];
+}
+// Hiptmair-Jacobi, vertex part: u_v = gdiag_v (G^T t)_v
+__global__ void k_mg_grad_t(int64_t nv, int64_t n, const int64_t *__restrict__ gp, const int32_t *__restrict__ gc,
+                            const double *__restrict__ gv, const double *__restrict__ gdiag,
+                            const double *__restrict__ t, double *__restrict__ u) {
+  const int c = blockIdx.y;
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  double sum = 0.0;
+  for (int64_t e = gp[v]; e < gp[v + 1]; ++e) sum += gv[e] * t[c * n + gc[e]];
+  u[c * nv + v] = gdiag[v] * sum;
+}
+// Hiptmair-Jacobi step: x += omega (dinv t + G u)
+__global__ void k_mg_hiptmair(int64_t n, int64_t nv, const double *__restrict__ dinv, const int64_t *__restrict__ gp,
+                              const int32_t *__restrict__ gc, const double *__restrict__ gv, double omega,
+                              const double *__restrict__ t, const double *__restrict__ u, double *__restrict__ x,
+                              int64_t ldx) {
+  const int c = blockIdx.y;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = dinv[i] * t[c * n + i];
+  for (int64_t e = gp[i]; e < gp[i + 1]; ++e) s += gv[e] * u[c * nv + gc[e]];
+  x[c * ldx + i] += omega * s;
+}
+// edge-star relaxation: z[faces of E] += A_E^{-1} t[faces of E], one thread per star
+__global__ void k_mg_stars(int64_t nstar, int64_t n, const int64_t *__restrict__ sp, const int32_t *__restrict__ sf,
+                           const int64_t *__restrict__ so, const double *__restrict__ sinv, const double *__restrict__ t,
+                           double *__restrict__ z) {
+  const int c = blockIdx.y;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nstar) return;
+  const int64_t f0 = sp[e];
+  const int m = int(sp[e + 1] - f0);
+  const double *Ai = sinv + so[e];
+  double tl[8];
+  for (int a = 0; a < m && a < 8; ++a) tl[a] = t[c * n + sf[f0 + a]];
+  for (int a = 0; a < m && a < 8; ++a) {
+    double acc = 0.0;
+    for (int b = 0; b < m && b < 8; ++b) acc += Ai[a * m + b] * tl[b];
+    atomicAdd(&z[c * n + sf[f0 + a]], acc);
+  }
+}
+__global__ void k_mg_axpy(int64_t n, double omega, const double *__restrict__ z, double *__restrict__ x, int64_t ldx) {
+  const int c = blockIdx.y;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[c * ldx + i] += omega * z[c * n + i];
+}
+// coarsest level: x = cinv b (dense, row-major)
+__global__ void k_mg_dense(int64_t n, const double *__restrict__ cinv, const double *__restrict__ b, int64_t ldb,
+                           double *__restrict__ x, int64_t ldx) {
+  const int c = blockIdx.y;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t j = 0; j < n; ++j) s += cinv[i * n + j] * b[c * ldb + j];
+  x[c * ldx + i] = s;
+}
+
+static void mg_level(const MgDev &mg, int l, const double *b, int64_t ldb, double *x, int64_t ldx, int ncol,
+                     hipStream_t s) {
+  const MgDevLevel &L = mg.lev[l];
+  const int64_t n = L.n;
+  const dim3 gn(grid_for(n, 256), ncol);
+  if (l == mg.L - 1) {
+    hipLaunchKernelGGL(k_mg_dense, gn, dim3(256), 0, s, n, mg.cinv, b, ldb, x, ldx);
+    return;
+  }
+  hipLaunchKernelGGL(k_fill_m, dim3(grid_for(n, 256, 2048), ncol), dim3(256), 0, s, x, n, ldx, nullptr);
+  auto smooth = [&]() {
+    hipLaunchKernelGGL(k_mg_resid, gn, dim3(256), 0, s, n, L.Ap, L.Ac, L.Av, b, ldb, x, ldx, L.t,
+                       mg.k == 2 ? L.z : nullptr);
+    if (mg.k == 0) {
+      hipLaunchKernelGGL(k_mg_jacobi, gn, dim3(256), 0, s, n, L.dinv, L.omega, L.t, x, ldx);
+    } else if (mg.k == 1) {
+      hipLaunchKernelGGL(k_mg_grad_t, dim3(grid_for(L.nv, 256), ncol), dim3(256), 0, s, L.nv, n, L.Gtp, L.Gtc,
+                         L.Gtv, L.gdiag, L.t, L.u);
+      hipLaunchKernelGGL(k_mg_hiptmair, gn, dim3(256), 0, s, n, L.nv, L.dinv, L.Gp, L.Gc, L.Gv, L.omega, L.t, L.u, x,
+                         ldx);
+    } else {
+      hipLaunchKernelGGL(k_mg_stars, dim3(grid_for(L.nstar, 128), ncol), dim3(128), 0, s, L.nstar, n, L.sp, L.sf,
+                         L.so, L.sinv, L.t, L.z);
+      hipLaunchKernelGGL(k_mg_axpy, gn, dim3(256), 0, s, n, L.omega, L.z, x, ldx);
+    }
+  };
+  for (int k = 0; k < mg.nu; ++k) smooth();
+  hipLaunchKernelGGL(k_mg_resid, gn, dim3(256), 0, s, n, L.Ap, L.Ac, L.Av, b, ldb, x, ldx, L.t, nullptr);
+  const MgDevLevel &C = mg.lev[l + 1];
+  hipLaunchKernelGGL(k_mg_spmv, dim3(grid_for(C.n, 256), ncol), dim3(256), 0, s, C.n, n, L.Rp, L.Rc, L.Rv, L.t, C.b,
+                     C.n, 0);
+  mg_level(mg, l + 1, C.b, C.n, C.x, C.n, ncol, s);
+  hipLaunchKernelGGL(k_mg_spmv, gn, dim3(256), 0, s, n, C.n, L.Pp, L.Pc, L.Pv, C.x, x, ldx, 1);
+  for (int k = 0; k < mg.nu; ++k) smooth();
+}
+
+void launch_mg_cycle(const MgDev &mg, const double *b0, int64_t ldb0, double *x0, int64_t ldx0, int ncol,
+                     hipStream_t s) {
+  mg_level(mg, 0, b0, ldb0, x0, ldx0, ncol, s);
+}
+
 void launch_coarse_tiles(const CoarseApply &ca, int ncol, const PcgState *st, hipStream_t s, bool lo) {
+  if (ca.mg) {
+    launch_mg_cycle(*ca.mg, ca.rW, int64_t(ca.NT) * 64, ca.zW, int64_t(ca.NT) * 64, ncol, s);
+    return;
+  }
   const unsigned nt = unsigned(int64_t(ca.NT) * (ca.NT + 1) / 2);
   const int npad = ca.NT * 64;
   if (ncol >= 8 && ca.full) {
@@ -1684,7 +1820,7 @@ void launch_coarse_gather(const CoarseApply &ca, const double *r, int64_t ldr, i
 void launch_coarse_scatter2(const CoarseApply &ca, int64_t n, double *d, double *z, int64_t ldz, int ncol,
                             const PcgState *st, hipStream_t s) {
   hipLaunchKernelGGL(k_coarse_scatter2_m, dim3(grid_for(ca.nW, 256), ncol), dim3(256), 0, s, ca.nW, ca.NT * 64,
-                     ca.wdofs, ca.zW, n, d, z, ldz, st);
+                     ca.wdofs, ca.zW, n, d, z, ldz, st, ca.wscale);
 }
 __global__ void k_zero_rows(const int32_t *__restrict__ rows, int64_t nrows, double *__restrict__ y, int64_t ld) {
   const int c = blockIdx.y;

@@ -104,6 +104,33 @@ struct PatchApply {
   const uint16_t *inv16;    // bfloat16 copy (V = 8), or null
   const int64_t *inv_off16;
 };
+// Geometric multigrid V-cycle on W^k (device data; host-resident struct).
+// Level l: operator A (CSR), prolongation P from level l+1 and R = P^T,
+// relaxation data (k = 0: dinv; k = 1: dinv, vertex-hat gradients G and
+// G^T, gdiag = 1 / (g^T A g); k = 2: edge stars with dense inverses), the
+// damping omega, and work vectors (per column: n entries of b, x, t, z and
+// nv of u).  The last level is solved with the dense inverse cinv.
+struct MgDevLevel {
+  int64_t n = 0;
+  const int64_t *Ap = nullptr, *Pp = nullptr, *Rp = nullptr, *Gp = nullptr, *Gtp = nullptr, *sp = nullptr,
+                *so = nullptr;
+  const int32_t *Ac = nullptr, *Pc = nullptr, *Rc = nullptr, *Gc = nullptr, *Gtc = nullptr, *sf = nullptr;
+  const double *Av = nullptr, *Pv = nullptr, *Rv = nullptr, *Gv = nullptr, *Gtv = nullptr, *sinv = nullptr;
+  const double *dinv = nullptr, *gdiag = nullptr;
+  int64_t nv = 0, nstar = 0;
+  double omega = 1.0;
+  double *b = nullptr, *x = nullptr, *t = nullptr, *z = nullptr, *u = nullptr;
+};
+struct MgDev {
+  int k = 0, nu = 2;
+  MgDevLevel lev[12];
+  int L = 0;
+  const double *cinv = nullptr;
+};
+// x0 = V-cycle(b0) for ncol columns (level-0 vectors at b0 + c ldb0, x0 + c ldx0)
+void launch_mg_cycle(const MgDev &mg, const double *b0, int64_t ldb0, double *x0, int64_t ldx0, int ncol,
+                     hipStream_t s);
+
 struct CoarseApply {
   int nW, NT;               // coarse size, tiles per side
   const int32_t *wdofs;
@@ -112,6 +139,8 @@ struct CoarseApply {
   const double *full;       // all NT x NT tiles in MFMA fragment order (many-column solves), or null
   const float *tiles32;     // FP32 copy of the upper tiles (mixed precision) or null
   const uint8_t *dmask;     // removed (Dirichlet) dofs read as zero by the coarse gather, or null
+  const MgDev *mg = nullptr;  // the W^k solver is this V-cycle (null: the dense inverse in tiles)
+  double wscale = 1.0;        // weight 1 / rho_W of the hybrid sweep's coarse correction (1: exact solve)
 };
 // builds CoarseApply::full from the packed upper tiles
 void launch_coarse_expand(int NT, const double *tiles, double *full, hipStream_t s);

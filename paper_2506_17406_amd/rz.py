@@ -42,7 +42,12 @@ class RzOptions(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("pc", ctypes.c_int32),
                 ("eager", ctypes.c_int32), ("decomposition", ctypes.c_int32),
-                ("dirichlet_facet", ctypes.POINTER(ctypes.c_uint8))]
+                ("dirichlet_facet", ctypes.POINTER(ctypes.c_uint8)), ("coarse", ctypes.c_int32),
+                ("mg_levels", ctypes.c_int32), ("mg_meshes", ctypes.POINTER(RzMesh))]
+
+
+RZ_COARSE_EXACT, RZ_COARSE_MG = 0, 1
+COARSE = {"exact": RZ_COARSE_EXACT, "mg": RZ_COARSE_MG}
 
 
 class RzInfo(ctypes.Structure):
@@ -176,9 +181,11 @@ class Problem:
 
     def __init__(self, coords, cells, degree, space, alpha=1.0, beta=1.0, max_iter=1000, precision="fp64",
                  inner_rtol=0.0, pc="hybrid", graphs=True, stream=None, decomposition="paper",
-                 dirichlet_facet=None):
+                 dirichlet_facet=None, coarse="exact", mg_meshes=None):
         """dirichlet_facet: None (pure Neumann) or (n_cells, dim + 1) flags, entry
-        (c, j) marking the facet of cell c opposite its j-th vertex as Gamma_D."""
+        (c, j) marking the facet of cell c opposite its j-th vertex as Gamma_D.
+        coarse: "exact" or "mg" (the V-cycle on W^k over mg_meshes, a list of
+        (coords, cells), finest first)."""
         m, keep = _mesh(coords, cells)
         prec = PRECISIONS[precision] if isinstance(precision, str) else precision
         dec = DECOMPOSITIONS[decomposition] if isinstance(decomposition, str) else decomposition
@@ -187,8 +194,17 @@ class Problem:
             flags = np.ascontiguousarray(dirichlet_facet, dtype=np.uint8)
             if flags.shape != (m.n_cells, m.dim + 1):
                 raise ValueError("dirichlet_facet must have shape (n_cells, dim + 1)")
+        levels, keep_mg = None, []
+        if mg_meshes is not None:
+            levels = (RzMesh * len(mg_meshes))()
+            for i, (Xl, Cl) in enumerate(mg_meshes):
+                levels[i], kl = _mesh(Xl, Cl)
+                keep_mg.append(kl)
         opts = RzOptions(alpha, beta, max_iter, prec, inner_rtol, PCS[pc] if isinstance(pc, str) else pc,
-                         0 if graphs else 1, dec, None if flags is None else _ptr(flags, ctypes.c_uint8))
+                         0 if graphs else 1, dec, None if flags is None else _ptr(flags, ctypes.c_uint8),
+                         COARSE[coarse] if isinstance(coarse, str) else coarse,
+                         0 if mg_meshes is None else len(mg_meshes),
+                         None if levels is None else ctypes.cast(levels, ctypes.POINTER(RzMesh)))
         h = ctypes.c_void_p()
         self._h = None
         self.space = SPACES[space] if isinstance(space, str) else space
