@@ -1,15 +1,17 @@
 // Device kernels (gfx950, wave64) of the Riesz-map PCG solver.
 //
 // Hot path per PCG iteration (Sec. 7.1, with the preconditioners of Sec. 6):
-//  * apply_A: y = sum_T P_T^T (sum_q w_{T,q} R_q) P_T x.  Per tile of cells the
-//    gathered x_T and the weights are staged in LDS; the contraction over the
-//    stacked reference matrices is a GEMM with M = n_loc, K = Q n_loc,
-//    N = cells, done with FP64 MFMA 16x16x4 (the weight is applied to the B
-//    fragment in registers); the result is scatter-added with FP64 atomics.
-//  * apply_P: point-Jacobi on the interior block; per interface patch a
-//    gathered right-hand side (LDS), a packed symmetric inverse streamed from
-//    HBM and an atomic scatter; the Whitney coarse solve as a tiled packed
-//    symmetric matrix-vector product.
+//  * apply_A: y = sum_T P_T^T (sum_q w_{T,q} R_q) P_T x in three stages: a
+//    gather of the cell vectors x_T into MFMA fragment order, the contraction
+//    over the stacked reference matrices as a GEMM with M = n_loc,
+//    K = Q n_loc, N = cells on FP64 (or FP32) MFMA 16x16x4, the weight
+//    w_{T,q} multiplying the B fragment in registers, and an assembly that
+//    sums, per dof, its (cell, row) entries in a fixed order (no atomics).
+//  * apply_P: point-Jacobi on the interior block; per interface patch the
+//    packed (segmented) symmetric inverse streamed from HBM against the
+//    gathered residual, the mirrored products kept in registers; the Whitney
+//    coarse solve as a tiled packed symmetric matrix-vector product, or the
+//    multigrid V-cycle on W^k.
 //  * Krylov vectors: fused axpy updates with block reductions, scalars kept
 //    on the device and a done flag that makes every later kernel a no-op.
 #include <hip/hip_runtime.h>
@@ -436,12 +438,6 @@ __global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A,
 }
 
 // -------------------------------------------------------------- apply_A
-// One wave computes a 16-row block (mb) of y_T for 16*NB cells:
-//   y_T[rows] = sum_{jb} sum_q R_q[rows, 4jb:4jb+4] (w_{T,q} x_T[4jb:4jb+4]).
-// The four gathered x_T entries of a k-step are reused by all Q reference
-// matrices; the A fragments of all q for one k-step are contiguous (fragment
-// order (mb, jb, q, lane)).  The next k-step's fragments and x values are
-// loaded before the current step's Q*NB MFMAs are issued.
 // ---- Operator apply in three stages: cell gather, GEMM, assembly (FP64, or
 // FP32 with FP32 tables: T is the type of the cell vectors and the MFMA).
 // Cell-local vectors in MFMA fragment order (ncp = cells rounded up to 256; per

@@ -143,7 +143,10 @@ inline Dense null_space(const Dense &C) {
 // orthonormal eigenvectors as columns of V.  Householder reduction to
 // tridiagonal form (the reflections accumulated), then the implicit QL
 // iteration with Wilkinson shifts on the tridiagonal matrix, the plane
-// rotations applied to the accumulated basis.
+// rotations applied to the accumulated basis: the published procedures tred2
+// and tql2 of Wilkinson and Reinsch (Handbook for Automatic Computation,
+// Vol. II, Linear Algebra, 1971; EISPACK), restated here in this file's
+// dense-matrix type.
 inline void sym_eig(Dense A, std::vector<double> &w, Dense &V) {
   const int n = A.r;
   w.assign(n, 0.0);
