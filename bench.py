@@ -530,9 +530,12 @@ def mixed_leg(args):
     from paper_2506_17406_amd import rz
     from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
     X, C = kuhn_mesh(16, 3, jitter=0.1, seed=4)
+    hierarchy = [kuhn_mesh(m, 3) for m in (16, 8, 4, 2, 1)]
     out, ref = {}, None
-    for mode in ("fp64", "fp32-ir", "bf16-pc"):
-        prob = rz.Problem(X, C, 6, "Ned", pc=args.pc, precision=mode)
+    for mode in ("fp64", "fp32-ir", "bf16-pc", "fp64+mg", "bf16-pc+mg"):
+        prec, _, coarse = mode.partition("+")
+        prob = rz.Problem(X, C, 6, "Ned", pc=args.pc, precision=prec, coarse=coarse or "exact",
+                          mg_meshes=hierarchy if coarse else None)
         b = torch.from_numpy(load_vectors(prob.n_dofs, 5)[:, 0]).cuda()
         x = torch.zeros_like(b)
         dt, info = _timed_solve(prob, b, x, args.leg_steps)
@@ -551,10 +554,11 @@ def mixed_leg(args):
         prob.close()
         del b, x, y
         torch.cuda.empty_cache()
-    ok = [m for m in ("fp32-ir", "bf16-pc") if out[m]["true_rel_residual"] <= 1.2e-10]
+    ok = [m for m in out if m != "fp64" and out[m]["true_rel_residual"] <= 1.2e-10]
     best = min(ok, key=lambda m: out[m]["ms"]) if ok else "fp64"
     return {"workload": "H(curl) Ned_6 Riesz map, jittered Kuhn 16^3x6 = 24576 tets, 3,181,344 dofs, to a true "
-                        "FP64 rel. residual 1e-10", "modes": out, "best": best,
+                        "FP64 rel. residual 1e-10; '+mg': the multigrid V-cycle on W^1 over the Kuhn meshes "
+                        "16, 8, 4, 2, 1 in place of the dense coarse inverse", "modes": out, "best": best,
             "speedup_vs_fp64": out["fp64"]["ms"] / out[best]["ms"]}
 
 
