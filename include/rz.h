@@ -293,8 +293,10 @@ int rz_solve(rz_problem *P, const double *b, double *x, int32_t n_rhs, int64_t l
  * apply), one at a time.  rz_patch_set_info: the number of families of the
  * handle (*n_sets; H(curl) under RZ_DECOMP_PAPER: the edge stars, then the
  * vertex-star potentials), and for family `set` its patch count, largest
- * patch, the FP64 entries stored for its inverses (segmented upper rows:
- * row i holds the columns from its 16-byte segment on) and the entries of the
+ * patch, the FP64 entries stored for its inverses (families of patches up
+ * to 128 dofs: segmented upper rows, row i holding the columns from its
+ * 16-byte segment on; larger ones: folded pair rows, ceil(m/2) + 1 rows of
+ * 2 hP entries, hP = ceil(m/2) rounded up to 8) and the entries of the
  * packed upper triangles sum m (m + 1) / 2, and sum m.  Any output pointer
  * may be NULL; with only n_sets requested any `set` is accepted.
  * rz_patch_set_apply: z += sum over the patches m of the family of

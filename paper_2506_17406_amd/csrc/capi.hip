@@ -210,6 +210,7 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
     throw RzError{RZ_ERR_UNSUPPORTED, "interface patch of " + std::to_string(maxsz) + " dofs exceeds " +
                                           std::to_string(rz::kMaxPatch)};
   const int E = 2;  // FP64 segment length
+  const bool fold = maxsz > rz::kFoldMin;
   const int N = std::max(32, round_up(maxsz, 32));
   std::vector<int32_t> sizes(B);
   std::vector<int64_t> off(B);
@@ -217,7 +218,7 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
   for (int64_t b = 0; b < B; ++b) {
     sizes[b] = int32_t(ps.patch_col[b + 1] - ps.patch_col[b]);
     off[b] = tot;
-    tot += rz::seg_size(sizes[b], E);
+    tot += fold ? rz::fold_size(sizes[b], 8) : rz::seg_size(sizes[b], E);
   }
   double *inv = P.dev<double>(tot);
   const int64_t budget = int64_t(6) << 30;  // bytes for A + L^{-1} per chunk
@@ -278,7 +279,8 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
     rz::launch_patch_assemble(i1 - i0, d_ip, d_ic, d_it, t_col, t_loc, t_coef, P.el.n, P.el.Q, P.R, P.w, N, Abuf,
                               s);
     rz::launch_chol_inverse(nb, N, Abuf, Lbuf, dstatus, s);
-    rz::launch_pack_seg(nb, N, E, dsizes + p0, doff + p0, Abuf, inv, s);
+    if (fold) rz::launch_pack_fold(nb, N, dsizes + p0, doff + p0, Abuf, inv, s);
+    else rz::launch_pack_seg(nb, N, E, dsizes + p0, doff + p0, Abuf, inv, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
   }
@@ -291,18 +293,20 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
 #ifndef RZ_CHUNK
 #define RZ_CHUNK 32768
 #endif
-// patches above 1024 dofs take chunks of at least 64 rows: every chunk
-// gathers the patch's right-hand side and adds its column products to the
-// whole remaining column range with atomics, so short chunks of long rows
-// spend a large share on those (measured: 8-17% faster applies of the
-// 1080-1980-dof patches than with 32k-entry chunks; 32 and 128 rows were
-// slower on some sets)
-#ifndef RZ_BIG_ROWS
-#define RZ_BIG_ROWS 64
-#endif
-  for (int64_t b = 0; b < B; ++b) {
+  for (int64_t b = 0; b < B && fold; ++b) {
+    // folded: chunks of equal pair-row counts (2 hP entries each)
     const int m = sizes[b];
-    const int64_t target = m > 1024 ? std::max<int64_t>(RZ_CHUNK, int64_t(RZ_BIG_ROWS) * m) : RZ_CHUNK;
+    const int h = (m + 1) / 2;
+    const int rows = int(std::max<int64_t>(1, RZ_CHUNK / (2 * int64_t(rz::fold_hp(m, 8)))));
+    for (int r0 = 0; r0 <= h; r0 += rows) {
+      chunk_patch.push_back(b);
+      chunk_rows.push_back(r0);
+      chunk_rows.push_back(std::min(h + 1, r0 + rows));
+    }
+  }
+  for (int64_t b = 0; b < B && !fold; ++b) {
+    const int m = sizes[b];
+    const int64_t target = RZ_CHUNK;
     int r0 = 0;
     int64_t acc = 0;
     for (int i = 0; i < m; ++i) {
@@ -316,11 +320,33 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
       }
     }
   }
+  // folded sets in XCD-aware order: workgroups go to the 8 XCDs round robin
+  // (block j to XCD j % 8), so block j = 8 i + x takes chunk start[x] + i of
+  // XCD x's contiguous eighth of the list; the chunks of one patch then share
+  // one XCD's L2 for the patch's gather and scatter maps and right-hand side
+  // (measured 3-5% faster on the 625-855-dof star sets; slower on sets of
+  // one or two chunks per patch, which keep the patch order)
+  const int64_t nck = int64_t(chunk_patch.size());
+  if (fold && nck > 8) {
+    const int64_t q = nck / 8, rem = nck % 8;
+    std::vector<int64_t> cp(nck);
+    std::vector<int32_t> cr(2 * nck);
+    for (int64_t j = 0; j < nck; ++j) {
+      const int64_t x = j % 8, i = j / 8;
+      const int64_t src = x * q + std::min<int64_t>(x, rem) + i;  // i < q + (x < rem)
+      cp[j] = chunk_patch[src];
+      cr[2 * j] = chunk_rows[2 * src];
+      cr[2 * j + 1] = chunk_rows[2 * src + 1];
+    }
+    chunk_patch.swap(cp);
+    chunk_rows.swap(cr);
+  }
   out.pa.n_patches = B;
-  out.pa.n_chunks = int64_t(chunk_patch.size());
+  out.pa.n_chunks = nck;
   out.pa.chunk_patch = P.upload(chunk_patch, s);
   out.pa.chunk_rows = P.upload(chunk_rows, s);
   out.pa.max_size = maxsz;
+  out.pa.fold = fold ? 1 : 0;
   out.pa.n_entries = tot;
   out.pa.patch_col = P.upload(ps.patch_col, s);
   out.pa.col_ent = P.upload(ps.col_ent, s);
@@ -735,17 +761,17 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
         int64_t totl = 0;
         for (size_t b = 0; b < d.sizes.size(); ++b) {
           offl[b] = totl;
-          totl += rz::seg_size(int(d.sizes[b]), VL);
+          totl += d.pa.fold ? rz::fold_size(int(d.sizes[b]), bf16 ? 2 : 4) : rz::seg_size(int(d.sizes[b]), VL);
         }
         const int64_t *doff = P->upload(offl, s);
         if (bf16) {
           uint16_t *inv16 = P->dev<uint16_t>(size_t(totl));
-          rz::launch_seg_to_bf16(d.pa.n_patches, d.pa.patch_col, d.pa.inv_off, doff, d.pa.inv, inv16, s);
+          rz::launch_seg_to_bf16(d.pa.n_patches, d.pa.patch_col, d.pa.inv_off, doff, d.pa.inv, inv16, d.pa.fold, s);
           d.pa.inv16 = inv16;
           d.pa.inv_off16 = doff;
         } else {
           float *inv32 = P->dev<float>(size_t(totl));
-          rz::launch_seg_to_float(d.pa.n_patches, d.pa.patch_col, d.pa.inv_off, doff, d.pa.inv, inv32, s);
+          rz::launch_seg_to_float(d.pa.n_patches, d.pa.patch_col, d.pa.inv_off, doff, d.pa.inv, inv32, d.pa.fold, s);
           d.pa.inv32 = inv32;
           d.pa.inv_off32 = doff;
         }

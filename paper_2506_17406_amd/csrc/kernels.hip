@@ -423,6 +423,33 @@ __global__ void k_pack_seg(int N, int E, const int32_t *__restrict__ sizes, cons
 // 2q + 1 of its slice) per lane c.
 __device__ __host__ inline int ctile_idx(int r, int c) { return (r >> 4) * 1024 + ((r & 15) >> 1) * 128 + c * 2 + (r & 1); }
 
+// the folded layout (see kFoldMin) of the upper triangles of the inverses
+__global__ void k_pack_fold(int N, const int32_t *__restrict__ sizes, const int64_t *__restrict__ off,
+                            const double *__restrict__ A, double *__restrict__ P) {
+  const int64_t b = blockIdx.x;
+  const int m = sizes[b];
+  const int h = (m + 1) / 2, hP = fold_hp(m, 8);
+  const double *M = A + b * N * N;
+  double *out = P + off[b];
+  const int64_t total = int64_t(h + 1) * 2 * hP;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int k = int(e / (2 * hP)), q = int(e % (2 * hP));
+    double v = 0.0;
+    if (q < hP) {
+      const int p = q;
+      if (p >= k) {
+        if (p < h) v = (p == k ? 0.5 : 1.0) * M[int64_t(k) * N + p];
+      } else if (h + k - 1 < m) {
+        v = (p == k - 1 ? 0.5 : 1.0) * M[int64_t(h + p) * N + h + k - 1];
+      }
+    } else {
+      const int p = q - hP;
+      if (k < h && h + p < m) v = M[int64_t(k) * N + h + p];
+    }
+    out[e] = v;
+  }
+}
+
 __global__ void k_pack_tiles(int N, int n, int NT, const double *__restrict__ A, double *__restrict__ T) {
   const int64_t t = blockIdx.x;
   // decode upper tile (I <= J): t = I*NT - I(I-1)/2 + (J - I)
@@ -603,7 +630,10 @@ __global__ void k_axpy_m(int64_t n, const double *__restrict__ d, double *__rest
 // cache) are read with non-temporal loads; smaller ones may stay cached
 // from one apply to the next (measured over the sweep's patch sets and
 // coarse inverses).
-constexpr int64_t kStreamBytes = int64_t(192) << 20;
+#ifndef RZ_STREAM_MB
+#define RZ_STREAM_MB 192
+#endif
+constexpr int64_t kStreamBytes = int64_t(RZ_STREAM_MB) << 20;
 
 // Patch solves z += R_p^T A_p^{-1} R_p r for a chunk of rows of one patch
 // (NT: the rows are read with non-temporal loads, for sets too large to stay
@@ -752,6 +782,193 @@ __global__ __launch_bounds__(64 * NW) void k_patch_seg(const int64_t *__restrict
   }
 }
 
+// Patch solves from the folded layout (see kFoldMin): a chunk of pair rows
+// k in [k0, k1) of one patch, G right-hand sides (blockIdx.y).  A wave works
+// on 64 / L pair rows at a time, L lanes each; lane t owns positions
+// p = q V L + t V + [0, V), q < NQ, of both halves, i.e. the fixed columns p
+// (first half, p < h) and h + p (second half, and the trailing block's rows
+// in the first half).  Per entry, with a = first-half entry and b =
+// second-half entry of pair row k:
+//   p >= k: a = A[k][p]:          y_k += a r_p,     y_p += a r_k
+//   p <  k: a = A[h+p][h+k-1]:    y_{h+k-1} += a r_{h+p},  y_{h+p} += a r_{h+k-1}
+//           b = A[k][h+p]:        y_k += b r_{h+p}, y_{h+p} += b r_k
+// The two row sums of a pair row are summed over its L lanes (DPP); the
+// column products stay in registers until the end of the chunk.  Every load
+// slot below hP carries an entry.
+#ifndef RZ_FOLD_RL
+#define RZ_FOLD_RL 8
+#endif
+template <int V, int L, int NQ, int G, int D, typename T, int NW, bool NT>
+__global__ __launch_bounds__(64 * NW) void k_patch_fold(const int64_t *__restrict__ chunk_patch,
+                                                    const int32_t *__restrict__ chunk_rows,
+                                                    const int64_t *__restrict__ patch_col,
+                                                    const int64_t *__restrict__ col_ent,
+                                                    const int32_t *__restrict__ ent_dof,
+                                                    const double *__restrict__ ent_coef,
+                                                    const int64_t *__restrict__ inv_off, const T *__restrict__ inv,
+                                                    const double *__restrict__ r, int64_t ldr, double *__restrict__ z,
+                                                    int64_t ldz, int ncol, double scale, const PcgState *st) {
+  typedef decltype(widen(T())) C;
+  constexpr int RPW = 64 / L;        // pair rows per wave step
+  constexpr int W = NQ * L * V;      // positions of a half (>= hP)
+  constexpr int W2 = 2 * W;          // LDS stride: patch dofs 0 .. 2W - 1
+  typedef T vecV __attribute__((ext_vector_type(V)));
+  const int cbase = blockIdx.y * G;
+  if (st) {
+    bool any = false;
+    for (int g = 0; g < G; ++g)
+      if (cbase + g < ncol && !st[cbase + g].done) any = true;
+    if (!any) return;
+  }
+  extern __shared__ double sm[];
+  double *yr = sm;            // G x W2 row products
+  double *rp = sm + G * W2;   // G x W2 gathered right-hand sides (zero padded)
+  double *yc = rp;            // after the rows: NW waves x G x W2 column products
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int slot = lane / L, t = lane % L;
+  const int64_t pt = chunk_patch[blockIdx.x];
+  const int k0 = chunk_rows[2 * blockIdx.x], k1 = chunk_rows[2 * blockIdx.x + 1];
+  const int64_t c0 = patch_col[pt];
+  const int m = int(patch_col[pt + 1] - c0);
+  const int h = (m + 1) >> 1, hP = fold_hp(m, int(sizeof(T)));
+  const T *A = inv + inv_off[pt];
+  auto load_row = [&](int k, bool ok, vecV *b1, vecV *b2) {
+    const T *row = A + int64_t(k) * 2 * hP;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int c = q * V * L + t * V;
+      if (ok && c < hP) {
+        b1[q] = NT ? __builtin_nontemporal_load(reinterpret_cast<const vecV *>(row + c))
+                   : *reinterpret_cast<const vecV *>(row + c);
+        b2[q] = NT ? __builtin_nontemporal_load(reinterpret_cast<const vecV *>(row + hP + c))
+                   : *reinterpret_cast<const vecV *>(row + hP + c);
+      } else {
+        b1[q] = vecV(0);
+        b2[q] = vecV(0);
+      }
+    }
+  };
+  // pair rows in flight: a ring of D buffers, D - 1 loads ahead of the
+  // products (with one buffer, the first row's load); the first loads are
+  // issued before the gather of the right-hand sides
+  const int step = NW * RPW;
+  const int niter = (k1 - k0 + step - 1) / step;
+  const int i0 = k0 + wave * RPW + slot;
+  constexpr int D0 = D == 1 ? 1 : D - 1;
+  vecV buf[D][2][NQ];
+#pragma unroll
+  for (int u = 0; u < D0; ++u) load_row(i0 + u * step, i0 + u * step < k1, buf[u][0], buf[u][1]);
+  for (int t2 = threadIdx.x; t2 < G * W2; t2 += 64 * NW) {
+    const int g = t2 / W2, j = t2 - g * W2;
+    double sv = 0;
+    if (j < m && cbase + g < ncol) {
+      const double *rc = r + int64_t(cbase + g) * ldr;
+      for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) sv += ent_coef[e] * rc[ent_dof[e]];
+    }
+    rp[t2] = sv;
+    yr[t2] = 0.0;
+  }
+  __syncthreads();
+  // the right-hand side values of the lane's columns: registers, or for
+  // FP64 entries with NQ V >= RZ_FOLD_RL LDS reads per pair row (fewer
+  // registers, more waves per SIMD: measured 2-5% faster on the 431-855-dof
+  // star sets).  Reduced-precision entries keep them in registers: an LDS
+  // read per entry would move 4-8 times the streamed bytes through LDS.
+  constexpr bool RL = sizeof(T) == 8 && NQ * V >= RZ_FOLD_RL;
+  C rA[RL ? 1 : NQ][G][V], rB[RL ? 1 : NQ][G][V], accA[NQ][G][V], accB[NQ][G][V];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int c = q * V * L + t * V + v;
+        if (!RL) {
+          rA[q][g][v] = C(rp[g * W2 + c]);
+          rB[q][g][v] = C(rp[g * W2 + h + c]);
+        }
+        accA[q][g][v] = C(0);
+        accB[q][g][v] = C(0);
+      }
+  for (int it = 0; it < niter; it += D) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int kk = it + u;
+      if (kk >= niter) break;  // uniform over the block
+      const int k = i0 + kk * step;
+      const int ka = k + (D - 1) * step;
+      if (D > 1 || kk > 0) load_row(ka, ka < k1, buf[(u + D - 1) % D][0], buf[(u + D - 1) % D][1]);
+      const bool ok = k < k1;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const C rk = ok ? C(rp[g * W2 + k]) : C(0);
+        const C rk2 = (ok && k >= 1) ? C(rp[g * W2 + h + k - 1]) : C(0);
+        C s1 = C(0), s2 = C(0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const C a = widen(buf[u][0][q][v]), b = widen(buf[u][1][q][v]);
+            const int c = q * V * L + t * V + v;
+            const C ra = RL ? C(rp[g * W2 + c]) : rA[RL ? 0 : q][g][v];
+            const C rb = RL ? C(rp[g * W2 + h + c]) : rB[RL ? 0 : q][g][v];
+            const bool up = c >= k;
+            const C a1 = up ? a : C(0), a2 = up ? C(0) : a;
+            s1 += a1 * ra + b * rb;
+            s2 += a2 * rb;
+            accA[q][g][v] += a1 * rk;
+            accB[q][g][v] += b * rk + a2 * rk2;
+          }
+        s1 = group_sum<L>(s1);
+        s2 = group_sum<L>(s2);
+        if (ok && t == 0) {
+          if (k < h) yr[g * W2 + k] = double(s1);
+          if (k >= 1) yr[g * W2 + h + k - 1] = double(s2);
+        }
+      }
+    }
+  }
+  // column products: sum the pair-row slots of the wave, then one LDS row
+  // per wave (first-half positions below h, and every second-half one)
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        C a = accA[q][g][v], b = accB[q][g][v];
+        if (L <= 16) a += __shfl_xor(a, 16, 64), b += __shfl_xor(b, 16, 64);
+        if (L <= 32) a += __shfl_xor(a, 32, 64), b += __shfl_xor(b, 32, 64);
+        accA[q][g][v] = a;
+        accB[q][g][v] = b;
+      }
+  __syncthreads();  // the column products overwrite the right-hand sides
+  if (slot == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int c = q * V * L + t * V + v;
+          double *row = yc + (wave * G + g) * W2;
+          if (c < h) row[c] = double(accA[q][g][v]);
+          row[h + c] = double(accB[q][g][v]);
+        }
+  }
+  __syncthreads();
+  for (int t2 = threadIdx.x; t2 < G * m; t2 += 64 * NW) {
+    const int g = t2 / m, j = t2 - g * m;
+    if ((j < h && j < k0) || cbase + g >= ncol) continue;
+    double cs = yc[g * W2 + j];
+    if (NW == 4)
+      cs = (cs + yc[(1 * G + g) * W2 + j]) + (yc[(2 * G + g) * W2 + j] + yc[(3 * G + g) * W2 + j]);
+    const double y = scale * (yr[g * W2 + j] + cs);
+    double *zc = z + int64_t(cbase + g) * ldz;
+    for (int64_t e = col_ent[c0 + j]; e < col_ent[c0 + j + 1]; ++e) atomicAdd(&zc[ent_dof[e]], ent_coef[e] * y);
+  }
+}
+
 // Reduced-precision copy of a patch inverse: from the V = 2 FP64 segmented
 // layout to the VT-element layout of T (VT = 16 bytes / sizeof(T))
 template <typename T, int VT>
@@ -767,6 +984,24 @@ __global__ void k_seg_to_low(const int64_t *__restrict__ patch_col, const int64_
     const double *ra = a + seg_row_off(i, m2, 2) - s2;
     T *rb = b + seg_row_off(i, mv, VT) - sv;
     for (int c = sv + threadIdx.x; c < mv; c += blockDim.x) rb[c] = from_f64<T>((c >= i && c < m) ? ra[c] : 0.0);
+  }
+}
+
+// Reduced-precision copy of a folded patch inverse: the halves of the pair
+// rows change length from the FP64 hP to that of T (zero padded)
+template <typename T, int VT>
+__global__ void k_fold_to_low(const int64_t *__restrict__ patch_col, const int64_t *__restrict__ off64,
+                              const int64_t *__restrict__ offlo, const double *__restrict__ A, T *__restrict__ B) {
+  const int64_t p = blockIdx.x;
+  const int m = int(patch_col[p + 1] - patch_col[p]);
+  const int h = (m + 1) / 2, h2 = fold_hp(m, 8), hv = fold_hp(m, int(sizeof(T)));
+  const double *a = A + off64[p];
+  T *b = B + offlo[p];
+  const int64_t total = int64_t(h + 1) * 2 * hv;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int64_t k = e / (2 * hv);
+    const int q = int(e % (2 * hv)), half = q / hv, c = q % hv;
+    b[e] = from_f64<T>(c < h2 ? a[k * 2 * h2 + half * h2 + c] : 0.0);
   }
 }
 
@@ -1429,15 +1664,30 @@ int64_t seg_size(int m, int V) {
   return seg_row_off(m, mS, V);
 }
 
+int64_t fold_size(int m, int esize) { return int64_t((m + 1) / 2 + 1) * 2 * fold_hp(m, esize); }
+
+void launch_pack_fold(int64_t B, int N, const int32_t *sizes, const int64_t *off, const double *Ainv,
+                      double *packed, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_fold, dim3(unsigned(B)), dim3(256), 0, s, N, sizes, off, Ainv, packed);
+}
+
 void launch_seg_to_float(int64_t n_patches, const int64_t *patch_col, const int64_t *off64, const int64_t *off32,
-                         const double *A, float *B, hipStream_t s) {
-  hipLaunchKernelGGL((k_seg_to_low<float, 4>), dim3(unsigned(n_patches)), dim3(256), 0, s, patch_col, off64, off32,
-                     A, B);
+                         const double *A, float *B, bool fold, hipStream_t s) {
+  if (fold)
+    hipLaunchKernelGGL((k_fold_to_low<float, 4>), dim3(unsigned(n_patches)), dim3(256), 0, s, patch_col, off64,
+                       off32, A, B);
+  else
+    hipLaunchKernelGGL((k_seg_to_low<float, 4>), dim3(unsigned(n_patches)), dim3(256), 0, s, patch_col, off64,
+                       off32, A, B);
 }
 void launch_seg_to_bf16(int64_t n_patches, const int64_t *patch_col, const int64_t *off64, const int64_t *off16,
-                        const double *A, uint16_t *B, hipStream_t s) {
-  hipLaunchKernelGGL((k_seg_to_low<uint16_t, 8>), dim3(unsigned(n_patches)), dim3(256), 0, s, patch_col, off64,
-                     off16, A, B);
+                        const double *A, uint16_t *B, bool fold, hipStream_t s) {
+  if (fold)
+    hipLaunchKernelGGL((k_fold_to_low<uint16_t, 8>), dim3(unsigned(n_patches)), dim3(256), 0, s, patch_col, off64,
+                       off16, A, B);
+  else
+    hipLaunchKernelGGL((k_seg_to_low<uint16_t, 8>), dim3(unsigned(n_patches)), dim3(256), 0, s, patch_col, off64,
+                       off16, A, B);
 }
 
 // rows in flight per lane group: deeper for short rows
@@ -1538,13 +1788,90 @@ static void patch_dispatch(const PatchApply &pa, const int64_t *off, const T *in
   patch_seg<V, 64, 32 / V, T>(pa, off, inv, r, ldr, z, ldz, ncol, scale, st, s);
 }
 
+template <int V, int L, int NQ, int G, typename T, bool NT>
+static void patch_fold_nt(const PatchApply &pa, const int64_t *off, const T *inv, dim3 grid, size_t lds,
+                          const double *r, int64_t ldr, double *z, int64_t ldz, int ncol, double scale,
+                          const PcgState *st, hipStream_t s) {
+#ifdef RZ_FOLD_D
+  constexpr int D = RZ_FOLD_D;
+#else
+  constexpr int D = patch_depth<2 * NQ * V, T>();
+#endif
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_patch_fold<V, L, NQ, G, D, T, 4, NT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_patch_fold<V, L, NQ, G, D, T, 4, NT>), grid, dim3(256), lds, s, pa.chunk_patch,
+                     pa.chunk_rows, pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, off, inv, r, ldr, z, ldz,
+                     ncol, scale, st);
+}
+
+template <int V, int L, int NQ, int G, typename T>
+static void patch_fold_g(const PatchApply &pa, const int64_t *off, const T *inv, dim3 grid, size_t lds,
+                         const double *r, int64_t ldr, double *z, int64_t ldz, int ncol, double scale,
+                         const PcgState *st, hipStream_t s) {
+  if (pa.n_entries * int64_t(sizeof(T)) > kStreamBytes)
+    patch_fold_nt<V, L, NQ, G, T, true>(pa, off, inv, grid, lds, r, ldr, z, ldz, ncol, scale, st, s);
+  else
+    patch_fold_nt<V, L, NQ, G, T, false>(pa, off, inv, grid, lds, r, ldr, z, ldz, ncol, scale, st, s);
+}
+
+// right-hand sides per block as for the segmented kernel, counting the four
+// per-position register arrays (2 NQ V values per array pair)
+template <int V, int L, int NQ, typename T>
+static void patch_fold_w(const PatchApply &pa, const int64_t *off, const T *inv, const double *r, int64_t ldr,
+                         double *z, int64_t ldz, int ncol, double scale, const PcgState *st, hipStream_t s) {
+  constexpr int W2 = 2 * NQ * L * V;
+  constexpr int VQ2 = 2 * NQ * V;
+  const size_t lds_per_g = size_t(1 + 4) * W2 * sizeof(double);
+  int G = 4;
+  while (G > 1 && (G > ncol || lds_per_g * G > 96 * 1024 || VQ2 * G > 32)) G /= 2;
+  const dim3 grid(unsigned(pa.n_chunks), unsigned((ncol + G - 1) / G));
+  if (G == 4)
+    patch_fold_g<V, L, NQ, (VQ2 <= 8 ? 4 : 1), T>(pa, off, inv, grid, lds_per_g * G, r, ldr, z, ldz, ncol, scale,
+                                                   st, s);
+  else if (G == 2)
+    patch_fold_g<V, L, NQ, (VQ2 <= 16 ? 2 : 1), T>(pa, off, inv, grid, lds_per_g * G, r, ldr, z, ldz, ncol,
+                                                    scale, st, s);
+  else patch_fold_g<V, L, NQ, 1, T>(pa, off, inv, grid, lds_per_g, r, ldr, z, ldz, ncol, scale, st, s);
+}
+
+// lanes per pair row and stripes covering hP positions of the largest patch
+template <typename T>
+static void fold_dispatch(const PatchApply &pa, const int64_t *off, const T *inv, const double *r, int64_t ldr,
+                          double *z, int64_t ldz, int ncol, double scale, const PcgState *st, hipStream_t s) {
+  constexpr int V = 16 / sizeof(T);
+  static_assert(kMaxPatch / 2 <= 64 * 16, "fold stripes cover at most 64 * 16 V positions");
+  const int hP = fold_hp(pa.max_size, int(sizeof(T)));
+  const int L = hP <= 16 * V ? 16 : (hP <= 32 * V ? 32 : 64);
+  const int nq = (hP + V * L - 1) / (V * L);
+  const int NQ = nq <= 1 ? 1 : nq <= 2 ? 2 : nq <= 4 ? 4 : nq <= 8 ? 8 : 16;
+#define RZ_FQ(LL, QQ)                                                                          \
+  if constexpr (QQ * V <= 16)                                                                  \
+    if (L == LL && NQ == QQ) return patch_fold_w<V, LL, QQ, T>(pa, off, inv, r, ldr, z, ldz, ncol, scale, st, s)
+  RZ_FQ(16, 1); RZ_FQ(32, 1); RZ_FQ(64, 1); RZ_FQ(64, 2); RZ_FQ(64, 4); RZ_FQ(64, 8);
+#undef RZ_FQ
+  patch_fold_w<V, 64, 16 / V, T>(pa, off, inv, r, ldr, z, ldz, ncol, scale, st, s);
+}
+
+template <typename T>
+static void patch_any(const PatchApply &pa, const int64_t *off, const T *inv, const double *r, int64_t ldr,
+                      double *z, int64_t ldz, int ncol, double scale, const PcgState *st, hipStream_t s) {
+  if (pa.fold) fold_dispatch<T>(pa, off, inv, r, ldr, z, ldz, ncol, scale, st, s);
+  else patch_dispatch<T>(pa, off, inv, r, ldr, z, ldz, ncol, scale, st, s);
+}
+
+static_assert(kSmallPatch < kFoldMin, "the multi-column GEMM path reads the segmented layout");
+
 void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
                         const PcgState *st, hipStream_t s, bool lo, double scale) {
   if (pa.n_chunks == 0) return;
   if (lo && pa.inv16)
-    return patch_dispatch<uint16_t>(pa, pa.inv_off16, pa.inv16, r, ldr, z, ldz, ncol, scale, st, s);
+    return patch_any<uint16_t>(pa, pa.inv_off16, pa.inv16, r, ldr, z, ldz, ncol, scale, st, s);
   if (lo && pa.inv32)
-    return patch_dispatch<float>(pa, pa.inv_off32, pa.inv32, r, ldr, z, ldz, ncol, scale, st, s);
+    return patch_any<float>(pa, pa.inv_off32, pa.inv32, r, ldr, z, ldz, ncol, scale, st, s);
   if (ncol >= 8 && pa.max_size <= kSmallPatch) {
     const int MP = (pa.max_size + 15) & ~15;
     const size_t lds = size_t(MP * (MP + 1) + MP * 65) * sizeof(double);
@@ -1558,7 +1885,7 @@ void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, doub
                        ncol, scale, st);
     return;
   }
-  patch_dispatch<double>(pa, pa.inv_off, pa.inv, r, ldr, z, ldz, ncol, scale, st, s);
+  patch_any<double>(pa, pa.inv_off, pa.inv, r, ldr, z, ldz, ncol, scale, st, s);
 }
 
 // ---- geometric multigrid V-cycle on W^k (small sparse levels; one thread

@@ -82,23 +82,54 @@ void launch_apply_A(const ApplyATables &t, const double *x, int64_t ldx, double 
 // V = 8 for bfloat16 copies.
 constexpr int kMaxPatch = 2048;
 int64_t seg_size(int m, int V);  // stored entries of one patch
+// Patch sets whose largest patch exceeds kFoldMin dofs store their inverses
+// in the folded layout instead: with h = ceil(m / 2) and hP = fold_hp (h
+// rounded up, below), pair row k = 0 .. h holds 2 hP entries; position p < hP of its
+// first half is A[k][p] for k <= p < h (row k of the leading h x h block)
+// or A[h + p][h + k - 1] for p < k (column k - 1 of the trailing block's
+// upper triangle), position p of its second half A[k][h + p] (row k of the
+// off-diagonal block); the diagonal halved, entries beyond m zero.  Every
+// upper-triangle entry is stored once, all pair rows have one length, and
+// a lane's positions stand for fixed columns (p and h + p).
+#ifndef RZ_FOLD_MIN
+#define RZ_FOLD_MIN 128
+#endif
+constexpr int kFoldMin = RZ_FOLD_MIN;
+// half-row length of the folded layout for entries of `esize` bytes --
+// hP: h rounded up to a multiple of max(16 bytes, RZ_FOLD_ALIGN_EL
+// entries): FP64 half rows start on 64-byte boundaries (measured 2-3%
+// faster streams of the 625-855-dof star sets than 16-byte alignment),
+// reduced-precision ones add at most 7 padding entries per half row
+#ifndef RZ_FOLD_ALIGN_EL
+#define RZ_FOLD_ALIGN_EL 8
+#endif
+__host__ __device__ inline int fold_hp(int m, int esize) {
+  const int a = 16 / esize > RZ_FOLD_ALIGN_EL ? 16 / esize : RZ_FOLD_ALIGN_EL;
+  return ((m + 1) / 2 + a - 1) / a * a;
+}
+int64_t fold_size(int m, int esize);  // stored entries of one patch, folded
+void launch_pack_fold(int64_t B, int N, const int32_t *sizes, const int64_t *off, const double *Ainv,
+                      double *packed, hipStream_t s);
+// FP32 copy of the patch inverses (V = 4), from the FP64 layout (segmented,
+// or folded when `fold`)
 void launch_seg_to_float(int64_t n_patches, const int64_t *patch_col, const int64_t *off64, const int64_t *off32,
-                         const double *A, float *B, hipStream_t s);
+                         const double *A, float *B, bool fold, hipStream_t s);
 // bfloat16 copy of the patch inverses (bits in uint16_t, round to nearest
-// even) in the V = 8 segmented layout
+// even) in the V = 8 layout
 void launch_seg_to_bf16(int64_t n_patches, const int64_t *patch_col, const int64_t *off64, const int64_t *off16,
-                        const double *A, uint16_t *B, hipStream_t s);
+                        const double *A, uint16_t *B, bool fold, hipStream_t s);
 
 struct PatchApply {
   int64_t n_patches, n_chunks;
   int64_t n_entries;        // stored entries of the set (FP64 copy)
   int max_size;
+  int fold;                    // 1: the folded layout (max_size > kFoldMin), 0: segmented rows
   const int64_t *chunk_patch;  // patch of each work chunk
-  const int32_t *chunk_rows;   // [r0, r1) row range of each chunk
+  const int32_t *chunk_rows;   // [r0, r1) row range (pair rows when folded) of each chunk
   const int64_t *patch_col, *col_ent, *inv_off;
   const int32_t *ent_dof;
   const double *ent_coef;
-  const double *inv;        // segmented upper rows per patch (V = 2)
+  const double *inv;        // segmented upper rows or folded pair rows per patch (V = 2)
   const float *inv32;       // FP32 copy (V = 4) for mixed precision, or null
   const int64_t *inv_off32; // its patch offsets
   const uint16_t *inv16;    // bfloat16 copy (V = 8), or null
