@@ -62,7 +62,10 @@ enum {
   RZ_ERR_OOM = -9               /* device allocation failed */
 };
 
-typedef enum { RZ_HGRAD = 0, RZ_HCURL = 1, RZ_HDIV = 2 } rz_space;
+/* The space: one of the constants below, passed as a 32-bit integer (an
+ * out-of-range value is an argument error, never undefined behaviour). */
+enum { RZ_HGRAD = 0, RZ_HCURL = 1, RZ_HDIV = 2 };
+typedef int32_t rz_space;
 
 typedef struct {
   int32_t dim;            /* 2 or 3 */

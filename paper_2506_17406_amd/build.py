@@ -50,5 +50,48 @@ def build(verbose=False, jobs=4):
     return LIB
 
 
+def build_host_sanitized(out_dir, verbose=False, jobs=4):
+    """The library with its host code built with AddressSanitizer and
+    UndefinedBehaviorSanitizer (the device code as usual), for
+    the CPU tests of the host-only entry points (reference tables,
+    numbering, patch lists, argument and mesh checks).  Load it with the
+    sanitizer runtime preloaded (see sanitizer_runtime) and RZ_LIBRARY set to
+    the returned path."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(out_dir, exist_ok=True)
+    flags = [f for f in HIPCC_FLAGS if f != "--offload-arch=gfx950"]
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined", "-O1", "-g"]
+    procs, objs = [], []
+    for src in SOURCES:
+        obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+        objs.append(obj)
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        cmd = [hipcc, "--offload-arch=gfx950"] + flags + san + lang + ["-c", os.path.join(HERE, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+    failed = []
+    for src, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            failed.append(src)
+            print(out.decode(errors="replace"), file=sys.stderr)
+    if failed:
+        raise RuntimeError("hipcc failed for " + ", ".join(failed))
+    lib = os.path.join(out_dir, "librz_hostsan.so")
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+                    "-Xarch_host", "-fsanitize=undefined", "-shared-libasan", "-o", lib] + objs, check=True)
+    return lib
+
+
+def sanitizer_runtime():
+    """Path of the clang AddressSanitizer runtime that a Python process must
+    preload to load the host-sanitizer build."""
+    out = subprocess.run(["/opt/rocm/llvm/bin/clang", "-print-file-name=libclang_rt.asan-x86_64.so"],
+                         capture_output=True, text=True, check=True).stdout.strip()
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))

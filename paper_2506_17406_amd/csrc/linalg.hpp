@@ -1,7 +1,7 @@
 // Small dense FP64 linear algebra for the host-side reference-element build:
 // row-major matrices, Householder QR with column pivoting (ranges and null
-// spaces), the cyclic Jacobi eigenvalue method for symmetric matrices, and LU
-// with partial pivoting.  Sizes are at most a few hundred, built once per
+// spaces), the symmetric eigenproblem (Householder tridiagonalisation and
+// implicit QL), and LU with partial pivoting.  Sizes are at most a few hundred, built once per
 // (dimension, space, degree).
 #pragma once
 #include <algorithm>
@@ -28,12 +28,13 @@ struct Dense {
 inline Dense matmul(const Dense &A, const Dense &B) {
   if (A.c != B.r) throw std::runtime_error("matmul shape");
   Dense C(A.r, B.c);
+  if (B.c == 0) return C;  // no columns: nothing to index
   for (int i = 0; i < A.r; ++i)
     for (int k = 0; k < A.c; ++k) {
       const double aik = A(i, k);
       if (aik == 0.0) continue;
-      const double *b = &B.a[size_t(k) * B.c];
-      double *cc = &C.a[size_t(i) * C.c];
+      const double *b = B.a.data() + size_t(k) * B.c;
+      double *cc = C.a.data() + size_t(i) * C.c;
       for (int j = 0; j < B.c; ++j) cc[j] += aik * b[j];
     }
   return C;
@@ -182,7 +183,7 @@ inline void sym_eig(Dense A, std::vector<double> &w, Dense &V) {
     std::vector<double> pvec(i, 0.0);
     for (int j = 0; j <= l; ++j) {
       double sacc = 0.0;
-      const double *aj = &A.a[size_t(j) * n];
+      const double *aj = A.a.data() + (size_t(j) * n);
       for (int k = 0; k <= l; ++k) sacc += aj[k] * u[k];
       pvec[j] = sacc / h;
     }
@@ -191,7 +192,7 @@ inline void sym_eig(Dense A, std::vector<double> &w, Dense &V) {
     K /= (h + h);
     for (int j = 0; j <= l; ++j) pvec[j] -= K * u[j];
     for (int j = 0; j <= l; ++j) {
-      double *aj = &A.a[size_t(j) * n];
+      double *aj = A.a.data() + (size_t(j) * n);
       const double uj = u[j], qj = pvec[j];
       for (int k = 0; k <= l; ++k) aj[k] -= uj * pvec[k] + qj * u[k];
     }
@@ -208,7 +209,7 @@ inline void sym_eig(Dense A, std::vector<double> &w, Dense &V) {
     const std::vector<double> &u = hv[idx];
     // Z_rows: for every row r of Z (an eigenbasis vector), z[0..i-1] -= (u . z) u / h
     for (int r = 0; r < n; ++r) {
-      double *zr = &Z.a[size_t(r) * n];
+      double *zr = Z.a.data() + (size_t(r) * n);
       double sacc = 0.0;
       for (int k = 0; k < i; ++k) sacc += u[k] * zr[k];
       if (sacc == 0.0) continue;
@@ -255,7 +256,7 @@ inline void sym_eig(Dense A, std::vector<double> &w, Dense &V) {
         d[i + 1] = g + p;
         g = c * r - b;
         // rotate basis vectors i and i+1 (rows of Qt)
-        double *qa = &Qt.a[size_t(i) * n], *qb = &Qt.a[size_t(i + 1) * n];
+        double *qa = Qt.a.data() + (size_t(i) * n), *qb = Qt.a.data() + (size_t(i + 1) * n);
         for (int k = 0; k < n; ++k) {
           f = qb[k];
           qb[k] = s * qa[k] + c * f;

@@ -166,7 +166,7 @@ Csr whitney_prolongation(int k, const Topology &tf, const double *Xf, const Topo
   if (tc.d != 3 || tf.d != 3) throw std::invalid_argument("the multigrid hierarchy is built for tetrahedral meshes");
   const int64_t nc = tc.n_cells;
   std::vector<Dense> L(nc);
-  for (int64_t c = 0; c < nc; ++c) L[c] = barycentric(Xc, &tc.cells[c * 4]);
+  for (int64_t c = 0; c < nc; ++c) L[c] = barycentric(Xc, tc.cells.data() + (c * 4));
   // bucket grid over the coarse cells' bounding boxes
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int64_t v = 0; v < tc.n_vertices; ++v)
@@ -195,7 +195,7 @@ Csr whitney_prolongation(int k, const Topology &tf, const double *Xf, const Topo
   std::vector<int32_t> cols;
   std::vector<double> vals;
   for (int64_t e = 0; e < tf.n_ent[k]; ++e) {
-    const int64_t *tup = &tf.ent[k][e * (k + 1)];
+    const int64_t *tup = tf.ent[k].data() + (e * (k + 1));
     double xb[3] = {0, 0, 0};
     for (int a = 0; a <= k; ++a)
       for (int b = 0; b < 3; ++b) xb[b] += Xf[tup[a] * 3 + b] / (k + 1);
@@ -408,7 +408,7 @@ MgHierarchy build_multigrid(int k, const Csr &AW, const std::vector<const Topolo
       for (int64_t e = 0; e < t.n_ent[1]; ++e) eid[{t.ent[1][e * 2], t.ent[1][e * 2 + 1]}] = e;
       std::vector<std::vector<int32_t>> faces(t.n_ent[1]);
       for (int64_t f = 0; f < t.n_ent[2]; ++f) {
-        const int64_t *v = &t.ent[2][f * 3];
+        const int64_t *v = t.ent[2].data() + (f * 3);
         faces[eid.at({v[0], v[1]})].push_back(int32_t(f));
         faces[eid.at({v[0], v[2]})].push_back(int32_t(f));
         faces[eid.at({v[1], v[2]})].push_back(int32_t(f));

@@ -374,13 +374,13 @@ struct Space {
       for (int t = ch * 16; t < std::min(npts, ch * 16 + 16); ++t)
         for (int comp = 0; comp < c; ++comp)
           for (int b = 0; b < n; ++b) {
-            const double *crow = &coef.a[size_t(comp * n + b) * m];
+            const double *crow = coef.a.data() + (size_t(comp * n + b) * m);
             const double vb = V[size_t(t) * n + b];
-            double *vo = &vals[(size_t(t) * c + comp) * m];
+            double *vo = vals.data() + ((size_t(t) * c + comp) * m);
             for (int j = 0; j < m; ++j) vo[j] += vb * crow[j];
             for (int a = 0; a < l; ++a) {
               const double gb = G[(size_t(t) * l + a) * n + b];
-              double *jo = &jac[((size_t(t) * c + comp) * l + a) * m];
+              double *jo = jac.data() + (((size_t(t) * c + comp) * l + a) * m);
               for (int j = 0; j < m; ++j) jo[j] += gb * crow[j];
             }
           }
@@ -397,7 +397,7 @@ void d_op(int k, int l, int c, int npts, int m, const std::vector<double> &jac, 
   auto J = [&](int t, int comp, int a, int j) { return jac[((size_t(t) * c + comp) * l + a) * m + j]; };
   for (int t = 0; t < npts; ++t)
     for (int j = 0; j < m; ++j) {
-      double *o = &out[size_t(t) * co * m + j];
+      double *o = out.data() + (size_t(t) * co * m + j);
       if (k == 0) {
         for (int a = 0; a < l; ++a) o[a * m] = J(t, 0, a, j);
       } else if (k == 1 && l == 2) {
@@ -470,7 +470,7 @@ std::shared_ptr<Space> make_space(int l, Family fam, int p) {
           for (int t = 0; t < nq; ++t) {
             double g[3] = {0, 0, 0};
             g[comp] = V[size_t(t) * n + b];
-            const double *x = &q.x[size_t(t) * 3];
+            const double *x = q.x.data() + (size_t(t) * 3);
             f[t * 3 + 0] = g[1] * x[2] - g[2] * x[1];
             f[t * 3 + 1] = g[2] * x[0] - g[0] * x[2];
             f[t * 3 + 2] = g[0] * x[1] - g[1] * x[0];
@@ -572,8 +572,8 @@ void trace(int k, const Dense &A, int npts, int c, int m, const std::vector<doub
       for (int b = 0; b < l; ++b)
         for (int a = 0; a < d; ++a) {
           const double w = A(a, b);
-          const double *vi = &vals[(size_t(t) * c + a) * m];
-          double *o = &out[(size_t(t) * l + b) * m];
+          const double *vi = vals.data() + ((size_t(t) * c + a) * m);
+          double *o = out.data() + ((size_t(t) * l + b) * m);
           for (int j = 0; j < m; ++j) o[j] += w * vi[j];
         }
     return;
@@ -585,8 +585,8 @@ void trace(int k, const Dense &A, int npts, int c, int m, const std::vector<doub
     out.assign(size_t(npts) * m, 0.0);
     for (int t = 0; t < npts; ++t)
       for (int a = 0; a < 3; ++a) {
-        const double *vi = &vals[(size_t(t) * c + a) * m];
-        double *o = &out[size_t(t) * m];
+        const double *vi = vals.data() + ((size_t(t) * c + a) * m);
+        double *o = out.data() + (size_t(t) * m);
         for (int j = 0; j < m; ++j) o[j] += nrm[a] * vi[j];
       }
     return;
@@ -660,7 +660,7 @@ std::shared_ptr<Eigen> eigenbasis(int l, Family fam, int p) {
         std::vector<double> row(m, 0.0);
         for (int t = 0; t < nq; ++t) {
           const double wt = fq.w[t] * T[size_t(t) * test.n + b];
-          const double *tv = &tr[(size_t(t) * ct + comp) * m];
+          const double *tv = tr.data() + ((size_t(t) * ct + comp) * m);
           for (int j = 0; j < m; ++j) row[j] += wt * tv[j];
         }
         rows.push_back(row);
@@ -686,7 +686,7 @@ std::shared_ptr<Eigen> eigenbasis(int l, Family fam, int p) {
   Dense K(nb, nb);
   for (int t = 0; t < nq; ++t)
     for (int comp = 0; comp < cd; ++comp) {
-      const double *v = &dv[(size_t(t) * cd + comp) * nb];
+      const double *v = dv.data() + ((size_t(t) * cd + comp) * nb);
       for (int i = 0; i < nb; ++i) {
         const double wi = q.w[t] * v[i];
         for (int j = 0; j < nb; ++j) K(i, j) += wi * v[j];
@@ -824,7 +824,7 @@ RefElement build_reference(int d, Family fam, int p) {
         for (int t = 0; t < nq; ++t)
           for (int a = 0; a < ct; ++a) {
             const double wv = q.w[t] * fn[size_t(t) * ct + a];
-            const double *tv = &tr[(size_t(t) * ct + a) * nfull];
+            const double *tv = tr.data() + ((size_t(t) * ct + a) * nfull);
             for (int b = 0; b < nfull; ++b) row[b] += wv * tv[b];
           }
         rows.push_back(row);
@@ -911,11 +911,11 @@ RefElement build_reference(int d, Family fam, int p) {
       for (int j0 = 0; j0 < n; j0 += TB) {
         const int i1 = std::min(n, i0 + TB), j1 = std::min(n, j0 + TB);
         for (int t = 0; t < nq; ++t) {
-          const double *fa = &F[(size_t(t) * cf + a) * n];
-          const double *fb = &F[(size_t(t) * cf + b) * n];
+          const double *fa = F.data() + ((size_t(t) * cf + a) * n);
+          const double *fb = F.data() + ((size_t(t) * cf + b) * n);
           for (int i = i0; i < i1; ++i) {
             const double wi = q.w[t] * fa[i];
-            double *rr = &R.a[size_t(i) * n];
+            double *rr = R.a.data() + (size_t(i) * n);
             for (int j = j0; j < j1; ++j) rr[j] += wi * fb[j];
           }
         }

@@ -43,7 +43,7 @@ Topology build_topology(int d, int64_t nv, int64_t nc, const int64_t *cells, con
   const int nvc = d + 1;
   t.cells.assign(cells, cells + nc * nvc);
   for (int64_t c = 0; c < nc; ++c) {
-    int64_t *cv = &t.cells[c * nvc];
+    int64_t *cv = t.cells.data() + (c * nvc);
     for (int a = 0; a < nvc; ++a)
       if (cv[a] < 0 || cv[a] >= nv) throw std::invalid_argument("cell vertex index out of range");
     std::sort(cv, cv + nvc);
@@ -162,7 +162,7 @@ Incidence incidence(const Topology &t) {
       throw std::logic_error("edge not found");
     };
     for (int64_t f = 0; f < t.n_ent[2]; ++f) {
-      const int64_t *v = &t.ent[2][f * 3];
+      const int64_t *v = t.ent[2].data() + (f * 3);
       in.e_faces[edge_id(v[0], v[1])].push_back(f);
       in.e_faces[edge_id(v[0], v[2])].push_back(f);
       in.e_faces[edge_id(v[1], v[2])].push_back(f);
@@ -268,7 +268,7 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
       for (int64_t f : in.e_faces[e]) {
         std::vector<int32_t> w;
         entity_dofs(t, el, 2, f, KIND_W, w);
-        const int64_t *v = &t.ent[2][f * 3];
+        const int64_t *v = t.ent[2].data() + (f * 3);
         cols[0].push_back({w[0], (a0 == v[0] && b0 == v[2]) ? -1.0 : 1.0});
       }
       auto add_typeII = [&](int l, int64_t ent) {

@@ -11,7 +11,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librz.so")
+# RZ_LIBRARY names another build of the same library (the host-sanitizer
+# build of the CPU tests); by default the in-tree librz.so
+LIB_PATH = os.environ.get("RZ_LIBRARY") or os.path.join(_HERE, "librz.so")
 
 RZ_HGRAD, RZ_HCURL, RZ_HDIV = 0, 1, 2
 SPACES = {"CG": RZ_HGRAD, "hgrad": RZ_HGRAD, "Ned": RZ_HCURL, "hcurl": RZ_HCURL, "RT": RZ_HDIV, "hdiv": RZ_HDIV}
