@@ -341,6 +341,40 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
     chunk_patch.swap(cp);
     chunk_rows.swap(cr);
   }
+  if (!fold) {
+    // the set's dofs with their (patch column, coefficient) entries, patch
+    // columns ascending: the fixed-order scatter of the multi-column solves
+    const int64_t SM = ps.patch_col[B], nE = ps.col_ent[SM], nd = P.top.n_dofs;
+    std::vector<int64_t> start(nd + 1, 0);
+    for (int64_t e = 0; e < nE; ++e) ++start[ps.ent_dof[e] + 1];
+    for (int64_t d = 0; d < nd; ++d) start[d + 1] += start[d];
+    std::vector<int64_t> pos(start.begin(), start.end() - 1);
+    std::vector<int32_t> apr(nE);
+    std::vector<double> acoef(nE);
+    for (int64_t pr = 0; pr < SM; ++pr)
+      for (int64_t e = ps.col_ent[pr]; e < ps.col_ent[pr + 1]; ++e) {
+        const int64_t k = pos[ps.ent_dof[e]]++;
+        apr[k] = int32_t(pr);
+        acoef[k] = ps.ent_coef[e];
+      }
+    std::vector<int32_t> adof;
+    std::vector<int64_t> aptr{0};
+    for (int64_t d = 0; d < nd; ++d)
+      if (start[d + 1] > start[d]) {
+        adof.push_back(int32_t(d));
+        aptr.push_back(start[d + 1]);
+      }
+    std::vector<int32_t> where(nd, -1), ent_a(nE);
+    for (size_t a = 0; a < adof.size(); ++a) where[adof[a]] = int32_t(a);
+    for (int64_t e = 0; e < nE; ++e) ent_a[e] = where[ps.ent_dof[e]];
+    out.pa.ent_a = P.upload(ent_a, s);
+    out.pa.sum_size = SM;
+    out.pa.n_adof = int64_t(adof.size());
+    out.pa.adof = P.upload(adof, s);
+    out.pa.aptr = P.upload(aptr, s);
+    out.pa.apr = P.upload(apr, s);
+    out.pa.acoef = P.upload(acoef, s);
+  }
   out.pa.n_patches = B;
   out.pa.n_chunks = nck;
   out.pa.chunk_patch = P.upload(chunk_patch, s);
@@ -882,6 +916,8 @@ static void ensure_ws(rz_problem *P, int ncol) {
   if (ncol <= P->ws_cols) return;
   P->free_ws();
   ++P->ws_gen;
+  for (auto &d : P->dps) d.pa.zb = d.pa.rt = nullptr, d.pa.zb_cols = 0;
+  for (auto &pa : P->pas) pa.zb = pa.rt = nullptr, pa.zb_cols = 0;
   const int64_t nd = P->top.n_dofs;
   const int RB = reduction_blocks(ncol);
   auto alloc = [&](size_t bytes) {
@@ -932,6 +968,46 @@ static void ensure_ws(rz_problem *P, int ncol) {
     if (dl.nv) dl.u = static_cast<double *>(alloc(sizeof(double) * dl.nv * ncol));
   }
   P->ws_cols = ncol;
+  if (ncol >= 8 && (P->precision == RZ_FP64 || P->precision == RZ_BF16_PC)) {
+    // many columns: the patch solves of the segmented sets become MFMA
+    // products over fragment-ordered copies of the inverses (FP64, or
+    // bfloat16 under RZ_BF16_PC), with one shared result buffer
+    const bool bf = P->precision == RZ_BF16_PC;
+    size_t zbytes = 0, rbytes = 0;
+    for (auto &d : P->dps) {
+      if (d.pa.fold || d.pa.n_patches == 0) continue;
+      if (!(bf ? (const void *)d.pa.frag16 : (const void *)d.pa.frag64)) {
+        std::vector<int64_t> off(d.sizes.size());
+        int64_t tot = 0;
+        for (size_t b = 0; b < d.sizes.size(); ++b) {
+          off[b] = tot;
+          tot += rz::frag_size(int(d.sizes[b]), bf);
+        }
+        const int64_t *doff = P->upload(off, nullptr);
+        if (bf) {
+          uint16_t *f = P->dev<uint16_t>(size_t(tot));
+          rz::launch_seg_to_frag(d.pa, true, f, doff, nullptr);
+          d.pa.frag16 = f;
+          d.pa.frag_off16 = doff;
+        } else {
+          double *f = P->dev<double>(size_t(tot));
+          rz::launch_seg_to_frag(d.pa, false, f, doff, nullptr);
+          d.pa.frag64 = f;
+          d.pa.frag_off64 = doff;
+        }
+      }
+      zbytes = std::max(zbytes, size_t(d.pa.sum_size) * ncol * (bf ? 4 : 8));
+      rbytes = std::max(rbytes, size_t(d.pa.n_adof) * ncol * 8);
+    }
+    if (zbytes) {
+      void *zb = alloc(zbytes), *rt = alloc(rbytes);
+      for (auto &d : P->dps)
+        if (!d.pa.fold) d.pa.zb = zb, d.pa.rt = rt, d.pa.zb_cols = ncol;
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipDeviceSynchronize());
+    for (size_t i = 0; i < P->dps.size() && i < P->pas.size(); ++i) P->pas[i] = P->dps[i].pa;
+  }
   if (ncol >= 8 && !P->ca.full && P->ca.tiles) {
     // many columns: the coarse solve becomes a GEMM over a full copy of the inverse
     const int NT = P->ca.NT;

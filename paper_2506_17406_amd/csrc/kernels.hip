@@ -1171,19 +1171,115 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(int NT, int nsplit, const d
   }
 }
 
-// One patch (m <= 96) and 64 columns per block: the packed inverse unpacked
-// to a full MP x MP matrix in LDS, the gathered right-hand sides MP x 64 in
-// LDS, Z = A R by FP64 MFMA, then the scatter-add.
-constexpr int kSmallPatch = 96;
-__global__ __launch_bounds__(256) void k_patch_gemm(const int64_t *__restrict__ patch_col,
-                                                    const int64_t *__restrict__ col_ent,
-                                                    const int32_t *__restrict__ ent_dof,
-                                                    const double *__restrict__ ent_coef,
-                                                    const int64_t *__restrict__ inv_off,
-                                                    const double *__restrict__ inv, int E,
-                                                    const double *__restrict__ r, int64_t ldr,
-                                                    double *__restrict__ z, int64_t ldz, int ncol, double scale,
-                                                    const PcgState *st) {
+// ---- multi-column patch solves on MFMA (sets of patches up to kFoldMin
+// dofs, 8 or more columns).  Each patch inverse is copied once into MFMA
+// A-fragment order (full MP x MP, zero padded); per block one patch and up
+// to 64 columns: the gathered right-hand sides are staged in LDS as B
+// fragments, one wave per 16-row block computes Z_p = A_p R_p for the four
+// 16-column blocks, and Z_p goes to a buffer indexed by patch column;
+// k_patch_zb_scatter then adds each dof's entries in a fixed order
+// (deterministic, no atomics).  The right-hand sides of the set's dofs are
+// first copied dof-major (k_patch_rt: rt[a * NC + c], NC the buffer's
+// columns) and the results are written dof-major too (zb[pr * NC + c]):
+// with the column-major vectors (columns 8 MB apart) each block touched
+// some 200 pages and the address translation thrashed.
+//   FP64 (mfma_f64_16x16x4f64): MP = m rounded up to 16; fragment (mb, kb)
+//     lane l = A[16 mb + l % 16][4 kb + l / 16]; B lane l = R[4 kb + l / 16]
+//     [16 nb + l % 16]; accumulator v = Z[16 mb + l / 16 + 4 v][16 nb + l % 16].
+//   bfloat16 (mfma_f32_16x16x32_bf16, FP32 accumulation): MP = m rounded up
+//     to 32; fragment (mb, kb) lane l, element j = A[16 mb + l % 16]
+//     [32 kb + 8 (l / 16) + j]; B likewise R[32 kb + 8 (l / 16) + j][16 nb +
+//     l % 16]; accumulator v = Z[16 mb + 4 (l / 16) + v][16 nb + l % 16].
+//     The right-hand sides are split r = r_hi + r_lo into two bfloat16 parts
+//     (their sum carries 16 significant bits) and both are multiplied, so
+//     the patch solve applies the bfloat16-stored inverse to r with FP32
+//     accumulation like the streamed kernels do.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename F>
+struct FragTraits;
+template <>
+struct FragTraits<double> {
+  static constexpr int KS = 4, MPA = 16;  // k per MFMA, padding of MP
+  typedef double A_t;
+  typedef double Z_t;
+};
+template <>
+struct FragTraits<uint16_t> {
+  static constexpr int KS = 32, MPA = 32;
+  typedef uint4 A_t;   // 8 bfloat16 bits
+  typedef float Z_t;
+};
+
+__device__ inline uint16_t bf16_bits(float v) {  // round to nearest even
+  uint32_t u = __float_as_uint(v);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+template <typename F>
+__global__ void k_seg_to_frag(const int64_t *__restrict__ patch_col, const int64_t *__restrict__ seg_off,
+                              const double *__restrict__ P, const int64_t *__restrict__ frag_off,
+                              F *__restrict__ out) {
+  constexpr int KS = FragTraits<F>::KS, MPA = FragTraits<F>::MPA;
+  const int64_t p = blockIdx.x;
+  const int m = int(patch_col[p + 1] - patch_col[p]);
+  const int MP = (m + MPA - 1) / MPA * MPA, KB = MP / KS, mS = (m + 1) / 2 * 2;
+  const double *S = P + seg_off[p];
+  F *o = out + frag_off[p];
+  const int64_t total = int64_t(MP) * MP;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    int i, k;
+    if constexpr (KS == 4) {  // e = (mb KB + kb) 64 + l
+      const int l = int(e & 63), blk = int(e >> 6);
+      i = 16 * (blk / KB) + (l & 15);
+      k = 4 * (blk % KB) + (l >> 4);
+    } else {                  // e = ((mb KB + kb) 64 + l) 8 + j
+      const int j = int(e & 7), l = int((e >> 3) & 63), blk = int(e >> 9);
+      i = 16 * (blk / KB) + (l & 15);
+      k = 32 * (blk % KB) + 8 * (l >> 4) + j;
+    }
+    double v = 0.0;
+    if (i < m && k < m) {
+      const int a = min(i, k), b = max(i, k);
+      v = (a == b ? 2.0 : 1.0) * S[seg_row_off(a, mS, 2) + b - a / 2 * 2];
+    }
+    if constexpr (KS == 4) o[e] = v;
+    else o[e] = bf16_bits(float(v));
+  }
+}
+
+// rt[a * NC + c] = r[c * ldr + adof[a]] for the set's dofs a and columns
+// c < ncol: a 64-dof x 64-column tile per block through LDS (reads along
+// columns, writes along dof rows)
+__global__ __launch_bounds__(256) void k_patch_rt(int64_t na, const int32_t *__restrict__ adof,
+                                                  const double *__restrict__ r, int64_t ldr, int ncol,
+                                                  double *__restrict__ rt, int NC) {
+  __shared__ double tile[64][65];
+  const int64_t a0 = int64_t(blockIdx.x) * 64;
+  const int c0 = blockIdx.y * 64;
+  const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t a = a0 + t;
+  const int32_t d = a < na ? adof[a] : 0;
+  for (int c = w; c < 64; c += 4)
+    tile[c][t] = (a < na && c0 + c < ncol) ? r[int64_t(c0 + c) * ldr + d] : 0.0;
+  __syncthreads();
+  for (int i = w; i < 64; i += 4)
+    if (a0 + i < na && c0 + t < ncol) rt[(a0 + i) * NC + c0 + t] = tile[t][i];
+}
+
+template <typename F, int MPMAX>
+__global__ __launch_bounds__(64 * (MPMAX / 16)) void k_patch_mfma(
+    const int64_t *__restrict__ patch_col, const int64_t *__restrict__ col_ent, const int32_t *__restrict__ ent_a,
+    const double *__restrict__ ent_coef, const int64_t *__restrict__ frag_off, const F *__restrict__ frag,
+    const double *__restrict__ rt, typename FragTraits<F>::Z_t *__restrict__ zb, int NC, int ncol,
+    const PcgState *st) {
+  constexpr int KS = FragTraits<F>::KS, MPA = FragTraits<F>::MPA;
+  constexpr bool BF = KS == 32;
+  typedef typename FragTraits<F>::A_t A_t;
+  typedef typename FragTraits<F>::Z_t Z_t;
+  typedef Z_t acc_t __attribute__((ext_vector_type(4)));
   const int64_t p = blockIdx.x;
   const int c0 = blockIdx.y * 64;
   if (st) {
@@ -1192,58 +1288,139 @@ __global__ __launch_bounds__(256) void k_patch_gemm(const int64_t *__restrict__ 
       if (!st[c].done) any = true;
     if (!any) return;
   }
+  // B fragments in LDS, in units U (FP64: one double; bfloat16: 8 halves):
+  // fragment (kb, nb) lane l at (kb 4 + nb) 68 + 17 (l / 16) + l % 16 -- each
+  // 16-lane group padded by one unit, so the gather's writes (lanes apart by
+  // one row k) fall in different banks; the bfloat16 lo parts follow the hi
+  // parts at KB 4 68 units
   extern __shared__ double sm[];
+  double *Rd = sm;
+  uint4 *Ru = reinterpret_cast<uint4 *>(sm);
+  uint16_t *Rh = reinterpret_cast<uint16_t *>(sm);
   const int64_t cb = patch_col[p];
   const int m = int(patch_col[p + 1] - cb);
-  const int MP = (m + 15) & ~15;
-  double *A = sm;              // MP x (MP + 1)
-  double *R = sm + MP * (MP + 1);  // MP x 65 (row k, column c)
-  const double *P = inv + inv_off[p];
-  const int mS = (m + E - 1) / E * E;
-  for (int t = threadIdx.x; t < MP * MP; t += 256) {
-    const int i = t / MP, j = t - i * MP;
-    double v = 0.0;
-    if (i < m && j < m) {
-      const int a = min(i, j), b = max(i, j);
-      v = (a == b ? 2.0 : 1.0) * P[seg_row_off(a, mS, E) + b - a / E * E];
-    }
-    A[i * (MP + 1) + j] = v;
-  }
-  for (int t = threadIdx.x; t < MP * 64; t += 256) {
-    const int c = t / MP, j = t - c * MP;
-    double v = 0.0;
-    if (j < m && c0 + c < ncol) {
-      const double *rc = r + int64_t(c0 + c) * ldr;
-      for (int64_t e = col_ent[cb + j]; e < col_ent[cb + j + 1]; ++e) v += ent_coef[e] * rc[ent_dof[e]];
-    }
-    R[j * 65 + c] = v;
-  }
-  __syncthreads();
+  const int MP = (m + MPA - 1) / MPA * MPA, KB = MP / KS;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int li = lane & 15, lk = lane >> 4;
-  const int nmb = MP / 16, nkb = MP / 4;
-  for (int mb = wave; mb < nmb; mb += 4) {
-    d4 acc[4];
-    for (int nb = 0; nb < 4; ++nb) acc[nb] = d4{0, 0, 0, 0};
-    for (int kb = 0; kb < nkb; ++kb) {
-      const double a = A[(mb * 16 + li) * (MP + 1) + kb * 4 + lk];
+  const int mb = wave;
+  const bool active = 16 * mb < MP;
+  // the wave's A fragments, loaded before the gather (they do not depend on it)
+  constexpr int KBMAX = MPMAX / KS;
+  A_t a[KBMAX];
+  if (active) {
+    const A_t *Af = reinterpret_cast<const A_t *>(frag + frag_off[p]) + int64_t(mb) * KB * 64 + lane;
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, R[(kb * 4 + lk) * 65 + nb * 16 + li], acc[nb], 0, 0, 0);
-    }
+    for (int kb = 0; kb < KBMAX; ++kb)
+      if (kb < KB) a[kb] = Af[kb * 64];
+  }
+  // gather: thread t takes patch column k = t % MP and the 16 columns of
+  // group t / MP (4 MP = the block's threads), its map entries loaded once
+  // and the 16 right-hand side values read as one dof-major row piece
+  {
+    const int t = threadIdx.x;
+    const int k = t % MP, cg = t / MP;
+    double v[16];
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      const int c = c0 + nb * 16 + li;
-      if (c >= ncol) continue;
-      double *zc = z + int64_t(c) * ldz;
+    for (int j = 0; j < 16; ++j) v[j] = 0.0;
+    if (cg < 4 && k < m) {
+      for (int64_t e = col_ent[cb + k]; e < col_ent[cb + k + 1]; ++e) {
+        const double *row = rt + int64_t(ent_a[e]) * NC + c0 + 16 * cg;
+        const double cf = ent_coef[e];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = mb * 16 + lk + 4 * v;
-        if (row < m)
-          for (int64_t e = col_ent[cb + row]; e < col_ent[cb + row + 1]; ++e)
-            atomicAdd(&zc[ent_dof[e]], scale * ent_coef[e] * acc[nb][v]);
+        for (int j = 0; j < 16; ++j)
+          if (c0 + 16 * cg + j < ncol) v[j] += cf * row[j];
       }
     }
+    if (cg < 4) {
+      if constexpr (!BF) {
+        double *dst = Rd + ((k >> 2) * 4 + cg) * 68 + (k & 3) * 17;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dst[j] = v[j];
+      } else {
+        const int kb = k >> 5, kk = k & 31;
+        const int u = ((kb * 4 + cg) * 68 + (kk >> 3) * 17) * 8 + (kk & 7);
+        const int lo = KB * 4 * 68 * 8;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const float vf = float(v[j]);
+          const uint16_t hi = bf16_bits(vf);
+          Rh[u + 8 * j] = hi;
+          Rh[lo + u + 8 * j] = bf16_bits(vf - __uint_as_float(uint32_t(hi) << 16));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+  acc_t acc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = acc_t{0, 0, 0, 0};
+  const int lu = (lane >> 4) * 17 + (lane & 15);
+#pragma unroll
+  for (int kb = 0; kb < KBMAX; ++kb) {
+    if (kb >= KB) break;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      if constexpr (!BF) {
+        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kb], Rd[(kb * 4 + nb) * 68 + lu], acc[nb], 0, 0, 0);
+      } else {
+        const int u = (kb * 4 + nb) * 68 + lu;
+        const bf16x8 av = __builtin_bit_cast(bf16x8, a[kb]);
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, Ru[u]);
+        const bf16x8 bl = __builtin_bit_cast(bf16x8, Ru[KB * 4 * 68 + u]);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bh, acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl, acc[nb], 0, 0, 0);
+      }
+    }
+  }
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int c = c0 + nb * 16 + li;
+    if (c >= ncol) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * mb + (BF ? 4 * lk + v : lk + 4 * v);
+      if (row < m) zb[(cb + row) * NC + c] = acc[nb][v];
+    }
+  }
+}
+
+// z[c][d] += scale sum_e coef_e zb[pr_e * NC + c] over the dofs d of a
+// patch set (ascending), entries in a fixed order: a 64-dof x 64-column
+// tile per block, the dof sums read along zb rows into LDS, then added to z
+// along columns
+template <typename Z>
+__global__ __launch_bounds__(256) void k_patch_zb_scatter(int64_t nd, const int32_t *__restrict__ dof,
+                                                          const int64_t *__restrict__ ptr,
+                                                          const int32_t *__restrict__ pr,
+                                                          const double *__restrict__ coef,
+                                                          const Z *__restrict__ zb, int NC,
+                                                          double *__restrict__ z, int64_t ldz, int ncol,
+                                                          double scale, const PcgState *st) {
+  __shared__ double tile[64][65];
+  const int64_t a0 = int64_t(blockIdx.x) * 64;
+  const int c0 = blockIdx.y * 64;
+  const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t a = a0 + t;
+  double v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = 0.0;
+  if (a < nd)
+    for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) {
+      const Z *row = zb + int64_t(pr[e]) * NC + c0 + 16 * w;
+      const double cf = coef[e];
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (c0 + 16 * w + j < ncol) v[j] += cf * double(row[j]);
+    }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) tile[16 * w + j][t] = v[j];
+  __syncthreads();
+  if (a >= nd) return;
+  const int64_t d = dof[a];
+  for (int c = w; c < 64; c += 4) {
+    const int cc = c0 + c;
+    if (cc < ncol && !(st && st[cc].done)) z[int64_t(cc) * ldz + d] += scale * tile[c][t];
   }
 }
 
@@ -1863,27 +2040,70 @@ static void patch_any(const PatchApply &pa, const int64_t *off, const T *inv, co
   else patch_dispatch<T>(pa, off, inv, r, ldr, z, ldz, ncol, scale, st, s);
 }
 
-static_assert(kSmallPatch < kFoldMin, "the multi-column GEMM path reads the segmented layout");
+template <typename F>
+static void patch_mfma(const PatchApply &pa, const F *frag, const int64_t *frag_off, const double *r, int64_t ldr,
+                       int ncol, const PcgState *st, hipStream_t s) {
+  typedef typename FragTraits<F>::Z_t Z_t;
+  constexpr int MPA = FragTraits<F>::MPA;
+  const int MP = (pa.max_size + MPA - 1) / MPA * MPA;
+  const size_t lds = size_t(MP) * 68 * (sizeof(F) == 8 ? 8 : 4);
+  hipLaunchKernelGGL(k_patch_rt, dim3(unsigned((pa.n_adof + 63) / 64), unsigned((ncol + 63) / 64)), dim3(256), 0,
+                     s, pa.n_adof, pa.adof, r, ldr, ncol, static_cast<double *>(pa.rt), pa.zb_cols);
+  const dim3 grid(unsigned(pa.n_patches), unsigned((ncol + 63) / 64));
+  Z_t *zb = static_cast<Z_t *>(pa.zb);
+#define RZ_PM(MM)                                                                                               \
+  if (MP <= MM) {                                                                                               \
+    static bool attr = false;                                                                                   \
+    if (!attr) {                                                                                                \
+      (void)hipFuncSetAttribute((const void *)k_patch_mfma<F, MM>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
+                                160 * 1024);                                                                    \
+      attr = true;                                                                                              \
+    }                                                                                                           \
+    hipLaunchKernelGGL((k_patch_mfma<F, MM>), grid, dim3(64 * (MM / 16)), lds, s, pa.patch_col, pa.col_ent,     \
+                       pa.ent_a, pa.ent_coef, frag_off, frag, static_cast<const double *>(pa.rt), zb, pa.zb_cols, \
+                       ncol, st);                                                                               \
+    return;                                                                                                     \
+  }
+  RZ_PM(32) RZ_PM(64) RZ_PM(96) RZ_PM(128)
+#undef RZ_PM
+}
+
+template <typename Z>
+static void patch_zb_scatter(const PatchApply &pa, double *z, int64_t ldz, int ncol, double scale,
+                             const PcgState *st, hipStream_t s) {
+  hipLaunchKernelGGL((k_patch_zb_scatter<Z>), dim3(unsigned((pa.n_adof + 63) / 64), unsigned((ncol + 63) / 64)),
+                     dim3(256), 0, s, pa.n_adof, pa.adof, pa.aptr, pa.apr, pa.acoef, static_cast<const Z *>(pa.zb),
+                     pa.zb_cols, z, ldz, ncol, scale, st);
+}
+
+void launch_seg_to_frag(const PatchApply &pa, bool bf16, void *frag, const int64_t *frag_off, hipStream_t s) {
+  if (bf16)
+    hipLaunchKernelGGL((k_seg_to_frag<uint16_t>), dim3(unsigned(pa.n_patches)), dim3(256), 0, s, pa.patch_col,
+                       pa.inv_off, pa.inv, frag_off, static_cast<uint16_t *>(frag));
+  else
+    hipLaunchKernelGGL((k_seg_to_frag<double>), dim3(unsigned(pa.n_patches)), dim3(256), 0, s, pa.patch_col,
+                       pa.inv_off, pa.inv, frag_off, static_cast<double *>(frag));
+}
+
+int64_t frag_size(int m, bool bf16) {
+  const int64_t a = bf16 ? 32 : 16, MP = (m + a - 1) / a * a;
+  return MP * MP;
+}
 
 void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, double *z, int64_t ldz, int ncol,
                         const PcgState *st, hipStream_t s, bool lo, double scale) {
   if (pa.n_chunks == 0) return;
+  if (lo && pa.inv16 && ncol >= 8 && pa.frag16 && pa.zb && ncol <= pa.zb_cols) {
+    patch_mfma<uint16_t>(pa, pa.frag16, pa.frag_off16, r, ldr, ncol, st, s);
+    return patch_zb_scatter<float>(pa, z, ldz, ncol, scale, st, s);
+  }
   if (lo && pa.inv16)
     return patch_any<uint16_t>(pa, pa.inv_off16, pa.inv16, r, ldr, z, ldz, ncol, scale, st, s);
   if (lo && pa.inv32)
     return patch_any<float>(pa, pa.inv_off32, pa.inv32, r, ldr, z, ldz, ncol, scale, st, s);
-  if (ncol >= 8 && pa.max_size <= kSmallPatch) {
-    const int MP = (pa.max_size + 15) & ~15;
-    const size_t lds = size_t(MP * (MP + 1) + MP * 65) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-      (void)hipFuncSetAttribute((const void *)k_patch_gemm, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      attr = true;
-    }
-    hipLaunchKernelGGL(k_patch_gemm, dim3(unsigned(pa.n_patches), unsigned((ncol + 63) / 64)), dim3(256), lds, s,
-                       pa.patch_col, pa.col_ent, pa.ent_dof, pa.ent_coef, pa.inv_off, pa.inv, 2, r, ldr, z, ldz,
-                       ncol, scale, st);
-    return;
+  if (ncol >= 8 && pa.frag64 && pa.zb && ncol <= pa.zb_cols) {
+    patch_mfma<double>(pa, pa.frag64, pa.frag_off64, r, ldr, ncol, st, s);
+    return patch_zb_scatter<double>(pa, z, ldz, ncol, scale, st, s);
   }
   patch_any<double>(pa, pa.inv_off, pa.inv, r, ldr, z, ldz, ncol, scale, st, s);
 }

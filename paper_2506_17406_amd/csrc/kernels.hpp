@@ -134,7 +134,26 @@ struct PatchApply {
   const int64_t *inv_off32; // its patch offsets
   const uint16_t *inv16;    // bfloat16 copy (V = 8), or null
   const int64_t *inv_off16;
+  // multi-column solves of segmented sets on MFMA (see frag_size): the
+  // inverses in fragment order (FP64 and/or bfloat16, or null), their patch
+  // offsets, the result buffer (sum_size x columns; double or float), and
+  // the set's dofs with their (patch column, coefficient) entries
+  const double *frag64;
+  const uint16_t *frag16;
+  const int64_t *frag_off64, *frag_off16;
+  void *zb;                    // results, dof-major: zb[pr * zb_cols + c]
+  void *rt;                    // right-hand sides of the set's dofs, dof-major: rt[a * zb_cols + c]
+  int zb_cols;                 // columns zb and rt hold (the MFMA path needs ncol <= zb_cols)
+  int64_t sum_size, n_adof;
+  const int32_t *ent_a;        // per map entry: the index a of its dof in adof
+  const int32_t *adof, *apr;
+  const int64_t *aptr;
+  const double *acoef;
 };
+// entries of one patch inverse in MFMA fragment order (full MP x MP; MP = m
+// rounded up to 16 for FP64, 32 for bfloat16)
+int64_t frag_size(int m, bool bf16);
+void launch_seg_to_frag(const PatchApply &pa, bool bf16, void *frag, const int64_t *frag_off, hipStream_t s);
 // Geometric multigrid V-cycle on W^k (device data; host-resident struct).
 // Level l: operator A (CSR), prolongation P from level l+1 and R = P^T,
 // relaxation data (k = 0: dinv; k = 1: dinv, vertex-hat gradients G and
