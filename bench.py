@@ -192,13 +192,23 @@ def mixed(args):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     print(f"setup Ned6 n=16 (FP64 + FP32 copies): {pm.n_dofs} dofs in {t_setup:.1f}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
     p64 = rz.Problem(X, C, 6, "Ned", pc=args.pc)
+    torch.cuda.synchronize()
+    t_set64 = time.perf_counter() - t0
+    # the W^1 multigrid V-cycle over the Kuhn meshes 16, 8, 4, 2, 1 in place
+    # of the dense coarse inverse
+    t0 = time.perf_counter()
+    pmg = rz.Problem(X, C, 6, "Ned", pc=args.pc, coarse="mg", mg_meshes=[kuhn_mesh(m, 3) for m in (16, 8, 4, 2, 1)])
+    torch.cuda.synchronize()
+    t_setmg = time.perf_counter() - t0
     ppc = rz.Problem(X, C, 6, "Ned", precision="fp32-pc", pc=args.pc)
     pbf = rz.Problem(X, C, 6, "Ned", precision="bf16-pc", pc=args.pc)
     torch.cuda.synchronize()
     print("setup FP64, FP32- and BF16-preconditioner handles done", file=sys.stderr, flush=True)
     b = torch.from_numpy(load_vectors(pm.n_dofs, 5)[:, 0]).cuda()
     xm, x64, xpc, xbf = torch.zeros_like(b), torch.zeros_like(b), torch.zeros_like(b), torch.zeros_like(b)
+    xmg = torch.zeros_like(b)
 
     def timed(prob, x):
         for _ in range(args.warmup):
@@ -221,6 +231,9 @@ def mixed(args):
     print(f"FP32 preconditioner: {dt_pc * 1e3:.1f} ms, {info_pc['iterations']} its", file=sys.stderr, flush=True)
     dt_bf, info_bf = timed(pbf, xbf)
     print(f"BF16 preconditioner: {dt_bf * 1e3:.1f} ms, {info_bf['iterations']} its", file=sys.stderr, flush=True)
+    dt_mg, info_mg = timed(pmg, xmg)
+    print(f"FP64 with the W^1 V-cycle: {dt_mg * 1e3:.1f} ms, {info_mg['iterations']} its, setup {t_setmg:.2f} s "
+          f"(dense coarse inverse: {t_set64:.2f} s)", file=sys.stderr, flush=True)
     # true FP64 residuals and the distance between the solutions
     r = torch.empty_like(b)
     nb = b.norm().item()
@@ -230,6 +243,7 @@ def mixed(args):
         return (b - r).norm().item() / nb
 
     res64, res_m, res_pc, res_bf = true_res(x64), true_res(xm), true_res(xpc), true_res(xbf)
+    res_mg = true_res(xmg)
     diff = (xm - x64).norm().item() / x64.norm().item()
     diff_pc = (xpc - x64).norm().item() / x64.norm().item()
     diff_bf = (xbf - x64).norm().item() / x64.norm().item()
@@ -268,6 +282,9 @@ def mixed(args):
                       "flops_per_launch": flops, "launch_us": t_a32 * 1e6}),
         "bf16_pc": {"value": pm.n_dofs / dt_bf, "ms": dt_bf * 1e3, "iterations": info_bf["iterations"],
                     "true_rel_residual": res_bf, "rel_diff_vs_fp64_solution": diff_bf},
+        "fp64_mg": {"value": pm.n_dofs / dt_mg, "ms": dt_mg * 1e3, "iterations": info_mg["iterations"],
+                    "true_rel_residual": res_mg, "setup_s": round(t_setmg, 2),
+                    "setup_s_dense_coarse": round(t_set64, 2)},
         "fp32_pc": {"value": pm.n_dofs / dt_pc, "ms": dt_pc * 1e3, "iterations": info_pc["iterations"],
                     "true_rel_residual": res_pc, "rel_diff_vs_fp64_solution": diff_pc},
         "fp32_ir": {"value": pm.n_dofs / dt_m, "ms": dt_m * 1e3, "iterations": info_m["iterations"],
@@ -744,11 +761,17 @@ def main():
     patch_bytes = 8.0 * pinfo["packed_entries"] + 24.0 * pinfo["sum_size"]
     fam_names = {("CG", 0): "vertex stars", ("Ned", 0): "edge stars", ("Ned", 1): "vertex-star potentials",
                  ("RT", 0): "edge stars"}
+    # HBM traffic of that pass from committed counter runs of the same
+    # kernel source (the 855-dof star streams of the n = 8 sweep), else null
+    from paper_2506_17406_amd.profile_summary import read_traffic
+    trp = read_traffic(os.path.join(ROOT, "profiles", "patch_fold_CG8_sweep_traffic.md"))
+    traffic_patch = (float(trp["traffic_bytes_per_launch"])
+                     if trp and pe["fam"] == "CG" and pe["p"] == 8 and args.n == 8 else None)
     roofline_patch = {
         "kernel": f"patch solves ({pe['fam']}{pe['p']} {fam_names.get((pe['fam'], pk), 'family %d' % pk)}, "
                   f"{pinfo['n_patches']} patches of <= {pinfo['max_size']} dofs): one pass",
         "bound": "hbm", "achieved": patch_bytes / t_patch / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-        "frac": patch_bytes / t_patch / 1e9 / PEAK_HBM_GBS, "traffic": None, "bytes_per_launch": patch_bytes,
+        "frac": patch_bytes / t_patch / 1e9 / PEAK_HBM_GBS, "traffic": traffic_patch, "bytes_per_launch": patch_bytes,
         "stored_bytes": 8.0 * pinfo["stored_entries"], "launch_us": t_patch * 1e6}
     legs = {}
     if not args.no_legs:

@@ -19,6 +19,9 @@
     python -m paper_2506_17406_amd.profile_summary bandwidth <fetch.csv> <write.csv> <results.db> <copy_bytes> [top]
         per kernel name: mean HBM bytes per dispatch (counters scaled by the
         copy kernel, as for traffic) over mean duration in a kernel trace;
+    python -m paper_2506_17406_amd.profile_summary kernel_traffic <fetch.csv> <write.csv> <kernel> <copy_bytes> [grid|max]
+        HBM bytes per dispatch of one kernel (of that grid, or its largest
+        grid), scaled by the copy kernel as for traffic; key: value lines;
     python -m paper_2506_17406_amd.profile_summary applies <results.db> <kernel> [grid_y]
         mean duration of those applies (gather start to assembly end) and of
         their GEMM kernel in a kernel trace (with grid_y, only GEMM dispatches
@@ -105,6 +108,34 @@ def traffic(fetch_csv, write_csv, kernel, copy_bytes, grid=None):
             "kernels_hip_sha256": kernels_sha256(),
             "fetch_kib_per_apply": fk, "write_kib_per_apply": wk, "applies": len(fs), "copy_bytes": copy_bytes,
             "copy_fetch_factor": ff, "copy_write_factor": fw, "traffic_bytes_per_launch": t}
+
+
+def kernel_traffic(fetch_csv, write_csv, kernel, copy_bytes, grid=None):
+    """HBM bytes per dispatch of one kernel (of `grid` work-items; "max": the
+    largest grid it ran on) from the two counter runs, scaled by the copy
+    kernel's readings as in `traffic`."""
+    f = _dispatches(fetch_csv, "FETCH_SIZE")
+    w = _dispatches(write_csv, "WRITE_SIZE")
+
+    def copy_kib(rows):
+        cands = [v for _, name, v, _ in rows if "copy" in name.lower() or "elementwise" in name.lower()]
+        return min(cands, key=lambda v: abs(v * 1024 - copy_bytes))
+
+    if grid == "max":
+        grid = max(g for _, name, _, g in f if name == kernel)
+    ff = copy_bytes / (copy_kib(f) * 1024)
+    fw = copy_bytes / (copy_kib(w) * 1024)
+    fs = [v for _, name, v, g in f if name == kernel and (not grid or g == int(grid))]
+    ws = [v for _, name, v, g in w if name == kernel and (not grid or g == int(grid))]
+    # dispatches that did the work (inside PCG chunks, launches that found
+    # their column converged exit at once and read almost nothing)
+    fs = [v for v in fs if v >= 0.5 * max(fs)]
+    ws = [v for v in ws if v >= 0.5 * max(ws)]
+    fk, wk = sum(fs) / len(fs), sum(ws) / len(ws)
+    return {"kernel": kernel + (f", grid {grid}" if grid else ""), "kernels_hip_sha256": kernels_sha256(),
+            "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk, "dispatches": len(fs),
+            "copy_bytes": copy_bytes, "copy_fetch_factor": ff, "copy_write_factor": fw,
+            "traffic_bytes_per_launch": fk * 1024 * ff + wk * 1024 * fw}
 
 
 def apply_durations(db, kernel, grid_y=None):
@@ -212,6 +243,10 @@ if __name__ == "__main__":
     elif sys.argv[1] == "bandwidth":
         print(bandwidth(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]),
                         int(sys.argv[6]) if len(sys.argv) > 6 else 20))
+    elif sys.argv[1] == "kernel_traffic":
+        grid = sys.argv[6] if len(sys.argv) > 6 else None
+        for k, v in kernel_traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), grid).items():
+            print(f"{k}: {v}")
     elif sys.argv[1] == "applies":
         gy = int(sys.argv[4]) if len(sys.argv) > 4 else None
         d = [a for a in apply_durations(sys.argv[2], sys.argv[3], gy) if a[1] > 10.0]
