@@ -162,19 +162,25 @@ class Smoother:
             self.G = G
             self.gdiag = 1.0 / (G.T @ (A @ G)).diagonal()
         if k == 2:
-            self.stars = []
+            # the additive edge-star relaxation sum_s R_s^T A_s^{-1} R_s,
+            # assembled once as a sparse matrix (each star's principal
+            # submatrix inverted through its Cholesky factor)
+            rows, cols, vals = [], [], []
             for idx in edge_face_stars(top):
-                self.stars.append((idx, sla.cho_factor(A[idx][:, idx].toarray(), lower=True)))
+                F = sla.cho_factor(A[idx][:, idx].toarray(), lower=True)
+                inv = sla.cho_solve(F, np.eye(len(idx)))
+                rows.append(np.repeat(idx, len(idx)))
+                cols.append(np.tile(idx, len(idx)))
+                vals.append(inv.ravel())
+            n = A.shape[0]
+            self.S = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
 
     def apply(self, r):
         if self.k == 0:
             return self.dinv * r
         if self.k == 1:
             return self.dinv * r + self.G @ (self.gdiag * (self.G.T @ r))
-        z = np.zeros_like(r)
-        for idx, F in self.stars:
-            z[idx] += sla.cho_solve(F, r[idx])
-        return z
+        return self.S @ r
 
 
 class WhitneyMultigrid:

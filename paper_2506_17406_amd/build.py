@@ -50,13 +50,15 @@ def build(verbose=False, jobs=4):
     return LIB
 
 
-def build_host_sanitized(out_dir, verbose=False, jobs=4):
+def build_host_sanitized(out_dir, verbose=False, jobs=4, reuse_kernels=True):
     """The library with its host code built with AddressSanitizer and
     UndefinedBehaviorSanitizer (the device code as usual), for
     the CPU tests of the host-only entry points (reference tables,
     numbering, patch lists, argument and mesh checks).  Load it with the
     sanitizer runtime preloaded (see sanitizer_runtime) and RZ_LIBRARY set to
-    the returned path."""
+    the returned path.  With reuse_kernels the up-to-date in-tree object of
+    the device kernels (whose host side is only their launchers) is linked
+    in instead of being rebuilt."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     os.makedirs(out_dir, exist_ok=True)
     flags = [f for f in HIPCC_FLAGS if f != "--offload-arch=gfx950"]
@@ -65,6 +67,14 @@ def build_host_sanitized(out_dir, verbose=False, jobs=4):
     procs, objs = [], []
     for src in SOURCES:
         obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+        if src == "csrc/kernels.hip" and reuse_kernels:
+            # the device kernels and their thin launchers: the in-tree object
+            # when it is newer than every source it includes
+            built = os.path.join(HERE, "_build", "kernels.hip.o")
+            deps = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "kernels.hpp")]
+            if os.path.exists(built) and all(os.path.getmtime(built) > os.path.getmtime(d) for d in deps):
+                objs.append(built)
+                continue
         objs.append(obj)
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [hipcc, "--offload-arch=gfx950"] + flags + san + lang + ["-c", os.path.join(HERE, src), "-o", obj]
