@@ -58,6 +58,36 @@ def kuhn_mesh(n, dim=3, jitter=0.0, seed=0):
     return coords, np.asarray(cells, dtype=np.int64)
 
 
+def fichera_mesh(n, jitter=0.0, seed=0):
+    """Vertices and cells of the Freudenthal mesh of the Fichera corner
+    (0, 1)^3 minus [1/2, 1)^3 with n cells per edge (n even): the Kuhn cubes
+    (i, j, k) of the unit-cube mesh except those with i, j, k >= n / 2,
+    vertices renumbered in the unit-cube order.  jitter: interior vertices
+    (all eight surrounding cubes present) moved by U(-jitter h, jitter h)
+    per coordinate."""
+    if n % 2:
+        raise ValueError("the Fichera mesh needs an even n")
+    X, C = kuhn_mesh(n, 3)
+    h, m = 1.0 / n, n // 2
+    cube = np.repeat(np.arange(n ** 3), 6)                      # cells come 6 per cube, cube index i + n (j + n k)
+    ci, cj, ck = cube % n, (cube // n) % n, cube // (n * n)
+    keep = ~((ci >= m) & (cj >= m) & (ck >= m))
+    C = C[keep]
+    used = np.zeros(len(X), dtype=bool)
+    used[C.ravel()] = True
+    new = -np.ones(len(X), dtype=np.int64)
+    new[used] = np.arange(used.sum())
+    X, C = X[used], new[C]
+    if jitter:
+        g = np.rint(X / h).astype(np.int64)
+        present = lambda i, j, k: (0 <= i < n and 0 <= j < n and 0 <= k < n and not (i >= m and j >= m and k >= m))
+        interior = np.array([all(present(i + a, j + b, k + c) for a in (-1, 0) for b in (-1, 0) for c in (-1, 0))
+                             for i, j, k in g])
+        rng = np.random.default_rng(seed)
+        X = X + rng.uniform(-jitter * h, jitter * h, size=X.shape) * interior[:, None]
+    return X, C
+
+
 def load_vectors(n_dofs, seed, n_rhs=1):
     """Column-major (n_dofs, n_rhs) uniform[-1, 1] load vectors; column j is
     the j-th block of n_dofs consecutive draws of default_rng(seed)."""
