@@ -363,6 +363,41 @@ int rz_patch_lists(const rz_mesh *mesh, int32_t degree, rz_space space, int32_t 
 
 void rz_destroy(rz_problem *P);
 
+/* ---- Hodge Laplacians (Sec. 7.2, eq:hodge-laplace)
+ * The mixed problem on X^{k-1} x X^k with natural boundary conditions,
+ * k = 1 (CG_p x Ned_p) or k = 2 (Ned_p x RT_p), in the two bases:
+ *   [ -M_{k-1}   D^T M_k ] [sigma]   [b_0]
+ *   [  M_k D     K_k     ] [  u  ] = [b_1],
+ * M the mass matrices, K_k the matrix of (d u, d v) and D the exterior
+ * derivative in the X^k basis (the discrete complex is exact).  Vectors are
+ * [sigma (n0 entries); u (n1)], caller-owned device FP64 arrays.
+ * rz_hodge_setup: builds two Riesz-map handles for the block-diagonal
+ * weighted Riesz-map preconditioner of eq:augmented-lagrangian,
+ * (sigma, tau) + gamma (d sigma, d tau) on X^{k-1} and gamma^{-1} (u, v) +
+ * (d u, d v) on X^k, each applied as one application of the handle's
+ * Schwarz preconditioner (opts: pc form, decomposition, coarse solver and
+ * max_iter as for rz_setup; NULL: the hybrid form; RZ_FP64 only, no
+ * Dirichlet facets -> RZ_ERR_UNSUPPORTED), and D on the device.  gamma > 0
+ * (RZ_ERR_ARG otherwise).
+ * rz_hodge_apply: y = A x.  rz_hodge_apply_P: z = blockdiag(B_0, B_1) r.
+ * rz_hodge_solve: preconditioned MINRES from x = 0 until the preconditioned
+ * residual norm falls to rtol times its initial value (the paper's MINRES
+ * test), at most max_iter iterations (RZ_ERR_NO_CONVERGENCE, info still
+ * filled); info: status, iterations, rel_residual (the preconditioned
+ * residual ratio), solve_ms.  Calls on one handle must not overlap.
+ * rz_derivative_reference (host only): the reference-cell derivative
+ * matrix D_hat of the complex (k = 1: grad CG_p -> Ned_p, k = 2: curl
+ * Ned_p -> RT_p), n_to x n_from row-major, any pointer may be NULL. */
+typedef struct rz_hodge rz_hodge;
+int rz_hodge_setup(const rz_mesh *mesh, int32_t degree, int32_t k, double gamma, const rz_options *opts,
+                   void *hip_stream, rz_hodge **out);
+int rz_hodge_sizes(const rz_hodge *H, int64_t *n0, int64_t *n1);
+int rz_hodge_apply(rz_hodge *H, const double *x, double *y, void *hip_stream);
+int rz_hodge_apply_P(rz_hodge *H, const double *r, double *z, void *hip_stream);
+int rz_hodge_solve(rz_hodge *H, const double *b, double *x, double rtol, rz_info *info, void *hip_stream);
+void rz_hodge_destroy(rz_hodge *H);
+int rz_derivative_reference(int32_t k, int32_t degree, int32_t *n_to, int32_t *n_from, double *D);
+
 /* Tile shape of the operator apply's contraction: each wave multiplies the
  * reference stack into 16, 32 or 64 cells (more cells reuse each loaded
  * reference fragment more often, fewer keep more waves in flight).  The

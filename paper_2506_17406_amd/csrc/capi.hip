@@ -1954,3 +1954,331 @@ int rz_batch_solve(rz_batch *B, const double *const *b, double *const *x, double
 void rz_batch_destroy(rz_batch *B) { delete B; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- Hodge Laplacians
+// eq:hodge-laplace on X^{k-1} x X^k (k = 1: CG_p x Ned_p, k = 2: Ned_p x RT_p),
+// natural boundary conditions, in the two bases:
+//   [ -M_{k-1}   D^T M_k ] [sigma]
+//   [  M_k D     K_k     ] [  u  ]
+// with D the exterior derivative in the X^k basis (d X^{k-1}_p lies in X^k_p),
+// preconditioned by the weighted Riesz maps of eq:augmented-lagrangian, each
+// one application of the Schwarz preconditioner of its handle:
+// (sigma, tau) + gamma (d sigma, d tau) on X^{k-1} (alpha = gamma, beta = 1)
+// and gamma^{-1} (u, v) + (d u, d v) on X^k (alpha = 1, beta = 1 / gamma).
+struct rz_hodge {
+  rz_problem *P0 = nullptr, *P1 = nullptr;
+  int k = 1, p = 1, max_iter = 1000;
+  double gamma = 1.0;
+  int64_t n0 = 0, n1 = 0;
+  rz::ApplyATables tM0{}, tM1{}, tK1{};  // mass of X^{k-1}, mass and stiffness of X^k
+  const int64_t *dp = nullptr, *dtp = nullptr;
+  const int32_t *dc = nullptr, *dtc = nullptr;
+  const double *dv = nullptr, *dtv = nullptr;
+  std::vector<void *> mem;
+  double *t2 = nullptr, *m2 = nullptr;  // 2 n1 each: [D sigma, u] and their X^k masses
+  double *vec = nullptr;               // MINRES: 7 vectors of n0 + n1
+  double *part = nullptr, *part_host = nullptr;
+  static constexpr int kParts = 256;
+  template <class T>
+  T *dev(size_t count) {
+    void *ptr = nullptr;
+    HIPCHK(hipMalloc(&ptr, std::max<size_t>(count, 1) * sizeof(T)));
+    mem.push_back(ptr);
+    return static_cast<T *>(ptr);
+  }
+  template <class T>
+  T *upload(const std::vector<T> &v) {
+    T *ptr = dev<T>(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return ptr;
+  }
+  ~rz_hodge() {
+    for (void *ptr : mem) (void)hipFree(ptr);
+    if (part_host) (void)hipHostFree(part_host);
+    rz_destroy(P1);
+    rz_destroy(P0);
+  }
+};
+
+namespace {
+// y = A x for the mixed matrix (x, y: [sigma; u])
+int hodge_apply(rz_hodge *H, const double *x, double *y, hipStream_t s) {
+  const int64_t n0 = H->n0, n1 = H->n1;
+  const double *sg = x, *u = x + n0;
+  double *y0 = y, *y1 = y + n0;
+  rz::launch_csr_spmv(n1, H->dp, H->dc, H->dv, sg, H->t2, 1.0, false, s);              // D sigma
+  HIPCHK(hipMemcpyAsync(H->t2 + n1, u, size_t(n1) * 8, hipMemcpyDeviceToDevice, s));   // u
+  rz::launch_apply_A(H->tM1, H->t2, n1, H->m2, n1, 2, nullptr, s, false, 0, -1, 1.0, 0, 0, true);
+  rz::launch_apply_A(H->tK1, u, n1, y1, n1, 1, nullptr, s, false, 0, -1, 1.0, 0, 0, true);  // K u
+  rz::launch_lincomb3(n1, 1.0, y1, 1.0, H->m2, 0.0, nullptr, y1, s);                    // + M D sigma
+  rz::launch_apply_A(H->tM0, sg, n0, y0, n0, 1, nullptr, s, false, 0, -1, -1.0, 0, 0, true);  // -M sigma
+  rz::launch_csr_spmv(n0, H->dtp, H->dtc, H->dtv, H->m2 + n1, y0, 1.0, true, s);        // + D^T M u
+  return RZ_OK;
+}
+
+int hodge_apply_P(rz_hodge *H, const double *r, double *z, hipStream_t s) {
+  int rc = apply_P(H->P0, r, z, 1, H->n0, s, false);
+  if (rc != RZ_OK) return rc;
+  return apply_P(H->P1, r + H->n0, z + H->n0, 1, H->n1, s, false);
+}
+
+double hodge_dot(rz_hodge *H, const double *a, const double *b, hipStream_t s) {
+  rz::launch_dot_part(H->n0 + H->n1, a, b, H->part, rz_hodge::kParts, s);
+  HIPCHK(hipMemcpyAsync(H->part_host, H->part, sizeof(double) * rz_hodge::kParts, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double v = 0.0;
+  for (int i = 0; i < rz_hodge::kParts; ++i) v += H->part_host[i];  // fixed order
+  return v;
+}
+}  // namespace
+
+extern "C" {
+
+int rz_derivative_reference(int32_t k, int32_t degree, int32_t *n_to, int32_t *n_from, double *D) {
+  if (k != 1 && k != 2) return fail(RZ_ERR_UNSUPPORTED, "k must be 1 (grad: CG -> Ned) or 2 (curl: Ned -> RT)");
+  if (degree < 1 || degree > 10) return fail(RZ_ERR_UNSUPPORTED, "degree must be in 1..10");
+  try {
+    const rz::Family from = k == 1 ? rz::FAM_CG : rz::FAM_NED, to = k == 1 ? rz::FAM_NED : rz::FAM_RT;
+    const int na = rz::build_reference(3, from, degree).n, nb = rz::build_reference(3, to, degree).n;
+    if (n_to) *n_to = nb;
+    if (n_from) *n_from = na;
+    if (D) {
+      std::vector<double> Dh = rz::derivative_reference(3, from, to, degree);
+      std::copy(Dh.begin(), Dh.end(), D);
+    }
+  } catch (const std::exception &e) {
+    return fail(RZ_ERR_UNSUPPORTED, e.what());
+  }
+  return RZ_OK;
+}
+
+int rz_hodge_setup(const rz_mesh *m, int32_t degree, int32_t k, double gamma, const rz_options *opts,
+                   void *hip_stream, rz_hodge **out) {
+  if (!m || !out) return fail(RZ_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (k != 1 && k != 2) return fail(RZ_ERR_UNSUPPORTED, "k must be 1 (CG x Ned) or 2 (Ned x RT)");
+  if (m->dim != 3) return fail(RZ_ERR_UNSUPPORTED, "the Hodge Laplacians are built for tetrahedral meshes");
+  if (!(gamma > 0.0)) return fail(RZ_ERR_ARG, "need gamma > 0");
+  if (opts && opts->precision != RZ_FP64) return fail(RZ_ERR_UNSUPPORTED, "the Hodge Laplacians run in RZ_FP64");
+  if (opts && opts->dirichlet_facet) return fail(RZ_ERR_UNSUPPORTED, "the Hodge Laplacians take natural boundary conditions");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  auto H = std::make_unique<rz_hodge>();
+  H->k = k;
+  H->p = degree;
+  H->gamma = gamma;
+  if (opts && opts->max_iter > 0) H->max_iter = opts->max_iter;
+  rz_options o0{};
+  if (opts) o0 = *opts;
+  else {
+    o0.max_iter = 1000;
+    o0.pc = RZ_PC_HYBRID;
+  }
+  rz_options o1 = o0;
+  o0.alpha = gamma;  // (sigma, tau) + gamma (d sigma, d tau)
+  o0.beta = 1.0;
+  o1.alpha = 1.0;    // gamma^{-1} (u, v) + (d u, d v)
+  o1.beta = 1.0 / gamma;
+  const rz_space s0 = k == 1 ? RZ_HGRAD : RZ_HCURL, s1 = k == 1 ? RZ_HCURL : RZ_HDIV;
+  int rc = rz_setup(m, degree, s0, &o0, hip_stream, &H->P0);
+  if (rc != RZ_OK) return rc;
+  rc = rz_setup(m, degree, s1, &o1, hip_stream, &H->P1);
+  if (rc != RZ_OK) return rc;
+  rz_problem *P0 = H->P0, *P1 = H->P1;
+  H->n0 = P0->top.n_dofs;
+  H->n1 = P1->top.n_dofs;
+  try {
+    ensure_ws(P0, 1);
+    ensure_ws(P1, 2);
+    // mass-only and stiffness-only weights (linear in (alpha, beta); the
+    // stacked mass family comes first: one matrix for a scalar field, six
+    // component pairs for a vector field)
+    const int64_t nc = P0->top.n_cells;
+    const int qm0 = P0->k == 0 ? 1 : 6, qm1 = P1->k == 0 ? 1 : 6;
+    double *wM0 = H->dev<double>(size_t(nc) * P0->el.Q), *wM1 = H->dev<double>(size_t(nc) * P1->el.Q),
+           *wK1 = H->dev<double>(size_t(nc) * P1->el.Q);
+    rz::launch_scale_weights(nc, P0->el.Q, qm0, P0->w, 1.0, 0.0, wM0, s);
+    rz::launch_scale_weights(nc, P1->el.Q, qm1, P1->w, gamma, 0.0, wM1, s);
+    rz::launch_scale_weights(nc, P1->el.Q, qm1, P1->w, 0.0, 1.0, wK1, s);
+    H->tM0 = P0->at;
+    H->tM0.w = wM0;
+    H->tM1 = P1->at;
+    H->tM1.w = wM1;
+    H->tK1 = P1->at;
+    H->tK1.w = wK1;
+    // D (n1 x n0) from the reference D_hat placed per cell (every cell's
+    // basis is the pullback of the sorted-vertex reference basis, and the
+    // pullbacks commute with d), and its transpose
+    const rz::Family f0 = k == 1 ? rz::FAM_CG : rz::FAM_NED, f1 = k == 1 ? rz::FAM_NED : rz::FAM_RT;
+    const std::vector<double> Dh = rz::derivative_reference(3, f0, f1, degree);
+    const int na = P0->el.n, nb = P1->el.n;
+    std::vector<std::pair<int64_t, double>> ent;  // key row * n0 + col
+    ent.reserve(size_t(nc) * nb * 4);
+    for (int64_t c = 0; c < nc; ++c)
+      for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < na; ++j) {
+          const double v = Dh[size_t(i) * na + j];
+          if (v == 0.0) continue;
+          ent.push_back({int64_t(P1->top.cell_dofs[c * nb + i]) * H->n0 + P0->top.cell_dofs[c * na + j], v});
+        }
+    std::sort(ent.begin(), ent.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    std::vector<int64_t> keys;
+    std::vector<double> vals;
+    for (size_t e = 0; e < ent.size(); ++e)
+      if (keys.empty() || keys.back() != ent[e].first) {
+        keys.push_back(ent[e].first);
+        vals.push_back(ent[e].second);
+      }
+    auto csr = [&](bool transpose, std::vector<int64_t> &ptr, std::vector<int32_t> &col, std::vector<double> &val) {
+      const int64_t nr = transpose ? H->n0 : H->n1;
+      ptr.assign(nr + 1, 0);
+      for (int64_t key : keys) ++ptr[(transpose ? key % H->n0 : key / H->n0) + 1];
+      for (int64_t r = 0; r < nr; ++r) ptr[r + 1] += ptr[r];
+      std::vector<int64_t> pos(ptr.begin(), ptr.end() - 1);
+      col.assign(keys.size(), 0);
+      val.assign(keys.size(), 0.0);
+      for (size_t e = 0; e < keys.size(); ++e) {
+        const int64_t r = transpose ? keys[e] % H->n0 : keys[e] / H->n0;
+        const int64_t cc = transpose ? keys[e] / H->n0 : keys[e] % H->n0;
+        col[pos[r]] = int32_t(cc);
+        val[pos[r]++] = vals[e];
+      }
+    };
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    csr(false, ptr, col, val);
+    H->dp = H->upload(ptr);
+    H->dc = H->upload(col);
+    H->dv = H->upload(val);
+    csr(true, ptr, col, val);
+    H->dtp = H->upload(ptr);
+    H->dtc = H->upload(col);
+    H->dtv = H->upload(val);
+    H->t2 = H->dev<double>(size_t(2) * H->n1);
+    H->m2 = H->dev<double>(size_t(2) * H->n1);
+    H->vec = H->dev<double>(size_t(7) * (H->n0 + H->n1));
+    H->part = H->dev<double>(rz_hodge::kParts);
+    HIPCHK(hipHostMalloc((void **)&H->part_host, sizeof(double) * rz_hodge::kParts, hipHostMallocDefault));
+    HIPCHK(hipStreamSynchronize(s));
+  } catch (const RzError &e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc &) {
+    return fail(RZ_ERR_OOM, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(RZ_ERR_UNSUPPORTED, e.what());
+  }
+  *out = H.release();
+  return RZ_OK;
+}
+
+int rz_hodge_sizes(const rz_hodge *H, int64_t *n0, int64_t *n1) {
+  if (!H) return fail(RZ_ERR_ARG, "null handle");
+  if (n0) *n0 = H->n0;
+  if (n1) *n1 = H->n1;
+  return RZ_OK;
+}
+
+int rz_hodge_apply(rz_hodge *H, const double *x, double *y, void *hip_stream) {
+  if (!H || !x || !y) return fail(RZ_ERR_ARG, "null argument");
+  try {
+    hodge_apply(H, x, y, static_cast<hipStream_t>(hip_stream));
+  } catch (const RzError &e) {
+    return fail(e.code, e.msg);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RZ_ERR_DEVICE, hipGetErrorString(e));
+  return RZ_OK;
+}
+
+int rz_hodge_apply_P(rz_hodge *H, const double *r, double *z, void *hip_stream) {
+  if (!H || !r || !z) return fail(RZ_ERR_ARG, "null argument");
+  return hodge_apply_P(H, r, z, static_cast<hipStream_t>(hip_stream));
+}
+
+// Preconditioned MINRES (Paige & Saunders 1975): the Lanczos process in the
+// P^{-1} inner product and the Givens QR of its tridiagonal matrix, x_0 = 0,
+// stopping when the preconditioned residual norm |phibar| <= rtol ||b||_P.
+// The scalars live on the host (two inner products per iteration); the
+// vectors, the operator and the preconditioner on the device.
+int rz_hodge_solve(rz_hodge *H, const double *b, double *x, double rtol, rz_info *info, void *hip_stream) {
+  if (!H || !b || !x) return fail(RZ_ERR_ARG, "null argument");
+  if (!(rtol > 0.0)) return fail(RZ_ERR_ARG, "need rtol > 0");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int64_t n = H->n0 + H->n1;
+  double *r1 = H->vec, *r2 = H->vec + n, *y = H->vec + 2 * n, *v = H->vec + 3 * n, *w = H->vec + 4 * n,
+         *w1 = H->vec + 5 * n, *w2 = H->vec + 6 * n;
+  const auto t0 = std::chrono::steady_clock::now();
+  int it = 0, status = RZ_ERR_NO_CONVERGENCE;
+  double rel = 1.0;
+  try {
+    rz::launch_lincomb3(n, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, x, s);   // x = 0
+    rz::launch_lincomb3(n, 1.0, b, 0.0, nullptr, 0.0, nullptr, r1, s);        // r1 = b
+    rz::launch_lincomb3(n, 1.0, b, 0.0, nullptr, 0.0, nullptr, r2, s);        // r2 = b
+    rz::launch_lincomb3(n, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, w, s);
+    rz::launch_lincomb3(n, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, w2, s);
+    int rc = hodge_apply_P(H, r1, y, s);
+    if (rc != RZ_OK) return rc;
+    const double beta1 = std::sqrt(std::max(0.0, hodge_dot(H, r1, y, s)));
+    if (beta1 == 0.0) {
+      status = RZ_OK;
+      rel = 0.0;
+    } else {
+      double oldb = 0.0, beta = beta1, dbar = 0.0, epsln = 0.0, phibar = beta1, cs = -1.0, sn = 0.0;
+      for (it = 1; it <= H->max_iter; ++it) {
+        rz::launch_lincomb3(n, 1.0 / beta, y, 0.0, nullptr, 0.0, nullptr, v, s);   // v = y / beta
+        hodge_apply(H, v, y, s);                                                    // y = A v
+        if (it >= 2) rz::launch_lincomb3(n, 1.0, y, -beta / oldb, r1, 0.0, nullptr, y, s);
+        const double alfa = hodge_dot(H, v, y, s);
+        rz::launch_lincomb3(n, 1.0, y, -alfa / beta, r2, 0.0, nullptr, y, s);
+        std::swap(r1, r2);  // r1 = old r2; r2 <- y (copied below)
+        rz::launch_lincomb3(n, 1.0, y, 0.0, nullptr, 0.0, nullptr, r2, s);
+        rc = hodge_apply_P(H, r2, y, s);
+        if (rc != RZ_OK) return rc;
+        oldb = beta;
+        beta = std::sqrt(std::max(0.0, hodge_dot(H, r2, y, s)));
+        const double oldeps = epsln;
+        const double delta = cs * dbar + sn * alfa;
+        const double gbar = sn * dbar - cs * alfa;
+        epsln = sn * beta;
+        dbar = -cs * beta;
+        const double gmm = std::max(std::hypot(gbar, beta), 1e-300);
+        cs = gbar / gmm;
+        sn = beta / gmm;
+        const double phi = cs * phibar;
+        phibar = sn * phibar;
+        std::swap(w1, w2);  // w1 <- old w2, w2 <- old w (rotate)
+        std::swap(w2, w);
+        // w = (v - oldeps w1 - delta w2) / gamma; x += phi w
+        rz::launch_lincomb3(n, 1.0 / gmm, v, -oldeps / gmm, w1, -delta / gmm, w2, w, s);
+        rz::launch_lincomb3(n, 1.0, x, phi, w, 0.0, nullptr, x, s);
+        rel = std::fabs(phibar) / beta1;
+        if (!std::isfinite(rel)) {
+          status = RZ_ERR_BREAKDOWN;
+          break;
+        }
+        if (rel <= rtol) {
+          status = RZ_OK;
+          break;
+        }
+      }
+      if (it > H->max_iter) it = H->max_iter;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+  } catch (const RzError &e) {
+    return fail(e.code, e.msg);
+  }
+  if (info) {
+    *info = rz_info{};
+    info->status = status;
+    info->iterations = it;
+    info->rel_residual = rel;
+    info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (status == RZ_ERR_NO_CONVERGENCE) return fail(status, "MINRES reached max_iter");
+  if (status == RZ_ERR_BREAKDOWN) return fail(status, "non-finite MINRES scalar");
+  return RZ_OK;
+}
+
+void rz_hodge_destroy(rz_hodge *H) { delete H; }
+
+}  // extern "C"

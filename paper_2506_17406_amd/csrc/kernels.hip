@@ -2108,6 +2108,70 @@ void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, doub
   patch_any<double>(pa, pa.inv_off, pa.inv, r, ldr, z, ldz, ncol, scale, st, s);
 }
 
+// ---- Hodge Laplacians: the exterior derivative as CSR, weight scaling,
+// MINRES vector kernels
+// y = alpha A x (+ y when accumulate), A in CSR (one thread per row)
+__global__ void k_csr_spmv(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                           const double *__restrict__ val, const double *__restrict__ x, double *__restrict__ y,
+                           double alpha, int accumulate) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    double v = 0.0;
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) v += val[e] * x[col[e]];
+    y[i] = accumulate ? y[i] + alpha * v : alpha * v;
+  }
+}
+
+// out[c, q] = w[c, q] * (q < qm ? smass : sderiv): the mass family of the
+// stacked matrices comes first
+__global__ void k_scale_weights(int64_t nc, int Q, int qm, const double *__restrict__ w, double smass, double sderiv,
+                                double *__restrict__ out) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nc * Q; i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = w[i] * (int(i % Q) < qm ? smass : sderiv);
+}
+
+// out = a x + b y + c z (null vectors count as zero; out may alias x)
+__global__ void k_lincomb3(int64_t n, double a, const double *x, double b, const double *y, double c,
+                           const double *z, double *out) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    double v = 0.0;
+    if (x) v += a * x[i];
+    if (y) v += b * y[i];
+    if (z) v += c * z[i];
+    out[i] = v;
+  }
+}
+
+// per-block partial sums of a . b (blockDim 256; gridDim.x partials)
+__global__ __launch_bounds__(256) void k_dot_part(int64_t n, const double *__restrict__ a,
+                                                  const double *__restrict__ b, double *__restrict__ part) {
+  __shared__ double sm4[4];
+  double v = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) v += a[i] * b[i];
+  v = block_sum256(v, sm4);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+void launch_csr_spmv(int64_t n, const int64_t *ptr, const int32_t *col, const double *val, const double *x,
+                     double *y, double alpha, bool accumulate, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned g = unsigned(std::min<int64_t>((n + 255) / 256, 8192));
+  hipLaunchKernelGGL(k_csr_spmv, dim3(g), dim3(256), 0, s, n, ptr, col, val, x, y, alpha, accumulate ? 1 : 0);
+}
+void launch_scale_weights(int64_t nc, int Q, int qm, const double *w, double smass, double sderiv, double *out,
+                          hipStream_t s) {
+  const unsigned g = unsigned(std::min<int64_t>((nc * Q + 255) / 256, 8192));
+  hipLaunchKernelGGL(k_scale_weights, dim3(g), dim3(256), 0, s, nc, Q, qm, w, smass, sderiv, out);
+}
+void launch_lincomb3(int64_t n, double a, const double *x, double b, const double *y, double c, const double *z,
+                     double *out, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned g = unsigned(std::min<int64_t>((n + 255) / 256, 8192));
+  hipLaunchKernelGGL(k_lincomb3, dim3(g), dim3(256), 0, s, n, a, x, b, y, c, z, out);
+}
+void launch_dot_part(int64_t n, const double *a, const double *b, double *part, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_part, dim3(unsigned(nparts)), dim3(256), 0, s, n, a, b, part);
+}
+
 // ---- geometric multigrid V-cycle on W^k (small sparse levels; one thread
 // per row, columns in blockIdx.y)
 // t = b - A x (and z = 0 when zero_z: the edge-star relaxation accumulates there)

@@ -154,6 +154,17 @@ struct PatchApply {
 // rounded up to 16 for FP64, 32 for bfloat16)
 int64_t frag_size(int m, bool bf16);
 void launch_seg_to_frag(const PatchApply &pa, bool bf16, void *frag, const int64_t *frag_off, hipStream_t s);
+// ---- Hodge Laplacians (Sec. 7.2): y = alpha A x (+ y), A in CSR; weights
+// w[c, q] scaled by smass for q < qm (the mass family) and sderiv after;
+// out = a x + b y + c z (null: zero); per-block partials of a . b
+void launch_csr_spmv(int64_t n, const int64_t *ptr, const int32_t *col, const double *val, const double *x,
+                     double *y, double alpha, bool accumulate, hipStream_t s);
+void launch_scale_weights(int64_t nc, int Q, int qm, const double *w, double smass, double sderiv, double *out,
+                          hipStream_t s);
+void launch_lincomb3(int64_t n, double a, const double *x, double b, const double *y, double c, const double *z,
+                     double *out, hipStream_t s);
+void launch_dot_part(int64_t n, const double *a, const double *b, double *part, int nparts, hipStream_t s);
+
 // Geometric multigrid V-cycle on W^k (device data; host-resident struct).
 // Level l: operator A (CSR), prolongation P from level l+1 and R = P^T,
 // relaxation data (k = 0: dinv; k = 1: dinv, vertex-hat gradients G and

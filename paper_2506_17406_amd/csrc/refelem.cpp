@@ -789,23 +789,30 @@ void eigen_dvalues(const Eigen &eb, const std::vector<double> &y, int npts, std:
 
 void eq_vertices(int d, double *out) { eq_vertices_impl(d, out); }
 
-RefElement build_reference(int d, Family fam, int p) {
+namespace {
+std::mutex &build_mutex() {
   static std::mutex mtx;
-  std::lock_guard<std::mutex> lock(mtx);
-  if (d < 2 || d > 3 || p < 1 || (d == 2 && fam != FAM_CG) || fam == FAM_NEDTWO)
-    throw std::runtime_error("unsupported (dimension, space, degree)");
-  RefElement el;
-  el.d = d;
-  el.fam = fam;
-  el.p = p;
-  el.k = form_of(fam);
-  const int k = el.k;
+  return mtx;
+}
+
+// The element's dofs as functionals on the primal coefficients of its space
+// (rows of L, in the element's dof order) and the dual basis in primal
+// coefficients; `el` (if given) receives the dof list and the counts.
+struct DualBasis {
+  std::shared_ptr<Space> sp;
+  Dense L, coef;
+};
+
+DualBasis dual_basis(int d, Family fam, int p, RefElement *el) {
+  const int k = form_of(fam);
   auto sp = make_space(d, fam, p);
   const int c = sp->c, nfull = sp->B.r;
   Dense full = Dense::eye(nfull);
   std::vector<std::vector<double>> rows;
-  el.per_entity.assign(d + 1, 0);
-  el.kind_start.assign(3 * (d + 1), -1);
+  RefElement scratch;
+  RefElement &E = el ? *el : scratch;
+  E.per_entity.assign(d + 1, 0);
+  E.kind_start.assign(3 * (d + 1), -1);
   const Family typeII = (k == 1) ? FAM_CG : FAM_NEDTWO;
   auto ents = entities(d);
   double cond = 1.0, gap = 1e300;
@@ -836,8 +843,8 @@ RefElement build_reference(int d, Family fam, int p) {
         trace(k, em.A, nq, c, nfull, vals, tr, ct);
         std::vector<double> one(nq, 1.0);
         add_row(one, tr, 1, 0);
-        el.dofs.push_back({l, ei, KIND_W, 0});
-        if (ei == 0) el.kind_start[3 * l + KIND_W] = count;
+        E.dofs.push_back({l, ei, KIND_W, 0});
+        if (ei == 0) E.kind_start[3 * l + KIND_W] = count;
         ++count;
       }
       if (l > k) {  // type-I: (d_S psi_j, tr^{k+1} d v)_S
@@ -850,13 +857,13 @@ RefElement build_reference(int d, Family fam, int p) {
         d_op(k, d, c, nq, nfull, jac, dv);
         int ct;
         trace(k + 1, em.A, nq, dcomp(k, d), nfull, dv, trdv, ct);
-        if (ei == 0 && eb->N) el.kind_start[3 * l + KIND_I] = count;
+        if (ei == 0 && eb->N) E.kind_start[3 * l + KIND_I] = count;
         for (int j = 0; j < eb->N; ++j) {
           std::vector<double> fn(size_t(nq) * ct);
           for (int t = 0; t < nq; ++t)
             for (int a = 0; a < ct; ++a) fn[size_t(t) * ct + a] = dpsi[(size_t(t) * ct + a) * eb->N + j];
           add_row(fn, trdv, ct, j);
-          el.dofs.push_back({l, ei, KIND_I, j});
+          E.dofs.push_back({l, ei, KIND_I, j});
           ++count;
         }
       }
@@ -869,29 +876,50 @@ RefElement build_reference(int d, Family fam, int p) {
         std::vector<double> tr;
         int ct;
         trace(k, em.A, nq, c, nfull, vals, tr, ct);
-        if (ei == 0 && eb->N) el.kind_start[3 * l + KIND_II] = count;
+        if (ei == 0 && eb->N) E.kind_start[3 * l + KIND_II] = count;
         for (int j = 0; j < eb->N; ++j) {
           std::vector<double> fn(size_t(nq) * ct);
           for (int t = 0; t < nq; ++t)
             for (int a = 0; a < ct; ++a) fn[size_t(t) * ct + a] = dpsi[(size_t(t) * ct + a) * eb->N + j];
           add_row(fn, tr, ct, j);
-          el.dofs.push_back({l, ei, KIND_II, j});
+          E.dofs.push_back({l, ei, KIND_II, j});
           ++count;
         }
       }
-      if (ei == 0) el.per_entity[l] = count;
+      if (ei == 0) E.per_entity[l] = count;
     }
   }
-  el.cond_probe = cond;
-  el.min_cluster_gap = gap;
+  E.cond_probe = cond;
+  E.min_cluster_gap = gap;
   const int n = int(rows.size());
   if (n != sp->B.c) throw std::runtime_error("dof count differs from the space dimension");
-  el.n = n;
-  Dense L(n, nfull);
+  E.n = n;
+  DualBasis db;
+  db.sp = sp;
+  db.L = Dense(n, nfull);
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < nfull; ++j) L(i, j) = rows[i][j];
-  Dense D = matmul(L, sp->B);
-  Dense coef = matmul(sp->B, inverse(D));  // dual basis in primal coefficients
+    for (int j = 0; j < nfull; ++j) db.L(i, j) = rows[i][j];
+  Dense D = matmul(db.L, sp->B);
+  db.coef = matmul(sp->B, inverse(D));  // dual basis in primal coefficients
+  return db;
+}
+}  // namespace
+
+RefElement build_reference(int d, Family fam, int p) {
+  std::lock_guard<std::mutex> lock(build_mutex());
+  if (d < 2 || d > 3 || p < 1 || (d == 2 && fam != FAM_CG) || fam == FAM_NEDTWO)
+    throw std::runtime_error("unsupported (dimension, space, degree)");
+  RefElement el;
+  el.d = d;
+  el.fam = fam;
+  el.p = p;
+  el.k = form_of(fam);
+  const int k = el.k;
+  DualBasis db = dual_basis(d, fam, p, &el);
+  auto sp = db.sp;
+  const int c = sp->c;
+  const int n = el.n;
+  const Dense &coef = db.coef;
   // stacked reference matrices
   Quad q = simplex_quad(d, p + 2);
   const int nq = q.size();
@@ -946,6 +974,58 @@ RefElement build_reference(int d, Family fam, int p) {
       for (int j = 0; j < n; ++j)  // exact symmetry
         el.R[(size_t(qi) * n + i) * n + j] = 0.5 * (stack[qi](i, j) + stack[qi](j, i));
   return el;
+}
+
+// The exterior derivative X^{k-1}_p -> X^k_p on the reference cell in the two
+// bases: D_hat (n_to x n_from), column j the coefficients of d phi_j in the
+// X^k basis.  d phi_j lies in X^k_p (the discrete complex is exact), so its
+// L2 projection onto the primal polynomial basis of X^k's space (Gram
+// system by a rule exact to degree 2p + 3) is d phi_j itself; the X^k dofs
+// applied to those coefficients give its expansion.
+std::vector<double> derivative_reference(int d, Family from, Family to, int p) {
+  std::lock_guard<std::mutex> lock(build_mutex());
+  if (d != 3 || form_of(to) != form_of(from) + 1 || from == FAM_NEDTWO || to == FAM_NEDTWO)
+    throw std::runtime_error("derivative_reference: needs consecutive first-kind 3D families");
+  RefElement ea, eb;
+  DualBasis da = dual_basis(d, from, p, &ea), dbb = dual_basis(d, to, p, &eb);
+  Quad q = simplex_quad(d, p + 2);
+  const int nq = q.size(), na = ea.n, nb = eb.n;
+  std::vector<double> vals, jac, dv;
+  da.sp->field(q.x.data(), nq, da.coef, vals, jac);
+  d_op(form_of(from), d, da.sp->c, nq, na, jac, dv);  // (nq x c' x na)
+  const int cd = dcomp(form_of(from), d);
+  if (cd != dbb.sp->c) throw std::runtime_error("derivative_reference: component mismatch");
+  const int nfull = dbb.sp->B.r;
+  std::vector<double> pv, pj;
+  dbb.sp->field(q.x.data(), nq, Dense::eye(nfull), pv, pj);  // primal basis values (nq x c x nfull)
+  Dense proj(nfull, na);
+  for (int t = 0; t < nq; ++t)
+    for (int a = 0; a < cd; ++a) {
+      const double *fb = pv.data() + ((size_t(t) * cd + a) * nfull);
+      const double *fa = dv.data() + ((size_t(t) * cd + a) * na);
+      for (int b = 0; b < nfull; ++b) {
+        const double wb = q.w[t] * fb[b];
+        if (wb == 0.0) continue;
+        for (int j = 0; j < na; ++j) proj(b, j) += wb * fa[j];
+      }
+    }
+  // Gram matrix of the primal basis under the same rule (the identity if
+  // the polynomial basis is orthonormal on the reference cell)
+  Dense G(nfull, nfull);
+  for (int t = 0; t < nq; ++t)
+    for (int a = 0; a < cd; ++a) {
+      const double *fb = pv.data() + ((size_t(t) * cd + a) * nfull);
+      for (int i = 0; i < nfull; ++i) {
+        const double wi = q.w[t] * fb[i];
+        if (wi == 0.0) continue;
+        for (int j = 0; j < nfull; ++j) G(i, j) += wi * fb[j];
+      }
+    }
+  Dense Dh = matmul(dbb.L, matmul(inverse(G), proj));
+  std::vector<double> out(size_t(nb) * na);
+  for (int i = 0; i < nb; ++i)
+    for (int j = 0; j < na; ++j) out[size_t(i) * na + j] = Dh(i, j);
+  return out;
 }
 
 }  // namespace rz

@@ -36,6 +36,12 @@ struct RefElement {
 // Throws std::runtime_error when a numerical check of the construction fails.
 RefElement build_reference(int d, Family fam, int p);
 
+// The exterior derivative from the first-kind 3D family `from` to the next
+// one (CG -> NED, NED -> RT) on the reference cell in the two elements'
+// bases: n_to x n_from, row-major (Sec. 7.2; lem:d-preserves-basis-functions
+// makes it the signed incidence on the Whitney functions).
+std::vector<double> derivative_reference(int d, Family from, Family to, int p);
+
 // Equilateral reference simplex of edge length 2 centred at the origin.
 void eq_vertices(int d, double *out /* (d+1) x d */);
 

@@ -98,6 +98,14 @@ def _load():
         "rz_batch_solve": (ctypes.c_int, [P, ctypes.POINTER(P), ctypes.POINTER(P), dbl, ctypes.POINTER(RzInfo), P]),
         "rz_batch_destroy": (None, [P]),
         "rz_last_error": (ctypes.c_char_p, []),
+        "rz_hodge_setup": (ctypes.c_int, [ctypes.POINTER(RzMesh), i32, i32, dbl, ctypes.POINTER(RzOptions), P,
+                                          ctypes.POINTER(P)]),
+        "rz_hodge_sizes": (ctypes.c_int, [P, pi64, pi64]),
+        "rz_hodge_apply": (ctypes.c_int, [P, P, P, P]),
+        "rz_hodge_apply_P": (ctypes.c_int, [P, P, P, P]),
+        "rz_hodge_solve": (ctypes.c_int, [P, P, P, dbl, ctypes.POINTER(RzInfo), P]),
+        "rz_hodge_destroy": (None, [P]),
+        "rz_derivative_reference": (ctypes.c_int, [i32, i32, pi32, pi32, pdbl]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -383,3 +391,75 @@ class Batch:
             _check(code)
         return [_info_dict(i, code) for i in info]
 
+
+
+def derivative_reference(k, degree):
+    """The reference-cell derivative matrix of the complex (k = 1: grad
+    CG_p -> Ned_p; k = 2: curl Ned_p -> RT_p), host only."""
+    nt, nf = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.rz_derivative_reference(k, degree, ctypes.byref(nt), ctypes.byref(nf), None))
+    D = np.empty((nt.value, nf.value))
+    _check(lib.rz_derivative_reference(k, degree, None, None, _ptr(D, ctypes.c_double)))
+    return D
+
+
+class Hodge:
+    """Hodge Laplacian on X^{k-1} x X^k with the weighted Riesz-map block
+    preconditioner and MINRES (rz_hodge_*).  Vectors: contiguous float64
+    device tensors of n0 + n1 entries, [sigma; u]."""
+
+    def __init__(self, coords, cells, degree, k, gamma=1.0, pc="hybrid", decomposition="paper", max_iter=1000,
+                 coarse="exact", mg_meshes=None, stream=None):
+        m, keep = _mesh(coords, cells)
+        levels, keep_mg = None, []
+        if mg_meshes is not None:
+            levels = (RzMesh * len(mg_meshes))()
+            for i, (Xl, Cl) in enumerate(mg_meshes):
+                levels[i], kl = _mesh(Xl, Cl)
+                keep_mg.append(kl)
+        dec = DECOMPOSITIONS[decomposition] if isinstance(decomposition, str) else decomposition
+        opts = RzOptions(1.0, 1.0, max_iter, 0, 0.0, PCS[pc] if isinstance(pc, str) else pc, 0, dec, None,
+                         COARSE[coarse] if isinstance(coarse, str) else coarse,
+                         0 if mg_meshes is None else len(mg_meshes),
+                         None if levels is None else ctypes.cast(levels, ctypes.POINTER(RzMesh)))
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(lib.rz_hodge_setup(ctypes.byref(m), degree, k, gamma, ctypes.byref(opts), _stream(stream),
+                                  ctypes.byref(h)))
+        self._h = h
+        n0, n1 = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.rz_hodge_sizes(h, ctypes.byref(n0), ctypes.byref(n1)))
+        self.n0, self.n1 = n0.value, n1.value
+        self.n = self.n0 + self.n1
+
+    def close(self):
+        if self._h:
+            lib.rz_hodge_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, t):
+        Problem._dev(t)
+        if t.dim() != 1 or not t.is_contiguous() or t.numel() != self.n:
+            raise ValueError("vectors must be contiguous with n0 + n1 entries")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def apply(self, x, y, stream=None):
+        _check(lib.rz_hodge_apply(self._h, self._vec(x), self._vec(y), _stream(stream)))
+        return y
+
+    def apply_P(self, r, z, stream=None):
+        _check(lib.rz_hodge_apply_P(self._h, self._vec(r), self._vec(z), _stream(stream)))
+        return z
+
+    def solve(self, b, x, rtol=1e-8, stream=None, check=True):
+        info = RzInfo()
+        code = lib.rz_hodge_solve(self._h, self._vec(b), self._vec(x), rtol, ctypes.byref(info), _stream(stream))
+        if check:
+            _check(code)
+        return _info_dict(info, code)

@@ -227,3 +227,17 @@ def test_hiptmair_only_for_hcurl():
     opts = rz.RzOptions(1.0, 1.0, 100, 0, 0.0, 1, 0, 4)
     assert rz.lib.rz_setup(ctypes.byref(m), 2, 2, ctypes.byref(opts), None, ctypes.byref(h)) == -2
     assert b"H(curl)" in rz.lib.rz_last_error()
+
+
+@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_derivative_reference_matches_oracle(k, p):
+    """The library's reference derivative matrix of the complex (its own
+    quadrature, Gram-system projection and dofs) against the oracle's
+    (Gauss-Jacobi rules, orthonormal projection): 1e-11 of the largest
+    entry."""
+    from oracle.hodge import derivative_reference
+    D = rz.derivative_reference(k, p)
+    Do = derivative_reference(k, p)
+    assert D.shape == Do.shape
+    assert np.abs(D - Do).max() <= 1e-11 * max(1.0, np.abs(Do).max())
