@@ -4,9 +4,10 @@ sec:results-hodge-laplace; the appendix on augmented Lagrangian
 preconditioning for Hodge Laplacians).  Test infrastructure: a plain FP64
 restatement, used only by the tests and the benchmark's CPU baseline.
 
-For k = 1 (X^0 x X^1 = CG_p x Ned_p) and k = 2 (X^1 x X^2 = Ned_p x RT_p),
-eq:hodge-laplace with natural boundary conditions reads, in the bases of the
-two spaces,
+For k = 1 (X^0 x X^1 = CG_p x Ned_p), k = 2 (X^1 x X^2 = Ned_p x RT_p) and
+k = 3 (X^2 x X^3 = RT_p x DG_{p-1}, the mixed scalar Poisson problem; d^3 =
+0, so K_3 = 0), eq:hodge-laplace with natural boundary conditions reads, in
+the bases of the two spaces,
     [ -M_{k-1}    D^T M_k ] [sigma]   [0]
     [  M_k D      K_k     ] [  u  ] = [b]
 with M the mass matrices, K_k the matrix of (d u, d v) and D the exterior
@@ -19,7 +20,11 @@ The preconditioner is eq:augmented-lagrangian: the Riesz maps
 (d u, d v) on X^k, each replaced by one application of the hybrid Schwarz
 method of the Riesz experiments (the weak form a = beta (u, v) + alpha
 (d u, d v): (alpha, beta) = (gamma, 1) and (1, 1 / gamma)), or inverted
-exactly.
+exactly.  DG_{p-1} has the L2-orthonormal Dubiner basis of P_{p-1} pulled
+back as a 3-form (psi = psi_hat o F^{-1} / det J), so its mass matrix is
+diagonal, 1 / |det J_T| per cell, and its Riesz map gamma^{-1} M_3 is
+inverted exactly (the paper's J(X^3), exact because the basis is
+orthogonal).
 """
 import numpy as np
 import scipy.linalg as sla
@@ -30,9 +35,31 @@ from .element import element
 from .mesh import Topology
 from .operator import all_cell_matrices, assemble
 from .precond import HybridSchwarz
-from .simplex import quadrature
+from .simplex import EQ_VERTICES, PolyBasis, quadrature
 
-PAIRS_K = {1: ("CG", "Ned"), 2: ("Ned", "RT")}
+PAIRS_K = {1: ("CG", "Ned"), 2: ("Ned", "RT"), 3: ("RT", "DG")}
+
+
+def divergence_reference_dg(p, d=3):
+    """(n_dg x n_rt): the coefficients of div phi_j (RT_p reference basis) in
+    the L2-orthonormal Dubiner basis of P_{p-1} on the reference cell, which
+    is the DG_{p-1} basis (div RT_p = P_{p-1})."""
+    el = element(d, "RT", p)
+    xq, wq = quadrature(d, p + 2)
+    _, dv = el.tabulate(xq)                               # (N, 1, n_rt)
+    V = PolyBasis(d, p - 1).values(xq)                    # (N, n_dg)
+    return np.einsum("q,qi,qj->ij", wq, V, dv[:, 0, :])
+
+
+def cell_volume_ratio(X, C):
+    """|det J_T| of the map from the equilateral reference cell, per cell."""
+    E = EQ_VERTICES[3]
+    Ei = np.linalg.inv((E[1:] - E[0]).T)
+    out = np.empty(len(C))
+    for c, cell in enumerate(np.sort(C, axis=1)):
+        Xc = X[cell]
+        out[c] = abs(np.linalg.det((Xc[1:] - Xc[0]).T @ Ei))
+    return out
 
 
 def derivative_reference(k, p, d=3):
@@ -78,6 +105,9 @@ class HodgeLaplacian:
     def __init__(self, X, C, k, p, gamma=1.0, exact=False, decomposition="paper"):
         fa, fb = PAIRS_K[k]
         self.k, self.p, self.gamma = k, p, gamma
+        if k == 3:
+            self._init_dg(X, C, p, gamma, exact, decomposition)
+            return
         self.el0, self.el1 = element(3, fa, p), element(3, fb, p)
         self.top0, self.top1 = Topology(X, C, self.el0), Topology(X, C, self.el1)
         self.n0, self.n1 = self.top0.n_dofs, self.top1.n_dofs
@@ -96,6 +126,35 @@ class HodgeLaplacian:
         else:
             self.P0 = HybridSchwarz(self.R0, self.top0, fa, decomposition=decomposition).apply
             self.P1 = HybridSchwarz(self.R1, self.top1, fb, decomposition=decomposition).apply
+
+    def _init_dg(self, X, C, p, gamma, exact, decomposition):
+        self.el0 = element(3, "RT", p)
+        self.top0 = Topology(X, C, self.el0)
+        self.n0 = self.top0.n_dofs
+        Dh = divergence_reference_dg(p)
+        self.ndg = Dh.shape[0]
+        nc = self.top0.n_cells
+        self.n1 = nc * self.ndg
+        rows = (np.arange(nc)[:, None, None] * self.ndg + np.arange(self.ndg)[None, :, None]) \
+            * np.ones((1, 1, Dh.shape[1]), dtype=np.int64)
+        cols = np.broadcast_to(self.top0.cell_dofs[:, None, :], rows.shape)
+        vals = np.broadcast_to(Dh[None], rows.shape)
+        self.D = sp.csr_matrix((vals.ravel(), (rows.ravel(), cols.ravel())), shape=(self.n1, self.n0))
+        self.detJ = cell_volume_ratio(self.top0.coords, C)
+        m3 = np.repeat(1.0 / self.detJ, self.ndg)
+        self.M0 = assemble(self.top0, all_cell_matrices(self.el0, self.top0, alpha=0.0, beta=1.0))
+        self.M1 = sp.diags(m3).tocsr()
+        self.K1 = sp.csr_matrix((self.n1, self.n1))
+        M1D = (self.M1 @ self.D).tocsr()
+        self.A = sp.bmat([[-self.M0, M1D.T], [M1D, None]], format="csr")
+        self.R0 = assemble(self.top0, all_cell_matrices(self.el0, self.top0, alpha=gamma, beta=1.0))
+        self.R1 = sp.diags(m3 / gamma).tocsr()
+        if exact:
+            self.P0 = spla.splu(self.R0.tocsc()).solve
+        else:
+            self.P0 = HybridSchwarz(self.R0, self.top0, "RT", decomposition=decomposition).apply
+        inv1 = gamma / m3
+        self.P1 = lambda r: inv1 * r
 
     def apply_P(self, r):
         return np.concatenate([self.P0(r[:self.n0]), self.P1(r[self.n0:])])
