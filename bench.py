@@ -666,18 +666,19 @@ def hodge(args):
     """Hodge Laplacians (Sec. 7.2, eq:hodge-laplace) on the Freudenthal mesh
     of the Fichera corner (0,1)^3 minus [1/2,1)^3 with 8 cells per edge
     (2688 tets, interior vertices jittered by 0.1 h, mesh seed 31), load
-    uniform[-1, 1] on the X^k equation (seed 32): CG_p x Ned_p and
-    Ned_p x RT_p, p = 1, 4, 6, gamma = 1 and 1e3, the split (paper) and
-    full decompositions, preconditioned MINRES to 1e-8 (the paper's
-    tolerance) from x = 0; per case setup, iterations, time and the true
-    residual ||b - A x|| / ||b|| by the library's own operator apply."""
+    uniform[-1, 1] on the X^k equation (seed 32): CG_p x Ned_p,
+    Ned_p x RT_p and RT_p x DG_{p-1}, p = 1, 4, 6, gamma = 1 and 1e3, the
+    split (paper) and full decompositions, preconditioned MINRES to 1e-8
+    (the paper's tolerance) from x = 0; per case setup, iterations, time
+    and the true residual ||b - A x|| / ||b|| by the library's own operator
+    apply."""
     import torch
     from paper_2506_17406_amd import rz
     from paper_2506_17406_amd.workloads import fichera_mesh
     torch.cuda.set_device(0)
     X, C = fichera_mesh(8, jitter=0.1, seed=31)
     rows, tot_dofs, tot_s = [], 0, 0.0
-    for k, name in ((1, "CG x Ned"), (2, "Ned x RT")):
+    for k, name in ((1, "CG x Ned"), (2, "Ned x RT"), (3, "RT x DG")):
         for p in (1, 4, 6):
             for dec in ("paper", "paper-full"):
                 for gamma in (1.0, 1e3):
@@ -712,7 +713,8 @@ def hodge(args):
     line = {"metric": "Hodge-Laplacian MINRES solve DOFs/s to rel. residual 1e-8", "value": tot_dofs / tot_s,
             "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": tot_s * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "Hodge Laplacians CG_p x Ned_p and Ned_p x RT_p, p = 1, 4, 6, gamma = 1 and 1e3, "
+            "config": {"workload": "Hodge Laplacians CG_p x Ned_p, Ned_p x RT_p and RT_p x DG_{p-1}, p = 1, 4, 6, "
+                                   "gamma = 1 and 1e3, "
                                    "Fichera-corner Freudenthal mesh 8 cells per edge (2688 tets), split "
                                    "decompositions in the value, full ones reported beside them"},
             "cases": rows}

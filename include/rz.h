@@ -365,7 +365,8 @@ void rz_destroy(rz_problem *P);
 
 /* ---- Hodge Laplacians (Sec. 7.2, eq:hodge-laplace)
  * The mixed problem on X^{k-1} x X^k with natural boundary conditions,
- * k = 1 (CG_p x Ned_p) or k = 2 (Ned_p x RT_p), in the two bases:
+ * k = 1 (CG_p x Ned_p), k = 2 (Ned_p x RT_p) or k = 3 (RT_p x DG_{p-1},
+ * the mixed Poisson problem, K_3 = 0), in the two bases:
  *   [ -M_{k-1}   D^T M_k ] [sigma]   [b_0]
  *   [  M_k D     K_k     ] [  u  ] = [b_1],
  * M the mass matrices, K_k the matrix of (d u, d v) and D the exterior
@@ -378,7 +379,12 @@ void rz_destroy(rz_problem *P);
  * Schwarz preconditioner (opts: pc form, decomposition, coarse solver and
  * max_iter as for rz_setup; NULL: the hybrid form; RZ_FP64 only, no
  * Dirichlet facets -> RZ_ERR_UNSUPPORTED), and D on the device.  gamma > 0
- * (RZ_ERR_ARG otherwise).
+ * (RZ_ERR_ARG otherwise); k outside 1..3 -> RZ_ERR_UNSUPPORTED.  For
+ * k = 3 the DG_{p-1} dofs are numbered cell by cell (cell c owns n_dg = p
+ * (p+1) (p+2) / 6 consecutive dofs, cells in input order) and carry the
+ * L2-orthonormal basis of P_{p-1} on the reference cell pulled back as a
+ * 3-form, so M_3 is diagonal (1 / |det J_c|) and B_1 = gamma |det J_c| is
+ * the exact inverse of gamma^{-1} M_3 (the paper's exact solver on X^3).
  * rz_hodge_apply: y = A x.  rz_hodge_apply_P: z = blockdiag(B_0, B_1) r.
  * rz_hodge_solve: preconditioned MINRES from x = 0 until the preconditioned
  * residual norm falls to rtol times its initial value (the paper's MINRES
@@ -387,7 +393,8 @@ void rz_destroy(rz_problem *P);
  * residual ratio), solve_ms.  Calls on one handle must not overlap.
  * rz_derivative_reference (host only): the reference-cell derivative
  * matrix D_hat of the complex (k = 1: grad CG_p -> Ned_p, k = 2: curl
- * Ned_p -> RT_p), n_to x n_from row-major, any pointer may be NULL. */
+ * Ned_p -> RT_p, k = 3: div RT_p -> DG_{p-1} in that orthonormal basis),
+ * n_to x n_from row-major, any pointer may be NULL. */
 typedef struct rz_hodge rz_hodge;
 int rz_hodge_setup(const rz_mesh *mesh, int32_t degree, int32_t k, double gamma, const rz_options *opts,
                    void *hip_stream, rz_hodge **out);

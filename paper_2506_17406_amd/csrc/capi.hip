@@ -1956,8 +1956,8 @@ void rz_batch_destroy(rz_batch *B) { delete B; }
 }  // extern "C"
 
 // ---------------------------------------------------------------- Hodge Laplacians
-// eq:hodge-laplace on X^{k-1} x X^k (k = 1: CG_p x Ned_p, k = 2: Ned_p x RT_p),
-// natural boundary conditions, in the two bases:
+// eq:hodge-laplace on X^{k-1} x X^k (k = 1: CG_p x Ned_p, k = 2: Ned_p x RT_p,
+// k = 3: RT_p x DG_{p-1}), natural boundary conditions, in the two bases:
 //   [ -M_{k-1}   D^T M_k ] [sigma]
 //   [  M_k D     K_k     ] [  u  ]
 // with D the exterior derivative in the X^k basis (d X^{k-1}_p lies in X^k_p),
@@ -1965,6 +1965,10 @@ void rz_batch_destroy(rz_batch *B) { delete B; }
 // one application of the Schwarz preconditioner of its handle:
 // (sigma, tau) + gamma (d sigma, d tau) on X^{k-1} (alpha = gamma, beta = 1)
 // and gamma^{-1} (u, v) + (d u, d v) on X^k (alpha = 1, beta = 1 / gamma).
+// For k = 3, K_3 = 0 and DG_{p-1} carries the L2-orthonormal basis of
+// P_{p-1} on the reference cell pulled back as a 3-form (psi_hat / det J), so
+// M_3 is diagonal, 1 / |det J_T| per cell: it is folded into the rows of D
+// (the stored matrix is M_3 D), and gamma^{-1} M_3 is inverted exactly.
 struct rz_hodge {
   rz_problem *P0 = nullptr, *P1 = nullptr;
   int k = 1, p = 1, max_iter = 1000;
@@ -1976,6 +1980,7 @@ struct rz_hodge {
   const double *dv = nullptr, *dtv = nullptr;
   std::vector<void *> mem;
   double *t2 = nullptr, *m2 = nullptr;  // 2 n1 each: [D sigma, u] and their X^k masses
+  double *dg_inv = nullptr;            // k = 3: gamma |det J_T| per DG dof
   double *vec = nullptr;               // MINRES: 7 vectors of n0 + n1
   double *part = nullptr, *part_host = nullptr;
   static constexpr int kParts = 256;
@@ -2006,6 +2011,12 @@ int hodge_apply(rz_hodge *H, const double *x, double *y, hipStream_t s) {
   const int64_t n0 = H->n0, n1 = H->n1;
   const double *sg = x, *u = x + n0;
   double *y0 = y, *y1 = y + n0;
+  if (H->k == 3) {
+    rz::launch_csr_spmv(n1, H->dp, H->dc, H->dv, sg, y1, 1.0, false, s);                   // M_3 D sigma
+    rz::launch_apply_A(H->tM0, sg, n0, y0, n0, 1, nullptr, s, false, 0, -1, -1.0, 0, 0, true);  // -M sigma
+    rz::launch_csr_spmv(n0, H->dtp, H->dtc, H->dtv, u, y0, 1.0, true, s);                 // + (M_3 D)^T u
+    return RZ_OK;
+  }
   rz::launch_csr_spmv(n1, H->dp, H->dc, H->dv, sg, H->t2, 1.0, false, s);              // D sigma
   HIPCHK(hipMemcpyAsync(H->t2 + n1, u, size_t(n1) * 8, hipMemcpyDeviceToDevice, s));   // u
   rz::launch_apply_A(H->tM1, H->t2, n1, H->m2, n1, 2, nullptr, s, false, 0, -1, 1.0, 0, 0, true);
@@ -2019,6 +2030,10 @@ int hodge_apply(rz_hodge *H, const double *x, double *y, hipStream_t s) {
 int hodge_apply_P(rz_hodge *H, const double *r, double *z, hipStream_t s) {
   int rc = apply_P(H->P0, r, z, 1, H->n0, s, false);
   if (rc != RZ_OK) return rc;
+  if (H->k == 3) {
+    rz::launch_diag_mul(H->n1, H->dg_inv, r + H->n0, z + H->n0, s);
+    return RZ_OK;
+  }
   return apply_P(H->P1, r + H->n0, z + H->n0, 1, H->n1, s, false);
 }
 
@@ -2035,9 +2050,20 @@ double hodge_dot(rz_hodge *H, const double *a, const double *b, hipStream_t s) {
 extern "C" {
 
 int rz_derivative_reference(int32_t k, int32_t degree, int32_t *n_to, int32_t *n_from, double *D) {
-  if (k != 1 && k != 2) return fail(RZ_ERR_UNSUPPORTED, "k must be 1 (grad: CG -> Ned) or 2 (curl: Ned -> RT)");
+  if (k < 1 || k > 3) return fail(RZ_ERR_UNSUPPORTED, "k must be 1 (grad), 2 (curl) or 3 (div)");
   if (degree < 1 || degree > 10) return fail(RZ_ERR_UNSUPPORTED, "degree must be in 1..10");
   try {
+    if (k == 3) {
+      const int na = rz::build_reference(3, rz::FAM_RT, degree).n;
+      const int nb = degree * (degree + 1) * (degree + 2) / 6;
+      if (n_to) *n_to = nb;
+      if (n_from) *n_from = na;
+      if (D) {
+        std::vector<double> Dh = rz::divergence_reference_dg(3, degree);
+        std::copy(Dh.begin(), Dh.end(), D);
+      }
+      return RZ_OK;
+    }
     const rz::Family from = k == 1 ? rz::FAM_CG : rz::FAM_NED, to = k == 1 ? rz::FAM_NED : rz::FAM_RT;
     const int na = rz::build_reference(3, from, degree).n, nb = rz::build_reference(3, to, degree).n;
     if (n_to) *n_to = nb;
@@ -2056,7 +2082,7 @@ int rz_hodge_setup(const rz_mesh *m, int32_t degree, int32_t k, double gamma, co
                    void *hip_stream, rz_hodge **out) {
   if (!m || !out) return fail(RZ_ERR_ARG, "null argument");
   *out = nullptr;
-  if (k != 1 && k != 2) return fail(RZ_ERR_UNSUPPORTED, "k must be 1 (CG x Ned) or 2 (Ned x RT)");
+  if (k < 1 || k > 3) return fail(RZ_ERR_UNSUPPORTED, "k must be 1 (CG x Ned), 2 (Ned x RT) or 3 (RT x DG)");
   if (m->dim != 3) return fail(RZ_ERR_UNSUPPORTED, "the Hodge Laplacians are built for tetrahedral meshes");
   if (!(gamma > 0.0)) return fail(RZ_ERR_ARG, "need gamma > 0");
   if (opts && opts->precision != RZ_FP64) return fail(RZ_ERR_UNSUPPORTED, "the Hodge Laplacians run in RZ_FP64");
@@ -2078,48 +2104,89 @@ int rz_hodge_setup(const rz_mesh *m, int32_t degree, int32_t k, double gamma, co
   o0.beta = 1.0;
   o1.alpha = 1.0;    // gamma^{-1} (u, v) + (d u, d v)
   o1.beta = 1.0 / gamma;
-  const rz_space s0 = k == 1 ? RZ_HGRAD : RZ_HCURL, s1 = k == 1 ? RZ_HCURL : RZ_HDIV;
+  const rz_space s0 = k == 1 ? RZ_HGRAD : k == 2 ? RZ_HCURL : RZ_HDIV, s1 = k == 1 ? RZ_HCURL : RZ_HDIV;
   int rc = rz_setup(m, degree, s0, &o0, hip_stream, &H->P0);
   if (rc != RZ_OK) return rc;
-  rc = rz_setup(m, degree, s1, &o1, hip_stream, &H->P1);
-  if (rc != RZ_OK) return rc;
+  if (k < 3) {
+    rc = rz_setup(m, degree, s1, &o1, hip_stream, &H->P1);
+    if (rc != RZ_OK) return rc;
+  }
   rz_problem *P0 = H->P0, *P1 = H->P1;
+  const int64_t nc = P0->top.n_cells;
   H->n0 = P0->top.n_dofs;
-  H->n1 = P1->top.n_dofs;
   try {
     ensure_ws(P0, 1);
-    ensure_ws(P1, 2);
     // mass-only and stiffness-only weights (linear in (alpha, beta); the
     // stacked mass family comes first: one matrix for a scalar field, six
     // component pairs for a vector field)
-    const int64_t nc = P0->top.n_cells;
-    const int qm0 = P0->k == 0 ? 1 : 6, qm1 = P1->k == 0 ? 1 : 6;
-    double *wM0 = H->dev<double>(size_t(nc) * P0->el.Q), *wM1 = H->dev<double>(size_t(nc) * P1->el.Q),
-           *wK1 = H->dev<double>(size_t(nc) * P1->el.Q);
+    const int qm0 = P0->k == 0 ? 1 : 6;
+    double *wM0 = H->dev<double>(size_t(nc) * P0->el.Q);
     rz::launch_scale_weights(nc, P0->el.Q, qm0, P0->w, 1.0, 0.0, wM0, s);
-    rz::launch_scale_weights(nc, P1->el.Q, qm1, P1->w, gamma, 0.0, wM1, s);
-    rz::launch_scale_weights(nc, P1->el.Q, qm1, P1->w, 0.0, 1.0, wK1, s);
     H->tM0 = P0->at;
     H->tM0.w = wM0;
-    H->tM1 = P1->at;
-    H->tM1.w = wM1;
-    H->tK1 = P1->at;
-    H->tK1.w = wK1;
-    // D (n1 x n0) from the reference D_hat placed per cell (every cell's
-    // basis is the pullback of the sorted-vertex reference basis, and the
-    // pullbacks commute with d), and its transpose
-    const rz::Family f0 = k == 1 ? rz::FAM_CG : rz::FAM_NED, f1 = k == 1 ? rz::FAM_NED : rz::FAM_RT;
-    const std::vector<double> Dh = rz::derivative_reference(3, f0, f1, degree);
-    const int na = P0->el.n, nb = P1->el.n;
-    std::vector<std::pair<int64_t, double>> ent;  // key row * n0 + col
-    ent.reserve(size_t(nc) * nb * 4);
-    for (int64_t c = 0; c < nc; ++c)
-      for (int i = 0; i < nb; ++i)
-        for (int j = 0; j < na; ++j) {
-          const double v = Dh[size_t(i) * na + j];
-          if (v == 0.0) continue;
-          ent.push_back({int64_t(P1->top.cell_dofs[c * nb + i]) * H->n0 + P0->top.cell_dofs[c * na + j], v});
+    // the entries of D (n1 x n0), keyed row * n0 + col
+    std::vector<std::pair<int64_t, double>> ent;
+    const int na = P0->el.n;
+    if (k < 3) {
+      H->n1 = P1->top.n_dofs;
+      ensure_ws(P1, 2);
+      const int qm1 = P1->k == 0 ? 1 : 6;
+      double *wM1 = H->dev<double>(size_t(nc) * P1->el.Q), *wK1 = H->dev<double>(size_t(nc) * P1->el.Q);
+      rz::launch_scale_weights(nc, P1->el.Q, qm1, P1->w, gamma, 0.0, wM1, s);
+      rz::launch_scale_weights(nc, P1->el.Q, qm1, P1->w, 0.0, 1.0, wK1, s);
+      H->tM1 = P1->at;
+      H->tM1.w = wM1;
+      H->tK1 = P1->at;
+      H->tK1.w = wK1;
+      // D from the reference D_hat placed per cell (every cell's basis is the
+      // pullback of the sorted-vertex reference basis, and the pullbacks
+      // commute with d); entries shared by cells coincide
+      const rz::Family f0 = k == 1 ? rz::FAM_CG : rz::FAM_NED, f1 = k == 1 ? rz::FAM_NED : rz::FAM_RT;
+      const std::vector<double> Dh = rz::derivative_reference(3, f0, f1, degree);
+      const int nb = P1->el.n;
+      ent.reserve(size_t(nc) * nb * 4);
+      for (int64_t c = 0; c < nc; ++c)
+        for (int i = 0; i < nb; ++i)
+          for (int j = 0; j < na; ++j) {
+            const double v = Dh[size_t(i) * na + j];
+            if (v == 0.0) continue;
+            ent.push_back({int64_t(P1->top.cell_dofs[c * nb + i]) * H->n0 + P0->top.cell_dofs[c * na + j], v});
+          }
+    } else {
+      // DG_{p-1}: cell c owns dofs c * nb .. c * nb + nb - 1; the stored
+      // matrix is M_3 D, row (c, i) = D_hat row i / |det J_c|
+      const std::vector<double> Dh = rz::divergence_reference_dg(3, degree);
+      const int nb = int(Dh.size() / size_t(na));
+      H->n1 = nc * nb;
+      std::vector<double> Ve(12);
+      rz::eq_vertices(3, Ve.data());
+      auto det3 = [](const double J[3][3]) {
+        return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+               J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      };
+      double E[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) E[a][b] = Ve[(b + 1) * 3 + a] - Ve[a];
+      const double detE = std::fabs(det3(E));
+      std::vector<double> inv(size_t(H->n1));
+      ent.reserve(size_t(nc) * nb * na);
+      for (int64_t c = 0; c < nc; ++c) {
+        const int64_t *v = &P0->top.cells[c * 4];
+        double J[3][3];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) J[a][b] = m->coords[v[b + 1] * 3 + a] - m->coords[v[0] * 3 + a];
+        const double dj = std::fabs(det3(J)) / detE;  // |det| of the map from the reference cell
+        for (int i = 0; i < nb; ++i) {
+          inv[size_t(c) * nb + i] = gamma * dj;
+          for (int j = 0; j < na; ++j) {
+            const double val = Dh[size_t(i) * na + j];
+            if (val == 0.0) continue;
+            ent.push_back({(c * nb + i) * H->n0 + P0->top.cell_dofs[c * na + j], val / dj});
+          }
         }
+      }
+      H->dg_inv = H->upload(inv);
+    }
     std::sort(ent.begin(), ent.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
     std::vector<int64_t> keys;
     std::vector<double> vals;
@@ -2154,8 +2221,10 @@ int rz_hodge_setup(const rz_mesh *m, int32_t degree, int32_t k, double gamma, co
     H->dtp = H->upload(ptr);
     H->dtc = H->upload(col);
     H->dtv = H->upload(val);
-    H->t2 = H->dev<double>(size_t(2) * H->n1);
-    H->m2 = H->dev<double>(size_t(2) * H->n1);
+    if (k < 3) {
+      H->t2 = H->dev<double>(size_t(2) * H->n1);
+      H->m2 = H->dev<double>(size_t(2) * H->n1);
+    }
     H->vec = H->dev<double>(size_t(7) * (H->n0 + H->n1));
     H->part = H->dev<double>(rz_hodge::kParts);
     HIPCHK(hipHostMalloc((void **)&H->part_host, sizeof(double) * rz_hodge::kParts, hipHostMallocDefault));

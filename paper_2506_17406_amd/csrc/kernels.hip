@@ -2141,6 +2141,12 @@ __global__ void k_lincomb3(int64_t n, double a, const double *x, double b, const
   }
 }
 
+// out = d .* x (out may alias x)
+__global__ void k_diag_mul(int64_t n, const double *d, const double *x, double *out) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = d[i] * x[i];
+}
+
 // per-block partial sums of a . b (blockDim 256; gridDim.x partials)
 __global__ __launch_bounds__(256) void k_dot_part(int64_t n, const double *__restrict__ a,
                                                   const double *__restrict__ b, double *__restrict__ part) {
@@ -2167,6 +2173,11 @@ void launch_lincomb3(int64_t n, double a, const double *x, double b, const doubl
   if (n <= 0) return;
   const unsigned g = unsigned(std::min<int64_t>((n + 255) / 256, 8192));
   hipLaunchKernelGGL(k_lincomb3, dim3(g), dim3(256), 0, s, n, a, x, b, y, c, z, out);
+}
+void launch_diag_mul(int64_t n, const double *d, const double *x, double *out, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned g = unsigned(std::min<int64_t>((n + 255) / 256, 8192));
+  hipLaunchKernelGGL(k_diag_mul, dim3(g), dim3(256), 0, s, n, d, x, out);
 }
 void launch_dot_part(int64_t n, const double *a, const double *b, double *part, int nparts, hipStream_t s) {
   hipLaunchKernelGGL(k_dot_part, dim3(unsigned(nparts)), dim3(256), 0, s, n, a, b, part);

@@ -164,6 +164,8 @@ void launch_scale_weights(int64_t nc, int Q, int qm, const double *w, double sma
 void launch_lincomb3(int64_t n, double a, const double *x, double b, const double *y, double c, const double *z,
                      double *out, hipStream_t s);
 void launch_dot_part(int64_t n, const double *a, const double *b, double *part, int nparts, hipStream_t s);
+// out = d .* x (elementwise; out may alias x)
+void launch_diag_mul(int64_t n, const double *d, const double *x, double *out, hipStream_t s);
 
 // Geometric multigrid V-cycle on W^k (device data; host-resident struct).
 // Level l: operator A (CSR), prolongation P from level l+1 and R = P^T,

@@ -1028,4 +1028,30 @@ std::vector<double> derivative_reference(int d, Family from, Family to, int p) {
   return out;
 }
 
+// The divergence RT_p -> DG_{p-1} on the reference cell: n_dg x n_rt with
+// entry (i, j) = (div phi_j, psi_i), psi the L2-orthonormal (Dubiner) basis
+// of P_{p-1} on the reference cell (the DG_{p-1} basis: div phi_j lies in
+// P_{p-1}, so these are its coefficients).
+std::vector<double> divergence_reference_dg(int d, int p) {
+  std::lock_guard<std::mutex> lock(build_mutex());
+  if (d != 3 || p < 1) throw std::runtime_error("divergence_reference_dg: 3D, p >= 1");
+  RefElement ea;
+  DualBasis da = dual_basis(d, FAM_RT, p, &ea);
+  Quad q = simplex_quad(d, p + 2);
+  const int nq = q.size(), na = ea.n;
+  std::vector<double> vals, jac, dv;
+  da.sp->field(q.x.data(), nq, da.coef, vals, jac);
+  d_op(2, d, da.sp->c, nq, na, jac, dv);  // (nq x 1 x na)
+  PolyBasis pb(d, p - 1);
+  std::vector<double> pv(size_t(nq) * pb.n);
+  pb.eval(q.x.data(), nq, pv.data(), nullptr);
+  std::vector<double> out(size_t(pb.n) * na, 0.0);
+  for (int t = 0; t < nq; ++t)
+    for (int i = 0; i < pb.n; ++i) {
+      const double wi = q.w[t] * pv[size_t(t) * pb.n + i];  // eval applies the normalisation
+      for (int j = 0; j < na; ++j) out[size_t(i) * na + j] += wi * dv[size_t(t) * na + j];
+    }
+  return out;
+}
+
 }  // namespace rz

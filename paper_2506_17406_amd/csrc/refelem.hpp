@@ -42,6 +42,11 @@ RefElement build_reference(int d, Family fam, int p);
 // makes it the signed incidence on the Whitney functions).
 std::vector<double> derivative_reference(int d, Family from, Family to, int p);
 
+// The divergence RT_p -> DG_{p-1} on the reference cell: n_dg x n_rt
+// row-major, the coefficients of div phi_j in the L2-orthonormal basis of
+// P_{p-1} (the DG_{p-1} basis).
+std::vector<double> divergence_reference_dg(int d, int p);
+
 // Equilateral reference simplex of edge length 2 centred at the origin.
 void eq_vertices(int d, double *out /* (d+1) x d */);
 

@@ -395,7 +395,8 @@ class Batch:
 
 def derivative_reference(k, degree):
     """The reference-cell derivative matrix of the complex (k = 1: grad
-    CG_p -> Ned_p; k = 2: curl Ned_p -> RT_p), host only."""
+    CG_p -> Ned_p; k = 2: curl Ned_p -> RT_p; k = 3: div RT_p -> DG_{p-1}
+    in the library's L2-orthonormal basis of P_{p-1}), host only."""
     nt, nf = ctypes.c_int32(), ctypes.c_int32()
     _check(lib.rz_derivative_reference(k, degree, ctypes.byref(nt), ctypes.byref(nf), None))
     D = np.empty((nt.value, nf.value))
@@ -404,9 +405,9 @@ def derivative_reference(k, degree):
 
 
 class Hodge:
-    """Hodge Laplacian on X^{k-1} x X^k with the weighted Riesz-map block
-    preconditioner and MINRES (rz_hodge_*).  Vectors: contiguous float64
-    device tensors of n0 + n1 entries, [sigma; u]."""
+    """Hodge Laplacian on X^{k-1} x X^k (k = 1, 2, 3) with the weighted
+    Riesz-map block preconditioner and MINRES (rz_hodge_*).  Vectors:
+    contiguous float64 device tensors of n0 + n1 entries, [sigma; u]."""
 
     def __init__(self, coords, cells, degree, k, gamma=1.0, pc="hybrid", decomposition="paper", max_iter=1000,
                  coarse="exact", mg_meshes=None, stream=None):

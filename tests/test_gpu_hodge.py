@@ -3,13 +3,19 @@ eq:hodge-laplace, eq:augmented-lagrangian) against the oracle
 (oracle/hodge.py) on Freudenthal meshes of the Fichera corner:
 
 * the mixed operator A = [-M_{k-1}, D^T M_k; M_k D, K_k] (1e-12 relative),
-  k = 1 (CG_p x Ned_p) and k = 2 (Ned_p x RT_p), p = 1..3, jittered;
+  k = 1 (CG_p x Ned_p), k = 2 (Ned_p x RT_p) and k = 3 (RT_p x DG_{p-1}),
+  p = 1..3, jittered.  The two sides build their orthonormal DG bases
+  independently, so for k = 3 the library's DG coefficients are the
+  oracle's times one orthogonal Q per cell (Q = D D_o^+ from the two
+  reference divergence matrices; the host tests pin it orthogonal), and
+  every comparison maps the oracle's vectors through diag(I, I x Q);
 * the block preconditioner (one Schwarz application per weighted Riesz
   map), hybrid and additive forms, gamma = 1, 10 and 1e3 (1e-10 times
   max(1, gamma / 10): the Riesz matrices' conditioning grows with gamma);
 * preconditioned MINRES: iteration count within one of the oracle's, the
   solution within 1e-7 of the dense solution, and the paper's p = 1 rows of
-  tab:hodge-fichera (6 iterations at gamma = 1, 3 at gamma = 1e3);
+  tab:hodge-fichera (6 iterations at gamma = 1, 3 at gamma = 1e3; 5 and 3
+  for RT_1 x DG_0);
 * the argument errors.
 """
 import numpy as np
@@ -19,7 +25,7 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-from oracle.hodge import HodgeLaplacian, minres  # noqa: E402
+from oracle.hodge import HodgeLaplacian, divergence_reference_dg, minres  # noqa: E402
 from paper_2506_17406_amd.workloads import fichera_mesh  # noqa: E402
 
 
@@ -31,7 +37,19 @@ def rz():
     return mod
 
 
-CASES = [(k, p) for k in (1, 2) for p in (1, 2, 3)]
+CASES = [(k, p) for k in (1, 2, 3) for p in (1, 2, 3)]
+
+
+def to_library_basis(rz, k, p, n0):
+    """x (oracle numbering and bases) -> the same function in the library's
+    coefficients: the identity for k = 1, 2; for k = 3 the DG block of each
+    cell is multiplied by Q (the change between the two orthonormal DG
+    bases)."""
+    if k < 3:
+        return lambda x: x
+    Q = rz.derivative_reference(3, p) @ np.linalg.pinv(divergence_reference_dg(p))
+    nd = Q.shape[0]
+    return lambda x: np.concatenate([x[:n0], (x[n0:].reshape(-1, nd) @ Q.T).ravel()])
 
 
 @pytest.mark.parametrize("k,p", CASES, ids=[f"k{k}-p{p}" for k, p in CASES])
@@ -43,21 +61,23 @@ def test_operator_and_preconditioner(rz, k, p):
         if H is None:
             from oracle.precond import AdditiveSchwarz
             H = HodgeLaplacian(X, C, k, p, gamma=gamma, exact=True)
-            fa, fb = {1: ("CG", "Ned"), 2: ("Ned", "RT")}[k]
+            fa, fb = {1: ("CG", "Ned"), 2: ("Ned", "RT"), 3: ("RT", None)}[k]
             H.P0 = AdditiveSchwarz(H.R0, H.top0, fa).apply
-            H.P1 = AdditiveSchwarz(H.R1, H.top1, fb).apply
+            if fb is not None:   # DG_{p-1}: the exact diagonal inverse either way
+                H.P1 = AdditiveSchwarz(H.R1, H.top1, fb).apply
         G = rz.Hodge(X, C, p, k, gamma=gamma, pc=pc)
         assert (G.n0, G.n1) == (H.n0, H.n1)
+        T = to_library_basis(rz, k, p, H.n0)
         x = np.random.default_rng(3).uniform(-1, 1, G.n)
-        xt = torch.from_numpy(x).cuda()
+        xt = torch.from_numpy(T(x)).cuda()
         yt = torch.empty_like(xt)
         G.apply(xt, yt)
         zt = torch.empty_like(xt)
         G.apply_P(xt, zt)
         torch.cuda.synchronize()
-        ref = H.A @ x
+        ref = T(H.A @ x)
         assert np.abs(yt.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
-        refp = H.apply_P(x)
+        refp = T(H.apply_P(x))
         # the weighted Riesz matrices' condition numbers grow like gamma (the
         # gamma-weighted derivative term), and so does the rounding of the
         # explicit patch and coarse inverses on both sides
@@ -66,7 +86,7 @@ def test_operator_and_preconditioner(rz, k, p):
         G.close()
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 @pytest.mark.parametrize("p", [2, 3])
 def test_minres_matches_oracle(rz, k, p):
     X, C = fichera_mesh(2, jitter=0.1, seed=23)
@@ -75,19 +95,20 @@ def test_minres_matches_oracle(rz, k, p):
     b = H.rhs(np.random.default_rng(5).uniform(-1, 1, H.n1))
     xo, io = minres(lambda v: H.A @ v, H.apply_P, b, rtol=1e-10)
     G = rz.Hodge(X, C, p, k, gamma=gamma)
-    bt = torch.from_numpy(b).cuda()
+    T = to_library_basis(rz, k, p, H.n0)
+    bt = torch.from_numpy(T(b)).cuda()
     xt = torch.empty_like(bt)
     info = G.solve(bt, xt, rtol=1e-10)
     x = xt.cpu().numpy()
     xd = np.linalg.solve(H.A.toarray(), b)
+    xo, xd = T(xo), T(xd)
     assert abs(info["iterations"] - io["iterations"]) <= 1, (info["iterations"], io["iterations"])
     assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)
     assert np.linalg.norm(xo - xd) <= 1e-7 * np.linalg.norm(xd)
     G.close()
 
 
-@pytest.mark.parametrize("k", [1, 2])
-@pytest.mark.parametrize("gamma,want", [(1.0, 6), (1e3, 3)])
+@pytest.mark.parametrize("k,gamma,want", [(1, 1.0, 6), (1, 1e3, 3), (2, 1.0, 6), (2, 1e3, 3), (3, 1.0, 5), (3, 1e3, 3)])
 def test_paper_p1_counts(rz, k, gamma, want):
     X, C = fichera_mesh(4)
     G = rz.Hodge(X, C, 1, k, gamma=gamma)
@@ -103,7 +124,7 @@ def test_paper_p1_counts(rz, k, gamma, want):
 def test_argument_errors(rz):
     X, C = fichera_mesh(2)
     with pytest.raises(rz.RzError):
-        rz.Hodge(X, C, 2, 3)
+        rz.Hodge(X, C, 2, 4)
     with pytest.raises(rz.RzError):
         rz.Hodge(X, C, 2, 1, gamma=0.0)
     G = rz.Hodge(X, C, 1, 1)

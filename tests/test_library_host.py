@@ -241,3 +241,23 @@ def test_derivative_reference_matches_oracle(k, p):
     Do = derivative_reference(k, p)
     assert D.shape == Do.shape
     assert np.abs(D - Do).max() <= 1e-11 * max(1.0, np.abs(Do).max())
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_divergence_reference_matches_oracle(p):
+    """div RT_p -> DG_{p-1} on the reference cell.  Both sides expand in an
+    L2-orthonormal basis of P_{p-1} of their own (each builds its Dubiner
+    basis independently, with its own ordering and signs), so the two
+    matrices agree up to one orthogonal change of basis Q: Q = D D_o^+ must
+    be orthogonal and carry D_o to D (1e-11), and D^T D (the reference
+    div-div matrix, which no choice of orthonormal basis changes) must
+    agree."""
+    from oracle.hodge import divergence_reference_dg
+    D = rz.derivative_reference(3, p)
+    Do = divergence_reference_dg(p)
+    assert D.shape == Do.shape == (p * (p + 1) * (p + 2) // 6, p * (p + 1) * (p + 3) // 2)
+    scale = max(1.0, np.abs(Do).max())
+    assert np.abs(D.T @ D - Do.T @ Do).max() <= 1e-11 * scale ** 2
+    Q = D @ np.linalg.pinv(Do)
+    assert np.abs(Q.T @ Q - np.eye(len(Q))).max() <= 1e-11
+    assert np.abs(Q @ Do - D).max() <= 1e-11 * scale
