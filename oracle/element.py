@@ -26,7 +26,10 @@ Readings where the paper is silent (each is listed in the design notes):
   cluster of m functions W (L2-orthonormal) the basis is rotated to
   W R, R = Y^T (Y Y^T)^{-1/2}, where Y_ij = pi_i(W_j) for the first m probe
   functionals pi_i of a fixed sequence (point values, projected on a fixed
-  direction for vector fields, at points drawn from SplitMix64).  The result
+  direction for vector fields, at points drawn from SplitMix64; for the 2D
+  H(div) family the direction is turned by R, so that 2D RT_p is exactly the
+  quarter turn R of 2D Ned_p, as the remark after eq:hdiv-dofs describes).
+  The result
   does not depend on which orthonormal basis of the cluster the
   eigensolver returned, and it fixes signs.
 * R3 "mu != 0": the number of discarded eigenpairs is the kernel dimension
@@ -49,6 +52,20 @@ from .simplex import EQ_VERTICES, PolyBasis, quadrature, splitmix64_stream
 
 TAU = 1e-7           # relative eigenvalue gap that defines a cluster (R2)
 FORM = {"CG": 0, "Ned": 1, "NedTwo": 1, "RT": 2}
+DIV_FAMILIES = ("RT",)
+
+
+def form_degree(l, family):
+    """k of a family on an l-simplex: H(div) is the (l-1)-forms (k = 1 in 2D:
+    the remark after eq:hdiv-dofs)."""
+    return l - 1 if family in DIV_FAMILIES else FORM[family]
+
+
+def rot90(v):
+    """R v = (v_1, -v_0) on the component axis 1: the quarter turn that carries
+    2D H(curl) to 2D H(div) (n = R t on an edge, curl = R grad, and
+    div R w = rot w)."""
+    return np.stack([v[:, 1], -v[:, 0]], axis=1)
 
 
 # --------------------------------------------------------------------------
@@ -92,6 +109,25 @@ def d_op(k, l, vals, jac):
     raise ValueError((k, l))
 
 
+def d_family(family, l, vals, jac):
+    """The exterior derivative of a family's fields on an l-simplex: div for
+    the H(div) families in any dimension, otherwise d^k."""
+    if family in DIV_FAMILIES:
+        return sum(jac[:, a, a] for a in range(l))[:, None, :]
+    return d_op(FORM[family], l, vals, jac)
+
+
+def trace_family(family, A, vals):
+    """tr of a family's field on a subsimplex with tangent frame A: the normal
+    component n.v for H(div) on a facet (n = a_1 x a_2 in 3D, n = R a_1 in
+    2D), otherwise tr^k (eq:tr-k)."""
+    d, l = A.shape
+    if family in DIV_FAMILIES and l == d - 1 and d == 2:
+        n = np.array([A[1, 0], -A[0, 0]])
+        return np.einsum("a,qam->qm", n, vals)[:, None, :]
+    return trace(form_degree(d, family), A, vals)
+
+
 def _orth_range(S, expected):
     U, s, _ = np.linalg.svd(S, full_matrices=False)
     rank = int(np.sum(s > 1e-10 * s[0]))
@@ -116,6 +152,8 @@ def space_dim(l, family, p):
             return p * (p + 2)
         return p * (p + 2) * (p + 3) // 2
     if family == "RT":
+        if l == 2:
+            return p * (p + 2)
         return p * (p + 1) * (p + 3) // 2
     raise ValueError(family)
 
@@ -151,7 +189,7 @@ def make_space(l, family, p):
     elif family == "Ned" and l == 2:
         for m in low:
             extra.append(np.stack([-x[:, 1] * V[:, m], x[:, 0] * V[:, m]], axis=1))
-    elif family == "RT" and l == 3:
+    elif family == "RT":
         for m in low:
             extra.append(x * V[:, m][:, None])
     else:
@@ -212,7 +250,7 @@ def bubble_space(l, family, p):
     """Orthonormal coefficient basis of X_ring^k(S_hat): the fields of the
     l-dimensional space whose trace vanishes on every facet."""
     sp = make_space(l, family, p)
-    k = FORM[family]
+    k = form_degree(l, family)
     rows = []
     for F in combinations(range(l + 1), l):
         o, A, y0 = entity_map(l, F)
@@ -225,7 +263,7 @@ def bubble_space(l, family, p):
             z = o + (zq - y0) @ A.T
             test = PolyBasis(l - 1, p).values(zq)
         vals, _ = sp.field(z)
-        tr = trace(k, A, vals) if l - 1 > 0 or k == 0 else None
+        tr = trace_family(family, A, vals) if l - 1 > 0 or k == 0 else None
         if tr is None:
             raise ValueError("no trace of a k>0 form on a vertex")
         # moments of each trace component against P_p on the facet
@@ -246,7 +284,7 @@ class EigenBasis:
         self.Psi, self.mu, self.lam = Psi, mu, 1.0 / mu
         self.mu_all, self.n_ker, self.cond_probe = mu_all, n_ker, cond_probe
         self.clusters = []
-        self.k = FORM[family]
+        self.k = form_degree(l, family)
         self.N = Psi.shape[1]
 
     def values(self, x):
@@ -255,12 +293,14 @@ class EigenBasis:
 
     def dvalues(self, x):
         vals, jac = self.space.field(x, self.Psi)
-        return d_op(self.k, self.l, vals, jac)
+        return d_family(self.family, self.l, vals, jac)
 
 
-def kernel_family(family, p):
+def kernel_family(family, p, l=3):
     """The (k-1)-form family whose bubble derivatives span ker d_S on the
-    k-form bubbles (exact bubble complex, eq:bubble-subcomplex)."""
+    k-form bubbles of an l-simplex (exact bubble complex,
+    eq:bubble-subcomplex); for RT_p in 2D it is CG_p (the remark after
+    eq:hdiv-dofs)."""
     if family == "CG":
         return None
     if family == "Ned":
@@ -268,7 +308,7 @@ def kernel_family(family, p):
     if family == "NedTwo":
         return ("CG", p + 1)
     if family == "RT":
-        return ("NedTwo", p)
+        return ("CG", p) if l == 2 else ("NedTwo", p)
     raise ValueError(family)
 
 
@@ -294,16 +334,15 @@ def bubble_eigenproblem(l, family, p):
     kernel eigenpairs to discard (R3: the dimension N^{k-1}_S of
     eq:bubble-trace-dim-counts, not a threshold)."""
     sp, Bb = bubble_space(l, family, p)
-    k = FORM[family]
     if Bb.shape[1] == 0:
         return sp, Bb, None, np.zeros(0), None, 0
     x, w = quadrature(l, p + 2)
     vals, jac = sp.field(x, Bb)
-    dv = d_op(k, l, vals, jac)
+    dv = d_family(family, l, vals, jac)
     M = np.einsum("q,qcm,qcn->mn", w, vals, vals)
     K = np.einsum("q,qcm,qcn->mn", w, dv, dv)
     mu, Vec = sla.eigh(K, M)
-    kf = kernel_family(family, p)
+    kf = kernel_family(family, p, l)
     n_ker = 0 if kf is None else eigenbasis(l, *kf).N
     if n_ker:
         assert np.all(np.abs(mu[:n_ker]) < 1e-10 * mu[-1]), "kernel not null"
@@ -355,6 +394,8 @@ def canonical_clusters(l, sp, Bb, K, mu, W):
         Wc = W[:, i:j]
         m = j - i
         pts, dirs = probes(l, sp.c, m)
+        if sp.family in DIV_FAMILIES and l == 2:
+            dirs = np.stack([dirs[:, 1], -dirs[:, 0]], axis=1)   # R e: 2D H(div) = R (2D H(curl))
         pv, _ = sp.field(pts, Bb @ Wc)          # (m, c, m)
         Y = np.einsum("ic,icj->ij", dirs, pv)   # Y_ij = pi_i(W_j)
         ev, evec = np.linalg.eigh(Y @ Y.T)
@@ -399,7 +440,7 @@ class Element:
     def __init__(self, d, family, p):
         if family not in ("CG", "Ned", "RT", "NedTwo"):
             raise ValueError(family)
-        self.d, self.family, self.p, self.k = d, family, p, FORM[family]
+        self.d, self.family, self.p, self.k = d, family, p, form_degree(d, family)
         self.space = make_space(d, family, p)
         self.dofs = []
         rows = []
@@ -407,8 +448,9 @@ class Element:
         # functionals act on the whole primal space P_p^c (identity basis)
         full = np.eye(self.space.B.shape[0])
         # the (k-1)-form family whose bubble derivatives give the type-II dofs:
-        # CG_p for Ned_p, NedTwo_p for RT_p (R4), CG_{p+1} for NedTwo_p
-        typeII = kernel_family(family, p)
+        # CG_p for Ned_p, NedTwo_p for RT_p (R4; CG_p in 2D), CG_{p+1} for
+        # NedTwo_p
+        typeII = kernel_family(family, p, d)
         for l, ents in enumerate(entities(d)):
             for ei, verts in enumerate(ents):
                 o, A, y0 = entity_map(d, verts)
@@ -422,14 +464,14 @@ class Element:
                 vals, jac = self.space.field(xq, full)
                 if l == k:
                     # Whitney moment (1, tr v)_S  (point value for k = 0)
-                    tr = trace(k, A, vals)
+                    tr = trace_family(family, A, vals)
                     rows.append(np.einsum("q,qm->m", wq, tr[:, 0, :]))
                     self.dofs.append(DofInfo(l, ei, verts, "W", 0))
                 if l > k:
                     # type-I: (d_S psi_j, d_S tr v)_S, via tr^{k+1} d v
                     eb = eigenbasis(l, family, p)
                     dpsi = eb.dvalues(yq)
-                    dv = d_op(k, d, vals, jac)
+                    dv = d_family(family, d, vals, jac)
                     trdv = trace(k + 1, A, dv)
                     for j in range(eb.N):
                         rows.append(np.einsum("q,qc,qcm->m", wq, dpsi[:, :, j], trdv))
@@ -438,7 +480,9 @@ class Element:
                     # type-II: (d_S psi^{k-1}_j, tr v)_S
                     eb = eigenbasis(l, *typeII)
                     dpsi = eb.dvalues(yq)
-                    tr = trace(k, A, vals)
+                    if family in DIV_FAMILIES and d == 2 and l == 2:
+                        dpsi = rot90(dpsi)      # curl = R grad in 2D
+                    tr = trace_family(family, A, vals)
                     for j in range(eb.N):
                         rows.append(np.einsum("q,qc,qcm->m", wq, dpsi[:, :, j], tr))
                         self.dofs.append(DofInfo(l, ei, verts, "II", j))
@@ -458,7 +502,7 @@ class Element:
         if self.k == 0:
             dv = jac[:, 0, :, :]
         else:
-            dv = d_op(self.k, self.d, vals, jac)
+            dv = d_family(self.family, self.d, vals, jac)
         return vals, dv
 
     def counts(self):

@@ -2,8 +2,9 @@
 
 eq:weak-form: a^k(u, v) = (u, beta v) + (d^k u, alpha d^k v).  A global basis
 function on T is the pullback eq:pullback-3d-def of a reference basis
-function: identity (k=0), covariant Piola J^{-T} (k=1), contravariant Piola
-J / det J (k=2).  ``cell_matrix`` evaluates the definition by quadrature on
+function: identity (H(grad)), covariant Piola J^{-T} (H(curl)), contravariant
+Piola J / det J (H(div), also in 2D where it is k = 1).  The derivatives map
+as J^{-T} grad, J curl / det J (3D), rot / det J (2D) and div / det J.  ``cell_matrix`` evaluates the definition by quadrature on
 the physical cell; ``reference_stack`` / ``cell_weights`` give the same
 matrix as a weighted sum of reference integrals (used only to check the
 library's exported tables and as an identity pin).
@@ -14,6 +15,28 @@ import scipy.sparse as sp
 from .simplex import EQ_VERTICES, quadrature
 
 PAIRS = {2: [(0, 0), (1, 1), (0, 1)], 3: [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]}
+
+
+def piola(el):
+    """0 identity, 1 covariant, 2 contravariant."""
+    if el.k == 0:
+        return 0
+    return 2 if el.family in ("RT",) else 1
+
+
+def physical_fields(el, J, vals, dv):
+    """Pulled-back values and derivatives on a cell with Jacobian J."""
+    det = np.linalg.det(J)
+    Jinv = np.linalg.inv(J)
+    kind = piola(el)
+    if kind == 0:
+        return vals, np.einsum("ba,qbn->qan", Jinv, dv)                 # J^{-T} grad
+    if kind == 1:
+        v = np.einsum("ba,qbn->qan", Jinv, vals)                        # J^{-T} v
+        if el.d == 2:
+            return v, dv / det                                          # rot / det J
+        return v, np.einsum("ab,qbn->qan", J, dv) / det                 # J curl / det J
+    return np.einsum("ab,qbn->qan", J, vals) / det, dv / det           # J v / det J, div / det J
 
 
 def jacobian(el, X):
@@ -30,18 +53,8 @@ def cell_matrix(el, X, alpha=1.0, beta=1.0, tab=None):
         tab = (wq,) + el.tabulate(xq)
     wq, vals, dv = tab
     J = jacobian(el, X)
-    det = np.linalg.det(J)
-    Jinv = np.linalg.inv(J)
-    if el.k == 0:
-        v = vals
-        dphys = np.einsum("ba,qbn->qan", Jinv, dv)        # J^{-T} grad
-    elif el.k == 1:
-        v = np.einsum("ba,qbn->qan", Jinv, vals)          # J^{-T} v
-        dphys = np.einsum("ab,qbn->qan", J, dv) / det     # J curl / det J
-    else:
-        v = np.einsum("ab,qbn->qan", J, vals) / det       # J v / det J
-        dphys = dv / det                                  # div / det J
-    s = abs(det)
+    v, dphys = physical_fields(el, J, vals, dv)
+    s = abs(np.linalg.det(J))
     # sum over quadrature points and components as one matrix product
     nq, n = v.shape[0], v.shape[2]
     V2 = v.reshape(-1, n)
@@ -108,10 +121,11 @@ def cell_weights(el, X, alpha=1.0, beta=1.0):
     G = Ji @ Ji.T          # J^{-1} J^{-T}
     H = J.T @ J
     pr = lambda Mx: [Mx[a, b] for a, b in PAIRS[el.d]]
-    if el.k == 0:
+    kind = piola(el)
+    if kind == 0:
         return np.array([beta * s] + pr(alpha * s * G))
-    if el.k == 1:
-        return np.array(pr(beta * s * G) + pr(alpha * H / s))
+    if kind == 1:
+        return np.array(pr(beta * s * G) + (pr(alpha * H / s) if el.d == 3 else [alpha / s]))
     return np.array(pr(beta * H / s) + [alpha / s])
 
 
@@ -129,17 +143,8 @@ def functional_load(el, top, u, du, alpha=1.0, beta=1.0, nq=None):
         X = top.coords[top.cells[c]]
         J = jacobian(el, X)
         det = np.linalg.det(J)
-        Jinv = np.linalg.inv(J)
         xp = X[0] + (xq - E[0]) @ J.T
-        if el.k == 0:
-            v = vals_r
-            dphys = np.einsum("ba,qbn->qan", Jinv, dv_r)
-        elif el.k == 1:
-            v = np.einsum("ba,qbn->qan", Jinv, vals_r)
-            dphys = np.einsum("ab,qbn->qan", J, dv_r) / det
-        else:
-            v = np.einsum("ab,qbn->qan", J, vals_r) / det
-            dphys = dv_r / det
+        v, dphys = physical_fields(el, J, vals_r, dv_r)
         U, DU = u(xp), du(xp)
         s = abs(det)
         b[top.cell_dofs[c]] += s * (beta * np.einsum("q,qc,qcn->n", wq, U, v)

@@ -14,6 +14,14 @@ Additive form (AdditiveSchwarz):
     plus edge stars of the type-I interface space X^{1,I}_Gamma|star E
     (eq:hcurl-decomp);
   - H(div): edge stars of X^2_Gamma, PAFW(1)(X^2_Gamma)+J (eq:hdiv-decomp).
+  - 2D H(curl) and 2D H(div) (both k = 1, and 2D RT_p is the quarter turn of
+    2D Ned_p, so the two share every decomposition, the curl of a CG
+    function having the coefficients of its gradient): the H(curl) form
+    above with the dimensions shifted -- the edge stars of X^{1,I}_Gamma
+    hold the edge's Whitney dof only (an edge of a triangle carries no
+    type-I dofs and the faces are the cells), the vertex-star potentials
+    the vertex function and the CG edge dofs; "full" adds the cells' type-I
+    dofs to the edge stars and the CG cell interiors to the potentials.
   A restriction to a star keeps the dofs of the entities that contain the
   star's centre (they vanish on the star's boundary).
 * Coarse space W^k (Whitney forms; lem:basis-contains-whitney): reading R9,
@@ -199,10 +207,17 @@ def curl_potential_patches(top, full=False):
     return out
 
 
+def solver_family(top, family):
+    """The family whose decompositions a space uses: 2D RT_p those of 2D
+    Ned_p (its quarter turn)."""
+    return "Ned" if (top.d == 2 and family == "RT") else family
+
+
 def patch_lists(top, family, decomposition="paper"):
     """Plain patches of a decomposition: list of ascending global dof
     arrays (the potentials are separate: potential_patches,
     curl_potential_patches)."""
+    family = solver_family(top, family)
     if decomposition in ("vertex", "vertex-full"):
         return vertex_star_lists(top, decomposition == "vertex-full")
     if decomposition not in DECOMPOSITIONS:
@@ -226,7 +241,7 @@ def patch_lists(top, family, decomposition="paper"):
         # type-I stars: the edge's Whitney dof and the type-I dofs of the faces
         # (and cells) containing it; Hiptmair stars: every dof of those
         typeI = decomposition.startswith("paper")
-        faces_of = top.edge_faces()
+        faces_of = top.edge_faces() if d == 3 else [[] for _ in range(top.n_ent[1])]
         cells_of = cells_containing(top, 1)
         for e in range(top.n_ent[1]):
             idx = top.entity_dofs(1, e, kinds=("W",) if typeI else None)
@@ -234,7 +249,7 @@ def patch_lists(top, family, decomposition="paper"):
                 idx += top.entity_dofs(2, f, kinds=("I",) if typeI else None)
             if full:
                 for c in cells_of[e]:
-                    idx += top.entity_dofs(3, c, kinds=("I",) if typeI else None)
+                    idx += top.entity_dofs(d, c, kinds=("I",) if typeI else None)
             out.append(np.array(sorted(idx), dtype=np.int64))
     elif family == "RT":
         faces_of = top.edge_faces()
@@ -282,10 +297,10 @@ DECOMPOSITIONS = ("paper", "vertex", "vertex-full", "paper-full", "hiptmair", "h
 
 def potential_patches(top, cg_N, full=False):
     """H(curl) vertex potentials: sparse G_V (n_dofs x n_V) per vertex.
-    cg_N = dofs per entity of the CG_p potential space (vertex, edge, face,
-    and cell when full).  Columns: the vertex, then the CG dofs of its edges
-    (ascending edge id, then index), then of its faces, then (full) of its
-    cells."""
+    cg_N = dofs per entity dimension of the CG_p potential space.  Columns:
+    the vertex, then the CG dofs of its edges (ascending edge id, then
+    index), then of its faces (3D), then (full) of its cells."""
+    d = top.d
     edges_of, faces_of = top.vertex_star()
     cells_of = cells_containing(top, 0) if full else None
     out = []
@@ -310,8 +325,8 @@ def potential_patches(top, cg_N, full=False):
                 rows.append(j); cols.append(col); vals.append(1.0); col += 1
         if full:
             for c in cells_of[v]:
-                ii = top.entity_dofs(3, c, kinds=("II",))
-                assert len(ii) == cg_N[3]
+                ii = top.entity_dofs(d, c, kinds=("II",))
+                assert len(ii) == cg_N[d]
                 for j in ii:
                     rows.append(j); cols.append(col); vals.append(1.0); col += 1
         out.append(sp.csc_matrix((vals, (rows, cols)), shape=(top.n_dofs, col)))
@@ -349,11 +364,12 @@ class AdditiveSchwarz:
         self.A = A
         self.top = top
         self.family = family
+        family = solver_family(top, family)
         self.decomposition = decomposition
         self.removed = np.zeros(0, dtype=np.int64) if dirichlet is None else np.asarray(dirichlet, dtype=np.int64)
         keep = np.ones(top.n_dofs, dtype=bool)
         keep[self.removed] = False
-        k = {"CG": 0, "Ned": 1, "RT": 2}[family]
+        k = top.el.k
         diag = A.diagonal()
         full = decomposition.endswith("full")
         self.I = np.zeros(0, dtype=np.int64) if full else interior_dofs(top)
@@ -368,9 +384,8 @@ class AdditiveSchwarz:
         self.potentials = []    # (G_V, cho factor)
         pots = []
         if family == "Ned" and not decomposition.startswith("vertex"):
-            p = top.el.p
-            cg_N = (1, p - 1, (p - 1) * (p - 2) // 2, (p - 1) * (p - 2) * (p - 3) // 6)
-            pots = potential_patches(top, cg_N, full)
+            from .element import element
+            pots = potential_patches(top, element(top.d, "CG", top.el.p).counts(), full)
         if family == "RT" and decomposition.startswith("typeI"):
             pots = curl_potential_patches(top, full)
         for G in pots:
