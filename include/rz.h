@@ -5,9 +5,9 @@
  *
  * Problem (Sec. 2, eq:weak-form): find u in X^k_p(T_h) with
  *     (u, beta v) + (d^k u, alpha d^k v) = F(v)   for all v in X^k_p(T_h),
- * for k = 0 (H(grad), CG_p), k = 1 (H(curl), Ned_p first kind) and k = 2
- * (H(div), RT_p first kind), on a conforming simplicial mesh (triangles for
- * k = 0 in 2D, tetrahedra in 3D), with natural (pure Neumann) boundary
+ * for H(grad) (k = 0, CG_p), H(curl) (k = 1, Ned_p first kind) and H(div)
+ * (k = 2 in 3D, k = 1 in 2D; RT_p first kind), on a conforming simplicial
+ * mesh (triangles or tetrahedra), with natural (pure Neumann) boundary
  * conditions, or on X^k_{p,D} with a Dirichlet part Gamma_D of the
  * boundary (rz_options.dirichlet_facet; Sec. 5).  F is given as its load
  * vector b_i = F(phi_i) in the paper's orthogonality-promoting basis
@@ -18,6 +18,12 @@
  *   H(grad)  PAFW(0)(X^0_Gamma) + J(X^0_I)          (eq:approx-sc-pafw)
  *   H(curl)  PH(X^0_Gamma, X^{1,I}_Gamma) + J(X^1_I) (eq:hcurl-decomp)
  *   H(div)   PAFW(1)(X^2_Gamma) + J(X^2_I)           (eq:hdiv-decomp)
+ * In 2D, RT_p is the quarter turn R v = (v_1, -v_0) of Ned_p (the remark
+ * after eq:hdiv-dofs: its dofs are the H(curl) ones with n = R t and
+ * curl = R grad), so the two 2D spaces have the same numbering, the same
+ * matrices and the H(curl) decompositions with the dimensions shifted (an
+ * edge star holds the edge's Whitney dof; the vertex-star potentials the
+ * vertex function and the CG edge dofs).
  * each with an exact solve on the Whitney coarse space W^k.
  *
  * Numbering (host-exported, see rz_export_topology): each cell's vertices are
@@ -52,7 +58,7 @@ extern "C" {
 enum {
   RZ_OK = 0,
   RZ_ERR_ARG = -1,              /* bad pointer, size, alpha < 0, beta <= 0, dim */
-  RZ_ERR_UNSUPPORTED = -2,      /* (dim, space, degree) outside 2D CG / 3D CG,Ned,RT, 1 <= p <= 10 */
+  RZ_ERR_UNSUPPORTED = -2,      /* (dim, space, degree) outside CG, Ned, RT in 2D / 3D, 1 <= p <= 10 */
   RZ_ERR_MESH = -3,             /* vertex index out of range or repeated in a cell */
   RZ_ERR_DEGENERATE_CELL = -4,  /* |det J_T| <= 1e-12 h^d */
   RZ_ERR_NOT_SPD = -5,          /* non-positive pivot in a patch or coarse Cholesky */
@@ -333,7 +339,8 @@ int rz_export_topology(const rz_problem *P, int32_t *cell_dofs, int64_t *n_patch
  * row-major), ordered: the value family then the derivative family; a vector
  * family lists the component pairs 00, 11, 22, 01, 02, 12 (3D; 00, 11, 01 in
  * 2D) with off-diagonal pairs symmetrised (R_ab + R_ba), a scalar family one
- * matrix.  A_T = sum_q w_{T,q} R_q with w from the Piola maps of
+ * matrix (the 2D rot and div are scalars: Q = 4 for 2D Ned_p and RT_p).
+ * A_T = sum_q w_{T,q} R_q with w from the Piola maps of
  * eq:pullback-3d-def. */
 int rz_export_reference(const rz_problem *P, double *Rq);
 

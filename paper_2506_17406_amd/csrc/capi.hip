@@ -477,6 +477,7 @@ void setup_multigrid(rz_problem &P, const rz_mesh *m, const rz_options *o, hipSt
   if (P.d != 3) throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for tetrahedral meshes"};
   if (!P.dir_dofs.empty())
     throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for pure Neumann problems"};
+  if (P.d != 3) throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for tetrahedral meshes"};
   if (o->mg_levels < 2 || !o->mg_meshes) throw RzError{RZ_ERR_ARG, "multigrid needs mg_levels >= 2 meshes"};
   const rz_mesh *H = o->mg_meshes;
   for (int l = 0; l < o->mg_levels; ++l)
@@ -656,9 +657,11 @@ double *scratch_address() {
 }  // namespace
 
 // rz_decomposition values and the spaces they are built for
-static int check_decomposition(int32_t dec, int space) {
+static int check_decomposition(int32_t dec, int space, int dim) {
   if (dec < RZ_DECOMP_PAPER || dec > RZ_DECOMP_TYPEI_FULL) return fail(RZ_ERR_ARG, "unknown decomposition");
-  if ((dec == RZ_DECOMP_HIPTMAIR || dec == RZ_DECOMP_HIPTMAIR_FULL) && space != RZ_HCURL)
+  // 2D H(div) is the quarter turn of 2D H(curl) and shares its decompositions
+  if ((dec == RZ_DECOMP_HIPTMAIR || dec == RZ_DECOMP_HIPTMAIR_FULL) && space != RZ_HCURL &&
+      !(dim == 2 && space == RZ_HDIV))
     return fail(RZ_ERR_UNSUPPORTED, "the standard Hiptmair-Toselli decompositions are built for H(curl) only");
   if ((dec == RZ_DECOMP_TYPEI || dec == RZ_DECOMP_TYPEI_FULL) && space == RZ_HGRAD)
     return fail(RZ_ERR_UNSUPPORTED, "the type-I Hiptmair-Toselli decompositions need H(curl) or H(div)");
@@ -679,7 +682,6 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
   if (!(alpha >= 0.0) || !(beta > 0.0)) return fail(RZ_ERR_ARG, "need alpha >= 0 and beta > 0");
   if (degree < 1 || degree > 10) return fail(RZ_ERR_UNSUPPORTED, "degree must be in 1..10");
   if (space < RZ_HGRAD || space > RZ_HDIV) return fail(RZ_ERR_ARG, "unknown space");
-  if (m->dim == 2 && space != RZ_HGRAD) return fail(RZ_ERR_UNSUPPORTED, "2D supports H(grad) only");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const auto t_setup = std::chrono::steady_clock::now();
   auto P = std::make_unique<rz_problem>();
@@ -694,7 +696,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     if (opts->pc != RZ_PC_ADDITIVE && opts->pc != RZ_PC_HYBRID) return fail(RZ_ERR_ARG, "unknown preconditioner");
     P->pc = opts->pc;
     P->graphs = opts->eager == 0;
-    if (int e = check_decomposition(opts->decomposition, space)) return e;
+    if (int e = check_decomposition(opts->decomposition, space, m->dim)) return e;
     P->decomp = opts->decomposition;
     if (opts->dirichlet_facet)
       P->dir_flags.assign(opts->dirichlet_facet, opts->dirichlet_facet + m->n_cells * (m->dim + 1));
@@ -723,7 +725,8 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
       rz::Dense Ei = rz::inverse(E);
       double *dX = P->upload(X, s);
       double *dEi = P->upload(Ei.a, s);
-      rz::launch_weights(d, P->k, nc, dX, dEi, alpha, beta, P->w, Q, s);
+      const int pullback = P->k == 0 ? 0 : (P->el.fam == rz::FAM_RT ? 2 : 1);
+      rz::launch_weights(d, pullback, nc, dX, dEi, alpha, beta, P->w, Q, s);
     }
     // interior diagonal (Jacobi on X^k_I; an empty group under the full
     // vertex stars)
@@ -1541,7 +1544,6 @@ static int check_space(int32_t dim, int32_t degree, rz_space space, rz::Family &
   if (dim != 2 && dim != 3) return fail(RZ_ERR_ARG, "dim must be 2 or 3");
   if (space < RZ_HGRAD || space > RZ_HDIV) return fail(RZ_ERR_ARG, "unknown space");
   if (degree < 1 || degree > 10) return fail(RZ_ERR_UNSUPPORTED, "degree must be in 1..10");
-  if (dim == 2 && space != RZ_HGRAD) return fail(RZ_ERR_UNSUPPORTED, "2D supports H(grad) only");
   fam = space == RZ_HGRAD ? rz::FAM_CG : (space == RZ_HCURL ? rz::FAM_NED : rz::FAM_RT);
   return RZ_OK;
 }
@@ -1564,7 +1566,7 @@ static int numbering_impl(const rz_mesh *m, int32_t degree, rz_space space, int3
                           int32_t *cell_dofs, int64_t *n_patches, int64_t *n_patch_entries, int64_t *patch_ptr,
                           int32_t *patch_dofs) {
   if (!m || !m->cells) return fail(RZ_ERR_ARG, "null argument");
-  if (int e = check_decomposition(dec, space)) return e;
+  if (int e = check_decomposition(dec, space, m->dim)) return e;
   rz::Family fam;
   if (int e = check_space(m->dim, degree, space, fam)) return e;
   if (m->n_vertices <= 0 || m->n_cells <= 0) return fail(RZ_ERR_ARG, "empty mesh");

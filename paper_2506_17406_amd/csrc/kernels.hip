@@ -95,6 +95,9 @@ inline unsigned grid_for(int64_t n, int bs, unsigned cap = 1u << 20) {
 }
 
 // ------------------------------------------------------------------ setup
+// w_{T,q} of the stacked form for one cell per thread.  k selects the pullback
+// (eq:pullback-3d-def): 0 identity (H(grad)), 1 covariant Piola (H(curl)),
+// 2 contravariant Piola (H(div), also the 2D RT_p whose form degree is 1).
 __global__ void k_weights(int d, int k, int64_t nc, const double *__restrict__ X, const double *__restrict__ Einv,
                           double alpha, double beta, double *__restrict__ w, int Q) {
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -150,10 +153,11 @@ __global__ void k_weights(int d, int k, int64_t nc, const double *__restrict__ X
     wc[0] = beta * s;
     for (int i = 0; i < np; ++i) wc[1 + i] = alpha * s * G[pa[i]][pb[i]];
   } else if (k == 1) {
-    for (int i = 0; i < np; ++i) {
-      wc[i] = beta * s * G[pa[i]][pb[i]];
-      wc[np + i] = alpha * H[pa[i]][pb[i]] / s;
-    }
+    for (int i = 0; i < np; ++i) wc[i] = beta * s * G[pa[i]][pb[i]];
+    if (d == 3)
+      for (int i = 0; i < np; ++i) wc[np + i] = alpha * H[pa[i]][pb[i]] / s;  // J curl / det J
+    else
+      wc[np] = alpha / s;  // the 2D rot is a scalar: rot / det J
   } else {
     for (int i = 0; i < np; ++i) wc[i] = beta * H[pa[i]][pb[i]] / s;
     wc[np] = alpha / s;

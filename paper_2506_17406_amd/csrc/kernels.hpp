@@ -17,6 +17,7 @@ struct PcgState {
 enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_MAXIT = 2, PCG_BREAKDOWN = 3 };
 
 // ---- setup
+// k: the pullback, 0 identity, 1 covariant Piola, 2 contravariant Piola
 void launch_weights(int d, int k, int64_t n_cells, const double *X, const double *Einv, double alpha, double beta,
                     double *w, int Q, hipStream_t s);
 void launch_interior_diag(int64_t n_cells, int n, int Q, const double *R, const double *w, const int32_t *cell_dofs,

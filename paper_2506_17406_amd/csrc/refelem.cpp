@@ -906,8 +906,22 @@ DualBasis dual_basis(int d, Family fam, int p, RefElement *el) {
 }  // namespace
 
 RefElement build_reference(int d, Family fam, int p) {
+  if (d == 2 && fam == FAM_RT && p >= 1) {
+    // 2D RT_p is the quarter turn R v = (v_1, -v_0) of 2D Ned_p (its dofs are
+    // the H(curl) ones with n = R t, curl = R grad: the remark after
+    // eq:hdiv-dofs): the same dofs and numbering, div R phi = rot phi, and
+    // the component mass tables become R_00 <- R_11, R_11 <- R_00, R_01 <- -R_01
+    RefElement el = build_reference(2, FAM_NED, p);
+    el.fam = FAM_RT;
+    const size_t nn = size_t(el.n) * el.n;
+    std::vector<double> r00(el.R.begin(), el.R.begin() + nn);
+    std::copy(el.R.begin() + nn, el.R.begin() + 2 * nn, el.R.begin());
+    std::copy(r00.begin(), r00.end(), el.R.begin() + nn);
+    for (size_t i = 2 * nn; i < 3 * nn; ++i) el.R[i] = -el.R[i];
+    return el;
+  }
   std::lock_guard<std::mutex> lock(build_mutex());
-  if (d < 2 || d > 3 || p < 1 || (d == 2 && fam != FAM_CG) || fam == FAM_NEDTWO)
+  if (d < 2 || d > 3 || p < 1 || (d == 2 && fam != FAM_CG && fam != FAM_NED) || fam == FAM_NEDTWO)
     throw std::runtime_error("unsupported (dimension, space, degree)");
   RefElement el;
   el.d = d;

@@ -148,9 +148,12 @@ Incidence incidence(const Topology &t) {
     for (int a = 0; a < 2; ++a) in.v_edges[t.ent[1][e * 2 + a]].push_back(e);
   for (int64_t c = 0; c < t.n_cells; ++c)
     for (int a = 0; a <= d; ++a) in.v_cells[t.cells[c * (d + 1) + a]].push_back(c);
+  in.e_cells.resize(t.n_ent[1]);
+  if (d == 2)
+    for (int64_t c = 0; c < t.n_cells; ++c)
+      for (int s = 0; s < 3; ++s) in.e_cells[t.cell_ent[1][c * 3 + s]].push_back(c);
   if (d == 3) {
     in.e_faces.resize(t.n_ent[1]);
-    in.e_cells.resize(t.n_ent[1]);
     for (int64_t f = 0; f < t.n_ent[2]; ++f) {
       for (int a = 0; a < 3; ++a) in.v_faces[t.ent[2][f * 3 + a]].push_back(f);
       // the three edges of face f are cell-edge ids of any cell; find them via sorted lookup
@@ -237,11 +240,15 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
   const bool full = decomposition_full(dec);
   const bool hiptmair = dec == DECOMP_HIPTMAIR || dec == DECOMP_HIPTMAIR_FULL;
   const bool typeI = dec == DECOMP_TYPEI || dec == DECOMP_TYPEI_FULL;
-  if (hiptmair && el.fam != FAM_NED)
+  // 2D RT_p is the quarter turn of 2D Ned_p: the same dofs, and the curl of a
+  // CG function has the coefficients of its gradient, so it takes the H(curl)
+  // decompositions
+  const Family fam = (d == 2 && el.fam == FAM_RT) ? FAM_NED : el.fam;
+  if (hiptmair && fam != FAM_NED)
     throw std::runtime_error("the Hiptmair-Toselli decompositions are built for H(curl) only");
-  if (typeI && el.fam == FAM_CG)
+  if (typeI && fam == FAM_CG)
     throw std::runtime_error("the type-I Hiptmair-Toselli decompositions need H(curl) or H(div)");
-  if (typeI && el.fam == FAM_RT) {
+  if (typeI && fam == FAM_RT) {
     // PH(X^{1,I}, X^{2,I}) (eq:pavarino_hiptmair-novel; split: eq:hdiv-ph-reduced)
     if (full) {
       // face stars X^{2,I}|star F: the face's Whitney dof and the type-I
@@ -284,7 +291,7 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
     out.push_back(std::move(pv));
     return out;
   }
-  if (dec == DECOMP_VERTEX || dec == DECOMP_VERTEX_FULL || el.fam == FAM_CG) {
+  if (dec == DECOMP_VERTEX || dec == DECOMP_VERTEX_FULL || fam == FAM_CG) {
     // vertex stars (eq:approx-sc-pafw; with the cell interiors, eq:pafw):
     // the entities containing the vertex carry the dofs whose support lies
     // in its star; entity_dofs adds nothing where the space has no dofs
@@ -302,18 +309,21 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
     out.push_back(std::move(ps));
     return out;
   }
-  if (el.fam == FAM_NED) {
+  if (fam == FAM_NED) {
     // edge stars of the type-I interface space X^{1,I}_Gamma (eq:hcurl-decomp),
     // or of every kind of dof (eq:pavarino_hiptmair); the full forms add the
-    // dofs of those kinds of the cells containing the edge
+    // dofs of those kinds of the cells containing the edge.  In 2D the faces
+    // are the cells: an edge star holds the edge's Whitney dof (Hiptmair:
+    // every edge dof) and, full, the cells' type-I (every) dofs
     const int kw = hiptmair ? -1 : KIND_W, ki = hiptmair ? -1 : KIND_I;  // type-I forms: as DECOMP_PAPER
     PatchSet pe = empty_set();
     for (int64_t e = 0; e < t.n_ent[1]; ++e) {
       std::vector<int32_t> dofs;
       entity_dofs(t, el, 1, e, kw, dofs);
-      for (int64_t f : in.e_faces[e]) entity_dofs(t, el, 2, f, ki, dofs);
+      if (d == 3)
+        for (int64_t f : in.e_faces[e]) entity_dofs(t, el, 2, f, ki, dofs);
       if (full)
-        for (int64_t c : in.e_cells[e]) entity_dofs(t, el, 3, c, ki, dofs);
+        for (int64_t c : in.e_cells[e]) entity_dofs(t, el, d, c, ki, dofs);
       add_patch(pe, t, el, plain_cols(dofs), in.e_cells[e], mark_col, mark_coef);
     }
     out.push_back(std::move(pe));
@@ -342,13 +352,13 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
       if (full)  // the CG cell interiors: the Ned type-II cell dofs
         for (int64_t c : in.v_cells[v]) {
           std::vector<int32_t> ii;
-          entity_dofs(t, el, 3, c, KIND_II, ii);
+          entity_dofs(t, el, d, c, KIND_II, ii);
           for (int32_t g : ii) cols.push_back({{g, 1.0}});
         }
       add_patch(pv, t, el, cols, in.v_cells[v], mark_col, mark_coef);
     }
     out.push_back(std::move(pv));
-  } else if (el.fam == FAM_RT) {
+  } else if (fam == FAM_RT) {
     // edge stars of X^2_Gamma (eq:hdiv-decomp); full: PAFW(1)(X^2)
     PatchSet ps = empty_set();
     for (int64_t e = 0; e < t.n_ent[1]; ++e) {

@@ -7,7 +7,9 @@ H(div) PAFW(1)(X^2)); the standard Hiptmair-Toselli decompositions of
 H(curl) PH(X^0_Gamma, X^1_Gamma) + J ("hiptmair") and PH(X^0, X^1)
 ("hiptmair-full"); the type-I Hiptmair-Toselli decompositions
 PH(X^{k-1,I}, X^{k,I}) with and without the split ("typeI", "typeI-full";
-for H(div) built from curl potentials).
+for H(div) built from curl potentials).  2D H(curl) and H(div) take the
+H(curl) forms with the dimensions shifted (2D RT_p is the quarter turn of
+2D Ned_p).
 
 Sizes: meshes of 6-162 cells, degrees 2-8, seeded jitter and load vectors;
 the largest full stars near the 2048-dof patch limit (H(grad) p = 8: 1695,
@@ -51,7 +53,10 @@ SETS = ([(c, f) for f in ("vertex", "vertex-full") for c in CASES] +
         [(c, f) for f in ("hiptmair", "hiptmair-full") for c in OTHER] +
         [(c, f) for f in ("typeI", "typeI-full")
          for c in [(3, "RT", 3, 2, 0.1), (3, "RT", 4, 3, 0.0), (3, "RT", 2, 2, 0.1), (3, "RT", 3, 0, 0.0),
-                   (3, "RT", 6, 2, 0.1), (3, "Ned", 3, 2, 0.1)]])
+                   (3, "RT", 6, 2, 0.1), (3, "Ned", 3, 2, 0.1)]] +
+        # 2D H(curl) and H(div) (the quarter turn): every decomposition
+        [(c, f) for f in ("paper-full", "vertex", "vertex-full", "hiptmair", "hiptmair-full", "typeI")
+         for c in [(2, "Ned", 4, 3, 0.1), (2, "RT", 5, 3, 0.1)]])
 PCS = ["additive", "hybrid"]
 _cache = {}
 

@@ -9,6 +9,10 @@ workloads run that the basic parity cases do not reach (through the C ABI).
   restricted applies), for Q = 4, 7 and 12 stacked matrices, in FP64 and in
   the FP32 refinement copy.
 * Coefficients away from alpha = beta = 1, one case per space.
+* 2D H(curl) (Ned_p) and 2D H(div) (RT_p, the quarter turn of Ned_p) as
+  solve spaces, p = 1..10 on Kuhn meshes of the square: apply_A, apply_P
+  and the solve, with the same bars; the 2D stacked form has Q = 4 (three
+  mass components and the scalar rot or div).
 
 Bars: apply_A, two checks that separate the two error sources -- the
 kernels' arithmetic: max |y - A_lib x| <= 1e-12 max |A_lib x|, where A_lib
@@ -173,8 +177,36 @@ def test_degree_solve(fam, p):
     check_solve(top, A, P, prob)
 
 
+# ---- 2D H(curl) and H(div) ---------------------------------------------------
+DEGREES_2D = [(f, p) for f in ("Ned", "RT") for p in range(1, 11)]
+
+
+def mesh_n_2d(p):
+    return 4 if p <= 6 else 2
+
+
+@pytest.mark.parametrize("fam,p", DEGREES_2D, ids=lambda v: str(v))
+def test_2d_apply_A(fam, p):
+    top, A, P, prob = setup(2, fam, p, mesh_n_2d(p))
+    check_apply_A(top, A, prob, p)
+
+
+@pytest.mark.parametrize("fam,p", DEGREES_2D, ids=lambda v: str(v))
+def test_2d_apply_P(fam, p):
+    top, A, P, prob = setup(2, fam, p, mesh_n_2d(p))
+    rho = prob.pc_weights()
+    assert abs(rho[0] / P.rho_I - 1) <= 1e-10 and abs(rho[1] / P.rho_Gamma - 1) <= 1e-10
+    check_apply_P(top, P, prob)
+
+
+@pytest.mark.parametrize("fam,p", DEGREES_2D, ids=lambda v: str(v))
+def test_2d_solve(fam, p):
+    top, A, P, prob = setup(2, fam, p, mesh_n_2d(p))
+    check_solve(top, A, P, prob)
+
+
 # ---- every tile instance of the contraction ---------------------------------
-TILE_CASES = [(2, "CG", 4, 4), (3, "CG", 5, 2), (3, "RT", 4, 2), (3, "Ned", 4, 2)]
+TILE_CASES = [(2, "CG", 4, 4), (3, "CG", 5, 2), (3, "RT", 4, 2), (3, "Ned", 4, 2), (2, "Ned", 4, 4)]
 
 
 def tile_ids(v):
@@ -239,7 +271,8 @@ def test_tile_argument_errors():
 
 
 # ---- coefficients away from one ---------------------------------------------
-COEFF_CASES = [(2, "CG", 4, 4), (3, "CG", 4, 2), (3, "Ned", 4, 2), (3, "RT", 4, 2)]
+COEFF_CASES = [(2, "CG", 4, 4), (3, "CG", 4, 2), (3, "Ned", 4, 2), (3, "RT", 4, 2), (2, "Ned", 4, 4),
+               (2, "RT", 4, 4)]
 COEFFS = [(1e3, 1.0), (1e-3, 1.0), (1.0, 0.25)]
 
 

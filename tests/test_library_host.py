@@ -42,7 +42,8 @@ def test_reference_argument_errors():
     assert rz.lib.rz_reference(4, 3, 0, ctypes.byref(n), ctypes.byref(Q), None) == -1      # dim
     assert rz.lib.rz_reference(3, 11, 0, ctypes.byref(n), ctypes.byref(Q), None) == -2     # degree
     assert rz.lib.rz_reference(3, 0, 0, ctypes.byref(n), ctypes.byref(Q), None) == -2
-    assert rz.lib.rz_reference(2, 3, 1, ctypes.byref(n), ctypes.byref(Q), None) == -2      # 2D H(curl)
+    assert rz.lib.rz_reference(2, 3, 1, ctypes.byref(n), ctypes.byref(Q), None) == 0       # 2D H(curl)
+    assert (n.value, Q.value) == (15, 4)                                                  # p (p + 2); 3 + 1
     assert rz.lib.rz_reference(3, 3, 7, ctypes.byref(n), ctypes.byref(Q), None) == -1      # space
     assert b"space" in rz.lib.rz_last_error()
 
@@ -99,7 +100,7 @@ def test_setup_rejects_before_device_work():
 # p = 8 in 3D take 20-80 s each, so Ned_9, Ned_10 and RT_9, RT_10 are
 # "heavy" (run with RZ_HEAVY_TESTS=1)
 HEAVY = pytest.mark.heavy
-REF_CASES = [(2, "CG", p) for p in range(1, 11)] + [(3, "CG", p) for p in range(1, 11)] + \
+REF_CASES = [(2, f, p) for f in ("CG", "Ned", "RT") for p in range(1, 11)] + [(3, "CG", p) for p in range(1, 11)] + \
             [(3, f, p) for f in ("Ned", "RT") for p in range(1, 9)] + \
             [pytest.param(3, f, p, marks=HEAVY) for f in ("Ned", "RT") for p in (9, 10)]
 
@@ -112,7 +113,9 @@ def table_tolerance(d, fam, p):
     2.1e-10: their type-II dofs use the NedTwo cell eigenbasis, whose
     canonical cluster rotation has the census's worst probe conditioning
     (cond(Y) = 3.3e3 at p = 9), which amplifies the rounding of each
-    eigensolver's cluster subspace."""
+    eigensolver's cluster subspace.  2D Ned_p and RT_p (the library rotates
+    its Ned tables, the oracle builds RT from its own functionals): <= 9.2e-12
+    at p = 10."""
     if p <= 8:
         return 1e-11
     return 5e-10 if fam == "RT" else 5e-11
@@ -128,7 +131,8 @@ def test_reference_tables_match_oracle(d, fam, p):
 
 
 NUM_CASES = [(2, "CG", 4, 4), (2, "CG", 2, 3), (3, "CG", 1, 2), (3, "CG", 4, 2), (3, "Ned", 1, 2),
-             (3, "Ned", 3, 3), (3, "RT", 1, 2), (3, "RT", 3, 3)]
+             (3, "Ned", 3, 3), (3, "RT", 1, 2), (3, "RT", 3, 3), (2, "Ned", 1, 3), (2, "Ned", 4, 3),
+             (2, "RT", 3, 3)]
 
 
 @pytest.mark.parametrize("d,fam,p,n", NUM_CASES, ids=lambda v: str(v))
@@ -150,7 +154,8 @@ def test_numbering_bit_exact(d, fam, p, n, shuffle):
         assert np.array_equal(dofs[ptr[i]:ptr[i + 1]], idx)
 
 
-VSTAR_CASES = [(2, "CG", 4, 3), (3, "CG", 4, 2), (3, "Ned", 3, 2), (3, "RT", 3, 2), (3, "Ned", 1, 2)]
+VSTAR_CASES = [(2, "CG", 4, 3), (3, "CG", 4, 2), (3, "Ned", 3, 2), (3, "RT", 3, 2), (3, "Ned", 1, 2),
+               (2, "Ned", 3, 3), (2, "RT", 4, 3)]
 
 
 @pytest.mark.parametrize("d,fam,p,n", VSTAR_CASES, ids=lambda v: str(v))
