@@ -51,8 +51,8 @@ import scipy.linalg as sla
 from .simplex import EQ_VERTICES, PolyBasis, quadrature, splitmix64_stream
 
 TAU = 1e-7           # relative eigenvalue gap that defines a cluster (R2)
-FORM = {"CG": 0, "Ned": 1, "NedTwo": 1, "RT": 2}
-DIV_FAMILIES = ("RT",)
+FORM = {"CG": 0, "Ned": 1, "NedTwo": 1, "RT": 2, "BDM": 2}
+DIV_FAMILIES = ("RT", "BDM")
 
 
 def form_degree(l, family):
@@ -145,7 +145,7 @@ def space_dim(l, family, p):
     P = lambda q: comb(q + l, l) if q >= 0 else 0
     if family == "CG":
         return P(p)
-    if family == "NedTwo":
+    if family in ("NedTwo", "BDM"):
         return l * P(p)
     if family == "Ned":
         if l == 2:
@@ -167,7 +167,8 @@ def make_space(l, family, p):
     n = poly.n
     if family == "CG":
         return Space(l, 1, poly, np.eye(n), family, p)
-    if family == "NedTwo":
+    if family in ("NedTwo", "BDM"):
+        # second kind (eq:second-kind-def): all of P_p^l
         return Space(l, l, poly, np.eye(l * n), family, p)
     c = l
     low = np.flatnonzero(poly.degree <= p - 1)
@@ -309,6 +310,10 @@ def kernel_family(family, p, l=3):
         return ("CG", p + 1)
     if family == "RT":
         return ("CG", p) if l == 2 else ("NedTwo", p)
+    if family == "BDM":
+        # the remark after eq:hdiv-dofs: X^0 = CG_{p+1} in 2D; in 3D the
+        # eigenfunctions are those of NedTwo_{p+1} (second kind, as for RT)
+        return ("CG", p + 1) if l == 2 else ("NedTwo", p + 1)
     raise ValueError(family)
 
 
@@ -438,7 +443,7 @@ class Element:
     """The Ciarlet element (T_hat, X^k_p, L) of Sec. 3.3 and its dual basis."""
 
     def __init__(self, d, family, p):
-        if family not in ("CG", "Ned", "RT", "NedTwo"):
+        if family not in ("CG", "Ned", "RT", "NedTwo", "BDM"):
             raise ValueError(family)
         self.d, self.family, self.p, self.k = d, family, p, form_degree(d, family)
         self.space = make_space(d, family, p)
@@ -449,7 +454,7 @@ class Element:
         full = np.eye(self.space.B.shape[0])
         # the (k-1)-form family whose bubble derivatives give the type-II dofs:
         # CG_p for Ned_p, NedTwo_p for RT_p (R4; CG_p in 2D), CG_{p+1} for
-        # NedTwo_p
+        # NedTwo_p, NedTwo_{p+1} for BDM_p
         typeII = kernel_family(family, p, d)
         for l, ents in enumerate(entities(d)):
             for ei, verts in enumerate(ents):

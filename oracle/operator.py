@@ -21,7 +21,7 @@ def piola(el):
     """0 identity, 1 covariant, 2 contravariant."""
     if el.k == 0:
         return 0
-    return 2 if el.family in ("RT",) else 1
+    return 2 if el.family in ("RT", "BDM") else 1
 
 
 def physical_fields(el, J, vals, dv):

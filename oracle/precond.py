@@ -14,6 +14,13 @@ Additive form (AdditiveSchwarz):
     plus edge stars of the type-I interface space X^{1,I}_Gamma|star E
     (eq:hcurl-decomp);
   - H(div): edge stars of X^2_Gamma, PAFW(1)(X^2_Gamma)+J (eq:hdiv-decomp).
+  - the second-kind spaces (eq:second-kind-def) take the decompositions of
+    the first-kind space of the same form degree, with the potentials from
+    the next-lower space of the second-kind sequence: NedTwo_p the H(curl)
+    ones with CG_{p+1} vertex-star potentials (the NedTwo_p type-II dofs are
+    gradients of CG_{p+1} type-I functions), BDM_p the H(div) ones, whose
+    type-I Hiptmair-Toselli and standard Hiptmair-Toselli potentials are
+    curls of NedTwo_{p+1} functions.
   - 2D H(curl) and 2D H(div) (both k = 1, and 2D RT_p is the quarter turn of
     2D Ned_p, so the two share every decomposition, the curl of a CG
     function having the coefficients of its gradient): the H(curl) form
@@ -209,8 +216,20 @@ def curl_potential_patches(top, full=False):
 
 def solver_family(top, family):
     """The family whose decompositions a space uses: 2D RT_p those of 2D
-    Ned_p (its quarter turn)."""
-    return "Ned" if (top.d == 2 and family == "RT") else family
+    Ned_p (its quarter turn); the second-kind spaces those of their first-
+    kind counterparts (NedTwo_p: H(curl) with CG_{p+1} potentials, BDM_p:
+    H(div) with NedTwo_{p+1} potentials)."""
+    if family == "NedTwo" or (top.d == 2 and family == "RT"):
+        return "Ned"
+    if family == "BDM":
+        return "RT"
+    return family
+
+
+def potential_degree(top, family):
+    """Degree of the potential space: X^{k-1} is CG_{p+1} for NedTwo_p and
+    NedTwo_{p+1} for BDM_p (exact second-kind sequence), degree p otherwise."""
+    return top.el.p + (1 if family in ("NedTwo", "BDM") else 0)
 
 
 def patch_lists(top, family, decomposition="paper"):
@@ -364,6 +383,7 @@ class AdditiveSchwarz:
         self.A = A
         self.top = top
         self.family = family
+        pdeg = potential_degree(top, family)
         family = solver_family(top, family)
         self.decomposition = decomposition
         self.removed = np.zeros(0, dtype=np.int64) if dirichlet is None else np.asarray(dirichlet, dtype=np.int64)
@@ -385,7 +405,7 @@ class AdditiveSchwarz:
         pots = []
         if family == "Ned" and not decomposition.startswith("vertex"):
             from .element import element
-            pots = potential_patches(top, element(top.d, "CG", top.el.p).counts(), full)
+            pots = potential_patches(top, element(top.d, "CG", pdeg).counts(), full)
         if family == "RT" and decomposition.startswith("typeI"):
             pots = curl_potential_patches(top, full)
         for G in pots:
@@ -404,7 +424,7 @@ class AdditiveSchwarz:
             from .element import element
             from .mesh import Topology
             from .operator import all_cell_matrices, assemble
-            el2 = element(top.d, "NedTwo", top.el.p)
+            el2 = element(top.d, "NedTwo", pdeg)
             top2 = Topology(top.coords, top.cells, el2)
             M2 = assemble(top2, all_cell_matrices(el2, top2, alpha=0.0, beta=1.0))
             eps = 1e-8 * beta

@@ -73,7 +73,8 @@ def test_splitmix64_published_value():
     assert next(g) == (0xE220A8397B1DCDAF >> 11) / 2.0 ** 53
 
 
-@pytest.mark.parametrize("l,fam", [(2, "Ned"), (3, "Ned"), (2, "RT"), (3, "RT"), (2, "NedTwo"), (3, "NedTwo")])
+@pytest.mark.parametrize("l,fam", [(2, "Ned"), (3, "Ned"), (2, "RT"), (3, "RT"), (2, "NedTwo"), (3, "NedTwo"),
+                                   (3, "BDM")])
 @pytest.mark.parametrize("p", [1, 2, 3, 5])
 def test_space_dimensions(l, fam, p):
     assert make_space(l, fam, p).m == space_dim(l, fam, p)
@@ -119,7 +120,8 @@ def _blocks(el):
 @pytest.mark.parametrize("d,fam,p", [(2, "CG", 4), (2, "CG", 7), (3, "CG", 3), (3, "CG", 6),
                                      (3, "Ned", 2), (3, "Ned", 4), (3, "Ned", 6),
                                      (3, "RT", 2), (3, "RT", 4), (3, "RT", 6),
-                                     (2, "Ned", 3), (2, "Ned", 6), (2, "RT", 3), (2, "RT", 6)])
+                                     (2, "Ned", 3), (2, "Ned", 6), (2, "RT", 3), (2, "RT", 6),
+                                     (3, "NedTwo", 2), (3, "NedTwo", 4), (3, "BDM", 2), (3, "BDM", 4)])
 def test_reference_matrix_structure(d, fam, p):
     """lem:ref-element-matrix-properties."""
     el = element(d, fam, p)

@@ -43,7 +43,8 @@ def _cells(d, rng, n=20):
 
 
 @pytest.mark.parametrize("d,fam,p", [(2, f, p) for f in ("CG", "Ned", "RT") for p in range(1, 7)]
-                         + [(3, f, p) for f in ("CG", "Ned", "RT") for p in range(1, 7)])
+                         + [(3, f, p) for f in ("CG", "Ned", "RT") for p in range(1, 7)]
+                         + [(3, f, p) for f in ("NedTwo", "BDM") for p in range(1, 5)])
 def test_stacked_form_equals_cell_quadrature(d, fam, p):
     el = element(d, fam, p)
     R = reference_stack(el)
@@ -82,7 +83,7 @@ def _random_cluster_rotation(bounds, n, rng):
 
 @pytest.mark.parametrize("l,fam,p", [(2, "CG", 4), (2, "CG", 7), (3, "CG", 6), (3, "CG", 8), (2, "Ned", 5),
                                      (3, "Ned", 4), (3, "Ned", 5), (3, "RT", 4), (3, "RT", 5), (2, "NedTwo", 4),
-                                     (3, "NedTwo", 4), (2, "RT", 5)])
+                                     (3, "NedTwo", 4), (2, "RT", 5), (3, "BDM", 4)])
 def test_cluster_canonicalisation_is_basis_invariant(l, fam, p):
     sp, Bb, K, mu, Vec, n_ker = bubble_eigenproblem(l, fam, p)
     mu_keep, W = mu[n_ker:], Vec[:, n_ker:]
