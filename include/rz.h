@@ -58,7 +58,7 @@ extern "C" {
 enum {
   RZ_OK = 0,
   RZ_ERR_ARG = -1,              /* bad pointer, size, alpha < 0, beta <= 0, dim */
-  RZ_ERR_UNSUPPORTED = -2,      /* (dim, space, degree) outside CG, Ned, RT in 2D / 3D, 1 <= p <= 10 */
+  RZ_ERR_UNSUPPORTED = -2,      /* (dim, space, degree) outside CG, Ned, RT in 2D / 3D, NedTwo, BDM in 3D, 1 <= p <= 10 */
   RZ_ERR_MESH = -3,             /* vertex index out of range or repeated in a cell */
   RZ_ERR_DEGENERATE_CELL = -4,  /* |det J_T| <= 1e-12 h^d */
   RZ_ERR_NOT_SPD = -5,          /* non-positive pivot in a patch or coarse Cholesky */
@@ -69,8 +69,16 @@ enum {
 };
 
 /* The space: one of the constants below, passed as a 32-bit integer (an
- * out-of-range value is an argument error, never undefined behaviour). */
-enum { RZ_HGRAD = 0, RZ_HCURL = 1, RZ_HDIV = 2 };
+ * out-of-range value is an argument error, never undefined behaviour).
+ * RZ_HCURL2 and RZ_HDIV2 are the second-kind spaces NedTwo_p and BDM_p
+ * (eq:second-kind-def; tetrahedra only): all of P_p^3, with the dofs of
+ * eq:hcurl-dofs / eq:hdiv-dofs whose type-II moments come from the next-lower
+ * space of the second-kind sequence (CG_{p+1} for NedTwo_p, NedTwo_{p+1} for
+ * BDM_p, the remark after eq:hdiv-dofs).  They take the decompositions of
+ * RZ_HCURL and RZ_HDIV, the potentials from those lower spaces (the standard
+ * Hiptmair-Toselli decompositions: RZ_HCURL2 only) and the exact coarse
+ * solver only (RZ_COARSE_MG -> RZ_ERR_UNSUPPORTED). */
+enum { RZ_HGRAD = 0, RZ_HCURL = 1, RZ_HDIV = 2, RZ_HCURL2 = 3, RZ_HDIV2 = 4 };
 typedef int32_t rz_space;
 
 typedef struct {

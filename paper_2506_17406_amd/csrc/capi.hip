@@ -475,9 +475,13 @@ void setup_coarse(rz_problem &P, hipStream_t s) {
 // element's Whitney sub-blocks and the geometric weights.
 void setup_multigrid(rz_problem &P, const rz_mesh *m, const rz_options *o, hipStream_t s) {
   if (P.d != 3) throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for tetrahedral meshes"};
+  if (P.fam == rz::FAM_NEDTWO || P.fam == rz::FAM_BDM)
+    throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for the first-kind spaces"};
   if (!P.dir_dofs.empty())
     throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for pure Neumann problems"};
   if (P.d != 3) throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for tetrahedral meshes"};
+  if (P.fam == rz::FAM_NEDTWO || P.fam == rz::FAM_BDM)
+    throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for the first-kind spaces"};
   if (o->mg_levels < 2 || !o->mg_meshes) throw RzError{RZ_ERR_ARG, "multigrid needs mg_levels >= 2 meshes"};
   const rz_mesh *H = o->mg_meshes;
   for (int l = 0; l < o->mg_levels; ++l)
@@ -657,11 +661,22 @@ double *scratch_address() {
 }  // namespace
 
 // rz_decomposition values and the spaces they are built for
+// the family of a space constant (second kind: NedTwo_p, BDM_p)
+static rz::Family family_of(int space) {
+  switch (space) {
+    case RZ_HGRAD: return rz::FAM_CG;
+    case RZ_HCURL: return rz::FAM_NED;
+    case RZ_HDIV: return rz::FAM_RT;
+    case RZ_HCURL2: return rz::FAM_NEDTWO;
+    default: return rz::FAM_BDM;
+  }
+}
+
 static int check_decomposition(int32_t dec, int space, int dim) {
   if (dec < RZ_DECOMP_PAPER || dec > RZ_DECOMP_TYPEI_FULL) return fail(RZ_ERR_ARG, "unknown decomposition");
   // 2D H(div) is the quarter turn of 2D H(curl) and shares its decompositions
   if ((dec == RZ_DECOMP_HIPTMAIR || dec == RZ_DECOMP_HIPTMAIR_FULL) && space != RZ_HCURL &&
-      !(dim == 2 && space == RZ_HDIV))
+      space != RZ_HCURL2 && !(dim == 2 && space == RZ_HDIV))
     return fail(RZ_ERR_UNSUPPORTED, "the standard Hiptmair-Toselli decompositions are built for H(curl) only");
   if ((dec == RZ_DECOMP_TYPEI || dec == RZ_DECOMP_TYPEI_FULL) && space == RZ_HGRAD)
     return fail(RZ_ERR_UNSUPPORTED, "the type-I Hiptmair-Toselli decompositions need H(curl) or H(div)");
@@ -681,7 +696,9 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
   const double alpha = opts ? opts->alpha : 1.0, beta = opts ? opts->beta : 1.0;
   if (!(alpha >= 0.0) || !(beta > 0.0)) return fail(RZ_ERR_ARG, "need alpha >= 0 and beta > 0");
   if (degree < 1 || degree > 10) return fail(RZ_ERR_UNSUPPORTED, "degree must be in 1..10");
-  if (space < RZ_HGRAD || space > RZ_HDIV) return fail(RZ_ERR_ARG, "unknown space");
+  if (space < RZ_HGRAD || space > RZ_HDIV2) return fail(RZ_ERR_ARG, "unknown space");
+  if (m->dim == 2 && space > RZ_HDIV)
+    return fail(RZ_ERR_UNSUPPORTED, "the second-kind spaces are built for tetrahedral meshes");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const auto t_setup = std::chrono::steady_clock::now();
   auto P = std::make_unique<rz_problem>();
@@ -703,7 +720,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     if (opts->coarse != RZ_COARSE_EXACT && opts->coarse != RZ_COARSE_MG)
       return fail(RZ_ERR_ARG, "unknown coarse solver");
   }
-  P->fam = space == RZ_HGRAD ? rz::FAM_CG : (space == RZ_HCURL ? rz::FAM_NED : rz::FAM_RT);
+  P->fam = family_of(space);
   try {
     P->el = rz::build_reference(P->d, P->fam, degree);
     P->k = P->el.k;
@@ -725,7 +742,7 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
       rz::Dense Ei = rz::inverse(E);
       double *dX = P->upload(X, s);
       double *dEi = P->upload(Ei.a, s);
-      const int pullback = P->k == 0 ? 0 : (P->el.fam == rz::FAM_RT ? 2 : 1);
+      const int pullback = P->k == 0 ? 0 : ((P->el.fam == rz::FAM_RT || P->el.fam == rz::FAM_BDM) ? 2 : 1);
       rz::launch_weights(d, pullback, nc, dX, dEi, alpha, beta, P->w, Q, s);
     }
     // interior diagonal (Jacobi on X^k_I; an empty group under the full
@@ -1542,9 +1559,11 @@ int rz_export_reference(const rz_problem *P, double *Rq) {
 
 static int check_space(int32_t dim, int32_t degree, rz_space space, rz::Family &fam) {
   if (dim != 2 && dim != 3) return fail(RZ_ERR_ARG, "dim must be 2 or 3");
-  if (space < RZ_HGRAD || space > RZ_HDIV) return fail(RZ_ERR_ARG, "unknown space");
+  if (space < RZ_HGRAD || space > RZ_HDIV2) return fail(RZ_ERR_ARG, "unknown space");
   if (degree < 1 || degree > 10) return fail(RZ_ERR_UNSUPPORTED, "degree must be in 1..10");
-  fam = space == RZ_HGRAD ? rz::FAM_CG : (space == RZ_HCURL ? rz::FAM_NED : rz::FAM_RT);
+  if (dim == 2 && space > RZ_HDIV)
+    return fail(RZ_ERR_UNSUPPORTED, "the second-kind spaces are built for tetrahedral meshes");
+  fam = family_of(space);
   return RZ_OK;
 }
 

@@ -334,7 +334,7 @@ struct PolyBasis {
 };
 
 // ------------------------------------------------------------------ spaces
-int form_of(Family f) { return f == FAM_CG ? 0 : (f == FAM_RT ? 2 : 1); }
+int form_of(Family f) { return f == FAM_CG ? 0 : ((f == FAM_RT || f == FAM_BDM) ? 2 : 1); }
 
 int binom(int n, int k) {
   if (k < 0 || n < k) return 0;
@@ -347,7 +347,8 @@ int space_dim(int l, Family f, int p) {
   auto P = [&](int q) { return q < 0 ? 0 : binom(q + l, l); };
   switch (f) {
     case FAM_CG: return P(p);
-    case FAM_NEDTWO: return l * P(p);
+    case FAM_NEDTWO:
+    case FAM_BDM: return l * P(p);
     case FAM_NED: return l == 2 ? p * (p + 2) : p * (p + 2) * (p + 3) / 2;
     case FAM_RT: return p * (p + 1) * (p + 3) / 2;
   }
@@ -433,7 +434,7 @@ std::shared_ptr<Space> make_space(int l, Family fam, int p) {
   if (fam == FAM_CG) {
     sp->c = 1;
     sp->B = Dense::eye(n);
-  } else if (fam == FAM_NEDTWO) {
+  } else if (fam == FAM_NEDTWO || fam == FAM_BDM) {  // second kind: all of P_p^l
     sp->c = l;
     sp->B = Dense::eye(l * n);
   } else {
@@ -620,6 +621,7 @@ Family kernel_family(Family f, int p, int &pk) {
   if (f == FAM_NED) return FAM_CG;
   if (f == FAM_NEDTWO) { pk = p + 1; return FAM_CG; }
   if (f == FAM_RT) return FAM_NEDTWO;
+  if (f == FAM_BDM) { pk = p + 1; return FAM_NEDTWO; }  // NedTwo_{p+1} for BDM_p
   return FAM_CG;
 }
 
@@ -813,7 +815,8 @@ DualBasis dual_basis(int d, Family fam, int p, RefElement *el) {
   RefElement &E = el ? *el : scratch;
   E.per_entity.assign(d + 1, 0);
   E.kind_start.assign(3 * (d + 1), -1);
-  const Family typeII = (k == 1) ? FAM_CG : FAM_NEDTWO;
+  int p2 = p;  // the type-II family and degree: the next-lower space of the sequence
+  const Family typeII = kernel_family(fam, p, p2);
   auto ents = entities(d);
   double cond = 1.0, gap = 1e300;
   for (int l = 0; l <= d; ++l) {
@@ -868,7 +871,7 @@ DualBasis dual_basis(int d, Family fam, int p, RefElement *el) {
         }
       }
       if (k >= 1 && l >= k) {  // type-II: (d_S psi^{k-1}_j, tr v)_S
-        auto eb = eigenbasis(l, typeII, p);
+        auto eb = eigenbasis(l, typeII, p2);
         cond = std::max(cond, eb->cond_probe);
         gap = std::min(gap, eb->min_gap);
         std::vector<double> dpsi;
@@ -921,7 +924,7 @@ RefElement build_reference(int d, Family fam, int p) {
     return el;
   }
   std::lock_guard<std::mutex> lock(build_mutex());
-  if (d < 2 || d > 3 || p < 1 || (d == 2 && fam != FAM_CG && fam != FAM_NED) || fam == FAM_NEDTWO)
+  if (d < 2 || d > 3 || p < 1 || (d == 2 && fam != FAM_CG && fam != FAM_NED))
     throw std::runtime_error("unsupported (dimension, space, degree)");
   RefElement el;
   el.d = d;

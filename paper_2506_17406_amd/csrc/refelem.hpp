@@ -9,7 +9,7 @@
 
 namespace rz {
 
-enum Family { FAM_CG = 0, FAM_NED = 1, FAM_NEDTWO = 2, FAM_RT = 3 };
+enum Family { FAM_CG = 0, FAM_NED = 1, FAM_NEDTWO = 2, FAM_RT = 3, FAM_BDM = 4 };
 enum DofKind { KIND_W = 0, KIND_I = 1, KIND_II = 2 };
 
 struct LocalDof {
@@ -32,7 +32,8 @@ struct RefElement {
   double min_cluster_gap = 1e300;  // smallest relative gap between distinct eigenvalues
 };
 
-// Builds the element for (dimension d, first-kind family CG/NED/RT, degree p).
+// Builds the element for (dimension d, family, degree p): CG/NED/RT in 2D
+// and 3D, the second-kind NEDTWO/BDM in 3D.
 // Throws std::runtime_error when a numerical check of the construction fails.
 RefElement build_reference(int d, Family fam, int p);
 

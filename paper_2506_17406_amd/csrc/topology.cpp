@@ -243,7 +243,13 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
   // 2D RT_p is the quarter turn of 2D Ned_p: the same dofs, and the curl of a
   // CG function has the coefficients of its gradient, so it takes the H(curl)
   // decompositions
-  const Family fam = (d == 2 && el.fam == FAM_RT) ? FAM_NED : el.fam;
+  // the second-kind spaces take the decompositions of the first-kind space of
+  // the same form degree (their potentials come from the next-lower space of
+  // the second-kind sequence: CG_{p+1}, NedTwo_{p+1}; entity_dofs reads the
+  // per-entity counts from the element)
+  const Family fam = (d == 2 && el.fam == FAM_RT) || el.fam == FAM_NEDTWO ? FAM_NED
+                     : el.fam == FAM_BDM                                  ? FAM_RT
+                                                                          : el.fam;
   if (hiptmair && fam != FAM_NED)
     throw std::runtime_error("the Hiptmair-Toselli decompositions are built for H(curl) only");
   if (typeI && fam == FAM_CG)

@@ -15,8 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # build of the CPU tests); by default the in-tree librz.so
 LIB_PATH = os.environ.get("RZ_LIBRARY") or os.path.join(_HERE, "librz.so")
 
-RZ_HGRAD, RZ_HCURL, RZ_HDIV = 0, 1, 2
-SPACES = {"CG": RZ_HGRAD, "hgrad": RZ_HGRAD, "Ned": RZ_HCURL, "hcurl": RZ_HCURL, "RT": RZ_HDIV, "hdiv": RZ_HDIV}
+RZ_HGRAD, RZ_HCURL, RZ_HDIV, RZ_HCURL2, RZ_HDIV2 = 0, 1, 2, 3, 4
+SPACES = {"CG": RZ_HGRAD, "hgrad": RZ_HGRAD, "Ned": RZ_HCURL, "hcurl": RZ_HCURL, "RT": RZ_HDIV, "hdiv": RZ_HDIV,
+          "NedTwo": RZ_HCURL2, "hcurl2": RZ_HCURL2, "BDM": RZ_HDIV2, "hdiv2": RZ_HDIV2}
 ERRORS = {0: "RZ_OK", -1: "RZ_ERR_ARG", -2: "RZ_ERR_UNSUPPORTED", -3: "RZ_ERR_MESH", -4: "RZ_ERR_DEGENERATE_CELL",
           -5: "RZ_ERR_NOT_SPD", -6: "RZ_ERR_NO_CONVERGENCE", -7: "RZ_ERR_BREAKDOWN", -8: "RZ_ERR_DEVICE",
           -9: "RZ_ERR_OOM"}

@@ -9,7 +9,8 @@ H(curl) PH(X^0_Gamma, X^1_Gamma) + J ("hiptmair") and PH(X^0, X^1)
 PH(X^{k-1,I}, X^{k,I}) with and without the split ("typeI", "typeI-full";
 for H(div) built from curl potentials).  2D H(curl) and H(div) take the
 H(curl) forms with the dimensions shifted (2D RT_p is the quarter turn of
-2D Ned_p).
+2D Ned_p); the second-kind NedTwo_p and BDM_p those of H(curl) and H(div)
+with potentials from CG_{p+1} and NedTwo_{p+1}.
 
 Sizes: meshes of 6-162 cells, degrees 2-8, seeded jitter and load vectors;
 the largest full stars near the 2048-dof patch limit (H(grad) p = 8: 1695,
@@ -56,7 +57,11 @@ SETS = ([(c, f) for f in ("vertex", "vertex-full") for c in CASES] +
                    (3, "RT", 6, 2, 0.1), (3, "Ned", 3, 2, 0.1)]] +
         # 2D H(curl) and H(div) (the quarter turn): every decomposition
         [(c, f) for f in ("paper-full", "vertex", "vertex-full", "hiptmair", "hiptmair-full", "typeI")
-         for c in [(2, "Ned", 4, 3, 0.1), (2, "RT", 5, 3, 0.1)]])
+         for c in [(2, "Ned", 4, 3, 0.1), (2, "RT", 5, 3, 0.1)]] +
+        # the second-kind spaces
+        [((3, "NedTwo", 3, 2, 0.1), f) for f in ("paper-full", "vertex", "vertex-full", "hiptmair",
+                                                 "hiptmair-full", "typeI")] +
+        [((3, "BDM", 3, 2, 0.1), f) for f in ("paper-full", "vertex", "vertex-full", "typeI", "typeI-full")])
 PCS = ["additive", "hybrid"]
 _cache = {}
 

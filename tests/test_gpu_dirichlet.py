@@ -45,7 +45,7 @@ def boundary_flags(C, X, where):
 
 CASES = [(2, "CG", 4, 4, "all"), (3, "CG", 3, 2, "face"), (3, "CG", 5, 2, "all"), (3, "Ned", 3, 2, "all"),
          (3, "Ned", 4, 2, "face"), (3, "RT", 3, 2, "face"), (3, "RT", 4, 2, "all"), (3, "Ned", 1, 2, "face"),
-         (2, "Ned", 4, 4, "all"), (2, "RT", 3, 4, "face")]
+         (2, "Ned", 4, 4, "all"), (2, "RT", 3, 4, "face"), (3, "NedTwo", 2, 2, "face"), (3, "BDM", 2, 2, "all")]
 _cache = {}
 
 

@@ -45,6 +45,9 @@ def test_reference_argument_errors():
     assert rz.lib.rz_reference(2, 3, 1, ctypes.byref(n), ctypes.byref(Q), None) == 0       # 2D H(curl)
     assert (n.value, Q.value) == (15, 4)                                                  # p (p + 2); 3 + 1
     assert rz.lib.rz_reference(3, 3, 7, ctypes.byref(n), ctypes.byref(Q), None) == -1      # space
+    assert rz.lib.rz_reference(2, 3, 3, ctypes.byref(n), ctypes.byref(Q), None) == -2      # 2D second kind
+    assert rz.lib.rz_reference(3, 3, 4, ctypes.byref(n), ctypes.byref(Q), None) == 0       # BDM_3
+    assert (n.value, Q.value) == (60, 7)
     assert b"space" in rz.lib.rz_last_error()
 
 
@@ -101,6 +104,7 @@ def test_setup_rejects_before_device_work():
 # "heavy" (run with RZ_HEAVY_TESTS=1)
 HEAVY = pytest.mark.heavy
 REF_CASES = [(2, f, p) for f in ("CG", "Ned", "RT") for p in range(1, 11)] + [(3, "CG", p) for p in range(1, 11)] + \
+            [(3, f, p) for f in ("NedTwo", "BDM") for p in range(1, 9)] + \
             [(3, f, p) for f in ("Ned", "RT") for p in range(1, 9)] + \
             [pytest.param(3, f, p, marks=HEAVY) for f in ("Ned", "RT") for p in (9, 10)]
 
@@ -115,7 +119,11 @@ def table_tolerance(d, fam, p):
     (cond(Y) = 3.3e3 at p = 9), which amplifies the rounding of each
     eigensolver's cluster subspace.  2D Ned_p and RT_p (the library rotates
     its Ned tables, the oracle builds RT from its own functionals): <= 9.2e-12
-    at p = 10."""
+    at p = 10.  Second kind: <= 4.7e-12 up to NedTwo_8 and BDM_7; BDM_8
+    2.1e-10, its type-II moments using the same NedTwo_9 cell eigenbasis as
+    RT_9."""
+    if fam == "BDM" and p >= 8:
+        return 5e-10
     if p <= 8:
         return 1e-11
     return 5e-10 if fam == "RT" else 5e-11
@@ -132,7 +140,7 @@ def test_reference_tables_match_oracle(d, fam, p):
 
 NUM_CASES = [(2, "CG", 4, 4), (2, "CG", 2, 3), (3, "CG", 1, 2), (3, "CG", 4, 2), (3, "Ned", 1, 2),
              (3, "Ned", 3, 3), (3, "RT", 1, 2), (3, "RT", 3, 3), (2, "Ned", 1, 3), (2, "Ned", 4, 3),
-             (2, "RT", 3, 3)]
+             (2, "RT", 3, 3), (3, "NedTwo", 1, 2), (3, "NedTwo", 3, 2), (3, "BDM", 2, 2)]
 
 
 @pytest.mark.parametrize("d,fam,p,n", NUM_CASES, ids=lambda v: str(v))
@@ -155,7 +163,7 @@ def test_numbering_bit_exact(d, fam, p, n, shuffle):
 
 
 VSTAR_CASES = [(2, "CG", 4, 3), (3, "CG", 4, 2), (3, "Ned", 3, 2), (3, "RT", 3, 2), (3, "Ned", 1, 2),
-               (2, "Ned", 3, 3), (2, "RT", 4, 3)]
+               (2, "Ned", 3, 3), (2, "RT", 4, 3), (3, "NedTwo", 2, 2), (3, "BDM", 2, 2)]
 
 
 @pytest.mark.parametrize("d,fam,p,n", VSTAR_CASES, ids=lambda v: str(v))
