@@ -988,35 +988,43 @@ static void ensure_ws(rz_problem *P, int ncol) {
     if (dl.nv) dl.u = static_cast<double *>(alloc(sizeof(double) * dl.nv * ncol));
   }
   P->ws_cols = ncol;
-  if (ncol >= 8 && (P->precision == RZ_FP64 || P->precision == RZ_BF16_PC)) {
+  if (ncol >= 8) {
     // many columns: the patch solves of the segmented sets become MFMA
-    // products over fragment-ordered copies of the inverses (FP64, or
-    // bfloat16 under RZ_BF16_PC), with one shared result buffer
-    const bool bf = P->precision == RZ_BF16_PC;
+    // products over fragment-ordered copies of the inverses (FP64; bfloat16
+    // under RZ_BF16_PC; FP32 under RZ_FP32_PC and RZ_FP32_IR, whose inner
+    // solves use the FP32 copies), with one shared result buffer
+    const int kind = P->precision == RZ_BF16_PC ? 1 : (P->precision == RZ_FP64 ? 0 : 2);
     size_t zbytes = 0, rbytes = 0;
     for (auto &d : P->dps) {
       if (d.pa.fold || d.pa.n_patches == 0) continue;
-      if (!(bf ? (const void *)d.pa.frag16 : (const void *)d.pa.frag64)) {
+      const void *have = kind == 1 ? (const void *)d.pa.frag16
+                         : kind == 2 ? (const void *)d.pa.frag32 : (const void *)d.pa.frag64;
+      if (!have) {
         std::vector<int64_t> off(d.sizes.size());
         int64_t tot = 0;
         for (size_t b = 0; b < d.sizes.size(); ++b) {
           off[b] = tot;
-          tot += rz::frag_size(int(d.sizes[b]), bf);
+          tot += rz::frag_size(int(d.sizes[b]), kind);
         }
         const int64_t *doff = P->upload(off, nullptr);
-        if (bf) {
+        if (kind == 1) {
           uint16_t *f = P->dev<uint16_t>(size_t(tot));
-          rz::launch_seg_to_frag(d.pa, true, f, doff, nullptr);
+          rz::launch_seg_to_frag(d.pa, kind, f, doff, nullptr);
           d.pa.frag16 = f;
           d.pa.frag_off16 = doff;
+        } else if (kind == 2) {
+          float *f = P->dev<float>(size_t(tot));
+          rz::launch_seg_to_frag(d.pa, kind, f, doff, nullptr);
+          d.pa.frag32 = f;
+          d.pa.frag_off32 = doff;
         } else {
           double *f = P->dev<double>(size_t(tot));
-          rz::launch_seg_to_frag(d.pa, false, f, doff, nullptr);
+          rz::launch_seg_to_frag(d.pa, kind, f, doff, nullptr);
           d.pa.frag64 = f;
           d.pa.frag_off64 = doff;
         }
       }
-      zbytes = std::max(zbytes, size_t(d.pa.sum_size) * ncol * (bf ? 4 : 8));
+      zbytes = std::max(zbytes, size_t(d.pa.sum_size) * ncol * (kind == 0 ? 8 : 4));
       rbytes = std::max(rbytes, size_t(d.pa.n_adof) * ncol * 8);
     }
     if (zbytes) {

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -1198,6 +1199,10 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(int NT, int nsplit, const d
 //     (their sum carries 16 significant bits) and both are multiplied, so
 //     the patch solve applies the bfloat16-stored inverse to r with FP32
 //     accumulation like the streamed kernels do.
+//   FP32 (mfma_f32_16x16x4f32, the FP32 copies of RZ_FP32_PC / RZ_FP32_IR):
+//     the FP64 fragment and B layouts with FP32 values (r rounded to FP32,
+//     of the order of the inverse's own rounding); accumulator v = Z[16 mb +
+//     4 (l / 16) + v][16 nb + l % 16] as for bfloat16.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
@@ -1213,6 +1218,12 @@ template <>
 struct FragTraits<uint16_t> {
   static constexpr int KS = 32, MPA = 32;
   typedef uint4 A_t;   // 8 bfloat16 bits
+  typedef float Z_t;
+};
+template <>
+struct FragTraits<float> {  // mfma_f32_16x16x4f32: the FP64 operand layouts
+  static constexpr int KS = 4, MPA = 16;
+  typedef float A_t;
   typedef float Z_t;
 };
 
@@ -1249,7 +1260,7 @@ __global__ void k_seg_to_frag(const int64_t *__restrict__ patch_col, const int64
       const int a = min(i, k), b = max(i, k);
       v = (a == b ? 2.0 : 1.0) * S[seg_row_off(a, mS, 2) + b - a / 2 * 2];
     }
-    if constexpr (KS == 4) o[e] = v;
+    if constexpr (KS == 4) o[e] = F(v);
     else o[e] = bf16_bits(float(v));
   }
 }
@@ -1281,6 +1292,7 @@ __global__ __launch_bounds__(64 * (MPMAX / 16)) void k_patch_mfma(
     const PcgState *st) {
   constexpr int KS = FragTraits<F>::KS, MPA = FragTraits<F>::MPA;
   constexpr bool BF = KS == 32;
+  constexpr bool F32 = std::is_same<F, float>::value;
   typedef typename FragTraits<F>::A_t A_t;
   typedef typename FragTraits<F>::Z_t Z_t;
   typedef Z_t acc_t __attribute__((ext_vector_type(4)));
@@ -1299,6 +1311,7 @@ __global__ __launch_bounds__(64 * (MPMAX / 16)) void k_patch_mfma(
   // parts at KB 4 68 units
   extern __shared__ double sm[];
   double *Rd = sm;
+  float *Rf = reinterpret_cast<float *>(sm);
   uint4 *Ru = reinterpret_cast<uint4 *>(sm);
   uint16_t *Rh = reinterpret_cast<uint16_t *>(sm);
   const int64_t cb = patch_col[p];
@@ -1335,7 +1348,11 @@ __global__ __launch_bounds__(64 * (MPMAX / 16)) void k_patch_mfma(
       }
     }
     if (cg < 4) {
-      if constexpr (!BF) {
+      if constexpr (F32) {
+        float *dst = Rf + ((k >> 2) * 4 + cg) * 68 + (k & 3) * 17;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dst[j] = float(v[j]);
+      } else if constexpr (!BF) {
         double *dst = Rd + ((k >> 2) * 4 + cg) * 68 + (k & 3) * 17;
 #pragma unroll
         for (int j = 0; j < 16; ++j) dst[j] = v[j];
@@ -1364,7 +1381,9 @@ __global__ __launch_bounds__(64 * (MPMAX / 16)) void k_patch_mfma(
     if (kb >= KB) break;
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
-      if constexpr (!BF) {
+      if constexpr (F32) {
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kb], Rf[(kb * 4 + nb) * 68 + lu], acc[nb], 0, 0, 0);
+      } else if constexpr (!BF) {
         acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kb], Rd[(kb * 4 + nb) * 68 + lu], acc[nb], 0, 0, 0);
       } else {
         const int u = (kb * 4 + nb) * 68 + lu;
@@ -1383,7 +1402,7 @@ __global__ __launch_bounds__(64 * (MPMAX / 16)) void k_patch_mfma(
     if (c >= ncol) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int row = 16 * mb + (BF ? 4 * lk + v : lk + 4 * v);
+      const int row = 16 * mb + ((BF || F32) ? 4 * lk + v : lk + 4 * v);
       if (row < m) zb[(cb + row) * NC + c] = acc[nb][v];
     }
   }
@@ -2050,7 +2069,7 @@ static void patch_mfma(const PatchApply &pa, const F *frag, const int64_t *frag_
   typedef typename FragTraits<F>::Z_t Z_t;
   constexpr int MPA = FragTraits<F>::MPA;
   const int MP = (pa.max_size + MPA - 1) / MPA * MPA;
-  const size_t lds = size_t(MP) * 68 * (sizeof(F) == 8 ? 8 : 4);
+  const size_t lds = size_t(MP) * 68 * (sizeof(F) == 8 ? 8 : 4);  // FP64 units, FP32 units, 8-half units / 2
   hipLaunchKernelGGL(k_patch_rt, dim3(unsigned((pa.n_adof + 63) / 64), unsigned((ncol + 63) / 64)), dim3(256), 0,
                      s, pa.n_adof, pa.adof, r, ldr, ncol, static_cast<double *>(pa.rt), pa.zb_cols);
   const dim3 grid(unsigned(pa.n_patches), unsigned((ncol + 63) / 64));
@@ -2080,17 +2099,20 @@ static void patch_zb_scatter(const PatchApply &pa, double *z, int64_t ldz, int n
                      pa.zb_cols, z, ldz, ncol, scale, st);
 }
 
-void launch_seg_to_frag(const PatchApply &pa, bool bf16, void *frag, const int64_t *frag_off, hipStream_t s) {
-  if (bf16)
+void launch_seg_to_frag(const PatchApply &pa, int kind, void *frag, const int64_t *frag_off, hipStream_t s) {
+  if (kind == 1)
     hipLaunchKernelGGL((k_seg_to_frag<uint16_t>), dim3(unsigned(pa.n_patches)), dim3(256), 0, s, pa.patch_col,
                        pa.inv_off, pa.inv, frag_off, static_cast<uint16_t *>(frag));
+  else if (kind == 2)
+    hipLaunchKernelGGL((k_seg_to_frag<float>), dim3(unsigned(pa.n_patches)), dim3(256), 0, s, pa.patch_col,
+                       pa.inv_off, pa.inv, frag_off, static_cast<float *>(frag));
   else
     hipLaunchKernelGGL((k_seg_to_frag<double>), dim3(unsigned(pa.n_patches)), dim3(256), 0, s, pa.patch_col,
                        pa.inv_off, pa.inv, frag_off, static_cast<double *>(frag));
 }
 
-int64_t frag_size(int m, bool bf16) {
-  const int64_t a = bf16 ? 32 : 16, MP = (m + a - 1) / a * a;
+int64_t frag_size(int m, int kind) {
+  const int64_t a = kind == 1 ? 32 : 16, MP = (m + a - 1) / a * a;
   return MP * MP;
 }
 
@@ -2103,6 +2125,10 @@ void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, doub
   }
   if (lo && pa.inv16)
     return patch_any<uint16_t>(pa, pa.inv_off16, pa.inv16, r, ldr, z, ldz, ncol, scale, st, s);
+  if (lo && pa.inv32 && ncol >= 8 && pa.frag32 && pa.zb && ncol <= pa.zb_cols) {
+    patch_mfma<float>(pa, pa.frag32, pa.frag_off32, r, ldr, ncol, st, s);
+    return patch_zb_scatter<float>(pa, z, ldz, ncol, scale, st, s);
+  }
   if (lo && pa.inv32)
     return patch_any<float>(pa, pa.inv_off32, pa.inv32, r, ldr, z, ldz, ncol, scale, st, s);
   if (ncol >= 8 && pa.frag64 && pa.zb && ncol <= pa.zb_cols) {

@@ -141,7 +141,8 @@ struct PatchApply {
   // the set's dofs with their (patch column, coefficient) entries
   const double *frag64;
   const uint16_t *frag16;
-  const int64_t *frag_off64, *frag_off16;
+  const float *frag32;
+  const int64_t *frag_off64, *frag_off16, *frag_off32;
   void *zb;                    // results, dof-major: zb[pr * zb_cols + c]
   void *rt;                    // right-hand sides of the set's dofs, dof-major: rt[a * zb_cols + c]
   int zb_cols;                 // columns zb and rt hold (the MFMA path needs ncol <= zb_cols)
@@ -152,9 +153,10 @@ struct PatchApply {
   const double *acoef;
 };
 // entries of one patch inverse in MFMA fragment order (full MP x MP; MP = m
-// rounded up to 16 for FP64, 32 for bfloat16)
-int64_t frag_size(int m, bool bf16);
-void launch_seg_to_frag(const PatchApply &pa, bool bf16, void *frag, const int64_t *frag_off, hipStream_t s);
+// rounded up to 16 for FP64 and FP32, 32 for bfloat16); kind 0 FP64, 1
+// bfloat16, 2 FP32
+int64_t frag_size(int m, int kind);
+void launch_seg_to_frag(const PatchApply &pa, int kind, void *frag, const int64_t *frag_off, hipStream_t s);
 // ---- Hodge Laplacians (Sec. 7.2): y = alpha A x (+ y), A in CSR; weights
 // w[c, q] scaled by smass for q < qm (the mass family) and sderiv after;
 // out = a x + b y + c z (null: zero); per-block partials of a . b

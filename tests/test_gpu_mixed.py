@@ -233,3 +233,43 @@ def test_bf16_pc_many_columns_match_single_column(case):
         assert infos[j]["status"] == 0
         assert np.linalg.norm(B[:, j] - A @ X[:, j]) <= 1.2e-10 * np.linalg.norm(B[:, j])
     prob.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32-pc", "fp32-ir"])
+@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[5]], ids=ids)
+def test_fp32_many_columns_match_single_column(case, prec):
+    """With 8 or more columns the FP32-stored patch inverses are applied by
+    FP32 MFMA products (right-hand sides rounded to FP32, FP32 accumulation);
+    one column at a time they are streamed with FP64 accumulation.  Both
+    apply the same rounded inverses: the outputs agree to the FP32 rounding
+    of the right-hand sides and of a sum of at most 128 products (relative
+    2e-5 of the largest entry), and the many-column solve reaches the true
+    FP64 residual of every column (refinement: the inner solves run on the
+    new path)."""
+    from paper_2506_17406_amd import rz
+    top, A, P, _ = setup_case(*case)
+    d, fam, p, n = case
+    X, C = kuhn_mesh(n, d, jitter=0.1 if d == 3 else 0.0, seed=13)
+    prob = rz.Problem(X, C, p, fam, precision=prec)
+    nr = 9
+    B = load_vectors(top.n_dofs, 37, n_rhs=nr)
+    Bt = torch.from_numpy(np.ascontiguousarray(B.T)).cuda().T
+    if prec == "fp32-pc":
+        Zt = torch.zeros_like(Bt)
+        prob.apply_P(Bt, Zt, fp32=True)
+        torch.cuda.synchronize()
+        Z = Zt.cpu().numpy()
+        for j in range(nr):
+            z1 = torch.zeros(top.n_dofs, dtype=torch.float64, device="cuda")
+            prob.apply_P(Bt[:, j].contiguous(), z1, fp32=True)
+            ref = z1.cpu().numpy()
+            err = np.abs(Z[:, j] - ref).max() / np.abs(ref).max()
+            assert err <= 2e-5, err
+            assert np.abs(Z[:, j] - P.apply(B[:, j])).max() <= 1e-4 * np.abs(ref).max()
+    Xt = torch.zeros_like(Bt)
+    infos = prob.solve(Bt, Xt, rtol=1e-10)
+    Xs = Xt.cpu().numpy()
+    for j in range(nr):
+        assert infos[j]["status"] == 0
+        assert np.linalg.norm(B[:, j] - A @ Xs[:, j]) <= 1.2e-10 * np.linalg.norm(B[:, j])
+    prob.close()
