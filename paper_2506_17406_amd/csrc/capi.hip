@@ -228,17 +228,20 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
   int32_t *dsizes = nullptr;
   int64_t *doff = nullptr;
   int *dstatus = nullptr;
+  double *work = nullptr;  // split sums of the triangular inverse (chunks of nch and of the remainder)
+  const int64_t nwork = std::max(rz::chol_inverse_work(nch, N), B % nch ? rz::chol_inverse_work(B % nch, N) : 0);
   HIPCHK(hipMalloc(&Abuf, size_t(nch) * N * N * 8));
   HIPCHK(hipMalloc(&Lbuf, size_t(nch) * N * N * 8));
   HIPCHK(hipMalloc(&dsizes, size_t(B) * 4));
   HIPCHK(hipMalloc(&doff, size_t(B) * 8));
   HIPCHK(hipMalloc(&dstatus, 4));
+  if (nwork) HIPCHK(hipMalloc(&work, size_t(nwork) * 8));
   struct Freer {
     std::vector<void *> v;
     ~Freer() {
       for (void *p : v) (void)hipFree(p);
     }
-  } fr{{Abuf, Lbuf, dsizes, doff, dstatus}};
+  } fr{{Abuf, Lbuf, dsizes, doff, dstatus, work}};
   HIPCHK(hipMemcpyAsync(dsizes, sizes.data(), size_t(B) * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(doff, off.data(), size_t(B) * 8, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(dstatus, 0, 4, s));
@@ -278,7 +281,7 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
     rz::launch_pad_identity(nb, N, dsizes + p0, Abuf, s);
     rz::launch_patch_assemble(i1 - i0, d_ip, d_ic, d_it, t_col, t_loc, t_coef, P.el.n, P.el.Q, P.R, P.w, N, Abuf,
                               s);
-    rz::launch_chol_inverse(nb, N, Abuf, Lbuf, dstatus, s);
+    rz::launch_chol_inverse(nb, N, Abuf, Lbuf, dstatus, work, s);
     if (fold) rz::launch_pack_fold(nb, N, dsizes + p0, doff + p0, Abuf, inv, s);
     else rz::launch_pack_seg(nb, N, E, dsizes + p0, doff + p0, Abuf, inv, s);
     HIPCHK(hipGetLastError());
@@ -428,7 +431,9 @@ void setup_coarse(rz_problem &P, hipStream_t s) {
   HIPCHK(hipMalloc(&Lbuf, size_t(N) * N * 8));
   HIPCHK(hipMalloc(&dstatus, 4));
   HIPCHK(hipMalloc(&dsz, 4));
-  std::vector<void *> tmp{Abuf, Lbuf, dstatus, dsz};
+  double *work = nullptr;  // split sums of the triangular inverse
+  if (const int64_t nwork = rz::chol_inverse_work(1, N)) HIPCHK(hipMalloc(&work, size_t(nwork) * 8));
+  std::vector<void *> tmp{Abuf, Lbuf, dstatus, dsz, work};
   struct Freer {
     std::vector<void *> &v;
     ~Freer() {
@@ -453,7 +458,7 @@ void setup_coarse(rz_problem &P, hipStream_t s) {
   rz::launch_pad_identity(1, N, dsz, Abuf, s);
   rz::launch_patch_assemble(nc, d_ip, d_ic, d_it, d_col, d_loc, d_coef, P.el.n, P.el.Q, P.R, P.w, N, Abuf, s);
   if (!wrem_idx.empty()) rz::launch_set_diag(N, up(wrem_idx), int(wrem_idx.size()), Abuf, s);
-  rz::launch_chol_inverse(1, N, Abuf, Lbuf, dstatus, s);
+  rz::launch_chol_inverse(1, N, Abuf, Lbuf, dstatus, work, s);
   double *tiles = P.dev<double>(size_t(NT) * (NT + 1) / 2 * 4096);
   rz::launch_pack_tiles(N, nW, Abuf, tiles, s);
   HIPCHK(hipGetLastError());

@@ -314,43 +314,26 @@ __global__ void k_chol_update(int N, int kb, double *__restrict__ A) {
   }
 }
 
-// one block row step of X = L^{-1}: X[jb + s][jb] for every column block jb
-__global__ void k_trtri_step(int N, int s, const double *__restrict__ A, double *__restrict__ X) {
+// X = L^{-1}, lower triangular, by diagonal offsets s = ib - jb.  s = 0: the
+// diagonal tiles X[ib][ib] = L[ib][ib]^{-1} by forward substitution (one
+// column per thread).  s >= 1: X[ib][jb] = -X[ib][ib] sum_{jb <= mb < ib}
+// L[ib][mb] X[mb][jb], the sum and the product on MFMA; when a step has few
+// tiles (a large single matrix) the sum is split over blocks and the partial
+// tiles are added in a fixed order by the finishing kernel.
+__global__ void k_trtri_diag(int N, const double *__restrict__ A, double *__restrict__ X) {
   __shared__ double Lt[BS][BS + 1];
-  __shared__ double Xt[BS][BS + 1];
   __shared__ double S[BS][BS + 1];
-  const int NB = N / BS;
-  const int jb = blockIdx.x, ib = jb + s;
-  if (ib >= NB) return;
+  const int ib = blockIdx.x;
   const double *M = A + int64_t(blockIdx.y) * N * N;
   double *Y = X + int64_t(blockIdx.y) * N * N;
-  const int oi = ib * BS, oj = jb * BS;
-  d4 acc = {0, 0, 0, 0};  // sum over mb of L[ib][mb] X[mb][jb] (this wave's quadrant)
-  for (int mb = jb; mb < ib; ++mb) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
-      const int i = t / BS, j = t % BS;
-      Lt[i][j] = M[int64_t(oi + i) * N + mb * BS + j];
-      Xt[i][j] = Y[int64_t(mb * BS + i) * N + oj + j];
-    }
-    __syncthreads();
-    tile_mfma<false, false>(Lt, Xt, acc);
-  }
-  {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = 16 * (wave >> 1) + (lane >> 4) + 4 * v, j = 16 * (wave & 1) + (lane & 15);
-      S[i][j] = ((s == 0 && i == j) ? 1.0 : 0.0) - acc[v];
-    }
-  }
-  __syncthreads();
+  const int oi = ib * BS;
   for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
     const int i = t / BS, j = t % BS;
     Lt[i][j] = M[int64_t(oi + i) * N + oi + j];
+    S[i][j] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (threadIdx.x < BS) {  // forward substitution, one column each
+  if (threadIdx.x < BS) {
     const int c = threadIdx.x;
     for (int r = 0; r < BS; ++r) {
       double v = S[r][c];
@@ -361,8 +344,99 @@ __global__ void k_trtri_step(int N, int s, const double *__restrict__ A, double 
   __syncthreads();
   for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
     const int i = t / BS, j = t % BS;
-    Y[int64_t(oi + i) * N + oj + j] = S[i][j];
+    Y[int64_t(oi + i) * N + oi + j] = S[i][j];
   }
+}
+
+// acc += sum_{m0 <= mb < m1} L[ib][mb] X[mb][jb] (this wave's quadrant)
+__device__ inline void trtri_sum(int N, const double *M, const double *Y, int ib, int jb, int m0, int m1,
+                                 double (*Lt)[BS + 1], double (*Xt)[BS + 1], d4 &acc) {
+  const int oi = ib * BS, oj = jb * BS;
+  for (int mb = m0; mb < m1; ++mb) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+      const int i = t / BS, j = t % BS;
+      Lt[i][j] = M[int64_t(oi + i) * N + mb * BS + j];
+      Xt[i][j] = Y[int64_t(mb * BS + i) * N + oj + j];
+    }
+    __syncthreads();
+    tile_mfma<false, false>(Lt, Xt, acc);
+  }
+}
+
+// X[ib][jb] = X[ib][ib] (-acc) on MFMA (Dt, St: LDS tiles, free on entry)
+__device__ inline void trtri_finish(int N, double *Y, int ib, int jb, const d4 &acc, double (*Dt)[BS + 1],
+                                    double (*St)[BS + 1]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int oi = ib * BS, oj = jb * BS;
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 16 * (wave >> 1) + (lane >> 4) + 4 * v, j = 16 * (wave & 1) + (lane & 15);
+    St[i][j] = -acc[v];
+  }
+  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+    const int i = t / BS, j = t % BS;
+    Dt[i][j] = Y[int64_t(oi + i) * N + oi + j];
+  }
+  __syncthreads();
+  d4 out = {0, 0, 0, 0};
+  tile_mfma<false, false>(Dt, St, out);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 16 * (wave >> 1) + (lane >> 4) + 4 * v, j = 16 * (wave & 1) + (lane & 15);
+    Y[int64_t(oi + i) * N + oj + j] = out[v];
+  }
+}
+
+// step s >= 1, whole sums: grid (NB - s, B)
+__global__ void k_trtri_step(int N, int s, const double *__restrict__ A, double *__restrict__ X) {
+  __shared__ double Lt[BS][BS + 1];
+  __shared__ double Xt[BS][BS + 1];
+  const int NB = N / BS;
+  const int jb = blockIdx.x, ib = jb + s;
+  if (ib >= NB) return;
+  const double *M = A + int64_t(blockIdx.y) * N * N;
+  double *Y = X + int64_t(blockIdx.y) * N * N;
+  d4 acc = {0, 0, 0, 0};
+  trtri_sum(N, M, Y, ib, jb, jb, ib, Lt, Xt, acc);
+  trtri_finish(N, Y, ib, jb, acc, Lt, Xt);
+}
+
+// step s >= 1, split sums: grid (NB - s, nK, B); partial kc covers mb in
+// [jb + kc KC, min(ib, jb + (kc + 1) KC)), stored in accumulator order
+__global__ void k_trtri_part(int N, int s, int KC, int nK, const double *__restrict__ A,
+                             const double *__restrict__ X, double *__restrict__ P) {
+  __shared__ double Lt[BS][BS + 1];
+  __shared__ double Xt[BS][BS + 1];
+  const int NB = N / BS;
+  const int jb = blockIdx.x, ib = jb + s, kc = blockIdx.y;
+  if (ib >= NB) return;
+  const double *M = A + int64_t(blockIdx.z) * N * N;
+  const double *Y = X + int64_t(blockIdx.z) * N * N;
+  const int m0 = jb + kc * KC, m1 = min(ib, m0 + KC);
+  d4 acc = {0, 0, 0, 0};
+  trtri_sum(N, M, Y, ib, jb, m0, m1, Lt, Xt, acc);
+  double *out = P + ((int64_t(blockIdx.z) * (NB - s) + jb) * nK + kc) * (BS * BS) + threadIdx.x * 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) out[v] = acc[v];
+}
+
+// step s >= 1 after k_trtri_part: the partials added in kc order, then the
+// product with the diagonal inverse; grid (NB - s, B)
+__global__ void k_trtri_fin(int N, int s, int nK, const double *__restrict__ P, double *__restrict__ X) {
+  __shared__ double Dt[BS][BS + 1];
+  __shared__ double St[BS][BS + 1];
+  const int NB = N / BS;
+  const int jb = blockIdx.x, ib = jb + s;
+  if (ib >= NB) return;
+  double *Y = X + int64_t(blockIdx.y) * N * N;
+  const double *in = P + (int64_t(blockIdx.y) * (NB - s) + jb) * nK * (BS * BS) + threadIdx.x * 4;
+  d4 acc = {0, 0, 0, 0};
+  for (int kc = 0; kc < nK; ++kc)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] += in[int64_t(kc) * (BS * BS) + v];
+  trtri_finish(N, Y, ib, jb, acc, Dt, St);
 }
 
 // A^{-1} = X^T X with X = L^{-1} lower triangular: tile (I >= J)
@@ -1762,7 +1836,22 @@ void launch_patch_assemble(int64_t n_items, const int32_t *item_patch, const int
                      tr_col, tr_loc, tr_coef, n, Q, R, w, N, A);
 }
 
-void launch_chol_inverse(int64_t B, int N, double *A, double *Linv, int *status, hipStream_t s) {
+// blocks a trtri step aims for before its sums are split
+constexpr int64_t kTrtriBlocks = 4096;
+
+int64_t chol_inverse_work(int64_t B, int N) {
+  const int NB = N / BS;
+  int64_t most = 0;
+  for (int st = 1; st < NB; ++st) {
+    const int64_t tiles = int64_t(NB - st) * B;
+    if (tiles >= kTrtriBlocks) continue;
+    const int nK = int(std::min<int64_t>(st, (kTrtriBlocks + tiles - 1) / tiles));
+    if (nK > 1) most = std::max(most, tiles * nK);
+  }
+  return most * BS * BS;
+}
+
+void launch_chol_inverse(int64_t B, int N, double *A, double *Linv, int *status, double *work, hipStream_t s) {
   const int NB = N / BS;
   for (int kb = 0; kb < NB; ++kb) {
     hipLaunchKernelGGL(k_chol_diag, dim3(unsigned(B)), dim3(256), 0, s, N, kb, A, status);
@@ -1773,8 +1862,20 @@ void launch_chol_inverse(int64_t B, int N, double *A, double *Linv, int *status,
                          kb, A);
     }
   }
-  for (int st = 0; st < NB; ++st)
-    hipLaunchKernelGGL(k_trtri_step, dim3(NB - st, unsigned(B)), dim3(256), 0, s, N, st, A, Linv);
+  hipLaunchKernelGGL(k_trtri_diag, dim3(unsigned(NB), unsigned(B)), dim3(256), 0, s, N, A, Linv);
+  for (int st = 1; st < NB; ++st) {
+    const int64_t tiles = int64_t(NB - st) * B;
+    int nK = tiles >= kTrtriBlocks ? 1 : int(std::min<int64_t>(st, (kTrtriBlocks + tiles - 1) / tiles));
+    if (nK > 1 && work) {
+      const int KC = (st + nK - 1) / nK;
+      nK = (st + KC - 1) / KC;
+      hipLaunchKernelGGL(k_trtri_part, dim3(unsigned(NB - st), unsigned(nK), unsigned(B)), dim3(256), 0, s, N, st,
+                         KC, nK, A, Linv, work);
+      hipLaunchKernelGGL(k_trtri_fin, dim3(unsigned(NB - st), unsigned(B)), dim3(256), 0, s, N, st, nK, work, Linv);
+    } else {
+      hipLaunchKernelGGL(k_trtri_step, dim3(unsigned(NB - st), unsigned(B)), dim3(256), 0, s, N, st, A, Linv);
+    }
+  }
   hipLaunchKernelGGL(k_lauum, dim3(unsigned(int64_t(NB) * (NB + 1) / 2), unsigned(B)), dim3(256), 0, s, N, Linv, A);
 }
 

@@ -28,7 +28,11 @@ void launch_patch_assemble(int64_t n_items, const int32_t *item_patch, const int
                            const double *tr_coef, int n, int Q, const double *R, const double *w, int N,
                            double *A, hipStream_t s);
 // batched blocked Cholesky + inverse of B uniform N x N SPD matrices (N % 32 == 0)
-void launch_chol_inverse(int64_t B, int N, double *A, double *Linv, int *status, hipStream_t s);
+// A (B matrices N x N, N a multiple of 32) -> A^{-1} through Cholesky,
+// L^{-1} (in Linv) and L^{-T} L^{-1}; work: chol_inverse_work(B, N) doubles
+// for the split triangular-inverse sums (null: no splitting)
+int64_t chol_inverse_work(int64_t B, int N);
+void launch_chol_inverse(int64_t B, int N, double *A, double *Linv, int *status, double *work, hipStream_t s);
 // patch inverses in the segmented upper layout (see seg_size)
 void launch_pack_seg(int64_t B, int N, int E, const int32_t *sizes, const int64_t *off, const double *Ainv,
                      double *packed, hipStream_t s);
