@@ -103,9 +103,12 @@ def test_setup_rejects_before_device_work():
 # p = 8 in 3D take 20-80 s each, so Ned_9, Ned_10 and RT_9, RT_10 are
 # "heavy" (run with RZ_HEAVY_TESTS=1)
 HEAVY = pytest.mark.heavy
-REF_CASES = [(2, f, p) for f in ("CG", "Ned", "RT") for p in range(1, 11)] + [(3, "CG", p) for p in range(1, 11)] + \
-            [(3, f, p) for f in ("NedTwo", "BDM") for p in range(1, 9)] + \
-            [(3, f, p) for f in ("Ned", "RT") for p in range(1, 9)] + \
+SLOW = pytest.mark.slow
+REF_CASES = [(2, f, p) if p <= 8 else pytest.param(2, f, p, marks=SLOW) for f in ("CG", "Ned", "RT")
+             for p in range(1, 11)] + \
+            [(3, "CG", p) if p <= 5 else pytest.param(3, "CG", p, marks=SLOW) for p in range(1, 11)] + \
+            [(3, f, p) if p <= 4 else pytest.param(3, f, p, marks=SLOW) for f in ("NedTwo", "BDM") for p in range(1, 9)] + \
+            [(3, f, p) if p <= 4 else pytest.param(3, f, p, marks=SLOW) for f in ("Ned", "RT") for p in range(1, 9)] + \
             [pytest.param(3, f, p, marks=HEAVY) for f in ("Ned", "RT") for p in (9, 10)]
 
 
@@ -129,7 +132,6 @@ def table_tolerance(d, fam, p):
     return 5e-10 if fam == "RT" else 5e-11
 
 
-@pytest.mark.slow
 @pytest.mark.parametrize("d,fam,p", REF_CASES, ids=lambda v: str(v))
 def test_reference_tables_match_oracle(d, fam, p):
     R = rz.reference(d, p, fam)
@@ -243,7 +245,7 @@ def test_hiptmair_only_for_hcurl():
 
 
 @pytest.mark.parametrize("k", [1, 2])
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("p", [1, 2, 3, 4] + [pytest.param(q, marks=pytest.mark.slow) for q in (5, 6)])
 def test_derivative_reference_matches_oracle(k, p):
     """The library's reference derivative matrix of the complex (its own
     quadrature, Gram-system projection and dofs) against the oracle's
@@ -256,7 +258,7 @@ def test_derivative_reference_matches_oracle(k, p):
     assert np.abs(D - Do).max() <= 1e-11 * max(1.0, np.abs(Do).max())
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("p", [1, 2, 3, 4] + [pytest.param(q, marks=pytest.mark.slow) for q in (5, 6)])
 def test_divergence_reference_matches_oracle(p):
     """div RT_p -> DG_{p-1} on the reference cell.  Both sides expand in an
     L2-orthonormal basis of P_{p-1} of their own (each builds its Dubiner

@@ -90,7 +90,7 @@ def _bubble_counts(p):
     }
 
 
-@pytest.mark.parametrize("p", [2, 3, 4, 6])
+@pytest.mark.parametrize("p", [2, 3, 4, pytest.param(6, marks=pytest.mark.slow)])
 def test_type_one_counts_and_kernel(p):
     for (fam, l), n in _bubble_counts(p).items():
         eb = eigenbasis(l, fam, p)
@@ -118,8 +118,8 @@ def _blocks(el):
 
 
 @pytest.mark.parametrize("d,fam,p", [(2, "CG", 4), (2, "CG", 7), (3, "CG", 3), (3, "CG", 6),
-                                     (3, "Ned", 2), (3, "Ned", 4), (3, "Ned", 6),
-                                     (3, "RT", 2), (3, "RT", 4), (3, "RT", 6),
+                                     (3, "Ned", 2), (3, "Ned", 4), pytest.param(3, "Ned", 6, marks=pytest.mark.slow),
+                                     (3, "RT", 2), (3, "RT", 4), pytest.param(3, "RT", 6, marks=pytest.mark.slow),
                                      (2, "Ned", 3), (2, "Ned", 6), (2, "RT", 3), (2, "RT", 6),
                                      (3, "NedTwo", 2), (3, "NedTwo", 4), (3, "BDM", 2), (3, "BDM", 4)])
 def test_reference_matrix_structure(d, fam, p):
@@ -212,7 +212,7 @@ def _derivative_coeffs(el, target_space_l):
     return np.einsum("q,qcj,qn->cnj", w, dv, V).reshape(-1, el.n)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 5])
+@pytest.mark.parametrize("p", [1, 2, 3, pytest.param(5, marks=pytest.mark.slow)])
 def test_local_discrete_gradient_structure(p):
     """lem:d-preserves-basis-functions: the Ned_p dofs of grad phi^CG_j are the
     Whitney incidence (vertex -> +-1 on its edges) plus the identity from CG

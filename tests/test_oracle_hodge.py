@@ -47,7 +47,7 @@ def _paper_rows():
     return out
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, pytest.param(4, marks=pytest.mark.slow)])
 def test_derivatives_form_a_complex(p):
     X, C = kuhn_mesh(2, 3, jitter=0.1, seed=5)
     tops = [Topology(X, C, element(3, f, p)) for f in ("CG", "Ned", "RT")]
@@ -79,7 +79,7 @@ def test_derivative_reproduces_the_stiffness(k, p):
 
 
 @pytest.mark.parametrize("k", [1, 2, 3])
-@pytest.mark.parametrize("gamma", [1.0, 10.0, 1e3])
+@pytest.mark.parametrize("gamma", [1.0, pytest.param(10.0, marks=pytest.mark.slow), 1e3])
 def test_preconditioned_spectrum_is_the_theorems(k, gamma):
     X, C = fichera_mesh(2, jitter=0.1, seed=3)
     H = HodgeLaplacian(X, C, k, 1 if gamma != 10.0 else 2, gamma=gamma, exact=True)

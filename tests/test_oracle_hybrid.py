@@ -79,7 +79,14 @@ def test_paper_level0_iterations_and_condest(row):
     assert abs(lanczos_condest(info["alphas"], info["betas"]) / cond - 1.0) <= 0.06
 
 
-@pytest.mark.parametrize("row", golden_vstar_rows(), ids=lambda r: f"{r[0]}{r[2]}-{r[1]}-alpha{r[4]:g}")
+def _slow_above(rows, key, limit):
+    """The rows whose degree exceeds limit as slow cases (the cheapest degree
+    of every space, decomposition and coefficient always runs)."""
+    return [pytest.param(r, marks=pytest.mark.slow) if key(r) > limit else r for r in rows]
+
+
+@pytest.mark.parametrize("row", _slow_above(golden_vstar_rows(), lambda r: r[2], 2),
+                         ids=lambda r: f"{r[0]}{r[2]}-{r[1]}-alpha{r[4]:g}")
 def test_paper_level0_comparator_solvers(row):
     fam, form, p, dofs, alpha, its, cond = row
     top, A = build(fam, p, alpha=alpha)
@@ -102,7 +109,8 @@ def golden_l1_rows():
     return [(r[0], int(r[1]), int(r[2]), float(r[3]), int(r[4]), float(r[5])) for r in rows]
 
 
-@pytest.mark.parametrize("row", golden_l1_rows(), ids=lambda r: f"{r[0]}{r[1]}-alpha{r[3]:g}")
+@pytest.mark.parametrize("row", [r if r[3] == 1.0 else pytest.param(r, marks=pytest.mark.slow) for r in golden_l1_rows()],
+                         ids=lambda r: f"{r[0]}{r[1]}-alpha{r[3]:g}")
 def test_exact_coarse_solve_bounds_the_papers_multigrid_coarse(row):
     """Level 1: the paper's coarse solver is a V-cycle, the oracle's is exact
     (reading R9).  The dof counts match, and the exact coarse solve gives a
@@ -158,7 +166,7 @@ def test_comparator_lists_nest():
         assert np.all(Gf[:, Gs.shape[1]:].nonzero()[0] >= top.offset[3])
 
 
-@pytest.mark.parametrize("p", [2, 3, 4])
+@pytest.mark.parametrize("p", [2, 3, pytest.param(4, marks=pytest.mark.slow)])
 def test_curl_potentials_are_divergence_free(p):
     """The H(div) type-I potential columns are curls: div-div stiffness times
     every column vanishes (a wrong orientation sign or a non-curl column
@@ -198,7 +206,8 @@ def test_sweep_symmetric_positive_and_product_of_propagators(fam, p, form):
     assert np.abs((I - B @ Ad) - E).max() <= 1e-10
 
 
-@pytest.mark.parametrize("fam,p", [("CG", 5), ("Ned", 3), ("RT", 3)])
+@pytest.mark.parametrize("fam,p", [("CG", 3), ("RT", 2), pytest.param("Ned", 2, marks=pytest.mark.slow)] +
+                         [pytest.param(f, q, marks=pytest.mark.slow) for f, q in (("CG", 5), ("Ned", 3), ("RT", 3))])
 def test_weights_interlace_exact_spectrum(fam, p):
     top, A = build(fam, p, n=2, jitter=0.1)
     H = HybridSchwarz(A, top, fam)

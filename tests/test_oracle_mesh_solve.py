@@ -45,7 +45,7 @@ def per_entity(space, p):
 
 
 @pytest.mark.parametrize("space", ["CG", "Ned", "RT"])
-@pytest.mark.parametrize("p", [2, 3, 5, 7])
+@pytest.mark.parametrize("p", [2, 3] + [pytest.param(q, marks=pytest.mark.slow) for q in (5, 7)])
 def test_per_entity_counts_match_elements(space, p):
     assert tuple(element(3, space, p).counts()) == per_entity(space, p)
 

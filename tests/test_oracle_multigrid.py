@@ -45,7 +45,7 @@ def test_hierarchy():
 
 
 @pytest.mark.parametrize("k", [0, 1, 2])
-@pytest.mark.parametrize("nc", [1, 2])
+@pytest.mark.parametrize("nc", [1, pytest.param(2, marks=pytest.mark.slow)])
 def test_prolongation_reproduces_coarse_whitney_forms(k, nc):
     P, tc, tf = whitney_prolongation(nc, k)
     Xc, Cc = _kuhn_unit(nc)

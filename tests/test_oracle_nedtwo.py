@@ -32,7 +32,7 @@ def test_nedtwo_dimensions(p):
     assert el.counts() == [0, 1 + p, nI_f + p * (p - 1) // 2, nI_c + p * (p - 1) * (p - 2) // 6]
 
 
-@pytest.mark.parametrize("p", [3, 4, 5])
+@pytest.mark.parametrize("p", [3, 4, pytest.param(5, marks=pytest.mark.slow)])
 def test_nedtwo_reference_matrix_structure(p):
     el = element(3, "NedTwo", p)
     M, K = reference_matrices(el)

@@ -43,8 +43,10 @@ def _cells(d, rng, n=20):
 
 
 @pytest.mark.parametrize("d,fam,p", [(2, f, p) for f in ("CG", "Ned", "RT") for p in range(1, 7)]
-                         + [(3, f, p) for f in ("CG", "Ned", "RT") for p in range(1, 7)]
-                         + [(3, f, p) for f in ("NedTwo", "BDM") for p in range(1, 5)])
+                         + [(3, f, p) if p <= (4 if f == "CG" else 3) else pytest.param(3, f, p, marks=pytest.mark.slow)
+                            for f in ("CG", "Ned", "RT") for p in range(1, 7)]
+                         + [(3, f, p) if p <= 3 else pytest.param(3, f, p, marks=pytest.mark.slow)
+                            for f in ("NedTwo", "BDM") for p in range(1, 5)])
 def test_stacked_form_equals_cell_quadrature(d, fam, p):
     el = element(d, fam, p)
     R = reference_stack(el)
@@ -81,8 +83,9 @@ def _random_cluster_rotation(bounds, n, rng):
     return Q
 
 
-@pytest.mark.parametrize("l,fam,p", [(2, "CG", 4), (2, "CG", 7), (3, "CG", 6), (3, "CG", 8), (2, "Ned", 5),
-                                     (3, "Ned", 4), (3, "Ned", 5), (3, "RT", 4), (3, "RT", 5), (2, "NedTwo", 4),
+@pytest.mark.parametrize("l,fam,p", [(2, "CG", 4), (2, "CG", 7), (3, "CG", 6), pytest.param(3, "CG", 8, marks=pytest.mark.slow),
+                                     (2, "Ned", 5), (3, "Ned", 4), pytest.param(3, "Ned", 5, marks=pytest.mark.slow),
+                                     (3, "RT", 4), pytest.param(3, "RT", 5, marks=pytest.mark.slow), (2, "NedTwo", 4),
                                      (3, "NedTwo", 4), (2, "RT", 5), (3, "BDM", 4)])
 def test_cluster_canonicalisation_is_basis_invariant(l, fam, p):
     sp, Bb, K, mu, Vec, n_ker = bubble_eigenproblem(l, fam, p)
