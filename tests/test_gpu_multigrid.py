@@ -127,3 +127,7 @@ def test_vcycle_errors():
     with pytest.raises(rz.RzError) as e:           # Dirichlet + multigrid
         rz.Problem(X, C, 2, "CG", coarse="mg", mg_meshes=hierarchy(4), dirichlet_facet=flags)
     assert e.value.code in (-2, -3)
+    for fam in ("NedTwo", "BDM"):                  # the hierarchy is built for the first-kind spaces
+        with pytest.raises(rz.RzError) as e:
+            rz.Problem(X, C, 2, fam, coarse="mg", mg_meshes=hierarchy(4))
+        assert e.value.code == -2

@@ -89,6 +89,12 @@ def test_setup_rejects_before_device_work():
     assert b"decomposition" in rz.lib.rz_last_error()
     assert rz.lib.rz_setup(None, 2, 0, None, None, ctypes.byref(h)) == -1
     assert rz.lib.rz_setup(ctypes.byref(m), 12, 0, None, None, ctypes.byref(h)) == -2
+    X2, C2 = kuhn_mesh(2, 2)
+    m2, keep2 = _mesh_struct(X2, C2)
+    for space in (3, 4):                          # the second-kind spaces on triangles
+        assert rz.lib.rz_setup(ctypes.byref(m2), 2, space, None, None, ctypes.byref(h)) == -2
+        assert b"tetrahedral" in rz.lib.rz_last_error()
+    assert rz.lib.rz_setup(ctypes.byref(m), 2, 5, None, None, ctypes.byref(h)) == -1   # unknown space
     # a flat tetrahedron: all four vertices in one plane
     Xf = X.copy()
     flat = C[0]
