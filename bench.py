@@ -432,7 +432,9 @@ def decompositions(args):
     (H(curl) PH(X^0, X^{1,I}), H(div) PAFW(1)(X^2)), for H(curl) the
     standard Hiptmair-Toselli PH(X^0_Gamma, X^1_Gamma)+J and PH(X^0, X^1),
     and for H(div) the type-I Hiptmair-Toselli PH(X^{1,I}_Gamma,
-    X^{2,I}_Gamma)+J and PH(X^{1,I}, X^{2,I}).
+    X^{2,I}_Gamma)+J and PH(X^{1,I}, X^{2,I}) and the standard one
+    PH(X^1_Gamma, X^2_Gamma)+J and PH(X^1, X^2) (NedTwo potentials with the
+    regularising mass).
     Per problem: setup, iterations, solve time, patch sizes.  Roofline: the additive full-star
     preconditioner apply of the largest problem, an HBM stream of the packed
     patch and coarse inverses."""
@@ -446,7 +448,8 @@ def decompositions(args):
     degrees = [4, 5] if args.degrees == "3,4,5,6,7,8" else [int(p) for p in args.degrees.split(",")]
     forms_of = {"CG": ["paper", "vertex", "vertex-full"],
                 "Ned": ["paper", "paper-full", "hiptmair", "hiptmair-full", "vertex", "vertex-full"],
-                "RT": ["paper", "paper-full", "typeI", "typeI-full", "vertex", "vertex-full"]}
+                "RT": ["paper", "paper-full", "typeI", "typeI-full", "hiptmair", "hiptmair-full", "vertex",
+                       "vertex-full"]}
     forms = ["paper", "vertex", "vertex-full", "paper-full", "hiptmair", "hiptmair-full", "typeI", "typeI-full"]
     # Whitney (coarse) dof counts: vertices, edges or faces of the mesh
     Cs = np.sort(C, axis=1)
@@ -473,14 +476,15 @@ def decompositions(args):
                     info = prob.solve(b, x, rtol=1e-10)
                 torch.cuda.synchronize()
                 dt = (time.perf_counter() - t0) / args.steps
-                ptr, _ = rz.patch_lists(X, C, p, fam, form)
-                m = np.diff(ptr)
+                sets = prob.patch_sets()
+                m = np.array([st["max_size"] for st in sets])
+                packed = sum(st["packed_entries"] for st in sets)
                 t_p = _apply_time(prob.apply_P, b, x, args.apply_reps, stream)
                 rows.append(dict(space=fam, p=p, decomposition=form, dofs=prob.n_dofs, its=info["iterations"],
                                  rel_res=info["rel_residual"], cond=round(info["cond_estimate"], 3),
                                  solve_ms=round(dt * 1e3, 3), apply_P_us=round(t_p * 1e6, 1),
                                  setup_s=round(t_set, 2), max_patch=int(m.max()),
-                                 patch_mb=round(float((m * (m + 1) // 2).sum()) * 8 / 1e6, 1)))
+                                 patch_mb=round(float(packed) * 8 / 1e6, 1)))
                 tot[form][0] += prob.n_dofs
                 tot[form][1] += dt
                 if fam not in tot[form][2]:

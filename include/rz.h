@@ -75,9 +75,8 @@ enum {
  * eq:hcurl-dofs / eq:hdiv-dofs whose type-II moments come from the next-lower
  * space of the second-kind sequence (CG_{p+1} for NedTwo_p, NedTwo_{p+1} for
  * BDM_p, the remark after eq:hdiv-dofs).  They take the decompositions of
- * RZ_HCURL and RZ_HDIV, the potentials from those lower spaces (the standard
- * Hiptmair-Toselli decompositions: RZ_HCURL2 only) and the exact coarse
- * solver only (RZ_COARSE_MG -> RZ_ERR_UNSUPPORTED). */
+ * RZ_HCURL and RZ_HDIV, the potentials from those lower spaces, and the
+ * exact coarse solver only (RZ_COARSE_MG -> RZ_ERR_UNSUPPORTED). */
 enum { RZ_HGRAD = 0, RZ_HCURL = 1, RZ_HDIV = 2, RZ_HCURL2 = 3, RZ_HDIV2 = 4 };
 typedef int32_t rz_space;
 
@@ -142,12 +141,21 @@ typedef enum { RZ_PC_ADDITIVE = 0, RZ_PC_HYBRID = 1 } rz_pc;
  * holds the dofs (of the kinds it keeps) of the cells containing its centre,
  * the H(curl) potentials the CG cell interiors, and there is no Jacobi group:
  * H(grad) PAFW(0)(X^0), H(curl) PH(X^0, X^{1,I}), H(div) PAFW(1)(X^2).
- * RZ_DECOMP_HIPTMAIR (H(curl) only, else RZ_ERR_UNSUPPORTED): the standard
- * Hiptmair-Toselli decomposition with the split, PH(X^0_Gamma, X^1_Gamma) +
- * J(X^1_I) (eq:pavarino_hiptmair): the vertex-star potentials of
- * RZ_DECOMP_PAPER and edge stars of every kind of interface dof.
- * RZ_DECOMP_HIPTMAIR_FULL (H(curl) only): PH(X^0, X^1), the same with the
- * cell interiors and no Jacobi group.
+ * RZ_DECOMP_HIPTMAIR (H(curl) and H(div); H(grad) -> RZ_ERR_UNSUPPORTED):
+ * the standard Hiptmair-Toselli decomposition with the split
+ * (eq:pavarino_hiptmair).  H(curl): PH(X^0_Gamma, X^1_Gamma) + J(X^1_I), the
+ * vertex-star potentials of RZ_DECOMP_PAPER and edge stars of every kind of
+ * interface dof.  3D H(div): PH(X^1_Gamma, X^2_Gamma) + J(X^2_I), face stars
+ * X^2|star F (the face's dofs) and edge-star potentials curl X^1|star E with
+ * X^1 = NedTwo_p (NedTwo_{p+1} for BDM_p): one column per NedTwo dof of the
+ * edge and its faces, the curl in the H(div) basis, and each local matrix
+ * regularised by the NedTwo mass times 1e-8 beta
+ * (eq:local-potential-problem-added-mass; its condition number is then about
+ * 1e8, which the explicit inverse carries); pure Neumann only
+ * (dirichlet_facet -> RZ_ERR_UNSUPPORTED).
+ * RZ_DECOMP_HIPTMAIR_FULL: PH(X^0, X^1) or PH(X^1, X^2), the same with the
+ * cell interiors (their dofs in the stars, their NedTwo dofs in the
+ * potentials) and no Jacobi group.
  * RZ_DECOMP_TYPEI / RZ_DECOMP_TYPEI_FULL (H(curl) and H(div), else
  * RZ_ERR_UNSUPPORTED): the type-I Hiptmair-Toselli decomposition
  * PH(X^{k-1,I}, X^{k,I}) (eq:pavarino_hiptmair-novel) with / without the

@@ -60,6 +60,13 @@ struct rz_problem {
   rz::RefElement el;
   rz::Topology top;
   std::vector<rz::PatchSet> patches;
+  // the standard H(div) Hiptmair-Toselli decomposition only: per patch set
+  // the coupling of its columns to the NedTwo potential functions (empty
+  // sets elsewhere), their element, reference stack and weights (the
+  // regularising mass 1e-8 beta of eq:local-potential-problem-added-mass)
+  std::vector<rz::PatchSet> patches2;
+  rz::RefElement el2;
+  double *R2 = nullptr, *w2 = nullptr;
   int64_t off_I = 0;
   int max_iter = 1000;
   int precision = RZ_FP64;
@@ -203,7 +210,8 @@ void check_cells(const rz_problem &P, const double *coords) {
 }
 
 // factor a batch of patch matrices (chunked to bound the dense workspace)
-void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hipStream_t s) {
+void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hipStream_t s,
+                     const rz::PatchSet *ps2 = nullptr) {
   const int64_t B = ps.n_patches();
   const int maxsz = int(ps.max_size());
   if (maxsz > rz::kMaxPatch)
@@ -258,17 +266,35 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
   HIPCHK(hipMemcpyAsync(t_col, ps.tr_col.data(), ps.tr_col.size() * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(t_loc, ps.tr_loc.data(), ps.tr_loc.size() * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(t_coef, ps.tr_coef.data(), ps.tr_coef.size() * 8, hipMemcpyHostToDevice, s));
-  for (int64_t p0 = 0; p0 < B; p0 += nch) {
-    const int64_t p1 = std::min(B, p0 + nch), nb = p1 - p0;
-    const int64_t i0 = ps.pc_ptr[p0], i1 = ps.pc_ptr[p1];
-    std::vector<int32_t> item_patch(i1 - i0), item_cell(ps.pc_cell.begin() + i0, ps.pc_cell.begin() + i1);
-    std::vector<int64_t> item_trip(ps.pc_trip.begin() + i0, ps.pc_trip.begin() + i1 + 1);
+  // the second family's coupling triples (NedTwo potentials), if any
+  const bool two = ps2 && ps2->n_patches() == B && B > 0;
+  int32_t *t2_col = nullptr, *t2_loc = nullptr;
+  double *t2_coef = nullptr;
+  if (two) {
+    const size_t n2 = std::max<size_t>(1, ps2->tr_col.size());
+    HIPCHK(hipMalloc(&t2_col, n2 * 4));
+    HIPCHK(hipMalloc(&t2_loc, n2 * 4));
+    HIPCHK(hipMalloc(&t2_coef, n2 * 8));
+    fr.v.push_back(t2_col);
+    fr.v.push_back(t2_loc);
+    fr.v.push_back(t2_coef);
+    HIPCHK(hipMemcpyAsync(t2_col, ps2->tr_col.data(), ps2->tr_col.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(t2_loc, ps2->tr_loc.data(), ps2->tr_loc.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(t2_coef, ps2->tr_coef.data(), ps2->tr_coef.size() * 8, hipMemcpyHostToDevice, s));
+  }
+  // adds the (patch, cell) items of patches [p0, p1) of q to the chunk's matrices
+  auto assemble = [&](const rz::PatchSet &q, int64_t p0, int64_t p1, const int32_t *tc, const int32_t *tl,
+                      const double *tf, int n, int Q, const double *R, const double *w) {
+    const int64_t i0 = q.pc_ptr[p0], i1 = q.pc_ptr[p1];
+    if (i1 == i0) return;
+    std::vector<int32_t> item_patch(i1 - i0), item_cell(q.pc_cell.begin() + i0, q.pc_cell.begin() + i1);
+    std::vector<int64_t> item_trip(q.pc_trip.begin() + i0, q.pc_trip.begin() + i1 + 1);
     for (int64_t p = p0; p < p1; ++p)
-      for (int64_t it = ps.pc_ptr[p]; it < ps.pc_ptr[p + 1]; ++it) item_patch[it - i0] = int32_t(p - p0);
+      for (int64_t it = q.pc_ptr[p]; it < q.pc_ptr[p + 1]; ++it) item_patch[it - i0] = int32_t(p - p0);
     int32_t *d_ip = nullptr, *d_ic = nullptr;
     int64_t *d_it = nullptr;
-    HIPCHK(hipMalloc(&d_ip, std::max<size_t>(1, item_patch.size()) * 4));
-    HIPCHK(hipMalloc(&d_ic, std::max<size_t>(1, item_cell.size()) * 4));
+    HIPCHK(hipMalloc(&d_ip, item_patch.size() * 4));
+    HIPCHK(hipMalloc(&d_ic, item_cell.size() * 4));
     HIPCHK(hipMalloc(&d_it, item_trip.size() * 8));
     fr.v.push_back(d_ip);
     fr.v.push_back(d_ic);
@@ -276,11 +302,15 @@ void setup_patch_set(rz_problem &P, const rz::PatchSet &ps, DevPatchSet &out, hi
     HIPCHK(hipMemcpy(d_ip, item_patch.data(), item_patch.size() * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(d_ic, item_cell.data(), item_cell.size() * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(d_it, item_trip.data(), item_trip.size() * 8, hipMemcpyHostToDevice));
+    rz::launch_patch_assemble(i1 - i0, d_ip, d_ic, d_it, tc, tl, tf, n, Q, R, w, N, Abuf, s);
+  };
+  for (int64_t p0 = 0; p0 < B; p0 += nch) {
+    const int64_t p1 = std::min(B, p0 + nch), nb = p1 - p0;
     HIPCHK(hipMemsetAsync(Abuf, 0, size_t(nb) * N * N * 8, s));
     HIPCHK(hipMemsetAsync(Lbuf, 0, size_t(nb) * N * N * 8, s));
     rz::launch_pad_identity(nb, N, dsizes + p0, Abuf, s);
-    rz::launch_patch_assemble(i1 - i0, d_ip, d_ic, d_it, t_col, t_loc, t_coef, P.el.n, P.el.Q, P.R, P.w, N, Abuf,
-                              s);
+    assemble(ps, p0, p1, t_col, t_loc, t_coef, P.el.n, P.el.Q, P.R, P.w);
+    if (two) assemble(*ps2, p0, p1, t2_col, t2_loc, t2_coef, P.el2.n, P.el2.Q, P.R2, P.w2);
     rz::launch_chol_inverse(nb, N, Abuf, Lbuf, dstatus, work, s);
     if (fold) rz::launch_pack_fold(nb, N, dsizes + p0, doff + p0, Abuf, inv, s);
     else rz::launch_pack_seg(nb, N, E, dsizes + p0, doff + p0, Abuf, inv, s);
@@ -587,7 +617,16 @@ void do_setup(rz_problem &P, const rz_mesh *m, hipStream_t s) {
   // numbering, patches
   P.top = rz::build_topology(P.d, m->n_vertices, m->n_cells, m->cells, P.el);
   check_cells(P, m->coords);
-  P.patches = rz::build_patches(P.top, P.el, rz::Decomposition(P.decomp));
+  const bool hdiv_ht = P.d == 3 && (P.fam == rz::FAM_RT || P.fam == rz::FAM_BDM) &&
+                       (P.decomp == RZ_DECOMP_HIPTMAIR || P.decomp == RZ_DECOMP_HIPTMAIR_FULL);
+  if (hdiv_ht) {
+    // the potentials are NedTwo functions: NedTwo_p for RT_p, NedTwo_{p+1} for BDM_p
+    P.el2 = rz::build_reference(3, rz::FAM_NEDTWO, P.p + (P.fam == rz::FAM_BDM ? 1 : 0));
+    const rz::Topology t2 = rz::build_topology(3, m->n_vertices, m->n_cells, m->cells, P.el2);
+    P.patches = rz::build_hdiv_hiptmair(P.top, P.el, t2, P.el2, P.decomp == RZ_DECOMP_HIPTMAIR_FULL, P.patches2);
+  } else {
+    P.patches = rz::build_patches(P.top, P.el, rz::Decomposition(P.decomp));
+  }
   if (!P.dir_flags.empty()) {
     // X^k_{p,D} (Sec. 5): remove the functions tied to subsimplices of Gamma_D
     P.dir_dofs = rz::dirichlet_dofs(P.top, P.el, m->cells, P.dir_flags.data());
@@ -680,9 +719,8 @@ static rz::Family family_of(int space) {
 static int check_decomposition(int32_t dec, int space, int dim) {
   if (dec < RZ_DECOMP_PAPER || dec > RZ_DECOMP_TYPEI_FULL) return fail(RZ_ERR_ARG, "unknown decomposition");
   // 2D H(div) is the quarter turn of 2D H(curl) and shares its decompositions
-  if ((dec == RZ_DECOMP_HIPTMAIR || dec == RZ_DECOMP_HIPTMAIR_FULL) && space != RZ_HCURL &&
-      space != RZ_HCURL2 && !(dim == 2 && space == RZ_HDIV))
-    return fail(RZ_ERR_UNSUPPORTED, "the standard Hiptmair-Toselli decompositions are built for H(curl) only");
+  if ((dec == RZ_DECOMP_HIPTMAIR || dec == RZ_DECOMP_HIPTMAIR_FULL) && space == RZ_HGRAD)
+    return fail(RZ_ERR_UNSUPPORTED, "the Hiptmair-Toselli decompositions need H(curl) or H(div)");
   if ((dec == RZ_DECOMP_TYPEI || dec == RZ_DECOMP_TYPEI_FULL) && space == RZ_HGRAD)
     return fail(RZ_ERR_UNSUPPORTED, "the type-I Hiptmair-Toselli decompositions need H(curl) or H(div)");
   return RZ_OK;
@@ -720,8 +758,12 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     P->graphs = opts->eager == 0;
     if (int e = check_decomposition(opts->decomposition, space, m->dim)) return e;
     P->decomp = opts->decomposition;
-    if (opts->dirichlet_facet)
+    if (opts->dirichlet_facet) {
+      if ((opts->decomposition == RZ_DECOMP_HIPTMAIR || opts->decomposition == RZ_DECOMP_HIPTMAIR_FULL) &&
+          m->dim == 3 && (space == RZ_HDIV || space == RZ_HDIV2))
+        return fail(RZ_ERR_UNSUPPORTED, "the H(div) Hiptmair-Toselli potentials are built for pure Neumann problems");
       P->dir_flags.assign(opts->dirichlet_facet, opts->dirichlet_facet + m->n_cells * (m->dim + 1));
+    }
     if (opts->coarse != RZ_COARSE_EXACT && opts->coarse != RZ_COARSE_MG)
       return fail(RZ_ERR_ARG, "unknown coarse solver");
   }
@@ -749,6 +791,12 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
       double *dEi = P->upload(Ei.a, s);
       const int pullback = P->k == 0 ? 0 : ((P->el.fam == rz::FAM_RT || P->el.fam == rz::FAM_BDM) ? 2 : 1);
       rz::launch_weights(d, pullback, nc, dX, dEi, alpha, beta, P->w, Q, s);
+      if (!P->patches2.empty()) {
+        // the NedTwo mass 1e-8 beta (covariant pullback, no curl term)
+        P->w2 = P->dev<double>(size_t(nc) * P->el2.Q);
+        rz::launch_weights(d, 1, nc, dX, dEi, 0.0, 1e-8 * beta, P->w2, P->el2.Q, s);
+        P->R2 = P->upload(P->el2.R, s);
+      }
     }
     // interior diagonal (Jacobi on X^k_I; an empty group under the full
     // vertex stars)
@@ -797,7 +845,8 @@ int rz_setup(const rz_mesh *m, int32_t degree, rz_space space, const rz_options 
     }
     // interface patches and coarse space
     P->dps.resize(P->patches.size());
-    for (size_t i = 0; i < P->patches.size(); ++i) setup_patch_set(*P, P->patches[i], P->dps[i], s);
+    for (size_t i = 0; i < P->patches.size(); ++i)
+      setup_patch_set(*P, P->patches[i], P->dps[i], s, P->patches2.empty() ? nullptr : &P->patches2[i]);
     if (opts && opts->coarse == RZ_COARSE_MG)
       setup_multigrid(*P, m, opts, s);
     else

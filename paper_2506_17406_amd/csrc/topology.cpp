@@ -251,7 +251,7 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
                      : el.fam == FAM_BDM                                  ? FAM_RT
                                                                           : el.fam;
   if (hiptmair && fam != FAM_NED)
-    throw std::runtime_error("the Hiptmair-Toselli decompositions are built for H(curl) only");
+    throw std::runtime_error("the H(div) Hiptmair-Toselli decompositions are built by build_hdiv_hiptmair");
   if (typeI && fam == FAM_CG)
     throw std::runtime_error("the type-I Hiptmair-Toselli decompositions need H(curl) or H(div)");
   if (typeI && fam == FAM_RT) {
@@ -376,6 +376,83 @@ std::vector<PatchSet> build_patches(const Topology &t, const RefElement &el, Dec
     }
     out.push_back(std::move(ps));
   }
+  return out;
+}
+
+std::vector<PatchSet> build_hdiv_hiptmair(const Topology &t, const RefElement &el, const Topology &t2,
+                                          const RefElement &el2, bool full, std::vector<PatchSet> &second) {
+  Incidence in = incidence(t);
+  std::vector<int32_t> mark_col(t.n_dofs, -1), mark2(t2.n_dofs, -1);
+  std::vector<double> mark_coef(t.n_dofs, 0.0), mcoef2(t2.n_dofs, 0.0);
+  std::vector<PatchSet> out;
+  second.clear();
+  auto plain = [](std::vector<int32_t> &dofs) {
+    std::sort(dofs.begin(), dofs.end());
+    std::vector<std::vector<std::pair<int32_t, double>>> cols;
+    for (int32_t g : dofs) cols.push_back({{g, 1.0}});
+    return cols;
+  };
+  // face stars X^2|star F: the dofs of the face, and (full) of its cells
+  PatchSet pf = empty_set();
+  for (int64_t f = 0; f < t.n_ent[2]; ++f) {
+    std::vector<int32_t> dofs;
+    entity_dofs(t, el, 2, f, -1, dofs);
+    if (full)
+      for (int64_t c : in.f_cells[f]) entity_dofs(t, el, 3, c, -1, dofs);
+    add_patch(pf, t, el, plain(dofs), in.f_cells[f], mark_col, mark_coef);
+  }
+  out.push_back(std::move(pf));
+  second.push_back(empty_set());
+  // edge-star potentials: one column per NedTwo dof of the edge, of the faces
+  // containing it and (full) of its cells, holding the curl of that function
+  // in the H(div) basis -- the Whitney edge function to the signed Whitney
+  // functions of the faces (Stokes; -1 where the edge is (a, c) of the face
+  // (a, b, c)), a type-I function to the type-II function of the same entity
+  // and index (lem:d-preserves-basis-functions), a gradient to nothing; the
+  // second set couples the same columns to the NedTwo dofs themselves
+  PatchSet pv = empty_set(), p2 = empty_set();
+  auto kind_at = [&](int l, int j) {
+    int kj = KIND_W;
+    for (int kk = 0; kk < 3; ++kk)
+      if (el2.kind_start[3 * l + kk] >= 0 && j >= el2.kind_start[3 * l + kk]) kj = kk;
+    return kj;
+  };
+  for (int64_t e = 0; e < t.n_ent[1]; ++e) {
+    const int64_t a0 = t.ent[1][e * 2], b0 = t.ent[1][e * 2 + 1];
+    std::vector<std::pair<int, int64_t>> ents{{1, e}};
+    for (int64_t f : in.e_faces[e]) ents.push_back({2, f});
+    if (full)
+      for (int64_t c : in.e_cells[e]) ents.push_back({3, c});
+    std::vector<std::vector<std::pair<int32_t, double>>> cols, cols2;
+    for (auto [l, ent] : ents) {
+      const int N2 = el2.per_entity[l];
+      const int64_t base2 = t2.offset[l] + ent * N2;
+      std::vector<int32_t> two;
+      if (l >= 2) entity_dofs(t, el, l, ent, KIND_II, two);
+      size_t nI = 0;
+      for (int j = 0; j < N2; ++j) {
+        cols2.push_back({{int32_t(base2 + j), 1.0}});
+        std::vector<std::pair<int32_t, double>> col;
+        const int kj = kind_at(l, j);
+        if (kj == KIND_W) {
+          for (int64_t f : in.e_faces[e]) {
+            std::vector<int32_t> w;
+            entity_dofs(t, el, 2, f, KIND_W, w);
+            const int64_t *v = t.ent[2].data() + (f * 3);
+            col.push_back({w[0], (a0 == v[0] && b0 == v[2]) ? -1.0 : 1.0});
+          }
+        } else if (kj == KIND_I) {
+          if (nI >= two.size()) throw std::logic_error("type-I potential without a type-II image");
+          col.push_back({two[nI++], 1.0});
+        }
+        cols.push_back(std::move(col));
+      }
+    }
+    add_patch(pv, t, el, cols, in.e_cells[e], mark_col, mark_coef);
+    add_patch(p2, t2, el2, cols2, in.e_cells[e], mark2, mcoef2);
+  }
+  out.push_back(std::move(pv));
+  second.push_back(std::move(p2));
   return out;
 }
 

@@ -82,6 +82,16 @@ inline bool decomposition_full(int dec) {
 }
 std::vector<PatchSet> build_patches(const Topology &top, const RefElement &el, Decomposition dec = DECOMP_PAPER);
 
+// The standard H(div) Hiptmair-Toselli decomposition (eq:pavarino_hiptmair,
+// k = 2; full: without the split): the face stars X^2|star F and the
+// edge-star potentials curl X^1|star E with X^1 = NedTwo (t2, el2: its
+// topology on the same cells and its element, degree p for RT_p and p + 1 for
+// BDM_p).  Returns the two sets; `second` receives, per set, the coupling of
+// its columns to the NedTwo dofs (empty for the face stars), for the
+// regularising mass of eq:local-potential-problem-added-mass.
+std::vector<PatchSet> build_hdiv_hiptmair(const Topology &t, const RefElement &el, const Topology &t2,
+                                          const RefElement &el2, bool full, std::vector<PatchSet> &second);
+
 // Dirichlet boundary (Sec. 5): the dofs of every subsimplex of the marked
 // facets (the facet, its edges and vertices), ascending.  flags: n_cells x
 // (d+1), nonzero (c, j) marks the facet of input cell c (cells_in, the
