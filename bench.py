@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--sweep-mode", choices=["batched", "sequential"], default="batched",
                     help="sweep step: the 18 problems solved one after another, or together as one batch "
                          "(a stream per problem, captured iteration graphs)")
-    ap.add_argument("--workload", choices=["sweep", "multirhs", "mixed", "batch", "decompositions", "hodge"],
+    ap.add_argument("--workload", choices=["sweep", "multirhs", "mixed", "batch", "decompositions", "hodge", "spaces"],
                     default="sweep",
                     help="sweep: the 3D FP64 sweep (default, the headline line); multirhs: H(div) RT_5 on the "
                          "12^3x6 mesh with 64 right-hand sides, one batched solve vs 64 single solves; mixed: "
@@ -57,7 +57,9 @@ def parse():
                          "plain FP64 PCG; batch: 32 uneven "
                          "H(grad)/H(curl) problems solved together vs one by one; decompositions: the default "
                          "split solvers against the vertex-star comparators PAFW(0)(X^k_Gamma)+J and "
-                         "PAFW(0)(X^k) on the sweep mesh (--degrees, default 4,5 for this workload)")
+                         "PAFW(0)(X^k) and the Hiptmair-Toselli forms on the sweep mesh (--degrees, default 4,5 "
+                         "for this workload); hodge: the Hodge Laplacians on the Fichera corner with MINRES; "
+                         "spaces: 2D H(curl)/H(div) and the second-kind 3D spaces")
     ap.add_argument("--batch-count", type=int, default=32)
     ap.add_argument("--batch-max-gb", type=float, default=240.0)
     ap.add_argument("--batch-precision", choices=["fp64", "fp32-pc", "bf16-pc"], default="bf16-pc")
@@ -666,6 +668,63 @@ def cpu_baseline(pc="hybrid"):
             "seconds": t}
 
 
+def spaces_workload(args):
+    """The solve spaces beyond the 3D first kind: 2D H(curl) Ned_p and 2D
+    H(div) RT_p (k = 1, the quarter turn of Ned_p) on the Kuhn mesh of the
+    unit square with 96 cells per edge (18,432 triangles, interior vertices
+    jittered by 0.1 h, mesh seed 2), p = 2, 4, 6, 8, and the second-kind 3D
+    NedTwo_p and BDM_p on the sweep's jittered 8^3x6 mesh, p = 2, 3, 4, 5;
+    load seed 3, FP64 PCG to 1e-10 with the hybrid preconditioner of each
+    space's default decomposition.  Per case: dofs, setup, iterations (flat in
+    p is the paper's robustness claim), solve time and DOF/s."""
+    import torch
+    from paper_2506_17406_amd import rz
+    from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
+    torch.cuda.set_device(0)
+    cases = [("2D", 2, 96, f, p) for f in ("Ned", "RT") for p in (2, 4, 6, 8)] + \
+            [("3D", 3, args.n, f, p) for f in ("NedTwo", "BDM") for p in (2, 3, 4, 5)]
+    meshes, rows, tot_dofs, tot_s = {}, [], 0, 0.0
+    for label, d, n, fam, p in cases:
+        if (d, n) not in meshes:
+            meshes[(d, n)] = kuhn_mesh(n, d, jitter=0.1, seed=2)
+        X, C = meshes[(d, n)]
+        t0 = time.perf_counter()
+        prob = rz.Problem(X, C, p, fam, pc=args.pc)
+        torch.cuda.synchronize()
+        t_set = time.perf_counter() - t0
+        b = torch.from_numpy(load_vectors(prob.n_dofs, 3)[:, 0]).cuda()
+        x = torch.zeros_like(b)
+        for _ in range(args.warmup):
+            x.zero_()
+            prob.solve(b, x, rtol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x.zero_()
+            info = prob.solve(b, x, rtol=1e-10)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        rows.append(dict(mesh=label, space=fam, p=p, dofs=prob.n_dofs, its=info["iterations"],
+                         rel_res=info["rel_residual"], solve_ms=round(dt * 1e3, 3), setup_s=round(t_set, 2),
+                         dofs_per_s=prob.n_dofs / dt))
+        tot_dofs += prob.n_dofs
+        tot_s += dt
+        print(f"{label} {fam}{p}: {prob.n_dofs} dofs, setup {t_set:.2f}s, {info['iterations']} its, "
+              f"{dt * 1e3:.2f} ms, {prob.n_dofs / dt / 1e6:.1f} M DOF/s", file=sys.stderr, flush=True)
+        prob.close()
+        del prob
+        torch.cuda.empty_cache()
+    line = {"metric": "Riesz-map solve DOFs/s to rel. residual 1e-10 (2D and second-kind spaces)",
+            "value": tot_dofs / tot_s, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": tot_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"2D Ned_p / RT_p x p = 2,4,6,8 on the jittered Kuhn 96^2x2 mesh and 3D NedTwo_p "
+                                   f"/ BDM_p x p = 2..5 on the jittered Kuhn {args.n}^3x6 mesh, rtol 1e-10, "
+                                   f"{args.pc} preconditioner", "preconditioner": args.pc},
+            "cases": rows}
+    print(json.dumps(line), flush=True)
+
+
 def hodge(args):
     """Hodge Laplacians (Sec. 7.2, eq:hodge-laplace) on the Freudenthal mesh
     of the Fichera corner (0,1)^3 minus [1/2,1)^3 with 8 cells per edge
@@ -739,6 +798,8 @@ def main():
         return batch_workload(args)
     if args.workload == "hodge":
         return hodge(args)
+    if args.workload == "spaces":
+        return spaces_workload(args)
     if args.workload == "decompositions":
         return decompositions(args)
     import torch
