@@ -361,6 +361,24 @@ struct Space {
   PolyBasis poly;
   Dense B;  // (c * poly.n) x m, orthonormal columns
 
+  // values (npts x c x c n) and jacobians of the primal basis e_comp (x) q_b
+  // itself (the columns of the identity): the basis values put in place
+  void field_primal(const double *x, int npts, std::vector<double> &vals, std::vector<double> &jac) const {
+    const int n = poly.n, m = c * n;
+    std::vector<double> V(size_t(npts) * n), G(size_t(npts) * std::max(l, 1) * n);
+    poly.eval(x, npts, V.data(), l > 0 ? G.data() : nullptr);
+    vals.assign(size_t(npts) * c * m, 0.0);
+    jac.assign(size_t(npts) * c * std::max(l, 1) * m, 0.0);
+    for (int t = 0; t < npts; ++t)
+      for (int comp = 0; comp < c; ++comp)
+        for (int b = 0; b < n; ++b) {
+          const int j = comp * n + b;
+          vals[(size_t(t) * c + comp) * m + j] = V[size_t(t) * n + b];
+          for (int a = 0; a < l; ++a)
+            jac[((size_t(t) * c + comp) * l + a) * m + j] = G[(size_t(t) * l + a) * n + b];
+        }
+  }
+
   // values (npts x c x m) and jacobians (npts x c x l x m) of columns of coef
   void field(const double *x, int npts, const Dense &coef, std::vector<double> &vals,
              std::vector<double> &jac) const {
@@ -809,7 +827,6 @@ DualBasis dual_basis(int d, Family fam, int p, RefElement *el) {
   const int k = form_of(fam);
   auto sp = make_space(d, fam, p);
   const int c = sp->c, nfull = sp->B.r;
-  Dense full = Dense::eye(nfull);
   std::vector<std::vector<double>> rows;
   RefElement scratch;
   RefElement &E = el ? *el : scratch;
@@ -826,7 +843,7 @@ DualBasis dual_basis(int d, Family fam, int p, RefElement *el) {
       std::vector<double> x = (l == 0) ? em.origin : map_points(em, q, d);
       const int nq = q.size();
       std::vector<double> vals, jac;
-      sp->field(x.data(), nq, full, vals, jac);
+      sp->field_primal(x.data(), nq, vals, jac);  // the functionals act on the primal basis
       int count = 0;
       auto add_row = [&](const std::vector<double> &fn, const std::vector<double> &tr, int ct, int j) {
         // fn: (nq x ct) test values; tr: (nq x ct x nfull)
@@ -839,6 +856,22 @@ DualBasis dual_basis(int d, Family fam, int p, RefElement *el) {
           }
         rows.push_back(row);
         (void)j;
+      };
+      // the rows of the N functionals (d_S psi_j, tr)_S of one eigenbasis, on
+      // host threads (each row's sums run in the same order as add_row's)
+      auto add_rows = [&](const std::vector<double> &dpsi, int N, const std::vector<double> &tr, int ct) {
+        std::vector<std::vector<double>> blk(N);
+        parallel_for(N, [&](int j) {
+          std::vector<double> row(nfull, 0.0);
+          for (int t = 0; t < nq; ++t)
+            for (int a = 0; a < ct; ++a) {
+              const double wv = q.w[t] * dpsi[(size_t(t) * ct + a) * N + j];
+              const double *tv = tr.data() + ((size_t(t) * ct + a) * nfull);
+              for (int b = 0; b < nfull; ++b) row[b] += wv * tv[b];
+            }
+          blk[j] = std::move(row);
+        });
+        for (auto &r : blk) rows.push_back(std::move(r));
       };
       if (l == k) {  // Whitney moment (1, tr v)_S (a point value when k = 0)
         std::vector<double> tr;
@@ -861,11 +894,8 @@ DualBasis dual_basis(int d, Family fam, int p, RefElement *el) {
         int ct;
         trace(k + 1, em.A, nq, dcomp(k, d), nfull, dv, trdv, ct);
         if (ei == 0 && eb->N) E.kind_start[3 * l + KIND_I] = count;
+        add_rows(dpsi, eb->N, trdv, ct);
         for (int j = 0; j < eb->N; ++j) {
-          std::vector<double> fn(size_t(nq) * ct);
-          for (int t = 0; t < nq; ++t)
-            for (int a = 0; a < ct; ++a) fn[size_t(t) * ct + a] = dpsi[(size_t(t) * ct + a) * eb->N + j];
-          add_row(fn, trdv, ct, j);
           E.dofs.push_back({l, ei, KIND_I, j});
           ++count;
         }
@@ -880,11 +910,8 @@ DualBasis dual_basis(int d, Family fam, int p, RefElement *el) {
         int ct;
         trace(k, em.A, nq, c, nfull, vals, tr, ct);
         if (ei == 0 && eb->N) E.kind_start[3 * l + KIND_II] = count;
+        add_rows(dpsi, eb->N, tr, ct);
         for (int j = 0; j < eb->N; ++j) {
-          std::vector<double> fn(size_t(nq) * ct);
-          for (int t = 0; t < nq; ++t)
-            for (int a = 0; a < ct; ++a) fn[size_t(t) * ct + a] = dpsi[(size_t(t) * ct + a) * eb->N + j];
-          add_row(fn, tr, ct, j);
           E.dofs.push_back({l, ei, KIND_II, j});
           ++count;
         }
@@ -1014,7 +1041,7 @@ std::vector<double> derivative_reference(int d, Family from, Family to, int p) {
   if (cd != dbb.sp->c) throw std::runtime_error("derivative_reference: component mismatch");
   const int nfull = dbb.sp->B.r;
   std::vector<double> pv, pj;
-  dbb.sp->field(q.x.data(), nq, Dense::eye(nfull), pv, pj);  // primal basis values (nq x c x nfull)
+  dbb.sp->field_primal(q.x.data(), nq, pv, pj);  // primal basis values (nq x c x nfull)
   Dense proj(nfull, na);
   for (int t = 0; t < nq; ++t)
     for (int a = 0; a < cd; ++a) {
