@@ -1403,44 +1403,54 @@ __global__ __launch_bounds__(64 * (MPMAX / 16)) void k_patch_mfma(
     for (int kb = 0; kb < KBMAX; ++kb)
       if (kb < KB) a[kb] = Af[kb * 64];
   }
-  // gather: thread t takes patch column k = t % MP and the 16 columns of
-  // group t / MP (4 MP = the block's threads), its map entries loaded once
-  // and the 16 right-hand side values read as one dof-major row piece
-  {
+  // gather of the right-hand sides into the B fragments
+  if constexpr (!BF && !F32) {
+    // FP64: thread t takes patch column k = t % MP and the 16 columns of
+    // group t / MP (4 MP = the block's threads), its map entries loaded once
+    // and the 16 right-hand side values read as one dof-major row piece (at
+    // the occupancy the FP64 A fragments leave, one map chain per thread
+    // beats the coalesced form below)
     const int t = threadIdx.x;
     const int k = t % MP, cg = t / MP;
-    double v[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = 0.0;
-    if (cg < 4 && k < m) {
-      for (int64_t e = col_ent[cb + k]; e < col_ent[cb + k + 1]; ++e) {
-        const double *row = rt + int64_t(ent_a[e]) * NC + c0 + 16 * cg;
-        const double cf = ent_coef[e];
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (c0 + 16 * cg + j < ncol) v[j] += cf * row[j];
-      }
-    }
     if (cg < 4) {
+      double v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = 0.0;
+      if (k < m)
+        for (int64_t e = col_ent[cb + k]; e < col_ent[cb + k + 1]; ++e) {
+          const double *row = rt + int64_t(ent_a[e]) * NC + c0 + 16 * cg;
+          const double cf = ent_coef[e];
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (c0 + 16 * cg + j < ncol) v[j] += cf * row[j];
+        }
+      double *dst = Rd + ((k >> 2) * 4 + cg) * 68 + (k & 3) * 17;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) dst[j] = v[j];
+    }
+  } else {
+    // FP32 and bfloat16: 16 lanes take 16 consecutive columns of one patch
+    // row k (the row's four column groups on the wave's four 16-lane groups:
+    // one 512-byte piece of a dof-major row of rt per wave and map entry);
+    // the block's MPMAX / 4 lane groups step over the MP x 4 (row, group)
+    // pairs
+    const int cl = threadIdx.x & 15;
+    for (int q = threadIdx.x >> 4; q < 4 * MP; q += MPMAX / 4) {
+      const int k = q >> 2, cg = q & 3;
+      const int c = c0 + 16 * cg + cl;
+      double v = 0.0;
+      if (k < m && c < ncol)
+        for (int64_t e = col_ent[cb + k]; e < col_ent[cb + k + 1]; ++e)
+          v += ent_coef[e] * rt[int64_t(ent_a[e]) * NC + c];
       if constexpr (F32) {
-        float *dst = Rf + ((k >> 2) * 4 + cg) * 68 + (k & 3) * 17;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) dst[j] = float(v[j]);
-      } else if constexpr (!BF) {
-        double *dst = Rd + ((k >> 2) * 4 + cg) * 68 + (k & 3) * 17;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) dst[j] = v[j];
+        Rf[((k >> 2) * 4 + cg) * 68 + (k & 3) * 17 + cl] = float(v);
       } else {
         const int kb = k >> 5, kk = k & 31;
-        const int u = ((kb * 4 + cg) * 68 + (kk >> 3) * 17) * 8 + (kk & 7);
-        const int lo = KB * 4 * 68 * 8;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const float vf = float(v[j]);
-          const uint16_t hi = bf16_bits(vf);
-          Rh[u + 8 * j] = hi;
-          Rh[lo + u + 8 * j] = bf16_bits(vf - __uint_as_float(uint32_t(hi) << 16));
-        }
+        const int u = ((kb * 4 + cg) * 68 + (kk >> 3) * 17) * 8 + (kk & 7) + 8 * cl;
+        const float vf = float(v);
+        const uint16_t hi = bf16_bits(vf);
+        Rh[u] = hi;
+        Rh[KB * 4 * 68 * 8 + u] = bf16_bits(vf - __uint_as_float(uint32_t(hi) << 16));
       }
     }
   }
@@ -1452,7 +1462,10 @@ __global__ __launch_bounds__(64 * (MPMAX / 16)) void k_patch_mfma(
   const int lu = (lane >> 4) * 17 + (lane & 15);
 #pragma unroll
   for (int kb = 0; kb < KBMAX; ++kb) {
-    if (kb >= KB) break;
+    // a guarded body, not a break: the loop then unrolls fully and a[] stays
+    // in registers (with the early exit the FP64 instances above 64 dofs
+    // kept a[] in scratch, each fragment load waiting for its store)
+    if (kb < KB)
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
       if constexpr (F32) {
@@ -1484,8 +1497,12 @@ __global__ __launch_bounds__(64 * (MPMAX / 16)) void k_patch_mfma(
 
 // z[c][d] += scale sum_e coef_e zb[pr_e * NC + c] over the dofs d of a
 // patch set (ascending), entries in a fixed order: a 64-dof x 64-column
-// tile per block, the dof sums read along zb rows into LDS, then added to z
-// along columns
+// tile per block, the dof sums staged in LDS as tile[column][dof], then
+// added to z along columns.  FP64 entries: a wave sums one dof at a time
+// with its lanes along the 64 columns (one coalesced 512-byte piece of a zb
+// row per entry).  FP32 entries: a thread sums one dof over 16 columns
+// (one 64-byte row piece per entry; with half the bytes per entry the
+// dependent map loads of the coalesced form cost more than they save).
 template <typename Z>
 __global__ __launch_bounds__(256) void k_patch_zb_scatter(int64_t nd, const int32_t *__restrict__ dof,
                                                           const int64_t *__restrict__ ptr,
@@ -1498,26 +1515,39 @@ __global__ __launch_bounds__(256) void k_patch_zb_scatter(int64_t nd, const int3
   const int64_t a0 = int64_t(blockIdx.x) * 64;
   const int c0 = blockIdx.y * 64;
   const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t a = a0 + t;
-  double v[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = 0.0;
-  if (a < nd)
-    for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) {
-      const Z *row = zb + int64_t(pr[e]) * NC + c0 + 16 * w;
-      const double cf = coef[e];
-#pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (c0 + 16 * w + j < ncol) v[j] += cf * double(row[j]);
+  if constexpr (sizeof(Z) == 8) {
+    const int c = c0 + t;
+#pragma unroll 4
+    for (int i = w; i < 64; i += 4) {
+      const int64_t a = a0 + i;
+      double v = 0.0;
+      if (a < nd && c < ncol)
+        for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) v += coef[e] * double(zb[int64_t(pr[e]) * NC + c]);
+      tile[t][i] = v;
     }
+  } else {
+    const int64_t a = a0 + t;
+    double v[16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) tile[16 * w + j][t] = v[j];
+    for (int j = 0; j < 16; ++j) v[j] = 0.0;
+    if (a < nd)
+      for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) {
+        const Z *row = zb + int64_t(pr[e]) * NC + c0 + 16 * w;
+        const double cf = coef[e];
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (c0 + 16 * w + j < ncol) v[j] += cf * double(row[j]);
+      }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) tile[16 * w + j][t] = v[j];
+  }
   __syncthreads();
+  const int64_t a = a0 + t;
   if (a >= nd) return;
   const int64_t d = dof[a];
-  for (int c = w; c < 64; c += 4) {
-    const int cc = c0 + c;
-    if (cc < ncol && !(st && st[cc].done)) z[int64_t(cc) * ldz + d] += scale * tile[c][t];
+  for (int cc = w; cc < 64; cc += 4) {
+    const int col = c0 + cc;
+    if (col < ncol && !(st && st[col].done)) z[int64_t(col) * ldz + d] += scale * tile[cc][t];
   }
 }
 
