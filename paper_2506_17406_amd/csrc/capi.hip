@@ -2052,6 +2052,22 @@ void rz_batch_destroy(rz_batch *B) { delete B; }
 // P_{p-1} on the reference cell pulled back as a 3-form (psi_hat / det J), so
 // M_3 is diagonal, 1 / |det J_T| per cell: it is folded into the rows of D
 // (the stored matrix is M_3 D), and gamma^{-1} M_3 is inverted exactly.
+namespace {
+// Entries of a reference derivative matrix at or below 1e-12 of its largest
+// are taken as round-off of exact zeros and left out of the stored CSR
+// (lem:d-preserves-basis-functions makes the gradient matrix the signed
+// vertex-edge incidence plus an identity, yet its computed zeros fill the
+// rest of the matrix at 1e-16..1e-13; the curl and divergence matrices
+// carry round-off up to 1e-12 from p = 6 on, below the tables' own
+// accuracy).  Dropping them changes a row of D x by at most 1e-12 max|D_hat|
+// times the sum of |x| over the dropped columns.
+double drop_tol(const std::vector<double> &Dh) {
+  double mx = 0.0;
+  for (double v : Dh) mx = std::max(mx, std::fabs(v));
+  return 1e-12 * mx;
+}
+}  // namespace
+
 struct rz_hodge {
   rz_problem *P0 = nullptr, *P1 = nullptr;
   int k = 1, p = 1, max_iter = 1000;
@@ -2061,6 +2077,7 @@ struct rz_hodge {
   const int64_t *dp = nullptr, *dtp = nullptr;
   const int32_t *dc = nullptr, *dtc = nullptr;
   const double *dv = nullptr, *dtv = nullptr;
+  int d_lanes = 1, dt_lanes = 1;  // lanes per row of the two SpMVs
   std::vector<void *> mem;
   double *t2 = nullptr, *m2 = nullptr;  // 2 n1 each: [D sigma, u] and their X^k masses
   double *dg_inv = nullptr;            // k = 3: gamma |det J_T| per DG dof
@@ -2095,18 +2112,18 @@ int hodge_apply(rz_hodge *H, const double *x, double *y, hipStream_t s) {
   const double *sg = x, *u = x + n0;
   double *y0 = y, *y1 = y + n0;
   if (H->k == 3) {
-    rz::launch_csr_spmv(n1, H->dp, H->dc, H->dv, sg, y1, 1.0, false, s);                   // M_3 D sigma
+    rz::launch_csr_spmv(n1, H->dp, H->dc, H->dv, sg, y1, 1.0, false, H->d_lanes, s);                 // M_3 D sigma
     rz::launch_apply_A(H->tM0, sg, n0, y0, n0, 1, nullptr, s, false, 0, -1, -1.0, 0, 0, true);  // -M sigma
-    rz::launch_csr_spmv(n0, H->dtp, H->dtc, H->dtv, u, y0, 1.0, true, s);                 // + (M_3 D)^T u
+    rz::launch_csr_spmv(n0, H->dtp, H->dtc, H->dtv, u, y0, 1.0, true, H->dt_lanes, s);               // + (M_3 D)^T u
     return RZ_OK;
   }
-  rz::launch_csr_spmv(n1, H->dp, H->dc, H->dv, sg, H->t2, 1.0, false, s);              // D sigma
+  rz::launch_csr_spmv(n1, H->dp, H->dc, H->dv, sg, H->t2, 1.0, false, H->d_lanes, s);              // D sigma
   HIPCHK(hipMemcpyAsync(H->t2 + n1, u, size_t(n1) * 8, hipMemcpyDeviceToDevice, s));   // u
   rz::launch_apply_A(H->tM1, H->t2, n1, H->m2, n1, 2, nullptr, s, false, 0, -1, 1.0, 0, 0, true);
   rz::launch_apply_A(H->tK1, u, n1, y1, n1, 1, nullptr, s, false, 0, -1, 1.0, 0, 0, true);  // K u
   rz::launch_lincomb3(n1, 1.0, y1, 1.0, H->m2, 0.0, nullptr, y1, s);                    // + M D sigma
   rz::launch_apply_A(H->tM0, sg, n0, y0, n0, 1, nullptr, s, false, 0, -1, -1.0, 0, 0, true);  // -M sigma
-  rz::launch_csr_spmv(n0, H->dtp, H->dtc, H->dtv, H->m2 + n1, y0, 1.0, true, s);        // + D^T M u
+  rz::launch_csr_spmv(n0, H->dtp, H->dtc, H->dtv, H->m2 + n1, y0, 1.0, true, H->dt_lanes, s);        // + D^T M u
   return RZ_OK;
 }
 
@@ -2226,19 +2243,21 @@ int rz_hodge_setup(const rz_mesh *m, int32_t degree, int32_t k, double gamma, co
       // commute with d); entries shared by cells coincide
       const rz::Family f0 = k == 1 ? rz::FAM_CG : rz::FAM_NED, f1 = k == 1 ? rz::FAM_NED : rz::FAM_RT;
       const std::vector<double> Dh = rz::derivative_reference(3, f0, f1, degree);
+      const double tol = drop_tol(Dh);
       const int nb = P1->el.n;
       ent.reserve(size_t(nc) * nb * 4);
       for (int64_t c = 0; c < nc; ++c)
         for (int i = 0; i < nb; ++i)
           for (int j = 0; j < na; ++j) {
             const double v = Dh[size_t(i) * na + j];
-            if (v == 0.0) continue;
+            if (std::fabs(v) <= tol) continue;
             ent.push_back({int64_t(P1->top.cell_dofs[c * nb + i]) * H->n0 + P0->top.cell_dofs[c * na + j], v});
           }
     } else {
       // DG_{p-1}: cell c owns dofs c * nb .. c * nb + nb - 1; the stored
       // matrix is M_3 D, row (c, i) = D_hat row i / |det J_c|
       const std::vector<double> Dh = rz::divergence_reference_dg(3, degree);
+      const double tol = drop_tol(Dh);
       const int nb = int(Dh.size() / size_t(na));
       H->n1 = nc * nb;
       std::vector<double> Ve(12);
@@ -2263,7 +2282,7 @@ int rz_hodge_setup(const rz_mesh *m, int32_t degree, int32_t k, double gamma, co
           inv[size_t(c) * nb + i] = gamma * dj;
           for (int j = 0; j < na; ++j) {
             const double val = Dh[size_t(i) * na + j];
-            if (val == 0.0) continue;
+            if (std::fabs(val) <= tol) continue;
             ent.push_back({(c * nb + i) * H->n0 + P0->top.cell_dofs[c * na + j], val / dj});
           }
         }
@@ -2296,6 +2315,14 @@ int rz_hodge_setup(const rz_mesh *m, int32_t degree, int32_t k, double gamma, co
     std::vector<int64_t> ptr;
     std::vector<int32_t> col;
     std::vector<double> val;
+    // lanes per row from the mean row length (the SpMV sums a row's entries
+    // lane-strided and reduces them across the lanes)
+    auto lanes = [](int64_t nnz, int64_t rows) {
+      const double avg = rows > 0 ? double(nnz) / double(rows) : 0.0;
+      return avg < 3.0 ? 1 : avg < 12.0 ? 4 : avg < 48.0 ? 16 : 64;
+    };
+    H->d_lanes = lanes(int64_t(keys.size()), H->n1);
+    H->dt_lanes = lanes(int64_t(keys.size()), H->n0);
     csr(false, ptr, col, val);
     H->dp = H->upload(ptr);
     H->dc = H->upload(col);

@@ -2271,14 +2271,22 @@ void launch_patch_apply(const PatchApply &pa, const double *r, int64_t ldr, doub
 
 // ---- Hodge Laplacians: the exterior derivative as CSR, weight scaling,
 // MINRES vector kernels
-// y = alpha A x (+ y when accumulate), A in CSR (one thread per row)
-__global__ void k_csr_spmv(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                           const double *__restrict__ val, const double *__restrict__ x, double *__restrict__ y,
-                           double alpha, int accumulate) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+// y = alpha A x (+ y when accumulate), A in CSR: L lanes per row, lane j
+// summing entries j, j + L, ... of the row, then a butterfly over the L
+// lanes (a fixed order for a given L)
+template <int L>
+__global__ __launch_bounds__(256) void k_csr_spmv(int64_t n, const int64_t *__restrict__ ptr,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                  const double *__restrict__ x, double *__restrict__ y, double alpha,
+                                                  int accumulate) {
+  const int sub = int(threadIdx.x) & (L - 1);
+  const int64_t step = int64_t(gridDim.x) * (blockDim.x / L);
+  for (int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / L; i < n; i += step) {
     double v = 0.0;
-    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) v += val[e] * x[col[e]];
-    y[i] = accumulate ? y[i] + alpha * v : alpha * v;
+    for (int64_t e = ptr[i] + sub; e < ptr[i + 1]; e += L) v += val[e] * x[col[e]];
+#pragma unroll
+    for (int o = L / 2; o > 0; o /= 2) v += __shfl_xor(v, o, L);
+    if (sub == 0) y[i] = accumulate ? y[i] + alpha * v : alpha * v;
   }
 }
 
@@ -2319,10 +2327,15 @@ __global__ __launch_bounds__(256) void k_dot_part(int64_t n, const double *__res
 }
 
 void launch_csr_spmv(int64_t n, const int64_t *ptr, const int32_t *col, const double *val, const double *x,
-                     double *y, double alpha, bool accumulate, hipStream_t s) {
+                     double *y, double alpha, bool accumulate, int lanes, hipStream_t s) {
   if (n <= 0) return;
-  const unsigned g = unsigned(std::min<int64_t>((n + 255) / 256, 8192));
-  hipLaunchKernelGGL(k_csr_spmv, dim3(g), dim3(256), 0, s, n, ptr, col, val, x, y, alpha, accumulate ? 1 : 0);
+  const int L = lanes >= 64 ? 64 : lanes >= 16 ? 16 : lanes >= 4 ? 4 : 1;
+  const unsigned g = unsigned(std::min<int64_t>((n * L + 255) / 256, 8192));
+  const int acc = accumulate ? 1 : 0;
+  if (L == 64) hipLaunchKernelGGL(k_csr_spmv<64>, dim3(g), dim3(256), 0, s, n, ptr, col, val, x, y, alpha, acc);
+  else if (L == 16) hipLaunchKernelGGL(k_csr_spmv<16>, dim3(g), dim3(256), 0, s, n, ptr, col, val, x, y, alpha, acc);
+  else if (L == 4) hipLaunchKernelGGL(k_csr_spmv<4>, dim3(g), dim3(256), 0, s, n, ptr, col, val, x, y, alpha, acc);
+  else hipLaunchKernelGGL(k_csr_spmv<1>, dim3(g), dim3(256), 0, s, n, ptr, col, val, x, y, alpha, acc);
 }
 void launch_scale_weights(int64_t nc, int Q, int qm, const double *w, double smass, double sderiv, double *out,
                           hipStream_t s) {

@@ -161,11 +161,12 @@ struct PatchApply {
 // bfloat16, 2 FP32
 int64_t frag_size(int m, int kind);
 void launch_seg_to_frag(const PatchApply &pa, int kind, void *frag, const int64_t *frag_off, hipStream_t s);
-// ---- Hodge Laplacians (Sec. 7.2): y = alpha A x (+ y), A in CSR; weights
-// w[c, q] scaled by smass for q < qm (the mass family) and sderiv after;
-// out = a x + b y + c z (null: zero); per-block partials of a . b
+// ---- Hodge Laplacians (Sec. 7.2): y = alpha A x (+ y), A in CSR with
+// `lanes` (1, 4, 16 or 64) lanes per row; weights w[c, q] scaled by smass
+// for q < qm (the mass family) and sderiv after; out = a x + b y + c z
+// (null: zero); per-block partials of a . b
 void launch_csr_spmv(int64_t n, const int64_t *ptr, const int32_t *col, const double *val, const double *x,
-                     double *y, double alpha, bool accumulate, hipStream_t s);
+                     double *y, double alpha, bool accumulate, int lanes, hipStream_t s);
 void launch_scale_weights(int64_t nc, int Q, int qm, const double *w, double smass, double sderiv, double *out,
                           hipStream_t s);
 void launch_lincomb3(int64_t n, double a, const double *x, double b, const double *y, double c, const double *z,
