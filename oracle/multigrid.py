@@ -52,10 +52,21 @@ def kuhn_hierarchy(n):
     return out
 
 
-def _kuhn_unit(n):
+def _kuhn_unit(n, d=3):
     # the unperturbed Kuhn mesh with the vertex numbering of the workloads
     h = 1.0 / n
     g = np.arange(n + 1)
+    if d == 2:
+        J, I = np.meshgrid(g, g, indexing="ij")
+        X = np.stack([I.ravel(), J.ravel()], axis=1) * h
+        vid = lambda i, j: i + (n + 1) * j
+        cells = []
+        for j in range(n):
+            for i in range(n):
+                corner = lambda b: vid(i + (b & 1), j + ((b >> 1) & 1))
+                cells.append([corner(0), corner(1), corner(3)])
+                cells.append([corner(0), corner(2), corner(3)])
+        return X.astype(float), np.asarray(cells, dtype=np.int64)
     K, J, I = np.meshgrid(g, g, g, indexing="ij")
     X = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1) * h
     vid = lambda i, j, k: i + (n + 1) * (j + (n + 1) * k)
@@ -71,9 +82,10 @@ def _kuhn_unit(n):
 
 
 def _barycentric(Xc):
-    """Barycentric coordinates lam(x) = L @ [x, 1] of a tetrahedron and their
-    (constant) gradients (rows of L[:, :3])."""
-    M = np.vstack([Xc.T, np.ones(4)])
+    """Barycentric coordinates lam(x) = L @ [x, 1] of a simplex (d + 1
+    vertices in d dimensions) and their (constant) gradients (rows of
+    L[:, :d])."""
+    M = np.vstack([Xc.T, np.ones(len(Xc))])
     L = np.linalg.inv(M)
     return L
 
@@ -81,8 +93,9 @@ def _barycentric(Xc):
 def _whitney_value(k, L, verts, x):
     """The Whitney k-form of the local vertex tuple `verts` (ascending coarse
     ids) of a cell with barycentric matrix L, at the point x."""
-    lam = L[:, :3] @ x + L[:, 3]
-    g = L[:, :3]
+    d = L.shape[0] - 1
+    lam = L[:, :d] @ x + L[:, d]
+    g = L[:, :d]
     if k == 0:
         return lam[verts[0]]
     if k == 1:
@@ -93,32 +106,34 @@ def _whitney_value(k, L, verts, x):
     return 2.0 * (lam[a] * cr(g[b], g[c]) + lam[b] * cr(g[c], g[a]) + lam[c] * cr(g[a], g[b]))
 
 
-def whitney_prolongation(nc, k):
-    """Sparse P (n_W(fine) x n_W(coarse)) from W^k on the Kuhn mesh with nc
-    cells per edge to W^k on the mesh with 2 nc, both in the entity order of
-    their topologies (lowest-order elements: their dofs are the Whitney
-    dofs)."""
+def whitney_prolongation(nc, k, d=3):
+    """Sparse P (n_W(fine) x n_W(coarse)) from W^k on the Kuhn mesh of
+    [0,1]^d with nc cells per edge to W^k on the mesh with 2 nc, both in the
+    entity order of their topologies (lowest-order elements: their dofs are
+    the Whitney dofs).  In 2D, k = 1 is the H(curl) form; the 2D H(div)
+    Whitney functions are its quarter turns, with the same coefficients."""
     fam = {0: "CG", 1: "Ned", 2: "RT"}[k]
-    el = element(3, fam, 1)
-    Xc, Cc = _kuhn_unit(nc)
-    Xf, Cf = _kuhn_unit(2 * nc)
+    el = element(d, fam, 1)
+    Xc, Cc = _kuhn_unit(nc, d)
+    Xf, Cf = _kuhn_unit(2 * nc, d)
     tc, tf = Topology(Xc, Cc, el), Topology(Xf, Cf, el)
-    cid = [{tuple(t): e for e, t in enumerate(tc.ent_tuples[l])} for l in range(4)]
+    cid = [{tuple(t): e for e, t in enumerate(tc.ent_tuples[l])} for l in range(d + 1)]
     Lall = np.array([_barycentric(Xc[tc.cells[c]]) for c in range(tc.n_cells)])
+    per = 6 if d == 3 else 2                       # Kuhn cells per cube (square)
     rows, cols, vals = [], [], []
     for e, tup in enumerate(tf.ent_tuples[k]):
         xe = Xf[list(tup)]
         xb = xe.mean(axis=0)
         cube = np.minimum((xb * nc).astype(int), nc - 1)
-        base = 6 * (cube[0] + nc * (cube[1] + nc * cube[2]))
+        base = per * (cube[0] + nc * (cube[1] + (nc * cube[2] if d == 3 else 0)))
         # the coarse cell of the cube in which x_b has the largest smallest
         # barycentric coordinate (the one containing it)
-        lam = np.einsum("cij,j->ci", Lall[base:base + 6, :, :3], xb) + Lall[base:base + 6, :, 3]
-        c6 = int(np.argmax(lam.min(axis=1)))
-        best, L, cell = lam[c6].min(), Lall[base + c6], base + c6
+        lam = np.einsum("cij,j->ci", Lall[base:base + per, :, :d], xb) + Lall[base:base + per, :, d]
+        cp = int(np.argmax(lam.min(axis=1)))
+        best, L, cell = lam[cp].min(), Lall[base + cp], base + cp
         assert best > -1e-12, "fine entity outside its coarse cube"
         gv = tc.cells[cell]                        # ascending coarse vertex ids of the cell
-        for loc in combinations(range(4), k + 1):
+        for loc in combinations(range(d + 1), k + 1):
             glob = tuple(int(gv[a]) for a in loc)
             if k == 0:
                 v = _whitney_value(0, L, loc, xe[0])
@@ -185,17 +200,16 @@ class Smoother:
 
 class WhitneyMultigrid:
     """Symmetric V-cycle on W^k for the Whitney block AW of a problem on the
-    Kuhn mesh with n cells per edge (its dofs in the entity order of the
-    k-entities)."""
+    Kuhn mesh of [0,1]^d with n cells per edge (its dofs in the entity order
+    of the k-entities; k = 1 in 2D serves H(curl) and H(div) alike)."""
 
-    def __init__(self, AW, n, k, nu=NU):
+    def __init__(self, AW, n, k, nu=NU, d=3):
         self.k, self.nu = k, nu
         self.ns = kuhn_hierarchy(n)
-        el = element(3, {0: "CG", 1: "Ned", 2: "RT"}[k], 1)
         self.A, self.P, self.S, self.omega = [sp.csr_matrix(AW)], [], [], []
         tops = []
         for l, nl in enumerate(self.ns[:-1]):
-            P, tc, tf = whitney_prolongation(nl // 2, k)
+            P, tc, tf = whitney_prolongation(nl // 2, k, d)
             assert P.shape[0] == self.A[l].shape[0]
             self.P.append(P)
             tops.append(tf)

@@ -438,7 +438,7 @@ class AdditiveSchwarz:
             if len(self.removed):
                 raise ValueError("the multigrid coarse solver is built for pure Neumann problems")
             from .multigrid import WhitneyMultigrid
-            self.mg = WhitneyMultigrid(A[self.W][:, self.W], coarse_mg, k)
+            self.mg = WhitneyMultigrid(A[self.W][:, self.W], coarse_mg, k, d=top.el.d)
             self.coarse = None
         else:
             AW = A[self.W][:, self.W].toarray()
