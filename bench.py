@@ -676,20 +676,31 @@ def spaces_workload(args):
     NedTwo_p and BDM_p on the sweep's jittered 8^3x6 mesh, p = 2, 3, 4, 5;
     load seed 3, FP64 PCG to 1e-10 with the hybrid preconditioner of each
     space's default decomposition.  Per case: dofs, setup, iterations (flat in
-    p is the paper's robustness claim), solve time and DOF/s."""
+    p is the paper's robustness claim), solve time and DOF/s.  The 2D cases
+    run twice: with the exact coarse solve (in the value) and with the W^1
+    V-cycle over the Kuhn meshes 96, 48, 24, 12, 6, 3 (reported beside)."""
     import torch
     from paper_2506_17406_amd import rz
     from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
     torch.cuda.set_device(0)
-    cases = [("2D", 2, 96, f, p) for f in ("Ned", "RT") for p in (2, 4, 6, 8)] + \
-            [("3D", 3, args.n, f, p) for f in ("NedTwo", "BDM") for p in (2, 3, 4, 5)]
-    meshes, rows, tot_dofs, tot_s = {}, [], 0, 0.0
-    for label, d, n, fam, p in cases:
+    cases = [("2D", 2, 96, f, p, c) for f in ("Ned", "RT") for p in (2, 4, 6, 8) for c in ("exact", "mg")] + \
+            [("3D", 3, args.n, f, p, "exact") for f in ("NedTwo", "BDM") for p in (2, 3, 4, 5)]
+    meshes, rows, rows_mg, tot_dofs, tot_s = {}, [], [], 0, 0.0
+
+    def hierarchy(n, d):
+        out = [kuhn_mesh(n, d)]
+        while n % 2 == 0 and n > 1:
+            n //= 2
+            out.append(kuhn_mesh(n, d))
+        return out
+
+    for label, d, n, fam, p, coarse in cases:
         if (d, n) not in meshes:
             meshes[(d, n)] = kuhn_mesh(n, d, jitter=0.1, seed=2)
         X, C = meshes[(d, n)]
         t0 = time.perf_counter()
-        prob = rz.Problem(X, C, p, fam, pc=args.pc)
+        prob = rz.Problem(X, C, p, fam, pc=args.pc, coarse=coarse,
+                          mg_meshes=hierarchy(n, d) if coarse == "mg" else None)
         torch.cuda.synchronize()
         t_set = time.perf_counter() - t0
         b = torch.from_numpy(load_vectors(prob.n_dofs, 3)[:, 0]).cuda()
@@ -704,12 +715,15 @@ def spaces_workload(args):
             info = prob.solve(b, x, rtol=1e-10)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
-        rows.append(dict(mesh=label, space=fam, p=p, dofs=prob.n_dofs, its=info["iterations"],
-                         rel_res=info["rel_residual"], solve_ms=round(dt * 1e3, 3), setup_s=round(t_set, 2),
-                         dofs_per_s=prob.n_dofs / dt))
-        tot_dofs += prob.n_dofs
-        tot_s += dt
-        print(f"{label} {fam}{p}: {prob.n_dofs} dofs, setup {t_set:.2f}s, {info['iterations']} its, "
+        (rows if coarse == "exact" else rows_mg).append(
+            dict(mesh=label, space=fam, p=p, coarse=coarse, dofs=prob.n_dofs, its=info["iterations"],
+                 rel_res=info["rel_residual"], solve_ms=round(dt * 1e3, 3), setup_s=round(t_set, 2),
+                 dofs_per_s=prob.n_dofs / dt))
+        if coarse == "exact":
+            tot_dofs += prob.n_dofs
+            tot_s += dt
+        print(f"{label} {fam}{p}{' +mg' if coarse == 'mg' else ''}: {prob.n_dofs} dofs, setup {t_set:.2f}s, "
+              f"{info['iterations']} its, "
               f"{dt * 1e3:.2f} ms, {prob.n_dofs / dt / 1e6:.1f} M DOF/s", file=sys.stderr, flush=True)
         prob.close()
         del prob
@@ -720,8 +734,9 @@ def spaces_workload(args):
             "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"2D Ned_p / RT_p x p = 2,4,6,8 on the jittered Kuhn 96^2x2 mesh and 3D NedTwo_p "
                                    f"/ BDM_p x p = 2..5 on the jittered Kuhn {args.n}^3x6 mesh, rtol 1e-10, "
-                                   f"{args.pc} preconditioner", "preconditioner": args.pc},
-            "cases": rows}
+                                   f"{args.pc} preconditioner; exact coarse solve in the value, the 2D cases "
+                                   f"with the W^1 V-cycle beside", "preconditioner": args.pc},
+            "cases": rows, "cases_2d_vcycle": rows_mg}
     print(json.dumps(line), flush=True)
 
 

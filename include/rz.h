@@ -194,7 +194,10 @@ typedef enum {
  * 3 lambda_max) / 4 of S A from 10 CG steps (SplitMix64 right-hand side
  * seeded 0x5EED3000 + level); an explicit inverse on the coarsest mesh.  In
  * the hybrid sweep the cycle gets its own weight rho_W by the same rule
- * (seed 0x5EED4000).  3D only, pure Neumann only (RZ_ERR_UNSUPPORTED
+ * (seed 0x5EED4000).  Tetrahedra and triangles (in 2D, H(div) RT_p uses
+ * the H(curl) prolongation and smoother: its Whitney functions are the
+ * quarter turns of Ned_p's, so its flux dofs prolong like circulations);
+ * first-kind spaces and pure Neumann problems only (RZ_ERR_UNSUPPORTED
  * otherwise); RZ_ERR_MESH when the hierarchy does not match the problem's
  * mesh or is not nested. */
 typedef enum { RZ_COARSE_EXACT = 0, RZ_COARSE_MG = 1 } rz_coarse;

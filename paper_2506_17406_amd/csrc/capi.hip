@@ -509,31 +509,30 @@ void setup_coarse(rz_problem &P, hipStream_t s) {
 // upload.  The Whitney block A[W, W] is assembled on the host from the
 // element's Whitney sub-blocks and the geometric weights.
 void setup_multigrid(rz_problem &P, const rz_mesh *m, const rz_options *o, hipStream_t s) {
-  if (P.d != 3) throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for tetrahedral meshes"};
   if (P.fam == rz::FAM_NEDTWO || P.fam == rz::FAM_BDM)
     throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for the first-kind spaces"};
   if (!P.dir_dofs.empty())
     throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for pure Neumann problems"};
-  if (P.d != 3) throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for tetrahedral meshes"};
-  if (P.fam == rz::FAM_NEDTWO || P.fam == rz::FAM_BDM)
-    throw RzError{RZ_ERR_UNSUPPORTED, "the multigrid coarse solver is built for the first-kind spaces"};
   if (o->mg_levels < 2 || !o->mg_meshes) throw RzError{RZ_ERR_ARG, "multigrid needs mg_levels >= 2 meshes"};
+  const int d = P.d;
   const rz_mesh *H = o->mg_meshes;
   for (int l = 0; l < o->mg_levels; ++l)
-    if (H[l].dim != 3 || !H[l].coords || !H[l].cells || H[l].n_vertices <= 0 || H[l].n_cells <= 0)
+    if (H[l].dim != d || !H[l].coords || !H[l].cells || H[l].n_vertices <= 0 || H[l].n_cells <= 0)
       throw RzError{RZ_ERR_ARG, "bad mesh in the multigrid hierarchy"};
   if (H[0].n_vertices != m->n_vertices || H[0].n_cells != m->n_cells ||
-      std::memcmp(H[0].cells, m->cells, sizeof(int64_t) * 4 * m->n_cells) != 0)
+      std::memcmp(H[0].cells, m->cells, sizeof(int64_t) * (d + 1) * m->n_cells) != 0)
     throw RzError{RZ_ERR_MESH, "the finest hierarchy mesh must have the problem's vertices and cells"};
+  // the form degree of the Whitney space: 2D RT_p is k = 1 (the quarter
+  // turn of Ned_p: the H(curl) prolongation and smoother serve it unchanged)
   const int k = P.k;
   // level topologies (entity lists of the lowest-order element)
-  rz::RefElement el1 = rz::build_reference(3, P.fam, 1);
+  rz::RefElement el1 = rz::build_reference(d, P.fam, 1);
   std::vector<rz::Topology> coarse_tops;
   coarse_tops.reserve(o->mg_levels);
   std::vector<const rz::Topology *> tops{&P.top};
   std::vector<const double *> X{H[0].coords};
   for (int l = 1; l < o->mg_levels; ++l) {
-    coarse_tops.push_back(rz::build_topology(3, H[l].n_vertices, H[l].n_cells, H[l].cells, el1));
+    coarse_tops.push_back(rz::build_topology(d, H[l].n_vertices, H[l].n_cells, H[l].cells, el1));
     tops.push_back(&coarse_tops.back());
     X.push_back(H[l].coords);
   }

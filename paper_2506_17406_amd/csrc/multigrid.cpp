@@ -103,21 +103,24 @@ void csr_apply(const Csr &A, const double *x, double *y) {
 
 namespace {
 
-// barycentric coordinates lam(x) = L [x; 1] of a tetrahedron
-Dense barycentric(const double *X, const int64_t *v) {
-  Dense M(4, 4);
-  for (int a = 0; a < 4; ++a) {
-    for (int b = 0; b < 3; ++b) M(b, a) = X[v[a] * 3 + b];
-    M(3, a) = 1.0;
+// barycentric coordinates lam(x) = L [x; 1] of a simplex (d + 1 vertices
+// in d dimensions, coordinates with stride d)
+Dense barycentric(int d, const double *X, const int64_t *v) {
+  Dense M(d + 1, d + 1);
+  for (int a = 0; a <= d; ++a) {
+    for (int b = 0; b < d; ++b) M(b, a) = X[v[a] * d + b];
+    M(d, a) = 1.0;
   }
   return inverse(M);
 }
 
-void whitney_at(int k, const Dense &L, const int *loc, const double *x, double *out) {
-  double lam[4], g[4][3];
-  for (int a = 0; a < 4; ++a) {
-    lam[a] = L(a, 3);
-    for (int b = 0; b < 3; ++b) {
+// the Whitney k-form of the local vertex tuple loc at x (d components for
+// k = 1, 3 for k = 2)
+void whitney_at(int d, int k, const Dense &L, const int *loc, const double *x, double *out) {
+  double lam[4], g[4][3] = {};
+  for (int a = 0; a <= d; ++a) {
+    lam[a] = L(a, d);
+    for (int b = 0; b < d; ++b) {
       lam[a] += L(a, b) * x[b];
       g[a][b] = L(a, b);
     }
@@ -131,7 +134,7 @@ void whitney_at(int k, const Dense &L, const int *loc, const double *x, double *
     out[0] = lam[loc[0]];
   } else if (k == 1) {
     const int a = loc[0], b = loc[1];
-    for (int i = 0; i < 3; ++i) out[i] = lam[a] * g[b][i] - lam[b] * g[a][i];
+    for (int i = 0; i < d; ++i) out[i] = lam[a] * g[b][i] - lam[b] * g[a][i];
   } else {
     const int a = loc[0], b = loc[1], c = loc[2];
     double t1[3], t2[3], t3[3];
@@ -163,25 +166,28 @@ std::vector<std::vector<int>> subsets(int n, int m) {
 }  // namespace
 
 Csr whitney_prolongation(int k, const Topology &tf, const double *Xf, const Topology &tc, const double *Xc) {
-  if (tc.d != 3 || tf.d != 3) throw std::invalid_argument("the multigrid hierarchy is built for tetrahedral meshes");
+  const int d = tf.d, nv = tf.d + 1;
+  if (tc.d != d || (d != 2 && d != 3) || k < 0 || k >= d)
+    throw std::invalid_argument("the multigrid hierarchy is built for triangle and tetrahedral meshes");
   const int64_t nc = tc.n_cells;
   std::vector<Dense> L(nc);
-  for (int64_t c = 0; c < nc; ++c) L[c] = barycentric(Xc, tc.cells.data() + (c * 4));
+  for (int64_t c = 0; c < nc; ++c) L[c] = barycentric(d, Xc, tc.cells.data() + (c * nv));
   // bucket grid over the coarse cells' bounding boxes
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int64_t v = 0; v < tc.n_vertices; ++v)
-    for (int b = 0; b < 3; ++b) lo[b] = std::min(lo[b], Xc[v * 3 + b]), hi[b] = std::max(hi[b], Xc[v * 3 + b]);
-  const int G = std::max(1, int(std::cbrt(double(nc) / 6.0) + 0.5));
+    for (int b = 0; b < d; ++b) lo[b] = std::min(lo[b], Xc[v * d + b]), hi[b] = std::max(hi[b], Xc[v * d + b]);
+  const int G = std::max(1, d == 3 ? int(std::cbrt(double(nc) / 6.0) + 0.5) : int(std::sqrt(double(nc) / 2.0) + 0.5));
   auto bucket = [&](double x, int b) {
     const double t = (x - lo[b]) / std::max(1e-300, hi[b] - lo[b]) * G;
     return std::min(G - 1, std::max(0, int(std::floor(t))));
   };
-  std::vector<std::vector<int64_t>> cells_in(size_t(G) * G * G);
+  const size_t G2 = d == 3 ? size_t(G) : 1;  // extent of the third axis
+  std::vector<std::vector<int64_t>> cells_in(size_t(G) * G * G2);
   for (int64_t c = 0; c < nc; ++c) {
-    int b0[3], b1[3];
-    for (int b = 0; b < 3; ++b) {
+    int b0[3] = {0, 0, 0}, b1[3] = {0, 0, 0};
+    for (int b = 0; b < d; ++b) {
       double mn = 1e300, mx = -1e300;
-      for (int a = 0; a < 4; ++a) mn = std::min(mn, Xc[tc.cells[c * 4 + a] * 3 + b]), mx = std::max(mx, Xc[tc.cells[c * 4 + a] * 3 + b]);
+      for (int a = 0; a < nv; ++a) mn = std::min(mn, Xc[tc.cells[c * nv + a] * d + b]), mx = std::max(mx, Xc[tc.cells[c * nv + a] * d + b]);
       b0[b] = bucket(mn - 1e-12, b);
       b1[b] = bucket(mx + 1e-12, b);
     }
@@ -189,7 +195,7 @@ Csr whitney_prolongation(int k, const Topology &tf, const double *Xf, const Topo
       for (int j = b0[1]; j <= b1[1]; ++j)
         for (int l = b0[2]; l <= b1[2]; ++l) cells_in[(size_t(l) * G + j) * G + i].push_back(c);
   }
-  const auto loc_sets = subsets(4, k + 1);
+  const auto loc_sets = subsets(nv, k + 1);
   const int nsub = int(loc_sets.size());
   std::vector<int64_t> rows;
   std::vector<int32_t> cols;
@@ -198,15 +204,16 @@ Csr whitney_prolongation(int k, const Topology &tf, const double *Xf, const Topo
     const int64_t *tup = tf.ent[k].data() + (e * (k + 1));
     double xb[3] = {0, 0, 0};
     for (int a = 0; a <= k; ++a)
-      for (int b = 0; b < 3; ++b) xb[b] += Xf[tup[a] * 3 + b] / (k + 1);
-    const auto &cand = cells_in[(size_t(bucket(xb[2], 2)) * G + bucket(xb[1], 1)) * G + bucket(xb[0], 0)];
+      for (int b = 0; b < d; ++b) xb[b] += Xf[tup[a] * d + b] / (k + 1);
+    const int bz = d == 3 ? bucket(xb[2], 2) : 0;
+    const auto &cand = cells_in[(size_t(bz) * G + bucket(xb[1], 1)) * G + bucket(xb[0], 0)];
     int64_t cell = -1;
     double best = -1e300;
     for (int64_t c : cand) {
       double mn = 1e300;
-      for (int a = 0; a < 4; ++a) {
-        double l = L[c](a, 3);
-        for (int b = 0; b < 3; ++b) l += L[c](a, b) * xb[b];
+      for (int a = 0; a < nv; ++a) {
+        double l = L[c](a, d);
+        for (int b = 0; b < d; ++b) l += L[c](a, b) * xb[b];
         mn = std::min(mn, l);
       }
       if (mn > best) best = mn, cell = c;
@@ -217,13 +224,13 @@ Csr whitney_prolongation(int k, const Topology &tf, const double *Xf, const Topo
       const int *loc = loc_sets[s].data();
       double w[3], v = 0.0;
       if (k == 0) {
-        whitney_at(0, L[cell], loc, &Xf[tup[0] * 3], w);
+        whitney_at(d, 0, L[cell], loc, &Xf[tup[0] * d], w);
         v = w[0];
       } else if (k == 1) {
-        whitney_at(1, L[cell], loc, xb, w);
-        for (int b = 0; b < 3; ++b) v += w[b] * (Xf[tup[1] * 3 + b] - Xf[tup[0] * 3 + b]);
+        whitney_at(d, 1, L[cell], loc, xb, w);
+        for (int b = 0; b < d; ++b) v += w[b] * (Xf[tup[1] * d + b] - Xf[tup[0] * d + b]);
       } else {
-        whitney_at(2, L[cell], loc, xb, w);
+        whitney_at(3, 2, L[cell], loc, xb, w);
         double u[3], t[3], n[3];
         for (int b = 0; b < 3; ++b) u[b] = Xf[tup[1] * 3 + b] - Xf[tup[0] * 3 + b], t[b] = Xf[tup[2] * 3 + b] - Xf[tup[0] * 3 + b];
         n[0] = u[1] * t[2] - u[2] * t[1];

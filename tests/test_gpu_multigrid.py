@@ -1,5 +1,6 @@
 """GPU parity of the multigrid V-cycle on W^k (rz_options.coarse =
-RZ_COARSE_MG) against the oracle's (oracle.multigrid), through the C ABI.
+RZ_COARSE_MG) against the oracle's (oracle.multigrid), through the C ABI,
+on tetrahedra and triangles.
 
 The hierarchy is the Kuhn meshes with n, n/2, ..., 1 cells per edge; the
 problem's mesh is the jittered finest one (the prolongations use the
@@ -25,40 +26,42 @@ from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
 
 pytestmark = pytest.mark.gpu
 
-CASES = [("CG", 3, 4), ("Ned", 3, 4), ("RT", 2, 4), ("Ned", 2, 8), ("CG", 2, 2), ("RT", 3, 2)]
+CASES = [("CG", 3, 4), ("Ned", 3, 4), ("RT", 2, 4), ("Ned", 2, 8), ("CG", 2, 2), ("RT", 3, 2),
+         # triangles (2D RT_p takes the H(curl) prolongation and smoother)
+         ("CG", 4, 16, 2), ("Ned", 3, 16, 2), ("RT", 3, 16, 2), ("Ned", 5, 8, 2)]
 _cache = {}
 
 
-def hierarchy(n):
+def hierarchy(n, d=3):
     out, m = [], n
     while True:
-        out.append(kuhn_mesh(m, 3))
+        out.append(kuhn_mesh(m, d))
         if m % 2 or m == 1:
             return out
         m //= 2
 
 
-def setup(fam, p, n, pc="hybrid", precision="fp64"):
-    key = (fam, p, n, pc, precision)
+def setup(fam, p, n, d=3, pc="hybrid", precision="fp64"):
+    key = (fam, p, n, d, pc, precision)
     if key not in _cache:
         from paper_2506_17406_amd import rz
         print(f"setup {key}", flush=True)
-        X, C = kuhn_mesh(n, 3, jitter=0.1, seed=81)
-        okey = (fam, p, n)
+        X, C = kuhn_mesh(n, d, jitter=0.1, seed=81)
+        okey = (fam, p, n, d)
         if okey not in _cache:
-            top = Topology(X, C, element(3, fam, p))
+            top = Topology(X, C, element(d, fam, p))
             A = assemble(top, all_cell_matrices(top.el, top))
             _cache[okey] = (top, A, AdditiveSchwarz(A, top, fam, coarse_mg=n), {})
         top, A, Pa, pcs = _cache[okey]
         if pc not in pcs:
             pcs[pc] = Pa if pc == "additive" else HybridSchwarz(A, top, fam, additive=Pa)
-        prob = rz.Problem(X, C, p, fam, pc=pc, precision=precision, coarse="mg", mg_meshes=hierarchy(n))
+        prob = rz.Problem(X, C, p, fam, pc=pc, precision=precision, coarse="mg", mg_meshes=hierarchy(n, d))
         _cache[key] = (top, A, pcs[pc], prob)
     return _cache[key]
 
 
 def ids(c):
-    return "{}{}-n{}".format(*c)
+    return "{}{}-n{}".format(*c[:3]) + ("-2d" if len(c) > 3 and c[3] == 2 else "")
 
 
 @pytest.mark.parametrize("pc", ["additive", "hybrid"])
@@ -86,7 +89,7 @@ def test_vcycle_apply_P_and_solve(case, pc):
     assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
 
 
-@pytest.mark.parametrize("case", [CASES[1], CASES[2]], ids=ids)
+@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[8]], ids=ids)
 def test_vcycle_multi_column(case):
     top, A, P, prob = setup(*case)
     B = load_vectors(top.n_dofs, 84, n_rhs=3)
