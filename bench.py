@@ -73,8 +73,9 @@ def parse():
     ap.add_argument("--multirhs-modes", type=str, default="fp64,fp32-ir,bf16-pc",
                     help="precision modes timed by the multirhs workload (fp64 always runs)")
     ap.add_argument("--no-legs", action="store_true",
-                    help="sweep workload: skip the compact mixed-precision (Ned_6 16^3x6) and 64-column (RT_5 "
-                         "12^3x6) comparisons that the default line carries")
+                    help="sweep workload: skip the compact mixed-precision (Ned_6 16^3x6), 64-column (RT_5 "
+                         "12^3x6), Hodge-Laplacian (p = 4, Fichera corner) and 2D / second-kind spaces legs "
+                         "that the default line carries")
     ap.add_argument("--leg-steps", type=int, default=3)
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
                     help="after the measurement, one plain device copy of this many bytes (a known-size kernel "
@@ -629,6 +630,77 @@ def multirhs_leg(args):
             "speedup_batched_bf16pc_vs_one_by_one": out["fp64_one_by_one"]["ms"] / out["bf16-pc"]["ms"]}
 
 
+def hodge_leg(args):
+    """Compact Hodge-Laplacian leg for the default line: the three complexes
+    at p = 4 on the Fichera-corner Freudenthal mesh with 8 cells per edge
+    (2688 tets, jitter 0.1 h, mesh seed 31), gamma = 1, split decompositions,
+    load uniform[-1, 1] on the X^k equation (seed 32), preconditioned MINRES
+    to 1e-8; the true residual by the library's operator apply."""
+    import torch
+    from paper_2506_17406_amd import rz
+    from paper_2506_17406_amd.workloads import fichera_mesh
+    X, C = fichera_mesh(8, jitter=0.1, seed=31)
+    out, tot_dofs, tot_s = {}, 0, 0.0
+    for k, name in ((1, "CG4 x Ned4"), (2, "Ned4 x RT4"), (3, "RT4 x DG3")):
+        H = rz.Hodge(X, C, 4, k, gamma=1.0)
+        b = torch.zeros(H.n, dtype=torch.float64, device="cuda")
+        b[H.n0:] = torch.from_numpy(np.random.default_rng(32).uniform(-1, 1, H.n1)).cuda()
+        x = torch.empty_like(b)
+        H.solve(b, x, rtol=1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.leg_steps):
+            info = H.solve(b, x, rtol=1e-8)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.leg_steps
+        y = torch.empty_like(b)
+        H.apply(x, y)
+        res = ((b - y).norm() / b.norm()).item()
+        out[name] = {"dofs": H.n, "ms": dt * 1e3, "iterations": info["iterations"], "true_rel_residual": res}
+        tot_dofs += H.n
+        tot_s += dt
+        print(f"Hodge leg {name}: {H.n} dofs, {info['iterations']} its, {dt * 1e3:.1f} ms, true residual {res:.1e}",
+              file=sys.stderr, flush=True)
+        H.close()
+        del b, x, y
+        torch.cuda.empty_cache()
+    return {"workload": "Hodge Laplacians CG_4 x Ned_4, Ned_4 x RT_4, RT_4 x DG_3 on the Fichera-corner Freudenthal "
+                        "mesh, 8 cells per edge (2688 tets), gamma = 1, MINRES to 1e-8", "value": tot_dofs / tot_s,
+            "unit": "DOF/s", "cases": out}
+
+
+def spaces_leg(args):
+    """Compact leg of the spaces beyond the 3D first kind for the default
+    line: 2D Ned_6 and RT_6 on the jittered Kuhn 96^2x2 mesh (mesh seed 2)
+    with the W^1 V-cycle over the Kuhn meshes 96, 48, .., 3, and NedTwo_4
+    and BDM_4 on the jittered Kuhn 8^3x6 mesh; load seed 3, FP64 PCG to
+    1e-10, the default hybrid preconditioner."""
+    import torch
+    from paper_2506_17406_amd import rz
+    from paper_2506_17406_amd.workloads import kuhn_mesh, load_vectors
+    out, tot_dofs, tot_s = {}, 0, 0.0
+    X2, C2 = kuhn_mesh(96, 2, jitter=0.1, seed=2)
+    h2 = [kuhn_mesh(m, 2) for m in (96, 48, 24, 12, 6, 3)]
+    X3, C3 = kuhn_mesh(8, 3, jitter=0.1, seed=2)
+    for name, X, C, fam, p, mg in (("2D Ned6 +mg", X2, C2, "Ned", 6, h2), ("2D RT6 +mg", X2, C2, "RT", 6, h2),
+                                   ("NedTwo4", X3, C3, "NedTwo", 4, None), ("BDM4", X3, C3, "BDM", 4, None)):
+        prob = rz.Problem(X, C, p, fam, pc=args.pc, coarse="mg" if mg else "exact", mg_meshes=mg)
+        b = torch.from_numpy(load_vectors(prob.n_dofs, 3)[:, 0]).cuda()
+        x = torch.zeros_like(b)
+        dt, info = _timed_solve(prob, b, x, args.leg_steps)
+        out[name] = {"dofs": prob.n_dofs, "ms": dt * 1e3, "iterations": info["iterations"],
+                     "rel_residual": info["rel_residual"], "setup_ms": round(info["setup_ms"], 1)}
+        tot_dofs += prob.n_dofs
+        tot_s += dt
+        print(f"spaces leg {name}: {prob.n_dofs} dofs, {info['iterations']} its, {dt * 1e3:.1f} ms",
+              file=sys.stderr, flush=True)
+        prob.close()
+        del b, x
+        torch.cuda.empty_cache()
+    return {"workload": "2D Ned_6 / RT_6 (jittered Kuhn 96^2x2, W^1 V-cycle) and NedTwo_4 / BDM_4 (jittered Kuhn "
+                        "8^3x6), FP64 PCG to 1e-10", "value": tot_dofs / tot_s, "unit": "DOF/s", "cases": out}
+
+
 def cpu_baseline(pc="hybrid"):
     """The oracle, as it stands, on a bounded sample of the workload: the
     p = 3 and p = 4 problems of all three spaces of the sweep (same mesh and
@@ -919,6 +991,8 @@ def main():
     if not args.no_legs:
         legs["mixed_precision"] = mixed_leg(args)
         legs["multi_rhs"] = multirhs_leg(args)
+        legs["hodge"] = hodge_leg(args)
+        legs["spaces"] = spaces_leg(args)
 
     # HBM traffic of the roofline kernel from committed counter runs, if they
     # were taken on the current kernel source
