@@ -2111,18 +2111,18 @@ int hodge_apply(rz_hodge *H, const double *x, double *y, hipStream_t s) {
   const double *sg = x, *u = x + n0;
   double *y0 = y, *y1 = y + n0;
   if (H->k == 3) {
-    rz::launch_csr_spmv(n1, H->dp, H->dc, H->dv, sg, y1, 1.0, false, H->d_lanes, s);                 // M_3 D sigma
+    rz::launch_csr_spmv(n1, H->dp, H->dc, H->dv, sg, y1, 1.0, false, H->d_lanes, s);  // M_3 D sigma
     rz::launch_apply_A(H->tM0, sg, n0, y0, n0, 1, nullptr, s, false, 0, -1, -1.0, 0, 0, true);  // -M sigma
-    rz::launch_csr_spmv(n0, H->dtp, H->dtc, H->dtv, u, y0, 1.0, true, H->dt_lanes, s);               // + (M_3 D)^T u
+    rz::launch_csr_spmv(n0, H->dtp, H->dtc, H->dtv, u, y0, 1.0, true, H->dt_lanes, s);  // + (M_3 D)^T u
     return RZ_OK;
   }
-  rz::launch_csr_spmv(n1, H->dp, H->dc, H->dv, sg, H->t2, 1.0, false, H->d_lanes, s);              // D sigma
+  rz::launch_csr_spmv(n1, H->dp, H->dc, H->dv, sg, H->t2, 1.0, false, H->d_lanes, s);  // D sigma
   HIPCHK(hipMemcpyAsync(H->t2 + n1, u, size_t(n1) * 8, hipMemcpyDeviceToDevice, s));   // u
   rz::launch_apply_A(H->tM1, H->t2, n1, H->m2, n1, 2, nullptr, s, false, 0, -1, 1.0, 0, 0, true);
   rz::launch_apply_A(H->tK1, u, n1, y1, n1, 1, nullptr, s, false, 0, -1, 1.0, 0, 0, true);  // K u
   rz::launch_lincomb3(n1, 1.0, y1, 1.0, H->m2, 0.0, nullptr, y1, s);                    // + M D sigma
   rz::launch_apply_A(H->tM0, sg, n0, y0, n0, 1, nullptr, s, false, 0, -1, -1.0, 0, 0, true);  // -M sigma
-  rz::launch_csr_spmv(n0, H->dtp, H->dtc, H->dtv, H->m2 + n1, y0, 1.0, true, H->dt_lanes, s);        // + D^T M u
+  rz::launch_csr_spmv(n0, H->dtp, H->dtc, H->dtv, H->m2 + n1, y0, 1.0, true, H->dt_lanes, s);  // + D^T M u
   return RZ_OK;
 }
 
