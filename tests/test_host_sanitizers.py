@@ -38,7 +38,8 @@ def test_host_entry_points_clean_under_asan_ubsan():
         others = ["test_header_symbols_exported", "test_reference_argument_errors", "test_numbering_mesh_errors",
                   "test_setup_rejects_before_device_work", "test_numbering_bit_exact",
                   "test_vertex_star_lists_bit_exact", "test_comparator_lists_bit_exact",
-                  "test_hdiv_curl_potential_entries", "test_hiptmair_only_for_hcurl"]
+                  "test_hdiv_curl_potential_entries", "test_hiptmair_decompositions_need_a_derivative_space",
+                  "test_derivative_entries_left_out_of_the_hodge_csr"]
         sel = [host] if os.environ.get("RZ_HEAVY_TESTS") else (
             [host + "::test_reference_tables_match_oracle[%s]" % t for t in tables] +
             [host + "::" + f for f in others])
