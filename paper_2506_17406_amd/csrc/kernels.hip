@@ -1220,23 +1220,35 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(int NT, int nsplit, const d
 #pragma unroll
     for (int e = 0; e < 16; ++e) stage[e] = c < ncol ? src[e] : 0.0;
   };
-  if (J0 < J1) load_R(J0);
+  // the wave's 16 A fragments of tile J, loaded one tile ahead (a load's
+  // latency spans several tiles' MFMA time at this occupancy)
+  double a[16];
+  auto load_A = [&](int J) {
+    const double *Af = F + ((int64_t(I) * NT + J) * 4 + wave) * 1024 + lane;
+#pragma unroll
+    for (int kb = 0; kb < 16; ++kb) a[kb] = Af[kb * 64];
+  };
+  if (J0 < J1) {
+    load_R(J0);
+    load_A(J0);
+  }
   for (int J = J0; J < J1; ++J) {
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 16; ++e) R[srow + e][scol] = stage[e];
     __syncthreads();
-    if (J + 1 < J1) load_R(J + 1);
-    const double *Af = F + ((int64_t(I) * NT + J) * 4 + wave) * 1024 + lane;
-    double a_cur = Af[0];
-#pragma unroll 4
-    for (int kb = 0; kb < 16; ++kb) {
-      const double a_nxt = kb + 1 < 16 ? Af[(kb + 1) * 64] : 0.0;
+    double ac[16];
+#pragma unroll
+    for (int kb = 0; kb < 16; ++kb) ac[kb] = a[kb];
+    if (J + 1 < J1) {
+      load_R(J + 1);
+      load_A(J + 1);
+    }
+#pragma unroll
+    for (int kb = 0; kb < 16; ++kb)
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur, R[kb * 4 + lk][nb * 16 + li], acc[nb], 0, 0, 0);
-      a_cur = a_nxt;
-    }
+        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kb], R[kb * 4 + lk][nb * 16 + li], acc[nb], 0, 0, 0);
   }
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) {
