@@ -4,7 +4,7 @@ eq:hodge-laplace, eq:augmented-lagrangian) against the oracle
 
 * the mixed operator A = [-M_{k-1}, D^T M_k; M_k D, K_k] (1e-12 relative),
   k = 1 (CG_p x Ned_p), k = 2 (Ned_p x RT_p) and k = 3 (RT_p x DG_{p-1}),
-  p = 1..3, jittered.  The two sides build their orthonormal DG bases
+  p = 1..3, jittered; and at p = 5 (1e-11);  The two sides build their orthonormal DG bases
   independently, so for k = 3 the library's DG coefficients are the
   oracle's times one orthogonal Q per cell (Q = D D_o^+ from the two
   reference divergence matrices; the host tests pin it orthogonal), and
@@ -84,6 +84,26 @@ def test_operator_and_preconditioner(rz, k, p):
         tol = 1e-10 * max(1.0, gamma / 10.0)
         assert np.abs(zt.cpu().numpy() - refp).max() <= tol * np.abs(refp).max()
         G.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_operator_at_p5(rz, k):
+    """The mixed operator at p = 5, where the library's D leaves out more
+    round-off entries of the reference derivative matrix (up to 1e-12 of
+    the largest): 1e-11 relative, the two table builds' own agreement at
+    this degree (Ned_5 2.6e-12)."""
+    X, C = fichera_mesh(2, jitter=0.1, seed=25)
+    H = HodgeLaplacian(X, C, k, 5, gamma=10.0)
+    G = rz.Hodge(X, C, 5, k, gamma=10.0)
+    T = to_library_basis(rz, k, 5, H.n0)
+    x = np.random.default_rng(6).uniform(-1, 1, G.n)
+    xt = torch.from_numpy(T(x)).cuda()
+    yt = torch.empty_like(xt)
+    G.apply(xt, yt)
+    torch.cuda.synchronize()
+    ref = T(H.A @ x)
+    assert np.abs(yt.cpu().numpy() - ref).max() <= 1e-11 * np.abs(ref).max()
+    G.close()
 
 
 @pytest.mark.parametrize("k", [1, 2, 3])
