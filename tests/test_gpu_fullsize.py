@@ -20,10 +20,11 @@ sampled outputs one by one, and properties that hold at any size.
 * the mixed-precision, multi-RHS and uneven-batch workloads at their full
   size (Ned_6 on 16^3 x 6 cells in FP32 refinement and with the bfloat16
   preconditioner; RT_5 on 12^3 x 6 cells with 64 right-hand sides; the
-  batch's CG_10 16^3 x 6 and Ned_10 10^3 x 6 members): the oracle's sampled
-  residual rows of the returned solutions within 2e-10 ||b||_2, and the
-  sampled estimate sqrt(n / |S| sum_S res_i^2) / ||b|| of the relative
-  true residual printed.
+  batch's CG_10 16^3 x 6 and Ned_10 10^3 x 6 members; the spaces leg's 2D
+  Ned_6 and RT_6 on 96^2 x 2 triangles with the W^1 V-cycle, NedTwo_4 and
+  BDM_4 on 8^3 x 6): the oracle's sampled residual rows of the returned
+  solutions within 2e-10 ||b||_2, and the sampled estimate
+  sqrt(n / |S| sum_S res_i^2) / ||b|| of the relative true residual printed.
 """
 import numpy as np
 import pytest
@@ -59,7 +60,7 @@ def setup_full(fam, p, pc="hybrid"):
 def sample_dofs(top, per_block=12, seed=0):
     rng = np.random.default_rng(seed)
     out = []
-    for l in range(4):
+    for l in range(len(top.offset) - 1):
         lo, hi = top.offset[l], top.offset[l + 1]
         if hi > lo:
             out += list(rng.choice(np.arange(lo, hi), size=min(per_block, hi - lo), replace=False))
@@ -233,16 +234,32 @@ WORKLOADS = {
     "multirhs-fp32ir-RT5-n12-64": ("RT", 5, 12, 6, 7, "fp32-ir", 64),
     "batch-bf16pc-CG10-n16": ("CG", 10, 16, 128, 228, "bf16-pc", 1),
     "batch-bf16pc-Ned10-n10": ("Ned", 10, 10, 106, 206, "bf16-pc", 1),
+    # the spaces leg: 2D with the W^1 V-cycle over the Kuhn meshes 96, .., 3
+    # (dimension and coarse solver appended), second-kind 3D
+    "spaces-Ned6-n96-2d-mg": ("Ned", 6, 96, 2, 3, "fp64", 1, 2, "mg"),
+    "spaces-RT6-n96-2d-mg": ("RT", 6, 96, 2, 3, "fp64", 1, 2, "mg"),
+    "spaces-NedTwo4-n8": ("NedTwo", 4, 8, 2, 3, "fp64", 1),
+    "spaces-BDM4-n8": ("BDM", 4, 8, 2, 3, "fp64", 1),
 }
+
+
+def _hierarchy(n, d):
+    out = [kuhn_mesh(n, d)]
+    while n % 2 == 0 and n > 1:
+        n //= 2
+        out.append(kuhn_mesh(n, d))
+    return out
 
 
 @pytest.mark.parametrize("name", list(WORKLOADS))
 def test_workload_sampled_residual(name):
     from paper_2506_17406_amd import rz
-    fam, p, n, ms, ls, prec, nc = WORKLOADS[name]
+    fam, p, n, ms, ls, prec, nc = WORKLOADS[name][:7]
+    d, coarse = WORKLOADS[name][7:] if len(WORKLOADS[name]) > 7 else (3, "exact")
     print(f"workload {name}: setup", flush=True)
-    X, C = kuhn_mesh(n, 3, jitter=0.1, seed=ms)
-    prob = rz.Problem(X, C, p, fam, precision=prec)
+    X, C = kuhn_mesh(n, d, jitter=0.1, seed=ms)
+    prob = rz.Problem(X, C, p, fam, precision=prec, coarse=coarse,
+                      mg_meshes=_hierarchy(n, d) if coarse == "mg" else None)
     try:
         B = load_vectors(prob.n_dofs, ls, n_rhs=nc)
         Bt = torch.from_numpy(np.ascontiguousarray(B.T)).cuda().T if nc > 1 else torch.from_numpy(B[:, 0]).cuda()
@@ -254,7 +271,7 @@ def test_workload_sampled_residual(name):
     finally:
         prob.close()
         torch.cuda.empty_cache()
-    el = element(3, fam, p)
+    el = element(d, fam, p)
     top = Topology(X, C, el)
     R = reference_stack(el)
     rows = sample_dofs(top, per_block=10, seed=2)
