@@ -102,11 +102,14 @@ def derivative_matrix(top0, top1, Dhat):
 class HodgeLaplacian:
     """The mixed system and its block preconditioner on one mesh."""
 
-    def __init__(self, X, C, k, p, gamma=1.0, exact=False, decomposition="paper"):
+    def __init__(self, X, C, k, p, gamma=1.0, exact=False, decomposition="paper", preconditioner=True):
+        """preconditioner=False builds the mixed operator only (no Riesz maps
+        or Schwarz set-up): for checking residuals of solutions computed
+        elsewhere."""
         fa, fb = PAIRS_K[k]
         self.k, self.p, self.gamma = k, p, gamma
         if k == 3:
-            self._init_dg(X, C, p, gamma, exact, decomposition)
+            self._init_dg(X, C, p, gamma, exact, decomposition, preconditioner)
             return
         self.el0, self.el1 = element(3, fa, p), element(3, fb, p)
         self.top0, self.top1 = Topology(X, C, self.el0), Topology(X, C, self.el1)
@@ -117,6 +120,8 @@ class HodgeLaplacian:
         self.K1 = assemble(self.top1, all_cell_matrices(self.el1, self.top1, alpha=1.0, beta=0.0))
         M1D = (self.M1 @ self.D).tocsr()
         self.A = sp.bmat([[-self.M0, M1D.T], [M1D, self.K1]]).tocsr()
+        if not preconditioner:
+            return
         # the weighted Riesz maps of eq:augmented-lagrangian
         self.R0 = assemble(self.top0, all_cell_matrices(self.el0, self.top0, alpha=gamma, beta=1.0))
         self.R1 = assemble(self.top1, all_cell_matrices(self.el1, self.top1, alpha=1.0, beta=1.0 / gamma))
@@ -127,7 +132,7 @@ class HodgeLaplacian:
             self.P0 = HybridSchwarz(self.R0, self.top0, fa, decomposition=decomposition).apply
             self.P1 = HybridSchwarz(self.R1, self.top1, fb, decomposition=decomposition).apply
 
-    def _init_dg(self, X, C, p, gamma, exact, decomposition):
+    def _init_dg(self, X, C, p, gamma, exact, decomposition, preconditioner=True):
         self.el0 = element(3, "RT", p)
         self.top0 = Topology(X, C, self.el0)
         self.n0 = self.top0.n_dofs
@@ -147,6 +152,8 @@ class HodgeLaplacian:
         self.K1 = sp.csr_matrix((self.n1, self.n1))
         M1D = (self.M1 @ self.D).tocsr()
         self.A = sp.bmat([[-self.M0, M1D.T], [M1D, None]], format="csr")
+        if not preconditioner:
+            return
         self.R0 = assemble(self.top0, all_cell_matrices(self.el0, self.top0, alpha=gamma, beta=1.0))
         self.R1 = sp.diags(m3 / gamma).tocsr()
         if exact:
